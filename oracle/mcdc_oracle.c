@@ -1,0 +1,816 @@
+/*
+ * mcdc_oracle.c -- plain serial CPU oracle for multigroup, time-dependent,
+ * fixed-source Monte Carlo particle transport with track-length mesh tallies.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the judge of correctness of the GPU
+ * library.  Only the test suite, the smoke check and the CPU-baseline leg of
+ * the benchmark may load it.  It shares no code, header, table or constant
+ * generator with the GPU library: every piece (random numbers, grid, sampling,
+ * tallies) is written out here on its own, slowly and in the plainest order.
+ *
+ * What it computes.  The paper (Section 3) describes the method in words: MC
+ * transport of neutrons through multigroup materials (group-wise total cross
+ * section, isotropic scattering through a group-to-group transfer matrix, no
+ * fission here), on box geometry, with a time-dependent source, time census,
+ * time-dependent mesh tallies, and the track-length estimator of the
+ * time-averaged flux (Section 3.1); analog mode means uniform weight and no
+ * variance reduction (Section 3.3).  The paper prints no equations and no
+ * random-number scheme; every point where it is silent is fixed by an
+ * explicit reading, stated next to the code that implements it:
+ *
+ *   R1  RNG: 63-bit linear congruential generator s <- (g s + c) mod 2^63,
+ *       g = 2806196910506780709, c = 1; history i starts at the state
+ *       skip(seed, i * 152917); xi = (s >> 10) * 2^-53 after each advance.
+ *   R2  Floating point: IEEE binary64, round to nearest, no contraction;
+ *       an explicit fused multiply-add only in the position update.
+ *   R3  Tie order of the next event: census, then surface, then collision.
+ *   R4  Geometry, tally, weight-window and detector planes are merged per
+ *       axis into one sorted, exactly de-duplicated union grid; a crossing of
+ *       any union plane is one surface event; axes whose distance equals the
+ *       event distance all cross in that one event; the cell index moves by
+ *       one and is never recomputed from the position.
+ *   R5  Random-number order: birth draws x, y, z, t, group, direction,
+ *       optical depth; a collision draws the absorb test, the outgoing group
+ *       (always), the direction, the optical depth.
+ *   R6  Optical depth to collision tau = -log(1 - xi) is carried across
+ *       surfaces and census and reduced by d * Sigma_t on each flight.
+ *   R7  Isotropic directions by Marsaglia's (1972) method.
+ *   R8  Time bins are the census grid; a particle reaching the last edge is
+ *       killed (time cut-off) with no further tally.
+ *   R9  B contiguous batches of histories; mean and batch variance of the
+ *       normalised bin fluxes.
+ *   R10 Weight windows (optional): centre w_c per (time bin, group, window
+ *       cell); bounds w_L = 2 w_c / (1 + rho), w_U = rho w_L, survival weight
+ *       w_c; split into n = min(ceil(w / w_U), max_split) copies; children
+ *       take streams SplitMix64(parent state xor j) masked to 63 bits.
+ *
+ * Build: gcc -O2 -ffp-contract=off -fPIC -shared -o liboracle.so mcdc_oracle.c -lm
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ------------------------------------------------------------------------ */
+/* Problem description (this oracle's own layout)                            */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    int32_t G, M;
+    const double *sigma_t;   /* [M][G] */
+    const double *sigma_s;   /* [M][G][G], from g (row) to g' (column) */
+    const double *speed;     /* [G] */
+    int32_t n_planes[3];     /* 0 = infinite axis */
+    const double *planes[3];
+    const int32_t *material; /* [cz][cy][cx] over geometry cells */
+    int32_t bc[6];           /* x-, x+, y-, y+, z-, z+ : 0 vacuum, 1 reflective */
+    /* source */
+    double src_lo[3], src_hi[3];
+    double src_t_lo, src_t_hi;
+    const double *src_pmf;   /* [G] */
+    int32_t src_kind;        /* 0 isotropic, 1 surface */
+    int32_t src_axis, src_sign, src_mu_law; /* mu law: 0 beam, 1 uniform, 2 cosine */
+    /* tally */
+    int32_t n_mesh[3];       /* 0 = one bin spanning the axis */
+    const double *mesh[3];
+    int32_t n_time_edges;
+    const double *time_edges;
+    int32_t n_batches;
+    /* detector (quantity of interest) */
+    int32_t qoi_on;
+    double qoi_lo[3], qoi_hi[3];
+    const int32_t *qoi_groups; /* [G] 0/1 */
+    /* weight windows */
+    int32_t n_ww[3];         /* 0 = one window cell spanning the axis */
+    const double *ww[3];
+    const double *ww_center; /* [K][G][wz][wy][wx] or NULL (analog) */
+    double ww_ratio;
+    int32_t ww_max_split;
+} oracle_problem;
+
+enum { EV_CENSUS = 0, EV_SURFACE = 1, EV_COLLISION = 2 };
+enum { T_ABSORB = 0, T_LEAK = 1, T_TIME = 2, T_LOST = 3, T_ROULETTE = 4 };
+
+/* ------------------------------------------------------------------------ */
+/* R1: random numbers                                                         */
+/* ------------------------------------------------------------------------ */
+
+static const uint64_t LCG_MULT = 2806196910506780709ULL;
+static const uint64_t LCG_ADD = 1ULL;
+static const uint64_t LCG_STRIDE = 152917ULL;
+static const uint64_t MASK63 = 0x7FFFFFFFFFFFFFFFULL;
+
+/* s_k = g^k s + c (g^k - 1)/(g - 1) mod 2^63, by repeated squaring of the
+ * affine map s -> h s + f (F. B. Brown, "Random number generation with
+ * arbitrary strides", Trans. Am. Nucl. Soc. 71, 1994). */
+uint64_t oracle_rng_skip(uint64_t s, uint64_t k)
+{
+    uint64_t G = 1, C = 0, h = LCG_MULT, f = LCG_ADD;
+    while (k) {
+        if (k & 1ULL) {
+            G = G * h;
+            C = C * h + f;
+        }
+        f = f * (h + 1ULL);
+        h = h * h;
+        k >>= 1;
+    }
+    return (G * (s & MASK63) + C) & MASK63;
+}
+
+static double rn(uint64_t *s)
+{
+    *s = (LCG_MULT * (*s) + LCG_ADD) & MASK63;
+    return (double)((*s) >> 10) * 0x1p-53;
+}
+
+/* SplitMix64 output function (Steele, Lea & Flood, OOPSLA 2014). */
+static uint64_t splitmix64(uint64_t x)
+{
+    uint64_t z = x + 0x9E3779B97F4A7C15ULL;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+}
+
+/* exported for the random-number tests */
+void oracle_rng_draws(uint64_t s, int64_t n, uint64_t *states, double *xi)
+{
+    for (int64_t j = 0; j < n; j++) {
+        double x = rn(&s);
+        if (states) states[j] = s;
+        if (xi) xi[j] = x;
+    }
+}
+
+uint64_t oracle_child_stream(uint64_t parent, uint64_t j)
+{
+    return splitmix64(parent ^ j) & MASK63;
+}
+
+/* ------------------------------------------------------------------------ */
+/* R4: union grid per axis                                                    */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    int n;        /* number of union planes; 0 = infinite axis */
+    double *P;    /* [n] */
+    int *geo;     /* [n-1] geometry cell of each union cell */
+    int *tal;     /* [n-1] tally bin index along the axis, -1 outside mesh */
+    int *wwc;     /* [n-1] weight-window cell index, -1 outside */
+    int *inq;     /* [n-1] 1 if inside the detector box along this axis */
+} axis_grid;
+
+static int cmp_double(const void *a, const void *b)
+{
+    double x = *(const double *)a, y = *(const double *)b;
+    return (x < y) ? -1 : (x > y) ? 1 : 0;
+}
+
+/* index j with E[j] <= x < E[j+1] over n edges, or -1 if outside */
+static int bin_of(const double *E, int n, double x)
+{
+    if (n < 2 || x < E[0] || x >= E[n - 1]) return -1;
+    int j = 0;
+    while (!(x < E[j + 1])) j++;
+    return j;
+}
+
+static int build_axis(const oracle_problem *p, int a, axis_grid *A)
+{
+    memset(A, 0, sizeof(*A));
+    int ng = p->n_planes[a];
+    if (ng == 0) return 0;
+    int cap = ng + p->n_mesh[a] + p->n_ww[a] + 2;
+    double *all = (double *)malloc(sizeof(double) * cap);
+    int m = 0;
+    for (int j = 0; j < ng; j++) all[m++] = p->planes[a][j];
+    for (int j = 0; j < p->n_mesh[a]; j++) all[m++] = p->mesh[a][j];
+    for (int j = 0; j < p->n_ww[a]; j++) all[m++] = p->ww[a][j];
+    if (p->qoi_on) {
+        all[m++] = p->qoi_lo[a];
+        all[m++] = p->qoi_hi[a];
+    }
+    double lo = p->planes[a][0], hi = p->planes[a][ng - 1];
+    for (int j = 0; j < m; j++)
+        if (all[j] < lo || all[j] > hi) {
+            free(all);
+            return -1;
+        }
+    qsort(all, m, sizeof(double), cmp_double);
+    int n = 0;
+    for (int j = 0; j < m; j++)
+        if (n == 0 || all[j] != all[n - 1]) all[n++] = all[j];
+    A->n = n;
+    A->P = all;
+    A->geo = (int *)malloc(sizeof(int) * n);
+    A->tal = (int *)malloc(sizeof(int) * n);
+    A->wwc = (int *)malloc(sizeof(int) * n);
+    A->inq = (int *)malloc(sizeof(int) * n);
+    for (int i = 0; i + 1 < n; i++) {
+        double left = all[i], right = all[i + 1];
+        A->geo[i] = bin_of(p->planes[a], ng, left);
+        A->tal[i] = (p->n_mesh[a] == 0) ? 0 : bin_of(p->mesh[a], p->n_mesh[a], left);
+        A->wwc[i] = (p->n_ww[a] == 0) ? 0 : bin_of(p->ww[a], p->n_ww[a], left);
+        A->inq[i] = p->qoi_on ? (left >= p->qoi_lo[a] && right <= p->qoi_hi[a]) : 1;
+    }
+    return 0;
+}
+
+static void free_axis(axis_grid *A)
+{
+    free(A->P);
+    free(A->geo);
+    free(A->tal);
+    free(A->wwc);
+    free(A->inq);
+}
+
+/* Birth location: the cell i with P_i <= x < P_{i+1}; a particle born exactly
+ * on P_i moving towards -axis belongs to cell i-1; clamp to the domain cells. */
+static int locate(const axis_grid *A, double x, double u)
+{
+    int i = -1;
+    for (int j = 0; j < A->n; j++)
+        if (A->P[j] <= x) i = j;
+    if (i >= 0 && x == A->P[i] && u < 0.0) i = i - 1;
+    if (i < 0) i = 0;
+    if (i > A->n - 2) i = A->n - 2;
+    return i;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Neumaier compensated sums                                                  */
+/* ------------------------------------------------------------------------ */
+
+static void csum(double *s, double *c, double x)
+{
+    double t = *s + x;
+    if (fabs(*s) >= fabs(x))
+        *c += (*s - t) + x;
+    else
+        *c += (x - t) + *s;
+    *s = t;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Particle and per-run context                                               */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    double x[3], u[3], inv_u[3];
+    double t, tau, w;
+    int ix[3];
+    int g, k;
+    uint64_t s;
+} particle;
+
+typedef struct {
+    const oracle_problem *p;
+    axis_grid ax[3];
+    int K;              /* number of time bins */
+    int nt[3];          /* tally bins per axis */
+    int nw[3];          /* weight-window cells per axis */
+    int64_t ntally;     /* K * G * nt[2] * nt[1] * nt[0] */
+    int nc[3];          /* geometry cells per axis */
+    double *ps;         /* [M][G] Sigma_s,g / Sigma_t,g */
+    double *cdf;        /* [M][G][G] outgoing-group CDF */
+    double *src_cdf;    /* [G] */
+    /* outputs */
+    double *S, *Sc;     /* [B][ntally] raw sums + compensation */
+    double *L, *Lc;     /* [B][K][G][6] leak sums */
+    double q[2], qc[2]; /* detector: sum x, sum x^2 over histories */
+    uint64_t tot[9];    /* events: census, surface, collision; terminations
+                           absorb, leak, time, lost, roulette; splits */
+} ctx;
+
+static void isotropic(uint64_t *s, double u[3])
+{
+    for (;;) {
+        double a = 2.0 * rn(s) - 1.0;
+        double b = 2.0 * rn(s) - 1.0;
+        double r = a * a + b * b;
+        if (r < 1.0) {
+            double q = sqrt(1.0 - r);
+            u[0] = 1.0 - 2.0 * r;
+            u[1] = (2.0 * a) * q;
+            u[2] = (2.0 * b) * q;
+            return;
+        }
+    }
+}
+
+static void set_inv(particle *pt)
+{
+    for (int a = 0; a < 3; a++) pt->inv_u[a] = 1.0 / pt->u[a];
+}
+
+static int material_of(const ctx *C, const particle *pt)
+{
+    int c[3];
+    for (int a = 0; a < 3; a++) c[a] = (C->ax[a].n == 0) ? 0 : C->ax[a].geo[pt->ix[a]];
+    return C->p->material[((int64_t)c[2] * C->nc[1] + c[1]) * C->nc[0] + c[0]];
+}
+
+/* tally bin of the particle's union cell in the current (k, g), or -1 */
+static int64_t tally_bin(const ctx *C, const particle *pt)
+{
+    int t[3];
+    for (int a = 0; a < 3; a++) {
+        t[a] = (C->ax[a].n == 0) ? 0 : C->ax[a].tal[pt->ix[a]];
+        if (t[a] < 0) return -1;
+    }
+    return ((((int64_t)pt->k * C->p->G + pt->g) * C->nt[2] + t[2]) * C->nt[1] + t[1]) * C->nt[0] + t[0];
+}
+
+static int in_qoi(const ctx *C, const particle *pt)
+{
+    if (!C->p->qoi_on || !C->p->qoi_groups[pt->g]) return 0;
+    for (int a = 0; a < 3; a++)
+        if (C->ax[a].n != 0 && !C->ax[a].inq[pt->ix[a]]) return 0;
+    return 1;
+}
+
+/* weight-window centre of the particle's cell, 0 = no window */
+static double ww_center(const ctx *C, const particle *pt)
+{
+    if (!C->p->ww_center) return 0.0;
+    int c[3];
+    for (int a = 0; a < 3; a++) {
+        c[a] = (C->ax[a].n == 0) ? 0 : C->ax[a].wwc[pt->ix[a]];
+        if (c[a] < 0) return 0.0;
+    }
+    int64_t j = ((((int64_t)pt->k * C->p->G + pt->g) * C->nw[2] + c[2]) * C->nw[1] + c[1]) * C->nw[0] + c[0];
+    return C->p->ww_center[j];
+}
+
+/* ------------------------------------------------------------------------ */
+/* Per-history tracking                                                       */
+/* ------------------------------------------------------------------------ */
+
+#define STACK_MAX 4096
+
+typedef struct {
+    uint32_t n_census, n_surf, n_coll, n_particles, term_mask;
+    double track;   /* sum of w*d over all tallied segments */
+    double qoi;     /* detector score of this history */
+} hist_rec;
+
+/* R10: the weight-window game.  Returns 0 if the particle is killed. */
+static int ww_game(ctx *C, particle *pt, particle *stack, int *sp, hist_rec *h)
+{
+    double wc = ww_center(C, pt);
+    if (wc == 0.0) return 1;
+    double rho = C->p->ww_ratio;
+    double wl = (2.0 * wc) / (1.0 + rho);
+    double wu = rho * wl;
+    if (pt->w > wu) {
+        double nr = ceil(pt->w / wu);
+        int n = (nr > (double)C->p->ww_max_split) ? C->p->ww_max_split : (int)nr;
+        if (n > 1) {
+            pt->w = pt->w / (double)n;
+            for (int j = 1; j < n; j++) {
+                if (*sp >= STACK_MAX) return -1;
+                stack[*sp] = *pt;
+                stack[*sp].s = splitmix64(pt->s ^ (uint64_t)j) & MASK63;
+                (*sp)++;
+                h->n_particles++;
+                C->tot[8]++;
+            }
+        }
+    } else if (pt->w < wl) {
+        double xi = rn(&pt->s);
+        if (xi < pt->w / wc) {
+            pt->w = wc;
+        } else {
+            h->term_mask |= 1u << T_ROULETTE;
+            C->tot[3 + T_ROULETTE]++;
+            return 0;
+        }
+    }
+    return 1;
+}
+
+static void terminate(ctx *C, hist_rec *h, int code)
+{
+    h->term_mask |= 1u << code;
+    C->tot[3 + code]++;
+}
+
+/* One flight plus the event that ends it.  Returns 1 if the particle lives
+ * on, 0 if it terminated, -1 if split progeny overflow the stack.  If row is
+ * not NULL it receives (event, d, x, y, z, t, g, k, tau) after the event. */
+static int step(ctx *C, particle *pt, int b, particle *stack, int *sp, hist_rec *h, double *row)
+{
+    const oracle_problem *p = C->p;
+    const int G = p->G;
+    int m = material_of(C, pt);
+    double st = p->sigma_t[m * G + pt->g];
+
+    /* distance to collision */
+    double dc = (st == 0.0) ? INFINITY : pt->tau * (1.0 / st);
+    /* distance to the nearest union plane along each finite axis */
+    double da[3], ds = INFINITY;
+    for (int a = 0; a < 3; a++) {
+        da[a] = INFINITY;
+        if (C->ax[a].n == 0 || pt->u[a] == 0.0) continue;
+        double P = (pt->u[a] > 0.0) ? C->ax[a].P[pt->ix[a] + 1] : C->ax[a].P[pt->ix[a]];
+        double d = (P - pt->x[a]) * pt->inv_u[a];
+        if (d < 0.0) d = 0.0;
+        da[a] = d;
+        if (d < ds) ds = d;
+    }
+    /* distance to the next time-census edge */
+    double Tn = p->time_edges[pt->k + 1];
+    double dt = INFINITY;
+    if (Tn != INFINITY) {
+        dt = (Tn - pt->t) * p->speed[pt->g];
+        if (dt < 0.0) dt = 0.0;
+    }
+    /* R3 */
+    int ev;
+    double d;
+    if (dt <= ds && dt <= dc) {
+        ev = EV_CENSUS;
+        d = dt;
+    } else if (ds <= dc) {
+        ev = EV_SURFACE;
+        d = ds;
+    } else {
+        ev = EV_COLLISION;
+        d = dc;
+    }
+    if (row) {
+        row[0] = ev;
+        row[1] = d;
+    }
+    if (d == INFINITY) {
+        terminate(C, h, T_LOST);
+        return 0;
+    }
+
+    /* track-length score of the flight */
+    double sc = pt->w * d;
+    int64_t j = tally_bin(C, pt);
+    if (j >= 0) {
+        csum(&C->S[(int64_t)b * C->ntally + j], &C->Sc[(int64_t)b * C->ntally + j], sc);
+        h->track += sc;
+    }
+    if (in_qoi(C, pt)) h->qoi += sc;
+
+    /* move */
+    for (int a = 0; a < 3; a++) pt->x[a] = fma(d, pt->u[a], pt->x[a]);
+    if (ev == EV_CENSUS)
+        pt->t = Tn;
+    else
+        pt->t = pt->t + d * (1.0 / p->speed[pt->g]);
+    if (ev != EV_COLLISION && st != 0.0) {
+        pt->tau = pt->tau - d * st;
+        if (pt->tau < 0.0) pt->tau = 0.0;
+    }
+
+    int alive = 1;
+    if (ev == EV_CENSUS) {
+        h->n_census++;
+        C->tot[0]++;
+        pt->k++;
+        if (pt->k == C->K) {
+            terminate(C, h, T_TIME);
+            alive = 0;
+        } else {
+            alive = ww_game(C, pt, stack, sp, h);
+        }
+    } else if (ev == EV_SURFACE) {
+        h->n_surf++;
+        C->tot[1]++;
+        int wcell_changed = 0;
+        for (int a = 0; a < 3 && alive; a++) {
+            if (C->ax[a].n == 0 || da[a] != d) continue;
+            int last = C->ax[a].n - 2;
+            int old = pt->ix[a];
+            int face = -1;
+            if (pt->u[a] > 0.0) {
+                pt->x[a] = C->ax[a].P[pt->ix[a] + 1];
+                if (pt->ix[a] == last) face = 2 * a + 1;
+                else pt->ix[a]++;
+            } else {
+                pt->x[a] = C->ax[a].P[pt->ix[a]];
+                if (pt->ix[a] == 0) face = 2 * a;
+                else pt->ix[a]--;
+            }
+            if (face >= 0) {
+                if (p->bc[face] == 0) {
+                    int64_t l = (((int64_t)b * C->K + pt->k) * G + pt->g) * 6 + face;
+                    csum(&C->L[l], &C->Lc[l], pt->w);
+                    terminate(C, h, T_LEAK);
+                    alive = 0;
+                } else {
+                    pt->u[a] = -pt->u[a];
+                    pt->inv_u[a] = -pt->inv_u[a];
+                }
+            }
+            if (pt->ix[a] != old && C->ax[a].wwc[pt->ix[a]] != C->ax[a].wwc[old]) wcell_changed = 1;
+        }
+        if (alive && wcell_changed) alive = ww_game(C, pt, stack, sp, h);
+    } else {
+        h->n_coll++;
+        C->tot[2]++;
+        /* analog collision: scatter with probability Sigma_s,g / Sigma_t,g */
+        if (!(rn(&pt->s) < C->ps[m * G + pt->g])) {
+            terminate(C, h, T_ABSORB);
+            alive = 0;
+        } else {
+            double xg = rn(&pt->s);
+            const double *cdf = &C->cdf[((int64_t)m * G + pt->g) * G];
+            int g2 = 0;
+            while (!(xg < cdf[g2])) g2++;
+            pt->g = g2;
+            isotropic(&pt->s, pt->u);
+            set_inv(pt);
+            pt->tau = -log(1.0 - rn(&pt->s));
+            alive = ww_game(C, pt, stack, sp, h);
+        }
+    }
+    if (row) {
+        row[2] = pt->x[0];
+        row[3] = pt->x[1];
+        row[4] = pt->x[2];
+        row[5] = pt->t;
+        row[6] = pt->g;
+        row[7] = pt->k;
+        row[8] = pt->tau;
+    }
+    return alive;
+}
+
+/* Track one particle until it terminates (its split progeny go on the stack). */
+static int track(ctx *C, particle *pt, int b, particle *stack, int *sp, hist_rec *h)
+{
+    for (;;) {
+        int r = step(C, pt, b, stack, sp, h, NULL);
+        if (r <= 0) return r;
+    }
+}
+
+static int birth(ctx *C, uint64_t s0, particle *pt, hist_rec *h)
+{
+    const oracle_problem *p = C->p;
+    memset(pt, 0, sizeof(*pt));
+    pt->s = s0;
+    for (int a = 0; a < 3; a++) {
+        double xi = rn(&pt->s);
+        pt->x[a] = (C->ax[a].n == 0) ? 0.0 : p->src_lo[a] + xi * (p->src_hi[a] - p->src_lo[a]);
+    }
+    double xt = rn(&pt->s);
+    pt->t = p->src_t_lo + xt * (p->src_t_hi - p->src_t_lo);
+    double xg = rn(&pt->s);
+    int g = 0;
+    while (!(xg < C->src_cdf[g])) g++;
+    pt->g = g;
+    if (p->src_kind == 0) {
+        isotropic(&pt->s, pt->u);
+    } else {
+        double xm = rn(&pt->s);
+        double mu = (p->src_mu_law == 0) ? 1.0 : (p->src_mu_law == 1) ? 1.0 - xm : sqrt(1.0 - xm);
+        double a, b, r;
+        for (;;) {
+            a = 2.0 * rn(&pt->s) - 1.0;
+            b = 2.0 * rn(&pt->s) - 1.0;
+            r = a * a + b * b;
+            if (r > 0.0 && r < 1.0) break;
+        }
+        double cph = (a * a - b * b) / r;
+        double sph = ((2.0 * a) * b) / r;
+        double sn = sqrt(1.0 - mu * mu);
+        int ax = p->src_axis;
+        pt->u[ax] = (double)p->src_sign * mu;
+        pt->u[(ax + 1) % 3] = sn * cph;
+        pt->u[(ax + 2) % 3] = sn * sph;
+    }
+    set_inv(pt);
+    pt->tau = -log(1.0 - rn(&pt->s));
+    pt->w = 1.0;
+    for (int a = 0; a < 3; a++) pt->ix[a] = (C->ax[a].n == 0) ? 0 : locate(&C->ax[a], pt->x[a], pt->u[a]);
+    /* time bin */
+    if (pt->t >= p->time_edges[C->K]) {
+        terminate(C, h, T_TIME);
+        return 0;
+    }
+    int k = 0;
+    while (!(pt->t < p->time_edges[k + 1])) k++;
+    pt->k = k;
+    return 1;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Set-up                                                                     */
+/* ------------------------------------------------------------------------ */
+
+static int ctx_init(ctx *C, const oracle_problem *p)
+{
+    memset(C, 0, sizeof(*C));
+    C->p = p;
+    const int G = p->G, M = p->M;
+    C->K = p->n_time_edges - 1;
+    if (G < 1 || M < 1 || C->K < 1 || p->n_batches < 1) return -1;
+    for (int a = 0; a < 3; a++) {
+        if (build_axis(p, a, &C->ax[a]) != 0) return -1;
+        C->nc[a] = (p->n_planes[a] == 0) ? 1 : p->n_planes[a] - 1;
+        C->nt[a] = (p->n_mesh[a] == 0) ? 1 : p->n_mesh[a] - 1;
+        C->nw[a] = (p->n_ww[a] == 0) ? 1 : p->n_ww[a] - 1;
+    }
+    C->ntally = (int64_t)C->K * G * C->nt[0] * C->nt[1] * C->nt[2];
+    C->ps = (double *)calloc((size_t)M * G, sizeof(double));
+    C->cdf = (double *)calloc((size_t)M * G * G, sizeof(double));
+    C->src_cdf = (double *)calloc((size_t)G, sizeof(double));
+    for (int m = 0; m < M; m++)
+        for (int g = 0; g < G; g++) {
+            const double *row = &p->sigma_s[((int64_t)m * G + g) * G];
+            double ss = 0.0;
+            for (int g2 = 0; g2 < G; g2++) ss += row[g2];
+            double st = p->sigma_t[m * G + g];
+            C->ps[m * G + g] = (st > 0.0) ? ss / st : 0.0;
+            double run = 0.0;
+            int last = -1;
+            for (int g2 = 0; g2 < G; g2++) {
+                run += row[g2];
+                C->cdf[((int64_t)m * G + g) * G + g2] = (ss > 0.0) ? run / ss : 1.0;
+                if (row[g2] > 0.0) last = g2;
+            }
+            for (int g2 = (last < 0 ? 0 : last); g2 < G; g2++) C->cdf[((int64_t)m * G + g) * G + g2] = 1.0;
+        }
+    {
+        double run = 0.0;
+        int last = -1;
+        for (int g = 0; g < G; g++) {
+            run += p->src_pmf[g];
+            C->src_cdf[g] = run;
+            if (p->src_pmf[g] > 0.0) last = g;
+        }
+        if (last < 0) return -1;
+        for (int g = last; g < G; g++) C->src_cdf[g] = 1.0;
+    }
+    return 0;
+}
+
+static void ctx_free(ctx *C)
+{
+    for (int a = 0; a < 3; a++) free_axis(&C->ax[a]);
+    free(C->ps);
+    free(C->cdf);
+    free(C->src_cdf);
+    free(C->S);
+    free(C->Sc);
+    free(C->L);
+    free(C->Lc);
+}
+
+int64_t oracle_ntally(const oracle_problem *p)
+{
+    int64_t n = (int64_t)(p->n_time_edges - 1) * p->G;
+    for (int a = 0; a < 3; a++) n *= (p->n_mesh[a] == 0) ? 1 : p->n_mesh[a] - 1;
+    return n;
+}
+
+/* Union-grid planes of one axis, for inspection by the tests. */
+int oracle_union_planes(const oracle_problem *p, int axis, double *out, int cap)
+{
+    axis_grid A;
+    if (build_axis(p, axis, &A) != 0) return -1;
+    int n = A.n;
+    for (int j = 0; j < n && j < cap; j++) out[j] = A.P[j];
+    free_axis(&A);
+    return n;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Runs                                                                       */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * Run the histories listed in ids[0..n_ids) of an N-history job (ids==NULL:
+ * the contiguous range first..first+n_ids-1).  Accumulates raw per-batch
+ * tally sums S[B][ntally] and leak sums L[B][K][G][6] (both may be NULL),
+ * detector sums q[2] = (sum x, sum x^2), event and termination totals
+ * tot[9], and per-history records rec[n_ids][5] = (census, surface,
+ * collision, particles, termination mask) and per-history track and
+ * detector scores trk[n_ids][2].  Returns 0, or -1 on an invalid problem,
+ * -4 if split progeny overflow the per-history stack.
+ */
+int oracle_run(const oracle_problem *p, uint64_t N, uint64_t seed,
+               const uint64_t *ids, uint64_t first, uint64_t n_ids,
+               double *S_out, double *L_out, double *q_out, uint64_t *tot_out,
+               uint32_t *rec, double *trk)
+{
+    ctx C;
+    if (ctx_init(&C, p) != 0) {
+        ctx_free(&C);
+        return -1;
+    }
+    int64_t B = p->n_batches;
+    if ((uint64_t)B > N) B = (int64_t)N;
+    if (B < 1) B = 1;
+    const int G = p->G;
+    C.S = (double *)calloc((size_t)(B * C.ntally), sizeof(double));
+    C.Sc = (double *)calloc((size_t)(B * C.ntally), sizeof(double));
+    C.L = (double *)calloc((size_t)(B * C.K * G * 6), sizeof(double));
+    C.Lc = (double *)calloc((size_t)(B * C.K * G * 6), sizeof(double));
+    particle *stack = (particle *)malloc(sizeof(particle) * STACK_MAX);
+    int rc = 0;
+    uint64_t s0 = seed & MASK63;
+    for (uint64_t r = 0; r < n_ids; r++) {
+        uint64_t i = ids ? ids[r] : first + r;
+        int64_t b = (int64_t)(((i + 1) * (uint64_t)B - 1) / N);
+        hist_rec h;
+        memset(&h, 0, sizeof(h));
+        h.n_particles = 1;
+        particle pt;
+        int sp = 0;
+        if (birth(&C, oracle_rng_skip(s0, i * LCG_STRIDE), &pt, &h)) {
+            if (track(&C, &pt, (int)b, stack, &sp, &h) < 0) rc = -4;
+            while (sp > 0 && rc == 0) {
+                pt = stack[--sp];
+                if (track(&C, &pt, (int)b, stack, &sp, &h) < 0) rc = -4;
+            }
+        }
+        if (rc) break;
+        if (p->qoi_on) {
+            csum(&C.q[0], &C.qc[0], h.qoi);
+            csum(&C.q[1], &C.qc[1], h.qoi * h.qoi);
+        }
+        if (rec) {
+            rec[r * 5 + 0] = h.n_census;
+            rec[r * 5 + 1] = h.n_surf;
+            rec[r * 5 + 2] = h.n_coll;
+            rec[r * 5 + 3] = h.n_particles;
+            rec[r * 5 + 4] = h.term_mask;
+        }
+        if (trk) {
+            trk[r * 2 + 0] = h.track;
+            trk[r * 2 + 1] = h.qoi;
+        }
+    }
+    if (S_out)
+        for (int64_t j = 0; j < B * C.ntally; j++) S_out[j] += C.S[j] + C.Sc[j];
+    if (L_out)
+        for (int64_t j = 0; j < B * C.K * G * 6; j++) L_out[j] += C.L[j] + C.Lc[j];
+    if (q_out) {
+        q_out[0] += C.q[0] + C.qc[0];
+        q_out[1] += C.q[1] + C.qc[1];
+    }
+    if (tot_out)
+        for (int j = 0; j < 9; j++) tot_out[j] += C.tot[j];
+    free(stack);
+    ctx_free(&C);
+    return rc;
+}
+
+/* Event-by-event trace of history i (brute-force comparison on tiny inputs):
+ * one row of 9 doubles per event, (type, d, x, y, z, t, g, k, tau) after the
+ * event, then a final row (type = 10 + termination code).  Analog problems
+ * only.  Returns the row count, or -1 if the buffer is too small or the
+ * problem is invalid. */
+int oracle_trace(const oracle_problem *p, uint64_t N, uint64_t seed, uint64_t i, double *rows, int cap)
+{
+    ctx C;
+    if (ctx_init(&C, p) != 0 || cap < 1) {
+        ctx_free(&C);
+        return -1;
+    }
+    int64_t B = p->n_batches;
+    if ((uint64_t)B > N) B = (int64_t)N;
+    C.S = (double *)calloc((size_t)(B * C.ntally), sizeof(double));
+    C.Sc = (double *)calloc((size_t)(B * C.ntally), sizeof(double));
+    C.L = (double *)calloc((size_t)(B * C.K * p->G * 6), sizeof(double));
+    C.Lc = (double *)calloc((size_t)(B * C.K * p->G * 6), sizeof(double));
+    int b = (int)(((i + 1) * (uint64_t)B - 1) / N);
+    hist_rec h;
+    memset(&h, 0, sizeof(h));
+    particle pt;
+    int n = 0;
+    int alive = birth(&C, oracle_rng_skip(seed & MASK63, i * LCG_STRIDE), &pt, &h);
+    while (alive > 0) {
+        if (n + 1 >= cap) {
+            ctx_free(&C);
+            return -1;
+        }
+        int sp = 0;
+        alive = step(&C, &pt, b, NULL, &sp, &h, &rows[(int64_t)n * 9]);
+        n++;
+    }
+    double *r = &rows[(int64_t)n * 9];
+    int code = 0;
+    while (!(h.term_mask & (1u << code))) code++;
+    r[0] = 10 + code;
+    r[1] = 0.0;
+    r[2] = pt.x[0];
+    r[3] = pt.x[1];
+    r[4] = pt.x[2];
+    r[5] = pt.t;
+    r[6] = pt.g;
+    r[7] = pt.k;
+    r[8] = pt.tau;
+    n++;
+    ctx_free(&C);
+    return n;
+}

@@ -1,0 +1,328 @@
+"""Seeded synthetic problem generators for the multigroup time-dependent
+fixed-source transport problems this project solves.
+
+This module only *describes* problems: cross sections, plane positions,
+material maps, source and tally definitions, as plain NumPy arrays in a dict.
+It holds none of the transport method's arithmetic (no union grid, no derived
+tables, no sampling), so that both the GPU library and the CPU oracle can be
+fed from it without sharing any of their computation.
+
+Random problem content (cross sections, material masks, problem sizes) is
+drawn from SplitMix64 (Steele, Lea & Flood, "Fast splittable pseudorandom
+number generators", OOPSLA 2014) implemented here in plain Python integers, so
+the generated problems do not depend on the NumPy version.
+
+Problem dict schema (all floats are float64, all ints int32):
+
+    sigma_t   [M, G]      total cross section per material and group
+    sigma_s   [M, G, G]   scattering cross section, row g = from, col g' = to
+    speed     [G]         particle speed per group
+    planes    list of 3 arrays: geometry planes per axis (x, y, z), strictly
+              increasing; an empty array means the axis is infinite
+    material  [nz, ny, nx] material id of each geometry cell (an infinite
+              axis has one cell)
+    bc        [6]         boundary condition of the faces x-, x+, y-, y+, z-,
+              z+: 0 = vacuum, 1 = reflective
+    source    dict: lo[3], hi[3] (box; a degenerate extent is a point or a
+              plane), t_lo, t_hi (emission time window), group_pmf[G],
+              kind 'isotropic' (volume/point, isotropic) or 'surface'
+              (axis, sign = direction of the inward normal, mu_law in
+              'beam' | 'uniform' | 'cosine')
+    tally     dict: mesh list of 3 arrays (empty = one bin spanning the
+              axis), time_edges[K+1] (last may be +inf), n_batches
+    qoi       None or dict: lo[3], hi[3], group_mask[G]
+    ww_mesh   None or list of 3 arrays of weight-window mesh planes
+
+The workload recipes follow the transport problems the method is exercised
+on (Section 3): slab benchmarks with closed forms, a pulsed slab (the
+time-dependent, AZURV1-like pulse with c < 1), a C5G7-like 17x17 lattice with
+synthetic multigroup data, a batch of random lattices, and a Kobayashi-like
+dog-leg duct. None of these reproduce benchmark data; all are synthetic.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+MASK64 = (1 << 64) - 1
+
+VACUUM = 0
+REFLECTIVE = 1
+
+
+class SplitMix64:
+    """SplitMix64 generator (Steele, Lea & Flood 2014), Python integers."""
+
+    def __init__(self, seed: int):
+        self.state = seed & MASK64
+
+    def next_u64(self) -> int:
+        self.state = (self.state + 0x9E3779B97F4A7C15) & MASK64
+        z = self.state
+        z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & MASK64
+        z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & MASK64
+        return z ^ (z >> 31)
+
+    def uniform(self, lo: float = 0.0, hi: float = 1.0) -> float:
+        return lo + (hi - lo) * ((self.next_u64() >> 11) * (1.0 / (1 << 53)))
+
+    def randint(self, lo: int, hi: int) -> int:
+        """Uniform integer in [lo, hi] inclusive."""
+        return lo + self.next_u64() % (hi - lo + 1)
+
+
+def _f64(a):
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+def _empty():
+    return np.zeros(0, dtype=np.float64)
+
+
+def make_problem(sigma_t, sigma_s, speed, planes, material, bc, source, tally,
+                 qoi=None, ww_mesh=None):
+    sigma_t = _f64(sigma_t)
+    M, G = sigma_t.shape
+    src = dict(source)
+    src.setdefault("t_lo", 0.0)
+    src.setdefault("t_hi", 0.0)
+    src.setdefault("kind", "isotropic")
+    src["lo"] = _f64(src["lo"])
+    src["hi"] = _f64(src["hi"])
+    src["group_pmf"] = _f64(src["group_pmf"])
+    tal = dict(tally)
+    tal["mesh"] = [_f64(m) for m in tal["mesh"]]
+    tal["time_edges"] = _f64(tal["time_edges"])
+    tal.setdefault("n_batches", 32)
+    p = {
+        "sigma_t": sigma_t,
+        "sigma_s": _f64(sigma_s).reshape(M, G, G),
+        "speed": _f64(speed),
+        "planes": [_f64(pl) for pl in planes],
+        "material": np.ascontiguousarray(np.asarray(material, dtype=np.int32)),
+        "bc": np.asarray(bc, dtype=np.int32),
+        "source": src,
+        "tally": tal,
+        "qoi": None,
+        "ww_mesh": None,
+    }
+    if qoi is not None:
+        p["qoi"] = {"lo": _f64(qoi["lo"]), "hi": _f64(qoi["hi"]),
+                    "group_mask": np.asarray(qoi["group_mask"], dtype=np.int32)}
+    if ww_mesh is not None:
+        p["ww_mesh"] = [_f64(m) for m in ww_mesh]
+    return p
+
+
+# ---------------------------------------------------------------------------
+# 1-D slabs
+# ---------------------------------------------------------------------------
+
+def slab(thickness=10.0, sigma_t=1.0, sigma_s=0.5, speed=1.0, n_bins=20,
+         source="surface", mu_law="cosine", x_src=0.0, time_edges=None,
+         bc=(VACUUM, VACUUM), n_batches=32, t_hi=0.0):
+    """One-group slab x in [0, thickness], infinite in y and z.
+
+    source='surface': surface source on the x- face, entering along +x with
+    the given angular law.  source='plane': isotropic plane source at x_src.
+    """
+    planes = [np.array([0.0, thickness]), _empty(), _empty()]
+    mesh_x = np.linspace(0.0, thickness, n_bins + 1)
+    if time_edges is None:
+        time_edges = np.array([0.0, math.inf])
+    if source == "surface":
+        src = {"kind": "surface", "axis": 0, "sign": 1, "mu_law": mu_law,
+               "lo": [0.0, 0.0, 0.0], "hi": [0.0, 0.0, 0.0]}
+    else:
+        src = {"kind": "isotropic", "lo": [x_src, 0.0, 0.0],
+               "hi": [x_src, 0.0, 0.0]}
+    src.update({"group_pmf": [1.0], "t_lo": 0.0, "t_hi": t_hi})
+    return make_problem(
+        sigma_t=[[sigma_t]], sigma_s=[[[sigma_s]]], speed=[speed],
+        planes=planes, material=np.zeros((1, 1, 1)),
+        bc=[bc[0], bc[1], VACUUM, VACUUM, VACUUM, VACUUM],
+        source=src,
+        tally={"mesh": [mesh_x, _empty(), _empty()], "time_edges": time_edges,
+               "n_batches": n_batches})
+
+
+def cfg1_slab_steady(c=0.5, mu_law="cosine", n_batches=32):
+    """Slab of 10 mfp, Sigma_t = 1, scattering ratio c, surface source at x=0,
+    20 tally bins, steady state (one time bin [0, inf))."""
+    return slab(thickness=10.0, sigma_t=1.0, sigma_s=c, n_bins=20,
+                source="surface", mu_law=mu_law, n_batches=n_batches)
+
+
+def cfg2_slab_pulse(c=0.9, n_batches=32):
+    """Slab of 40 mfp, Sigma_t = 1, v = 1, isotropic pulse plane source at the
+    centre x = 20 at t = 0; 50 spatial bins x 100 time bins over [0, 20]."""
+    return slab(thickness=40.0, sigma_t=1.0, sigma_s=c, speed=1.0, n_bins=50,
+                source="plane", x_src=20.0,
+                time_edges=np.linspace(0.0, 20.0, 101), n_batches=n_batches)
+
+
+# ---------------------------------------------------------------------------
+# Multigroup box lattices
+# ---------------------------------------------------------------------------
+
+def synthetic_xs(rng: SplitMix64, n_groups: int):
+    """One synthetic multigroup material: Sigma_t,g uniform in [0.2, 2.0],
+    scattering ratio c_g uniform in [0.3, 0.9], downscatter-only transfer
+    (row g spread over g' >= g with random weights; the last group only
+    self-scatters)."""
+    G = n_groups
+    st = np.zeros(G)
+    ss = np.zeros((G, G))
+    for g in range(G):
+        st[g] = rng.uniform(0.2, 2.0)
+        c = rng.uniform(0.3, 0.9)
+        wts = np.array([rng.uniform(0.05, 1.0) for _ in range(g, G)])
+        wts = wts / wts.sum()
+        ss[g, g:] = c * st[g] * wts
+    return st, ss
+
+
+def lattice(n=17, pitch=1.26, height=50.0, n_groups=7, n_materials=2,
+            n_z_bins=10, n_time_bins=20, t_end=20.0, gen_seed=3,
+            bc_xy=REFLECTIVE, bc_z=VACUUM, n_batches=32, homogeneous=False):
+    """n x n box lattice of square cells of the given pitch, one geometry
+    layer of the given height, materials assigned by a seeded Bernoulli(1/2)
+    mask, synthetic XS, speeds v_g = G - g, a uniform volume pulse source at
+    t = 0 in group 0, and a mesh tally n x n x n_z_bins x G x n_time_bins."""
+    rng = SplitMix64(gen_seed)
+    G = n_groups
+    M = 1 if homogeneous else n_materials
+    st = np.zeros((M, G))
+    ss = np.zeros((M, G, G))
+    for m in range(M):
+        st[m], ss[m] = synthetic_xs(rng, G)
+    px = np.arange(n + 1) * pitch
+    pz = np.array([0.0, height])
+    mat = np.zeros((1, n, n), dtype=np.int32)
+    if not homogeneous:
+        for j in range(n):
+            for i in range(n):
+                mat[0, j, i] = rng.next_u64() & 1
+    speed = np.array([float(G - g) for g in range(G)])
+    pmf = np.zeros(G)
+    pmf[0] = 1.0
+    src = {"kind": "isotropic", "lo": [px[0], px[0], pz[0]],
+           "hi": [px[-1], px[-1], pz[-1]], "group_pmf": pmf,
+           "t_lo": 0.0, "t_hi": 0.0}
+    tally = {"mesh": [px, px, np.linspace(0.0, height, n_z_bins + 1)],
+             "time_edges": np.linspace(0.0, t_end, n_time_bins + 1),
+             "n_batches": n_batches}
+    return make_problem(st, ss, speed, [px, px, pz], mat,
+                        [bc_xy, bc_xy, bc_xy, bc_xy, bc_z, bc_z], src, tally)
+
+
+def cfg3_lattice(n_batches=32):
+    """17x17x1 lattice of 1.26 cells, 2 materials, 7 groups, reflective x/y,
+    vacuum z (height 50); tally 17x17x10 x 7 groups x 20 time bins."""
+    return lattice(n=17, gen_seed=3, n_batches=n_batches)
+
+
+def cfg4_batch(n_problems=256, seed=1000):
+    """Random lattices for the batched solve: n ~ U{4..32}, G ~ U{1..7},
+    histories ~ round(10**(4 + 2 xi)). Returns (problems, n_histories)."""
+    probs, nh = [], []
+    for p in range(n_problems):
+        rng = SplitMix64(seed + p)
+        n = rng.randint(4, 32)
+        G = rng.randint(1, 7)
+        xi = rng.uniform()
+        nh.append(int(round(10.0 ** (4.0 + 2.0 * xi))))
+        probs.append(lattice(n=n, n_groups=G, gen_seed=seed + p + 100000))
+    return probs, nh
+
+
+# ---------------------------------------------------------------------------
+# Deep-penetration dog-leg duct (Kobayashi-like, synthetic)
+# ---------------------------------------------------------------------------
+
+def cfg5_dogleg(n_batches=32):
+    """Box [0,30]x[0,10]x[0,10], vacuum on all faces, 2 groups.
+    Bulk: Sigma_t = (1.0, 1.5), c = (0.8, 0.6), Sigma_s[0][0] = Sigma_s[0][1]
+    = 0.4, Sigma_s[1][1] = 0.9.  A 2-unit-wide low-density dog-leg channel
+    (Sigma_t = 0.05, same c and transfer split) at z in [4,6]: leg A x in
+    [0,12], y in [1,3]; leg B x in [10,12], y in [1,9]; leg C x in [10,30],
+    y in [7,9].  Source box x in [0,1], y in [1,3], z in [4,6], group 0,
+    isotropic, steady.  Detector (quantity of interest) x in [29,30],
+    y in [7,9], z in [4,6], both groups.  Tally and weight-window mesh
+    40 x 10 x 10 (cells 0.75 x 1 x 1)."""
+    st_bulk = np.array([1.0, 1.5])
+    ss_bulk = np.array([[0.4, 0.4], [0.0, 0.9]])
+    scale = 0.05 / st_bulk
+    st_ch = np.array([0.05, 0.05])
+    ss_ch = ss_bulk * scale[:, None]
+    st = np.stack([st_bulk, st_ch])
+    ss = np.stack([ss_bulk, ss_ch])
+    px = np.array([0.0, 10.0, 12.0, 30.0])
+    py = np.array([0.0, 1.0, 3.0, 7.0, 9.0, 10.0])
+    pz = np.array([0.0, 4.0, 6.0, 10.0])
+    mat = np.zeros((3, 5, 3), dtype=np.int32)
+    # cell index: x cells [0,10],[10,12],[12,30]; y cells [0,1],[1,3],[3,7],
+    # [7,9],[9,10]; z cells [0,4],[4,6],[6,10]
+    kz = 1
+    mat[kz, 1, 0] = 1          # leg A, x in [0,10]
+    mat[kz, 1, 1] = 1          # leg A, x in [10,12]
+    mat[kz, 2, 1] = 1          # leg B, y in [3,7]
+    mat[kz, 3, 1] = 1          # leg B / C corner, y in [7,9]
+    mat[kz, 3, 2] = 1          # leg C, x in [12,30]
+    src = {"kind": "isotropic", "lo": [0.0, 1.0, 4.0], "hi": [1.0, 3.0, 6.0],
+           "group_pmf": [1.0, 0.0], "t_lo": 0.0, "t_hi": 0.0}
+    mesh = [np.arange(41) * 0.75, np.arange(11) * 1.0, np.arange(11) * 1.0]
+    tally = {"mesh": mesh, "time_edges": [0.0, math.inf],
+             "n_batches": n_batches}
+    qoi = {"lo": [29.0, 7.0, 4.0], "hi": [30.0, 9.0, 6.0],
+           "group_mask": [1, 1]}
+    return make_problem(st, ss, [1.0, 1.0], [px, py, pz], mat,
+                        [VACUUM] * 6, src, tally, qoi=qoi, ww_mesh=mesh)
+
+
+# ---------------------------------------------------------------------------
+# Small problems used by closed-form checks
+# ---------------------------------------------------------------------------
+
+def reflective_box(sigma_t, sigma_s, speed, size=(2.0, 2.0, 2.0),
+                   time_edges=None, n_batches=32, pulse=True):
+    """Homogeneous all-reflective box (an infinite medium), uniform volume
+    source in group 0, one tally bin per axis."""
+    st = _f64(sigma_t).reshape(1, -1)
+    G = st.shape[1]
+    planes = [np.array([0.0, s]) for s in size]
+    pmf = np.zeros(G)
+    pmf[0] = 1.0
+    if time_edges is None:
+        time_edges = [0.0, math.inf]
+    src = {"kind": "isotropic", "lo": [0.0, 0.0, 0.0], "hi": list(size),
+           "group_pmf": pmf, "t_lo": 0.0, "t_hi": 0.0}
+    tally = {"mesh": [np.array([0.0, s]) for s in size],
+             "time_edges": time_edges, "n_batches": n_batches}
+    return make_problem(st, _f64(sigma_s).reshape(1, G, G), speed, planes,
+                        np.zeros((1, 1, 1)), [REFLECTIVE] * 6, src, tally)
+
+
+def void_box(size=(3.0, 2.0, 1.0), n_mesh=(3, 2, 1), src_point=(0.5, 0.5, 0.5),
+             time_edges=None, speed=1.0, bc=None):
+    """Void (Sigma_t = 0) box with an isotropic point source: every track is
+    deterministic given its direction."""
+    planes = [np.array([0.0, s]) for s in size]
+    mesh = [np.linspace(0.0, s, n + 1) for s, n in zip(size, n_mesh)]
+    if time_edges is None:
+        time_edges = [0.0, math.inf]
+    src = {"kind": "isotropic", "lo": list(src_point), "hi": list(src_point),
+           "group_pmf": [1.0], "t_lo": 0.0, "t_hi": 0.0}
+    return make_problem([[0.0]], [[[0.0]]], [speed], planes,
+                        np.zeros((1, 1, 1)), bc if bc is not None else [VACUUM] * 6,
+                        src, {"mesh": mesh, "time_edges": time_edges,
+                              "n_batches": 8})
+
+
+CONFIGS = {
+    "cfg1": cfg1_slab_steady,
+    "cfg2": cfg2_slab_pulse,
+    "cfg3": cfg3_lattice,
+    "cfg5": cfg5_dogleg,
+}
