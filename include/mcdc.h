@@ -1,0 +1,247 @@
+/*
+ * mcdc.h -- C ABI of the MI355X (gfx950) multigroup, time-dependent Monte
+ * Carlo particle tracker.
+ *
+ * The operation is the fixed-source, multigroup, time-dependent neutron
+ * transport the paper describes in words (Section 3): multigroup materials
+ * (group-wise total cross section, isotropic scattering through a group-to-
+ * group transfer matrix), a time-dependent source, time census, and
+ * time-dependent mesh tallies scored with the track-length estimator of the
+ * time-averaged flux (Section 3.1).  Analog tracking means uniform particle
+ * weight and no variance reduction (Section 3.3).  The tracking runs in two
+ * forms the paper names (Section 2): history-based (one GPU thread follows
+ * one particle to its death) and event-based (particles are sorted into
+ * per-event queues and processed event kernel by event kernel).
+ *
+ * Conventions shared by every entry point
+ *  - Units are arbitrary but consistent (length, 1/length, length/time,
+ *    time).  Group 0 is the fastest group.
+ *  - Every array in a descriptor is copied during the call; the caller may
+ *    free it afterwards.  The library never frees caller memory.
+ *  - Return value: MCDC_OK (0) or a negative MCDC_E_* code; the message of
+ *    the last failure on the calling thread is mcdc_last_error().
+ *  - A problem handle is used by one host thread at a time.
+ *  - Random numbers: each history i of a run with seed s draws from its own
+ *    63-bit linear congruential stream starting at s skipped ahead by
+ *    i * 152917 steps, so results depend only on (problem, N, seed), never
+ *    on the algorithm, launch shape or GPU.
+ */
+#ifndef MCDC_H
+#define MCDC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MCDC_ABI_VERSION 1
+
+/* return codes */
+#define MCDC_OK 0
+#define MCDC_E_INVALID -1     /* bad descriptor or argument (message says which) */
+#define MCDC_E_HIP -2         /* a HIP runtime call failed */
+#define MCDC_E_NOMEM -3       /* device or host allocation failed */
+#define MCDC_E_OVERFLOW -4    /* particle bank, queue or split bank overflowed */
+#define MCDC_E_UNSUPPORTED -5 /* valid request this build does not support */
+
+/* boundary conditions of the six domain faces x-, x+, y-, y+, z-, z+ */
+#define MCDC_VACUUM 0
+#define MCDC_REFLECTIVE 1
+
+/* source kinds and angular laws of a surface source */
+#define MCDC_SRC_ISOTROPIC 0 /* volume, plane or point source, isotropic */
+#define MCDC_SRC_SURFACE 1   /* enters through a face with the given law */
+#define MCDC_MU_BEAM 0       /* mu = 1 */
+#define MCDC_MU_UNIFORM 1    /* mu uniform on (0, 1] */
+#define MCDC_MU_COSINE 2     /* isotropic incident flux: pdf 2 mu */
+
+/* tracking algorithms */
+#define MCDC_ALG_EVENT 0
+#define MCDC_ALG_HISTORY 1
+
+typedef struct mcdc_problem mcdc_problem;
+
+/*
+ * Problem descriptor (Section 3: fixed-source transport on box geometry
+ * with multigroup physics, time-dependent source and mesh tallies).
+ *
+ * Materials: sigma_t[M][G] >= 0; sigma_s[M][G][G] >= 0 with row g the
+ * outgoing distribution from group g (sum over g' <= sigma_t[m][g]);
+ * speed[G] > 0.  A zero sigma_t is a void.
+ *
+ * Geometry: per axis a (x, y, z) n_planes[a] strictly increasing plane
+ * positions planes[a]; n_planes[a] == 0 makes the axis infinite (a 1-D slab
+ * has planes only along x).  The outermost planes bound the domain.
+ * material[cz][cy][cx] gives the material of each geometry cell (cx runs
+ * over n_planes[0]-1 cells, or 1 cell on an infinite axis).  bc[6] are the
+ * face conditions.
+ *
+ * Source: src_kind ISOTROPIC samples position uniformly in the box
+ * [src_lo, src_hi] (a degenerate extent is a plane or a point; ignored on
+ * infinite axes) and an isotropic direction.  src_kind SURFACE places the
+ * particle the same way and gives it direction cosine mu (src_mu_law)
+ * about the axis src_axis, pointing along src_sign (+1 or -1), with a
+ * uniform azimuth.  Emission time is uniform on [src_t_lo, src_t_hi]; the
+ * group is drawn from src_group_pmf[G] (sum 1 within 1e-12).
+ *
+ * Tally: mesh planes per axis (0 planes = one bin spanning the axis, with
+ * width factor 1), strictly increasing and inside the domain; time edges
+ * T_0 < ... < T_K (T_K may be +inf; T_0 <= src_t_lo) are both the tally
+ * time bins and the census grid; n_batches >= 1 contiguous batches give
+ * the variance.  The tally holds the time-averaged scalar flux per source
+ * particle, shape [K][G][nz][ny][nx].
+ *
+ * Detector (optional, qoi_enabled = 1): a box [qoi_lo, qoi_hi] and a group
+ * mask qoi_group_mask[G]; its flux is tallied per history so its variance
+ * is the history variance (used for the figure of merit).
+ *
+ * Weight-window mesh (optional): planes per axis (0 = one window cell);
+ * the window centres are set with mcdc_set_weight_windows.
+ */
+typedef struct {
+    int32_t abi_version; /* MCDC_ABI_VERSION */
+    int32_t n_groups;
+    int32_t n_materials;
+    const double *sigma_t;
+    const double *sigma_s;
+    const double *speed;
+    int32_t n_planes[3];
+    const double *planes[3];
+    const int32_t *material;
+    int32_t bc[6];
+    int32_t src_kind;
+    int32_t src_axis;
+    int32_t src_sign;
+    int32_t src_mu_law;
+    double src_lo[3];
+    double src_hi[3];
+    double src_t_lo;
+    double src_t_hi;
+    const double *src_group_pmf;
+    int32_t n_mesh_planes[3];
+    const double *mesh_planes[3];
+    int32_t n_time_edges;
+    const double *time_edges;
+    int32_t n_batches;
+    int32_t qoi_enabled;
+    double qoi_lo[3];
+    double qoi_hi[3];
+    const int32_t *qoi_group_mask;
+    int32_t n_ww_planes[3];
+    const double *ww_planes[3];
+} mcdc_problem_desc;
+
+/*
+ * Run options (all-zero = defaults).
+ *  algorithm      MCDC_ALG_EVENT (default) or MCDC_ALG_HISTORY.
+ *  block_size     threads per block, 0 = tuned default (64..1024, multiple of 64).
+ *  bank_capacity  event form: particles resident at once (0 = auto).  Work
+ *                 is processed in chunks of this many histories.
+ *  tail_threshold event form: when fewer particles than this remain active
+ *                 in a census step, the rest are finished by one in-register
+ *                 pass (0 = auto, -1 = never).
+ *  stream         hipStream_t to run on (NULL = the null stream).  mcdc_run
+ *                 synchronises this stream before it returns.
+ *  debug_counts   device array [N][5] (census, surface, collision events,
+ *                 particles, termination mask per history) or NULL.
+ *  debug_scores   device array [N][2] (tallied track and detector score per
+ *                 history) or NULL.
+ */
+typedef struct {
+    int32_t algorithm;
+    int32_t block_size;
+    int64_t bank_capacity;
+    int32_t tail_threshold;
+    int32_t reserved;
+    void *stream;
+    uint32_t *debug_counts;
+    double *debug_scores;
+} mcdc_run_options;
+
+/*
+ * Results.  Array outputs are caller-allocated and are device pointers
+ * (hipMalloc or a torch CUDA tensor) unless host_outputs is 1; any may be
+ * NULL to skip it.  Scalars are filled on the host.
+ *  mean[ntally], var[ntally]   normalised bin flux and its batch variance:
+ *                              mean = sum_b S_b / (N V dt), var of the
+ *                              batch means m_b = S_b / (N_b V dt).
+ *  raw[ntally]                 unnormalised sum of w*d per bin.
+ *  leak_mean/leak_var[K][G][6] weight leaked through each face per source
+ *                              particle, and its batch variance.
+ *  qoi_sum[2]                  detector sum x and sum x^2 over histories
+ *                              (x = the history's track in the detector).
+ *  qoi_mean, qoi_var           detector flux per source particle and the
+ *                              variance of that mean (history variance).
+ *  n_events                    census, surface and collision events.
+ *  n_term                      terminations: absorbed, leaked, time cut-off,
+ *                              lost (infinite flight), rouletted.
+ *  n_splits                    weight-window split progeny created.
+ *  kernel_ms                   device time of the run (HIP events).
+ */
+typedef struct {
+    int32_t host_outputs;
+    int32_t reserved;
+    double *mean;
+    double *var;
+    double *raw;
+    double *leak_mean;
+    double *leak_var;
+    double qoi_sum[2];
+    double qoi_mean;
+    double qoi_var;
+    uint64_t n_events[3];
+    uint64_t n_term[5];
+    uint64_t n_splits;
+    double kernel_ms;
+} mcdc_result;
+
+/*
+ * Validate a descriptor and compile it: merge geometry, tally, detector and
+ * weight-window planes per axis into one union grid (exact de-duplication),
+ * derive the per-cell material/tally tables and the cross-section tables
+ * (1/sigma_t, scattering probability, outgoing-group CDF, 1/speed), and
+ * upload them to the current HIP device.  *out is owned by the caller and
+ * released with mcdc_problem_destroy.  Errors: MCDC_E_INVALID (message
+ * names the field), MCDC_E_NOMEM, MCDC_E_HIP.
+ */
+int mcdc_problem_create(const mcdc_problem_desc *desc, mcdc_problem **out);
+
+/* Release a problem and all device memory it owns.  NULL is a no-op. */
+int mcdc_problem_destroy(mcdc_problem *p);
+
+/* Tally shape [K][G][nz][ny][nx] into shape[5]; returns the element count
+ * in *ntally if ntally is not NULL. */
+int mcdc_problem_tally_shape(const mcdc_problem *p, int64_t shape[5], int64_t *ntally);
+
+/*
+ * Track n_histories source particles with the given seed (Section 3
+ * fixed-source transport, Section 3.1 track-length tally) and fill *out.
+ * opt == NULL means defaults.  Both algorithms give the same per-history
+ * event sequence for the same (problem, n_histories, seed); tallies differ
+ * only by floating-point summation order.  Errors: MCDC_E_INVALID (NULL
+ * problem or result, n_histories == 0, bad option), MCDC_E_OVERFLOW,
+ * MCDC_E_NOMEM, MCDC_E_HIP.
+ */
+int mcdc_run(mcdc_problem *p, uint64_t n_histories, uint64_t seed,
+             const mcdc_run_options *opt, mcdc_result *out);
+
+/*
+ * Set weight-window centres for later runs: centers[K][G][wz][wy][wx] over
+ * the weight-window mesh (0 = no window in that cell); ratio rho > 1 sets
+ * the window [2 w_c / (1 + rho), 2 rho w_c / (1 + rho)] with survival weight
+ * w_c; a particle above the window splits into min(ceil(w / w_U),
+ * max_split) copies.  centers == NULL returns the problem to analog
+ * tracking.  The table is copied.
+ */
+int mcdc_set_weight_windows(mcdc_problem *p, const double *centers, double ratio,
+                            int32_t max_split);
+
+/* Message of the last failure on the calling thread ("" if none). */
+const char *mcdc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MCDC_H */

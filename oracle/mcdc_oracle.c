@@ -262,8 +262,15 @@ typedef struct {
     double t, tau, w;
     int ix[3];
     int g, k;
+    int since;      /* events since birth or the last census */
     uint64_t s;
 } particle;
+
+/* A particle with this many events since its last census (or birth) is
+ * killed as lost: a guard against problems that trap a particle forever
+ * (e.g. a pure scatterer enclosed by reflective faces with no time limit).
+ * Normal problems never come near it. */
+#define MAX_EVENTS_PER_STEP (1 << 20)
 
 typedef struct {
     const oracle_problem *p;
@@ -404,6 +411,15 @@ static int step(ctx *C, particle *pt, int b, particle *stack, int *sp, hist_rec 
 {
     const oracle_problem *p = C->p;
     const int G = p->G;
+    if (pt->since >= MAX_EVENTS_PER_STEP) {
+        if (row) {
+            row[0] = EV_COLLISION;
+            row[1] = INFINITY;
+        }
+        terminate(C, h, T_LOST);
+        return 0;
+    }
+    pt->since++;
     int m = material_of(C, pt);
     double st = p->sigma_t[m * G + pt->g];
 
@@ -473,6 +489,7 @@ static int step(ctx *C, particle *pt, int b, particle *stack, int *sp, hist_rec 
     if (ev == EV_CENSUS) {
         h->n_census++;
         C->tot[0]++;
+        pt->since = 0;
         pt->k++;
         if (pt->k == C->K) {
             terminate(C, h, T_TIME);

@@ -1,0 +1,10 @@
+"""MI355X-native multigroup, time-dependent Monte Carlo particle tracker.
+
+The tracking runs in hand-written HIP kernels for gfx950 behind the C ABI
+declared in include/mcdc.h (libmcdc_hip.so, built in-tree).  This package
+is the thin Python binding: the same entry-point names, PyTorch tensors for
+device memory and the stream, and nothing else.
+"""
+from ._binding import (MCDCError, Problem, lib, mcdc_problem_create,  # noqa: F401
+                       mcdc_problem_destroy, mcdc_problem_tally_shape, mcdc_run,
+                       mcdc_set_weight_windows)

@@ -1,0 +1,265 @@
+"""ctypes binding of libmcdc_hip.so (the C ABI in include/mcdc.h).
+
+Argument marshalling only: every step of the transport runs in the HIP
+library.  Device buffers and the stream come from PyTorch.  The library must
+be built (``__graft_entry__.build()`` or ``python -m
+paper_2305_07636_amd.build``); importing this module on a machine without
+it raises, there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmcdc_hip.so")
+
+MCDC_ABI_VERSION = 1
+MCDC_OK, MCDC_E_INVALID, MCDC_E_HIP, MCDC_E_NOMEM, MCDC_E_OVERFLOW, MCDC_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5
+MCDC_ALG_EVENT, MCDC_ALG_HISTORY = 0, 1
+MCDC_SRC_ISOTROPIC, MCDC_SRC_SURFACE = 0, 1
+MU_LAWS = {"beam": 0, "uniform": 1, "cosine": 2}
+
+EXPORTS = ["mcdc_problem_create", "mcdc_problem_destroy", "mcdc_problem_tally_shape",
+           "mcdc_run", "mcdc_set_weight_windows", "mcdc_last_error"]
+
+_DP = C.POINTER(C.c_double)
+_IP = C.POINTER(C.c_int32)
+
+
+class mcdc_problem_desc(C.Structure):
+    _fields_ = [
+        ("abi_version", C.c_int32), ("n_groups", C.c_int32), ("n_materials", C.c_int32),
+        ("sigma_t", _DP), ("sigma_s", _DP), ("speed", _DP),
+        ("n_planes", C.c_int32 * 3), ("planes", _DP * 3),
+        ("material", _IP), ("bc", C.c_int32 * 6),
+        ("src_kind", C.c_int32), ("src_axis", C.c_int32), ("src_sign", C.c_int32),
+        ("src_mu_law", C.c_int32),
+        ("src_lo", C.c_double * 3), ("src_hi", C.c_double * 3),
+        ("src_t_lo", C.c_double), ("src_t_hi", C.c_double),
+        ("src_group_pmf", _DP),
+        ("n_mesh_planes", C.c_int32 * 3), ("mesh_planes", _DP * 3),
+        ("n_time_edges", C.c_int32), ("time_edges", _DP),
+        ("n_batches", C.c_int32),
+        ("qoi_enabled", C.c_int32), ("qoi_lo", C.c_double * 3), ("qoi_hi", C.c_double * 3),
+        ("qoi_group_mask", _IP),
+        ("n_ww_planes", C.c_int32 * 3), ("ww_planes", _DP * 3),
+    ]
+
+
+class mcdc_run_options(C.Structure):
+    _fields_ = [
+        ("algorithm", C.c_int32), ("block_size", C.c_int32), ("bank_capacity", C.c_int64),
+        ("tail_threshold", C.c_int32), ("reserved", C.c_int32), ("stream", C.c_void_p),
+        ("debug_counts", C.c_void_p), ("debug_scores", C.c_void_p),
+    ]
+
+
+class mcdc_result(C.Structure):
+    _fields_ = [
+        ("host_outputs", C.c_int32), ("reserved", C.c_int32),
+        ("mean", C.c_void_p), ("var", C.c_void_p), ("raw", C.c_void_p),
+        ("leak_mean", C.c_void_p), ("leak_var", C.c_void_p),
+        ("qoi_sum", C.c_double * 2), ("qoi_mean", C.c_double), ("qoi_var", C.c_double),
+        ("n_events", C.c_uint64 * 3), ("n_term", C.c_uint64 * 5), ("n_splits", C.c_uint64),
+        ("kernel_ms", C.c_double),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    """Load libmcdc_hip.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+        L = C.CDLL(LIB_PATH)
+        L.mcdc_problem_create.argtypes = [C.POINTER(mcdc_problem_desc), C.POINTER(C.c_void_p)]
+        L.mcdc_problem_create.restype = C.c_int
+        L.mcdc_problem_destroy.argtypes = [C.c_void_p]
+        L.mcdc_problem_destroy.restype = C.c_int
+        L.mcdc_problem_tally_shape.argtypes = [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
+        L.mcdc_problem_tally_shape.restype = C.c_int
+        L.mcdc_run.argtypes = [C.c_void_p, C.c_uint64, C.c_uint64, C.POINTER(mcdc_run_options),
+                               C.POINTER(mcdc_result)]
+        L.mcdc_run.restype = C.c_int
+        L.mcdc_set_weight_windows.argtypes = [C.c_void_p, _DP, C.c_double, C.c_int32]
+        L.mcdc_set_weight_windows.restype = C.c_int
+        L.mcdc_last_error.argtypes = []
+        L.mcdc_last_error.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+class MCDCError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"mcdc error {code}: {msg}")
+        self.code = code
+
+
+def _check(rc):
+    if rc != MCDC_OK:
+        raise MCDCError(rc, lib().mcdc_last_error().decode(errors="replace"))
+
+
+def _dp(a):
+    return a.ctypes.data_as(_DP)
+
+
+def make_desc(prob: dict):
+    """Marshal a problem dict (see ``workloads.problems``) into the C
+    descriptor.  Returns (desc, keep-alive list)."""
+    keep = []
+
+    def arr(a, dt=np.float64):
+        a = np.ascontiguousarray(np.asarray(a, dtype=dt))
+        keep.append(a)
+        return a
+
+    d = mcdc_problem_desc()
+    d.abi_version = MCDC_ABI_VERSION
+    st = arr(prob["sigma_t"])
+    M, G = st.shape
+    d.n_groups, d.n_materials = G, M
+    d.sigma_t = _dp(st)
+    d.sigma_s = _dp(arr(prob["sigma_s"]))
+    d.speed = _dp(arr(prob["speed"]))
+    for a in range(3):
+        pl = arr(prob["planes"][a])
+        d.n_planes[a] = pl.size
+        d.planes[a] = _dp(pl)
+    d.material = arr(prob["material"], np.int32).ctypes.data_as(_IP)
+    for f in range(6):
+        d.bc[f] = int(prob["bc"][f])
+    src = prob["source"]
+    d.src_kind = MCDC_SRC_SURFACE if src["kind"] == "surface" else MCDC_SRC_ISOTROPIC
+    if d.src_kind == MCDC_SRC_SURFACE:
+        d.src_axis = int(src["axis"])
+        d.src_sign = int(src["sign"])
+        d.src_mu_law = MU_LAWS[src["mu_law"]]
+    for a in range(3):
+        d.src_lo[a] = float(src["lo"][a])
+        d.src_hi[a] = float(src["hi"][a])
+    d.src_t_lo, d.src_t_hi = float(src["t_lo"]), float(src["t_hi"])
+    d.src_group_pmf = _dp(arr(src["group_pmf"]))
+    tal = prob["tally"]
+    for a in range(3):
+        m = arr(tal["mesh"][a])
+        d.n_mesh_planes[a] = m.size
+        d.mesh_planes[a] = _dp(m)
+    te = arr(tal["time_edges"])
+    d.n_time_edges = te.size
+    d.time_edges = _dp(te)
+    d.n_batches = int(tal["n_batches"])
+    q = prob.get("qoi")
+    if q is not None:
+        d.qoi_enabled = 1
+        for a in range(3):
+            d.qoi_lo[a] = float(q["lo"][a])
+            d.qoi_hi[a] = float(q["hi"][a])
+        d.qoi_group_mask = arr(q["group_mask"], np.int32).ctypes.data_as(_IP)
+    ww = prob.get("ww_mesh")
+    for a in range(3):
+        m = arr(ww[a] if ww is not None else np.zeros(0))
+        d.n_ww_planes[a] = m.size
+        d.ww_planes[a] = _dp(m)
+    return d, keep
+
+
+class Problem:
+    """Owning wrapper of an mcdc_problem handle."""
+
+    def __init__(self, prob: dict):
+        d, keep = make_desc(prob)
+        h = C.c_void_p()
+        _check(lib().mcdc_problem_create(C.byref(d), C.byref(h)))
+        self.handle = h
+        self.prob = prob
+        shape = (C.c_int64 * 5)()
+        n = C.c_int64()
+        _check(lib().mcdc_problem_tally_shape(h, shape, C.byref(n)))
+        self.tally_shape = tuple(int(s) for s in shape)
+        self.ntally = int(n.value)
+        K, G = self.tally_shape[0], self.tally_shape[1]
+        self.leak_shape = (K, G, 6)
+
+    def close(self):
+        if self.handle is not None and self.handle.value:
+            lib().mcdc_problem_destroy(self.handle)
+        self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def mcdc_problem_create(prob: dict) -> Problem:
+    return Problem(prob)
+
+
+def mcdc_problem_destroy(p: Problem) -> None:
+    p.close()
+
+
+def mcdc_problem_tally_shape(p: Problem):
+    return p.tally_shape
+
+
+def mcdc_set_weight_windows(p: Problem, centers, ratio: float = 5.0, max_split: int = 16) -> None:
+    if centers is None:
+        _check(lib().mcdc_set_weight_windows(p.handle, None, ratio, max_split))
+        return
+    c = np.ascontiguousarray(np.asarray(centers, dtype=np.float64))
+    _check(lib().mcdc_set_weight_windows(p.handle, _dp(c), float(ratio), int(max_split)))
+
+
+def mcdc_run(p: Problem, n_histories: int, seed: int, algorithm: str = "event",
+             block_size: int = 0, bank_capacity: int = 0, tail_threshold: int = 0,
+             debug: bool = False, outputs=("mean", "var", "raw", "leak_mean", "leak_var")):
+    """Run n_histories through the GPU tracker.  Returns a dict of torch
+    CUDA tensors (mean, var, raw [K, G, nz, ny, nx]; leak_mean, leak_var
+    [K, G, 6]; debug_counts [N, 5] and debug_scores [N, 2] if debug) plus
+    host scalars (events, terminations, splits, detector sums, kernel_ms)."""
+    import torch
+
+    dev = torch.device("cuda", torch.cuda.current_device())
+    res = mcdc_result()
+    out = {}
+    for name in ("mean", "var", "raw"):
+        if name in outputs:
+            t = torch.empty(p.tally_shape, dtype=torch.float64, device=dev)
+            out[name] = t
+            setattr(res, name, t.data_ptr())
+    for name in ("leak_mean", "leak_var"):
+        if name in outputs:
+            t = torch.empty(p.leak_shape, dtype=torch.float64, device=dev)
+            out[name] = t
+            setattr(res, name, t.data_ptr())
+    opt = mcdc_run_options()
+    opt.algorithm = MCDC_ALG_HISTORY if algorithm == "history" else MCDC_ALG_EVENT
+    opt.block_size = block_size
+    opt.bank_capacity = bank_capacity
+    opt.tail_threshold = tail_threshold
+    opt.stream = torch.cuda.current_stream(dev).cuda_stream
+    if debug:
+        dc = torch.empty((n_histories, 5), dtype=torch.int32, device=dev)
+        ds = torch.empty((n_histories, 2), dtype=torch.float64, device=dev)
+        opt.debug_counts = dc.data_ptr()
+        opt.debug_scores = ds.data_ptr()
+        out["debug_counts"] = dc
+        out["debug_scores"] = ds
+    _check(lib().mcdc_run(p.handle, int(n_histories), int(seed), C.byref(opt), C.byref(res)))
+    out["events"] = np.array(res.n_events[:], dtype=np.uint64)
+    out["terms"] = np.array(res.n_term[:], dtype=np.uint64)
+    out["splits"] = int(res.n_splits)
+    out["qoi_sum"] = (res.qoi_sum[0], res.qoi_sum[1])
+    out["qoi_mean"] = res.qoi_mean
+    out["qoi_var"] = res.qoi_var
+    out["kernel_ms"] = res.kernel_ms
+    return out

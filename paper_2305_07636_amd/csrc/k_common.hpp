@@ -1,0 +1,295 @@
+// Device building blocks of the tracker: random numbers, birth sampling,
+// distances, collision physics.  Used by the history-based kernel and by
+// the event-based kernels, so both forms take identical per-particle
+// decisions.  All floating point is IEEE binary64 with contraction off
+// (-ffp-contract=off); the only fused multiply-add is the explicit one in
+// the position update.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "mcdc_internal.hpp"
+
+namespace mcdc {
+namespace dev {
+
+constexpr uint64_t kMult = 2806196910506780709ULL;   // 63-bit LCG multiplier
+constexpr uint64_t kMask63 = 0x7FFFFFFFFFFFFFFFULL;
+constexpr double kInf = __builtin_huge_val();
+// A particle with this many events since its last census (or birth) is
+// killed as lost: a guard against problems that could trap it forever.
+constexpr int kMaxEventsPerStep = 1 << 20;
+
+enum Event : int { kCensus = 0, kSurface = 1, kCollision = 2 };
+
+// Advance the stream and return xi = (s >> 10) * 2^-53 in [0, 1 - 2^-53].
+__device__ __forceinline__ double rn(uint64_t &s) {
+    s = (kMult * s + 1ULL) & kMask63;
+    return (double)(s >> 10) * 0x1p-53;
+}
+
+// Start of history i's stream: the base state skipped i * stride steps,
+// composing the precomputed maps for stride * 2^j steps over the set bits.
+__device__ __forceinline__ uint64_t history_stream(const DevProblem &P, uint64_t seed,
+                                                   uint64_t i) {
+    uint64_t s = seed & kMask63;
+    int j = 0;
+    while (i) {
+        if (i & 1ULL) s = P.skipA[j] * s + P.skipC[j];
+        i >>= 1;
+        ++j;
+    }
+    return s & kMask63;
+}
+
+// SplitMix64 finaliser over parent ^ j (Steele, Lea & Flood, OOPSLA 2014):
+// the stream of the j-th split child, masked to 63 bits.
+__device__ __forceinline__ uint64_t child_stream(uint64_t parent, uint64_t j) {
+    uint64_t z = (parent ^ j) + 0x9E3779B97F4A7C15ULL;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return (z ^ (z >> 31)) & kMask63;
+}
+
+// Marsaglia (1972): isotropic unit vector from a point in the unit disk.
+__device__ __forceinline__ void isotropic(uint64_t &s, double &ux, double &uy, double &uz) {
+    for (;;) {
+        double a = 2.0 * rn(s) - 1.0;
+        double b = 2.0 * rn(s) - 1.0;
+        double r = a * a + b * b;
+        if (r < 1.0) {
+            double q = sqrt(1.0 - r);
+            ux = 1.0 - 2.0 * r;
+            uy = (2.0 * a) * q;
+            uz = (2.0 * b) * q;
+            return;
+        }
+    }
+}
+
+// Register-resident particle.
+struct Particle {
+    double x[3], u[3], iu[3];   // position, direction, 1 / direction
+    double t, tau, w;
+    int ix[3];
+    int g, k;
+    uint64_t s;
+};
+
+template <int FM>
+__device__ __forceinline__ bool finite_axis(const DevProblem &P, int a) {
+    if constexpr (FM != 0) return (FM >> a) & 1;
+    return (P.finite_mask >> a) & 1;
+}
+
+// 1 / u along the finite axes (recomputed whenever the direction changes;
+// a reflection negates it, which is exact).
+template <int FM>
+__device__ __forceinline__ void set_inverse(const DevProblem &P, Particle &p) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+        if (finite_axis<FM>(P, a)) p.iu[a] = 1.0 / p.u[a];
+}
+
+__device__ __forceinline__ int cell_index(const DevProblem &P, const int ix[3]) {
+    return (ix[2] * P.nc[1] + ix[1]) * P.nc[0] + ix[0];
+}
+
+// Birth cell along an axis: the i with U_i <= x < U_{i+1}; born exactly on
+// U_i moving towards -axis belongs to cell i-1; clamped to the domain.
+__device__ __forceinline__ int locate(const double *U, int n, double x, double u) {
+    int i = -1;
+    for (int j = 0; j < n; ++j)
+        if (U[j] <= x) i = j;
+    if (i >= 0 && x == U[i] && u < 0.0) i = i - 1;
+    if (i < 0) i = 0;
+    if (i > n - 2) i = n - 2;
+    return i;
+}
+
+// Sample the source particle of a history (draw order: x, y, z, t, group,
+// direction, optical depth).  Returns false if it is born at or after the
+// last time edge (time cut-off with no events).
+template <int FM>
+__device__ __forceinline__ bool birth(const DevProblem &P, uint64_t s0, Particle &p) {
+    p.s = s0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        double xi = rn(p.s);
+        p.x[a] = finite_axis<FM>(P, a) ? P.src_lo[a] + xi * (P.src_hi[a] - P.src_lo[a]) : 0.0;
+    }
+    double xt = rn(p.s);
+    p.t = P.src_t_lo + xt * (P.src_t_hi - P.src_t_lo);
+    double xg = rn(p.s);
+    int g = 0;
+    while (!(xg < P.src_cdf[g])) ++g;
+    p.g = g;
+    if (P.src_kind == MCDC_SRC_ISOTROPIC) {
+        isotropic(p.s, p.u[0], p.u[1], p.u[2]);
+    } else {
+        double xm = rn(p.s);
+        double mu = (P.src_mu_law == MCDC_MU_BEAM) ? 1.0
+                    : (P.src_mu_law == MCDC_MU_UNIFORM) ? 1.0 - xm
+                                                         : sqrt(1.0 - xm);
+        double a, b, r;
+        for (;;) {
+            a = 2.0 * rn(p.s) - 1.0;
+            b = 2.0 * rn(p.s) - 1.0;
+            r = a * a + b * b;
+            if (r > 0.0 && r < 1.0) break;
+        }
+        double cph = (a * a - b * b) / r;
+        double sph = ((2.0 * a) * b) / r;
+        double sn = sqrt(1.0 - mu * mu);
+        double v0 = P.src_sign * mu, v1 = sn * cph, v2 = sn * sph;
+        if (P.src_axis == 0) {
+            p.u[0] = v0; p.u[1] = v1; p.u[2] = v2;
+        } else if (P.src_axis == 1) {
+            p.u[1] = v0; p.u[2] = v1; p.u[0] = v2;
+        } else {
+            p.u[2] = v0; p.u[0] = v1; p.u[1] = v2;
+        }
+    }
+    set_inverse<FM>(P, p);
+    p.tau = -log(1.0 - rn(p.s));
+    p.w = 1.0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+        p.ix[a] = finite_axis<FM>(P, a) ? locate(P.U[a], P.nU[a], p.x[a], p.u[a]) : 0;
+    if (p.t >= P.T[P.K]) {
+        p.k = P.K;
+        return false;
+    }
+    int k = 0;
+    while (!(p.t < P.T[k + 1])) ++k;
+    p.k = k;
+    return true;
+}
+
+// Distances to the next collision, union plane (per axis) and census edge;
+// picks the event with the tie order census, surface, collision.
+struct Flight {
+    double d;
+    double da[3];
+    double st;
+    int ev;
+    int m;
+};
+
+template <int FM>
+__device__ __forceinline__ Flight next_event(const DevProblem &P, const Particle &p, int cell) {
+    Flight f;
+    f.m = P.cell_mat[cell];
+    const int mg = f.m * P.G + p.g;
+    f.st = P.sigma_t[mg];
+    double dc = (f.st == 0.0) ? kInf : p.tau * P.inv_st[mg];
+    double ds = kInf;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        f.da[a] = kInf;
+        if (!finite_axis<FM>(P, a) || p.u[a] == 0.0) continue;
+        double pl = (p.u[a] > 0.0) ? P.U[a][p.ix[a] + 1] : P.U[a][p.ix[a]];
+        double d = (pl - p.x[a]) * p.iu[a];
+        if (d < 0.0) d = 0.0;
+        f.da[a] = d;
+        if (d < ds) ds = d;
+    }
+    double Tn = P.T[p.k + 1];
+    double dt = kInf;
+    if (Tn != kInf) {
+        dt = (Tn - p.t) * P.speed[p.g];
+        if (dt < 0.0) dt = 0.0;
+    }
+    if (dt <= ds && dt <= dc) {
+        f.ev = kCensus;
+        f.d = dt;
+    } else if (ds <= dc) {
+        f.ev = kSurface;
+        f.d = ds;
+    } else {
+        f.ev = kCollision;
+        f.d = dc;
+    }
+    return f;
+}
+
+// Move along the flight (positions, time, optical depth).
+template <int FM>
+__device__ __forceinline__ void move(const DevProblem &P, Particle &p, const Flight &f) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+        if (finite_axis<FM>(P, a)) p.x[a] = __builtin_fma(f.d, p.u[a], p.x[a]);
+    if (f.ev == kCensus)
+        p.t = P.T[p.k + 1];
+    else
+        p.t = p.t + f.d * P.inv_v[p.g];
+    if (f.ev != kCollision && f.st != 0.0) {
+        p.tau = p.tau - f.d * f.st;
+        if (p.tau < 0.0) p.tau = 0.0;
+    }
+}
+
+// Surface crossing of every axis whose plane distance equals the flight.
+// Returns the vacuum face crossed (particle leaks), or -1.
+template <int FM>
+__device__ __forceinline__ int cross(const DevProblem &P, Particle &p, const Flight &f) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (!finite_axis<FM>(P, a) || f.da[a] != f.d) continue;
+        int face = -1;
+        if (p.u[a] > 0.0) {
+            p.x[a] = P.U[a][p.ix[a] + 1];
+            if (p.ix[a] == P.nU[a] - 2)
+                face = 2 * a + 1;
+            else
+                p.ix[a] += 1;
+        } else {
+            p.x[a] = P.U[a][p.ix[a]];
+            if (p.ix[a] == 0)
+                face = 2 * a;
+            else
+                p.ix[a] -= 1;
+        }
+        if (face >= 0) {
+            if (P.bc[face] == MCDC_VACUUM) return face;
+            p.u[a] = -p.u[a];
+            p.iu[a] = -p.iu[a];
+        }
+    }
+    return -1;
+}
+
+// Analog collision in material m: returns false if absorbed; otherwise the
+// particle takes its outgoing group, a new isotropic direction and a new
+// optical depth.
+template <int FM>
+__device__ __forceinline__ bool collide(const DevProblem &P, Particle &p, int m) {
+    const int mg = m * P.G + p.g;
+    if (!(rn(p.s) < P.ps[mg])) return false;
+    double xg = rn(p.s);
+    const double *cdf = P.cdf + (int64_t)mg * P.G;
+    int g2 = 0;
+    while (!(xg < cdf[g2])) ++g2;
+    p.g = g2;
+    isotropic(p.s, p.u[0], p.u[1], p.u[2]);
+    set_inverse<FM>(P, p);
+    p.tau = -log(1.0 - rn(p.s));
+    return true;
+}
+
+// Weight-window centre of a cell for the particle's (k, g), 0 = none.
+__device__ __forceinline__ double ww_centre(const DevProblem &P, int cell, int g, int k) {
+    if (P.ww_center == nullptr) return 0.0;
+    int c = P.cell_ww[cell];
+    if (c < 0) return 0.0;
+    return P.ww_center[((int64_t)k * P.G + g) * P.nww + c];
+}
+
+__device__ __forceinline__ void atomic_add_f64(double *a, double v) {
+    unsafeAtomicAdd(a, v);
+}
+
+}  // namespace dev
+}  // namespace mcdc

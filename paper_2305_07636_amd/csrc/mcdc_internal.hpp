@@ -1,0 +1,132 @@
+// Internal types of the MI355X tracker library: the compiled problem that
+// kernels receive by value, the per-run arguments, and the launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/mcdc.h"
+
+namespace mcdc {
+
+constexpr int kMaxGroups = 32;      // outgoing-group search is unrolled over this
+constexpr int kCounters = 9;        // census, surface, collision; 5 terminations; splits
+constexpr uint64_t kStride = 152917ULL;
+
+enum Term : int { kAbsorb = 0, kLeak = 1, kTime = 2, kLost = 3, kRoulette = 4 };
+
+// Compiled problem: device pointers to the read-only tables plus scalars.
+// Passed to every kernel by value (well under the kernel-argument limit).
+struct DevProblem {
+    int G, M, K;
+    int nU[3];             // union planes per axis (0 = infinite axis)
+    int nc[3];             // union cells per axis (1 on an infinite axis)
+    int finite_mask;       // bit a set if axis a is finite
+    int ncells;            // nc[0] * nc[1] * nc[2]
+    int nts;               // tally spatial bins nz * ny * nx
+    int64_t ntally;        // K * G * nts
+    const double *U[3];    // union planes
+    const int32_t *cell_mat;   // [ncells] material of each union cell
+    const int32_t *cell_tal;   // [ncells] spatial tally bin, -1 outside the mesh
+    const int32_t *cell_ww;    // [ncells] weight-window cell, -1 outside
+    const uint8_t *cell_qoi;   // [ncells] 1 inside the detector box
+    const double *sigma_t;     // [M][G]
+    const double *inv_st;      // [M][G] 1 / sigma_t (0 for a void)
+    const double *ps;          // [M][G] sigma_s,g / sigma_t,g
+    const double *cdf;         // [M][G][G] outgoing-group CDF
+    const double *speed;       // [G]
+    const double *inv_v;       // [G] 1 / speed
+    const double *T;           // [K + 1] census / time-bin edges
+    const double *src_cdf;     // [G]
+    const uint8_t *qoi_groups; // [G]
+    const uint64_t *skipA;     // [64] LCG map for stride * 2^j steps: s -> A s + C
+    const uint64_t *skipC;     // [64]
+    const double *bin_norm;    // [nts] tally-bin volume (product of bin widths)
+    const double *time_norm;   // [K] time-bin width (1 for an infinite bin)
+    int bc[6];
+    int src_kind, src_axis, src_mu_law;
+    double src_sign;
+    double src_lo[3], src_hi[3], src_t_lo, src_t_hi;
+    int qoi_on;
+    // weight windows
+    const double *ww_center;   // [K][G][nww] or nullptr (analog)
+    int nww;
+    int ww_max_split;
+    double ww_ratio;
+};
+
+// Per-launch arguments shared by the tracking kernels.
+struct RunArgs {
+    uint64_t N;          // histories in the whole run (sets the batch partition)
+    uint64_t seed;       // base LCG state (masked to 63 bits)
+    int B;               // batches
+    double *S;           // [B][ntally] raw track-length sums per batch
+    double *L;           // [B][K][G][6] leaked weight per batch
+    double *qoi_hist;    // [chunk] per-history detector score (WW runs) or nullptr
+    double *qoi_sums;    // [2] sum x, sum x^2
+    unsigned long long *counters;  // [kCounters]
+    uint32_t *dbg_counts;          // [N][5] or nullptr
+    double *dbg_scores;            // [N][2] or nullptr
+    int *overflow;                 // set to 1 when a bank overflows
+};
+
+// Host-side compiled problem (owns the device blob).
+struct HostProblem {
+    int G = 0, M = 0, K = 0, B = 0;
+    std::vector<double> U[3];
+    int nc[3] = {1, 1, 1};
+    int nt[3] = {1, 1, 1};     // tally bins per axis
+    int nw[3] = {1, 1, 1};     // window cells per axis
+    std::vector<int32_t> cell_mat, cell_tal, cell_ww;
+    std::vector<uint8_t> cell_qoi;
+    std::vector<double> sigma_t, inv_st, ps, cdf, speed, inv_v, T, src_cdf;
+    std::vector<uint8_t> qoi_groups;
+    std::vector<double> bin_norm;      // [nts] V_j (product of bin widths)
+    std::vector<double> time_norm;     // [K] dt_k (1 if infinite)
+    double qoi_volume = 1.0;
+    mcdc_problem_desc desc{};          // scalars of the descriptor
+};
+
+}  // namespace mcdc
+
+// The opaque handle of the C ABI.
+struct mcdc_problem {
+    mcdc::HostProblem h;
+    mcdc::DevProblem d{};
+    int device = 0;
+    void *blob = nullptr;          // device tables
+    size_t blob_bytes = 0;
+    // weight windows
+    double *ww_dev = nullptr;
+    std::vector<double> ww_host;
+    // work buffers, grown on demand and reused across runs
+    struct Buf {
+        void *p = nullptr;
+        size_t bytes = 0;
+    };
+    Buf S, L, qoi_hist, qoi_sums, counters, overflow, bank, queues, split;
+    Buf mean, var, raw, leak_mean, leak_var;
+};
+
+namespace mcdc {
+
+void set_error(const std::string &msg);
+int hip_fail(hipError_t e, const char *what);
+int ensure(mcdc_problem::Buf &b, size_t bytes);
+
+// launchers (return a hipError_t as int)
+int launch_history(const DevProblem &P, const RunArgs &R, uint64_t first, uint64_t count,
+                   int block, hipStream_t st);
+int launch_event(mcdc_problem *p, const RunArgs &R, uint64_t first, uint64_t count,
+                 const mcdc_run_options &opt, hipStream_t st);
+int launch_fold(const DevProblem &P, const double *S, const double *L, int B, uint64_t N,
+                const double *bin_norm_dev, const double *time_norm_dev, double *mean,
+                double *var, double *raw, double *leak_mean, double *leak_var,
+                hipStream_t st);
+int launch_zero(void *p, size_t bytes, hipStream_t st);
+int launch_qoi_reduce(const double *qoi_hist, uint64_t n, double *qoi_sums, hipStream_t st);
+
+}  // namespace mcdc

@@ -1,0 +1,104 @@
+"""Shared helpers of the GPU parity tests: run a problem through the HIP
+library and through the CPU oracle on the same seeded inputs and compare.
+
+Tolerances (written here, used by every parity test):
+* per-history event counts, particle counts, termination masks and every
+  event/termination total: bit-exact (integer work);
+* per-history scored track and detector score, raw bin sums and bin means:
+  |gpu - oracle| <= 1e-12 |oracle| + 1e-12 max|oracle| (the GPU sums the
+  same IEEE terms in another order: about sqrt(n) eps relative, far below);
+* batch variances: 1e-9 relative + 1e-12 of the largest variance.  The
+  variance is a difference of batch means that agree to ~1e-15 relative;
+  with batch means spread by ~1e-4 of the mean the difference keeps about
+  1e-11 relative accuracy, and 1e-9 leaves margin for bins with few scores.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+import oracle
+
+RTOL = 1e-12
+VAR_RTOL = 1e-9
+
+
+def close(gpu, ref, rtol=RTOL, what=""):
+    gpu = np.asarray(gpu, dtype=np.float64).ravel()
+    ref = np.asarray(ref, dtype=np.float64).ravel()
+    assert gpu.shape == ref.shape, (what, gpu.shape, ref.shape)
+    scale = np.abs(ref).max() if ref.size else 0.0
+    tol = rtol * np.abs(ref) + 1e-12 * scale
+    bad = np.abs(gpu - ref) > tol
+    assert not bad.any(), (what, int(bad.sum()), np.nonzero(bad)[0][:5], gpu[bad][:5], ref[bad][:5])
+
+
+def gpu_run(prob, N, seed, algorithm, debug=True, **kw):
+    import paper_2305_07636_amd as m
+
+    p = m.mcdc_problem_create(prob)
+    try:
+        out = m.mcdc_run(p, N, seed, algorithm=algorithm, debug=debug, **kw)
+        host = {k: (v.cpu().numpy() if hasattr(v, "cpu") else v) for k, v in out.items()}
+    finally:
+        p.close()
+    return host
+
+
+def compare_full(prob, N, seed, algorithm, **kw):
+    """Run all N histories on both sides and compare everything."""
+    g = gpu_run(prob, N, seed, algorithm, **kw)
+    r = oracle.run(prob, N, seed, records=True)
+    e = oracle.estimates(prob, r)
+    rec = r["rec"]
+    dc = g["debug_counts"].astype(np.uint32)
+    mism = np.nonzero((dc != rec).any(axis=1))[0]
+    assert mism.size == 0, ("per-history counts differ", mism[:10], dc[mism[:3]], rec[mism[:3]])
+    close(g["debug_scores"], r["trk"], what="per-history scores")
+    tot = r["tot"]
+    assert np.array_equal(g["events"], tot[0:3]), (g["events"], tot[0:3])
+    assert np.array_equal(g["terms"], tot[3:8]), (g["terms"], tot[3:8])
+    assert g["splits"] == int(tot[8])
+    close(g["raw"], e["raw"], what="raw")
+    close(g["mean"], e["mean"], what="mean")
+    close(g["var"], e["var"], rtol=VAR_RTOL, what="var")
+    close(g["leak_mean"], e["leak_mean"], what="leak mean")
+    close(g["leak_var"], e["leak_var"], rtol=VAR_RTOL, what="leak var")
+    if prob.get("qoi") is not None:
+        close(g["qoi_sum"], r["q"], what="detector sums")
+        close([g["qoi_mean"]], [e["qoi_mean"]], what="detector mean")
+        close([g["qoi_var"]], [e["qoi_var"]], rtol=VAR_RTOL, what="detector var")
+    return g, r, e
+
+
+def compare_sampled(prob, N, seed, algorithm, n_sample=2000, sample_seed=0, **kw):
+    """Full-size run on the GPU; the oracle recomputes a seeded sample of
+    histories one by one (skip-ahead makes each history independent) and
+    their per-history records must agree exactly."""
+    import torch
+
+    import paper_2305_07636_amd as m
+
+    rng = np.random.default_rng(sample_seed)
+    ids = np.unique(np.concatenate([rng.integers(0, N, n_sample), [0, N - 1]])).astype(np.uint64)
+    p = m.mcdc_problem_create(prob)
+    try:
+        out = m.mcdc_run(p, N, seed, algorithm=algorithm, debug=True, **kw)
+        idx = torch.as_tensor(ids.astype(np.int64), device=out["debug_counts"].device)
+        dc = out["debug_counts"].index_select(0, idx).cpu().numpy().astype(np.uint32)
+        ds = out["debug_scores"].index_select(0, idx).cpu().numpy()
+        ev_sum = out["debug_counts"][:, :3].to(torch.int64).sum(dim=0).cpu().numpy()
+        terms_hist = out["debug_counts"][:, 4]
+        n_term_bits = int((terms_hist != 0).sum().item())
+        one_bit = int(((terms_hist & (terms_hist - 1)) == 0).sum().item())
+    finally:
+        p.close()
+    r = oracle.run(prob, N, seed, ids=ids, records=True)
+    mism = np.nonzero((dc != r["rec"]).any(axis=1))[0]
+    assert mism.size == 0, ("sampled per-history counts differ", ids[mism[:10]], dc[mism[:3]], r["rec"][mism[:3]])
+    close(ds, r["trk"], what="sampled per-history scores")
+    # properties at any size: every history terminates exactly once and the
+    # per-history counts add up to the event totals
+    assert int(out["terms"].sum()) == N
+    assert n_term_bits == N and one_bit == N
+    assert np.array_equal(ev_sum, out["events"].astype(np.int64))
+    return out

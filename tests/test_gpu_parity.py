@@ -1,0 +1,104 @@
+"""GPU parity: the HIP tracker (history- and event-based forms, through the
+C ABI) against the CPU oracle on the same seeded inputs.  Tolerances are
+stated in gpu_common."""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as w
+from gpu_common import compare_full, compare_sampled
+from test_oracle_trace import tiny_lattice
+
+ALGS = ["history", "event"]
+
+# small cases: a few seconds of oracle time, several blocks and a ragged tail
+SMALL = {
+    "slab_c05_cosine": (lambda: w.cfg1_slab_steady(c=0.5, mu_law="cosine"), 20011, 1),
+    "slab_c0_beam": (lambda: w.cfg1_slab_steady(c=0.0, mu_law="beam"), 20011, 11),
+    "slab_c0_uniform": (lambda: w.cfg1_slab_steady(c=0.0, mu_law="uniform"), 9001, 12),
+    "pulse_c09": (lambda: w.cfg2_slab_pulse(c=0.9), 12345, 2),
+    "pulse_c0": (lambda: w.cfg2_slab_pulse(c=0.0), 7001, 4),
+    "lattice17": (lambda: w.cfg3_lattice(), 20011, 3),
+    "tiny_lattice": (tiny_lattice, 5003, 9),
+    "reflective_mg": (lambda: w.reflective_box([1.0, 1.5, 2.0], [[0.3, 0.4, 0.1], [0.0, 0.6, 0.5],
+                                                                [0.0, 0.2, 1.2]], [3.0, 2.0, 1.0],
+                                               time_edges=[0.0, 0.25, 0.5, 1.0, 2.0, 4.0]), 4099, 17),
+    "void_box": (lambda: w.void_box(), 3001, 5),
+    "dogleg": (lambda: w.cfg5_dogleg(), 4001, 50),
+    "census_heavy": (lambda: w.reflective_box([0.3, 0.5], [[0.1, 0.15], [0.0, 0.4]], [0.7, 1.3],
+                                              time_edges=np.linspace(0.0, 9.1, 71)), 2003, 8),
+    "surface_y_minus": (lambda: w.make_problem(
+        [[1.0]], [[[0.6]]], [1.0], [np.array([0.0, 1.0]), np.array([0.0, 0.5, 2.0]), np.array([])],
+        np.zeros((1, 2, 1)), [1, 1, 0, 0, 0, 0],
+        {"kind": "surface", "axis": 1, "sign": -1, "mu_law": "cosine", "lo": [0.0, 2.0, 0.0],
+         "hi": [1.0, 2.0, 0.0], "group_pmf": [1.0]},
+        {"mesh": [np.array([]), np.linspace(0, 2, 9), np.array([])], "time_edges": [0.0, math.inf],
+         "n_batches": 16}), 3001, 6),
+}
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("alg", ALGS)
+@pytest.mark.parametrize("case", list(SMALL))
+def test_parity_small(case, alg):
+    make, N, seed = SMALL[case]
+    print(f"[parity] {case} alg={alg} N={N} seed={seed}", flush=True)
+    compare_full(make(), N, seed, alg)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("alg", ALGS)
+def test_parity_edge_single_history(alg):
+    # one history: one batch, zero variance
+    print(f"[parity] single history alg={alg}", flush=True)
+    compare_full(w.cfg2_slab_pulse(), 1, 7, alg)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("alg", ALGS)
+def test_parity_edge_fewer_histories_than_batches(alg):
+    print(f"[parity] N < B alg={alg}", flush=True)
+    compare_full(w.cfg3_lattice(), 17, 8, alg)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("alg", ALGS)
+def test_parity_edge_born_after_cutoff(alg):
+    # emission window partly beyond the last time edge: some histories end
+    # at birth with zero events
+    p = w.slab(thickness=4.0, sigma_t=1.0, sigma_s=0.5, n_bins=8, source="plane", x_src=2.0,
+               time_edges=np.linspace(0.0, 2.0, 11), t_hi=3.0)
+    print(f"[parity] born after cutoff alg={alg}", flush=True)
+    g, r, _ = compare_full(p, 4001, 10, alg)
+    assert int(r["tot"][5]) > 0
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("alg", ALGS)
+def test_parity_full_size_pulse_sampled(alg):
+    """The 1e7-history pulsed slab as benchmarked, checked on a sample."""
+    print(f"[parity] pulse 1e7 sampled alg={alg}", flush=True)
+    compare_sampled(w.cfg2_slab_pulse(), 10_000_000, 2, alg)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("alg", ALGS)
+def test_parity_lattice_sampled(alg):
+    print(f"[parity] lattice 1e7 sampled alg={alg}", flush=True)
+    compare_sampled(w.cfg3_lattice(), 10_000_000, 3, alg)
+
+
+@pytest.mark.gpu
+def test_algorithms_agree_bitwise_on_counts():
+    """History and event forms give the same per-history records and totals
+    for the same (problem, N, seed)."""
+    from gpu_common import close, gpu_run
+
+    p = w.cfg3_lattice()
+    a = gpu_run(p, 200003, 31, "history")
+    b = gpu_run(p, 200003, 31, "event")
+    assert np.array_equal(a["debug_counts"], b["debug_counts"])
+    assert np.array_equal(a["events"], b["events"]) and np.array_equal(a["terms"], b["terms"])
+    close(b["debug_scores"], a["debug_scores"])
+    close(b["mean"], a["mean"])
