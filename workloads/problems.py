@@ -241,7 +241,11 @@ def cfg4_batch(n_problems=256, seed=1000):
 # Deep-penetration dog-leg duct (Kobayashi-like, synthetic)
 # ---------------------------------------------------------------------------
 
-def cfg5_dogleg(n_batches=32):
+CORNER_DETECTOR = ((10.0, 7.0, 4.0), (12.0, 9.0, 6.0))   # after the first bend
+LEG_A_DETECTOR = ((8.0, 1.0, 4.0), (10.0, 3.0, 6.0))     # in sight of the source
+
+
+def cfg5_dogleg(n_batches=32, detector=((29.0, 7.0, 4.0), (30.0, 9.0, 6.0))):
     """Box [0,30]x[0,10]x[0,10], vacuum on all faces, 2 groups.
     Bulk: Sigma_t = (1.0, 1.5), c = (0.8, 0.6), Sigma_s[0][0] = Sigma_s[0][1]
     = 0.4, Sigma_s[1][1] = 0.9.  A 2-unit-wide low-density dog-leg channel
@@ -249,8 +253,8 @@ def cfg5_dogleg(n_batches=32):
     [0,12], y in [1,3]; leg B x in [10,12], y in [1,9]; leg C x in [10,30],
     y in [7,9].  Source box x in [0,1], y in [1,3], z in [4,6], group 0,
     isotropic, steady.  Detector (quantity of interest) x in [29,30],
-    y in [7,9], z in [4,6], both groups.  Tally and weight-window mesh
-    40 x 10 x 10 (cells 0.75 x 1 x 1)."""
+    y in [7,9], z in [4,6] (default), both groups.  Tally and weight-window
+    mesh 40 x 10 x 10 (cells 0.75 x 1 x 1)."""
     st_bulk = np.array([1.0, 1.5])
     ss_bulk = np.array([[0.4, 0.4], [0.0, 0.9]])
     scale = 0.05 / st_bulk
@@ -275,8 +279,7 @@ def cfg5_dogleg(n_batches=32):
     mesh = [np.arange(41) * 0.75, np.arange(11) * 1.0, np.arange(11) * 1.0]
     tally = {"mesh": mesh, "time_edges": [0.0, math.inf],
              "n_batches": n_batches}
-    qoi = {"lo": [29.0, 7.0, 4.0], "hi": [30.0, 9.0, 6.0],
-           "group_mask": [1, 1]}
+    qoi = {"lo": list(detector[0]), "hi": list(detector[1]), "group_mask": [1, 1]}
     return make_problem(st, ss, [1.0, 1.0], [px, py, pz], mat,
                         [VACUUM] * 6, src, tally, qoi=qoi, ww_mesh=mesh)
 
