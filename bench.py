@@ -1,0 +1,170 @@
+"""Benchmark of the MI355X Monte Carlo tracker.
+
+One step = one complete run of the hot path (source sampling, event-based
+tracking with census steps, track-length tallies, batch statistics) over the
+workload below, inputs resident on the GPU.  Prints ONE JSON line.
+
+Workload (single GPU): the pulsed slab -- one group, Sigma_t = 1, c = 0.9,
+v = 1, 40 mean free paths, isotropic pulse at the centre at t = 0,
+50 spatial x 100 time tally bins over [0, 20], 1e7 histories, FP64.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+       [--algorithm event|history] [--histories N] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "histories/sec + figure of merit 1/(σ²T), plain analog vs learned-WW, 1×MI355X"
+WORKLOAD = ("pulsed slab: 1 group, Sigma_t=1, c=0.9, v=1, 40 mfp, isotropic centre pulse at t=0, "
+            "50 x-bins x 100 time bins on [0,20], 1e7 histories, FP64")
+HBM_PEAK_GBS = 8000.0
+
+
+def cpu_worker(args):
+    """Run a contiguous history range of the job through the oracle."""
+    first, count, N, seed = args
+    import oracle
+    import workloads as w
+
+    prob = w.cfg2_slab_pulse()
+    t0 = time.perf_counter()
+    oracle.run(prob, N, seed, first=first, count=count)
+    return time.perf_counter() - t0
+
+
+def cpu_baseline(N, seed, target_s=15.0):
+    """The oracle as it stands, on the host cores, over a bounded sample of
+    the same job (histories 0..n-1), in independent processes over
+    contiguous history ranges (skip-ahead makes them independent)."""
+    import multiprocessing as mp
+
+    import oracle
+
+    oracle.build()
+    cores = min(16, os.cpu_count() or 1)
+    # calibrate the per-core rate on a short range
+    t = cpu_worker((0, 20000, N, seed))
+    rate1 = 20000 / t
+    per = max(1000, int(rate1 * target_s / 2))
+    n = per * cores
+    ctx = mp.get_context("spawn")
+    with ctx.Pool(cores) as pool:
+        t0 = time.perf_counter()
+        pool.map(cpu_worker, [(j * per, per, N, seed) for j in range(cores)])
+        wall = time.perf_counter() - t0
+    return {
+        "value": n / wall, "unit": "histories/s", "cores": cores, "kind": "oracle",
+        "sample": f"histories 0..{n - 1} of the {N:.0e}-history job, {cores} processes x {per} "
+                  f"contiguous histories, serial C oracle (gcc -O2, no contraction), wall {wall:.1f} s",
+        "single_core_histories_per_s": rate1,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--algorithm", default="event", choices=["event", "history"])
+    ap.add_argument("--histories", type=float, default=1e7)
+    ap.add_argument("--event-iters", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-history-form", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU: this build runs on a single MI355X and has no "
+              "multi-GPU path (histories would shard by batch with one all-reduce of the "
+              "tallies at the end); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    N = int(args.histories)
+    seed = 2
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(N, seed)    # before the GPU is touched (spawned workers)
+
+    import numpy as np
+    import torch
+
+    import paper_2305_07636_amd as m
+    import workloads as w
+
+    torch.cuda.set_device(0)
+    prob = w.cfg2_slab_pulse()
+    p = m.mcdc_problem_create(prob)
+    outs = ("mean", "var")
+
+    def step(alg, s, profile=None):
+        return m.mcdc_run(p, N, seed + s, algorithm=alg, outputs=outs, profile=profile,
+                          event_iters=args.event_iters)
+
+    for s in range(args.warmup):
+        step(args.algorithm, s)
+    torch.cuda.synchronize()
+    prof = np.zeros((len(m._binding.PROF_CLASSES), 4))
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        last = step(args.algorithm, s, profile=prof)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    value = N * args.steps / elapsed
+
+    # dominant kernel: the class with the most device time
+    names = m._binding.PROF_CLASSES
+    cls = int(np.argmax(prof[:, 0]))
+    ms, launches, items, nbytes = prof[cls]
+    if args.algorithm == "event":
+        achieved = nbytes / (ms * 1e-3) / 1e9
+        roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": f"k_{names[cls]}",
+                    "launches": int(launches), "avg_launch_ms": ms / launches,
+                    "algorithmic_bytes_per_launch": nbytes / launches,
+                    "particles_per_launch": items / launches}
+    else:
+        # history form: state in registers; bounded by FP64 vector ALU and
+        # divergence, reported as events per second against the FP64 rate
+        ev = float(sum(last["events"]))
+        roofline = {"bound": "alu", "achieved": ev * args.steps / (ms * 1e-3) / 1e9,
+                    "peak": None, "unit": "Gevents/s", "frac": None, "traffic": None,
+                    "kernel": "k_history", "launches": int(launches), "avg_launch_ms": ms / launches}
+    per_class = {names[c]: {"ms": prof[c, 0] / args.steps, "launches": prof[c, 1] / args.steps,
+                            "particles": prof[c, 2] / args.steps, "bytes": prof[c, 3] / args.steps}
+                 for c in range(len(names)) if prof[c, 1] > 0}
+
+    extra = {}
+    if not args.no_history_form and args.algorithm == "event":
+        torch.cuda.synchronize()
+        step("history", 0)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for s in range(args.steps):
+            step("history", s)
+        torch.cuda.synchronize()
+        extra["history_form_histories_per_s"] = N * args.steps / (time.perf_counter() - t1)
+
+    line = {
+        "metric": METRIC, "value": value, "unit": "histories/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": WORKLOAD, "algorithm": args.algorithm, "histories_per_step": N,
+                   "events_per_step": [int(x) for x in last["events"]]},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "kernels_per_step": per_class,
+    }
+    line.update(extra)
+    p.close()
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

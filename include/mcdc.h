@@ -138,25 +138,43 @@ typedef struct {
  *  block_size     threads per block, 0 = tuned default (64..1024, multiple of 64).
  *  bank_capacity  event form: particles resident at once (0 = auto).  Work
  *                 is processed in chunks of this many histories.
- *  tail_threshold event form: when fewer particles than this remain active
- *                 in a census step, the rest are finished by one in-register
- *                 pass (0 = auto, -1 = never).
+ *  event_iters    event form: queue iterations (advance, then the surface
+ *                 and collision kernels) per census step before the
+ *                 particles still in flight are finished by one in-register
+ *                 pass that takes each to its census or death (0 = auto).
  *  stream         hipStream_t to run on (NULL = the null stream).  mcdc_run
  *                 synchronises this stream before it returns.
  *  debug_counts   device array [N][5] (census, surface, collision events,
  *                 particles, termination mask per history) or NULL.
  *  debug_scores   device array [N][2] (tallied track and detector score per
  *                 history) or NULL.
+ *  profile        host array [MCDC_PROF_CLASSES][4] or NULL.  When given,
+ *                 each kernel launch is bracketed by HIP events on the run's
+ *                 stream and row c (a MCDC_PROF_* class) receives: total
+ *                 device milliseconds, launches, particles processed, and
+ *                 algorithmic HBM bytes (the particle-state and queue bytes
+ *                 the kernels' loads and stores request, tally atomics
+ *                 excluded).  Values are added to what the array holds.
  */
+#define MCDC_PROF_CLASSES 8
+#define MCDC_PROF_SOURCE 0
+#define MCDC_PROF_ADVANCE 1    /* advance over the dense census bank */
+#define MCDC_PROF_ADVANCE_Q 2  /* advance over the active queue */
+#define MCDC_PROF_SURFACE 3
+#define MCDC_PROF_COLLISION 4
+#define MCDC_PROF_FINISH 5
+#define MCDC_PROF_HISTORY 6
+#define MCDC_PROF_OTHER 7      /* fills, control, batch statistics */
 typedef struct {
     int32_t algorithm;
     int32_t block_size;
     int64_t bank_capacity;
-    int32_t tail_threshold;
+    int32_t event_iters;
     int32_t reserved;
     void *stream;
     uint32_t *debug_counts;
     double *debug_scores;
+    double *profile;
 } mcdc_run_options;
 
 /*
@@ -227,6 +245,25 @@ int mcdc_run(mcdc_problem *p, uint64_t n_histories, uint64_t seed,
              const mcdc_run_options *opt, mcdc_result *out);
 
 /*
+ * Batched solve: run n independent problems (any sizes, group counts and
+ * history counts) in one persistent launch.  A fixed grid of workgroups
+ * pulls chunks of histories from one device-wide work counter over the
+ * concatenated history ranges, so large and small problems share the GPU
+ * without per-problem launch or tail costs.  Problem j runs n_hist[j]
+ * histories with seed seeds[j]; outs[j] is filled exactly as mcdc_run
+ * would fill it for that problem, and per-history results are identical to
+ * separate mcdc_run calls (tallies differ only in summation order).  The
+ * launch shape (workgroup size, histories per pull) is autotuned on the
+ * first call for a batch signature (problem shapes and history counts) and
+ * reused after that; opt->block_size forces a workgroup size.
+ * opt->algorithm must be MCDC_ALG_HISTORY (or the default, which the batched
+ * path maps to it); debug arrays and weight windows are not supported here
+ * (MCDC_E_UNSUPPORTED).  All problems must live on the same device.
+ */
+int mcdc_run_batched(mcdc_problem *const *ps, int32_t n, const uint64_t *n_hist, const uint64_t *seeds,
+                     const mcdc_run_options *opt, mcdc_result *outs);
+
+/*
  * Set weight-window centres for later runs: centers[K][G][wz][wy][wx] over
  * the weight-window mesh (0 = no window in that cell); ratio rho > 1 sets
  * the window [2 w_c / (1 + rho), 2 rho w_c / (1 + rho)] with survival weight
@@ -236,6 +273,48 @@ int mcdc_run(mcdc_problem *p, uint64_t n_histories, uint64_t seed,
  */
 int mcdc_set_weight_windows(mcdc_problem *p, const double *centers, double ratio,
                             int32_t max_split);
+
+/*
+ * Weight-window network: the learned weight-window generator maps a tally
+ * cell's features (x, y, z scaled to [0, 1], one-hot group, scaled time,
+ * zero-padded to 8) to the log10 of a flux estimate, from which window
+ * centres are formed.  Architecture: 8 -> 64 -> 64 -> 64 -> 1, tanh on the
+ * hidden layers, linear output (the only supported widths).  Training is
+ * FP32 on matrix cores (weighted mean-squared error, full batch, Adam with
+ * beta = (0.9, 0.999), eps = 1e-8); inference rounds weights and
+ * activations to bfloat16 with FP32 accumulation.
+ *
+ * Flat parameter layout, MCDC_MLP_PARAMS floats: W1[8][64], b1[64],
+ * W2[64][64], b2[64], W3[64][64], b3[64], w4[64], b4[1] (W[k][j] links
+ * input k to output j).
+ *
+ * X[n][8], T[n] (targets), W[n] (sample weights) and Y[n] are device
+ * pointers; params and grads are host pointers; stream is a hipStream_t
+ * (NULL = null stream).  Each call synchronises its stream before it
+ * returns.  Gradients are reduced in a fixed order, so they are
+ * reproducible run to run.
+ */
+#define MCDC_MLP_PARAMS 8961
+typedef struct mcdc_mlp mcdc_mlp;
+
+/* widths = {8, 64, 64, 64, 1}, n_layers = 4; Xavier-uniform weights from
+ * SplitMix64(seed), zero biases.  Errors: MCDC_E_UNSUPPORTED for other
+ * shapes, MCDC_E_NOMEM, MCDC_E_HIP. */
+int mcdc_mlp_create(const int32_t *widths, int32_t n_layers, uint64_t seed, mcdc_mlp **out);
+int mcdc_mlp_destroy(mcdc_mlp *m);
+/* Copy the parameters out / in (setting them also resets Adam's moments). */
+int mcdc_mlp_get_params(const mcdc_mlp *m, float *params);
+int mcdc_mlp_set_params(mcdc_mlp *m, const float *params);
+/* Loss sum_i W_i (y_i - T_i)^2 and its gradient (host grads[MCDC_MLP_PARAMS],
+ * may be NULL) at the current parameters. */
+int mcdc_mlp_grad(mcdc_mlp *m, const float *X, const float *T, const float *W, int64_t n, float *loss,
+                  float *grads, void *stream);
+/* steps full-batch Adam steps with learning rate lr; loss_out[steps] (host,
+ * may be NULL) receives the loss before each step. */
+int mcdc_mlp_train(mcdc_mlp *m, const float *X, const float *T, const float *W, int64_t n, int32_t steps,
+                   float lr, float *loss_out, void *stream);
+/* BF16 inference: Y[i] = network(X[i]). */
+int mcdc_mlp_infer(mcdc_mlp *m, const float *X, int64_t n, float *Y, void *stream);
 
 /* Message of the last failure on the calling thread ("" if none). */
 const char *mcdc_last_error(void);

@@ -23,7 +23,9 @@ MCDC_SRC_ISOTROPIC, MCDC_SRC_SURFACE = 0, 1
 MU_LAWS = {"beam": 0, "uniform": 1, "cosine": 2}
 
 EXPORTS = ["mcdc_problem_create", "mcdc_problem_destroy", "mcdc_problem_tally_shape",
-           "mcdc_run", "mcdc_set_weight_windows", "mcdc_last_error"]
+           "mcdc_run", "mcdc_run_batched", "mcdc_set_weight_windows", "mcdc_last_error", "mcdc_mlp_create",
+           "mcdc_mlp_destroy", "mcdc_mlp_get_params", "mcdc_mlp_set_params", "mcdc_mlp_grad",
+           "mcdc_mlp_train", "mcdc_mlp_infer"]
 
 _DP = C.POINTER(C.c_double)
 _IP = C.POINTER(C.c_int32)
@@ -52,9 +54,13 @@ class mcdc_problem_desc(C.Structure):
 class mcdc_run_options(C.Structure):
     _fields_ = [
         ("algorithm", C.c_int32), ("block_size", C.c_int32), ("bank_capacity", C.c_int64),
-        ("tail_threshold", C.c_int32), ("reserved", C.c_int32), ("stream", C.c_void_p),
+        ("event_iters", C.c_int32), ("reserved", C.c_int32), ("stream", C.c_void_p),
         ("debug_counts", C.c_void_p), ("debug_scores", C.c_void_p),
+        ("profile", C.c_void_p),
     ]
+
+
+PROF_CLASSES = ["source", "advance", "advance_q", "surface", "collision", "finish", "history", "other"]
 
 
 class mcdc_result(C.Structure):
@@ -220,12 +226,15 @@ def mcdc_set_weight_windows(p: Problem, centers, ratio: float = 5.0, max_split: 
 
 
 def mcdc_run(p: Problem, n_histories: int, seed: int, algorithm: str = "event",
-             block_size: int = 0, bank_capacity: int = 0, tail_threshold: int = 0,
-             debug: bool = False, outputs=("mean", "var", "raw", "leak_mean", "leak_var")):
+             block_size: int = 0, bank_capacity: int = 0, event_iters: int = 0,
+             debug: bool = False, outputs=("mean", "var", "raw", "leak_mean", "leak_var"),
+             profile=None):
     """Run n_histories through the GPU tracker.  Returns a dict of torch
     CUDA tensors (mean, var, raw [K, G, nz, ny, nx]; leak_mean, leak_var
     [K, G, 6]; debug_counts [N, 5] and debug_scores [N, 2] if debug) plus
-    host scalars (events, terminations, splits, detector sums, kernel_ms)."""
+    host scalars (events, terminations, splits, detector sums, kernel_ms).
+    profile: optional float64 array [8, 4] that accumulates per kernel class
+    (ms, launches, particles, algorithmic bytes)."""
     import torch
 
     dev = torch.device("cuda", torch.cuda.current_device())
@@ -245,7 +254,7 @@ def mcdc_run(p: Problem, n_histories: int, seed: int, algorithm: str = "event",
     opt.algorithm = MCDC_ALG_HISTORY if algorithm == "history" else MCDC_ALG_EVENT
     opt.block_size = block_size
     opt.bank_capacity = bank_capacity
-    opt.tail_threshold = tail_threshold
+    opt.event_iters = event_iters
     opt.stream = torch.cuda.current_stream(dev).cuda_stream
     if debug:
         dc = torch.empty((n_histories, 5), dtype=torch.int32, device=dev)
@@ -254,6 +263,10 @@ def mcdc_run(p: Problem, n_histories: int, seed: int, algorithm: str = "event",
         opt.debug_scores = ds.data_ptr()
         out["debug_counts"] = dc
         out["debug_scores"] = ds
+    if profile is not None:
+        assert profile.dtype == np.float64 and profile.shape == (len(PROF_CLASSES), 4)
+        assert profile.flags["C_CONTIGUOUS"]
+        opt.profile = profile.ctypes.data
     _check(lib().mcdc_run(p.handle, int(n_histories), int(seed), C.byref(opt), C.byref(res)))
     out["events"] = np.array(res.n_events[:], dtype=np.uint64)
     out["terms"] = np.array(res.n_term[:], dtype=np.uint64)
@@ -263,3 +276,152 @@ def mcdc_run(p: Problem, n_histories: int, seed: int, algorithm: str = "event",
     out["qoi_var"] = res.qoi_var
     out["kernel_ms"] = res.kernel_ms
     return out
+
+
+# ---------------------------------------------------------------------------
+# weight-window network
+# ---------------------------------------------------------------------------
+MLP_WIDTHS = (8, 64, 64, 64, 1)
+MLP_PARAMS = 8961
+_mlp_ready = False
+
+
+def _mlp_lib():
+    global _mlp_ready
+    L = lib()
+    if not _mlp_ready:
+        L.mcdc_mlp_create.argtypes = [C.POINTER(C.c_int32), C.c_int32, C.c_uint64, C.POINTER(C.c_void_p)]
+        L.mcdc_mlp_create.restype = C.c_int
+        L.mcdc_mlp_destroy.argtypes = [C.c_void_p]
+        L.mcdc_mlp_destroy.restype = C.c_int
+        L.mcdc_mlp_get_params.argtypes = [C.c_void_p, C.c_void_p]
+        L.mcdc_mlp_get_params.restype = C.c_int
+        L.mcdc_mlp_set_params.argtypes = [C.c_void_p, C.c_void_p]
+        L.mcdc_mlp_set_params.restype = C.c_int
+        L.mcdc_mlp_grad.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64,
+                                    C.POINTER(C.c_float), C.c_void_p, C.c_void_p]
+        L.mcdc_mlp_grad.restype = C.c_int
+        L.mcdc_mlp_train.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int32,
+                                     C.c_float, C.c_void_p, C.c_void_p]
+        L.mcdc_mlp_train.restype = C.c_int
+        L.mcdc_mlp_infer.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]
+        L.mcdc_mlp_infer.restype = C.c_int
+        _mlp_ready = True
+    return L
+
+
+def _f32_dev(t):
+    import torch
+
+    assert t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()
+    return t.data_ptr()
+
+
+class MLP:
+    """Owning wrapper of an mcdc_mlp handle (device tensors in, device
+    tensors out)."""
+
+    def __init__(self, seed: int = 1):
+        L = _mlp_lib()
+        w = (C.c_int32 * 5)(*MLP_WIDTHS)
+        h = C.c_void_p()
+        _check(L.mcdc_mlp_create(w, 4, seed, C.byref(h)))
+        self.handle = h
+
+    def close(self):
+        if self.handle is not None and self.handle.value:
+            _mlp_lib().mcdc_mlp_destroy(self.handle)
+        self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def get_params(self):
+        out = np.zeros(MLP_PARAMS, dtype=np.float32)
+        _check(_mlp_lib().mcdc_mlp_get_params(self.handle, out.ctypes.data))
+        return out
+
+    def set_params(self, p):
+        p = np.ascontiguousarray(np.asarray(p, dtype=np.float32))
+        assert p.size == MLP_PARAMS
+        _check(_mlp_lib().mcdc_mlp_set_params(self.handle, p.ctypes.data))
+
+    def _stream(self):
+        import torch
+
+        return torch.cuda.current_stream().cuda_stream
+
+    def grad(self, X, T, W):
+        g = np.zeros(MLP_PARAMS, dtype=np.float32)
+        loss = C.c_float()
+        _check(_mlp_lib().mcdc_mlp_grad(self.handle, _f32_dev(X), _f32_dev(T), _f32_dev(W), X.shape[0],
+                                        C.byref(loss), g.ctypes.data, self._stream()))
+        return float(loss.value), g
+
+    def train(self, X, T, W, steps: int, lr: float = 1e-3):
+        losses = np.zeros(max(steps, 1), dtype=np.float32)
+        _check(_mlp_lib().mcdc_mlp_train(self.handle, _f32_dev(X), _f32_dev(T), _f32_dev(W), X.shape[0],
+                                         steps, lr, losses.ctypes.data, self._stream()))
+        return losses[:steps]
+
+    def infer(self, X):
+        import torch
+
+        Y = torch.empty(X.shape[0], dtype=torch.float32, device=X.device)
+        _check(_mlp_lib().mcdc_mlp_infer(self.handle, _f32_dev(X), X.shape[0], _f32_dev(Y), self._stream()))
+        return Y
+
+
+def mcdc_mlp_create(seed: int = 1) -> MLP:
+    return MLP(seed)
+
+
+def mcdc_run_batched(problems, n_hist, seeds, block_size: int = 0, outputs=("mean", "var")):
+    """Run many problems in one persistent launch (history-based).  Returns
+    one result dict per problem, like mcdc_run."""
+    import torch
+
+    L = lib()
+    if not getattr(L, "_batched_ready", False):
+        L.mcdc_run_batched.argtypes = [C.POINTER(C.c_void_p), C.c_int32, C.POINTER(C.c_uint64),
+                                       C.POINTER(C.c_uint64), C.POINTER(mcdc_run_options),
+                                       C.POINTER(mcdc_result)]
+        L.mcdc_run_batched.restype = C.c_int
+        L._batched_ready = True
+    n = len(problems)
+    dev = torch.device("cuda", torch.cuda.current_device())
+    hs = (C.c_void_p * n)(*[p.handle.value for p in problems])
+    nh = (C.c_uint64 * n)(*[int(x) for x in n_hist])
+    sd = (C.c_uint64 * n)(*[int(x) for x in seeds])
+    res = (mcdc_result * n)()
+    outs = []
+    for j, p in enumerate(problems):
+        o = {}
+        for name in ("mean", "var", "raw"):
+            if name in outputs:
+                t = torch.empty(p.tally_shape, dtype=torch.float64, device=dev)
+                o[name] = t
+                setattr(res[j], name, t.data_ptr())
+        for name in ("leak_mean", "leak_var"):
+            if name in outputs:
+                t = torch.empty(p.leak_shape, dtype=torch.float64, device=dev)
+                o[name] = t
+                setattr(res[j], name, t.data_ptr())
+        outs.append(o)
+    opt = mcdc_run_options()
+    opt.algorithm = MCDC_ALG_HISTORY
+    opt.block_size = block_size
+    opt.stream = torch.cuda.current_stream(dev).cuda_stream
+    _check(L.mcdc_run_batched(hs, n, nh, sd, C.byref(opt), res))
+    for j, o in enumerate(outs):
+        r = res[j]
+        o["events"] = np.array(r.n_events[:], dtype=np.uint64)
+        o["terms"] = np.array(r.n_term[:], dtype=np.uint64)
+        o["qoi_sum"] = (r.qoi_sum[0], r.qoi_sum[1])
+        o["qoi_mean"] = r.qoi_mean
+        o["qoi_var"] = r.qoi_var
+        o["kernel_ms"] = r.kernel_ms
+    return outs

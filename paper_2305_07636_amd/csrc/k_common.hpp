@@ -231,13 +231,25 @@ __device__ __forceinline__ void move(const DevProblem &P, Particle &p, const Fli
     }
 }
 
-// Surface crossing of every axis whose plane distance equals the flight.
-// Returns the vacuum face crossed (particle leaks), or -1.
+// Axes whose plane distance equals the flight: they all cross in this one
+// surface event.
 template <int FM>
-__device__ __forceinline__ int cross(const DevProblem &P, Particle &p, const Flight &f) {
+__device__ __forceinline__ int crossing_mask(const DevProblem &P, const Flight &f) {
+    int m = 0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+        if (finite_axis<FM>(P, a) && f.da[a] == f.d) m |= 1 << a;
+    return m;
+}
+
+// Surface crossing of the axes in mask, in axis order: snap onto the plane,
+// step the cell index, reflect at a reflective face.  Returns the vacuum
+// face crossed (the particle leaks; later axes are not processed), or -1.
+template <int FM>
+__device__ __forceinline__ int cross(const DevProblem &P, Particle &p, int mask) {
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        if (!finite_axis<FM>(P, a) || f.da[a] != f.d) continue;
+        if (!finite_axis<FM>(P, a) || !((mask >> a) & 1)) continue;
         int face = -1;
         if (p.u[a] > 0.0) {
             p.x[a] = P.U[a][p.ix[a] + 1];
@@ -285,6 +297,98 @@ __device__ __forceinline__ double ww_centre(const DevProblem &P, int cell, int g
     int c = P.cell_ww[cell];
     if (c < 0) return 0.0;
     return P.ww_center[((int64_t)k * P.G + g) * P.nww + c];
+}
+
+// Weight-window game at a check point (after a scatter, a census, or a
+// surface crossing into a new window cell).  Returns false if the particle
+// loses the roulette.  On a split the particle keeps weight w / n and
+// n_children = n - 1 copies are to be made, child j taking the stream
+// child_stream(s, j) of the particle's current state s.
+__device__ __forceinline__ bool ww_check(const DevProblem &P, Particle &p, int cell, int &n_children) {
+    n_children = 0;
+    const double wc = ww_centre(P, cell, p.g, p.k);
+    if (wc == 0.0) return true;
+    const double rho = P.ww_ratio;
+    const double wl = (2.0 * wc) / (1.0 + rho);
+    const double wu = rho * wl;
+    if (p.w > wu) {
+        const double nr = ceil(p.w / wu);
+        const int n = (nr > (double)P.ww_max_split) ? P.ww_max_split : (int)nr;
+        if (n > 1) {
+            p.w = p.w / (double)n;
+            n_children = n - 1;
+        }
+    } else if (p.w < wl) {
+        const double xi = rn(p.s);
+        if (xi < p.w / wc)
+            p.w = wc;
+        else
+            return false;
+    }
+    return true;
+}
+
+// Structure-of-arrays bank of split progeny (whole particle states).
+struct SplitBank {
+    double *x[3], *u[3], *t, *tau, *w;
+    uint64_t *s;
+    uint32_t *ixyz, *gk;      // gk = g | batch << 5 | k << 15
+    uint64_t *hid;            // global history index
+    unsigned int *count;      // device counter of entries
+    unsigned int cap;
+};
+
+__device__ __forceinline__ void split_store(const SplitBank &B, unsigned int slot, const Particle &p, int b,
+                                            uint64_t hid) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        B.x[a][slot] = p.x[a];
+        B.u[a][slot] = p.u[a];
+    }
+    B.t[slot] = p.t;
+    B.tau[slot] = p.tau;
+    B.w[slot] = p.w;
+    B.s[slot] = p.s;
+    B.ixyz[slot] = (uint32_t)p.ix[0] | ((uint32_t)p.ix[1] << 11) | ((uint32_t)p.ix[2] << 22);
+    B.gk[slot] = (uint32_t)p.g | ((uint32_t)b << 5) | ((uint32_t)p.k << 15);
+    B.hid[slot] = hid;
+}
+
+__device__ __forceinline__ void split_load(const SplitBank &B, unsigned int slot, Particle &p, int &b,
+                                           uint64_t &hid) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        p.x[a] = B.x[a][slot];
+        p.u[a] = B.u[a][slot];
+    }
+    p.t = B.t[slot];
+    p.tau = B.tau[slot];
+    p.w = B.w[slot];
+    p.s = B.s[slot];
+    const uint32_t c = B.ixyz[slot];
+    p.ix[0] = c & 2047u;
+    p.ix[1] = (c >> 11) & 2047u;
+    p.ix[2] = c >> 22;
+    const uint32_t gk = B.gk[slot];
+    p.g = gk & 31u;
+    b = (gk >> 5) & 1023u;
+    p.k = gk >> 15;
+    hid = B.hid[slot];
+}
+
+// Append the n_children split copies of p (streams child_stream(p.s, j),
+// j = 1..n_children) to the split bank.  Returns false on overflow.
+__device__ __forceinline__ bool spawn_children(const SplitBank &B, const Particle &p, int n_children, int b,
+                                               uint64_t hid) {
+    if (n_children <= 0) return true;
+    const unsigned int base = atomicAdd(B.count, (unsigned int)n_children);
+    if (base + (unsigned int)n_children > B.cap) return false;
+    Particle c = p;
+    for (int j = 1; j <= n_children; ++j) {
+        c.s = child_stream(p.s, (uint64_t)j);
+        split_store(B, base + j - 1, c, b, hid);
+    }
+    return true;
 }
 
 __device__ __forceinline__ void atomic_add_f64(double *a, double v) {

@@ -71,6 +71,25 @@ struct RunArgs {
     uint32_t *dbg_counts;          // [N][5] or nullptr
     double *dbg_scores;            // [N][2] or nullptr
     int *overflow;                 // set to 1 when a bank overflows
+    unsigned long long *prof;      // [MCDC_PROF_CLASSES][2] particles, bytes; or nullptr
+};
+
+// One problem of a batched solve (device array element).
+struct BatchItem {
+    DevProblem P;
+    RunArgs R;
+};
+
+// Host-side launch profiler: HIP events around each launch of a class.
+struct Profiler {
+    double *out = nullptr;             // host [classes][4] or nullptr
+    hipStream_t st = nullptr;
+    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> marks;
+    int cls = -1;
+    hipEvent_t open = nullptr;
+    void begin(int c);
+    void end();
+    int finish();                      // synchronise, accumulate, destroy events
 };
 
 // Host-side compiled problem (owns the device blob).
@@ -107,7 +126,7 @@ struct mcdc_problem {
         void *p = nullptr;
         size_t bytes = 0;
     };
-    Buf S, L, qoi_hist, qoi_sums, counters, overflow, bank, queues, split;
+    Buf S, L, qoi_hist, qoi_sums, counters, overflow, bank, queues, split, prof, counters_split, tally_part;
     Buf mean, var, raw, leak_mean, leak_var;
 };
 
@@ -118,15 +137,17 @@ int hip_fail(hipError_t e, const char *what);
 int ensure(mcdc_problem::Buf &b, size_t bytes);
 
 // launchers (return a hipError_t as int)
-int launch_history(const DevProblem &P, const RunArgs &R, uint64_t first, uint64_t count,
-                   int block, hipStream_t st);
+int launch_history(mcdc_problem *p, const RunArgs &R, uint64_t first, uint64_t count,
+                   int block, hipStream_t st, Profiler &prof);
 int launch_event(mcdc_problem *p, const RunArgs &R, uint64_t first, uint64_t count,
-                 const mcdc_run_options &opt, hipStream_t st);
+                 const mcdc_run_options &opt, hipStream_t st, Profiler &prof);
 int launch_fold(const DevProblem &P, const double *S, const double *L, int B, uint64_t N,
                 const double *bin_norm_dev, const double *time_norm_dev, double *mean,
                 double *var, double *raw, double *leak_mean, double *leak_var,
                 hipStream_t st);
 int launch_zero(void *p, size_t bytes, hipStream_t st);
+int launch_batched(const BatchItem *items, const uint64_t *offs, int n_items, uint64_t total,
+                   unsigned long long *next, int finite_mask, int block, int per_thread, hipStream_t st);
 int launch_qoi_reduce(const double *qoi_hist, uint64_t n, double *qoi_sums, hipStream_t st);
 
 }  // namespace mcdc

@@ -426,7 +426,8 @@ extern "C" int mcdc_problem_destroy(mcdc_problem *p) {
     if (p->blob) (void)hipFree(p->blob);
     if (p->ww_dev) (void)hipFree(p->ww_dev);
     mcdc_problem::Buf *bufs[] = {&p->S, &p->L, &p->qoi_hist, &p->qoi_sums, &p->counters,
-                                 &p->overflow, &p->bank, &p->queues, &p->split, &p->mean,
+                                 &p->overflow, &p->bank, &p->queues, &p->split, &p->prof,
+                                 &p->counters_split, &p->tally_part, &p->mean,
                                  &p->var, &p->raw, &p->leak_mean, &p->leak_var};
     for (auto *b : bufs) free_buf(*b);
     delete p;

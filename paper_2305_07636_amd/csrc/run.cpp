@@ -1,13 +1,52 @@
-// mcdc_run: buffers, kernel sequence, batch statistics and result hand-off.
+// mcdc_run and mcdc_run_batched: buffers, kernel sequence, batch statistics
+// and result hand-off.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <string>
+#include <vector>
 
 #include "mcdc_internal.hpp"
 
 using namespace mcdc;
+
+void Profiler::begin(int c) {
+    if (!out) return;
+    cls = c;
+    open = nullptr;
+    if (hipEventCreate(&open) != hipSuccess) {
+        open = nullptr;
+        return;
+    }
+    (void)hipEventRecord(open, st);
+}
+
+void Profiler::end() {
+    if (!out || !open) return;
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return;
+    (void)hipEventRecord(e, st);
+    marks.push_back({cls, {open, e}});
+    open = nullptr;
+}
+
+int Profiler::finish() {
+    if (!out) return MCDC_OK;
+    hipError_t err = hipStreamSynchronize(st);
+    for (auto &m : marks) {
+        float ms = 0.f;
+        if (err == hipSuccess) err = hipEventElapsedTime(&ms, m.second.first, m.second.second);
+        out[m.first * 4 + 0] += ms;
+        out[m.first * 4 + 1] += 1.0;
+        (void)hipEventDestroy(m.second.first);
+        (void)hipEventDestroy(m.second.second);
+    }
+    marks.clear();
+    if (err != hipSuccess) return hip_fail(err, "profile events");
+    return MCDC_OK;
+}
 
 namespace {
 
@@ -17,63 +56,48 @@ namespace {
         if (e_ != hipSuccess) return hip_fail(e_, what);       \
     } while (0)
 
+#define ZERO(ptr, bytes)                                                        \
+    do {                                                                        \
+        int r_ = launch_zero((ptr), (bytes), st);                               \
+        if (r_) return hip_fail((hipError_t)r_, "zero fill");                   \
+    } while (0)
+
 int bad(const char *m) {
     set_error(std::string("invalid argument: ") + m);
     return MCDC_E_INVALID;
 }
 
-}  // namespace
-
-extern "C" int mcdc_run(mcdc_problem *p, uint64_t n_histories, uint64_t seed,
-                        const mcdc_run_options *opt_in, mcdc_result *out) {
-    if (!p) return bad("problem is NULL");
-    if (!out) return bad("result is NULL");
-    if (n_histories == 0) return bad("n_histories must be > 0");
-    mcdc_run_options opt{};
-    if (opt_in) opt = *opt_in;
-    if (opt.algorithm != MCDC_ALG_EVENT && opt.algorithm != MCDC_ALG_HISTORY)
-        return bad("unknown algorithm");
+int check_options(const mcdc_run_options &opt) {
+    if (opt.algorithm != MCDC_ALG_EVENT && opt.algorithm != MCDC_ALG_HISTORY) return bad("unknown algorithm");
     if (opt.block_size != 0 && (opt.block_size < 64 || opt.block_size > 1024 || opt.block_size % 64))
         return bad("block_size must be a multiple of 64 in [64, 1024]");
     if (opt.bank_capacity < 0) return bad("bank_capacity must be >= 0");
-    if (opt.algorithm == MCDC_ALG_HISTORY && p->d.ww_center != nullptr) {
-        set_error("weight windows run with the event-based algorithm only");
-        return MCDC_E_UNSUPPORTED;
-    }
-    HIP_CHECK(hipSetDevice(p->device), "hipSetDevice");
-    hipStream_t st = (hipStream_t)opt.stream;
+    if (opt.event_iters < 0) return bad("event_iters must be >= 0");
+    return MCDC_OK;
+}
+
+// Allocate and clear the per-run device buffers of a problem; fill R.
+int prepare(mcdc_problem *p, uint64_t N, uint64_t seed, const mcdc_run_options &opt, hipStream_t st, RunArgs &R) {
     const DevProblem &P = p->d;
-    const uint64_t N = n_histories;
     const int B = (int)((uint64_t)p->h.B < N ? (uint64_t)p->h.B : N);
     const size_t nS = (size_t)B * P.ntally;
     const size_t nL = (size_t)B * P.K * P.G * 6;
-
     int rc;
     if ((rc = ensure(p->S, nS * sizeof(double)))) return rc;
     if ((rc = ensure(p->L, nL * sizeof(double)))) return rc;
     if ((rc = ensure(p->qoi_sums, 2 * sizeof(double)))) return rc;
     if ((rc = ensure(p->counters, kCounters * sizeof(unsigned long long)))) return rc;
     if ((rc = ensure(p->overflow, sizeof(int)))) return rc;
-
-    hipEvent_t e0, e1;
-    HIP_CHECK(hipEventCreate(&e0), "hipEventCreate");
-    HIP_CHECK(hipEventCreate(&e1), "hipEventCreate");
-    HIP_CHECK(hipEventRecord(e0, st), "hipEventRecord");
-
-    if ((rc = launch_zero(p->S.p, nS * sizeof(double), st))) return hip_fail((hipError_t)rc, "zero");
-    if ((rc = launch_zero(p->L.p, nL * sizeof(double), st))) return hip_fail((hipError_t)rc, "zero");
-    if ((rc = launch_zero(p->qoi_sums.p, 2 * sizeof(double), st))) return hip_fail((hipError_t)rc, "zero");
-    if ((rc = launch_zero(p->counters.p, kCounters * sizeof(unsigned long long), st)))
-        return hip_fail((hipError_t)rc, "zero");
-    if ((rc = launch_zero(p->overflow.p, sizeof(int), st))) return hip_fail((hipError_t)rc, "zero");
-    if (opt.debug_counts &&
-        (rc = launch_zero(opt.debug_counts, (size_t)N * 5 * sizeof(uint32_t), st)))
-        return hip_fail((hipError_t)rc, "zero");
-    if (opt.debug_scores &&
-        (rc = launch_zero(opt.debug_scores, (size_t)N * 2 * sizeof(double), st)))
-        return hip_fail((hipError_t)rc, "zero");
-
-    RunArgs R{};
+    if ((rc = ensure(p->prof, 2 * MCDC_PROF_CLASSES * sizeof(unsigned long long)))) return rc;
+    ZERO(p->S.p, nS * sizeof(double));
+    ZERO(p->L.p, nL * sizeof(double));
+    ZERO(p->qoi_sums.p, 2 * sizeof(double));
+    ZERO(p->counters.p, kCounters * sizeof(unsigned long long));
+    ZERO(p->overflow.p, sizeof(int));
+    if (opt.profile) ZERO(p->prof.p, 2 * MCDC_PROF_CLASSES * sizeof(unsigned long long));
+    if (opt.debug_counts) ZERO(opt.debug_counts, (size_t)N * 5 * sizeof(uint32_t));
+    if (opt.debug_scores) ZERO(opt.debug_scores, (size_t)N * 2 * sizeof(double));
+    R = RunArgs{};
     R.N = N;
     R.seed = seed;
     R.B = B;
@@ -85,19 +109,18 @@ extern "C" int mcdc_run(mcdc_problem *p, uint64_t n_histories, uint64_t seed,
     R.dbg_scores = opt.debug_scores;
     R.overflow = (int *)p->overflow.p;
     R.qoi_hist = nullptr;
+    R.prof = opt.profile ? (unsigned long long *)p->prof.p : nullptr;
+    return MCDC_OK;
+}
 
-    if (opt.algorithm == MCDC_ALG_HISTORY) {
-        rc = launch_history(P, R, 0, N, opt.block_size, st);
-        if (rc) return hip_fail((hipError_t)rc, "history kernel launch");
-    } else {
-        rc = launch_event(p, R, 0, N, opt, st);
-        if (rc) return rc;
-    }
-
-    // batch statistics into caller buffers (device) or staging (host outputs)
+// Batch statistics into the caller's buffers (device) or staging buffers
+// (host outputs).
+int fold(mcdc_problem *p, const RunArgs &R, mcdc_result *out, hipStream_t st, Profiler &prof) {
+    const DevProblem &P = p->d;
     double *mean = out->mean, *var = out->var, *raw = out->raw;
     double *lmean = out->leak_mean, *lvar = out->leak_var;
     const size_t nleak = (size_t)P.K * P.G * 6;
+    int rc;
     if (out->host_outputs) {
         if (mean && (rc = ensure(p->mean, P.ntally * sizeof(double)))) return rc;
         if (var && (rc = ensure(p->var, P.ntally * sizeof(double)))) return rc;
@@ -110,46 +133,265 @@ extern "C" int mcdc_run(mcdc_problem *p, uint64_t n_histories, uint64_t seed,
         lmean = lmean ? (double *)p->leak_mean.p : nullptr;
         lvar = lvar ? (double *)p->leak_var.p : nullptr;
     }
-    rc = launch_fold(P, R.S, R.L, B, N, P.bin_norm, P.time_norm, mean, var, raw, lmean, lvar, st);
-    if (rc) return hip_fail((hipError_t)rc, "fold kernel launch");
-    HIP_CHECK(hipEventRecord(e1, st), "hipEventRecord");
+    prof.begin(MCDC_PROF_OTHER);
+    rc = launch_fold(P, R.S, R.L, R.B, R.N, P.bin_norm, P.time_norm, mean, var, raw, lmean, lvar, st);
+    prof.end();
+    return rc ? hip_fail((hipError_t)rc, "fold kernel launch") : MCDC_OK;
+}
 
+// Host copies of counters, detector sums and (host) outputs.  The caller
+// synchronises the stream between collect_begin and collect_end.
+struct Collect {
     unsigned long long cnt[kCounters];
     double qs[2];
-    int ovf = 0;
-    HIP_CHECK(hipMemcpyAsync(cnt, p->counters.p, sizeof(cnt), hipMemcpyDeviceToHost, st), "copy counters");
-    HIP_CHECK(hipMemcpyAsync(qs, p->qoi_sums.p, sizeof(qs), hipMemcpyDeviceToHost, st), "copy detector");
-    HIP_CHECK(hipMemcpyAsync(&ovf, p->overflow.p, sizeof(int), hipMemcpyDeviceToHost, st), "copy flag");
+    int ovf;
+};
+
+int collect_begin(mcdc_problem *p, mcdc_result *out, Collect &c, hipStream_t st) {
+    const DevProblem &P = p->d;
+    HIP_CHECK(hipMemcpyAsync(c.cnt, p->counters.p, sizeof(c.cnt), hipMemcpyDeviceToHost, st), "copy counters");
+    HIP_CHECK(hipMemcpyAsync(c.qs, p->qoi_sums.p, sizeof(c.qs), hipMemcpyDeviceToHost, st), "copy detector");
+    HIP_CHECK(hipMemcpyAsync(&c.ovf, p->overflow.p, sizeof(int), hipMemcpyDeviceToHost, st), "copy flag");
     if (out->host_outputs) {
-        if (out->mean)
-            HIP_CHECK(hipMemcpyAsync(out->mean, mean, P.ntally * sizeof(double), hipMemcpyDeviceToHost, st), "copy mean");
-        if (out->var)
-            HIP_CHECK(hipMemcpyAsync(out->var, var, P.ntally * sizeof(double), hipMemcpyDeviceToHost, st), "copy var");
-        if (out->raw)
-            HIP_CHECK(hipMemcpyAsync(out->raw, raw, P.ntally * sizeof(double), hipMemcpyDeviceToHost, st), "copy raw");
+        const size_t nt = P.ntally * sizeof(double), nl = (size_t)P.K * P.G * 6 * sizeof(double);
+        if (out->mean) HIP_CHECK(hipMemcpyAsync(out->mean, p->mean.p, nt, hipMemcpyDeviceToHost, st), "copy mean");
+        if (out->var) HIP_CHECK(hipMemcpyAsync(out->var, p->var.p, nt, hipMemcpyDeviceToHost, st), "copy var");
+        if (out->raw) HIP_CHECK(hipMemcpyAsync(out->raw, p->raw.p, nt, hipMemcpyDeviceToHost, st), "copy raw");
         if (out->leak_mean)
-            HIP_CHECK(hipMemcpyAsync(out->leak_mean, lmean, nleak * sizeof(double), hipMemcpyDeviceToHost, st), "copy leak");
+            HIP_CHECK(hipMemcpyAsync(out->leak_mean, p->leak_mean.p, nl, hipMemcpyDeviceToHost, st), "copy leak");
         if (out->leak_var)
-            HIP_CHECK(hipMemcpyAsync(out->leak_var, lvar, nleak * sizeof(double), hipMemcpyDeviceToHost, st), "copy leak var");
+            HIP_CHECK(hipMemcpyAsync(out->leak_var, p->leak_var.p, nl, hipMemcpyDeviceToHost, st), "copy leak var");
     }
-    HIP_CHECK(hipStreamSynchronize(st), "hipStreamSynchronize");
-    float ms = 0.f;
-    HIP_CHECK(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    if (ovf) {
+    return MCDC_OK;
+}
+
+int collect_end(mcdc_problem *p, uint64_t N, const Collect &c, mcdc_result *out, double ms) {
+    if (c.ovf) {
         set_error("particle bank or split bank overflow");
         return MCDC_E_OVERFLOW;
     }
-    for (int j = 0; j < 3; ++j) out->n_events[j] = cnt[j];
-    for (int j = 0; j < 5; ++j) out->n_term[j] = cnt[3 + j];
-    out->n_splits = cnt[8];
-    out->qoi_sum[0] = qs[0];
-    out->qoi_sum[1] = qs[1];
+    for (int j = 0; j < 3; ++j) out->n_events[j] = c.cnt[j];
+    for (int j = 0; j < 5; ++j) out->n_term[j] = c.cnt[3 + j];
+    out->n_splits = c.cnt[8];
+    out->qoi_sum[0] = c.qs[0];
+    out->qoi_sum[1] = c.qs[1];
     const double V = p->h.qoi_volume;
     const double Nd = (double)N;
-    out->qoi_mean = P.qoi_on ? qs[0] / (Nd * V) : 0.0;
-    out->qoi_var = (P.qoi_on && N > 1) ? (qs[1] - qs[0] * qs[0] / Nd) / (Nd * (Nd - 1.0)) / (V * V) : 0.0;
+    const bool q = p->d.qoi_on != 0;
+    out->qoi_mean = q ? c.qs[0] / (Nd * V) : 0.0;
+    out->qoi_var = (q && N > 1) ? (c.qs[1] - c.qs[0] * c.qs[0] / Nd) / (Nd * (Nd - 1.0)) / (V * V) : 0.0;
     out->kernel_ms = ms;
+    return MCDC_OK;
+}
+
+struct Events {
+    hipEvent_t a = nullptr, b = nullptr;
+    ~Events() {
+        if (a) (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
+    }
+};
+
+}  // namespace
+
+extern "C" int mcdc_run(mcdc_problem *p, uint64_t n_histories, uint64_t seed, const mcdc_run_options *opt_in,
+                        mcdc_result *out) {
+    if (!p) return bad("problem is NULL");
+    if (!out) return bad("result is NULL");
+    if (n_histories == 0) return bad("n_histories must be > 0");
+    mcdc_run_options opt{};
+    if (opt_in) opt = *opt_in;
+    int rc = check_options(opt);
+    if (rc) return rc;
+    HIP_CHECK(hipSetDevice(p->device), "hipSetDevice");
+    hipStream_t st = (hipStream_t)opt.stream;
+    Profiler prof;
+    prof.out = opt.profile;
+    prof.st = st;
+    Events ev;
+    HIP_CHECK(hipEventCreate(&ev.a), "hipEventCreate");
+    HIP_CHECK(hipEventCreate(&ev.b), "hipEventCreate");
+    HIP_CHECK(hipEventRecord(ev.a, st), "hipEventRecord");
+
+    RunArgs R;
+    if ((rc = prepare(p, n_histories, seed, opt, st, R))) return rc;
+    if (opt.algorithm == MCDC_ALG_HISTORY)
+        rc = launch_history(p, R, 0, n_histories, opt.block_size, st, prof);
+    else
+        rc = launch_event(p, R, 0, n_histories, opt, st, prof);
+    if (rc) return rc;
+    if ((rc = fold(p, R, out, st, prof))) return rc;
+    HIP_CHECK(hipEventRecord(ev.b, st), "hipEventRecord");
+
+    Collect c{};
+    if ((rc = collect_begin(p, out, c, st))) return rc;
+    unsigned long long pc[2 * MCDC_PROF_CLASSES] = {};
+    if (opt.profile) HIP_CHECK(hipMemcpyAsync(pc, p->prof.p, sizeof(pc), hipMemcpyDeviceToHost, st), "copy profile");
+    HIP_CHECK(hipStreamSynchronize(st), "hipStreamSynchronize");
+    if ((rc = prof.finish())) return rc;
+    if (opt.profile)
+        for (int k = 0; k < MCDC_PROF_CLASSES; ++k) {
+            opt.profile[k * 4 + 2] += (double)pc[2 * k];
+            opt.profile[k * 4 + 3] += (double)pc[2 * k + 1];
+        }
+    float ms = 0.f;
+    HIP_CHECK(hipEventElapsedTime(&ms, ev.a, ev.b), "hipEventElapsedTime");
+    return collect_end(p, n_histories, c, out, ms);
+}
+
+// ---------------------------------------------------------------------------
+// batched solve
+// ---------------------------------------------------------------------------
+namespace {
+
+struct Tuned {
+    int block, per_thread;
+};
+
+std::map<std::string, Tuned> &tune_cache() {
+    static std::map<std::string, Tuned> m;
+    return m;
+}
+
+std::string signature(mcdc_problem *const *ps, int32_t n, const uint64_t *n_hist) {
+    std::string s;
+    for (int j = 0; j < n; ++j) {
+        const DevProblem &P = ps[j]->d;
+        s += std::to_string(P.G) + "," + std::to_string(P.ncells) + "," + std::to_string(P.ntally) + "," +
+             std::to_string(P.finite_mask) + "," + std::to_string(n_hist[j]) + ";";
+    }
+    return s;
+}
+
+struct DevMem {
+    void *mem = nullptr;
+    ~DevMem() {
+        if (mem) (void)hipFree(mem);
+    }
+};
+
+}  // namespace
+
+extern "C" int mcdc_run_batched(mcdc_problem *const *ps, int32_t n, const uint64_t *n_hist, const uint64_t *seeds,
+                                const mcdc_run_options *opt_in, mcdc_result *outs) {
+    if (!ps || !n_hist || !seeds || !outs || n <= 0) return bad("NULL argument or n <= 0");
+    mcdc_run_options opt{};
+    if (opt_in) opt = *opt_in;
+    int rc = check_options(opt);
+    if (rc) return rc;
+    if (opt.debug_counts || opt.debug_scores || opt.profile) {
+        set_error("batched solves take no debug or profile arrays");
+        return MCDC_E_UNSUPPORTED;
+    }
+    if (!ps[0]) return bad("NULL problem in batch");
+    const int dev = ps[0]->device;
+    int fm = -1;
+    uint64_t total = 0;
+    for (int j = 0; j < n; ++j) {
+        if (!ps[j]) return bad("NULL problem in batch");
+        if (ps[j]->device != dev) return bad("all problems of a batch must be on one device");
+        if (ps[j]->d.ww_center) {
+            set_error("batched solves run analog (no weight windows)");
+            return MCDC_E_UNSUPPORTED;
+        }
+        if (ps[j]->h.B > 1023) {
+            set_error("at most 1023 batches");
+            return MCDC_E_UNSUPPORTED;
+        }
+        for (int k = 0; k < j; ++k)
+            if (ps[k] == ps[j]) return bad("a problem appears twice in the batch");
+        const int m = ps[j]->d.finite_mask;
+        fm = (fm < 0 || fm == m) ? m : 0;
+        total += n_hist[j];
+    }
+    if (total == 0) return bad("no histories");
+    HIP_CHECK(hipSetDevice(dev), "hipSetDevice");
+    hipStream_t st = (hipStream_t)opt.stream;
+
+    // device arrays: items, history offsets, work counter
+    std::vector<BatchItem> items(n);
+    std::vector<uint64_t> offs(n + 1, 0);
+    for (int j = 0; j < n; ++j) offs[j + 1] = offs[j] + n_hist[j];
+    DevMem bd;
+    const size_t items_bytes = (sizeof(BatchItem) * n + 255) & ~size_t(255);
+    const size_t offs_bytes = ((n + 1) * sizeof(uint64_t) + 255) & ~size_t(255);
+    HIP_CHECK(hipMalloc(&bd.mem, items_bytes + offs_bytes + 256), "hipMalloc(batch)");
+    BatchItem *d_items = (BatchItem *)bd.mem;
+    uint64_t *d_offs = (uint64_t *)((char *)bd.mem + items_bytes);
+    unsigned long long *d_next = (unsigned long long *)((char *)bd.mem + items_bytes + offs_bytes);
+    HIP_CHECK(hipMemcpyAsync(d_offs, offs.data(), (n + 1) * sizeof(uint64_t), hipMemcpyHostToDevice, st),
+              "copy offsets");
+
+    mcdc_run_options popt = opt;
+    popt.algorithm = MCDC_ALG_HISTORY;
+    auto run_once = [&](int block, int per_thread, float *ms) -> int {
+        Events ev;
+        HIP_CHECK(hipEventCreate(&ev.a), "hipEventCreate");
+        HIP_CHECK(hipEventCreate(&ev.b), "hipEventCreate");
+        HIP_CHECK(hipEventRecord(ev.a, st), "hipEventRecord");
+        for (int j = 0; j < n; ++j) {
+            items[j] = BatchItem{};
+            items[j].P = ps[j]->d;
+            if (n_hist[j] == 0) continue;
+            int r = prepare(ps[j], n_hist[j], seeds[j], popt, st, items[j].R);
+            if (r) return r;
+        }
+        HIP_CHECK(hipMemcpyAsync(d_items, items.data(), sizeof(BatchItem) * n, hipMemcpyHostToDevice, st),
+                  "copy items");
+        int r = launch_zero(d_next, sizeof(unsigned long long), st);
+        if (r) return hip_fail((hipError_t)r, "zero");
+        r = launch_batched(d_items, d_offs, n, total, d_next, fm, block, per_thread, st);
+        if (r) return r;
+        HIP_CHECK(hipEventRecord(ev.b, st), "hipEventRecord");
+        HIP_CHECK(hipEventSynchronize(ev.b), "hipEventSynchronize");
+        HIP_CHECK(hipEventElapsedTime(ms, ev.a, ev.b), "hipEventElapsedTime");
+        return MCDC_OK;
+    };
+
+    // launch shape: forced, cached, or tuned now over workgroup size and
+    // histories per thread per pull (a shape never changes per-history
+    // results, only the summation order of the tallies)
+    Tuned t{opt.block_size ? opt.block_size : 256, 4};
+    const std::string sig = signature(ps, n, n_hist);
+    float ms = 0.f;
+    if (!opt.block_size) {
+        auto it = tune_cache().find(sig);
+        if (it != tune_cache().end()) {
+            t = it->second;
+        } else {
+            float best = 1e30f;
+            const int blocks[] = {128, 256, 512};
+            const int pts[] = {1, 4, 16};
+            for (int bsz : blocks)
+                for (int pt : pts) {
+                    float m = 0.f;
+                    if ((rc = run_once(bsz, pt, &m))) return rc;
+                    if (m < best) {
+                        best = m;
+                        t = Tuned{bsz, pt};
+                    }
+                }
+            tune_cache()[sig] = t;
+        }
+    }
+    if ((rc = run_once(t.block, t.per_thread, &ms))) return rc;
+
+    Profiler none;
+    std::vector<Collect> cs(n);
+    for (int j = 0; j < n; ++j) {
+        if (n_hist[j] == 0) continue;
+        if ((rc = fold(ps[j], items[j].R, &outs[j], st, none))) return rc;
+        if ((rc = collect_begin(ps[j], &outs[j], cs[j], st))) return rc;
+    }
+    HIP_CHECK(hipStreamSynchronize(st), "hipStreamSynchronize");
+    for (int j = 0; j < n; ++j) {
+        if (n_hist[j] == 0) {
+            std::memset(outs[j].n_events, 0, sizeof(outs[j].n_events));
+            std::memset(outs[j].n_term, 0, sizeof(outs[j].n_term));
+            outs[j].kernel_ms = ms;
+            continue;
+        }
+        if ((rc = collect_end(ps[j], n_hist[j], cs[j], &outs[j], ms))) return rc;
+    }
     return MCDC_OK;
 }

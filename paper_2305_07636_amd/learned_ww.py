@@ -1,0 +1,190 @@
+"""Learned weight-window generator.
+
+A small network maps a weight-window cell's features (scaled position,
+one-hot group, scaled time) to log10 of the adjoint (importance) flux of
+the problem's detector; the window centre of a cell is the importance of the
+source region divided by the cell's importance, so source particles start
+inside their window (weight 1) and particles gain weight where they matter
+less and are split where they matter more.  The network is trained with the
+library's own FP32 matrix-core kernels on the flux tally of the adjoint
+problem computed by plain (analog) batches of the same tracker, and run in
+BF16; it fills in and smooths cells the pilot tally saw poorly.  Windows
+only change the variance: the tracker's game is unbiased, and analog runs
+stay the judge of the figure of merit.
+
+Adjoint problem (steady state, isotropic scattering): the same geometry,
+total cross sections and boundaries, the transposed group-transfer matrix,
+and the detector box as a uniform volume source whose group spectrum is the
+detector's group response.  Its scalar flux is the importance of the
+forward problem's detector response.
+
+All arithmetic on the transport side runs in the HIP library; this module
+only builds inputs and tables from its outputs (NumPy on a few thousand
+numbers).
+"""
+from __future__ import annotations
+
+import copy
+import math
+import time
+
+import numpy as np
+
+from . import _binding as B
+
+
+def adjoint_problem(prob: dict) -> dict:
+    q = prob.get("qoi")
+    if q is None or prob.get("ww_mesh") is None:
+        raise ValueError("the problem needs a detector (qoi) and a weight-window mesh")
+    te = prob["tally"]["time_edges"]
+    if te.size != 2 or not math.isinf(te[1]):
+        raise ValueError("learned windows are built for steady-state problems (one time bin [t0, inf))")
+    st = prob["sigma_t"]
+    ssT = np.ascontiguousarray(np.transpose(prob["sigma_s"], (0, 2, 1)))
+    if (ssT.sum(axis=2) > st * (1 + 1e-12)).any():
+        raise ValueError("the transposed transfer matrix exceeds sigma_t: the adjoint needs weights")
+    mask = np.asarray(q["group_mask"], dtype=np.float64)
+    adj = copy.deepcopy(prob)
+    adj["sigma_s"] = ssT
+    adj["source"] = {"kind": "isotropic", "lo": np.array(q["lo"], dtype=np.float64),
+                     "hi": np.array(q["hi"], dtype=np.float64), "group_pmf": mask / mask.sum(),
+                     "t_lo": float(te[0]), "t_hi": float(te[0])}
+    adj["tally"] = {"mesh": [np.asarray(m, dtype=np.float64) for m in prob["ww_mesh"]],
+                    "time_edges": np.array(te, dtype=np.float64),
+                    "n_batches": prob["tally"]["n_batches"]}
+    adj["qoi"] = None
+    return adj
+
+
+def cell_features(prob: dict) -> np.ndarray:
+    """Features of every window cell in table order [K][G][wz][wy][wx]:
+    (x, y, z) centre scaled to [0, 1] over the mesh, one-hot group, scaled
+    time-bin centre, zero-padded to 8.  Returns float32 [n, 8]."""
+    mesh = prob["ww_mesh"]
+    G = prob["sigma_t"].shape[1]
+    if 3 + G + 1 > 8:
+        raise ValueError("at most 4 groups fit the 8 network inputs")
+    te = prob["tally"]["time_edges"]
+    K = te.size - 1
+    cen = []
+    for a in range(3):
+        m = mesh[a]
+        if m.size:
+            c = 0.5 * (m[:-1] + m[1:])
+            cen.append((c - m[0]) / (m[-1] - m[0]))
+        else:
+            cen.append(np.array([0.5]))
+    tt = np.zeros(K)
+    if K > 1 or math.isfinite(te[-1]):
+        fin = te[np.isfinite(te)]
+        tt = 0.5 * (te[:-1] + np.minimum(te[1:], fin[-1])) / max(fin[-1], 1e-300)
+    nz, ny, nx = cen[2].size, cen[1].size, cen[0].size
+    X = np.zeros((K, G, nz, ny, nx, 8), dtype=np.float32)
+    X[..., 0] = cen[0][None, None, None, None, :]
+    X[..., 1] = cen[1][None, None, None, :, None]
+    X[..., 2] = cen[2][None, None, :, None, None]
+    for g in range(G):
+        X[:, g, ..., 3 + g] = 1.0
+    X[..., 3 + G] = tt[:, None, None, None, None]
+    return X.reshape(-1, 8)
+
+
+def source_cells(prob: dict) -> np.ndarray:
+    """Boolean [wz, wy, wx] mask of window cells overlapping the source box."""
+    mesh = prob["ww_mesh"]
+    src = prob["source"]
+    sel = []
+    for a in range(3):
+        m = mesh[a]
+        if not m.size:
+            sel.append(np.array([True]))
+            continue
+        lo, hi = src["lo"][a], src["hi"][a]
+        s = (m[1:] > lo) & (m[:-1] < hi)
+        if lo == hi:
+            s = (m[:-1] <= lo) & (m[1:] >= lo)
+        sel.append(s)
+    return sel[2][:, None, None] & sel[1][None, :, None] & sel[0][None, None, :]
+
+
+def centres_from_log_importance(prob: dict, logI: np.ndarray, defined=None) -> np.ndarray:
+    """w_c(cell) = I(source) / I(cell), with I(source) the source-spectrum
+    weighted mean importance over the source cells.  Cells not defined get
+    no window (0)."""
+    K, G = 1, prob["sigma_t"].shape[1]
+    logI = logI.reshape(K, G, *source_cells(prob).shape)
+    sc = source_cells(prob)
+    pmf = np.asarray(prob["source"]["group_pmf"], dtype=np.float64)
+    I = 10.0 ** logI
+    if defined is not None:
+        I = np.where(defined.reshape(I.shape), I, np.nan)
+    Isrc = np.nansum([pmf[g] * np.nanmean(I[0, g][sc]) for g in range(G) if pmf[g] > 0])
+    w = Isrc / I
+    w = np.where(np.isfinite(w), w, 0.0)
+    return np.ascontiguousarray(w)
+
+
+def learned_windows(prob: dict, n_pilot: int = 10_000_000, seed: int = 50, steps: int = 3000,
+                    lr: float = 1e-3, net_seed: int = 1, rel_max: float = 1.0):
+    """Pilot (adjoint, analog) -> training set -> network -> window table.
+
+    Returns (table [K][G][wz][wy][wx], info dict with the raw-tally table
+    and timings)."""
+    import torch
+
+    adj = adjoint_problem(prob)
+    t0 = time.perf_counter()
+    p = B.mcdc_problem_create(adj)
+    try:
+        out = B.mcdc_run(p, n_pilot, seed, algorithm="history", outputs=("mean", "var"))
+        phi = out["mean"].double().cpu().numpy().ravel()
+        var = out["var"].double().cpu().numpy().ravel()
+    finally:
+        p.close()
+    t_pilot = time.perf_counter() - t0
+    X = cell_features(prob)
+    rel = np.sqrt(var) / np.where(phi > 0, phi, 1.0)
+    ok = (phi > 0) & (rel < rel_max)
+    T = np.log10(phi[ok]).astype(np.float32)
+    W = (1.0 / (rel[ok] ** 2 + 0.01)).astype(np.float32)
+    W /= W.sum()
+    t1 = time.perf_counter()
+    dev = torch.device("cuda", torch.cuda.current_device())
+    Xd = torch.as_tensor(X, device=dev).contiguous()
+    net = B.MLP(net_seed)
+    try:
+        losses = net.train(torch.as_tensor(X[ok], device=dev).contiguous(),
+                           torch.as_tensor(T, device=dev), torch.as_tensor(W, device=dev), steps, lr)
+        yhat = net.infer(Xd).double().cpu().numpy()
+    finally:
+        net.close()
+    t_train = time.perf_counter() - t1
+    # keep the prediction within the range the pilot saw (no runaway
+    # extrapolation into cells the network never observed)
+    yhat = np.clip(yhat, T.min() - 1.0, T.max() + 1.0)
+    table = centres_from_log_importance(prob, yhat)
+    raw = centres_from_log_importance(prob, np.log10(np.where(ok, phi, 1.0)), defined=ok)
+    info = {"pilot_s": t_pilot, "train_s": t_train, "n_train": int(ok.sum()), "loss_first": float(losses[0]),
+            "loss_last": float(losses[-1]), "raw_table": raw, "adjoint_flux": phi}
+    return table, info
+
+
+def figure_of_merit(prob: dict, n: int, seed: int, table=None, ratio: float = 5.0, max_split: int = 16,
+                    algorithm: str = "history"):
+    """Run n histories (analog if table is None) and return the detector
+    mean, its relative error R, the tracking time T (device ms of the run)
+    and FOM = 1 / (R^2 T)."""
+    p = B.mcdc_problem_create(prob)
+    try:
+        if table is not None:
+            B.mcdc_set_weight_windows(p, table, ratio, max_split)
+        out = B.mcdc_run(p, n, seed, algorithm=algorithm, outputs=())
+    finally:
+        p.close()
+    mean, var = out["qoi_mean"], out["qoi_var"]
+    R = math.sqrt(var) / mean if mean > 0 else math.inf
+    T = out["kernel_ms"] * 1e-3
+    return {"mean": mean, "sigma": math.sqrt(var), "R": R, "T_s": T,
+            "fom": 1.0 / (R * R * T) if mean > 0 else 0.0, "splits": out["splits"],
+            "events": [int(x) for x in out["events"]]}

@@ -32,11 +32,13 @@ def close(gpu, ref, rtol=RTOL, what=""):
     assert not bad.any(), (what, int(bad.sum()), np.nonzero(bad)[0][:5], gpu[bad][:5], ref[bad][:5])
 
 
-def gpu_run(prob, N, seed, algorithm, debug=True, **kw):
+def gpu_run(prob, N, seed, algorithm, debug=True, ww=None, **kw):
     import paper_2305_07636_amd as m
 
     p = m.mcdc_problem_create(prob)
     try:
+        if ww is not None:
+            m.mcdc_set_weight_windows(p, ww["centers"], ww.get("ratio", 5.0), ww.get("max_split", 16))
         out = m.mcdc_run(p, N, seed, algorithm=algorithm, debug=debug, **kw)
         host = {k: (v.cpu().numpy() if hasattr(v, "cpu") else v) for k, v in out.items()}
     finally:
@@ -44,10 +46,14 @@ def gpu_run(prob, N, seed, algorithm, debug=True, **kw):
     return host
 
 
-def compare_full(prob, N, seed, algorithm, **kw):
+def compare_full(prob, N, seed, algorithm, ww=None, **kw):
     """Run all N histories on both sides and compare everything."""
-    g = gpu_run(prob, N, seed, algorithm, **kw)
-    r = oracle.run(prob, N, seed, records=True)
+    g = gpu_run(prob, N, seed, algorithm, ww=ww, **kw)
+    if ww is not None:
+        r = oracle.run(prob, N, seed, records=True, ww_center=ww["centers"],
+                       ww_ratio=ww.get("ratio", 5.0), ww_max_split=ww.get("max_split", 16))
+    else:
+        r = oracle.run(prob, N, seed, records=True)
     e = oracle.estimates(prob, r)
     rec = r["rec"]
     dc = g["debug_counts"].astype(np.uint32)
