@@ -142,6 +142,10 @@ typedef struct {
  *                 and collision kernels) per census step before the
  *                 particles still in flight are finished by one in-register
  *                 pass that takes each to its census or death (0 = auto).
+ *  flags          bit 0 (MCDC_FLAG_EAGER): launch the event form's census
+ *                 steps one kernel at a time instead of replaying the
+ *                 captured step graphs (graphs are also skipped when a
+ *                 profile or debug array is given).
  *  stream         hipStream_t to run on (NULL = the null stream).  mcdc_run
  *                 synchronises this stream before it returns.
  *  debug_counts   device array [N][5] (census, surface, collision events,
@@ -156,6 +160,7 @@ typedef struct {
  *                 the kernels' loads and stores request, tally atomics
  *                 excluded).  Values are added to what the array holds.
  */
+#define MCDC_FLAG_EAGER 1
 #define MCDC_PROF_CLASSES 8
 #define MCDC_PROF_SOURCE 0
 #define MCDC_PROF_ADVANCE 1    /* advance over the dense census bank */
@@ -170,7 +175,7 @@ typedef struct {
     int32_t block_size;
     int64_t bank_capacity;
     int32_t event_iters;
-    int32_t reserved;
+    int32_t flags;
     void *stream;
     uint32_t *debug_counts;
     double *debug_scores;

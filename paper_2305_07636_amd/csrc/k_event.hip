@@ -17,6 +17,8 @@
 // append survivors to the active queue.  finish takes the few particles
 // still in flight after the last iteration to their census or death in
 // registers, so no step needs an unbounded number of passes.
+#include <vector>
+
 #include "k_common.hpp"
 
 namespace mcdc {
@@ -34,12 +36,17 @@ struct Bank {
     uint32_t *hid;    // history index within the chunk
 };
 
-// Device-resident queue counts and step index.
+// Device-resident queue counts and step index.  Every queue iteration j of
+// a step has its own surface / collision / active counts, so nothing needs
+// resetting between iterations; the step's counts are cleared once when the
+// previous step ends.
+constexpr int kMaxIters = 16;
 struct Ctl {
-    unsigned int n_cur, n_next, n_s, n_c;
-    unsigned int n_a[2];
+    unsigned int n_cur, n_next;
+    unsigned int n_s[kMaxIters], n_c[kMaxIters], n_a[kMaxIters];
     int step;
     int pad;
+    uint64_t first;   // global index of the chunk's first history
 };
 
 // LDS-privatised tally of one census step.  Every particle scored in step
@@ -226,16 +233,16 @@ enum Outcome : int { kNone = 0, kToNext = 1, kToSurface = 2, kToCollision = 3 };
 
 template <int FM, bool WW, bool DENSE, int CLS = DENSE ? MCDC_PROF_ADVANCE : MCDC_PROF_ADVANCE_Q>
 __global__ void __launch_bounds__(kBlock) k_advance(DevProblem P, RunArgs R, Bank cur, Bank next, Ctl *ctl,
-                                                    const uint32_t *__restrict__ aq, int qsel,
-                                                    uint32_t *sq, uint32_t *cq, uint64_t first,
-                                                    StepTally T) {
+                                                    const uint32_t *__restrict__ aq, int it,
+                                                    uint32_t *sq, uint32_t *cq, StepTally T) {
     __shared__ Counters cnt;
+    const uint64_t first = ctl->first;
     extern __shared__ double lt[];
     cnt.init();
     for (int j = threadIdx.x; j < T.n; j += kBlock) lt[j] = 0.0;
     __syncthreads();
     bool scored = false;
-    const unsigned int n = DENSE ? ctl->n_cur : ctl->n_a[qsel];
+    const unsigned int n = DENSE ? ctl->n_cur : ctl->n_a[it - 1];
     const int step = ctl->step;
     const bool per_hist = (R.dbg_counts != nullptr) || (R.dbg_scores != nullptr) || P.qoi_on;
     for (unsigned int base = blockIdx.x * kBlock; base < n; base += gridDim.x * kBlock) {
@@ -300,8 +307,8 @@ __global__ void __launch_bounds__(kBlock) k_advance(DevProblem P, RunArgs R, Ban
             }
         }
         const uint32_t ns = wave_append(outcome == kToNext, &ctl->n_next);
-        const uint32_t ss = wave_append(outcome == kToSurface, &ctl->n_s);
-        const uint32_t cs = wave_append(outcome == kToCollision, &ctl->n_c);
+        const uint32_t ss = wave_append(outcome == kToSurface, &ctl->n_s[it]);
+        const uint32_t cs = wave_append(outcome == kToCollision, &ctl->n_c[it]);
         if (outcome == kToNext) {
             p.s = cur.s[slot];
             if (!per_hist) hid = cur.hid[slot];
@@ -336,11 +343,12 @@ __global__ void __launch_bounds__(kBlock) k_advance(DevProblem P, RunArgs R, Ban
 template <int FM, bool WW, int CLS = MCDC_PROF_SURFACE>
 __global__ void __launch_bounds__(kBlock) k_surface(DevProblem P, RunArgs R, Bank cur, Ctl *ctl,
                                                     const uint32_t *__restrict__ sq, uint32_t *aq_out,
-                                                    int qout, uint64_t first) {
+                                                    int it) {
     __shared__ Counters cnt;
+    const uint64_t first = ctl->first;
     cnt.init();
     __syncthreads();
-    const unsigned int n = ctl->n_s;
+    const unsigned int n = ctl->n_s[it];
     for (unsigned int base = blockIdx.x * kBlock; base < n; base += gridDim.x * kBlock) {
         const unsigned int idx = base + threadIdx.x;
         const bool valid = idx < n;
@@ -371,7 +379,7 @@ __global__ void __launch_bounds__(kBlock) k_surface(DevProblem P, RunArgs R, Ban
                 cur.ixyz[slot] = pack_ix(p.ix);
             }
         }
-        const uint32_t as = wave_append(alive, &ctl->n_a[qout]);
+        const uint32_t as = wave_append(alive, &ctl->n_a[it]);
         if (alive) aq_out[as] = slot;
         if (R.prof && valid) {
             unsigned int by = 4u + load_bytes<FM, WW>(P);
@@ -389,11 +397,12 @@ __global__ void __launch_bounds__(kBlock) k_surface(DevProblem P, RunArgs R, Ban
 template <int FM, bool WW, int CLS = MCDC_PROF_COLLISION>
 __global__ void __launch_bounds__(kBlock) k_collision(DevProblem P, RunArgs R, Bank cur, Ctl *ctl,
                                                       const uint32_t *__restrict__ cq, uint32_t *aq_out,
-                                                      int qout, uint64_t first) {
+                                                      int it) {
     __shared__ Counters cnt;
+    const uint64_t first = ctl->first;
     cnt.init();
     __syncthreads();
-    const unsigned int n = ctl->n_c;
+    const unsigned int n = ctl->n_c[it];
     for (unsigned int base = blockIdx.x * kBlock; base < n; base += gridDim.x * kBlock) {
         const unsigned int idx = base + threadIdx.x;
         const bool valid = idx < n;
@@ -422,7 +431,7 @@ __global__ void __launch_bounds__(kBlock) k_collision(DevProblem P, RunArgs R, B
                 if (R.dbg_counts) Hist::term(R, first + cur.hid[slot], kAbsorb);
             }
         }
-        const uint32_t as = wave_append(alive, &ctl->n_a[qout]);
+        const uint32_t as = wave_append(alive, &ctl->n_a[it]);
         if (alive) aq_out[as] = slot;
         if (R.prof && valid)
             cnt.prof(1u, 20u + 8u + (alive ? 16u + 8u * nfinite<FM, WW>(P) + 4u : 0u));
@@ -436,15 +445,15 @@ __global__ void __launch_bounds__(kBlock) k_collision(DevProblem P, RunArgs R, B
 // ---------------------------------------------------------------------------
 template <int FM, bool WW, int CLS = MCDC_PROF_FINISH>
 __global__ void __launch_bounds__(kBlock) k_finish(DevProblem P, RunArgs R, Bank cur, Bank next, Ctl *ctl,
-                                                   const uint32_t *__restrict__ aq, int qsel, uint64_t first,
-                                                   StepTally T) {
+                                                   const uint32_t *__restrict__ aq, int it, StepTally T) {
     __shared__ Counters cnt;
+    const uint64_t first = ctl->first;
     extern __shared__ double lt[];
     cnt.init();
     for (int j = threadIdx.x; j < T.n; j += kBlock) lt[j] = 0.0;
     __syncthreads();
     bool scored = false;
-    const unsigned int n = ctl->n_a[qsel];
+    const unsigned int n = ctl->n_a[it - 1];
     const bool per_hist = (R.dbg_counts != nullptr) || (R.dbg_scores != nullptr) || P.qoi_on;
     for (unsigned int base = blockIdx.x * kBlock; base < n; base += gridDim.x * kBlock) {
         const unsigned int idx = base + threadIdx.x;
@@ -557,22 +566,21 @@ __global__ void __launch_bounds__(256) k_tally_reduce(StepTally T, int rows, con
 // ---------------------------------------------------------------------------
 // control
 // ---------------------------------------------------------------------------
-__global__ void k_ctl_init(Ctl *c) {
-    c->n_cur = c->n_next = c->n_s = c->n_c = 0u;
-    c->n_a[0] = c->n_a[1] = 0u;
+__device__ __forceinline__ void clear_step(Ctl *c) {
+    c->n_next = 0u;
+    for (int j = 0; j < kMaxIters; ++j) c->n_s[j] = c->n_c[j] = c->n_a[j] = 0u;
+}
+__global__ void k_ctl_init(Ctl *c, uint64_t first) {
+    c->n_cur = 0u;
     c->step = 0;
+    c->first = first;
+    clear_step(c);
 }
-__global__ void k_step_begin(Ctl *c) {
-    c->n_next = c->n_s = c->n_c = 0u;
-    c->n_a[0] = c->n_a[1] = 0u;
-}
-__global__ void k_iter_reset(Ctl *c, int q) {
-    c->n_s = c->n_c = 0u;
-    c->n_a[q] = 0u;
-}
+// end of a step: the census bank becomes the next step's dense bank
 __global__ void k_step_end(Ctl *c) {
     c->n_cur = c->n_next;
     c->step += 1;
+    clear_step(c);
 }
 
 // ---------------------------------------------------------------------------
@@ -622,6 +630,30 @@ Layout carve(void *bank_mem, void *queue_mem, uint64_t C) {
 
 size_t queue_bytes(uint64_t C) { return 4 * (((C * 4) + 255) & ~size_t(255)) + 256; }
 
+// Captured census steps (one graph per bank parity), cached per problem and
+// re-captured when any kernel argument changes.
+struct StepGraphs {
+    std::vector<char> key;
+    hipGraphExec_t exec[2] = {nullptr, nullptr};
+    hipGraph_t graph[2] = {nullptr, nullptr};
+    hipStream_t cs = nullptr;
+    void clear() {
+        for (int q = 0; q < 2; ++q) {
+            if (exec[q]) (void)hipGraphExecDestroy(exec[q]);
+            if (graph[q]) (void)hipGraphDestroy(graph[q]);
+            exec[q] = nullptr;
+            graph[q] = nullptr;
+        }
+        key.clear();
+    }
+};
+
+template <class T>
+void key_add(std::vector<char> &k, const T &v) {
+    const char *p = reinterpret_cast<const char *>(&v);
+    k.insert(k.end(), p, p + sizeof(T));
+}
+
 template <int FM, bool WW>
 int run_event(mcdc_problem *pb, const RunArgs &R0, uint64_t first, uint64_t count, const mcdc_run_options &opt,
               hipStream_t st, Profiler &prof) {
@@ -629,7 +661,8 @@ int run_event(mcdc_problem *pb, const RunArgs &R0, uint64_t first, uint64_t coun
     uint64_t C = opt.bank_capacity ? (uint64_t)opt.bank_capacity : (uint64_t)1 << 24;
     if (C > count) C = count;
     if (C > (1ULL << 29)) C = 1ULL << 29;
-    const int iters = opt.event_iters > 0 ? opt.event_iters : 3;
+    int iters = opt.event_iters > 0 ? opt.event_iters : 3;
+    if (iters > kMaxIters - 1) iters = kMaxIters - 1;
     int rc;
     if ((rc = ensure(pb->bank, bank_bytes(C) * 2 + 64 * 256))) return rc;
     if ((rc = ensure(pb->queues, queue_bytes(C)))) return rc;
@@ -643,76 +676,123 @@ int run_event(mcdc_problem *pb, const RunArgs &R0, uint64_t first, uint64_t coun
     const int64_t slice = (int64_t)R.B * gn;
     const bool lds = slice <= 4096;
     const unsigned grid_max = lds ? 1024u : 2048u;
+    unsigned grid = (unsigned)((C + kBlock - 1) / kBlock);
+    if (grid > grid_max) grid = grid_max;
     StepTally T{};
     const int launches_per_step = iters + 1;   // advance x iters + finish
     if (lds) {
         T.n = (int)slice;
-        const size_t rows = (size_t)launches_per_step * grid_max;
+        const size_t rows = (size_t)launches_per_step * grid;
         if ((rc = ensure(pb->tally_part, rows * slice * sizeof(double) + rows + 256))) return rc;
         T.partial = (double *)pb->tally_part.p;
         T.row_used = (uint8_t *)((char *)pb->tally_part.p + rows * slice * sizeof(double));
     }
     const size_t shmem = lds ? (size_t)slice * sizeof(double) : 0;
 
+    // the step kernels never read the seed or the history count
+    RunArgs Rs = R;
+    Rs.seed = 0;
+    Rs.N = 0;
+
+    auto enqueue_step = [&](int par, hipStream_t s, Profiler &pr) {
+        const Bank &cur = L.bank[par];
+        const Bank &nxt = L.bank[par ^ 1];
+        StepTally t = T;
+        int launch = 0;
+        t.row0 = launch++ * (int)grid;
+        pr.begin(MCDC_PROF_ADVANCE);
+        hipLaunchKernelGGL((k_advance<FM, WW, true>), dim3(grid), dim3(kBlock), shmem, s, P, Rs, cur, nxt, L.ctl,
+                           (const uint32_t *)nullptr, 0, L.sq, L.cq, t);
+        pr.end();
+        pr.begin(MCDC_PROF_SURFACE);
+        hipLaunchKernelGGL((k_surface<FM, WW>), dim3(grid), dim3(kBlock), 0, s, P, Rs, cur, L.ctl,
+                           (const uint32_t *)L.sq, L.aq[0], 0);
+        pr.end();
+        pr.begin(MCDC_PROF_COLLISION);
+        hipLaunchKernelGGL((k_collision<FM, WW>), dim3(grid), dim3(kBlock), 0, s, P, Rs, cur, L.ctl,
+                           (const uint32_t *)L.cq, L.aq[0], 0);
+        pr.end();
+        for (int j = 1; j < iters; ++j) {
+            t.row0 = launch++ * (int)grid;
+            pr.begin(MCDC_PROF_ADVANCE_Q);
+            hipLaunchKernelGGL((k_advance<FM, WW, false>), dim3(grid), dim3(kBlock), shmem, s, P, Rs, cur, nxt,
+                               L.ctl, (const uint32_t *)L.aq[(j - 1) & 1], j, L.sq, L.cq, t);
+            pr.end();
+            pr.begin(MCDC_PROF_SURFACE);
+            hipLaunchKernelGGL((k_surface<FM, WW>), dim3(grid), dim3(kBlock), 0, s, P, Rs, cur, L.ctl,
+                               (const uint32_t *)L.sq, L.aq[j & 1], j);
+            pr.end();
+            pr.begin(MCDC_PROF_COLLISION);
+            hipLaunchKernelGGL((k_collision<FM, WW>), dim3(grid), dim3(kBlock), 0, s, P, Rs, cur, L.ctl,
+                               (const uint32_t *)L.cq, L.aq[j & 1], j);
+            pr.end();
+        }
+        t.row0 = launch++ * (int)grid;
+        pr.begin(MCDC_PROF_FINISH);
+        hipLaunchKernelGGL((k_finish<FM, WW>), dim3(grid), dim3(kBlock), shmem, s, P, Rs, cur, nxt, L.ctl,
+                           (const uint32_t *)L.aq[(iters - 1) & 1], iters, t);
+        pr.end();
+        if (lds) {
+            pr.begin(MCDC_PROF_OTHER);
+            hipLaunchKernelGGL(k_tally_reduce, dim3((unsigned)((slice + 63) / 64)), dim3(256), 0, s, t,
+                               launch * (int)grid, (const Ctl *)L.ctl, R.S, P.ntally, (int)gn);
+            pr.end();
+        }
+        hipLaunchKernelGGL(k_step_end, dim3(1), dim3(1), 0, s, L.ctl);
+    };
+
+    // replay captured steps unless a per-launch profile or per-history
+    // debug output is requested (those launch eagerly)
+    const bool use_graph = !(opt.flags & MCDC_FLAG_EAGER) && !opt.profile && !R.dbg_counts && !R.dbg_scores && P.K > 1;
+    StepGraphs *G = nullptr;
+    if (use_graph) {
+        if (!pb->graph_cache) pb->graph_cache = new StepGraphs();
+        G = (StepGraphs *)pb->graph_cache;
+        std::vector<char> key;
+        key_add(key, P);
+        key_add(key, Rs);
+        key_add(key, L);
+        key_add(key, T);
+        key_add(key, grid);
+        key_add(key, iters);
+        key_add(key, shmem);
+        if (key != G->key) {
+            G->clear();
+            hipError_t e = hipSuccess;
+            if (!G->cs) e = hipStreamCreateWithFlags(&G->cs, hipStreamNonBlocking);
+            Profiler none;
+            for (int q = 0; q < 2 && e == hipSuccess; ++q) {
+                e = hipStreamBeginCapture(G->cs, hipStreamCaptureModeThreadLocal);
+                if (e != hipSuccess) break;
+                enqueue_step(q, G->cs, none);
+                e = hipStreamEndCapture(G->cs, &G->graph[q]);
+                if (e == hipSuccess) e = hipGraphInstantiate(&G->exec[q], G->graph[q], nullptr, nullptr, 0);
+            }
+            if (e != hipSuccess) {
+                G->clear();
+                return hip_fail(e, "census step capture");
+            }
+            G->key = key;
+        }
+    }
+
     for (uint64_t c0 = 0; c0 < count; c0 += C) {
         const uint64_t n = (count - c0 < C) ? count - c0 : C;
         const uint64_t cfirst = first + c0;
-        unsigned grid = (unsigned)((n + kBlock - 1) / kBlock);
-        if (grid > grid_max) grid = grid_max;
-        hipLaunchKernelGGL(k_ctl_init, dim3(1), dim3(1), 0, st, L.ctl);
+        hipLaunchKernelGGL(k_ctl_init, dim3(1), dim3(1), 0, st, L.ctl, cfirst);
         if (P.qoi_on && (rc = launch_zero(R.qoi_hist, n * sizeof(double), st))) return hip_fail((hipError_t)rc, "zero");
+        unsigned sgrid = (unsigned)((n + kBlock - 1) / kBlock);
+        if (sgrid > grid_max) sgrid = grid_max;
         prof.begin(MCDC_PROF_SOURCE);
-        hipLaunchKernelGGL((k_source<FM, WW>), dim3(grid), dim3(kBlock), 0, st, P, R, L.bank[0], L.ctl, cfirst, n);
+        hipLaunchKernelGGL((k_source<FM, WW>), dim3(sgrid), dim3(kBlock), 0, st, P, R, L.bank[0], L.ctl, cfirst, n);
         prof.end();
         for (int step = 0; step < P.K; ++step) {
-            const Bank &cur = L.bank[step & 1];
-            const Bank &nxt = L.bank[(step + 1) & 1];
-            int launch = 0;
-            hipLaunchKernelGGL(k_step_begin, dim3(1), dim3(1), 0, st, L.ctl);
-            T.row0 = launch++ * (int)grid;
-            prof.begin(MCDC_PROF_ADVANCE);
-            hipLaunchKernelGGL((k_advance<FM, WW, true>), dim3(grid), dim3(kBlock), shmem, st, P, R, cur, nxt, L.ctl,
-                               (const uint32_t *)nullptr, 0, L.sq, L.cq, cfirst, T);
-            prof.end();
-            int q = 0;
-            prof.begin(MCDC_PROF_SURFACE);
-            hipLaunchKernelGGL((k_surface<FM, WW>), dim3(grid), dim3(kBlock), 0, st, P, R, cur, L.ctl,
-                               (const uint32_t *)L.sq, L.aq[q], q, cfirst);
-            prof.end();
-            prof.begin(MCDC_PROF_COLLISION);
-            hipLaunchKernelGGL((k_collision<FM, WW>), dim3(grid), dim3(kBlock), 0, st, P, R, cur, L.ctl,
-                               (const uint32_t *)L.cq, L.aq[q], q, cfirst);
-            prof.end();
-            for (int j = 1; j < iters; ++j) {
-                const int qn = q ^ 1;
-                hipLaunchKernelGGL(k_iter_reset, dim3(1), dim3(1), 0, st, L.ctl, qn);
-                T.row0 = launch++ * (int)grid;
-                prof.begin(MCDC_PROF_ADVANCE_Q);
-                hipLaunchKernelGGL((k_advance<FM, WW, false>), dim3(grid), dim3(kBlock), shmem, st, P, R, cur, nxt,
-                                   L.ctl, (const uint32_t *)L.aq[q], q, L.sq, L.cq, cfirst, T);
-                prof.end();
-                prof.begin(MCDC_PROF_SURFACE);
-                hipLaunchKernelGGL((k_surface<FM, WW>), dim3(grid), dim3(kBlock), 0, st, P, R, cur, L.ctl,
-                                   (const uint32_t *)L.sq, L.aq[qn], qn, cfirst);
-                prof.end();
-                prof.begin(MCDC_PROF_COLLISION);
-                hipLaunchKernelGGL((k_collision<FM, WW>), dim3(grid), dim3(kBlock), 0, st, P, R, cur, L.ctl,
-                                   (const uint32_t *)L.cq, L.aq[qn], qn, cfirst);
-                prof.end();
-                q = qn;
+            if (G) {
+                hipError_t e = hipGraphLaunch(G->exec[step & 1], st);
+                if (e != hipSuccess) return hip_fail(e, "census step replay");
+            } else {
+                enqueue_step(step & 1, st, prof);
             }
-            T.row0 = launch++ * (int)grid;
-            prof.begin(MCDC_PROF_FINISH);
-            hipLaunchKernelGGL((k_finish<FM, WW>), dim3(grid), dim3(kBlock), shmem, st, P, R, cur, nxt, L.ctl,
-                               (const uint32_t *)L.aq[q], q, cfirst, T);
-            prof.end();
-            if (lds) {
-                prof.begin(MCDC_PROF_OTHER);
-                hipLaunchKernelGGL(k_tally_reduce, dim3((unsigned)((slice + 63) / 64)), dim3(256), 0, st, T,
-                                   launch * (int)grid, (const Ctl *)L.ctl, R.S, P.ntally, (int)gn);
-                prof.end();
-            }
-            hipLaunchKernelGGL(k_step_end, dim3(1), dim3(1), 0, st, L.ctl);
         }
         if (P.qoi_on && (rc = launch_qoi_reduce(R.qoi_hist, n, R.qoi_sums, st)))
             return hip_fail((hipError_t)rc, "detector reduce");
@@ -723,6 +803,15 @@ int run_event(mcdc_problem *pb, const RunArgs &R0, uint64_t first, uint64_t coun
 }
 
 }  // namespace
+
+void destroy_graph_cache(mcdc_problem *p) {
+    if (!p->graph_cache) return;
+    StepGraphs *G = (StepGraphs *)p->graph_cache;
+    G->clear();
+    if (G->cs) (void)hipStreamDestroy(G->cs);
+    delete G;
+    p->graph_cache = nullptr;
+}
 
 int launch_event(mcdc_problem *p, const RunArgs &R, uint64_t first, uint64_t count,
                  const mcdc_run_options &opt, hipStream_t st, Profiler &prof) {

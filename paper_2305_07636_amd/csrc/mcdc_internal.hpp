@@ -128,6 +128,7 @@ struct mcdc_problem {
     };
     Buf S, L, qoi_hist, qoi_sums, counters, overflow, bank, queues, split, prof, counters_split, tally_part;
     Buf mean, var, raw, leak_mean, leak_var;
+    void *graph_cache = nullptr;   // captured census steps of the event form
 };
 
 namespace mcdc {
@@ -146,6 +147,7 @@ int launch_fold(const DevProblem &P, const double *S, const double *L, int B, ui
                 double *var, double *raw, double *leak_mean, double *leak_var,
                 hipStream_t st);
 int launch_zero(void *p, size_t bytes, hipStream_t st);
+void destroy_graph_cache(mcdc_problem *p);
 int launch_batched(const BatchItem *items, const uint64_t *offs, int n_items, uint64_t total,
                    unsigned long long *next, int finite_mask, int block, int per_thread, hipStream_t st);
 int launch_qoi_reduce(const double *qoi_hist, uint64_t n, double *qoi_sums, hipStream_t st);

@@ -423,6 +423,7 @@ extern "C" int mcdc_problem_create(const mcdc_problem_desc *desc, mcdc_problem *
 
 extern "C" int mcdc_problem_destroy(mcdc_problem *p) {
     if (!p) return MCDC_OK;
+    destroy_graph_cache(p);
     if (p->blob) (void)hipFree(p->blob);
     if (p->ww_dev) (void)hipFree(p->ww_dev);
     mcdc_problem::Buf *bufs[] = {&p->S, &p->L, &p->qoi_hist, &p->qoi_sums, &p->counters,

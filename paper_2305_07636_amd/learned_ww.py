@@ -2,10 +2,10 @@
 
 A small network maps a weight-window cell's features (scaled position,
 one-hot group, scaled time) to log10 of the adjoint (importance) flux of
-the problem's detector; the window centre of a cell is the importance of the
-source region divided by the cell's importance, so source particles start
-inside their window (weight 1) and particles gain weight where they matter
-less and are split where they matter more.  The network is trained with the
+the problem's detector; the window centre of a cell is a reference
+importance divided by the cell's importance, so particles are split as they
+move toward the detector and rouletted where they matter less (see
+centres_from_log_importance for the reference).  The network is trained with the
 library's own FP32 matrix-core kernels on the flux tally of the adjoint
 problem computed by plain (analog) batches of the same tracker, and run in
 BF16; it fills in and smooths cells the pilot tally saw poorly.  Windows
@@ -108,25 +108,23 @@ def source_cells(prob: dict) -> np.ndarray:
     return sel[2][:, None, None] & sel[1][None, :, None] & sel[0][None, None, :]
 
 
-def centres_from_log_importance(prob: dict, logI: np.ndarray, defined=None) -> np.ndarray:
-    """w_c(cell) = I(source) / I(cell), with I(source) the source-spectrum
-    weighted mean importance over the source cells.  Cells not defined get
-    no window (0)."""
-    K, G = 1, prob["sigma_t"].shape[1]
-    logI = logI.reshape(K, G, *source_cells(prob).shape)
-    sc = source_cells(prob)
-    pmf = np.asarray(prob["source"]["group_pmf"], dtype=np.float64)
-    I = 10.0 ** logI
-    if defined is not None:
-        I = np.where(defined.reshape(I.shape), I, np.nan)
-    Isrc = np.nansum([pmf[g] * np.nanmean(I[0, g][sc]) for g in range(G) if pmf[g] > 0])
-    w = Isrc / I
-    w = np.where(np.isfinite(w), w, 0.0)
+def centres_from_log_importance(logI: np.ndarray, log_ref: float, shape) -> np.ndarray:
+    """w_c(cell) = I_ref / I(cell) on cells at least as important as the
+    reference level, 0 (no window: analog tracking) elsewhere.
+
+    The reference is the importance at the frontier of the region the
+    adjoint pilot resolved: particles coming from the source travel analog
+    (weight 1) until they reach that frontier, where the window centre is 1,
+    and are split as they move on toward the detector.  Source-normalised
+    windows would need the importance at the source, which an analog
+    adjoint pilot of a deep-penetration problem does not reach."""
+    logI = np.asarray(logI, dtype=np.float64).reshape(shape)
+    w = np.where(logI >= log_ref, 10.0 ** (log_ref - logI), 0.0)
     return np.ascontiguousarray(w)
 
 
 def learned_windows(prob: dict, n_pilot: int = 10_000_000, seed: int = 50, steps: int = 3000,
-                    lr: float = 1e-3, net_seed: int = 1, rel_max: float = 1.0):
+                    lr: float = 1e-3, net_seed: int = 1, rel_max: float = 0.3, frontier_pct: float = 5.0):
     """Pilot (adjoint, analog) -> training set -> network -> window table.
 
     Returns (table [K][G][wz][wy][wx], info dict with the raw-tally table
@@ -163,8 +161,10 @@ def learned_windows(prob: dict, n_pilot: int = 10_000_000, seed: int = 50, steps
     # keep the prediction within the range the pilot saw (no runaway
     # extrapolation into cells the network never observed)
     yhat = np.clip(yhat, T.min() - 1.0, T.max() + 1.0)
-    table = centres_from_log_importance(prob, yhat)
-    raw = centres_from_log_importance(prob, np.log10(np.where(ok, phi, 1.0)), defined=ok)
+    log_ref = float(np.percentile(T, frontier_pct))
+    shape = (1, prob["sigma_t"].shape[1]) + source_cells(prob).shape
+    table = centres_from_log_importance(yhat, log_ref, shape)
+    raw = centres_from_log_importance(np.where(ok, np.log10(np.where(ok, phi, 1.0)), -np.inf), log_ref, shape)
     info = {"pilot_s": t_pilot, "train_s": t_train, "n_train": int(ok.sum()), "loss_first": float(losses[0]),
             "loss_last": float(losses[-1]), "raw_table": raw, "adjoint_flux": phi}
     return table, info

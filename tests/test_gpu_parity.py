@@ -102,3 +102,36 @@ def test_algorithms_agree_bitwise_on_counts():
     assert np.array_equal(a["events"], b["events"]) and np.array_equal(a["terms"], b["terms"])
     close(b["debug_scores"], a["debug_scores"])
     close(b["mean"], a["mean"])
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("case", ["pulse_c09", "lattice17", "census_heavy"])
+def test_event_graph_replays_match_eager_and_oracle(case):
+    """The event form replays captured census-step graphs when no debug or
+    profile output is asked for.  Several replays, with eager runs and
+    synchronisations in between, must each equal the eager result."""
+    import torch
+
+    import oracle
+    import paper_2305_07636_amd as m
+    from gpu_common import close
+
+    make, N, seed = SMALL[case]
+    prob = make()
+    ref = oracle.run(prob, N, seed)
+    e = oracle.estimates(prob, ref)
+    p = m.mcdc_problem_create(prob)
+    try:
+        eager = m.mcdc_run(p, N, seed, algorithm="event", eager=True)
+        for rep in range(3):
+            print(f"[graph] {case} replay {rep}", flush=True)
+            g = m.mcdc_run(p, N, seed, algorithm="event")
+            torch.cuda.synchronize()
+            assert np.array_equal(g["events"], eager["events"]) and np.array_equal(g["terms"], eager["terms"])
+            assert np.array_equal(g["events"], ref["tot"][0:3]) and np.array_equal(g["terms"], ref["tot"][3:8])
+            close(g["mean"].cpu().numpy(), eager["mean"].cpu().numpy())
+            close(g["mean"].cpu().numpy(), e["mean"])
+            close(g["var"].cpu().numpy(), e["var"], rtol=1e-9)
+            m.mcdc_run(p, 1000, seed + 1 + rep, algorithm="history")   # unrelated eager work in between
+    finally:
+        p.close()
