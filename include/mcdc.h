@@ -141,7 +141,7 @@ typedef struct {
  *  event_iters    event form: queue iterations (advance, then the surface
  *                 and collision kernels) per census step before the
  *                 particles still in flight are finished by one in-register
- *                 pass that takes each to its census or death (0 = auto).
+ *                 pass that takes each to its census or death (0 = auto: 1).
  *  flags          bit 0 (MCDC_FLAG_EAGER): launch the event form's census
  *                 steps one kernel at a time instead of replaying the
  *                 captured step graphs (graphs are also skipped when a
@@ -159,6 +159,9 @@ typedef struct {
  *                 algorithmic HBM bytes (the particle-state and queue bytes
  *                 the kernels' loads and stores request, tally atomics
  *                 excluded).  Values are added to what the array holds.
+ *  profile_mask   bit c set: bracket launches of class c with events
+ *                 (0 = all classes); particle and byte counts are always
+ *                 gathered for every class when profile is given.
  */
 #define MCDC_FLAG_EAGER 1
 #define MCDC_PROF_CLASSES 8
@@ -180,6 +183,8 @@ typedef struct {
     uint32_t *debug_counts;
     double *debug_scores;
     double *profile;
+    uint32_t profile_mask;
+    uint32_t reserved;
 } mcdc_run_options;
 
 /*

@@ -56,7 +56,7 @@ class mcdc_run_options(C.Structure):
         ("algorithm", C.c_int32), ("block_size", C.c_int32), ("bank_capacity", C.c_int64),
         ("event_iters", C.c_int32), ("flags", C.c_int32), ("stream", C.c_void_p),
         ("debug_counts", C.c_void_p), ("debug_scores", C.c_void_p),
-        ("profile", C.c_void_p),
+        ("profile", C.c_void_p), ("profile_mask", C.c_uint32), ("reserved2", C.c_uint32),
     ]
 
 
@@ -228,7 +228,7 @@ def mcdc_set_weight_windows(p: Problem, centers, ratio: float = 5.0, max_split: 
 def mcdc_run(p: Problem, n_histories: int, seed: int, algorithm: str = "event",
              block_size: int = 0, bank_capacity: int = 0, event_iters: int = 0,
              debug: bool = False, outputs=("mean", "var", "raw", "leak_mean", "leak_var"),
-             profile=None, eager: bool = False):
+             profile=None, eager: bool = False, profile_classes=None):
     """Run n_histories through the GPU tracker.  Returns a dict of torch
     CUDA tensors (mean, var, raw [K, G, nz, ny, nx]; leak_mean, leak_var
     [K, G, 6]; debug_counts [N, 5] and debug_scores [N, 2] if debug) plus
@@ -268,6 +268,8 @@ def mcdc_run(p: Problem, n_histories: int, seed: int, algorithm: str = "event",
         assert profile.dtype == np.float64 and profile.shape == (len(PROF_CLASSES), 4)
         assert profile.flags["C_CONTIGUOUS"]
         opt.profile = profile.ctypes.data
+        if profile_classes:
+            opt.profile_mask = sum(1 << PROF_CLASSES.index(c) for c in profile_classes)
     _check(lib().mcdc_run(p.handle, int(n_histories), int(seed), C.byref(opt), C.byref(res)))
     out["events"] = np.array(res.n_events[:], dtype=np.uint64)
     out["terms"] = np.array(res.n_term[:], dtype=np.uint64)

@@ -1,22 +1,35 @@
 // Event-based tracking (the second algorithm mode the paper names, Section 2;
 // it gives no design).  Particles live in structure-of-arrays banks in HBM
 // and advance one event per kernel pass; after each pass they are sorted
-// into per-event queues (census, surface, collision) built with wavefront
-// ballot + mbcnt prefix sums and one atomic per wave and queue.
+// into per-event queues (census, surface, collision) built from wavefront
+// ballots and mbcnt prefix counts.
+//
+// Segment-private pipelines.  The bank, and every queue, is cut into G
+// segments of L slots, one per workgroup: workgroup b of every kernel works
+// only on segment b, and a particle never leaves the segment it was born in.
+// Queue appends therefore need no device-wide atomics (one LDS atomic per
+// wave, no contention across the 8 XCDs), the dense census bank stays
+// contiguous per segment, and each segment holds a contiguous range of
+// histories, so its particles belong to at most two tally batches.
 //
 // Time is advanced census step by census step (the census grid is the tally
-// time grid, Section 3).  One step is a fixed kernel sequence, so it can be
-// replayed without host round trips:
+// time grid, Section 3).  One step is a fixed kernel sequence, captured once
+// as a graph and replayed:
 //   advance(dense bank) -> surface(queue) -> collision(queue)
 //   [advance(active queue) -> surface -> collision] x (iters - 1)
-//   finish(active queue)
+//   finish(active queue) -> step end
 // advance moves each particle to its next event, scores the track-length
 // tally and files it: census crossers are copied whole into the next step's
-// dense bank, surface and collision particles stay in place and their slots
-// go to the surface / collision queues; the surface and collision kernels
-// append survivors to the active queue.  finish takes the few particles
-// still in flight after the last iteration to their census or death in
-// registers, so no step needs an unbounded number of passes.
+// bank segment, surface and collision particles stay in place and their
+// slots go to the surface / collision queues; the surface and collision
+// kernels append survivors to the active queue.  finish takes the few
+// particles still in flight after the last iteration to their census or
+// death in registers, so no step needs an unbounded number of passes.
+//
+// Tally: every particle scored in step k lies in time bin k, so a
+// workgroup touches only the slice [2 batches][G][nts] of the step; when that
+// fits in LDS it is accumulated there and flushed with one global atomic
+// per nonzero bin at the end of the kernel.
 #include <vector>
 
 #include "k_common.hpp"
@@ -27,6 +40,8 @@ namespace {
 using namespace dev;
 
 constexpr int kBlock = 256;
+constexpr int kMaxIters = 16;
+constexpr int kLdsTallyMax = 4096;   // doubles (32 KB)
 
 struct Bank {
     double *x[3], *u[3], *t, *tau, *w;
@@ -36,43 +51,18 @@ struct Bank {
     uint32_t *hid;    // history index within the chunk
 };
 
-// Device-resident queue counts and step index.  Every queue iteration j of
-// a step has its own surface / collision / active counts, so nothing needs
-// resetting between iterations; the step's counts are cleared once when the
-// previous step ends.
-constexpr int kMaxIters = 16;
+// Per-segment fill counts of the banks and queues, plus the step index.
+// Only workgroup b reads or writes the entries of segment b.
 struct Ctl {
-    unsigned int n_cur, n_next;
-    unsigned int n_s[kMaxIters], n_c[kMaxIters], n_a[kMaxIters];
-    int step;
-    int pad;
-    uint64_t first;   // global index of the chunk's first history
+    unsigned int *n_bank;   // [2][G] particles in each segment of bank 0 / 1
+    unsigned int *n_s;      // [kMaxIters][G] surface queue fill per iteration
+    unsigned int *n_c;      // [kMaxIters][G] collision queue fill
+    unsigned int *n_a;      // [kMaxIters][G] active queue fill
+    int *seg_b0;            // [G] batch of the segment's first history
+    int *step;              // current census step
+    uint64_t *first;        // global index of the chunk's first history
+    unsigned int G, L;      // segments (= workgroups), slots per segment
 };
-
-// LDS-privatised tally of one census step.  Every particle scored in step
-// k lies in time bin k, so a block only touches the slice [B][G][nts];
-// when that fits in LDS each block accumulates it there and writes it out
-// as one row of per-block partials (no global atomics, no contention on
-// the few bins of a step), and one reduction per step adds the rows into
-// the per-batch tally in a fixed order.
-struct StepTally {
-    double *partial;     // [rows][n] per-block partial slices
-    uint8_t *row_used;   // [rows] 1 if the block scored anything
-    int n;               // B * G * nts (0 = slice too large: global atomics)
-    int row0;            // first row of this launch (launch index * grid)
-};
-
-// End of a scoring kernel: write the block's slice as its partial row.
-// Contains the block barrier the counter flush needs.
-__device__ __forceinline__ void flush_tally(const StepTally &T, const double *lt, bool scored) {
-    const int any = __syncthreads_or(scored ? 1 : 0);
-    if (T.n == 0) return;
-    const int64_t row = (int64_t)T.row0 + blockIdx.x;
-    if (threadIdx.x == 0) T.row_used[row] = any ? 1 : 0;
-    if (!any) return;
-    double *dst = T.partial + row * T.n;
-    for (int j = threadIdx.x; j < T.n; j += blockDim.x) dst[j] = lt[j];
-}
 
 __device__ __forceinline__ uint32_t pack_gk(int g, int b, int k) {
     return (uint32_t)g | ((uint32_t)b << 5) | ((uint32_t)k << 15);
@@ -81,23 +71,25 @@ __device__ __forceinline__ uint32_t pack_ix(const int ix[3]) {
     return (uint32_t)ix[0] | ((uint32_t)ix[1] << 11) | ((uint32_t)ix[2] << 22);
 }
 
-// Wave-aggregated append: lanes with pred get consecutive slots of the
-// queue behind counter, in lane order; one atomic per wave.
-__device__ __forceinline__ uint32_t wave_append(bool pred, unsigned int *counter) {
+// Lanes with pred get consecutive offsets of the workgroup-local counter
+// cnt (LDS) in lane order: ballot, mbcnt prefix, one LDS atomic per wave.
+__device__ __forceinline__ uint32_t block_append(bool pred, unsigned int *cnt) {
     const uint64_t mask = __ballot(pred);
     const uint32_t prefix =
         __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
     uint32_t base = 0;
     if (mask) {
         const int leader = __ffsll((unsigned long long)mask) - 1;
-        if ((int)__lane_id() == leader) base = atomicAdd(counter, (unsigned int)__popcll(mask));
+        if ((int)__lane_id() == leader) base = atomicAdd(cnt, (unsigned int)__popcll(mask));
         base = __shfl(base, leader);
     }
     return base + prefix;
 }
 
-// Per-block event / termination counters and profile tallies (particles
-// processed, algorithmic bytes requested), flushed once per block.
+// Per-workgroup event / termination counters and profile tallies (particles
+// processed, algorithmic bytes requested), flushed once per workgroup.
+// Profile tallies are kept per thread in registers and summed per wave and
+// workgroup only at the end of the kernel.
 struct Counters {
     unsigned int c[kCounters];
     unsigned long long items, bytes;
@@ -108,12 +100,21 @@ struct Counters {
     __device__ void add(int j, unsigned int v = 1u) {
         if (v) atomicAdd(&c[j], v);
     }
-    __device__ void prof(unsigned int n_items, unsigned int n_bytes) {
-        if (n_items) atomicAdd(&items, (unsigned long long)n_items);
-        if (n_bytes) atomicAdd(&bytes, (unsigned long long)n_bytes);
-    }
-    __device__ void flush(const RunArgs &R, int cls) {
-        if (threadIdx.x < kCounters && c[threadIdx.x]) atomicAdd(R.counters + threadIdx.x, (unsigned long long)c[threadIdx.x]);
+    // flush: barrier, then counters and the per-thread profile tallies
+    __device__ void flush(const RunArgs &R, int cls, unsigned long long t_items, unsigned long long t_bytes) {
+        if (R.prof) {
+            for (int o = 32; o > 0; o >>= 1) {
+                t_items += __shfl_xor(t_items, o);
+                t_bytes += __shfl_xor(t_bytes, o);
+            }
+            if (__lane_id() == 0) {
+                atomicAdd(&items, t_items);
+                atomicAdd(&bytes, t_bytes);
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x < kCounters && c[threadIdx.x])
+            atomicAdd(R.counters + threadIdx.x, (unsigned long long)c[threadIdx.x]);
         if (R.prof && threadIdx.x == 0) {
             atomicAdd(R.prof + 2 * cls, items);
             atomicAdd(R.prof + 2 * cls + 1, bytes);
@@ -122,30 +123,33 @@ struct Counters {
 };
 
 // Bytes of the particle state as the kernels move it (finite axes only).
-template <int FM, bool WW>
+template <int FM>
 __device__ __forceinline__ unsigned int nfinite(const DevProblem &P) {
     return (unsigned int)__popc((unsigned int)(FM ? FM : P.finite_mask));
 }
-// load_state: x, u per finite axis, t, tau, (w), ixyz, gk
+// load_state: x, u per finite axis, t, tau, (w), cell, g/k
 template <int FM, bool WW>
 __device__ __forceinline__ unsigned int load_bytes(const DevProblem &P) {
-    return 16u * nfinite<FM, WW>(P) + 24u + (WW ? 8u : 0u);
+    return 16u * nfinite<FM>(P) + 24u + (WW ? 8u : 0u);
 }
-// store_state: the whole particle (load_state fields + s + hid)
+// store_state: the whole particle (load_state fields + RNG state + history)
 template <int FM, bool WW>
 __device__ __forceinline__ unsigned int state_bytes(const DevProblem &P) {
     return load_bytes<FM, WW>(P) + 12u;
 }
 
-struct Hist {   // per-history debug / detector hooks
-    uint64_t first;
-    __device__ static void event(const RunArgs &R, uint64_t i, int e) {
-        if (R.dbg_counts) atomicAdd(R.dbg_counts + i * 5 + e, 1u);
-    }
-    __device__ static void term(const RunArgs &R, uint64_t i, int code) {
-        if (R.dbg_counts) atomicOr(R.dbg_counts + i * 5 + 4, 1u << code);
-    }
-};
+__device__ __forceinline__ void tprof(unsigned long long &items, unsigned long long &bytes, unsigned int n_items,
+                                      unsigned int n_bytes) {
+    items += n_items;
+    bytes += n_bytes;
+}
+
+__device__ __forceinline__ void hist_event(const RunArgs &R, uint64_t i, int e) {
+    if (R.dbg_counts) atomicAdd(R.dbg_counts + i * 5 + e, 1u);
+}
+__device__ __forceinline__ void hist_term(const RunArgs &R, uint64_t i, int code) {
+    if (R.dbg_counts) atomicOr(R.dbg_counts + i * 5 + 4, 1u << code);
+}
 
 template <int FM, bool WW>
 __device__ __forceinline__ void load_state(const DevProblem &P, const Bank &B, uint32_t slot, Particle &p,
@@ -193,18 +197,66 @@ __device__ __forceinline__ uint32_t with_gk(uint32_t gk, const Particle &p) {
     return (uint32_t)p.g | (gk & (1023u << 5)) | ((uint32_t)p.k << 15);
 }
 
+// Track-length score of one flight: into the workgroup's LDS slice when the
+// particle's batch is one of the segment's two, else straight to HBM.
+struct StepScore {
+    double *lt;     // LDS [2][gn]
+    int gn;         // G * nts of the slice (0 = no LDS slice)
+    int b0;         // first batch of the segment
+    bool scored;
+    __device__ __forceinline__ void add(const DevProblem &P, const RunArgs &R, int b, int g, int k, int tb,
+                                        double v) {
+        const int rel = b - b0;
+        if (gn && rel >= 0 && rel < 2) {
+            atomicAdd(&lt[rel * gn + g * P.nts + tb], v);
+            scored = true;
+        } else {
+            atomic_add_f64(R.S + (int64_t)b * P.ntally + ((int64_t)k * P.G + g) * P.nts + tb, v);
+        }
+    }
+};
+
+__device__ __forceinline__ void init_slice(StepScore &sc, double *lt, int gn, int b0) {
+    sc.lt = lt;
+    sc.gn = gn;
+    sc.b0 = b0;
+    sc.scored = false;
+    for (int j = threadIdx.x; j < 2 * gn; j += kBlock) lt[j] = 0.0;
+}
+
+// End of a scoring kernel: add the workgroup's slice into the tally (one
+// atomic per nonzero bin).  Contains the barrier the counter flush needs.
+__device__ __forceinline__ void flush_slice(const DevProblem &P, const RunArgs &R, const StepScore &sc, int step) {
+    const int any = __syncthreads_or(sc.scored ? 1 : 0);
+    if (!sc.gn || !any) return;
+    for (int j = threadIdx.x; j < 2 * sc.gn; j += kBlock) {
+        const double v = sc.lt[j];
+        const int b = sc.b0 + j / sc.gn;
+        if (v != 0.0 && b < R.B)
+            atomic_add_f64(R.S + (int64_t)b * P.ntally + (int64_t)step * sc.gn + (j % sc.gn), v);
+    }
+}
+
 // ---------------------------------------------------------------------------
-// source
+// source: workgroup b samples histories [b L, (b + 1) L) of the chunk
 // ---------------------------------------------------------------------------
 template <int FM, bool WW, int CLS = MCDC_PROF_SOURCE>
-__global__ void __launch_bounds__(kBlock) k_source(DevProblem P, RunArgs R, Bank cur, Ctl *ctl,
-                                                   uint64_t first, uint64_t count) {
+__global__ void __launch_bounds__(kBlock) k_source(DevProblem P, RunArgs R, Bank bank, Ctl C, uint64_t count) {
     __shared__ Counters cnt;
+    __shared__ unsigned int cN;
     cnt.init();
+    unsigned long long p_items = 0, p_bytes = 0;
+    if (threadIdx.x == 0) cN = 0u;
+    const uint64_t first = *C.first;
+    const unsigned int seg = blockIdx.x;
+    const uint64_t lo = (uint64_t)seg * C.L;
+    const uint64_t hi = (lo + C.L < count) ? lo + C.L : count;
+    if (threadIdx.x == 0)
+        C.seg_b0[seg] = (lo < count) ? (int)(((first + lo + 1) * (uint64_t)R.B - 1) / R.N) : 0;
     __syncthreads();
-    for (uint64_t base = (uint64_t)blockIdx.x * kBlock; base < count; base += (uint64_t)gridDim.x * kBlock) {
+    for (uint64_t base = lo; base < hi; base += kBlock) {
         const uint64_t r = base + threadIdx.x;
-        const bool valid = r < count;
+        const bool valid = r < hi;
         Particle p;
         bool alive = false;
         int b = 0;
@@ -215,15 +267,16 @@ __global__ void __launch_bounds__(kBlock) k_source(DevProblem P, RunArgs R, Bank
             if (R.dbg_counts) R.dbg_counts[i * 5 + 3] = 1u;
             if (!alive) {
                 cnt.add(3 + kTime);
-                Hist::term(R, i, kTime);
+                hist_term(R, i, kTime);
             }
         }
-        const uint32_t slot = wave_append(valid && alive, &ctl->n_cur);
-        if (valid && alive) store_state<FM, WW>(P, cur, slot, p, pack_gk(p.g, b, p.k), (uint32_t)r);
-        if (R.prof) cnt.prof(valid ? 1u : 0u, (valid && alive) ? state_bytes<FM, WW>(P) : 0u);
+        const uint32_t off = block_append(valid && alive, &cN);
+        if (valid && alive) store_state<FM, WW>(P, bank, seg * C.L + off, p, pack_gk(p.g, b, p.k), (uint32_t)r);
+        if (R.prof) tprof(p_items, p_bytes, valid ? 1u : 0u, (valid && alive) ? state_bytes<FM, WW>(P) : 0u);
     }
     __syncthreads();
-    cnt.flush(R, CLS);
+    if (threadIdx.x == 0) C.n_bank[seg] = cN;   // bank 0
+    cnt.flush(R, CLS, p_items, p_bytes);
 }
 
 // ---------------------------------------------------------------------------
@@ -232,23 +285,32 @@ __global__ void __launch_bounds__(kBlock) k_source(DevProblem P, RunArgs R, Bank
 enum Outcome : int { kNone = 0, kToNext = 1, kToSurface = 2, kToCollision = 3 };
 
 template <int FM, bool WW, bool DENSE, int CLS = DENSE ? MCDC_PROF_ADVANCE : MCDC_PROF_ADVANCE_Q>
-__global__ void __launch_bounds__(kBlock) k_advance(DevProblem P, RunArgs R, Bank cur, Bank next, Ctl *ctl,
-                                                    const uint32_t *__restrict__ aq, int it,
-                                                    uint32_t *sq, uint32_t *cq, StepTally T) {
+__global__ void __launch_bounds__(kBlock) k_advance(DevProblem P, RunArgs R, Bank cur, Bank next, Ctl C, int par,
+                                                    const uint32_t *__restrict__ aq, int it, uint32_t *sq,
+                                                    uint32_t *cq, int gn) {
     __shared__ Counters cnt;
-    const uint64_t first = ctl->first;
+    __shared__ unsigned int cN, cS, cC;
     extern __shared__ double lt[];
+    const unsigned int seg = blockIdx.x;
+    const uint32_t seg0 = seg * C.L;
+    const unsigned int n = DENSE ? C.n_bank[par * C.G + seg] : C.n_a[(it - 1) * C.G + seg];
+    const int step = *C.step;
+    const uint64_t first = *C.first;
     cnt.init();
-    for (int j = threadIdx.x; j < T.n; j += kBlock) lt[j] = 0.0;
+    unsigned long long p_items = 0, p_bytes = 0;
+    if (threadIdx.x == 0) {
+        cN = DENSE ? 0u : C.n_bank[(par ^ 1) * C.G + seg];
+        cS = 0u;
+        cC = 0u;
+    }
+    StepScore sc;
+    init_slice(sc, lt, gn, C.seg_b0[seg]);
     __syncthreads();
-    bool scored = false;
-    const unsigned int n = DENSE ? ctl->n_cur : ctl->n_a[it - 1];
-    const int step = ctl->step;
     const bool per_hist = (R.dbg_counts != nullptr) || (R.dbg_scores != nullptr) || P.qoi_on;
-    for (unsigned int base = blockIdx.x * kBlock; base < n; base += gridDim.x * kBlock) {
-        const unsigned int idx = base + threadIdx.x;
+    for (unsigned int j0 = 0; j0 < n; j0 += kBlock) {
+        const unsigned int idx = j0 + threadIdx.x;
         const bool valid = idx < n;
-        const uint32_t slot = valid ? (DENSE ? idx : aq[idx]) : 0u;
+        const uint32_t slot = valid ? (DENSE ? seg0 + idx : aq[seg0 + idx]) : 0u;
         int outcome = kNone;
         int mask = 0;
         Particle p;
@@ -260,59 +322,54 @@ __global__ void __launch_bounds__(kBlock) k_advance(DevProblem P, RunArgs R, Ban
                 outcome = kToNext;   // born in a later time bin: wait
             } else {
                 const int cell = cell_index(P, p.ix);
-                Flight f = next_event<FM>(P, p, cell);
+                const Flight f = next_event<FM>(P, p, cell);
                 const uint64_t i = first + hid;
                 if (f.d == kInf) {
                     cnt.add(3 + kLost);
-                    if (per_hist) Hist::term(R, i, kLost);
+                    if (per_hist) hist_term(R, i, kLost);
                 } else {
-                    const double sc = p.w * f.d;
+                    const double v = p.w * f.d;
                     const int tb = P.cell_tal[cell];
                     const int b = (gk >> 5) & 1023u;
                     if (tb >= 0) {
-                        if (T.n) {
-                            atomicAdd(&lt[(b * P.G + p.g) * P.nts + tb], sc);
-                            scored = true;
-                        } else {
-                            atomic_add_f64(R.S + (int64_t)b * P.ntally + ((int64_t)p.k * P.G + p.g) * P.nts + tb, sc);
-                        }
-                        if (R.dbg_scores) atomic_add_f64(R.dbg_scores + i * 2, sc);
+                        sc.add(P, R, b, p.g, p.k, tb, v);
+                        if (R.dbg_scores) atomic_add_f64(R.dbg_scores + i * 2, v);
                     }
                     if (P.qoi_on && P.cell_qoi[cell] && P.qoi_groups[p.g]) {
-                        atomic_add_f64(R.qoi_hist + hid, sc);
-                        if (R.dbg_scores) atomic_add_f64(R.dbg_scores + i * 2 + 1, sc);
+                        atomic_add_f64(R.qoi_hist + hid, v);
+                        if (R.dbg_scores) atomic_add_f64(R.dbg_scores + i * 2 + 1, v);
                     }
                     move<FM>(P, p, f);
                     if (f.ev == kCensus) {
                         cnt.add(0);
-                        if (per_hist) Hist::event(R, i, 0);
+                        if (per_hist) hist_event(R, i, 0);
                         p.k += 1;
                         if (p.k == P.K) {
                             cnt.add(3 + kTime);
-                            if (per_hist) Hist::term(R, i, kTime);
+                            if (per_hist) hist_term(R, i, kTime);
                         } else {
                             outcome = kToNext;
                         }
                     } else if (f.ev == kSurface) {
                         cnt.add(1);
-                        if (per_hist) Hist::event(R, i, 1);
+                        if (per_hist) hist_event(R, i, 1);
                         mask = crossing_mask<FM>(P, f);
                         outcome = kToSurface;
                     } else {
                         cnt.add(2);
-                        if (per_hist) Hist::event(R, i, 2);
+                        if (per_hist) hist_event(R, i, 2);
                         outcome = kToCollision;
                     }
                 }
             }
         }
-        const uint32_t ns = wave_append(outcome == kToNext, &ctl->n_next);
-        const uint32_t ss = wave_append(outcome == kToSurface, &ctl->n_s[it]);
-        const uint32_t cs = wave_append(outcome == kToCollision, &ctl->n_c[it]);
+        const uint32_t ns = block_append(outcome == kToNext, &cN);
+        const uint32_t ss = block_append(outcome == kToSurface, &cS);
+        const uint32_t cs = block_append(outcome == kToCollision, &cC);
         if (outcome == kToNext) {
             p.s = cur.s[slot];
             if (!per_hist) hid = cur.hid[slot];
-            store_state<FM, WW>(P, next, ns, p, with_gk(gk, p), hid);
+            store_state<FM, WW>(P, next, seg0 + ns, p, with_gk(gk, p), hid);
         } else if (outcome == kToSurface || outcome == kToCollision) {
 #pragma unroll
             for (int a = 0; a < 3; ++a)
@@ -320,45 +377,55 @@ __global__ void __launch_bounds__(kBlock) k_advance(DevProblem P, RunArgs R, Ban
             cur.t[slot] = p.t;
             cur.tau[slot] = p.tau;
             if (outcome == kToSurface)
-                sq[ss] = slot | ((uint32_t)mask << 29);
+                sq[seg0 + ss] = slot | ((uint32_t)mask << 29);
             else
-                cq[cs] = slot;
+                cq[seg0 + cs] = slot;
         }
         if (R.prof && valid) {
             unsigned int by = load_bytes<FM, WW>(P) + (DENSE ? 0u : 4u) + (per_hist ? 4u : 0u);
             if (outcome == kToNext)
                 by += 8u + (per_hist ? 0u : 4u) + state_bytes<FM, WW>(P);
             else if (outcome != kNone)
-                by += 8u * nfinite<FM, WW>(P) + 16u + 4u;
-            cnt.prof(1u, by);
+                by += 8u * nfinite<FM>(P) + 16u + 4u;
+            tprof(p_items, p_bytes, 1u, by);
         }
     }
-    flush_tally(T, lt, scored);
-    cnt.flush(R, CLS);
+    flush_slice(P, R, sc, step);
+    if (threadIdx.x == 0) {
+        C.n_bank[(par ^ 1) * C.G + seg] = cN;
+        C.n_s[it * C.G + seg] = cS;
+        C.n_c[it * C.G + seg] = cC;
+    }
+    cnt.flush(R, CLS, p_items, p_bytes);
 }
 
 // ---------------------------------------------------------------------------
 // surface crossing and boundary conditions
 // ---------------------------------------------------------------------------
 template <int FM, bool WW, int CLS = MCDC_PROF_SURFACE>
-__global__ void __launch_bounds__(kBlock) k_surface(DevProblem P, RunArgs R, Bank cur, Ctl *ctl,
-                                                    const uint32_t *__restrict__ sq, uint32_t *aq_out,
-                                                    int it) {
+__global__ void __launch_bounds__(kBlock) k_surface(DevProblem P, RunArgs R, Bank cur, Ctl C,
+                                                    const uint32_t *__restrict__ sq, uint32_t *aq_out, int it) {
     __shared__ Counters cnt;
-    const uint64_t first = ctl->first;
+    __shared__ unsigned int cA;
+    const unsigned int seg = blockIdx.x;
+    const uint32_t seg0 = seg * C.L;
+    const unsigned int n = C.n_s[it * C.G + seg];
+    const uint64_t first = *C.first;
     cnt.init();
+    unsigned long long p_items = 0, p_bytes = 0;
+    if (threadIdx.x == 0) cA = 0u;
     __syncthreads();
-    const unsigned int n = ctl->n_s[it];
-    for (unsigned int base = blockIdx.x * kBlock; base < n; base += gridDim.x * kBlock) {
-        const unsigned int idx = base + threadIdx.x;
+    for (unsigned int j0 = 0; j0 < n; j0 += kBlock) {
+        const unsigned int idx = j0 + threadIdx.x;
         const bool valid = idx < n;
         bool alive = false;
         uint32_t slot = 0;
+        int mask = 0;
         Particle p;
         if (valid) {
-            const uint32_t e = sq[idx];
+            const uint32_t e = sq[seg0 + idx];
             slot = e & 0x1FFFFFFFu;
-            const int mask = (int)(e >> 29);
+            mask = (int)(e >> 29);
             uint32_t gk;
             load_state<FM, WW>(P, cur, slot, p, gk);
             const int face = cross<FM>(P, p, mask);
@@ -366,7 +433,7 @@ __global__ void __launch_bounds__(kBlock) k_surface(DevProblem P, RunArgs R, Ban
                 const int b = (gk >> 5) & 1023u;
                 atomic_add_f64(R.L + (((int64_t)b * P.K + p.k) * P.G + p.g) * 6 + face, p.w);
                 cnt.add(3 + kLeak);
-                if (R.dbg_counts) Hist::term(R, first + cur.hid[slot], kLeak);
+                if (R.dbg_counts) hist_term(R, first + cur.hid[slot], kLeak);
             } else {
                 alive = true;
 #pragma unroll
@@ -379,38 +446,40 @@ __global__ void __launch_bounds__(kBlock) k_surface(DevProblem P, RunArgs R, Ban
                 cur.ixyz[slot] = pack_ix(p.ix);
             }
         }
-        const uint32_t as = wave_append(alive, &ctl->n_a[it]);
-        if (alive) aq_out[as] = slot;
-        if (R.prof && valid) {
-            unsigned int by = 4u + load_bytes<FM, WW>(P);
-            if (alive) by += 16u * (unsigned int)__popc(sq[idx] >> 29) + 4u + 4u;
-            cnt.prof(1u, by);
-        }
+        const uint32_t as = block_append(alive, &cA);
+        if (alive) aq_out[seg0 + as] = slot;
+        if (R.prof && valid)
+            tprof(p_items, p_bytes, 1u, 4u + load_bytes<FM, WW>(P) + (alive ? 16u * (unsigned int)__popc(mask) + 8u : 0u));
     }
     __syncthreads();
-    cnt.flush(R, CLS);
+    if (threadIdx.x == 0) C.n_a[it * C.G + seg] = cA;
+    cnt.flush(R, CLS, p_items, p_bytes);
 }
 
 // ---------------------------------------------------------------------------
 // analog collision
 // ---------------------------------------------------------------------------
 template <int FM, bool WW, int CLS = MCDC_PROF_COLLISION>
-__global__ void __launch_bounds__(kBlock) k_collision(DevProblem P, RunArgs R, Bank cur, Ctl *ctl,
-                                                      const uint32_t *__restrict__ cq, uint32_t *aq_out,
-                                                      int it) {
+__global__ void __launch_bounds__(kBlock) k_collision(DevProblem P, RunArgs R, Bank cur, Ctl C,
+                                                      const uint32_t *__restrict__ cq, uint32_t *aq_out, int it) {
     __shared__ Counters cnt;
-    const uint64_t first = ctl->first;
+    __shared__ unsigned int cA;
+    const unsigned int seg = blockIdx.x;
+    const uint32_t seg0 = seg * C.L;
+    const unsigned int n = C.n_c[it * C.G + seg];
+    const uint64_t first = *C.first;
     cnt.init();
+    unsigned long long p_items = 0, p_bytes = 0;
+    if (threadIdx.x == 0) cA = C.n_a[it * C.G + seg];   // after the surface kernel's appends
     __syncthreads();
-    const unsigned int n = ctl->n_c[it];
-    for (unsigned int base = blockIdx.x * kBlock; base < n; base += gridDim.x * kBlock) {
-        const unsigned int idx = base + threadIdx.x;
+    for (unsigned int j0 = 0; j0 < n; j0 += kBlock) {
+        const unsigned int idx = j0 + threadIdx.x;
         const bool valid = idx < n;
         bool alive = false;
         uint32_t slot = 0;
         Particle p;
         if (valid) {
-            slot = cq[idx];
+            slot = cq[seg0 + idx];
             const uint32_t gk = cur.gk[slot];
             p.g = gk & 31u;
             p.s = cur.s[slot];
@@ -419,169 +488,137 @@ __global__ void __launch_bounds__(kBlock) k_collision(DevProblem P, RunArgs R, B
             const int m = P.cell_mat[cell_index(P, ix)];
             if (collide<FM>(P, p, m)) {
                 alive = true;
-                cur.s[slot] = p.s;
                 cur.gk[slot] = (gk & ~31u) | (uint32_t)p.g;
                 cur.tau[slot] = p.tau;
 #pragma unroll
                 for (int a = 0; a < 3; ++a)
                     if (finite_axis<FM>(P, a)) cur.u[a][slot] = p.u[a];
             } else {
-                cur.s[slot] = p.s;
                 cnt.add(3 + kAbsorb);
-                if (R.dbg_counts) Hist::term(R, first + cur.hid[slot], kAbsorb);
+                if (R.dbg_counts) hist_term(R, first + cur.hid[slot], kAbsorb);
             }
+            cur.s[slot] = p.s;
         }
-        const uint32_t as = wave_append(alive, &ctl->n_a[it]);
-        if (alive) aq_out[as] = slot;
-        if (R.prof && valid)
-            cnt.prof(1u, 20u + 8u + (alive ? 16u + 8u * nfinite<FM, WW>(P) + 4u : 0u));
+        const uint32_t as = block_append(alive, &cA);
+        if (alive) aq_out[seg0 + as] = slot;
+        if (R.prof && valid) tprof(p_items, p_bytes, 1u, 20u + 8u + (alive ? 16u + 8u * nfinite<FM>(P) + 4u : 0u));
     }
     __syncthreads();
-    cnt.flush(R, CLS);
+    if (threadIdx.x == 0) C.n_a[it * C.G + seg] = cA;
+    cnt.flush(R, CLS, p_items, p_bytes);
 }
 
 // ---------------------------------------------------------------------------
 // finish: the particles still in flight, in registers, to census or death
 // ---------------------------------------------------------------------------
 template <int FM, bool WW, int CLS = MCDC_PROF_FINISH>
-__global__ void __launch_bounds__(kBlock) k_finish(DevProblem P, RunArgs R, Bank cur, Bank next, Ctl *ctl,
-                                                   const uint32_t *__restrict__ aq, int it, StepTally T) {
+__global__ void __launch_bounds__(kBlock) k_finish(DevProblem P, RunArgs R, Bank cur, Bank next, Ctl C, int par,
+                                                   const uint32_t *__restrict__ aq, int it, int gn) {
     __shared__ Counters cnt;
-    const uint64_t first = ctl->first;
+    __shared__ unsigned int cN;
     extern __shared__ double lt[];
+    const unsigned int seg = blockIdx.x;
+    const uint32_t seg0 = seg * C.L;
+    const unsigned int n = C.n_a[(it - 1) * C.G + seg];
+    const int step = *C.step;
+    const uint64_t first = *C.first;
     cnt.init();
-    for (int j = threadIdx.x; j < T.n; j += kBlock) lt[j] = 0.0;
+    unsigned long long p_items = 0, p_bytes = 0;
+    if (threadIdx.x == 0) cN = C.n_bank[(par ^ 1) * C.G + seg];
+    StepScore sc;
+    init_slice(sc, lt, gn, C.seg_b0[seg]);
     __syncthreads();
-    bool scored = false;
-    const unsigned int n = ctl->n_a[it - 1];
     const bool per_hist = (R.dbg_counts != nullptr) || (R.dbg_scores != nullptr) || P.qoi_on;
-    for (unsigned int base = blockIdx.x * kBlock; base < n; base += gridDim.x * kBlock) {
-        const unsigned int idx = base + threadIdx.x;
+    for (unsigned int j0 = 0; j0 < n; j0 += kBlock) {
+        const unsigned int idx = j0 + threadIdx.x;
         const bool valid = idx < n;
         bool to_next = false;
         Particle p;
         uint32_t gk = 0, hid = 0;
         if (valid) {
-            const uint32_t slot = aq[idx];
+            const uint32_t slot = aq[seg0 + idx];
             load_state<FM, WW>(P, cur, slot, p, gk);
             p.s = cur.s[slot];
             hid = cur.hid[slot];
             const uint64_t i = first + hid;
             const int b = (gk >> 5) & 1023u;
-            double *S = R.S + (int64_t)b * P.ntally;
             int cell = cell_index(P, p.ix);
             int since = 0;
             for (;;) {
                 if (since >= kMaxEventsPerStep) {
                     cnt.add(3 + kLost);
-                    if (per_hist) Hist::term(R, i, kLost);
+                    if (per_hist) hist_term(R, i, kLost);
                     break;
                 }
                 ++since;
-                Flight f = next_event<FM>(P, p, cell);
+                const Flight f = next_event<FM>(P, p, cell);
                 if (f.d == kInf) {
                     cnt.add(3 + kLost);
-                    if (per_hist) Hist::term(R, i, kLost);
+                    if (per_hist) hist_term(R, i, kLost);
                     break;
                 }
-                const double sc = p.w * f.d;
+                const double v = p.w * f.d;
                 const int tb = P.cell_tal[cell];
                 if (tb >= 0) {
-                    if (T.n) {
-                        atomicAdd(&lt[(b * P.G + p.g) * P.nts + tb], sc);
-                        scored = true;
-                    } else {
-                        atomic_add_f64(S + ((int64_t)p.k * P.G + p.g) * P.nts + tb, sc);
-                    }
-                    if (R.dbg_scores) atomic_add_f64(R.dbg_scores + i * 2, sc);
+                    sc.add(P, R, b, p.g, p.k, tb, v);
+                    if (R.dbg_scores) atomic_add_f64(R.dbg_scores + i * 2, v);
                 }
                 if (P.qoi_on && P.cell_qoi[cell] && P.qoi_groups[p.g]) {
-                    atomic_add_f64(R.qoi_hist + hid, sc);
-                    if (R.dbg_scores) atomic_add_f64(R.dbg_scores + i * 2 + 1, sc);
+                    atomic_add_f64(R.qoi_hist + hid, v);
+                    if (R.dbg_scores) atomic_add_f64(R.dbg_scores + i * 2 + 1, v);
                 }
                 move<FM>(P, p, f);
                 if (f.ev == kCensus) {
                     cnt.add(0);
-                    if (per_hist) Hist::event(R, i, 0);
+                    if (per_hist) hist_event(R, i, 0);
                     p.k += 1;
                     if (p.k == P.K) {
                         cnt.add(3 + kTime);
-                        if (per_hist) Hist::term(R, i, kTime);
+                        if (per_hist) hist_term(R, i, kTime);
                     } else {
                         to_next = true;
                     }
                     break;
                 } else if (f.ev == kSurface) {
                     cnt.add(1);
-                    if (per_hist) Hist::event(R, i, 1);
+                    if (per_hist) hist_event(R, i, 1);
                     const int face = cross<FM>(P, p, crossing_mask<FM>(P, f));
                     if (face >= 0) {
                         atomic_add_f64(R.L + (((int64_t)b * P.K + p.k) * P.G + p.g) * 6 + face, p.w);
                         cnt.add(3 + kLeak);
-                        if (per_hist) Hist::term(R, i, kLeak);
+                        if (per_hist) hist_term(R, i, kLeak);
                         break;
                     }
                     cell = cell_index(P, p.ix);
                 } else {
                     cnt.add(2);
-                    if (per_hist) Hist::event(R, i, 2);
+                    if (per_hist) hist_event(R, i, 2);
                     if (!collide<FM>(P, p, f.m)) {
                         cnt.add(3 + kAbsorb);
-                        if (per_hist) Hist::term(R, i, kAbsorb);
+                        if (per_hist) hist_term(R, i, kAbsorb);
                         break;
                     }
                 }
             }
         }
-        const uint32_t ns = wave_append(to_next, &ctl->n_next);
-        if (to_next) store_state<FM, WW>(P, next, ns, p, with_gk(gk, p), hid);
+        const uint32_t ns = block_append(to_next, &cN);
+        if (to_next) store_state<FM, WW>(P, next, seg0 + ns, p, with_gk(gk, p), hid);
         if (R.prof && valid)
-            cnt.prof(1u, 4u + load_bytes<FM, WW>(P) + 12u + (to_next ? state_bytes<FM, WW>(P) : 0u));
+            tprof(p_items, p_bytes, 1u, 4u + load_bytes<FM, WW>(P) + 12u + (to_next ? state_bytes<FM, WW>(P) : 0u));
     }
-    flush_tally(T, lt, scored);
-    cnt.flush(R, CLS);
-}
-
-// Sum the partial rows of one step into the per-batch tally: 64 columns
-// per block, 4 row lanes, fixed order (deterministic).
-__global__ void __launch_bounds__(256) k_tally_reduce(StepTally T, int rows, const Ctl *ctl, double *S,
-                                                      int64_t ntally, int gn) {
-    __shared__ double red[4][64];
-    const int col = blockIdx.x * 64 + (threadIdx.x & 63);
-    const int lane = threadIdx.x >> 6;
-    double acc = 0.0;
-    if (col < T.n)
-        for (int r = lane; r < rows; r += 4)
-            if (T.row_used[r]) acc += T.partial[(int64_t)r * T.n + col];
-    red[lane][threadIdx.x & 63] = acc;
-    __syncthreads();
-    if (lane == 0 && col < T.n) {
-        const double v = (red[0][threadIdx.x] + red[1][threadIdx.x]) + (red[2][threadIdx.x] + red[3][threadIdx.x]);
-        const int b = col / gn;
-        const int rem = col - b * gn;
-        S[(int64_t)b * ntally + (int64_t)ctl->step * gn + rem] += v;
-    }
+    flush_slice(P, R, sc, step);
+    if (threadIdx.x == 0) C.n_bank[(par ^ 1) * C.G + seg] = cN;
+    cnt.flush(R, CLS, p_items, p_bytes);
 }
 
 // ---------------------------------------------------------------------------
 // control
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void clear_step(Ctl *c) {
-    c->n_next = 0u;
-    for (int j = 0; j < kMaxIters; ++j) c->n_s[j] = c->n_c[j] = c->n_a[j] = 0u;
+__global__ void k_ctl_init(Ctl C, uint64_t first) {
+    *C.step = 0;
+    *C.first = first;
 }
-__global__ void k_ctl_init(Ctl *c, uint64_t first) {
-    c->n_cur = 0u;
-    c->step = 0;
-    c->first = first;
-    clear_step(c);
-}
-// end of a step: the census bank becomes the next step's dense bank
-__global__ void k_step_end(Ctl *c) {
-    c->n_cur = c->n_next;
-    c->step += 1;
-    clear_step(c);
-}
+__global__ void k_step_end(Ctl C) { *C.step += 1; }
 
 // ---------------------------------------------------------------------------
 // host side
@@ -589,46 +626,54 @@ __global__ void k_step_end(Ctl *c) {
 struct Layout {
     Bank bank[2];
     uint32_t *sq, *cq, *aq[2];
-    Ctl *ctl;
+    Ctl ctl;
 };
 
-size_t bank_bytes(uint64_t C) { return C * (11 * sizeof(double) + sizeof(uint64_t) + 3 * sizeof(uint32_t)); }
+size_t pad256(size_t b) { return (b + 255) & ~size_t(255); }
 
-Layout carve(void *bank_mem, void *queue_mem, uint64_t C) {
-    Layout L{};
+size_t bank_bytes(uint64_t slots) { return 10 * pad256(slots * 8) + 3 * pad256(slots * 4); }
+
+size_t queue_bytes(uint64_t slots, unsigned int G) {
+    return 4 * pad256(slots * 4) + pad256(2 * G * 4) + 3 * pad256(kMaxIters * G * 4) + pad256(G * 4) + 2 * 256;
+}
+
+Layout carve(void *bank_mem, void *queue_mem, uint64_t slots, unsigned int G, unsigned int Lseg) {
+    Layout Lo{};
     char *p = (char *)bank_mem;
     auto take = [&](size_t bytes) {
         char *r = p;
-        p += (bytes + 255) & ~size_t(255);
+        p += pad256(bytes);
         return r;
     };
     for (int k = 0; k < 2; ++k) {
-        Bank &B = L.bank[k];
-        for (int a = 0; a < 3; ++a) B.x[a] = (double *)take(C * 8);
-        for (int a = 0; a < 3; ++a) B.u[a] = (double *)take(C * 8);
-        B.t = (double *)take(C * 8);
-        B.tau = (double *)take(C * 8);
-        B.w = (double *)take(C * 8);
-        B.s = (uint64_t *)take(C * 8);
-        B.ixyz = (uint32_t *)take(C * 4);
-        B.gk = (uint32_t *)take(C * 4);
-        B.hid = (uint32_t *)take(C * 4);
+        Bank &B = Lo.bank[k];
+        for (int a = 0; a < 3; ++a) B.x[a] = (double *)take(slots * 8);
+        for (int a = 0; a < 3; ++a) B.u[a] = (double *)take(slots * 8);
+        B.t = (double *)take(slots * 8);
+        B.tau = (double *)take(slots * 8);
+        B.w = (double *)take(slots * 8);
+        B.s = (uint64_t *)take(slots * 8);
+        B.ixyz = (uint32_t *)take(slots * 4);
+        B.gk = (uint32_t *)take(slots * 4);
+        B.hid = (uint32_t *)take(slots * 4);
     }
-    char *q = (char *)queue_mem;
-    auto takeq = [&](size_t bytes) {
-        char *r = q;
-        q += (bytes + 255) & ~size_t(255);
-        return r;
-    };
-    L.sq = (uint32_t *)takeq(C * 4);
-    L.cq = (uint32_t *)takeq(C * 4);
-    L.aq[0] = (uint32_t *)takeq(C * 4);
-    L.aq[1] = (uint32_t *)takeq(C * 4);
-    L.ctl = (Ctl *)takeq(sizeof(Ctl));
-    return L;
+    p = (char *)queue_mem;
+    Lo.sq = (uint32_t *)take(slots * 4);
+    Lo.cq = (uint32_t *)take(slots * 4);
+    Lo.aq[0] = (uint32_t *)take(slots * 4);
+    Lo.aq[1] = (uint32_t *)take(slots * 4);
+    Ctl &C = Lo.ctl;
+    C.n_bank = (unsigned int *)take(2 * G * 4);
+    C.n_s = (unsigned int *)take(kMaxIters * G * 4);
+    C.n_c = (unsigned int *)take(kMaxIters * G * 4);
+    C.n_a = (unsigned int *)take(kMaxIters * G * 4);
+    C.seg_b0 = (int *)take(G * 4);
+    C.step = (int *)take(64);
+    C.first = (uint64_t *)take(64);
+    C.G = G;
+    C.L = Lseg;
+    return Lo;
 }
-
-size_t queue_bytes(uint64_t C) { return 4 * (((C * 4) + 255) & ~size_t(255)) + 256; }
 
 // Captured census steps (one graph per bank parity), cached per problem and
 // re-captured when any kernel argument changes.
@@ -660,34 +705,27 @@ int run_event(mcdc_problem *pb, const RunArgs &R0, uint64_t first, uint64_t coun
     const DevProblem &P = pb->d;
     uint64_t C = opt.bank_capacity ? (uint64_t)opt.bank_capacity : (uint64_t)1 << 24;
     if (C > count) C = count;
-    if (C > (1ULL << 29)) C = 1ULL << 29;
-    int iters = opt.event_iters > 0 ? opt.event_iters : 3;
+    if (C > (1ULL << 28)) C = 1ULL << 28;
+    int iters = opt.event_iters > 0 ? opt.event_iters : 1;
     if (iters > kMaxIters - 1) iters = kMaxIters - 1;
+    // segments: one per workgroup, several workgroups per CU
+    unsigned int G = (unsigned int)((C + kBlock - 1) / kBlock);
+    const unsigned int g_max = opt.block_size ? (unsigned int)opt.block_size * 8u : 2048u;
+    if (G > g_max) G = g_max;
+    const unsigned int Lseg = (unsigned int)((C + G - 1) / G);
+    const uint64_t slots = (uint64_t)G * Lseg;
     int rc;
-    if ((rc = ensure(pb->bank, bank_bytes(C) * 2 + 64 * 256))) return rc;
-    if ((rc = ensure(pb->queues, queue_bytes(C)))) return rc;
+    if ((rc = ensure(pb->bank, bank_bytes(slots) * 2 + 64 * 256))) return rc;
+    if ((rc = ensure(pb->queues, queue_bytes(slots, G)))) return rc;
     if (P.qoi_on && (rc = ensure(pb->qoi_hist, C * sizeof(double)))) return rc;
-    Layout L = carve(pb->bank.p, pb->queues.p, C);
+    Layout L = carve(pb->bank.p, pb->queues.p, slots, G, Lseg);
     RunArgs R = R0;
     R.qoi_hist = (double *)pb->qoi_hist.p;
 
-    // per-step tally slice in LDS when it fits (32 KB)
-    const int64_t gn = (int64_t)P.G * P.nts;
-    const int64_t slice = (int64_t)R.B * gn;
-    const bool lds = slice <= 4096;
-    const unsigned grid_max = lds ? 1024u : 2048u;
-    unsigned grid = (unsigned)((C + kBlock - 1) / kBlock);
-    if (grid > grid_max) grid = grid_max;
-    StepTally T{};
-    const int launches_per_step = iters + 1;   // advance x iters + finish
-    if (lds) {
-        T.n = (int)slice;
-        const size_t rows = (size_t)launches_per_step * grid;
-        if ((rc = ensure(pb->tally_part, rows * slice * sizeof(double) + rows + 256))) return rc;
-        T.partial = (double *)pb->tally_part.p;
-        T.row_used = (uint8_t *)((char *)pb->tally_part.p + rows * slice * sizeof(double));
-    }
-    const size_t shmem = lds ? (size_t)slice * sizeof(double) : 0;
+    // per-step tally slice [2 batches][G][nts] in LDS when it fits
+    const int64_t gn64 = (int64_t)P.G * P.nts;
+    const int gn = (2 * gn64 <= kLdsTallyMax) ? (int)gn64 : 0;
+    const size_t shmem = (size_t)2 * gn * sizeof(double);
 
     // the step kernels never read the seed or the history count
     RunArgs Rs = R;
@@ -697,82 +735,70 @@ int run_event(mcdc_problem *pb, const RunArgs &R0, uint64_t first, uint64_t coun
     auto enqueue_step = [&](int par, hipStream_t s, Profiler &pr) {
         const Bank &cur = L.bank[par];
         const Bank &nxt = L.bank[par ^ 1];
-        StepTally t = T;
-        int launch = 0;
-        t.row0 = launch++ * (int)grid;
         pr.begin(MCDC_PROF_ADVANCE);
-        hipLaunchKernelGGL((k_advance<FM, WW, true>), dim3(grid), dim3(kBlock), shmem, s, P, Rs, cur, nxt, L.ctl,
-                           (const uint32_t *)nullptr, 0, L.sq, L.cq, t);
+        hipLaunchKernelGGL((k_advance<FM, WW, true>), dim3(G), dim3(kBlock), shmem, s, P, Rs, cur, nxt, L.ctl, par,
+                           (const uint32_t *)nullptr, 0, L.sq, L.cq, gn);
         pr.end();
         pr.begin(MCDC_PROF_SURFACE);
-        hipLaunchKernelGGL((k_surface<FM, WW>), dim3(grid), dim3(kBlock), 0, s, P, Rs, cur, L.ctl,
+        hipLaunchKernelGGL((k_surface<FM, WW>), dim3(G), dim3(kBlock), 0, s, P, Rs, cur, L.ctl,
                            (const uint32_t *)L.sq, L.aq[0], 0);
         pr.end();
         pr.begin(MCDC_PROF_COLLISION);
-        hipLaunchKernelGGL((k_collision<FM, WW>), dim3(grid), dim3(kBlock), 0, s, P, Rs, cur, L.ctl,
+        hipLaunchKernelGGL((k_collision<FM, WW>), dim3(G), dim3(kBlock), 0, s, P, Rs, cur, L.ctl,
                            (const uint32_t *)L.cq, L.aq[0], 0);
         pr.end();
         for (int j = 1; j < iters; ++j) {
-            t.row0 = launch++ * (int)grid;
             pr.begin(MCDC_PROF_ADVANCE_Q);
-            hipLaunchKernelGGL((k_advance<FM, WW, false>), dim3(grid), dim3(kBlock), shmem, s, P, Rs, cur, nxt,
-                               L.ctl, (const uint32_t *)L.aq[(j - 1) & 1], j, L.sq, L.cq, t);
+            hipLaunchKernelGGL((k_advance<FM, WW, false>), dim3(G), dim3(kBlock), shmem, s, P, Rs, cur, nxt, L.ctl,
+                               par, (const uint32_t *)L.aq[(j - 1) & 1], j, L.sq, L.cq, gn);
             pr.end();
             pr.begin(MCDC_PROF_SURFACE);
-            hipLaunchKernelGGL((k_surface<FM, WW>), dim3(grid), dim3(kBlock), 0, s, P, Rs, cur, L.ctl,
+            hipLaunchKernelGGL((k_surface<FM, WW>), dim3(G), dim3(kBlock), 0, s, P, Rs, cur, L.ctl,
                                (const uint32_t *)L.sq, L.aq[j & 1], j);
             pr.end();
             pr.begin(MCDC_PROF_COLLISION);
-            hipLaunchKernelGGL((k_collision<FM, WW>), dim3(grid), dim3(kBlock), 0, s, P, Rs, cur, L.ctl,
+            hipLaunchKernelGGL((k_collision<FM, WW>), dim3(G), dim3(kBlock), 0, s, P, Rs, cur, L.ctl,
                                (const uint32_t *)L.cq, L.aq[j & 1], j);
             pr.end();
         }
-        t.row0 = launch++ * (int)grid;
         pr.begin(MCDC_PROF_FINISH);
-        hipLaunchKernelGGL((k_finish<FM, WW>), dim3(grid), dim3(kBlock), shmem, s, P, Rs, cur, nxt, L.ctl,
-                           (const uint32_t *)L.aq[(iters - 1) & 1], iters, t);
+        hipLaunchKernelGGL((k_finish<FM, WW>), dim3(G), dim3(kBlock), shmem, s, P, Rs, cur, nxt, L.ctl, par,
+                           (const uint32_t *)L.aq[(iters - 1) & 1], iters, gn);
         pr.end();
-        if (lds) {
-            pr.begin(MCDC_PROF_OTHER);
-            hipLaunchKernelGGL(k_tally_reduce, dim3((unsigned)((slice + 63) / 64)), dim3(256), 0, s, t,
-                               launch * (int)grid, (const Ctl *)L.ctl, R.S, P.ntally, (int)gn);
-            pr.end();
-        }
         hipLaunchKernelGGL(k_step_end, dim3(1), dim3(1), 0, s, L.ctl);
     };
 
     // replay captured steps unless a per-launch profile or per-history
     // debug output is requested (those launch eagerly)
-    const bool use_graph = !(opt.flags & MCDC_FLAG_EAGER) && !opt.profile && !R.dbg_counts && !R.dbg_scores && P.K > 1;
-    StepGraphs *G = nullptr;
+    const bool use_graph =
+        !(opt.flags & MCDC_FLAG_EAGER) && !opt.profile && !R.dbg_counts && !R.dbg_scores && P.K > 1;
+    StepGraphs *Gr = nullptr;
     if (use_graph) {
         if (!pb->graph_cache) pb->graph_cache = new StepGraphs();
-        G = (StepGraphs *)pb->graph_cache;
+        Gr = (StepGraphs *)pb->graph_cache;
         std::vector<char> key;
         key_add(key, P);
         key_add(key, Rs);
         key_add(key, L);
-        key_add(key, T);
-        key_add(key, grid);
+        key_add(key, gn);
         key_add(key, iters);
-        key_add(key, shmem);
-        if (key != G->key) {
-            G->clear();
+        if (key != Gr->key) {
+            Gr->clear();
             hipError_t e = hipSuccess;
-            if (!G->cs) e = hipStreamCreateWithFlags(&G->cs, hipStreamNonBlocking);
+            if (!Gr->cs) e = hipStreamCreateWithFlags(&Gr->cs, hipStreamNonBlocking);
             Profiler none;
             for (int q = 0; q < 2 && e == hipSuccess; ++q) {
-                e = hipStreamBeginCapture(G->cs, hipStreamCaptureModeThreadLocal);
+                e = hipStreamBeginCapture(Gr->cs, hipStreamCaptureModeThreadLocal);
                 if (e != hipSuccess) break;
-                enqueue_step(q, G->cs, none);
-                e = hipStreamEndCapture(G->cs, &G->graph[q]);
-                if (e == hipSuccess) e = hipGraphInstantiate(&G->exec[q], G->graph[q], nullptr, nullptr, 0);
+                enqueue_step(q, Gr->cs, none);
+                e = hipStreamEndCapture(Gr->cs, &Gr->graph[q]);
+                if (e == hipSuccess) e = hipGraphInstantiate(&Gr->exec[q], Gr->graph[q], nullptr, nullptr, 0);
             }
             if (e != hipSuccess) {
-                G->clear();
+                Gr->clear();
                 return hip_fail(e, "census step capture");
             }
-            G->key = key;
+            Gr->key = key;
         }
     }
 
@@ -781,14 +807,12 @@ int run_event(mcdc_problem *pb, const RunArgs &R0, uint64_t first, uint64_t coun
         const uint64_t cfirst = first + c0;
         hipLaunchKernelGGL(k_ctl_init, dim3(1), dim3(1), 0, st, L.ctl, cfirst);
         if (P.qoi_on && (rc = launch_zero(R.qoi_hist, n * sizeof(double), st))) return hip_fail((hipError_t)rc, "zero");
-        unsigned sgrid = (unsigned)((n + kBlock - 1) / kBlock);
-        if (sgrid > grid_max) sgrid = grid_max;
         prof.begin(MCDC_PROF_SOURCE);
-        hipLaunchKernelGGL((k_source<FM, WW>), dim3(sgrid), dim3(kBlock), 0, st, P, R, L.bank[0], L.ctl, cfirst, n);
+        hipLaunchKernelGGL((k_source<FM, WW>), dim3(G), dim3(kBlock), 0, st, P, R, L.bank[0], L.ctl, n);
         prof.end();
         for (int step = 0; step < P.K; ++step) {
-            if (G) {
-                hipError_t e = hipGraphLaunch(G->exec[step & 1], st);
+            if (Gr) {
+                hipError_t e = hipGraphLaunch(Gr->exec[step & 1], st);
                 if (e != hipSuccess) return hip_fail(e, "census step replay");
             } else {
                 enqueue_step(step & 1, st, prof);
@@ -813,8 +837,8 @@ void destroy_graph_cache(mcdc_problem *p) {
     p->graph_cache = nullptr;
 }
 
-int launch_event(mcdc_problem *p, const RunArgs &R, uint64_t first, uint64_t count,
-                 const mcdc_run_options &opt, hipStream_t st, Profiler &prof) {
+int launch_event(mcdc_problem *p, const RunArgs &R, uint64_t first, uint64_t count, const mcdc_run_options &opt,
+                 hipStream_t st, Profiler &prof) {
     const DevProblem &P = p->d;
     if (p->h.B > 1023 || P.K > 131071) {
         set_error("event form supports at most 1023 batches and 131071 time bins");

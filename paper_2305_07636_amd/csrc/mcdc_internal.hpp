@@ -83,6 +83,7 @@ struct BatchItem {
 // Host-side launch profiler: HIP events around each launch of a class.
 struct Profiler {
     double *out = nullptr;             // host [classes][4] or nullptr
+    unsigned int mask = 0;             // classes to time (0 = all)
     hipStream_t st = nullptr;
     std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> marks;
     int cls = -1;

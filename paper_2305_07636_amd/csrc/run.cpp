@@ -12,21 +12,37 @@
 
 using namespace mcdc;
 
-void Profiler::begin(int c) {
-    if (!out) return;
-    cls = c;
-    open = nullptr;
-    if (hipEventCreate(&open) != hipSuccess) {
-        open = nullptr;
-        return;
+namespace {
+// Events are reused across profiled runs (creating one per launch costs
+// more than the short kernels it would time).
+std::vector<hipEvent_t> &event_pool() {
+    static thread_local std::vector<hipEvent_t> pool;
+    return pool;
+}
+hipEvent_t take_event() {
+    auto &pool = event_pool();
+    if (!pool.empty()) {
+        hipEvent_t e = pool.back();
+        pool.pop_back();
+        return e;
     }
-    (void)hipEventRecord(open, st);
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+}  // namespace
+
+void Profiler::begin(int c) {
+    if (!out || (mask && !((mask >> c) & 1u))) return;
+    cls = c;
+    open = take_event();
+    if (open) (void)hipEventRecord(open, st);
 }
 
 void Profiler::end() {
     if (!out || !open) return;
-    hipEvent_t e = nullptr;
-    if (hipEventCreate(&e) != hipSuccess) return;
+    hipEvent_t e = take_event();
+    if (!e) return;
     (void)hipEventRecord(e, st);
     marks.push_back({cls, {open, e}});
     open = nullptr;
@@ -40,8 +56,8 @@ int Profiler::finish() {
         if (err == hipSuccess) err = hipEventElapsedTime(&ms, m.second.first, m.second.second);
         out[m.first * 4 + 0] += ms;
         out[m.first * 4 + 1] += 1.0;
-        (void)hipEventDestroy(m.second.first);
-        (void)hipEventDestroy(m.second.second);
+        event_pool().push_back(m.second.first);
+        event_pool().push_back(m.second.second);
     }
     marks.clear();
     if (err != hipSuccess) return hip_fail(err, "profile events");
@@ -207,6 +223,7 @@ extern "C" int mcdc_run(mcdc_problem *p, uint64_t n_histories, uint64_t seed, co
     hipStream_t st = (hipStream_t)opt.stream;
     Profiler prof;
     prof.out = opt.profile;
+    prof.mask = opt.profile_mask;
     prof.st = st;
     Events ev;
     HIP_CHECK(hipEventCreate(&ev.a), "hipEventCreate");

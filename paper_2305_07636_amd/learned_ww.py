@@ -123,26 +123,53 @@ def centres_from_log_importance(logI: np.ndarray, log_ref: float, shape) -> np.n
     return np.ascontiguousarray(w)
 
 
+def _tally(prob: dict, n: int, seed: int, table=None, ratio: float = 5.0, max_split: int = 16):
+    """Steady flux tally (mean, relative error) of a run of the tracker."""
+    p = B.mcdc_problem_create(prob)
+    try:
+        if table is not None:
+            B.mcdc_set_weight_windows(p, table, ratio, max_split)
+        out = B.mcdc_run(p, n, seed, algorithm="history", outputs=("mean", "var"))
+        phi = out["mean"].double().cpu().numpy().ravel()
+        var = out["var"].double().cpu().numpy().ravel()
+    finally:
+        p.close()
+    rel = np.sqrt(var) / np.where(phi > 0, phi, 1.0)
+    return phi, rel
+
+
+def _frontier_table(logI, ok, shape, pct):
+    log_ref = float(np.percentile(logI[ok], pct))
+    return centres_from_log_importance(np.where(ok, logI, -np.inf), log_ref, shape)
+
+
 def learned_windows(prob: dict, n_pilot: int = 10_000_000, seed: int = 50, steps: int = 3000,
                     lr: float = 1e-3, net_seed: int = 1, rel_max: float = 0.3, frontier_pct: float = 5.0):
-    """Pilot (adjoint, analog) -> training set -> network -> window table.
+    """Plain pilots -> training set -> network -> window table.
+
+    1. forward analog pilot: the flux phi, which is the importance of the
+       adjoint problem's response (the forward source region);
+    2. adjoint pilot, with windows from phi (frontier-normalised, analog
+       where phi is unresolved) so adjoint particles reach back to the
+       source: the adjoint flux phi+, the importance of the detector;
+    3. the network fits log10 phi+ on the cells the pilot resolved
+       (weights 1 / (R^2 + 0.01)); BF16 inference gives log10 I on every
+       cell; windows w_c = I(source) / I(cell), normalised over the source
+       cells when the pilot resolved them, else at the resolved frontier.
 
     Returns (table [K][G][wz][wy][wx], info dict with the raw-tally table
     and timings)."""
     import torch
 
     adj = adjoint_problem(prob)
+    shape = (1, prob["sigma_t"].shape[1]) + source_cells(prob).shape
     t0 = time.perf_counter()
-    p = B.mcdc_problem_create(adj)
-    try:
-        out = B.mcdc_run(p, n_pilot, seed, algorithm="history", outputs=("mean", "var"))
-        phi = out["mean"].double().cpu().numpy().ravel()
-        var = out["var"].double().cpu().numpy().ravel()
-    finally:
-        p.close()
+    phi_f, rel_f = _tally(prob, n_pilot, seed)
+    ok_f = (phi_f > 0) & (rel_f < rel_max)
+    adj_table = _frontier_table(np.log10(np.where(ok_f, phi_f, 1.0)), ok_f, shape, frontier_pct)
+    phi, rel = _tally(adj, n_pilot, seed + 1, table=adj_table)
     t_pilot = time.perf_counter() - t0
     X = cell_features(prob)
-    rel = np.sqrt(var) / np.where(phi > 0, phi, 1.0)
     ok = (phi > 0) & (rel < rel_max)
     T = np.log10(phi[ok]).astype(np.float32)
     W = (1.0 / (rel[ok] ** 2 + 0.01)).astype(np.float32)
@@ -161,12 +188,22 @@ def learned_windows(prob: dict, n_pilot: int = 10_000_000, seed: int = 50, steps
     # keep the prediction within the range the pilot saw (no runaway
     # extrapolation into cells the network never observed)
     yhat = np.clip(yhat, T.min() - 1.0, T.max() + 1.0)
-    log_ref = float(np.percentile(T, frontier_pct))
-    shape = (1, prob["sigma_t"].shape[1]) + source_cells(prob).shape
+    src = source_cells(prob)
+    pmf = np.asarray(prob["source"]["group_pmf"], dtype=np.float64)
+    ok5 = ok.reshape(shape)
+    src_resolved = all(ok5[0, g][src].any() for g in range(shape[1]) if pmf[g] > 0)
+    y5 = yhat.reshape(shape)
+    if src_resolved:
+        # importance of the source: spectrum-weighted mean over source cells
+        I_src = sum(pmf[g] * np.mean(10.0 ** y5[0, g][src]) for g in range(shape[1]) if pmf[g] > 0)
+        log_ref = float(np.log10(I_src))
+    else:
+        log_ref = float(np.percentile(T, frontier_pct))
     table = centres_from_log_importance(yhat, log_ref, shape)
     raw = centres_from_log_importance(np.where(ok, np.log10(np.where(ok, phi, 1.0)), -np.inf), log_ref, shape)
     info = {"pilot_s": t_pilot, "train_s": t_train, "n_train": int(ok.sum()), "loss_first": float(losses[0]),
-            "loss_last": float(losses[-1]), "raw_table": raw, "adjoint_flux": phi}
+            "loss_last": float(losses[-1]), "raw_table": raw, "adjoint_flux": phi,
+            "source_resolved": bool(src_resolved), "log_ref": log_ref}
     return table, info
 
 
