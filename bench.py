@@ -15,6 +15,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -68,6 +69,75 @@ def cpu_baseline(N, seed, target_s=15.0):
     }
 
 
+def batched_section(m, w):
+    """256 uneven lattices (n x n, n ~ U{4..32}, G ~ U{1..7}, 1e4..1e6
+    histories each): one persistent batched launch (autotuned on its first
+    call) against 256 separate runs of the same problems and seeds."""
+    import torch
+
+    probs, nh = w.cfg4_batch()
+    seeds = [2000 + j for j in range(len(probs))]
+    hs = [m.mcdc_problem_create(p) for p in probs]
+    try:
+        m.mcdc_run_batched(hs, nh, seeds)          # tunes and caches the launch shape
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        outs = m.mcdc_run_batched(hs, nh, seeds)
+        torch.cuda.synchronize()
+        t_b = time.perf_counter() - t0
+        res = {"problems": len(probs), "histories": int(sum(nh)), "batched_s": t_b,
+               "batched_histories_per_s": sum(nh) / t_b}
+        for alg in ("history", "event"):
+            m.mcdc_run(hs[0], nh[0], seeds[0], algorithm=alg)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            seq = [m.mcdc_run(h, n, s, algorithm=alg) for h, n, s in zip(hs, nh, seeds)]
+            torch.cuda.synchronize()
+            t_s = time.perf_counter() - t0
+            res[f"sequential_{alg}_s"] = t_s
+            res[f"speedup_vs_sequential_{alg}"] = t_s / t_b
+            if alg == "history":
+                res["counts_match_sequential"] = all(
+                    (a["events"] == b["events"]).all() and (a["terms"] == b["terms"]).all()
+                    for a, b in zip(outs, seq))
+            del seq
+        return res
+    finally:
+        for h in hs:
+            h.close()
+
+
+def fom_section(w, n_pilot, n_analog, n_ww, steps):
+    """Dog-leg duct, detector behind the second bend: analog against learned
+    weight windows (pilots, network fit, BF16 inference) and against windows
+    from the raw pilot tally with no network."""
+    from paper_2305_07636_amd import learned_ww as lw
+
+    p = w.cfg5_dogleg()
+    t0 = time.perf_counter()
+    table, info = lw.learned_windows(p, n_pilot=n_pilot, steps=steps)
+    t_build = time.perf_counter() - t0
+    a = lw.figure_of_merit(p, n_analog, 52)
+    b = lw.figure_of_merit(p, n_ww, 51, table=table)
+    c = lw.figure_of_merit(p, n_ww, 53, table=info["raw_table"])
+
+    def diff(x, y):
+        s = math.hypot(x["sigma"], y["sigma"])
+        return abs(x["mean"] - y["mean"]) / s if s > 0 else None
+
+    return {
+        "workload": "dog-leg duct 30x10x10, 2 groups, 40x10x10 window mesh, detector box "
+                    "[29,30]x[7,9]x[4,6]",
+        "pilot_histories": n_pilot, "train_steps": steps, "window_build_s": t_build,
+        "pilot_s": info["pilot_s"], "train_s": info["train_s"], "loss": [info["loss_first"], info["loss_last"]],
+        "analog": a, "learned": b, "raw_tally_windows": c,
+        "fom_gain_learned_vs_analog": (b["fom"] / a["fom"]) if a["fom"] > 0 else None,
+        "fom_gain_learned_vs_raw": (b["fom"] / c["fom"]) if c["fom"] > 0 else None,
+        "mean_diff_sigma_learned_vs_analog": diff(a, b),
+        "mean_diff_sigma_raw_vs_analog": diff(a, c),
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -78,6 +148,12 @@ def main():
     ap.add_argument("--event-iters", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-history-form", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-fom", action="store_true")
+    ap.add_argument("--fom-pilot", type=float, default=1e7)
+    ap.add_argument("--fom-analog", type=float, default=1e9)
+    ap.add_argument("--fom-ww", type=float, default=1e8)
+    ap.add_argument("--fom-steps", type=int, default=3000)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 1 GiB device-to-device copy (reference for HBM counters)")
     args = ap.parse_args()
@@ -163,6 +239,12 @@ def main():
             step("history", s)
         torch.cuda.synchronize()
         extra["history_form_histories_per_s"] = N * args.steps / (time.perf_counter() - t1)
+    p.close()
+    if not args.no_batched:
+        extra["batched"] = batched_section(m, w)
+    if not args.no_fom:
+        extra["figure_of_merit"] = fom_section(w, int(args.fom_pilot), int(args.fom_analog),
+                                               int(args.fom_ww), args.fom_steps)
 
     line = {
         "metric": METRIC, "value": value, "unit": "histories/s", "n_gpus": 1,
@@ -176,7 +258,6 @@ def main():
         "kernels_per_step": per_class,
     }
     line.update(extra)
-    p.close()
     print(json.dumps(line))
 
 

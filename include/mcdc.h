@@ -135,7 +135,8 @@ typedef struct {
 /*
  * Run options (all-zero = defaults).
  *  algorithm      MCDC_ALG_EVENT (default) or MCDC_ALG_HISTORY.
- *  block_size     threads per block, 0 = tuned default (64..1024, multiple of 64).
+ *  block_size     history form: threads per block, 0 = tuned default (64..1024,
+ *                 multiple of 64).  The event form always uses 256.
  *  bank_capacity  event form: particles resident at once (0 = auto).  Work
  *                 is processed in chunks of this many histories.
  *  event_iters    event form: queue iterations (advance, then the surface
@@ -162,6 +163,10 @@ typedef struct {
  *  profile_mask   bit c set: bracket launches of class c with events
  *                 (0 = all classes); particle and byte counts are always
  *                 gathered for every class when profile is given.
+ *  segments       event form: bank segments, one per workgroup of every
+ *                 event kernel (0 = auto: as many workgroups of the advance
+ *                 kernel as the GPU holds resident at once, so each census
+ *                 pass runs in a single round).  Results do not depend on it.
  */
 #define MCDC_FLAG_EAGER 1
 #define MCDC_PROF_CLASSES 8
@@ -184,7 +189,7 @@ typedef struct {
     double *debug_scores;
     double *profile;
     uint32_t profile_mask;
-    uint32_t reserved;
+    int32_t segments;
 } mcdc_run_options;
 
 /*

@@ -56,7 +56,7 @@ class mcdc_run_options(C.Structure):
         ("algorithm", C.c_int32), ("block_size", C.c_int32), ("bank_capacity", C.c_int64),
         ("event_iters", C.c_int32), ("flags", C.c_int32), ("stream", C.c_void_p),
         ("debug_counts", C.c_void_p), ("debug_scores", C.c_void_p),
-        ("profile", C.c_void_p), ("profile_mask", C.c_uint32), ("reserved2", C.c_uint32),
+        ("profile", C.c_void_p), ("profile_mask", C.c_uint32), ("segments", C.c_int32),
     ]
 
 
@@ -226,7 +226,7 @@ def mcdc_set_weight_windows(p: Problem, centers, ratio: float = 5.0, max_split: 
 
 
 def mcdc_run(p: Problem, n_histories: int, seed: int, algorithm: str = "event",
-             block_size: int = 0, bank_capacity: int = 0, event_iters: int = 0,
+             block_size: int = 0, bank_capacity: int = 0, event_iters: int = 0, segments: int = 0,
              debug: bool = False, outputs=("mean", "var", "raw", "leak_mean", "leak_var"),
              profile=None, eager: bool = False, profile_classes=None):
     """Run n_histories through the GPU tracker.  Returns a dict of torch
@@ -255,6 +255,7 @@ def mcdc_run(p: Problem, n_histories: int, seed: int, algorithm: str = "event",
     opt.block_size = block_size
     opt.bank_capacity = bank_capacity
     opt.event_iters = event_iters
+    opt.segments = segments
     opt.flags = 1 if eager else 0
     opt.stream = torch.cuda.current_stream(dev).cuda_stream
     if debug:

@@ -708,10 +708,28 @@ int run_event(mcdc_problem *pb, const RunArgs &R0, uint64_t first, uint64_t coun
     if (C > (1ULL << 28)) C = 1ULL << 28;
     int iters = opt.event_iters > 0 ? opt.event_iters : 1;
     if (iters > kMaxIters - 1) iters = kMaxIters - 1;
-    // segments: one per workgroup, several workgroups per CU
-    unsigned int G = (unsigned int)((C + kBlock - 1) / kBlock);
-    const unsigned int g_max = opt.block_size ? (unsigned int)opt.block_size * 8u : 2048u;
-    if (G > g_max) G = g_max;
+    // per-step tally slice [2 batches][G][nts] in LDS when it fits
+    const int64_t gn64 = (int64_t)P.G * P.nts;
+    const int gn = (2 * gn64 <= kLdsTallyMax) ? (int)gn64 : 0;
+    const size_t shmem = (size_t)2 * gn * sizeof(double);
+
+    // segments: one per workgroup.  Auto: the advance kernel's resident
+    // capacity, so its pass over the census bank is one round of workgroups
+    // (a second, partly filled round would cost nearly a full one).
+    unsigned int G;
+    if (opt.segments > 0) {
+        G = (unsigned int)opt.segments;
+    } else {
+        int per_cu = 0, n_cu = 0;
+        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &per_cu, reinterpret_cast<const void *>(&k_advance<FM, WW, true>), kBlock, shmem);
+        if (e == hipSuccess) e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, pb->device);
+        if (e != hipSuccess) return hip_fail(e, "occupancy query");
+        G = (unsigned int)(per_cu > 0 ? per_cu : 1) * (unsigned int)(n_cu > 0 ? n_cu : 1);
+    }
+    const uint64_t g_need = (C + kBlock - 1) / kBlock;
+    if (G > g_need) G = (unsigned int)g_need;
+    if (G < 1) G = 1;
     const unsigned int Lseg = (unsigned int)((C + G - 1) / G);
     const uint64_t slots = (uint64_t)G * Lseg;
     int rc;
@@ -721,11 +739,6 @@ int run_event(mcdc_problem *pb, const RunArgs &R0, uint64_t first, uint64_t coun
     Layout L = carve(pb->bank.p, pb->queues.p, slots, G, Lseg);
     RunArgs R = R0;
     R.qoi_hist = (double *)pb->qoi_hist.p;
-
-    // per-step tally slice [2 batches][G][nts] in LDS when it fits
-    const int64_t gn64 = (int64_t)P.G * P.nts;
-    const int gn = (2 * gn64 <= kLdsTallyMax) ? (int)gn64 : 0;
-    const size_t shmem = (size_t)2 * gn * sizeof(double);
 
     // the step kernels never read the seed or the history count
     RunArgs Rs = R;

@@ -87,6 +87,7 @@ int check_options(const mcdc_run_options &opt) {
     if (opt.algorithm != MCDC_ALG_EVENT && opt.algorithm != MCDC_ALG_HISTORY) return bad("unknown algorithm");
     if (opt.block_size != 0 && (opt.block_size < 64 || opt.block_size > 1024 || opt.block_size % 64))
         return bad("block_size must be a multiple of 64 in [64, 1024]");
+    if (opt.segments < 0 || opt.segments > (1 << 20)) return bad("segments must be in [0, 2^20]");
     if (opt.bank_capacity < 0) return bad("bank_capacity must be >= 0");
     if (opt.event_iters < 0) return bad("event_iters must be >= 0");
     return MCDC_OK;

@@ -135,3 +135,25 @@ def test_event_graph_replays_match_eager_and_oracle(case):
             m.mcdc_run(p, 1000, seed + 1 + rep, algorithm="history")   # unrelated eager work in between
     finally:
         p.close()
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("segments", [1, 7, 300])
+def test_event_segment_count_does_not_change_results(segments):
+    """The bank is cut into segments owned by workgroups; how many there
+    are changes the schedule, never the counts or (beyond summation order)
+    the tallies."""
+    from gpu_common import close, gpu_run
+
+    p = w.cfg3_lattice()
+    a = gpu_run(p, 30011, 41, "event")
+    import paper_2305_07636_amd as m
+
+    print(f"[segments] {segments}", flush=True)
+    h = m.mcdc_problem_create(p)
+    try:
+        b = m.mcdc_run(h, 30011, 41, algorithm="event", segments=segments)
+    finally:
+        h.close()
+    assert np.array_equal(a["events"], b["events"]) and np.array_equal(a["terms"], b["terms"])
+    close(b["mean"].cpu().numpy(), a["mean"])
