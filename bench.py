@@ -27,6 +27,12 @@ METRIC = "histories/sec + figure of merit 1/(σ²T), plain analog vs learned-WW,
 WORKLOAD = ("pulsed slab: 1 group, Sigma_t=1, c=0.9, v=1, 40 mfp, isotropic centre pulse at t=0, "
             "50 x-bins x 100 time bins on [0,20], 1e7 histories, FP64")
 HBM_PEAK_GBS = 8000.0
+T_START = time.perf_counter()
+
+
+def log(msg):
+    """Progress to stderr (the JSON line alone goes to stdout)."""
+    print(f"[bench {time.perf_counter() - T_START:7.1f}s] {msg}", file=sys.stderr, flush=True)
 
 
 def cpu_worker(args):
@@ -46,6 +52,7 @@ def cpu_baseline(N, seed, target_s=15.0):
     the same job (histories 0..n-1), in independent processes over
     contiguous history ranges (skip-ahead makes them independent)."""
     import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor
 
     import oracle
 
@@ -55,11 +62,13 @@ def cpu_baseline(N, seed, target_s=15.0):
     t = cpu_worker((0, 20000, N, seed))
     rate1 = 20000 / t
     per = max(1000, int(rate1 * target_s / 2))
+    per = min(per, N // cores)       # the sample stays inside the job
     n = per * cores
-    ctx = mp.get_context("spawn")
-    with ctx.Pool(cores) as pool:
+    # a worker that dies raises BrokenProcessPool here instead of hanging
+    with ProcessPoolExecutor(cores, mp_context=mp.get_context("spawn")) as ex:
+        list(ex.map(cpu_worker, [(0, 1000, N, seed)] * cores))    # start the workers
         t0 = time.perf_counter()
-        pool.map(cpu_worker, [(j * per, per, N, seed) for j in range(cores)])
+        list(ex.map(cpu_worker, [(j * per, per, N, seed) for j in range(cores)]))
         wall = time.perf_counter() - t0
     return {
         "value": n / wall, "unit": "histories/s", "cores": cores, "kind": "oracle",
@@ -78,9 +87,11 @@ def batched_section(m, w):
     probs, nh = w.cfg4_batch()
     seeds = [2000 + j for j in range(len(probs))]
     hs = [m.mcdc_problem_create(p) for p in probs]
+    log(f"batched: {len(hs)} problems created")
     try:
         m.mcdc_run_batched(hs, nh, seeds)          # tunes and caches the launch shape
         torch.cuda.synchronize()
+        log("batched: tuned")
         t0 = time.perf_counter()
         outs = m.mcdc_run_batched(hs, nh, seeds)
         torch.cuda.synchronize()
@@ -94,6 +105,7 @@ def batched_section(m, w):
             seq = [m.mcdc_run(h, n, s, algorithm=alg) for h, n, s in zip(hs, nh, seeds)]
             torch.cuda.synchronize()
             t_s = time.perf_counter() - t0
+            log(f"batched: {len(hs)} separate {alg} runs {t_s:.3f} s vs batched {t_b:.3f} s")
             res[f"sequential_{alg}_s"] = t_s
             res[f"speedup_vs_sequential_{alg}"] = t_s / t_b
             if alg == "history":
@@ -117,9 +129,13 @@ def fom_section(w, n_pilot, n_analog, n_ww, steps):
     t0 = time.perf_counter()
     table, info = lw.learned_windows(p, n_pilot=n_pilot, steps=steps)
     t_build = time.perf_counter() - t0
+    log(f"fom: windows built in {t_build:.1f} s")
     a = lw.figure_of_merit(p, n_analog, 52)
+    log(f"fom: analog {a}")
     b = lw.figure_of_merit(p, n_ww, 51, table=table)
+    log(f"fom: learned {b}")
     c = lw.figure_of_merit(p, n_ww, 53, table=info["raw_table"])
+    log(f"fom: raw-tally windows {c}")
 
     def diff(x, y):
         s = math.hypot(x["sigma"], y["sigma"])
@@ -168,6 +184,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(N, seed)    # before the GPU is touched (spawned workers)
+        log(f"cpu baseline: {cpu['value']:.3g} histories/s on {cpu['cores']} processes")
 
     import numpy as np
     import torch
@@ -192,6 +209,7 @@ def main():
         return m.mcdc_run(p, N, seed + s, algorithm=alg, outputs=outs, profile=profile,
                           profile_classes=classes, event_iters=args.event_iters)
 
+    log("problem on the GPU")
     names = m._binding.PROF_CLASSES
     # per-class breakdown (HIP events around every launch) in an untimed
     # step: it names the dominant kernel class
@@ -210,6 +228,7 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     value = N * args.steps / elapsed
+    log(f"{args.steps} timed steps: {elapsed / args.steps * 1e3:.2f} ms/step")
     ms, launches, items, nbytes = prof[cls]
     if args.algorithm == "event":
         achieved = nbytes / (ms * 1e-3) / 1e9
@@ -239,6 +258,7 @@ def main():
             step("history", s)
         torch.cuda.synchronize()
         extra["history_form_histories_per_s"] = N * args.steps / (time.perf_counter() - t1)
+        log("history form timed")
     p.close()
     if not args.no_batched:
         extra["batched"] = batched_section(m, w)

@@ -216,8 +216,12 @@ def run(prob, N: int, seed: int, ids=None, first: int = 0, count=None,
     if ids is not None:
         ids = np.ascontiguousarray(np.asarray(ids, dtype=np.uint64))
         n = ids.size
+        if n and int(ids.max()) >= N:
+            raise ValueError("history ids must be below N")
     else:
         n = N - first if count is None else count
+        if first < 0 or n < 0 or first + n > N:
+            raise ValueError(f"histories [{first}, {first + n}) outside the {N}-history job")
     S = np.zeros((B, op.ntally))
     L = np.zeros((B, op.K, op.G, 6))
     q = np.zeros(2)

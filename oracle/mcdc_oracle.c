@@ -712,7 +712,8 @@ int oracle_union_planes(const oracle_problem *p, int axis, double *out, int cap)
  * tot[9], and per-history records rec[n_ids][5] = (census, surface,
  * collision, particles, termination mask) and per-history track and
  * detector scores trk[n_ids][2].  Returns 0, or -1 on an invalid problem,
- * -4 if split progeny overflow the per-history stack.
+ * -4 if split progeny overflow the per-history stack, -5 if a history
+ * index is not below N.
  */
 int oracle_run(const oracle_problem *p, uint64_t N, uint64_t seed,
                const uint64_t *ids, uint64_t first, uint64_t n_ids,
@@ -737,6 +738,10 @@ int oracle_run(const oracle_problem *p, uint64_t N, uint64_t seed,
     uint64_t s0 = seed & MASK63;
     for (uint64_t r = 0; r < n_ids; r++) {
         uint64_t i = ids ? ids[r] : first + r;
+        if (i >= N) {
+            rc = -5;
+            break;
+        }
         int64_t b = (int64_t)(((i + 1) * (uint64_t)B - 1) / N);
         hist_rec h;
         memset(&h, 0, sizeof(h));

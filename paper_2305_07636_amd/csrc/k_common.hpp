@@ -396,4 +396,13 @@ __device__ __forceinline__ void atomic_add_f64(double *a, double v) {
 }
 
 }  // namespace dev
+
+// Split bank of the weight-window game (k_history.hip): carve two
+// generations' banks for chunks of up to `chunk` histories, clear the first
+// generation's count, and track every generation of progeny of a chunk.
+int split_prepare(mcdc_problem *pb, uint64_t chunk, dev::SplitBank SB[2]);
+void split_reset(const dev::SplitBank SB[2], hipStream_t st);
+int split_generations(mcdc_problem *pb, const RunArgs &R, dev::SplitBank SB[2], uint64_t cfirst, hipStream_t st,
+                      Profiler &prof);
+
 }  // namespace mcdc

@@ -159,6 +159,9 @@ __device__ __forceinline__ void load_state(const DevProblem &P, const Bank &B, u
         if (finite_axis<FM>(P, a)) {
             p.x[a] = B.x[a][slot];
             p.u[a] = B.u[a][slot];
+        } else if (WW) {
+            p.x[a] = 0.0;   // copied to split progeny; never used in flight
+            p.u[a] = 0.0;
         }
     }
     set_inverse<FM>(P, p);
@@ -191,6 +194,27 @@ __device__ __forceinline__ void store_state(const DevProblem &P, const Bank &B, 
     B.ixyz[slot] = pack_ix(p.ix);
     B.gk[slot] = gk;
     B.hid[slot] = hid;
+}
+
+// Weight-window check point of the event kernels: roulette (returns false)
+// or split, with the progeny written whole to the split bank; they are
+// tracked after the chunk's census steps, generation by generation.
+template <bool WW>
+__device__ __forceinline__ bool ww_point(const DevProblem &P, const RunArgs &R, const SplitBank &SB, Particle &p,
+                                         int cell, int b, uint64_t i, Counters &cnt) {
+    if (!WW) return true;
+    int nc = 0;
+    if (!ww_check(P, p, cell, nc)) {
+        cnt.add(3 + kRoulette);
+        hist_term(R, i, kRoulette);
+        return false;
+    }
+    if (nc > 0) {
+        if (!spawn_children(SB, p, nc, b, i)) *R.overflow = 1;
+        cnt.add(8, (unsigned int)nc);
+        if (R.dbg_counts) atomicAdd(R.dbg_counts + i * 5 + 3, (unsigned int)nc);
+    }
+    return true;
 }
 
 __device__ __forceinline__ uint32_t with_gk(uint32_t gk, const Particle &p) {
@@ -287,7 +311,7 @@ enum Outcome : int { kNone = 0, kToNext = 1, kToSurface = 2, kToCollision = 3 };
 template <int FM, bool WW, bool DENSE, int CLS = DENSE ? MCDC_PROF_ADVANCE : MCDC_PROF_ADVANCE_Q>
 __global__ void __launch_bounds__(kBlock) k_advance(DevProblem P, RunArgs R, Bank cur, Bank next, Ctl C, int par,
                                                     const uint32_t *__restrict__ aq, int it, uint32_t *sq,
-                                                    uint32_t *cq, int gn) {
+                                                    uint32_t *cq, int gn, SplitBank SB) {
     __shared__ Counters cnt;
     __shared__ unsigned int cN, cS, cC;
     extern __shared__ double lt[];
@@ -306,13 +330,14 @@ __global__ void __launch_bounds__(kBlock) k_advance(DevProblem P, RunArgs R, Ban
     StepScore sc;
     init_slice(sc, lt, gn, C.seg_b0[seg]);
     __syncthreads();
-    const bool per_hist = (R.dbg_counts != nullptr) || (R.dbg_scores != nullptr) || P.qoi_on;
+    const bool per_hist = WW || (R.dbg_counts != nullptr) || (R.dbg_scores != nullptr) || P.qoi_on;
     for (unsigned int j0 = 0; j0 < n; j0 += kBlock) {
         const unsigned int idx = j0 + threadIdx.x;
         const bool valid = idx < n;
         const uint32_t slot = valid ? (DENSE ? seg0 + idx : aq[seg0 + idx]) : 0u;
         int outcome = kNone;
         int mask = 0;
+        bool have_s = false;
         Particle p;
         uint32_t gk = 0, hid = 0;
         if (valid) {
@@ -349,6 +374,11 @@ __global__ void __launch_bounds__(kBlock) k_advance(DevProblem P, RunArgs R, Ban
                             if (per_hist) hist_term(R, i, kTime);
                         } else {
                             outcome = kToNext;
+                            if (WW) {
+                                p.s = cur.s[slot];
+                                have_s = true;
+                                if (!ww_point<WW>(P, R, SB, p, cell, b, i, cnt)) outcome = kNone;
+                            }
                         }
                     } else if (f.ev == kSurface) {
                         cnt.add(1);
@@ -367,7 +397,7 @@ __global__ void __launch_bounds__(kBlock) k_advance(DevProblem P, RunArgs R, Ban
         const uint32_t ss = block_append(outcome == kToSurface, &cS);
         const uint32_t cs = block_append(outcome == kToCollision, &cC);
         if (outcome == kToNext) {
-            p.s = cur.s[slot];
+            if (!have_s) p.s = cur.s[slot];
             if (!per_hist) hid = cur.hid[slot];
             store_state<FM, WW>(P, next, seg0 + ns, p, with_gk(gk, p), hid);
         } else if (outcome == kToSurface || outcome == kToCollision) {
@@ -404,7 +434,8 @@ __global__ void __launch_bounds__(kBlock) k_advance(DevProblem P, RunArgs R, Ban
 // ---------------------------------------------------------------------------
 template <int FM, bool WW, int CLS = MCDC_PROF_SURFACE>
 __global__ void __launch_bounds__(kBlock) k_surface(DevProblem P, RunArgs R, Bank cur, Ctl C,
-                                                    const uint32_t *__restrict__ sq, uint32_t *aq_out, int it) {
+                                                    const uint32_t *__restrict__ sq, uint32_t *aq_out, int it,
+                                                    SplitBank SB) {
     __shared__ Counters cnt;
     __shared__ unsigned int cA;
     const unsigned int seg = blockIdx.x;
@@ -428,14 +459,26 @@ __global__ void __launch_bounds__(kBlock) k_surface(DevProblem P, RunArgs R, Ban
             mask = (int)(e >> 29);
             uint32_t gk;
             load_state<FM, WW>(P, cur, slot, p, gk);
+            const int old_ww = WW ? P.cell_ww[cell_index(P, p.ix)] : 0;
             const int face = cross<FM>(P, p, mask);
+            const int b = (gk >> 5) & 1023u;
             if (face >= 0) {
-                const int b = (gk >> 5) & 1023u;
                 atomic_add_f64(R.L + (((int64_t)b * P.K + p.k) * P.G + p.g) * 6 + face, p.w);
                 cnt.add(3 + kLeak);
                 if (R.dbg_counts) hist_term(R, first + cur.hid[slot], kLeak);
             } else {
                 alive = true;
+                if (WW) {
+                    const int cell = cell_index(P, p.ix);
+                    if (P.cell_ww[cell] != old_ww) {
+                        p.s = cur.s[slot];
+                        alive = ww_point<WW>(P, R, SB, p, cell, b, first + cur.hid[slot], cnt);
+                        cur.s[slot] = p.s;
+                        cur.w[slot] = p.w;
+                    }
+                }
+            }
+            if (alive) {
 #pragma unroll
                 for (int a = 0; a < 3; ++a) {
                     if (finite_axis<FM>(P, a) && ((mask >> a) & 1)) {
@@ -461,7 +504,8 @@ __global__ void __launch_bounds__(kBlock) k_surface(DevProblem P, RunArgs R, Ban
 // ---------------------------------------------------------------------------
 template <int FM, bool WW, int CLS = MCDC_PROF_COLLISION>
 __global__ void __launch_bounds__(kBlock) k_collision(DevProblem P, RunArgs R, Bank cur, Ctl C,
-                                                      const uint32_t *__restrict__ cq, uint32_t *aq_out, int it) {
+                                                      const uint32_t *__restrict__ cq, uint32_t *aq_out, int it,
+                                                      SplitBank SB) {
     __shared__ Counters cnt;
     __shared__ unsigned int cA;
     const unsigned int seg = blockIdx.x;
@@ -481,18 +525,26 @@ __global__ void __launch_bounds__(kBlock) k_collision(DevProblem P, RunArgs R, B
         if (valid) {
             slot = cq[seg0 + idx];
             const uint32_t gk = cur.gk[slot];
+            if (WW) {
+                uint32_t gk_unused;
+                load_state<FM, WW>(P, cur, slot, p, gk_unused);   // whole state for split progeny
+            }
             p.g = gk & 31u;
             p.s = cur.s[slot];
             const uint32_t c = cur.ixyz[slot];
             const int ix[3] = {(int)(c & 2047u), (int)((c >> 11) & 2047u), (int)(c >> 22)};
-            const int m = P.cell_mat[cell_index(P, ix)];
+            const int cell = cell_index(P, ix);
+            const int m = P.cell_mat[cell];
             if (collide<FM>(P, p, m)) {
-                alive = true;
-                cur.gk[slot] = (gk & ~31u) | (uint32_t)p.g;
-                cur.tau[slot] = p.tau;
+                alive = !WW || ww_point<WW>(P, R, SB, p, cell, (gk >> 5) & 1023u, first + cur.hid[slot], cnt);
+                if (alive) {
+                    cur.gk[slot] = (gk & ~31u) | (uint32_t)p.g;
+                    cur.tau[slot] = p.tau;
+                    if (WW) cur.w[slot] = p.w;
 #pragma unroll
-                for (int a = 0; a < 3; ++a)
-                    if (finite_axis<FM>(P, a)) cur.u[a][slot] = p.u[a];
+                    for (int a = 0; a < 3; ++a)
+                        if (finite_axis<FM>(P, a)) cur.u[a][slot] = p.u[a];
+                }
             } else {
                 cnt.add(3 + kAbsorb);
                 if (R.dbg_counts) hist_term(R, first + cur.hid[slot], kAbsorb);
@@ -513,7 +565,7 @@ __global__ void __launch_bounds__(kBlock) k_collision(DevProblem P, RunArgs R, B
 // ---------------------------------------------------------------------------
 template <int FM, bool WW, int CLS = MCDC_PROF_FINISH>
 __global__ void __launch_bounds__(kBlock) k_finish(DevProblem P, RunArgs R, Bank cur, Bank next, Ctl C, int par,
-                                                   const uint32_t *__restrict__ aq, int it, int gn) {
+                                                   const uint32_t *__restrict__ aq, int it, int gn, SplitBank SB) {
     __shared__ Counters cnt;
     __shared__ unsigned int cN;
     extern __shared__ double lt[];
@@ -576,12 +628,13 @@ __global__ void __launch_bounds__(kBlock) k_finish(DevProblem P, RunArgs R, Bank
                         cnt.add(3 + kTime);
                         if (per_hist) hist_term(R, i, kTime);
                     } else {
-                        to_next = true;
+                        to_next = ww_point<WW>(P, R, SB, p, cell, b, i, cnt);
                     }
                     break;
                 } else if (f.ev == kSurface) {
                     cnt.add(1);
                     if (per_hist) hist_event(R, i, 1);
+                    const int old_ww = WW ? P.cell_ww[cell] : 0;
                     const int face = cross<FM>(P, p, crossing_mask<FM>(P, f));
                     if (face >= 0) {
                         atomic_add_f64(R.L + (((int64_t)b * P.K + p.k) * P.G + p.g) * 6 + face, p.w);
@@ -590,6 +643,7 @@ __global__ void __launch_bounds__(kBlock) k_finish(DevProblem P, RunArgs R, Bank
                         break;
                     }
                     cell = cell_index(P, p.ix);
+                    if (WW && P.cell_ww[cell] != old_ww && !ww_point<WW>(P, R, SB, p, cell, b, i, cnt)) break;
                 } else {
                     cnt.add(2);
                     if (per_hist) hist_event(R, i, 2);
@@ -598,6 +652,7 @@ __global__ void __launch_bounds__(kBlock) k_finish(DevProblem P, RunArgs R, Bank
                         if (per_hist) hist_term(R, i, kAbsorb);
                         break;
                     }
+                    if (WW && !ww_point<WW>(P, R, SB, p, cell, b, i, cnt)) break;
                 }
             }
         }
@@ -739,6 +794,10 @@ int run_event(mcdc_problem *pb, const RunArgs &R0, uint64_t first, uint64_t coun
     Layout L = carve(pb->bank.p, pb->queues.p, slots, G, Lseg);
     RunArgs R = R0;
     R.qoi_hist = (double *)pb->qoi_hist.p;
+    // weight windows: split progeny of a chunk go to the split bank and are
+    // tracked after its census steps
+    SplitBank SB[2]{};
+    if (WW && (rc = split_prepare(pb, C, SB))) return rc;
 
     // the step kernels never read the seed or the history count
     RunArgs Rs = R;
@@ -750,33 +809,33 @@ int run_event(mcdc_problem *pb, const RunArgs &R0, uint64_t first, uint64_t coun
         const Bank &nxt = L.bank[par ^ 1];
         pr.begin(MCDC_PROF_ADVANCE);
         hipLaunchKernelGGL((k_advance<FM, WW, true>), dim3(G), dim3(kBlock), shmem, s, P, Rs, cur, nxt, L.ctl, par,
-                           (const uint32_t *)nullptr, 0, L.sq, L.cq, gn);
+                           (const uint32_t *)nullptr, 0, L.sq, L.cq, gn, SB[0]);
         pr.end();
         pr.begin(MCDC_PROF_SURFACE);
         hipLaunchKernelGGL((k_surface<FM, WW>), dim3(G), dim3(kBlock), 0, s, P, Rs, cur, L.ctl,
-                           (const uint32_t *)L.sq, L.aq[0], 0);
+                           (const uint32_t *)L.sq, L.aq[0], 0, SB[0]);
         pr.end();
         pr.begin(MCDC_PROF_COLLISION);
         hipLaunchKernelGGL((k_collision<FM, WW>), dim3(G), dim3(kBlock), 0, s, P, Rs, cur, L.ctl,
-                           (const uint32_t *)L.cq, L.aq[0], 0);
+                           (const uint32_t *)L.cq, L.aq[0], 0, SB[0]);
         pr.end();
         for (int j = 1; j < iters; ++j) {
             pr.begin(MCDC_PROF_ADVANCE_Q);
             hipLaunchKernelGGL((k_advance<FM, WW, false>), dim3(G), dim3(kBlock), shmem, s, P, Rs, cur, nxt, L.ctl,
-                               par, (const uint32_t *)L.aq[(j - 1) & 1], j, L.sq, L.cq, gn);
+                               par, (const uint32_t *)L.aq[(j - 1) & 1], j, L.sq, L.cq, gn, SB[0]);
             pr.end();
             pr.begin(MCDC_PROF_SURFACE);
             hipLaunchKernelGGL((k_surface<FM, WW>), dim3(G), dim3(kBlock), 0, s, P, Rs, cur, L.ctl,
-                               (const uint32_t *)L.sq, L.aq[j & 1], j);
+                               (const uint32_t *)L.sq, L.aq[j & 1], j, SB[0]);
             pr.end();
             pr.begin(MCDC_PROF_COLLISION);
             hipLaunchKernelGGL((k_collision<FM, WW>), dim3(G), dim3(kBlock), 0, s, P, Rs, cur, L.ctl,
-                               (const uint32_t *)L.cq, L.aq[j & 1], j);
+                               (const uint32_t *)L.cq, L.aq[j & 1], j, SB[0]);
             pr.end();
         }
         pr.begin(MCDC_PROF_FINISH);
         hipLaunchKernelGGL((k_finish<FM, WW>), dim3(G), dim3(kBlock), shmem, s, P, Rs, cur, nxt, L.ctl, par,
-                           (const uint32_t *)L.aq[(iters - 1) & 1], iters, gn);
+                           (const uint32_t *)L.aq[(iters - 1) & 1], iters, gn, SB[0]);
         pr.end();
         hipLaunchKernelGGL(k_step_end, dim3(1), dim3(1), 0, s, L.ctl);
     };
@@ -795,6 +854,7 @@ int run_event(mcdc_problem *pb, const RunArgs &R0, uint64_t first, uint64_t coun
         key_add(key, L);
         key_add(key, gn);
         key_add(key, iters);
+        key_add(key, SB[0]);
         if (key != Gr->key) {
             Gr->clear();
             hipError_t e = hipSuccess;
@@ -820,6 +880,7 @@ int run_event(mcdc_problem *pb, const RunArgs &R0, uint64_t first, uint64_t coun
         const uint64_t cfirst = first + c0;
         hipLaunchKernelGGL(k_ctl_init, dim3(1), dim3(1), 0, st, L.ctl, cfirst);
         if (P.qoi_on && (rc = launch_zero(R.qoi_hist, n * sizeof(double), st))) return hip_fail((hipError_t)rc, "zero");
+        if (WW) split_reset(SB, st);
         prof.begin(MCDC_PROF_SOURCE);
         hipLaunchKernelGGL((k_source<FM, WW>), dim3(G), dim3(kBlock), 0, st, P, R, L.bank[0], L.ctl, n);
         prof.end();
@@ -831,10 +892,11 @@ int run_event(mcdc_problem *pb, const RunArgs &R0, uint64_t first, uint64_t coun
                 enqueue_step(step & 1, st, prof);
             }
         }
-        if (P.qoi_on && (rc = launch_qoi_reduce(R.qoi_hist, n, R.qoi_sums, st)))
-            return hip_fail((hipError_t)rc, "detector reduce");
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return hip_fail(e, "event kernel launch");
+        if (WW && (rc = split_generations(pb, R, SB, cfirst, st, prof))) return rc;
+        if (P.qoi_on && (rc = launch_qoi_reduce(R.qoi_hist, n, R.qoi_sums, st)))
+            return hip_fail((hipError_t)rc, "detector reduce");
     }
     return MCDC_OK;
 }
@@ -858,8 +920,9 @@ int launch_event(mcdc_problem *p, const RunArgs &R, uint64_t first, uint64_t cou
         return MCDC_E_UNSUPPORTED;
     }
     if (P.ww_center != nullptr) {
-        set_error("weight windows run with the history-based algorithm");
-        return MCDC_E_UNSUPPORTED;
+        if (P.finite_mask == 1) return run_event<1, true>(p, R, first, count, opt, st, prof);
+        if (P.finite_mask == 7) return run_event<7, true>(p, R, first, count, opt, st, prof);
+        return run_event<0, true>(p, R, first, count, opt, st, prof);
     }
     if (P.finite_mask == 1) return run_event<1, false>(p, R, first, count, opt, st, prof);
     if (P.finite_mask == 7) return run_event<7, false>(p, R, first, count, opt, st, prof);

@@ -225,6 +225,32 @@ void launch_main(const DevProblem &P, const RunArgs &R, uint64_t first, uint64_t
                        chunk_first, SB);
 }
 
+// Split progeny of one chunk, generation by generation, until none are left
+// (the count of each generation is read back to size the next launch).
+template <int FM>
+int run_generations(const DevProblem &P, const RunArgs &R, SplitBank SB[2], uint64_t cfirst, hipStream_t st,
+                    Profiler &prof) {
+    for (int gen = 0;; ++gen) {
+        unsigned int n_in = 0;
+        hipError_t e = hipMemcpyAsync(&n_in, SB[gen & 1].count, sizeof(unsigned int), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return hip_fail(e, "split count");
+        if (n_in == 0) return MCDC_OK;
+        if (n_in > SB[gen & 1].cap || gen > 10000) {
+            set_error("split bank overflow (weight windows split too many particles)");
+            return MCDC_E_OVERFLOW;
+        }
+        const SplitBank &in = SB[gen & 1], &out = SB[(gen + 1) & 1];
+        hipLaunchKernelGGL(k_zero_count, dim3(1), dim3(1), 0, st, out.count);
+        prof.begin(MCDC_PROF_HISTORY);
+        hipLaunchKernelGGL(k_history_children<FM>, dim3((n_in + 255) / 256), dim3(256), 0, st, P, R, in, n_in,
+                           cfirst, out);
+        prof.end();
+        e = hipGetLastError();
+        if (e != hipSuccess) return hip_fail(e, "history children launch");
+    }
+}
+
 template <int FM>
 int run_history(mcdc_problem *pb, const RunArgs &R0, uint64_t first, uint64_t count, hipStream_t st,
                 Profiler &prof) {
@@ -237,12 +263,7 @@ int run_history(mcdc_problem *pb, const RunArgs &R0, uint64_t first, uint64_t co
     SplitBank SB[2]{};
     int rc;
     if (ww) {
-        const unsigned int cap = (unsigned int)((chunk < (1u << 20)) ? (1u << 20) : chunk);
-        if ((rc = ensure(pb->split, 2 * split_bytes(cap) + 256))) return rc;
-        if ((rc = ensure(pb->counters_split, 2 * sizeof(unsigned int)))) return rc;
-        unsigned int *cnt = (unsigned int *)pb->counters_split.p;
-        SB[0] = carve_split(pb->split.p, cap, cnt);
-        SB[1] = carve_split((char *)pb->split.p + split_bytes(cap), cap, cnt + 1);
+        if ((rc = split_prepare(pb, chunk, SB))) return rc;
         if (P.qoi_on) {
             if ((rc = ensure(pb->qoi_hist, chunk * sizeof(double)))) return rc;
             R.qoi_hist = (double *)pb->qoi_hist.p;
@@ -251,7 +272,7 @@ int run_history(mcdc_problem *pb, const RunArgs &R0, uint64_t first, uint64_t co
     for (uint64_t c0 = 0; c0 < count; c0 += chunk) {
         const uint64_t n = (count - c0 < chunk) ? count - c0 : chunk;
         const uint64_t cfirst = first + c0;
-        if (ww) hipLaunchKernelGGL(k_zero_count, dim3(1), dim3(1), 0, st, SB[0].count);
+        if (ww) split_reset(SB, st);
         prof.begin(MCDC_PROF_HISTORY);
         if (ww)
             launch_main<FM, true>(P, R, cfirst, n, cfirst, SB[0], st);
@@ -261,26 +282,7 @@ int run_history(mcdc_problem *pb, const RunArgs &R0, uint64_t first, uint64_t co
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return hip_fail(e, "history kernel launch");
         if (!ww) continue;
-        // generations of split progeny
-        for (int gen = 0;; ++gen) {
-            unsigned int n_in = 0;
-            e = hipMemcpyAsync(&n_in, SB[gen & 1].count, sizeof(unsigned int), hipMemcpyDeviceToHost, st);
-            if (e == hipSuccess) e = hipStreamSynchronize(st);
-            if (e != hipSuccess) return hip_fail(e, "split count");
-            if (n_in == 0) break;
-            if (n_in > SB[gen & 1].cap || gen > 10000) {
-                set_error("split bank overflow (weight windows split too many particles)");
-                return MCDC_E_OVERFLOW;
-            }
-            const SplitBank &in = SB[gen & 1], &out = SB[(gen + 1) & 1];
-            hipLaunchKernelGGL(k_zero_count, dim3(1), dim3(1), 0, st, out.count);
-            prof.begin(MCDC_PROF_HISTORY);
-            hipLaunchKernelGGL(k_history_children<FM>, dim3((n_in + 255) / 256), dim3(256), 0, st, P, R, in,
-                               n_in, cfirst, out);
-            prof.end();
-            e = hipGetLastError();
-            if (e != hipSuccess) return hip_fail(e, "history children launch");
-        }
+        if ((rc = run_generations<FM>(P, R, SB, cfirst, st, prof))) return rc;
         if (P.qoi_on && (rc = launch_qoi_reduce(R.qoi_hist, n, R.qoi_sums, st)))
             return hip_fail((hipError_t)rc, "detector reduce");
     }
@@ -394,6 +396,29 @@ int launch_batched(const BatchItem *items, const uint64_t *offs, int n_items, ui
     if (finite_mask == 7) return launch_batched_fm<7>(items, offs, n_items, total, next, block, per_thread, st);
     if (finite_mask == 1) return launch_batched_fm<1>(items, offs, n_items, total, next, block, per_thread, st);
     return launch_batched_fm<0>(items, offs, n_items, total, next, block, per_thread, st);
+}
+
+int split_prepare(mcdc_problem *pb, uint64_t chunk, dev::SplitBank SB[2]) {
+    const unsigned int cap = (unsigned int)((chunk < (1u << 20)) ? (1u << 20) : chunk);
+    int rc;
+    if ((rc = ensure(pb->split, 2 * split_bytes(cap) + 256))) return rc;
+    if ((rc = ensure(pb->counters_split, 2 * sizeof(unsigned int)))) return rc;
+    unsigned int *cnt = (unsigned int *)pb->counters_split.p;
+    SB[0] = carve_split(pb->split.p, cap, cnt);
+    SB[1] = carve_split((char *)pb->split.p + split_bytes(cap), cap, cnt + 1);
+    return MCDC_OK;
+}
+
+void split_reset(const dev::SplitBank SB[2], hipStream_t st) {
+    hipLaunchKernelGGL(k_zero_count, dim3(1), dim3(1), 0, st, SB[0].count);
+}
+
+int split_generations(mcdc_problem *pb, const RunArgs &R, dev::SplitBank SB[2], uint64_t cfirst, hipStream_t st,
+                      Profiler &prof) {
+    const int fm = pb->d.finite_mask;
+    if (fm == 1) return run_generations<1>(pb->d, R, SB, cfirst, st, prof);
+    if (fm == 7) return run_generations<7>(pb->d, R, SB, cfirst, st, prof);
+    return run_generations<0>(pb->d, R, SB, cfirst, st, prof);
 }
 
 int launch_history(mcdc_problem *p, const RunArgs &R, uint64_t first, uint64_t count, int block, hipStream_t st,

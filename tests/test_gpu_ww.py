@@ -7,7 +7,7 @@ import workloads as w
 from gpu_common import compare_full
 from ww_tables import flux_table
 
-WW_ALGS = ["history"]
+WW_ALGS = ["history", "event"]
 
 
 @pytest.mark.gpu
@@ -42,7 +42,8 @@ def test_ww_parity_pulse_census_checks(alg):
 
 
 @pytest.mark.gpu
-def test_ww_overflow_reported():
+@pytest.mark.parametrize("alg", WW_ALGS)
+def test_ww_overflow_reported(alg):
     """A tiny split limit per particle cannot overflow; an impossible table
     (every cell asks for heavy splitting) runs to completion or reports
     MCDC_E_OVERFLOW, never corrupts memory."""
@@ -53,9 +54,32 @@ def test_ww_overflow_reported():
     h = m.mcdc_problem_create(p)
     try:
         m.mcdc_set_weight_windows(h, table, 5.0, 2)
-        out = m.mcdc_run(h, 2000, 3, algorithm="history")
+        print(f"[ww] heavy splitting alg={alg}", flush=True)
+        out = m.mcdc_run(h, 2000, 3, algorithm=alg)
         assert out["splits"] > 0
     except m.MCDCError as e:
         assert e.code == -4
     finally:
         h.close()
+
+
+@pytest.mark.gpu
+def test_ww_forms_agree_at_full_size():
+    """Windowed runs of the two forms, 1e6 histories of the dog-leg duct:
+    the same counts, splits and detector sums."""
+    import paper_2305_07636_amd as m
+    from gpu_common import close
+
+    p = w.cfg5_dogleg(detector=w.LEG_A_DETECTOR)
+    table = flux_table(p, floor=1e-3)
+    h = m.mcdc_problem_create(p)
+    try:
+        m.mcdc_set_weight_windows(h, table, 5.0, 16)
+        a = m.mcdc_run(h, 1_000_000, 12, algorithm="history")
+        b = m.mcdc_run(h, 1_000_000, 12, algorithm="event")
+    finally:
+        h.close()
+    assert np.array_equal(a["events"], b["events"]) and np.array_equal(a["terms"], b["terms"])
+    assert a["splits"] == b["splits"] > 0
+    close(np.array(b["qoi_sum"]), np.array(a["qoi_sum"]))
+    close(b["mean"].cpu().numpy(), a["mean"].cpu().numpy())
