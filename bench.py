@@ -27,6 +27,9 @@ METRIC = "histories/sec + figure of merit 1/(σ²T), plain analog vs learned-WW,
 WORKLOAD = ("pulsed slab: 1 group, Sigma_t=1, c=0.9, v=1, 40 mfp, isotropic centre pulse at t=0, "
             "50 x-bins x 100 time bins on [0,20], 1e7 histories, FP64")
 HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_advance_pulsed_slab_1e7_traffic.json")
+KERNEL_SOURCES = ["paper_2305_07636_amd/csrc/k_event.hip", "paper_2305_07636_amd/csrc/k_common.hpp",
+                  "paper_2305_07636_amd/csrc/mcdc_internal.hpp", "paper_2305_07636_amd/build.py"]
 T_START = time.perf_counter()
 
 
@@ -76,6 +79,29 @@ def cpu_baseline(N, seed, target_s=15.0):
                   f"contiguous histories, serial C oracle (gcc -O2, no contraction), wall {wall:.1f} s",
         "single_core_histories_per_s": rate1,
     }
+
+
+def kernel_source_hash():
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per k_advance launch from the committed FETCH_SIZE /
+    WRITE_SIZE summary, or None if the kernel sources changed since."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_sha256") != kernel_source_hash():
+        return None
+    return rec
 
 
 def batched_section(m, w):
@@ -161,7 +187,6 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--algorithm", default="event", choices=["event", "history"])
     ap.add_argument("--histories", type=float, default=1e7)
-    ap.add_argument("--event-iters", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-history-form", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
@@ -205,9 +230,9 @@ def main():
     p = m.mcdc_problem_create(prob)
     outs = ("mean", "var")
 
-    def step(alg, s, profile=None, classes=None):
+    def step(alg, s, profile=None, classes=None, every=0, phase=0):
         return m.mcdc_run(p, N, seed + s, algorithm=alg, outputs=outs, profile=profile,
-                          profile_classes=classes, event_iters=args.event_iters)
+                          profile_classes=classes, profile_every=every, profile_phase=phase)
 
     log("problem on the GPU")
     names = m._binding.PROF_CLASSES
@@ -224,7 +249,9 @@ def main():
     prof = np.zeros((len(names), 4))
     t0 = time.perf_counter()
     for s in range(args.steps):
-        last = step(args.algorithm, s, profile=prof, classes=[names[cls]])
+        # timed step s brackets census steps k = s mod K_timed: over the timed
+        # region every census step is timed once
+        last = step(args.algorithm, s, profile=prof, classes=[names[cls]], every=args.steps, phase=s)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     value = N * args.steps / elapsed
@@ -232,11 +259,18 @@ def main():
     ms, launches, items, nbytes = prof[cls]
     if args.algorithm == "event":
         achieved = nbytes / (ms * 1e-3) / 1e9
+        tr = measured_traffic() if names[cls] == "advance" and N == 10_000_000 else None
         roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": f"k_{names[cls]}",
+                    "frac": achieved / HBM_PEAK_GBS,
+                    "traffic": tr["hbm_bytes_per_launch"] if tr else None,
+                    "kernel": f"k_{names[cls]}",
                     "launches": int(launches), "avg_launch_ms": ms / launches,
                     "algorithmic_bytes_per_launch": nbytes / launches,
-                    "particles_per_launch": items / launches}
+                    "particles_per_launch": items / launches,
+                    "timed_launches": f"timed step s brackets census steps k = s mod {args.steps} with HIP "
+                                      f"events on the library's stream (each census step once)"}
+        if tr:
+            roofline["traffic_source"] = os.path.relpath(TRAFFIC_FILE, ROOT)
     else:
         # history form: state in registers; bounded by FP64 vector ALU and
         # divergence, reported as events per second against the FP64 rate

@@ -135,14 +135,11 @@ typedef struct {
 /*
  * Run options (all-zero = defaults).
  *  algorithm      MCDC_ALG_EVENT (default) or MCDC_ALG_HISTORY.
- *  block_size     history form: threads per block, 0 = tuned default (64..1024,
- *                 multiple of 64).  The event form always uses 256.
+ *  block_size     mcdc_run_batched: threads per block of the persistent
+ *                 launch (64..1024, multiple of 64; 0 = autotuned).  The
+ *                 kernels of mcdc_run use 256 in both forms.
  *  bank_capacity  event form: particles resident at once (0 = auto).  Work
  *                 is processed in chunks of this many histories.
- *  event_iters    event form: queue iterations (advance, then the surface
- *                 and collision kernels) per census step before the
- *                 particles still in flight are finished by one in-register
- *                 pass that takes each to its census or death (0 = auto: 1).
  *  flags          bit 0 (MCDC_FLAG_EAGER): launch the event form's census
  *                 steps one kernel at a time instead of replaying the
  *                 captured step graphs (graphs are also skipped when a
@@ -163,32 +160,38 @@ typedef struct {
  *  profile_mask   bit c set: bracket launches of class c with events
  *                 (0 = all classes); particle and byte counts are always
  *                 gathered for every class when profile is given.
+ *  profile_every, profile_phase
+ *                 event form, with profile: time and count only the census
+ *                 steps k with k mod profile_every == profile_phase mod
+ *                 profile_every (profile_every 0 or 1 = every step); those
+ *                 launch one kernel at a time, the others replay the
+ *                 captured step graphs uninstrumented.  Runs with phases
+ *                 0 .. profile_every-1 together sample every step once.
  *  segments       event form: bank segments, one per workgroup of every
- *                 event kernel (0 = auto: as many workgroups of the advance
- *                 kernel as the GPU holds resident at once, so each census
- *                 pass runs in a single round).  Results do not depend on it.
+ *                 event kernel (0 = auto: 4 per compute unit, or fewer if
+ *                 the advance kernel cannot hold that many resident).
+ *                 Results do not depend on it beyond summation order.
  */
 #define MCDC_FLAG_EAGER 1
-#define MCDC_PROF_CLASSES 8
-#define MCDC_PROF_SOURCE 0
-#define MCDC_PROF_ADVANCE 1    /* advance over the dense census bank */
-#define MCDC_PROF_ADVANCE_Q 2  /* advance over the active queue */
-#define MCDC_PROF_SURFACE 3
-#define MCDC_PROF_COLLISION 4
-#define MCDC_PROF_FINISH 5
-#define MCDC_PROF_HISTORY 6
-#define MCDC_PROF_OTHER 7      /* fills, control, batch statistics */
+#define MCDC_PROF_CLASSES 6
+#define MCDC_PROF_SOURCE 0     /* event form: source sampling */
+#define MCDC_PROF_ADVANCE 1    /* event form: one flight over the census bank */
+#define MCDC_PROF_SURFACE 2    /* event form: surface queue, then on to census */
+#define MCDC_PROF_COLLISION 3  /* event form: collision queue, then on to census */
+#define MCDC_PROF_HISTORY 4    /* history form (and weight-window progeny) */
+#define MCDC_PROF_OTHER 5      /* fills, control, batch statistics */
 typedef struct {
     int32_t algorithm;
     int32_t block_size;
     int64_t bank_capacity;
-    int32_t event_iters;
     int32_t flags;
     void *stream;
     uint32_t *debug_counts;
     double *debug_scores;
     double *profile;
     uint32_t profile_mask;
+    int32_t profile_every;
+    int32_t profile_phase;
     int32_t segments;
 } mcdc_run_options;
 

@@ -54,13 +54,14 @@ class mcdc_problem_desc(C.Structure):
 class mcdc_run_options(C.Structure):
     _fields_ = [
         ("algorithm", C.c_int32), ("block_size", C.c_int32), ("bank_capacity", C.c_int64),
-        ("event_iters", C.c_int32), ("flags", C.c_int32), ("stream", C.c_void_p),
+        ("flags", C.c_int32), ("stream", C.c_void_p),
         ("debug_counts", C.c_void_p), ("debug_scores", C.c_void_p),
-        ("profile", C.c_void_p), ("profile_mask", C.c_uint32), ("segments", C.c_int32),
+        ("profile", C.c_void_p), ("profile_mask", C.c_uint32), ("profile_every", C.c_int32), ("profile_phase", C.c_int32),
+        ("segments", C.c_int32),
     ]
 
 
-PROF_CLASSES = ["source", "advance", "advance_q", "surface", "collision", "finish", "history", "other"]
+PROF_CLASSES = ["source", "advance", "surface", "collision", "history", "other"]
 
 
 class mcdc_result(C.Structure):
@@ -226,9 +227,10 @@ def mcdc_set_weight_windows(p: Problem, centers, ratio: float = 5.0, max_split: 
 
 
 def mcdc_run(p: Problem, n_histories: int, seed: int, algorithm: str = "event",
-             block_size: int = 0, bank_capacity: int = 0, event_iters: int = 0, segments: int = 0,
+             block_size: int = 0, bank_capacity: int = 0, segments: int = 0,
              debug: bool = False, outputs=("mean", "var", "raw", "leak_mean", "leak_var"),
-             profile=None, eager: bool = False, profile_classes=None):
+             profile=None, eager: bool = False, profile_classes=None, profile_every: int = 0,
+             profile_phase: int = 0):
     """Run n_histories through the GPU tracker.  Returns a dict of torch
     CUDA tensors (mean, var, raw [K, G, nz, ny, nx]; leak_mean, leak_var
     [K, G, 6]; debug_counts [N, 5] and debug_scores [N, 2] if debug) plus
@@ -254,7 +256,6 @@ def mcdc_run(p: Problem, n_histories: int, seed: int, algorithm: str = "event",
     opt.algorithm = MCDC_ALG_HISTORY if algorithm == "history" else MCDC_ALG_EVENT
     opt.block_size = block_size
     opt.bank_capacity = bank_capacity
-    opt.event_iters = event_iters
     opt.segments = segments
     opt.flags = 1 if eager else 0
     opt.stream = torch.cuda.current_stream(dev).cuda_stream
@@ -271,6 +272,8 @@ def mcdc_run(p: Problem, n_histories: int, seed: int, algorithm: str = "event",
         opt.profile = profile.ctypes.data
         if profile_classes:
             opt.profile_mask = sum(1 << PROF_CLASSES.index(c) for c in profile_classes)
+        opt.profile_every = profile_every
+        opt.profile_phase = profile_phase
     _check(lib().mcdc_run(p.handle, int(n_histories), int(seed), C.byref(opt), C.byref(res)))
     out["events"] = np.array(res.n_events[:], dtype=np.uint64)
     out["terms"] = np.array(res.n_term[:], dtype=np.uint64)

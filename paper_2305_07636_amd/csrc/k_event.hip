@@ -1,30 +1,31 @@
 // Event-based tracking (the second algorithm mode the paper names, Section 2;
 // it gives no design).  Particles live in structure-of-arrays banks in HBM
-// and advance one event per kernel pass; after each pass they are sorted
-// into per-event queues (census, surface, collision) built from wavefront
-// ballots and mbcnt prefix counts.
+// and are sorted after every flight into per-event queues (census, surface,
+// collision) built from wavefront ballots and mbcnt prefix counts.
 //
-// Segment-private pipelines.  The bank, and every queue, is cut into G
-// segments of L slots, one per workgroup: workgroup b of every kernel works
-// only on segment b, and a particle never leaves the segment it was born in.
-// Queue appends therefore need no device-wide atomics (one LDS atomic per
-// wave, no contention across the 8 XCDs), the dense census bank stays
-// contiguous per segment, and each segment holds a contiguous range of
-// histories, so its particles belong to at most two tally batches.
+// Segment-private pipelines.  Every bank is cut into G segments of L slots,
+// one per workgroup: workgroup b of every kernel works only on segment b,
+// and a particle never leaves the segment it was born in.  Queue appends
+// therefore need no device-wide atomics (one LDS atomic per wave, no
+// contention across the 8 XCDs), and each segment holds a contiguous range
+// of histories, so its particles belong to at most two tally batches.
+//
+// Dense queues.  A queue is not a list of slot indices into a big bank (that
+// turns every later read into a sparse gather that pulls whole cache lines
+// for a few bytes): a particle filed into a queue is written whole and
+// contiguously.  The census queue is the next step's bank; the surface and
+// collision queues share one event bank, surface particles filling each
+// segment from the front and collision particles from the back.
 //
 // Time is advanced census step by census step (the census grid is the tally
 // time grid, Section 3).  One step is a fixed kernel sequence, captured once
 // as a graph and replayed:
-//   advance(dense bank) -> surface(queue) -> collision(queue)
-//   [advance(active queue) -> surface -> collision] x (iters - 1)
-//   finish(active queue) -> step end
+//   advance(bank) -> surface(event bank front) -> collision(event bank back)
 // advance moves each particle to its next event, scores the track-length
-// tally and files it: census crossers are copied whole into the next step's
-// bank segment, surface and collision particles stay in place and their
-// slots go to the surface / collision queues; the surface and collision
-// kernels append survivors to the active queue.  finish takes the few
-// particles still in flight after the last iteration to their census or
-// death in registers, so no step needs an unbounded number of passes.
+// tally and files it.  The surface and collision kernels each apply their
+// queue's event to a homogeneous set of particles, then take the survivors
+// on to their census or death in registers (the few further events of the
+// step), filing census crossers into the next bank.
 //
 // Tally: every particle scored in step k lies in time bin k, so a
 // workgroup touches only the slice [2 batches][G][nts] of the step; when that
@@ -40,24 +41,23 @@ namespace {
 using namespace dev;
 
 constexpr int kBlock = 256;
-constexpr int kMaxIters = 16;
-constexpr int kLdsTallyMax = 4096;   // doubles (32 KB)
+constexpr int kLdsTallyMax = 4096;          // doubles (32 KB)
+constexpr uint32_t kHidMask = 0x0FFFFFFFu;  // history index within a chunk (< 2^28)
 
 struct Bank {
     double *x[3], *u[3], *t, *tau, *w;
     uint64_t *s;
     uint32_t *ixyz;   // ix | iy << 11 | iz << 22
     uint32_t *gk;     // g | batch << 5 | k << 15
-    uint32_t *hid;    // history index within the chunk
+    uint32_t *hid;    // history index within the chunk | crossing axes << 29 (surface queue)
 };
 
 // Per-segment fill counts of the banks and queues, plus the step index.
 // Only workgroup b reads or writes the entries of segment b.
 struct Ctl {
     unsigned int *n_bank;   // [2][G] particles in each segment of bank 0 / 1
-    unsigned int *n_s;      // [kMaxIters][G] surface queue fill per iteration
-    unsigned int *n_c;      // [kMaxIters][G] collision queue fill
-    unsigned int *n_a;      // [kMaxIters][G] active queue fill
+    unsigned int *n_s;      // [G] surface particles at the front of the event bank segment
+    unsigned int *n_c;      // [G] collision particles at its back
     int *seg_b0;            // [G] batch of the segment's first history
     int *step;              // current census step
     uint64_t *first;        // global index of the chunk's first history
@@ -81,67 +81,63 @@ __device__ __forceinline__ uint32_t block_append(bool pred, unsigned int *cnt) {
     if (mask) {
         const int leader = __ffsll((unsigned long long)mask) - 1;
         if ((int)__lane_id() == leader) base = atomicAdd(cnt, (unsigned int)__popcll(mask));
-        base = __shfl(base, leader);
+        base = __builtin_amdgcn_readlane(base, leader);
     }
     return base + prefix;
 }
 
-// Per-workgroup event / termination counters and profile tallies (particles
-// processed, algorithmic bytes requested), flushed once per workgroup.
-// Profile tallies are kept per thread in registers and summed per wave and
-// workgroup only at the end of the kernel.
+// Event / termination counters and profile tallies (particles processed,
+// algorithmic bytes requested), kept per thread in registers (every index
+// is a compile-time constant) and reduced per wave, then per workgroup in
+// LDS, only at the end of the kernel.
 struct Counters {
     unsigned int c[kCounters];
     unsigned long long items, bytes;
-    __device__ void init() {
-        if (threadIdx.x < kCounters) c[threadIdx.x] = 0u;
-        if (threadIdx.x == 0) items = bytes = 0ull;
+    __device__ __forceinline__ void init(unsigned long long *red) {
+#pragma unroll
+        for (int j = 0; j < kCounters; ++j) c[j] = 0u;
+        items = bytes = 0ull;
+        if (threadIdx.x < kCounters + 2) red[threadIdx.x] = 0ull;
     }
-    __device__ void add(int j, unsigned int v = 1u) {
-        if (v) atomicAdd(&c[j], v);
+    __device__ __forceinline__ void add(int j, unsigned int v = 1u) { c[j] += v; }
+    __device__ __forceinline__ void prof(unsigned int n_items, unsigned int n_bytes) {
+        items += n_items;
+        bytes += n_bytes;
     }
-    // flush: barrier, then counters and the per-thread profile tallies
-    __device__ void flush(const RunArgs &R, int cls, unsigned long long t_items, unsigned long long t_bytes) {
+    // flush: barrier, then one global atomic per nonzero counter per workgroup
+    __device__ void flush(const RunArgs &R, int cls, unsigned long long *red) {
+#pragma unroll
+        for (int j = 0; j < kCounters; ++j) {
+            unsigned int v = c[j];
+            for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+            if (__lane_id() == 0 && v) atomicAdd(&red[j], (unsigned long long)v);
+        }
         if (R.prof) {
+            unsigned long long a = items, b = bytes;
             for (int o = 32; o > 0; o >>= 1) {
-                t_items += __shfl_xor(t_items, o);
-                t_bytes += __shfl_xor(t_bytes, o);
+                a += __shfl_xor(a, o);
+                b += __shfl_xor(b, o);
             }
             if (__lane_id() == 0) {
-                atomicAdd(&items, t_items);
-                atomicAdd(&bytes, t_bytes);
+                atomicAdd(&red[kCounters], a);
+                atomicAdd(&red[kCounters + 1], b);
             }
         }
         __syncthreads();
-        if (threadIdx.x < kCounters && c[threadIdx.x])
-            atomicAdd(R.counters + threadIdx.x, (unsigned long long)c[threadIdx.x]);
+        if (threadIdx.x < kCounters && red[threadIdx.x]) atomicAdd(R.counters + threadIdx.x, red[threadIdx.x]);
         if (R.prof && threadIdx.x == 0) {
-            atomicAdd(R.prof + 2 * cls, items);
-            atomicAdd(R.prof + 2 * cls + 1, bytes);
+            atomicAdd(R.prof + 2 * cls, red[kCounters]);
+            atomicAdd(R.prof + 2 * cls + 1, red[kCounters + 1]);
         }
     }
 };
 
-// Bytes of the particle state as the kernels move it (finite axes only).
-template <int FM>
-__device__ __forceinline__ unsigned int nfinite(const DevProblem &P) {
-    return (unsigned int)__popc((unsigned int)(FM ? FM : P.finite_mask));
-}
-// load_state: x, u per finite axis, t, tau, (w), cell, g/k
-template <int FM, bool WW>
-__device__ __forceinline__ unsigned int load_bytes(const DevProblem &P) {
-    return 16u * nfinite<FM>(P) + 24u + (WW ? 8u : 0u);
-}
-// store_state: the whole particle (load_state fields + RNG state + history)
+// Bytes of one particle's state as the kernels move it (finite axes only):
+// x, u per finite axis, t, tau, (w), RNG state, cell, g/batch/k, history.
 template <int FM, bool WW>
 __device__ __forceinline__ unsigned int state_bytes(const DevProblem &P) {
-    return load_bytes<FM, WW>(P) + 12u;
-}
-
-__device__ __forceinline__ void tprof(unsigned long long &items, unsigned long long &bytes, unsigned int n_items,
-                                      unsigned int n_bytes) {
-    items += n_items;
-    bytes += n_bytes;
+    const unsigned int nf = (unsigned int)__popc((unsigned int)(FM ? FM : P.finite_mask));
+    return 16u * nf + 36u + (WW ? 8u : 0u);
 }
 
 __device__ __forceinline__ void hist_event(const RunArgs &R, uint64_t i, int e) {
@@ -153,33 +149,35 @@ __device__ __forceinline__ void hist_term(const RunArgs &R, uint64_t i, int code
 
 template <int FM, bool WW>
 __device__ __forceinline__ void load_state(const DevProblem &P, const Bank &B, uint32_t slot, Particle &p,
-                                           uint32_t &gk) {
+                                           uint32_t &gk, uint32_t &hidw) {
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         if (finite_axis<FM>(P, a)) {
             p.x[a] = B.x[a][slot];
             p.u[a] = B.u[a][slot];
-        } else if (WW) {
-            p.x[a] = 0.0;   // copied to split progeny; never used in flight
+        } else {
+            p.x[a] = 0.0;   // stays 0 in flight; copied whole to split progeny
             p.u[a] = 0.0;
         }
     }
-    set_inverse<FM>(P, p);
     p.t = B.t[slot];
     p.tau = B.tau[slot];
     p.w = WW ? B.w[slot] : 1.0;
+    p.s = B.s[slot];
     const uint32_t c = B.ixyz[slot];
+    gk = B.gk[slot];
+    hidw = B.hid[slot];
+    set_inverse<FM>(P, p);
     p.ix[0] = c & 2047u;
     p.ix[1] = (c >> 11) & 2047u;
     p.ix[2] = c >> 22;
-    gk = B.gk[slot];
     p.g = gk & 31u;
     p.k = gk >> 15;
 }
 
 template <int FM, bool WW>
 __device__ __forceinline__ void store_state(const DevProblem &P, const Bank &B, uint32_t slot,
-                                            const Particle &p, uint32_t gk, uint32_t hid) {
+                                            const Particle &p, uint32_t gk, uint32_t hidw) {
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         if (finite_axis<FM>(P, a)) {
@@ -193,7 +191,11 @@ __device__ __forceinline__ void store_state(const DevProblem &P, const Bank &B, 
     B.s[slot] = p.s;
     B.ixyz[slot] = pack_ix(p.ix);
     B.gk[slot] = gk;
-    B.hid[slot] = hid;
+    B.hid[slot] = hidw;
+}
+
+__device__ __forceinline__ uint32_t with_gk(uint32_t gk, const Particle &p) {
+    return (uint32_t)p.g | (gk & (1023u << 5)) | ((uint32_t)p.k << 15);
 }
 
 // Weight-window check point of the event kernels: roulette (returns false)
@@ -215,10 +217,6 @@ __device__ __forceinline__ bool ww_point(const DevProblem &P, const RunArgs &R, 
         if (R.dbg_counts) atomicAdd(R.dbg_counts + i * 5 + 3, (unsigned int)nc);
     }
     return true;
-}
-
-__device__ __forceinline__ uint32_t with_gk(uint32_t gk, const Particle &p) {
-    return (uint32_t)p.g | (gk & (1023u << 5)) | ((uint32_t)p.k << 15);
 }
 
 // Track-length score of one flight: into the workgroup's LDS slice when the
@@ -261,15 +259,30 @@ __device__ __forceinline__ void flush_slice(const DevProblem &P, const RunArgs &
     }
 }
 
+// Score one flight (tally bin and detector) before the move.
+__device__ __forceinline__ void score_flight(const DevProblem &P, const RunArgs &R, StepScore &sc, const Particle &p,
+                                             int cell, int b, uint64_t i, uint32_t hid, double d) {
+    const double v = p.w * d;
+    const int tb = P.cell_tal[cell];
+    if (tb >= 0) {
+        sc.add(P, R, b, p.g, p.k, tb, v);
+        if (R.dbg_scores) atomic_add_f64(R.dbg_scores + i * 2, v);
+    }
+    if (P.qoi_on && P.cell_qoi[cell] && P.qoi_groups[p.g]) {
+        atomic_add_f64(R.qoi_hist + hid, v);
+        if (R.dbg_scores) atomic_add_f64(R.dbg_scores + i * 2 + 1, v);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // source: workgroup b samples histories [b L, (b + 1) L) of the chunk
 // ---------------------------------------------------------------------------
 template <int FM, bool WW, int CLS = MCDC_PROF_SOURCE>
 __global__ void __launch_bounds__(kBlock) k_source(DevProblem P, RunArgs R, Bank bank, Ctl C, uint64_t count) {
-    __shared__ Counters cnt;
+    __shared__ unsigned long long red[kCounters + 2];
+    Counters cnt;
     __shared__ unsigned int cN;
-    cnt.init();
-    unsigned long long p_items = 0, p_bytes = 0;
+    cnt.init(red);
     if (threadIdx.x == 0) cN = 0u;
     const uint64_t first = *C.first;
     const unsigned int seg = blockIdx.x;
@@ -296,53 +309,49 @@ __global__ void __launch_bounds__(kBlock) k_source(DevProblem P, RunArgs R, Bank
         }
         const uint32_t off = block_append(valid && alive, &cN);
         if (valid && alive) store_state<FM, WW>(P, bank, seg * C.L + off, p, pack_gk(p.g, b, p.k), (uint32_t)r);
-        if (R.prof) tprof(p_items, p_bytes, valid ? 1u : 0u, (valid && alive) ? state_bytes<FM, WW>(P) : 0u);
+        if (R.prof) cnt.prof(valid ? 1u : 0u, (valid && alive) ? state_bytes<FM, WW>(P) : 0u);
     }
     __syncthreads();
     if (threadIdx.x == 0) C.n_bank[seg] = cN;   // bank 0
-    cnt.flush(R, CLS, p_items, p_bytes);
+    cnt.flush(R, CLS, red);
 }
 
 // ---------------------------------------------------------------------------
-// advance: one flight per particle, score, file into a queue
+// advance: one flight per particle of the bank, score, file into a queue
 // ---------------------------------------------------------------------------
 enum Outcome : int { kNone = 0, kToNext = 1, kToSurface = 2, kToCollision = 3 };
 
-template <int FM, bool WW, bool DENSE, int CLS = DENSE ? MCDC_PROF_ADVANCE : MCDC_PROF_ADVANCE_Q>
-__global__ void __launch_bounds__(kBlock) k_advance(DevProblem P, RunArgs R, Bank cur, Bank next, Ctl C, int par,
-                                                    const uint32_t *__restrict__ aq, int it, uint32_t *sq,
-                                                    uint32_t *cq, int gn, SplitBank SB) {
-    __shared__ Counters cnt;
+template <int FM, bool WW, int CLS = MCDC_PROF_ADVANCE>
+__global__ void __launch_bounds__(kBlock) k_advance(DevProblem P, RunArgs R, Bank cur, Bank next, Bank ev, Ctl C,
+                                                    int par, int gn, SplitBank SB) {
+    __shared__ unsigned long long red[kCounters + 2];
+    Counters cnt;
     __shared__ unsigned int cN, cS, cC;
     extern __shared__ double lt[];
     const unsigned int seg = blockIdx.x;
     const uint32_t seg0 = seg * C.L;
-    const unsigned int n = DENSE ? C.n_bank[par * C.G + seg] : C.n_a[(it - 1) * C.G + seg];
+    const uint32_t seg_end = seg0 + C.L - 1;
+    const unsigned int n = C.n_bank[par * C.G + seg];
     const int step = *C.step;
     const uint64_t first = *C.first;
-    cnt.init();
-    unsigned long long p_items = 0, p_bytes = 0;
+    cnt.init(red);
     if (threadIdx.x == 0) {
-        cN = DENSE ? 0u : C.n_bank[(par ^ 1) * C.G + seg];
+        cN = 0u;
         cS = 0u;
         cC = 0u;
     }
     StepScore sc;
     init_slice(sc, lt, gn, C.seg_b0[seg]);
     __syncthreads();
-    const bool per_hist = WW || (R.dbg_counts != nullptr) || (R.dbg_scores != nullptr) || P.qoi_on;
     for (unsigned int j0 = 0; j0 < n; j0 += kBlock) {
         const unsigned int idx = j0 + threadIdx.x;
         const bool valid = idx < n;
-        const uint32_t slot = valid ? (DENSE ? seg0 + idx : aq[seg0 + idx]) : 0u;
         int outcome = kNone;
         int mask = 0;
-        bool have_s = false;
         Particle p;
         uint32_t gk = 0, hid = 0;
         if (valid) {
-            load_state<FM, WW>(P, cur, slot, p, gk);
-            if (per_hist) hid = cur.hid[slot];
+            load_state<FM, WW>(P, cur, seg0 + idx, p, gk, hid);
             if (p.k > step) {
                 outcome = kToNext;   // born in a later time bin: wait
             } else {
@@ -351,43 +360,29 @@ __global__ void __launch_bounds__(kBlock) k_advance(DevProblem P, RunArgs R, Ban
                 const uint64_t i = first + hid;
                 if (f.d == kInf) {
                     cnt.add(3 + kLost);
-                    if (per_hist) hist_term(R, i, kLost);
+                    hist_term(R, i, kLost);
                 } else {
-                    const double v = p.w * f.d;
-                    const int tb = P.cell_tal[cell];
                     const int b = (gk >> 5) & 1023u;
-                    if (tb >= 0) {
-                        sc.add(P, R, b, p.g, p.k, tb, v);
-                        if (R.dbg_scores) atomic_add_f64(R.dbg_scores + i * 2, v);
-                    }
-                    if (P.qoi_on && P.cell_qoi[cell] && P.qoi_groups[p.g]) {
-                        atomic_add_f64(R.qoi_hist + hid, v);
-                        if (R.dbg_scores) atomic_add_f64(R.dbg_scores + i * 2 + 1, v);
-                    }
+                    score_flight(P, R, sc, p, cell, b, i, hid, f.d);
                     move<FM>(P, p, f);
                     if (f.ev == kCensus) {
                         cnt.add(0);
-                        if (per_hist) hist_event(R, i, 0);
+                        hist_event(R, i, 0);
                         p.k += 1;
                         if (p.k == P.K) {
                             cnt.add(3 + kTime);
-                            if (per_hist) hist_term(R, i, kTime);
-                        } else {
+                            hist_term(R, i, kTime);
+                        } else if (ww_point<WW>(P, R, SB, p, cell, b, i, cnt)) {
                             outcome = kToNext;
-                            if (WW) {
-                                p.s = cur.s[slot];
-                                have_s = true;
-                                if (!ww_point<WW>(P, R, SB, p, cell, b, i, cnt)) outcome = kNone;
-                            }
                         }
                     } else if (f.ev == kSurface) {
                         cnt.add(1);
-                        if (per_hist) hist_event(R, i, 1);
+                        hist_event(R, i, 1);
                         mask = crossing_mask<FM>(P, f);
                         outcome = kToSurface;
                     } else {
                         cnt.add(2);
-                        if (per_hist) hist_event(R, i, 2);
+                        hist_event(R, i, 2);
                         outcome = kToCollision;
                     }
                 }
@@ -396,191 +391,101 @@ __global__ void __launch_bounds__(kBlock) k_advance(DevProblem P, RunArgs R, Ban
         const uint32_t ns = block_append(outcome == kToNext, &cN);
         const uint32_t ss = block_append(outcome == kToSurface, &cS);
         const uint32_t cs = block_append(outcome == kToCollision, &cC);
-        if (outcome == kToNext) {
-            if (!have_s) p.s = cur.s[slot];
-            if (!per_hist) hid = cur.hid[slot];
+        if (outcome == kToNext)
             store_state<FM, WW>(P, next, seg0 + ns, p, with_gk(gk, p), hid);
-        } else if (outcome == kToSurface || outcome == kToCollision) {
-#pragma unroll
-            for (int a = 0; a < 3; ++a)
-                if (finite_axis<FM>(P, a)) cur.x[a][slot] = p.x[a];
-            cur.t[slot] = p.t;
-            cur.tau[slot] = p.tau;
-            if (outcome == kToSurface)
-                sq[seg0 + ss] = slot | ((uint32_t)mask << 29);
-            else
-                cq[seg0 + cs] = slot;
-        }
-        if (R.prof && valid) {
-            unsigned int by = load_bytes<FM, WW>(P) + (DENSE ? 0u : 4u) + (per_hist ? 4u : 0u);
-            if (outcome == kToNext)
-                by += 8u + (per_hist ? 0u : 4u) + state_bytes<FM, WW>(P);
-            else if (outcome != kNone)
-                by += 8u * nfinite<FM>(P) + 16u + 4u;
-            tprof(p_items, p_bytes, 1u, by);
-        }
+        else if (outcome == kToSurface)
+            store_state<FM, WW>(P, ev, seg0 + ss, p, gk, hid | ((uint32_t)mask << 29));
+        else if (outcome == kToCollision)
+            store_state<FM, WW>(P, ev, seg_end - cs, p, gk, hid);
+        if (R.prof && valid)
+            cnt.prof(1u, state_bytes<FM, WW>(P) * (outcome == kNone ? 1u : 2u));
     }
     flush_slice(P, R, sc, step);
     if (threadIdx.x == 0) {
         C.n_bank[(par ^ 1) * C.G + seg] = cN;
-        C.n_s[it * C.G + seg] = cS;
-        C.n_c[it * C.G + seg] = cC;
+        C.n_s[seg] = cS;
+        C.n_c[seg] = cC;
     }
-    cnt.flush(R, CLS, p_items, p_bytes);
+    cnt.flush(R, CLS, red);
 }
 
 // ---------------------------------------------------------------------------
-// surface crossing and boundary conditions
+// surface / collision: apply the queue's event, then the rest of the step
 // ---------------------------------------------------------------------------
-template <int FM, bool WW, int CLS = MCDC_PROF_SURFACE>
-__global__ void __launch_bounds__(kBlock) k_surface(DevProblem P, RunArgs R, Bank cur, Ctl C,
-                                                    const uint32_t *__restrict__ sq, uint32_t *aq_out, int it,
-                                                    SplitBank SB) {
-    __shared__ Counters cnt;
-    __shared__ unsigned int cA;
-    const unsigned int seg = blockIdx.x;
-    const uint32_t seg0 = seg * C.L;
-    const unsigned int n = C.n_s[it * C.G + seg];
-    const uint64_t first = *C.first;
-    cnt.init();
-    unsigned long long p_items = 0, p_bytes = 0;
-    if (threadIdx.x == 0) cA = 0u;
-    __syncthreads();
-    for (unsigned int j0 = 0; j0 < n; j0 += kBlock) {
-        const unsigned int idx = j0 + threadIdx.x;
-        const bool valid = idx < n;
-        bool alive = false;
-        uint32_t slot = 0;
-        int mask = 0;
-        Particle p;
-        if (valid) {
-            const uint32_t e = sq[seg0 + idx];
-            slot = e & 0x1FFFFFFFu;
-            mask = (int)(e >> 29);
-            uint32_t gk;
-            load_state<FM, WW>(P, cur, slot, p, gk);
-            const int old_ww = WW ? P.cell_ww[cell_index(P, p.ix)] : 0;
-            const int face = cross<FM>(P, p, mask);
-            const int b = (gk >> 5) & 1023u;
+// Takes a particle that survived its queued event on to its census (returns
+// true: file it in the next bank) or its death, in registers.  The event
+// cap counts flights from here.
+template <int FM, bool WW>
+__device__ __forceinline__ bool to_census(const DevProblem &P, const RunArgs &R, const SplitBank &SB, StepScore &sc,
+                                          Counters &cnt, Particle &p, int cell, int b, uint64_t i, uint32_t hid) {
+    for (int since = 0;; ++since) {
+        if (since >= kMaxEventsPerStep) {
+            cnt.add(3 + kLost);
+            hist_term(R, i, kLost);
+            return false;
+        }
+        const Flight f = next_event<FM>(P, p, cell);
+        if (f.d == kInf) {
+            cnt.add(3 + kLost);
+            hist_term(R, i, kLost);
+            return false;
+        }
+        score_flight(P, R, sc, p, cell, b, i, hid, f.d);
+        move<FM>(P, p, f);
+        if (f.ev == kCensus) {
+            cnt.add(0);
+            hist_event(R, i, 0);
+            p.k += 1;
+            if (p.k == P.K) {
+                cnt.add(3 + kTime);
+                hist_term(R, i, kTime);
+                return false;
+            }
+            return ww_point<WW>(P, R, SB, p, cell, b, i, cnt);
+        } else if (f.ev == kSurface) {
+            cnt.add(1);
+            hist_event(R, i, 1);
+            const int old_ww = WW ? P.cell_ww[cell] : 0;
+            const int face = cross<FM>(P, p, crossing_mask<FM>(P, f));
             if (face >= 0) {
                 atomic_add_f64(R.L + (((int64_t)b * P.K + p.k) * P.G + p.g) * 6 + face, p.w);
                 cnt.add(3 + kLeak);
-                if (R.dbg_counts) hist_term(R, first + cur.hid[slot], kLeak);
-            } else {
-                alive = true;
-                if (WW) {
-                    const int cell = cell_index(P, p.ix);
-                    if (P.cell_ww[cell] != old_ww) {
-                        p.s = cur.s[slot];
-                        alive = ww_point<WW>(P, R, SB, p, cell, b, first + cur.hid[slot], cnt);
-                        cur.s[slot] = p.s;
-                        cur.w[slot] = p.w;
-                    }
-                }
+                hist_term(R, i, kLeak);
+                return false;
             }
-            if (alive) {
-#pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    if (finite_axis<FM>(P, a) && ((mask >> a) & 1)) {
-                        cur.x[a][slot] = p.x[a];
-                        cur.u[a][slot] = p.u[a];
-                    }
-                }
-                cur.ixyz[slot] = pack_ix(p.ix);
-            }
-        }
-        const uint32_t as = block_append(alive, &cA);
-        if (alive) aq_out[seg0 + as] = slot;
-        if (R.prof && valid)
-            tprof(p_items, p_bytes, 1u, 4u + load_bytes<FM, WW>(P) + (alive ? 16u * (unsigned int)__popc(mask) + 8u : 0u));
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) C.n_a[it * C.G + seg] = cA;
-    cnt.flush(R, CLS, p_items, p_bytes);
-}
-
-// ---------------------------------------------------------------------------
-// analog collision
-// ---------------------------------------------------------------------------
-template <int FM, bool WW, int CLS = MCDC_PROF_COLLISION>
-__global__ void __launch_bounds__(kBlock) k_collision(DevProblem P, RunArgs R, Bank cur, Ctl C,
-                                                      const uint32_t *__restrict__ cq, uint32_t *aq_out, int it,
-                                                      SplitBank SB) {
-    __shared__ Counters cnt;
-    __shared__ unsigned int cA;
-    const unsigned int seg = blockIdx.x;
-    const uint32_t seg0 = seg * C.L;
-    const unsigned int n = C.n_c[it * C.G + seg];
-    const uint64_t first = *C.first;
-    cnt.init();
-    unsigned long long p_items = 0, p_bytes = 0;
-    if (threadIdx.x == 0) cA = C.n_a[it * C.G + seg];   // after the surface kernel's appends
-    __syncthreads();
-    for (unsigned int j0 = 0; j0 < n; j0 += kBlock) {
-        const unsigned int idx = j0 + threadIdx.x;
-        const bool valid = idx < n;
-        bool alive = false;
-        uint32_t slot = 0;
-        Particle p;
-        if (valid) {
-            slot = cq[seg0 + idx];
-            const uint32_t gk = cur.gk[slot];
-            if (WW) {
-                uint32_t gk_unused;
-                load_state<FM, WW>(P, cur, slot, p, gk_unused);   // whole state for split progeny
-            }
-            p.g = gk & 31u;
-            p.s = cur.s[slot];
-            const uint32_t c = cur.ixyz[slot];
-            const int ix[3] = {(int)(c & 2047u), (int)((c >> 11) & 2047u), (int)(c >> 22)};
-            const int cell = cell_index(P, ix);
-            const int m = P.cell_mat[cell];
-            if (collide<FM>(P, p, m)) {
-                alive = !WW || ww_point<WW>(P, R, SB, p, cell, (gk >> 5) & 1023u, first + cur.hid[slot], cnt);
-                if (alive) {
-                    cur.gk[slot] = (gk & ~31u) | (uint32_t)p.g;
-                    cur.tau[slot] = p.tau;
-                    if (WW) cur.w[slot] = p.w;
-#pragma unroll
-                    for (int a = 0; a < 3; ++a)
-                        if (finite_axis<FM>(P, a)) cur.u[a][slot] = p.u[a];
-                }
-            } else {
+            cell = cell_index(P, p.ix);
+            if (WW && P.cell_ww[cell] != old_ww && !ww_point<WW>(P, R, SB, p, cell, b, i, cnt)) return false;
+        } else {
+            cnt.add(2);
+            hist_event(R, i, 2);
+            if (!collide<FM>(P, p, f.m)) {
                 cnt.add(3 + kAbsorb);
-                if (R.dbg_counts) hist_term(R, first + cur.hid[slot], kAbsorb);
+                hist_term(R, i, kAbsorb);
+                return false;
             }
-            cur.s[slot] = p.s;
+            if (!ww_point<WW>(P, R, SB, p, cell, b, i, cnt)) return false;
         }
-        const uint32_t as = block_append(alive, &cA);
-        if (alive) aq_out[seg0 + as] = slot;
-        if (R.prof && valid) tprof(p_items, p_bytes, 1u, 20u + 8u + (alive ? 16u + 8u * nfinite<FM>(P) + 4u : 0u));
     }
-    __syncthreads();
-    if (threadIdx.x == 0) C.n_a[it * C.G + seg] = cA;
-    cnt.flush(R, CLS, p_items, p_bytes);
 }
 
-// ---------------------------------------------------------------------------
-// finish: the particles still in flight, in registers, to census or death
-// ---------------------------------------------------------------------------
-template <int FM, bool WW, int CLS = MCDC_PROF_FINISH>
-__global__ void __launch_bounds__(kBlock) k_finish(DevProblem P, RunArgs R, Bank cur, Bank next, Ctl C, int par,
-                                                   const uint32_t *__restrict__ aq, int it, int gn, SplitBank SB) {
-    __shared__ Counters cnt;
+template <int FM, bool WW, int EV, int CLS = (EV == kSurface) ? MCDC_PROF_SURFACE : MCDC_PROF_COLLISION>
+__global__ void __launch_bounds__(kBlock) k_event(DevProblem P, RunArgs R, Bank ev, Bank next, Ctl C, int par,
+                                                  int gn, SplitBank SB) {
+    __shared__ unsigned long long red[kCounters + 2];
+    Counters cnt;
     __shared__ unsigned int cN;
     extern __shared__ double lt[];
     const unsigned int seg = blockIdx.x;
     const uint32_t seg0 = seg * C.L;
-    const unsigned int n = C.n_a[(it - 1) * C.G + seg];
+    const uint32_t seg_end = seg0 + C.L - 1;
+    const unsigned int n = (EV == kSurface) ? C.n_s[seg] : C.n_c[seg];
     const int step = *C.step;
     const uint64_t first = *C.first;
-    cnt.init();
-    unsigned long long p_items = 0, p_bytes = 0;
-    if (threadIdx.x == 0) cN = C.n_bank[(par ^ 1) * C.G + seg];
+    cnt.init(red);
+    if (threadIdx.x == 0) cN = C.n_bank[(par ^ 1) * C.G + seg];   // after the earlier kernels' appends
     StepScore sc;
     init_slice(sc, lt, gn, C.seg_b0[seg]);
     __syncthreads();
-    const bool per_hist = (R.dbg_counts != nullptr) || (R.dbg_scores != nullptr) || P.qoi_on;
     for (unsigned int j0 = 0; j0 < n; j0 += kBlock) {
         const unsigned int idx = j0 + threadIdx.x;
         const bool valid = idx < n;
@@ -588,82 +493,43 @@ __global__ void __launch_bounds__(kBlock) k_finish(DevProblem P, RunArgs R, Bank
         Particle p;
         uint32_t gk = 0, hid = 0;
         if (valid) {
-            const uint32_t slot = aq[seg0 + idx];
-            load_state<FM, WW>(P, cur, slot, p, gk);
-            p.s = cur.s[slot];
-            hid = cur.hid[slot];
+            uint32_t hidw;
+            load_state<FM, WW>(P, ev, (EV == kSurface) ? seg0 + idx : seg_end - idx, p, gk, hidw);
+            hid = hidw & kHidMask;
             const uint64_t i = first + hid;
             const int b = (gk >> 5) & 1023u;
             int cell = cell_index(P, p.ix);
-            int since = 0;
-            for (;;) {
-                if (since >= kMaxEventsPerStep) {
-                    cnt.add(3 + kLost);
-                    if (per_hist) hist_term(R, i, kLost);
-                    break;
-                }
-                ++since;
-                const Flight f = next_event<FM>(P, p, cell);
-                if (f.d == kInf) {
-                    cnt.add(3 + kLost);
-                    if (per_hist) hist_term(R, i, kLost);
-                    break;
-                }
-                const double v = p.w * f.d;
-                const int tb = P.cell_tal[cell];
-                if (tb >= 0) {
-                    sc.add(P, R, b, p.g, p.k, tb, v);
-                    if (R.dbg_scores) atomic_add_f64(R.dbg_scores + i * 2, v);
-                }
-                if (P.qoi_on && P.cell_qoi[cell] && P.qoi_groups[p.g]) {
-                    atomic_add_f64(R.qoi_hist + hid, v);
-                    if (R.dbg_scores) atomic_add_f64(R.dbg_scores + i * 2 + 1, v);
-                }
-                move<FM>(P, p, f);
-                if (f.ev == kCensus) {
-                    cnt.add(0);
-                    if (per_hist) hist_event(R, i, 0);
-                    p.k += 1;
-                    if (p.k == P.K) {
-                        cnt.add(3 + kTime);
-                        if (per_hist) hist_term(R, i, kTime);
-                    } else {
-                        to_next = ww_point<WW>(P, R, SB, p, cell, b, i, cnt);
-                    }
-                    break;
-                } else if (f.ev == kSurface) {
-                    cnt.add(1);
-                    if (per_hist) hist_event(R, i, 1);
-                    const int old_ww = WW ? P.cell_ww[cell] : 0;
-                    const int face = cross<FM>(P, p, crossing_mask<FM>(P, f));
-                    if (face >= 0) {
-                        atomic_add_f64(R.L + (((int64_t)b * P.K + p.k) * P.G + p.g) * 6 + face, p.w);
-                        cnt.add(3 + kLeak);
-                        if (per_hist) hist_term(R, i, kLeak);
-                        break;
-                    }
-                    cell = cell_index(P, p.ix);
-                    if (WW && P.cell_ww[cell] != old_ww && !ww_point<WW>(P, R, SB, p, cell, b, i, cnt)) break;
+            bool alive;
+            if (EV == kSurface) {
+                const int old_ww = WW ? P.cell_ww[cell] : 0;
+                const int face = cross<FM>(P, p, (int)(hidw >> 29));
+                if (face >= 0) {
+                    atomic_add_f64(R.L + (((int64_t)b * P.K + p.k) * P.G + p.g) * 6 + face, p.w);
+                    cnt.add(3 + kLeak);
+                    hist_term(R, i, kLeak);
+                    alive = false;
                 } else {
-                    cnt.add(2);
-                    if (per_hist) hist_event(R, i, 2);
-                    if (!collide<FM>(P, p, f.m)) {
-                        cnt.add(3 + kAbsorb);
-                        if (per_hist) hist_term(R, i, kAbsorb);
-                        break;
-                    }
-                    if (WW && !ww_point<WW>(P, R, SB, p, cell, b, i, cnt)) break;
+                    cell = cell_index(P, p.ix);
+                    alive = !WW || P.cell_ww[cell] == old_ww || ww_point<WW>(P, R, SB, p, cell, b, i, cnt);
+                }
+            } else {
+                alive = collide<FM>(P, p, P.cell_mat[cell]);
+                if (!alive) {
+                    cnt.add(3 + kAbsorb);
+                    hist_term(R, i, kAbsorb);
+                } else {
+                    alive = ww_point<WW>(P, R, SB, p, cell, b, i, cnt);
                 }
             }
+            if (alive) to_next = to_census<FM, WW>(P, R, SB, sc, cnt, p, cell, b, i, hid);
         }
         const uint32_t ns = block_append(to_next, &cN);
         if (to_next) store_state<FM, WW>(P, next, seg0 + ns, p, with_gk(gk, p), hid);
-        if (R.prof && valid)
-            tprof(p_items, p_bytes, 1u, 4u + load_bytes<FM, WW>(P) + 12u + (to_next ? state_bytes<FM, WW>(P) : 0u));
+        if (R.prof && valid) cnt.prof(1u, state_bytes<FM, WW>(P) * (to_next ? 2u : 1u));
     }
     flush_slice(P, R, sc, step);
     if (threadIdx.x == 0) C.n_bank[(par ^ 1) * C.G + seg] = cN;
-    cnt.flush(R, CLS, p_items, p_bytes);
+    cnt.flush(R, CLS, red);
 }
 
 // ---------------------------------------------------------------------------
@@ -680,7 +546,7 @@ __global__ void k_step_end(Ctl C) { *C.step += 1; }
 // ---------------------------------------------------------------------------
 struct Layout {
     Bank bank[2];
-    uint32_t *sq, *cq, *aq[2];
+    Bank ev;
     Ctl ctl;
 };
 
@@ -688,11 +554,9 @@ size_t pad256(size_t b) { return (b + 255) & ~size_t(255); }
 
 size_t bank_bytes(uint64_t slots) { return 10 * pad256(slots * 8) + 3 * pad256(slots * 4); }
 
-size_t queue_bytes(uint64_t slots, unsigned int G) {
-    return 4 * pad256(slots * 4) + pad256(2 * G * 4) + 3 * pad256(kMaxIters * G * 4) + pad256(G * 4) + 2 * 256;
-}
+size_t ctl_bytes(unsigned int G) { return pad256(2 * G * 4) + 3 * pad256(G * 4) + 2 * 256; }
 
-Layout carve(void *bank_mem, void *queue_mem, uint64_t slots, unsigned int G, unsigned int Lseg) {
+Layout carve(void *bank_mem, void *ctl_mem, uint64_t slots, unsigned int G, unsigned int Lseg) {
     Layout Lo{};
     char *p = (char *)bank_mem;
     auto take = [&](size_t bytes) {
@@ -700,8 +564,8 @@ Layout carve(void *bank_mem, void *queue_mem, uint64_t slots, unsigned int G, un
         p += pad256(bytes);
         return r;
     };
-    for (int k = 0; k < 2; ++k) {
-        Bank &B = Lo.bank[k];
+    for (int k = 0; k < 3; ++k) {
+        Bank &B = (k < 2) ? Lo.bank[k] : Lo.ev;
         for (int a = 0; a < 3; ++a) B.x[a] = (double *)take(slots * 8);
         for (int a = 0; a < 3; ++a) B.u[a] = (double *)take(slots * 8);
         B.t = (double *)take(slots * 8);
@@ -712,16 +576,11 @@ Layout carve(void *bank_mem, void *queue_mem, uint64_t slots, unsigned int G, un
         B.gk = (uint32_t *)take(slots * 4);
         B.hid = (uint32_t *)take(slots * 4);
     }
-    p = (char *)queue_mem;
-    Lo.sq = (uint32_t *)take(slots * 4);
-    Lo.cq = (uint32_t *)take(slots * 4);
-    Lo.aq[0] = (uint32_t *)take(slots * 4);
-    Lo.aq[1] = (uint32_t *)take(slots * 4);
+    p = (char *)ctl_mem;
     Ctl &C = Lo.ctl;
     C.n_bank = (unsigned int *)take(2 * G * 4);
-    C.n_s = (unsigned int *)take(kMaxIters * G * 4);
-    C.n_c = (unsigned int *)take(kMaxIters * G * 4);
-    C.n_a = (unsigned int *)take(kMaxIters * G * 4);
+    C.n_s = (unsigned int *)take(G * 4);
+    C.n_c = (unsigned int *)take(G * 4);
     C.seg_b0 = (int *)take(G * 4);
     C.step = (int *)take(64);
     C.first = (uint64_t *)take(64);
@@ -754,6 +613,12 @@ void key_add(std::vector<char> &k, const T &v) {
     k.insert(k.end(), p, p + sizeof(T));
 }
 
+// Workgroups (= segments) per CU when the caller leaves it open: fewer,
+// longer-running workgroups than the advance kernel could hold resident
+// keep fewer concurrent streams open per HBM channel and measured faster
+// on both the slab and the lattice workloads.
+constexpr int kSegmentsPerCU = 4;
+
 template <int FM, bool WW>
 int run_event(mcdc_problem *pb, const RunArgs &R0, uint64_t first, uint64_t count, const mcdc_run_options &opt,
               hipStream_t st, Profiler &prof) {
@@ -761,26 +626,25 @@ int run_event(mcdc_problem *pb, const RunArgs &R0, uint64_t first, uint64_t coun
     uint64_t C = opt.bank_capacity ? (uint64_t)opt.bank_capacity : (uint64_t)1 << 24;
     if (C > count) C = count;
     if (C > (1ULL << 28)) C = 1ULL << 28;
-    int iters = opt.event_iters > 0 ? opt.event_iters : 1;
-    if (iters > kMaxIters - 1) iters = kMaxIters - 1;
+
     // per-step tally slice [2 batches][G][nts] in LDS when it fits
     const int64_t gn64 = (int64_t)P.G * P.nts;
     const int gn = (2 * gn64 <= kLdsTallyMax) ? (int)gn64 : 0;
     const size_t shmem = (size_t)2 * gn * sizeof(double);
 
-    // segments: one per workgroup.  Auto: the advance kernel's resident
-    // capacity, so its pass over the census bank is one round of workgroups
-    // (a second, partly filled round would cost nearly a full one).
+    // segments: one per workgroup
     unsigned int G;
     if (opt.segments > 0) {
         G = (unsigned int)opt.segments;
     } else {
         int per_cu = 0, n_cu = 0;
         hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &per_cu, reinterpret_cast<const void *>(&k_advance<FM, WW, true>), kBlock, shmem);
+            &per_cu, reinterpret_cast<const void *>(&k_advance<FM, WW>), kBlock, shmem);
         if (e == hipSuccess) e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, pb->device);
         if (e != hipSuccess) return hip_fail(e, "occupancy query");
-        G = (unsigned int)(per_cu > 0 ? per_cu : 1) * (unsigned int)(n_cu > 0 ? n_cu : 1);
+        if (per_cu < 1) per_cu = 1;
+        if (per_cu > kSegmentsPerCU) per_cu = kSegmentsPerCU;
+        G = (unsigned int)per_cu * (unsigned int)(n_cu > 0 ? n_cu : 1);
     }
     const uint64_t g_need = (C + kBlock - 1) / kBlock;
     if (G > g_need) G = (unsigned int)g_need;
@@ -788,8 +652,8 @@ int run_event(mcdc_problem *pb, const RunArgs &R0, uint64_t first, uint64_t coun
     const unsigned int Lseg = (unsigned int)((C + G - 1) / G);
     const uint64_t slots = (uint64_t)G * Lseg;
     int rc;
-    if ((rc = ensure(pb->bank, bank_bytes(slots) * 2 + 64 * 256))) return rc;
-    if ((rc = ensure(pb->queues, queue_bytes(slots, G)))) return rc;
+    if ((rc = ensure(pb->bank, bank_bytes(slots) * 3 + 64 * 256))) return rc;
+    if ((rc = ensure(pb->queues, ctl_bytes(G)))) return rc;
     if (P.qoi_on && (rc = ensure(pb->qoi_hist, C * sizeof(double)))) return rc;
     Layout L = carve(pb->bank.p, pb->queues.p, slots, G, Lseg);
     RunArgs R = R0;
@@ -799,51 +663,31 @@ int run_event(mcdc_problem *pb, const RunArgs &R0, uint64_t first, uint64_t coun
     SplitBank SB[2]{};
     if (WW && (rc = split_prepare(pb, C, SB))) return rc;
 
-    // the step kernels never read the seed or the history count
+    // the step kernels never read the seed or the history count; Rs is the
+    // uninstrumented form the graphs capture, Rp the profiled one
     RunArgs Rs = R;
     Rs.seed = 0;
     Rs.N = 0;
+    const RunArgs Rp = Rs;
+    Rs.prof = nullptr;
+    const int every = opt.profile_every > 1 ? opt.profile_every : 1;
 
-    auto enqueue_step = [&](int par, hipStream_t s, Profiler &pr) {
+    auto enqueue_step = [&](int par, hipStream_t s, Profiler &pr, const RunArgs &Ra) {
         const Bank &cur = L.bank[par];
         const Bank &nxt = L.bank[par ^ 1];
-        pr.begin(MCDC_PROF_ADVANCE);
-        hipLaunchKernelGGL((k_advance<FM, WW, true>), dim3(G), dim3(kBlock), shmem, s, P, Rs, cur, nxt, L.ctl, par,
-                           (const uint32_t *)nullptr, 0, L.sq, L.cq, gn, SB[0]);
-        pr.end();
-        pr.begin(MCDC_PROF_SURFACE);
-        hipLaunchKernelGGL((k_surface<FM, WW>), dim3(G), dim3(kBlock), 0, s, P, Rs, cur, L.ctl,
-                           (const uint32_t *)L.sq, L.aq[0], 0, SB[0]);
-        pr.end();
-        pr.begin(MCDC_PROF_COLLISION);
-        hipLaunchKernelGGL((k_collision<FM, WW>), dim3(G), dim3(kBlock), 0, s, P, Rs, cur, L.ctl,
-                           (const uint32_t *)L.cq, L.aq[0], 0, SB[0]);
-        pr.end();
-        for (int j = 1; j < iters; ++j) {
-            pr.begin(MCDC_PROF_ADVANCE_Q);
-            hipLaunchKernelGGL((k_advance<FM, WW, false>), dim3(G), dim3(kBlock), shmem, s, P, Rs, cur, nxt, L.ctl,
-                               par, (const uint32_t *)L.aq[(j - 1) & 1], j, L.sq, L.cq, gn, SB[0]);
-            pr.end();
-            pr.begin(MCDC_PROF_SURFACE);
-            hipLaunchKernelGGL((k_surface<FM, WW>), dim3(G), dim3(kBlock), 0, s, P, Rs, cur, L.ctl,
-                               (const uint32_t *)L.sq, L.aq[j & 1], j, SB[0]);
-            pr.end();
-            pr.begin(MCDC_PROF_COLLISION);
-            hipLaunchKernelGGL((k_collision<FM, WW>), dim3(G), dim3(kBlock), 0, s, P, Rs, cur, L.ctl,
-                               (const uint32_t *)L.cq, L.aq[j & 1], j, SB[0]);
-            pr.end();
-        }
-        pr.begin(MCDC_PROF_FINISH);
-        hipLaunchKernelGGL((k_finish<FM, WW>), dim3(G), dim3(kBlock), shmem, s, P, Rs, cur, nxt, L.ctl, par,
-                           (const uint32_t *)L.aq[(iters - 1) & 1], iters, gn, SB[0]);
-        pr.end();
+        launch_timed(pr, MCDC_PROF_ADVANCE, k_advance<FM, WW>, dim3(G), dim3(kBlock), (uint32_t)shmem, s, P, Ra, cur,
+                     nxt, L.ev, L.ctl, par, gn, SB[0]);
+        launch_timed(pr, MCDC_PROF_SURFACE, k_event<FM, WW, kSurface>, dim3(G), dim3(kBlock), (uint32_t)shmem, s, P,
+                     Ra, L.ev, nxt, L.ctl, par, gn, SB[0]);
+        launch_timed(pr, MCDC_PROF_COLLISION, k_event<FM, WW, kCollision>, dim3(G), dim3(kBlock), (uint32_t)shmem, s,
+                     P, Ra, L.ev, nxt, L.ctl, par, gn, SB[0]);
         hipLaunchKernelGGL(k_step_end, dim3(1), dim3(1), 0, s, L.ctl);
     };
 
-    // replay captured steps unless a per-launch profile or per-history
-    // debug output is requested (those launch eagerly)
-    const bool use_graph =
-        !(opt.flags & MCDC_FLAG_EAGER) && !opt.profile && !R.dbg_counts && !R.dbg_scores && P.K > 1;
+    // replay captured steps unless per-history debug output is requested;
+    // profiled steps launch eagerly
+    const bool use_graph = !(opt.flags & MCDC_FLAG_EAGER) && !(opt.profile && every == 1) && !R.dbg_counts &&
+                           !R.dbg_scores && P.K > 1;
     StepGraphs *Gr = nullptr;
     if (use_graph) {
         if (!pb->graph_cache) pb->graph_cache = new StepGraphs();
@@ -853,7 +697,6 @@ int run_event(mcdc_problem *pb, const RunArgs &R0, uint64_t first, uint64_t coun
         key_add(key, Rs);
         key_add(key, L);
         key_add(key, gn);
-        key_add(key, iters);
         key_add(key, SB[0]);
         if (key != Gr->key) {
             Gr->clear();
@@ -863,7 +706,7 @@ int run_event(mcdc_problem *pb, const RunArgs &R0, uint64_t first, uint64_t coun
             for (int q = 0; q < 2 && e == hipSuccess; ++q) {
                 e = hipStreamBeginCapture(Gr->cs, hipStreamCaptureModeThreadLocal);
                 if (e != hipSuccess) break;
-                enqueue_step(q, Gr->cs, none);
+                enqueue_step(q, Gr->cs, none, Rs);
                 e = hipStreamEndCapture(Gr->cs, &Gr->graph[q]);
                 if (e == hipSuccess) e = hipGraphInstantiate(&Gr->exec[q], Gr->graph[q], nullptr, nullptr, 0);
             }
@@ -881,15 +724,16 @@ int run_event(mcdc_problem *pb, const RunArgs &R0, uint64_t first, uint64_t coun
         hipLaunchKernelGGL(k_ctl_init, dim3(1), dim3(1), 0, st, L.ctl, cfirst);
         if (P.qoi_on && (rc = launch_zero(R.qoi_hist, n * sizeof(double), st))) return hip_fail((hipError_t)rc, "zero");
         if (WW) split_reset(SB, st);
-        prof.begin(MCDC_PROF_SOURCE);
-        hipLaunchKernelGGL((k_source<FM, WW>), dim3(G), dim3(kBlock), 0, st, P, R, L.bank[0], L.ctl, n);
-        prof.end();
+        launch_timed(prof, MCDC_PROF_SOURCE, k_source<FM, WW>, dim3(G), dim3(kBlock), 0u, st, P, R, L.bank[0], L.ctl,
+                     n);
         for (int step = 0; step < P.K; ++step) {
-            if (Gr) {
+            const bool sampled = opt.profile && step % every == opt.profile_phase % every;
+            if (Gr && !sampled) {
                 hipError_t e = hipGraphLaunch(Gr->exec[step & 1], st);
                 if (e != hipSuccess) return hip_fail(e, "census step replay");
             } else {
-                enqueue_step(step & 1, st, prof);
+                Profiler none;
+                enqueue_step(step & 1, st, sampled ? prof : none, sampled ? Rp : Rs);
             }
         }
         hipError_t e = hipGetLastError();

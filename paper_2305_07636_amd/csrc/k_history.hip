@@ -218,11 +218,11 @@ size_t split_bytes(unsigned int cap) { return (size_t)cap * (13 * 8 + 8) + 16 * 
 
 template <int FM, bool WW>
 void launch_main(const DevProblem &P, const RunArgs &R, uint64_t first, uint64_t count, uint64_t chunk_first,
-                 const SplitBank &SB, hipStream_t st) {
+                 const SplitBank &SB, hipStream_t st, Profiler &prof) {
     const int bs = 256;
     const uint64_t grid = (count + bs - 1) / bs;
-    hipLaunchKernelGGL((k_history<FM, WW>), dim3((unsigned)grid), dim3(bs), 0, st, P, R, first, count,
-                       chunk_first, SB);
+    launch_timed(prof, MCDC_PROF_HISTORY, k_history<FM, WW>, dim3((unsigned)grid), dim3(bs), 0u, st, P, R, first,
+                 count, chunk_first, SB);
 }
 
 // Split progeny of one chunk, generation by generation, until none are left
@@ -242,10 +242,8 @@ int run_generations(const DevProblem &P, const RunArgs &R, SplitBank SB[2], uint
         }
         const SplitBank &in = SB[gen & 1], &out = SB[(gen + 1) & 1];
         hipLaunchKernelGGL(k_zero_count, dim3(1), dim3(1), 0, st, out.count);
-        prof.begin(MCDC_PROF_HISTORY);
-        hipLaunchKernelGGL(k_history_children<FM>, dim3((n_in + 255) / 256), dim3(256), 0, st, P, R, in, n_in,
-                           cfirst, out);
-        prof.end();
+        launch_timed(prof, MCDC_PROF_HISTORY, k_history_children<FM>, dim3((n_in + 255) / 256), dim3(256), 0u, st,
+                     P, R, in, n_in, cfirst, out);
         e = hipGetLastError();
         if (e != hipSuccess) return hip_fail(e, "history children launch");
     }
@@ -273,12 +271,10 @@ int run_history(mcdc_problem *pb, const RunArgs &R0, uint64_t first, uint64_t co
         const uint64_t n = (count - c0 < chunk) ? count - c0 : chunk;
         const uint64_t cfirst = first + c0;
         if (ww) split_reset(SB, st);
-        prof.begin(MCDC_PROF_HISTORY);
         if (ww)
-            launch_main<FM, true>(P, R, cfirst, n, cfirst, SB[0], st);
+            launch_main<FM, true>(P, R, cfirst, n, cfirst, SB[0], st, prof);
         else
-            launch_main<FM, false>(P, R, cfirst, n, cfirst, SB[0], st);
-        prof.end();
+            launch_main<FM, false>(P, R, cfirst, n, cfirst, SB[0], st, prof);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return hip_fail(e, "history kernel launch");
         if (!ww) continue;
@@ -399,7 +395,7 @@ int launch_batched(const BatchItem *items, const uint64_t *offs, int n_items, ui
 }
 
 int split_prepare(mcdc_problem *pb, uint64_t chunk, dev::SplitBank SB[2]) {
-    const unsigned int cap = (unsigned int)((chunk < (1u << 20)) ? (1u << 20) : chunk);
+    const unsigned int cap = (unsigned int)((chunk < (1u << 22)) ? (1u << 22) : chunk);
     int rc;
     if ((rc = ensure(pb->split, 2 * split_bytes(cap) + 256))) return rc;
     if ((rc = ensure(pb->counters_split, 2 * sizeof(unsigned int)))) return rc;

@@ -2,6 +2,7 @@
 // kernels receive by value, the per-run arguments, and the launchers.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -88,10 +89,33 @@ struct Profiler {
     std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> marks;
     int cls = -1;
     hipEvent_t open = nullptr;
-    void begin(int c);
+    bool wants(int c) const { return out && (!mask || ((mask >> c) & 1u)); }
+    void begin(int c);                 // event pair around launches made in between
     void end();
-    int finish();                      // synchronise, accumulate, destroy events
+    hipEvent_t take();                 // an event from the reuse pool (nullptr on failure)
+    void give(hipEvent_t e);           // back to the pool
+    void add(int c, hipEvent_t a, hipEvent_t b) { marks.push_back({c, {a, b}}); }
+    int finish();                      // synchronise, accumulate, return events to the pool
 };
+
+// Launch a kernel; when the profiler times class cls the launch carries a
+// start / stop event pair that the runtime stamps at the kernel's own start
+// and end (no marker packets around the dispatch).
+template <typename F, typename... Args>
+void launch_timed(Profiler &pr, int cls, F kernel, dim3 grid, dim3 block, uint32_t shmem, hipStream_t s,
+                  Args... args) {
+    if (pr.wants(cls)) {
+        hipEvent_t a = pr.take(), b = pr.take();
+        if (a && b) {
+            hipExtLaunchKernelGGL(kernel, grid, block, shmem, s, a, b, 0u, args...);
+            pr.add(cls, a, b);
+            return;
+        }
+        if (a) pr.give(a);
+        if (b) pr.give(b);
+    }
+    hipLaunchKernelGGL(kernel, grid, block, shmem, s, args...);
+}
 
 // Host-side compiled problem (owns the device blob).
 struct HostProblem {

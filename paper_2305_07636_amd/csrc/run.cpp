@@ -32,8 +32,12 @@ hipEvent_t take_event() {
 }
 }  // namespace
 
+hipEvent_t Profiler::take() { return take_event(); }
+
+void Profiler::give(hipEvent_t e) { event_pool().push_back(e); }
+
 void Profiler::begin(int c) {
-    if (!out || (mask && !((mask >> c) & 1u))) return;
+    if (!wants(c)) return;
     cls = c;
     open = take_event();
     if (open) (void)hipEventRecord(open, st);
@@ -88,8 +92,8 @@ int check_options(const mcdc_run_options &opt) {
     if (opt.block_size != 0 && (opt.block_size < 64 || opt.block_size > 1024 || opt.block_size % 64))
         return bad("block_size must be a multiple of 64 in [64, 1024]");
     if (opt.segments < 0 || opt.segments > (1 << 20)) return bad("segments must be in [0, 2^20]");
+    if (opt.profile_every < 0 || opt.profile_phase < 0) return bad("profile_every and profile_phase must be >= 0");
     if (opt.bank_capacity < 0) return bad("bank_capacity must be >= 0");
-    if (opt.event_iters < 0) return bad("event_iters must be >= 0");
     return MCDC_OK;
 }
 

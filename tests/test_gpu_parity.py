@@ -157,3 +157,35 @@ def test_event_segment_count_does_not_change_results(segments):
         h.close()
     assert np.array_equal(a["events"], b["events"]) and np.array_equal(a["terms"], b["terms"])
     close(b["mean"].cpu().numpy(), a["mean"])
+
+
+@pytest.mark.gpu
+def test_sampled_profile_mixes_graph_and_eager_steps():
+    """With profile_every, sampled census steps launch eagerly between
+    graph replays; results equal an uninstrumented run, only the sampled
+    launches are timed and counted, and the phases 0..every-1 together
+    count every launch once."""
+    import paper_2305_07636_amd as m
+    from gpu_common import close
+
+    p = w.cfg2_slab_pulse()
+    h = m.mcdc_problem_create(p)
+    adv = m._binding.PROF_CLASSES.index("advance")
+    try:
+        a = m.mcdc_run(h, 200003, 21, algorithm="event")
+        full = np.zeros((len(m._binding.PROF_CLASSES), 4))
+        c = m.mcdc_run(h, 200003, 21, algorithm="event", profile=full)
+        total = np.zeros_like(full)
+        for phase in range(10):
+            prof = np.zeros_like(full)
+            b = m.mcdc_run(h, 200003, 21, algorithm="event", profile=prof, profile_classes=["advance"],
+                           profile_every=10, profile_phase=phase)
+            assert prof[adv, 1] == 10 and prof[adv, 0] > 0
+            assert np.array_equal(a["events"], b["events"]) and np.array_equal(a["terms"], b["terms"])
+            close(b["mean"].cpu().numpy(), a["mean"].cpu().numpy())
+            total += prof
+    finally:
+        h.close()
+    assert np.array_equal(a["events"], c["events"]) and np.array_equal(a["terms"], c["terms"])
+    assert full[adv, 1] == 100 and total[adv, 1] == 100
+    assert total[adv, 2] == full[adv, 2] and total[adv, 3] == full[adv, 3]
