@@ -108,9 +108,10 @@ def source_cells(prob: dict) -> np.ndarray:
     return sel[2][:, None, None] & sel[1][None, :, None] & sel[0][None, None, :]
 
 
-def centres_from_log_importance(logI: np.ndarray, log_ref: float, shape) -> np.ndarray:
-    """w_c(cell) = I_ref / I(cell) on cells at least as important as the
-    reference level, 0 (no window: analog tracking) elsewhere.
+def centres_from_log_importance(logI: np.ndarray, log_ref: float, shape, below: float = 0.0) -> np.ndarray:
+    """w_c(cell) = I_ref / I(cell) on cells at most `below` decades less
+    important than the reference level (there w_c > 1: particles entering
+    are rouletted), 0 (no window: analog tracking) elsewhere.
 
     The reference is the importance at the frontier of the region the
     adjoint pilot resolved: particles coming from the source travel analog
@@ -119,7 +120,7 @@ def centres_from_log_importance(logI: np.ndarray, log_ref: float, shape) -> np.n
     windows would need the importance at the source, which an analog
     adjoint pilot of a deep-penetration problem does not reach."""
     logI = np.asarray(logI, dtype=np.float64).reshape(shape)
-    w = np.where(logI >= log_ref, 10.0 ** (log_ref - logI), 0.0)
+    w = np.where(logI >= log_ref - below, 10.0 ** np.minimum(log_ref - logI, below), 0.0)
     return np.ascontiguousarray(w)
 
 
@@ -143,8 +144,9 @@ def _frontier_table(logI, ok, shape, pct):
     return centres_from_log_importance(np.where(ok, logI, -np.inf), log_ref, shape)
 
 
-def learned_windows(prob: dict, n_pilot: int = 10_000_000, seed: int = 50, steps: int = 3000,
-                    lr: float = 1e-3, net_seed: int = 1, rel_max: float = 0.3, frontier_pct: float = 5.0):
+def learned_windows(prob: dict, n_pilot: int = 100_000_000, seed: int = 50, steps: int = 3000,
+                    lr: float = 1e-3, net_seed: int = 1, rel_max: float = 0.3, frontier_pct: float = 5.0,
+                    below: float = 0.0):
     """Plain pilots -> training set -> network -> window table.
 
     1. forward analog pilot: the flux phi, which is the importance of the
@@ -199,8 +201,9 @@ def learned_windows(prob: dict, n_pilot: int = 10_000_000, seed: int = 50, steps
         log_ref = float(np.log10(I_src))
     else:
         log_ref = float(np.percentile(T, frontier_pct))
-    table = centres_from_log_importance(yhat, log_ref, shape)
-    raw = centres_from_log_importance(np.where(ok, np.log10(np.where(ok, phi, 1.0)), -np.inf), log_ref, shape)
+    table = centres_from_log_importance(yhat, log_ref, shape, below if src_resolved else 0.0)
+    raw = centres_from_log_importance(np.where(ok, np.log10(np.where(ok, phi, 1.0)), -np.inf), log_ref, shape,
+                                      below if src_resolved else 0.0)
     info = {"pilot_s": t_pilot, "train_s": t_train, "n_train": int(ok.sum()), "loss_first": float(losses[0]),
             "loss_last": float(losses[-1]), "raw_table": raw, "adjoint_flux": phi,
             "source_resolved": bool(src_resolved), "log_ref": log_ref}
