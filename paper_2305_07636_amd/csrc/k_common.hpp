@@ -250,22 +250,29 @@ __device__ __forceinline__ int cross(const DevProblem &P, Particle &p, int mask)
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         if (!finite_axis<FM>(P, a) || !((mask >> a) & 1)) continue;
+        // (each face's boundary condition is read with a constant index, so
+        // a local copy of the problem stays in registers)
         int face = -1;
+        bool vacuum = false;
         if (p.u[a] > 0.0) {
             p.x[a] = P.U[a][p.ix[a] + 1];
-            if (p.ix[a] == P.nU[a] - 2)
+            if (p.ix[a] == P.nU[a] - 2) {
                 face = 2 * a + 1;
-            else
+                vacuum = P.bc[2 * a + 1] == MCDC_VACUUM;
+            } else {
                 p.ix[a] += 1;
+            }
         } else {
             p.x[a] = P.U[a][p.ix[a]];
-            if (p.ix[a] == 0)
+            if (p.ix[a] == 0) {
                 face = 2 * a;
-            else
+                vacuum = P.bc[2 * a] == MCDC_VACUUM;
+            } else {
                 p.ix[a] -= 1;
+            }
         }
         if (face >= 0) {
-            if (P.bc[face] == MCDC_VACUUM) return face;
+            if (vacuum) return face;
             p.u[a] = -p.u[a];
             p.iu[a] = -p.iu[a];
         }

@@ -31,6 +31,11 @@
 // workgroup touches only the slice [2 batches][G][nts] of the step; when that
 // fits in LDS it is accumulated there and flushed with one global atomic
 // per nonzero bin at the end of the kernel.
+//
+// Tables: the read-only tables every flight consults (union planes, time
+// edges, cross sections, speeds, per-cell material and tally bin) are
+// copied into LDS at the start of each step kernel when they fit, so the
+// dependent table lookups of a flight cost LDS latency, not cache latency.
 #include <vector>
 
 #include "k_common.hpp"
@@ -42,6 +47,7 @@ using namespace dev;
 
 constexpr int kBlock = 256;
 constexpr int kLdsTallyMax = 4096;          // doubles (32 KB)
+constexpr int kLdsTablesMax = 32 * 1024;    // bytes of staged tables
 constexpr uint32_t kHidMask = 0x0FFFFFFFu;  // history index within a chunk (< 2^28)
 
 struct Bank {
@@ -274,6 +280,44 @@ __device__ __forceinline__ void score_flight(const DevProblem &P, const RunArgs 
     }
 }
 
+// Tables staged in LDS, behind the tally slice: byte offsets and element
+// counts per table.
+enum TabId : int { kTU0, kTU1, kTU2, kTT, kTSt, kTISt, kTPs, kTCdf, kTV, kTIV, kTMat, kTTal, kTabs };
+struct LdsTables {
+    int off[kTabs];
+    int count[kTabs];
+    int bytes;
+};
+
+template <class T>
+__device__ __forceinline__ const T *stage(const T *src, const LdsTables &lt, int id, char *base) {
+    T *dst = reinterpret_cast<T *>(base + lt.off[id]);
+    for (int j = threadIdx.x; j < lt.count[id]; j += kBlock) dst[j] = src[j];
+    return dst;
+}
+
+// The problem as the step kernels see it: with LT, every staged table is
+// read from LDS (the copies need a barrier before use).
+template <bool LT>
+__device__ __forceinline__ DevProblem stage_tables(const DevProblem &P0, const LdsTables &lt, char *base) {
+    DevProblem P = P0;
+    if (LT) {
+        P.U[0] = stage(P0.U[0], lt, kTU0, base);
+        P.U[1] = stage(P0.U[1], lt, kTU1, base);
+        P.U[2] = stage(P0.U[2], lt, kTU2, base);
+        P.T = stage(P0.T, lt, kTT, base);
+        P.sigma_t = stage(P0.sigma_t, lt, kTSt, base);
+        P.inv_st = stage(P0.inv_st, lt, kTISt, base);
+        P.ps = stage(P0.ps, lt, kTPs, base);
+        P.cdf = stage(P0.cdf, lt, kTCdf, base);
+        P.speed = stage(P0.speed, lt, kTV, base);
+        P.inv_v = stage(P0.inv_v, lt, kTIV, base);
+        P.cell_mat = stage(P0.cell_mat, lt, kTMat, base);
+        P.cell_tal = stage(P0.cell_tal, lt, kTTal, base);
+    }
+    return P;
+}
+
 // ---------------------------------------------------------------------------
 // source: workgroup b samples histories [b L, (b + 1) L) of the chunk
 // ---------------------------------------------------------------------------
@@ -321,9 +365,9 @@ __global__ void __launch_bounds__(kBlock) k_source(DevProblem P, RunArgs R, Bank
 // ---------------------------------------------------------------------------
 enum Outcome : int { kNone = 0, kToNext = 1, kToSurface = 2, kToCollision = 3 };
 
-template <int FM, bool WW, int CLS = MCDC_PROF_ADVANCE>
-__global__ void __launch_bounds__(kBlock) k_advance(DevProblem P, RunArgs R, Bank cur, Bank next, Bank ev, Ctl C,
-                                                    int par, int gn, SplitBank SB) {
+template <int FM, bool WW, bool LT, int CLS = MCDC_PROF_ADVANCE>
+__global__ void __launch_bounds__(kBlock) k_advance(DevProblem P0, RunArgs R, Bank cur, Bank next, Bank ev, Ctl C,
+                                                    int par, int gn, SplitBank SB, LdsTables tabs) {
     __shared__ unsigned long long red[kCounters + 2];
     Counters cnt;
     __shared__ unsigned int cN, cS, cC;
@@ -342,6 +386,7 @@ __global__ void __launch_bounds__(kBlock) k_advance(DevProblem P, RunArgs R, Ban
     }
     StepScore sc;
     init_slice(sc, lt, gn, C.seg_b0[seg]);
+    const DevProblem P = stage_tables<LT>(P0, tabs, reinterpret_cast<char *>(lt + 2 * gn));
     __syncthreads();
     for (unsigned int j0 = 0; j0 < n; j0 += kBlock) {
         const unsigned int idx = j0 + threadIdx.x;
@@ -468,9 +513,9 @@ __device__ __forceinline__ bool to_census(const DevProblem &P, const RunArgs &R,
     }
 }
 
-template <int FM, bool WW, int EV, int CLS = (EV == kSurface) ? MCDC_PROF_SURFACE : MCDC_PROF_COLLISION>
-__global__ void __launch_bounds__(kBlock) k_event(DevProblem P, RunArgs R, Bank ev, Bank next, Ctl C, int par,
-                                                  int gn, SplitBank SB) {
+template <int FM, bool WW, bool LT, int EV, int CLS = (EV == kSurface) ? MCDC_PROF_SURFACE : MCDC_PROF_COLLISION>
+__global__ void __launch_bounds__(kBlock) k_event(DevProblem P0, RunArgs R, Bank ev, Bank next, Ctl C, int par,
+                                                  int gn, SplitBank SB, LdsTables tabs) {
     __shared__ unsigned long long red[kCounters + 2];
     Counters cnt;
     __shared__ unsigned int cN;
@@ -485,6 +530,7 @@ __global__ void __launch_bounds__(kBlock) k_event(DevProblem P, RunArgs R, Bank 
     if (threadIdx.x == 0) cN = C.n_bank[(par ^ 1) * C.G + seg];   // after the earlier kernels' appends
     StepScore sc;
     init_slice(sc, lt, gn, C.seg_b0[seg]);
+    const DevProblem P = stage_tables<LT>(P0, tabs, reinterpret_cast<char *>(lt + 2 * gn));
     __syncthreads();
     for (unsigned int j0 = 0; j0 < n; j0 += kBlock) {
         const unsigned int idx = j0 + threadIdx.x;
@@ -619,18 +665,35 @@ void key_add(std::vector<char> &k, const T &v) {
 // on both the slab and the lattice workloads.
 constexpr int kSegmentsPerCU = 4;
 
-template <int FM, bool WW>
+// Layout of the staged tables; false if they do not fit the LDS budget.
+bool table_layout(const DevProblem &P, LdsTables &t) {
+    const int64_t mg = (int64_t)P.M * P.G;
+    const int64_t cnt[kTabs] = {P.nU[0], P.nU[1], P.nU[2], P.K + 1, mg, mg, mg, mg * P.G, P.G, P.G, P.ncells, P.ncells};
+    const int64_t size[kTabs] = {8, 8, 8, 8, 8, 8, 8, 8, 8, 8, 4, 4};
+    int64_t off = 0;
+    for (int j = 0; j < kTabs; ++j) {
+        t.off[j] = (int)off;
+        t.count[j] = (int)cnt[j];
+        off += (cnt[j] * size[j] + 15) & ~(int64_t)15;
+        if (off > kLdsTablesMax) return false;
+    }
+    t.bytes = (int)off;
+    return true;
+}
+
+template <int FM, bool WW, bool LT>
 int run_event(mcdc_problem *pb, const RunArgs &R0, uint64_t first, uint64_t count, const mcdc_run_options &opt,
-              hipStream_t st, Profiler &prof) {
+              hipStream_t st, Profiler &prof, const LdsTables &tabs) {
     const DevProblem &P = pb->d;
     uint64_t C = opt.bank_capacity ? (uint64_t)opt.bank_capacity : (uint64_t)1 << 24;
     if (C > count) C = count;
     if (C > (1ULL << 28)) C = 1ULL << 28;
 
-    // per-step tally slice [2 batches][G][nts] in LDS when it fits
+    // per-step tally slice [2 batches][G][nts] in LDS when it fits, then
+    // the staged tables
     const int64_t gn64 = (int64_t)P.G * P.nts;
     const int gn = (2 * gn64 <= kLdsTallyMax) ? (int)gn64 : 0;
-    const size_t shmem = (size_t)2 * gn * sizeof(double);
+    const size_t shmem = (size_t)2 * gn * sizeof(double) + (LT ? (size_t)tabs.bytes : 0);
 
     // segments: one per workgroup
     unsigned int G;
@@ -639,7 +702,7 @@ int run_event(mcdc_problem *pb, const RunArgs &R0, uint64_t first, uint64_t coun
     } else {
         int per_cu = 0, n_cu = 0;
         hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &per_cu, reinterpret_cast<const void *>(&k_advance<FM, WW>), kBlock, shmem);
+            &per_cu, reinterpret_cast<const void *>(&k_advance<FM, WW, LT>), kBlock, shmem);
         if (e == hipSuccess) e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, pb->device);
         if (e != hipSuccess) return hip_fail(e, "occupancy query");
         if (per_cu < 1) per_cu = 1;
@@ -675,12 +738,12 @@ int run_event(mcdc_problem *pb, const RunArgs &R0, uint64_t first, uint64_t coun
     auto enqueue_step = [&](int par, hipStream_t s, Profiler &pr, const RunArgs &Ra) {
         const Bank &cur = L.bank[par];
         const Bank &nxt = L.bank[par ^ 1];
-        launch_timed(pr, MCDC_PROF_ADVANCE, k_advance<FM, WW>, dim3(G), dim3(kBlock), (uint32_t)shmem, s, P, Ra, cur,
-                     nxt, L.ev, L.ctl, par, gn, SB[0]);
-        launch_timed(pr, MCDC_PROF_SURFACE, k_event<FM, WW, kSurface>, dim3(G), dim3(kBlock), (uint32_t)shmem, s, P,
-                     Ra, L.ev, nxt, L.ctl, par, gn, SB[0]);
-        launch_timed(pr, MCDC_PROF_COLLISION, k_event<FM, WW, kCollision>, dim3(G), dim3(kBlock), (uint32_t)shmem, s,
-                     P, Ra, L.ev, nxt, L.ctl, par, gn, SB[0]);
+        launch_timed(pr, MCDC_PROF_ADVANCE, k_advance<FM, WW, LT>, dim3(G), dim3(kBlock), (uint32_t)shmem, s, P, Ra,
+                     cur, nxt, L.ev, L.ctl, par, gn, SB[0], tabs);
+        launch_timed(pr, MCDC_PROF_SURFACE, k_event<FM, WW, LT, kSurface>, dim3(G), dim3(kBlock), (uint32_t)shmem, s,
+                     P, Ra, L.ev, nxt, L.ctl, par, gn, SB[0], tabs);
+        launch_timed(pr, MCDC_PROF_COLLISION, k_event<FM, WW, LT, kCollision>, dim3(G), dim3(kBlock), (uint32_t)shmem,
+                     s, P, Ra, L.ev, nxt, L.ctl, par, gn, SB[0], tabs);
         hipLaunchKernelGGL(k_step_end, dim3(1), dim3(1), 0, s, L.ctl);
     };
 
@@ -698,6 +761,8 @@ int run_event(mcdc_problem *pb, const RunArgs &R0, uint64_t first, uint64_t coun
         key_add(key, L);
         key_add(key, gn);
         key_add(key, SB[0]);
+        key_add(key, tabs);
+        key_add(key, LT);
         if (key != Gr->key) {
             Gr->clear();
             hipError_t e = hipSuccess;
@@ -745,6 +810,13 @@ int run_event(mcdc_problem *pb, const RunArgs &R0, uint64_t first, uint64_t coun
     return MCDC_OK;
 }
 
+template <int FM, bool WW>
+int run_event_lt(mcdc_problem *p, const RunArgs &R, uint64_t first, uint64_t count, const mcdc_run_options &opt,
+                 hipStream_t st, Profiler &prof, const LdsTables &tabs, bool lt) {
+    return lt ? run_event<FM, WW, true>(p, R, first, count, opt, st, prof, tabs)
+              : run_event<FM, WW, false>(p, R, first, count, opt, st, prof, tabs);
+}
+
 }  // namespace
 
 void destroy_graph_cache(mcdc_problem *p) {
@@ -763,14 +835,16 @@ int launch_event(mcdc_problem *p, const RunArgs &R, uint64_t first, uint64_t cou
         set_error("event form supports at most 1023 batches and 131071 time bins");
         return MCDC_E_UNSUPPORTED;
     }
+    LdsTables tabs{};
+    const bool lt = table_layout(P, tabs);
     if (P.ww_center != nullptr) {
-        if (P.finite_mask == 1) return run_event<1, true>(p, R, first, count, opt, st, prof);
-        if (P.finite_mask == 7) return run_event<7, true>(p, R, first, count, opt, st, prof);
-        return run_event<0, true>(p, R, first, count, opt, st, prof);
+        if (P.finite_mask == 1) return run_event_lt<1, true>(p, R, first, count, opt, st, prof, tabs, lt);
+        if (P.finite_mask == 7) return run_event_lt<7, true>(p, R, first, count, opt, st, prof, tabs, lt);
+        return run_event_lt<0, true>(p, R, first, count, opt, st, prof, tabs, lt);
     }
-    if (P.finite_mask == 1) return run_event<1, false>(p, R, first, count, opt, st, prof);
-    if (P.finite_mask == 7) return run_event<7, false>(p, R, first, count, opt, st, prof);
-    return run_event<0, false>(p, R, first, count, opt, st, prof);
+    if (P.finite_mask == 1) return run_event_lt<1, false>(p, R, first, count, opt, st, prof, tabs, lt);
+    if (P.finite_mask == 7) return run_event_lt<7, false>(p, R, first, count, opt, st, prof, tabs, lt);
+    return run_event_lt<0, false>(p, R, first, count, opt, st, prof, tabs, lt);
 }
 
 }  // namespace mcdc
