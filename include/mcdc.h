@@ -173,13 +173,12 @@ typedef struct {
  *                 Results do not depend on it beyond summation order.
  */
 #define MCDC_FLAG_EAGER 1
-#define MCDC_PROF_CLASSES 6
+#define MCDC_PROF_CLASSES 5
 #define MCDC_PROF_SOURCE 0     /* event form: source sampling */
 #define MCDC_PROF_ADVANCE 1    /* event form: one flight over the census bank */
-#define MCDC_PROF_SURFACE 2    /* event form: surface queue, then on to census */
-#define MCDC_PROF_COLLISION 3  /* event form: collision queue, then on to census */
-#define MCDC_PROF_HISTORY 4    /* history form (and weight-window progeny) */
-#define MCDC_PROF_OTHER 5      /* fills, control, batch statistics */
+#define MCDC_PROF_EVENTS 2     /* event form: surface and collision queues, on to census */
+#define MCDC_PROF_HISTORY 3    /* history form (and weight-window progeny) */
+#define MCDC_PROF_OTHER 4      /* fills, control, batch statistics */
 typedef struct {
     int32_t algorithm;
     int32_t block_size;

@@ -61,7 +61,7 @@ class mcdc_run_options(C.Structure):
     ]
 
 
-PROF_CLASSES = ["source", "advance", "surface", "collision", "history", "other"]
+PROF_CLASSES = ["source", "advance", "events", "history", "other"]
 
 
 class mcdc_result(C.Structure):

@@ -20,12 +20,13 @@
 // Time is advanced census step by census step (the census grid is the tally
 // time grid, Section 3).  One step is a fixed kernel sequence, captured once
 // as a graph and replayed:
-//   advance(bank) -> surface(event bank front) -> collision(event bank back)
+//   advance(bank) -> events(event bank: surface queue, then collision queue)
 // advance moves each particle to its next event, scores the track-length
-// tally and files it.  The surface and collision kernels each apply their
-// queue's event to a homogeneous set of particles, then take the survivors
-// on to their census or death in registers (the few further events of the
-// step), filing census crossers into the next bank.
+// tally and files it.  The events kernel applies each queued event (surface
+// crossing or collision) and takes the survivors on to their census or
+// death in registers (the few further events of the step), filing census
+// crossers into the next bank; its lanes refill from the work list as
+// their particles finish.
 //
 // Tally: every particle scored in step k lies in time bin k, so a
 // workgroup touches only the slice [2 batches][G][nts] of the step; when that
@@ -455,123 +456,139 @@ __global__ void __launch_bounds__(kBlock) k_advance(DevProblem P0, RunArgs R, Ba
 }
 
 // ---------------------------------------------------------------------------
-// surface / collision: apply the queue's event, then the rest of the step
+// events: apply each queued event, then the rest of the step, in registers
 // ---------------------------------------------------------------------------
-// Takes a particle that survived its queued event on to its census (returns
-// true: file it in the next bank) or its death, in registers.  The event
-// cap counts flights from here.
-template <int FM, bool WW>
-__device__ __forceinline__ bool to_census(const DevProblem &P, const RunArgs &R, const SplitBank &SB, StepScore &sc,
-                                          Counters &cnt, Particle &p, int cell, int b, uint64_t i, uint32_t hid) {
-    for (int since = 0;; ++since) {
-        if (since >= kMaxEventsPerStep) {
-            cnt.add(3 + kLost);
-            hist_term(R, i, kLost);
-            return false;
-        }
-        const Flight f = next_event<FM>(P, p, cell);
-        if (f.d == kInf) {
-            cnt.add(3 + kLost);
-            hist_term(R, i, kLost);
-            return false;
-        }
-        score_flight(P, R, sc, p, cell, b, i, hid, f.d);
-        move<FM>(P, p, f);
-        if (f.ev == kCensus) {
-            cnt.add(0);
-            hist_event(R, i, 0);
-            p.k += 1;
-            if (p.k == P.K) {
-                cnt.add(3 + kTime);
-                hist_term(R, i, kTime);
-                return false;
-            }
-            return ww_point<WW>(P, R, SB, p, cell, b, i, cnt);
-        } else if (f.ev == kSurface) {
-            cnt.add(1);
-            hist_event(R, i, 1);
-            const int old_ww = WW ? P.cell_ww[cell] : 0;
-            const int face = cross<FM>(P, p, crossing_mask<FM>(P, f));
-            if (face >= 0) {
-                atomic_add_f64(R.L + (((int64_t)b * P.K + p.k) * P.G + p.g) * 6 + face, p.w);
-                cnt.add(3 + kLeak);
-                hist_term(R, i, kLeak);
-                return false;
-            }
-            cell = cell_index(P, p.ix);
-            if (WW && P.cell_ww[cell] != old_ww && !ww_point<WW>(P, R, SB, p, cell, b, i, cnt)) return false;
-        } else {
-            cnt.add(2);
-            hist_event(R, i, 2);
-            if (!collide<FM>(P, p, f.m)) {
-                cnt.add(3 + kAbsorb);
-                hist_term(R, i, kAbsorb);
-                return false;
-            }
-            if (!ww_point<WW>(P, R, SB, p, cell, b, i, cnt)) return false;
-        }
-    }
-}
-
-template <int FM, bool WW, bool LT, int EV, int CLS = (EV == kSurface) ? MCDC_PROF_SURFACE : MCDC_PROF_COLLISION>
+// One launch takes both queues of a segment as one work list (surface
+// particles first, then collision particles).  A lane whose particle has
+// reached its census or died takes the next item of the list at once, so
+// a wave is never held back by its longest-lived particle while work is
+// left.  Each item starts with its queued event; every later step of it
+// is a flight to the next event and that event.  The event cap counts
+// flights from the item's start.
+template <int FM, bool WW, bool LT, int CLS = MCDC_PROF_EVENTS>
 __global__ void __launch_bounds__(kBlock) k_event(DevProblem P0, RunArgs R, Bank ev, Bank next, Ctl C, int par,
                                                   int gn, SplitBank SB, LdsTables tabs) {
     __shared__ unsigned long long red[kCounters + 2];
+    __shared__ unsigned int cN, cW;
     Counters cnt;
-    __shared__ unsigned int cN;
     extern __shared__ double lt[];
     const unsigned int seg = blockIdx.x;
     const uint32_t seg0 = seg * C.L;
     const uint32_t seg_end = seg0 + C.L - 1;
-    const unsigned int n = (EV == kSurface) ? C.n_s[seg] : C.n_c[seg];
+    const unsigned int n_s = C.n_s[seg];
+    const unsigned int n = n_s + C.n_c[seg];
     const int step = *C.step;
     const uint64_t first = *C.first;
     cnt.init(red);
-    if (threadIdx.x == 0) cN = C.n_bank[(par ^ 1) * C.G + seg];   // after the earlier kernels' appends
+    if (threadIdx.x == 0) {
+        cN = C.n_bank[(par ^ 1) * C.G + seg];   // after the advance kernel's census crossers
+        cW = 0u;
+    }
     StepScore sc;
     init_slice(sc, lt, gn, C.seg_b0[seg]);
     const DevProblem P = stage_tables<LT>(P0, tabs, reinterpret_cast<char *>(lt + 2 * gn));
     __syncthreads();
-    for (unsigned int j0 = 0; j0 < n; j0 += kBlock) {
-        const unsigned int idx = j0 + threadIdx.x;
-        const bool valid = idx < n;
+
+    Particle p;
+    uint32_t gk = 0, hid = 0;
+    int cell = 0, b = 0, queued = kCensus, mask = 0, since = 0;
+    uint64_t i = 0;
+    bool busy = false, exhausted = false;
+    for (;;) {
+        // idle lanes take the next items of the work list
+        if (!exhausted) {
+            const bool need = !busy;
+            const uint32_t w = block_append(need, &cW);
+            if (need && w < n) {
+                uint32_t hidw;
+                load_state<FM, WW>(P, ev, (w < n_s) ? seg0 + w : seg_end - (w - n_s), p, gk, hidw);
+                hid = hidw & kHidMask;
+                mask = (int)(hidw >> 29);
+                queued = (w < n_s) ? kSurface : kCollision;
+                i = first + hid;
+                b = (gk >> 5) & 1023u;
+                cell = cell_index(P, p.ix);
+                since = 0;
+                busy = true;
+                if (R.prof) cnt.prof(1u, state_bytes<FM, WW>(P));
+            }
+            exhausted = __ballot(need && w >= n) != 0;
+        }
+        if (!__any(busy)) break;
         bool to_next = false;
-        Particle p;
-        uint32_t gk = 0, hid = 0;
-        if (valid) {
-            uint32_t hidw;
-            load_state<FM, WW>(P, ev, (EV == kSurface) ? seg0 + idx : seg_end - idx, p, gk, hidw);
-            hid = hidw & kHidMask;
-            const uint64_t i = first + hid;
-            const int b = (gk >> 5) & 1023u;
-            int cell = cell_index(P, p.ix);
-            bool alive;
-            if (EV == kSurface) {
-                const int old_ww = WW ? P.cell_ww[cell] : 0;
-                const int face = cross<FM>(P, p, (int)(hidw >> 29));
-                if (face >= 0) {
-                    atomic_add_f64(R.L + (((int64_t)b * P.K + p.k) * P.G + p.g) * 6 + face, p.w);
-                    cnt.add(3 + kLeak);
-                    hist_term(R, i, kLeak);
-                    alive = false;
+        if (busy) {
+            int evt = queued;
+            bool flown = true;
+            if (queued == kCensus) {
+                // a flight to the next event
+                if (since >= kMaxEventsPerStep) {
+                    cnt.add(3 + kLost);
+                    hist_term(R, i, kLost);
+                    busy = false;
+                    flown = false;
                 } else {
-                    cell = cell_index(P, p.ix);
-                    alive = !WW || P.cell_ww[cell] == old_ww || ww_point<WW>(P, R, SB, p, cell, b, i, cnt);
-                }
-            } else {
-                alive = collide<FM>(P, p, P.cell_mat[cell]);
-                if (!alive) {
-                    cnt.add(3 + kAbsorb);
-                    hist_term(R, i, kAbsorb);
-                } else {
-                    alive = ww_point<WW>(P, R, SB, p, cell, b, i, cnt);
+                    ++since;
+                    const Flight f = next_event<FM>(P, p, cell);
+                    if (f.d == kInf) {
+                        cnt.add(3 + kLost);
+                        hist_term(R, i, kLost);
+                        busy = false;
+                        flown = false;
+                    } else {
+                        score_flight(P, R, sc, p, cell, b, i, hid, f.d);
+                        move<FM>(P, p, f);
+                        evt = f.ev;
+                        if (evt == kSurface) mask = crossing_mask<FM>(P, f);
+                        if (evt == kCensus)
+                            cnt.add(0);
+                        else if (evt == kSurface)
+                            cnt.add(1);
+                        else
+                            cnt.add(2);
+                        hist_event(R, i, evt);   // census 0, surface 1, collision 2
+                    }
                 }
             }
-            if (alive) to_next = to_census<FM, WW>(P, R, SB, sc, cnt, p, cell, b, i, hid);
+            queued = kCensus;   // from here on: flights
+            if (flown) {
+                if (evt == kCensus) {
+                    p.k += 1;
+                    if (p.k == P.K) {
+                        cnt.add(3 + kTime);
+                        hist_term(R, i, kTime);
+                    } else {
+                        to_next = ww_point<WW>(P, R, SB, p, cell, b, i, cnt);
+                    }
+                    busy = false;
+                } else if (evt == kSurface) {
+                    const int old_ww = WW ? P.cell_ww[cell] : 0;
+                    const int face = cross<FM>(P, p, mask);
+                    if (face >= 0) {
+                        atomic_add_f64(R.L + (((int64_t)b * P.K + p.k) * P.G + p.g) * 6 + face, p.w);
+                        cnt.add(3 + kLeak);
+                        hist_term(R, i, kLeak);
+                        busy = false;
+                    } else {
+                        cell = cell_index(P, p.ix);
+                        if (WW && P.cell_ww[cell] != old_ww && !ww_point<WW>(P, R, SB, p, cell, b, i, cnt))
+                            busy = false;
+                    }
+                } else {
+                    if (!collide<FM>(P, p, P.cell_mat[cell])) {
+                        cnt.add(3 + kAbsorb);
+                        hist_term(R, i, kAbsorb);
+                        busy = false;
+                    } else if (!ww_point<WW>(P, R, SB, p, cell, b, i, cnt)) {
+                        busy = false;
+                    }
+                }
+            }
         }
         const uint32_t ns = block_append(to_next, &cN);
-        if (to_next) store_state<FM, WW>(P, next, seg0 + ns, p, with_gk(gk, p), hid);
-        if (R.prof && valid) cnt.prof(1u, state_bytes<FM, WW>(P) * (to_next ? 2u : 1u));
+        if (to_next) {
+            store_state<FM, WW>(P, next, seg0 + ns, p, with_gk(gk, p), hid);
+            if (R.prof) cnt.prof(0u, state_bytes<FM, WW>(P));
+        }
     }
     flush_slice(P, R, sc, step);
     if (threadIdx.x == 0) C.n_bank[(par ^ 1) * C.G + seg] = cN;
@@ -740,10 +757,8 @@ int run_event(mcdc_problem *pb, const RunArgs &R0, uint64_t first, uint64_t coun
         const Bank &nxt = L.bank[par ^ 1];
         launch_timed(pr, MCDC_PROF_ADVANCE, k_advance<FM, WW, LT>, dim3(G), dim3(kBlock), (uint32_t)shmem, s, P, Ra,
                      cur, nxt, L.ev, L.ctl, par, gn, SB[0], tabs);
-        launch_timed(pr, MCDC_PROF_SURFACE, k_event<FM, WW, LT, kSurface>, dim3(G), dim3(kBlock), (uint32_t)shmem, s,
-                     P, Ra, L.ev, nxt, L.ctl, par, gn, SB[0], tabs);
-        launch_timed(pr, MCDC_PROF_COLLISION, k_event<FM, WW, LT, kCollision>, dim3(G), dim3(kBlock), (uint32_t)shmem,
-                     s, P, Ra, L.ev, nxt, L.ctl, par, gn, SB[0], tabs);
+        launch_timed(pr, MCDC_PROF_EVENTS, k_event<FM, WW, LT>, dim3(G), dim3(kBlock), (uint32_t)shmem, s, P, Ra,
+                     L.ev, nxt, L.ctl, par, gn, SB[0], tabs);
         hipLaunchKernelGGL(k_step_end, dim3(1), dim3(1), 0, s, L.ctl);
     };
 
