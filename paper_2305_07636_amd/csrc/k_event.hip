@@ -182,6 +182,52 @@ __device__ __forceinline__ void load_state(const DevProblem &P, const Bank &B, u
     p.k = gk >> 15;
 }
 
+// The state of one particle as loaded, before any arithmetic on it: lets
+// a kernel issue the loads of its next particle before working on the
+// current one.
+struct RawState {
+    double x[3], u[3], t, tau, w;
+    uint64_t s;
+    uint32_t c, gk, hidw;
+};
+
+template <int FM, bool WW>
+__device__ __forceinline__ void load_raw(const DevProblem &P, const Bank &B, uint32_t slot, RawState &r) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (finite_axis<FM>(P, a)) {
+            r.x[a] = B.x[a][slot];
+            r.u[a] = B.u[a][slot];
+        }
+    }
+    r.t = B.t[slot];
+    r.tau = B.tau[slot];
+    if (WW) r.w = B.w[slot];
+    r.s = B.s[slot];
+    r.c = B.ixyz[slot];
+    r.gk = B.gk[slot];
+    r.hidw = B.hid[slot];
+}
+
+template <int FM, bool WW>
+__device__ __forceinline__ void unpack(const DevProblem &P, const RawState &r, Particle &p) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        p.x[a] = finite_axis<FM>(P, a) ? r.x[a] : 0.0;
+        p.u[a] = finite_axis<FM>(P, a) ? r.u[a] : 0.0;
+    }
+    p.t = r.t;
+    p.tau = r.tau;
+    p.w = WW ? r.w : 1.0;
+    p.s = r.s;
+    set_inverse<FM>(P, p);
+    p.ix[0] = r.c & 2047u;
+    p.ix[1] = (r.c >> 11) & 2047u;
+    p.ix[2] = r.c >> 22;
+    p.g = r.gk & 31u;
+    p.k = r.gk >> 15;
+}
+
 template <int FM, bool WW>
 __device__ __forceinline__ void store_state(const DevProblem &P, const Bank &B, uint32_t slot,
                                             const Particle &p, uint32_t gk, uint32_t hidw) {
@@ -389,6 +435,10 @@ __global__ void __launch_bounds__(kBlock) k_advance(DevProblem P0, RunArgs R, Ba
     init_slice(sc, lt, gn, C.seg_b0[seg]);
     const DevProblem P = stage_tables<LT>(P0, tabs, reinterpret_cast<char *>(lt + 2 * gn));
     __syncthreads();
+    // software pipeline: the next particle's state is in flight while the
+    // current one is moved
+    RawState nx;
+    if (threadIdx.x < n) load_raw<FM, WW>(P, cur, seg0 + threadIdx.x, nx);
     for (unsigned int j0 = 0; j0 < n; j0 += kBlock) {
         const unsigned int idx = j0 + threadIdx.x;
         const bool valid = idx < n;
@@ -396,8 +446,12 @@ __global__ void __launch_bounds__(kBlock) k_advance(DevProblem P0, RunArgs R, Ba
         int mask = 0;
         Particle p;
         uint32_t gk = 0, hid = 0;
+        const RawState rs = nx;
+        if (idx + kBlock < n) load_raw<FM, WW>(P, cur, seg0 + idx + kBlock, nx);
         if (valid) {
-            load_state<FM, WW>(P, cur, seg0 + idx, p, gk, hid);
+            unpack<FM, WW>(P, rs, p);
+            gk = rs.gk;
+            hid = rs.hidw;
             if (p.k > step) {
                 outcome = kToNext;   // born in a later time bin: wait
             } else {
