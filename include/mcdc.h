@@ -137,7 +137,8 @@ typedef struct {
  *  algorithm      MCDC_ALG_EVENT (default) or MCDC_ALG_HISTORY.
  *  block_size     mcdc_run_batched: threads per block of the persistent
  *                 launch (64..1024, multiple of 64; 0 = autotuned).  The
- *                 kernels of mcdc_run use 256 in both forms.
+ *                 kernels of mcdc_run use 256 (history form) and 512
+ *                 (event form).
  *  bank_capacity  event form: particles resident at once (0 = auto).  Work
  *                 is processed in chunks of this many histories.
  *  flags          bit 0 (MCDC_FLAG_EAGER): launch the event form's census
@@ -168,7 +169,7 @@ typedef struct {
  *                 captured step graphs uninstrumented.  Runs with phases
  *                 0 .. profile_every-1 together sample every step once.
  *  segments       event form: bank segments, one per workgroup of every
- *                 event kernel (0 = auto: 4 per compute unit, or fewer if
+ *                 event kernel (0 = auto: 2 per compute unit, or fewer if
  *                 the advance kernel cannot hold that many resident).
  *                 Results do not depend on it beyond summation order.
  */

@@ -46,7 +46,7 @@ namespace {
 
 using namespace dev;
 
-constexpr int kBlock = 256;
+constexpr int kBlock = 512;
 constexpr int kLdsTallyMax = 4096;          // doubles (32 KB)
 constexpr int kLdsTablesMax = 32 * 1024;    // bytes of staged tables
 constexpr uint32_t kHidMask = 0x0FFFFFFFu;  // history index within a chunk (< 2^28)
@@ -730,11 +730,13 @@ void key_add(std::vector<char> &k, const T &v) {
     k.insert(k.end(), p, p + sizeof(T));
 }
 
-// Workgroups (= segments) per CU when the caller leaves it open: fewer,
-// longer-running workgroups than the advance kernel could hold resident
-// keep fewer concurrent streams open per HBM channel and measured faster
-// on both the slab and the lattice workloads.
-constexpr int kSegmentsPerCU = 4;
+// Workgroups (= segments) per CU when the caller leaves it open.  Each
+// segment streams its own slice of every bank array, so fewer, larger
+// workgroups keep fewer concurrent streams open per HBM channel: two
+// 512-thread workgroups per CU (16 waves) measured fastest on both the slab
+// and the lattice workloads (four 256-thread ones: 5 % slower; segment
+// counts that are not a multiple of the CU count: 10-20 % slower).
+constexpr int kSegmentsPerCU = 2;
 
 // Layout of the staged tables; false if they do not fit the LDS budget.
 bool table_layout(const DevProblem &P, LdsTables &t) {
