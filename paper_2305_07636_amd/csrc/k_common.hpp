@@ -402,6 +402,23 @@ __device__ __forceinline__ void atomic_add_f64(double *a, double v) {
     unsafeAtomicAdd(a, v);
 }
 
+// The tally copy of batch b this workgroup adds into.  Consecutive
+// workgroups go to different XCDs, so with X a multiple of 8 each copy is
+// touched by one XCD's L2 only, and concurrent flights of the same batch
+// spread their atomics over X addresses per bin.
+__device__ __forceinline__ double *tally_copy(const DevProblem &P, const RunArgs &R, int b) {
+    return R.S + ((int64_t)b * R.X + (int64_t)(blockIdx.x & (unsigned)(R.X - 1))) * P.ntally;
+}
+
+// Weight leaked through a face, into this workgroup's copy of the leakage
+// tally (a handful of bins per batch that every leaking particle hits).
+__device__ __forceinline__ void add_leak(const DevProblem &P, const RunArgs &R, int b, int k, int g, int face,
+                                         double w) {
+    const int64_t nl = (int64_t)P.K * P.G * 6;
+    double *L = R.L + ((int64_t)b * R.XL + (int64_t)(blockIdx.x & (unsigned)(R.XL - 1))) * nl;
+    atomic_add_f64(L + ((int64_t)k * P.G + g) * 6 + face, w);
+}
+
 }  // namespace dev
 
 // Split bank of the weight-window game (k_history.hip): carve two

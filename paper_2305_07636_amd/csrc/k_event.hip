@@ -286,7 +286,7 @@ struct StepScore {
             atomicAdd(&lt[rel * gn + g * P.nts + tb], v);
             scored = true;
         } else {
-            atomic_add_f64(R.S + (int64_t)b * P.ntally + ((int64_t)k * P.G + g) * P.nts + tb, v);
+            atomic_add_f64(tally_copy(P, R, b) + ((int64_t)k * P.G + g) * P.nts + tb, v);
         }
     }
 };
@@ -308,7 +308,7 @@ __device__ __forceinline__ void flush_slice(const DevProblem &P, const RunArgs &
         const double v = sc.lt[j];
         const int b = sc.b0 + j / sc.gn;
         if (v != 0.0 && b < R.B)
-            atomic_add_f64(R.S + (int64_t)b * P.ntally + (int64_t)step * sc.gn + (j % sc.gn), v);
+            atomic_add_f64(tally_copy(P, R, b) + (int64_t)step * sc.gn + (j % sc.gn), v);
     }
 }
 
@@ -618,7 +618,7 @@ __global__ void __launch_bounds__(kBlock) k_event(DevProblem P0, RunArgs R, Bank
                     const int old_ww = WW ? P.cell_ww[cell] : 0;
                     const int face = cross<FM>(P, p, mask);
                     if (face >= 0) {
-                        atomic_add_f64(R.L + (((int64_t)b * P.K + p.k) * P.G + p.g) * 6 + face, p.w);
+                        add_leak(P, R, b, p.k, p.g, face, p.w);
                         cnt.add(3 + kLeak);
                         hist_term(R, i, kLeak);
                         busy = false;

@@ -6,9 +6,17 @@
 namespace mcdc {
 namespace {
 
-// One thread per tally bin j: S is [B][ntally] raw sums, norm_j = dt_k * V_s.
+// Raw sum of batch b in bin j over its X tally copies (fixed order).
+__device__ __forceinline__ double batch_sum(const double *S, int64_t ntally, int X, int b, int64_t j) {
+    double v = 0.0;
+    for (int x = 0; x < X; ++x) v += S[((int64_t)b * X + x) * ntally + j];
+    return v;
+}
+
+// One thread per tally bin j: S is [B][X][ntally] raw sums (X copies per
+// batch), norm_j = dt_k * V_s.
 __global__ void __launch_bounds__(256) k_fold(const double *__restrict__ S, int64_t ntally,
-                                              int B, uint64_t N, int G, int nts,
+                                              int B, int X, uint64_t N, int G, int nts,
                                               const double *__restrict__ bin_norm,
                                               const double *__restrict__ time_norm,
                                               double *mean, double *var, double *raw) {
@@ -18,35 +26,36 @@ __global__ void __launch_bounds__(256) k_fold(const double *__restrict__ S, int6
     const int s = (int)(j % nts);
     const double norm = time_norm[k] * bin_norm[s];
     double total = 0.0;
-    for (int b = 0; b < B; ++b) total += S[(int64_t)b * ntally + j];
+    for (int b = 0; b < B; ++b) total += batch_sum(S, ntally, X, b, j);
     if (raw) raw[j] = total;
     if (mean) mean[j] = total / ((double)N * norm);
     if (var) {
         double mb_sum = 0.0;
         for (int b = 0; b < B; ++b) {
             const uint64_t nb = ((uint64_t)(b + 1) * N) / B - ((uint64_t)b * N) / B;
-            mb_sum += S[(int64_t)b * ntally + j] / ((double)nb * norm);
+            mb_sum += batch_sum(S, ntally, X, b, j) / ((double)nb * norm);
         }
         const double mbar = mb_sum / B;
         double acc = 0.0;
         for (int b = 0; b < B; ++b) {
             const uint64_t nb = ((uint64_t)(b + 1) * N) / B - ((uint64_t)b * N) / B;
-            const double d = S[(int64_t)b * ntally + j] / ((double)nb * norm) - mbar;
+            const double d = batch_sum(S, ntally, X, b, j) / ((double)nb * norm) - mbar;
             acc += d * d;
         }
         var[j] = (B > 1) ? acc / ((double)B * (double)(B - 1)) : 0.0;
     }
 }
 
-// Leakage per face: same statistics with unit normalisation.
-__global__ void k_fold_leak(const double *__restrict__ L, int n, int B, uint64_t N,
+// Leakage per face: same statistics with unit normalisation (L is
+// [B][XL][n], XL copies per batch).
+__global__ void k_fold_leak(const double *__restrict__ L, int n, int B, int XL, uint64_t N,
                             double *mean, double *var) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= n) return;
     double total = 0.0, mb_sum = 0.0;
     for (int b = 0; b < B; ++b) {
         const uint64_t nb = ((uint64_t)(b + 1) * N) / B - ((uint64_t)b * N) / B;
-        const double v = L[(int64_t)b * n + j];
+        const double v = batch_sum(L, n, XL, b, j);
         total += v;
         mb_sum += v / (double)nb;
     }
@@ -56,7 +65,7 @@ __global__ void k_fold_leak(const double *__restrict__ L, int n, int B, uint64_t
         double acc = 0.0;
         for (int b = 0; b < B; ++b) {
             const uint64_t nb = ((uint64_t)(b + 1) * N) / B - ((uint64_t)b * N) / B;
-            const double d = L[(int64_t)b * n + j] / (double)nb - mbar;
+            const double d = batch_sum(L, n, XL, b, j) / (double)nb - mbar;
             acc += d * d;
         }
         var[j] = (B > 1) ? acc / ((double)B * (double)(B - 1)) : 0.0;
@@ -93,19 +102,19 @@ __global__ void __launch_bounds__(256) k_qoi_reduce(const double *__restrict__ q
 
 }  // namespace
 
-int launch_fold(const DevProblem &P, const double *S, const double *L, int B, uint64_t N,
+int launch_fold(const DevProblem &P, const double *S, const double *L, int B, int X, int XL, uint64_t N,
                 const double *bin_norm_dev, const double *time_norm_dev, double *mean,
                 double *var, double *raw, double *leak_mean, double *leak_var,
                 hipStream_t st) {
     const int bs = 256;
     if (mean || var || raw) {
         const unsigned grid = (unsigned)((P.ntally + bs - 1) / bs);
-        hipLaunchKernelGGL(k_fold, dim3(grid), dim3(bs), 0, st, S, P.ntally, B, N, P.G, P.nts,
+        hipLaunchKernelGGL(k_fold, dim3(grid), dim3(bs), 0, st, S, P.ntally, B, X, N, P.G, P.nts,
                            bin_norm_dev, time_norm_dev, mean, var, raw);
     }
     if (leak_mean || leak_var) {
         const int n = P.K * P.G * 6;
-        hipLaunchKernelGGL(k_fold_leak, dim3((n + bs - 1) / bs), dim3(bs), 0, st, L, n, B, N,
+        hipLaunchKernelGGL(k_fold_leak, dim3((n + bs - 1) / bs), dim3(bs), 0, st, L, n, B, XL, N,
                            leak_mean, leak_var);
     }
     return (int)hipGetLastError();

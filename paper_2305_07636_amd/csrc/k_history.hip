@@ -25,131 +25,237 @@ struct Acc {
     double track = 0.0, qoi = 0.0;
 };
 
+// One flight of a particle of history hid and its event; returns the
+// termination code, or -1 while the particle lives.  Split progeny go to
+// the split bank.
+template <int FM, bool WW>
+__device__ __forceinline__ int hstep(const DevProblem &P, const RunArgs &R, Particle &p, int &cell, int b,
+                                     uint64_t hid, Acc &acc, const SplitBank &SB, int &since) {
+    if (since >= kMaxEventsPerStep) return kLost;
+    ++since;
+    const Flight f = next_event<FM>(P, p, cell);
+    if (f.d == kInf) return kLost;
+    const double sc = p.w * f.d;
+    const int tb = P.cell_tal[cell];
+    if (tb >= 0) {
+        atomic_add_f64(tally_copy(P, R, b) + ((int64_t)p.k * P.G + p.g) * P.nts + tb, sc);
+        acc.track += sc;
+    }
+    if (P.qoi_on && P.cell_qoi[cell] && P.qoi_groups[p.g]) acc.qoi += sc;
+    move<FM>(P, p, f);
+    bool check = false;
+    int code = -1;
+    if (f.ev == kCensus) {
+        ++acc.n_ev[0];
+        since = 0;
+        p.k += 1;
+        if (p.k == P.K)
+            code = kTime;
+        else
+            check = WW;
+    } else if (f.ev == kSurface) {
+        ++acc.n_ev[1];
+        const int old_ww = WW ? P.cell_ww[cell] : 0;
+        const int face = cross<FM>(P, p, crossing_mask<FM>(P, f));
+        if (face >= 0) {
+            add_leak(P, R, b, p.k, p.g, face, p.w);
+            code = kLeak;
+        } else {
+            cell = cell_index(P, p.ix);
+            check = WW && (P.cell_ww[cell] != old_ww);
+        }
+    } else {
+        ++acc.n_ev[2];
+        if (!collide<FM>(P, p, f.m))
+            code = kAbsorb;
+        else
+            check = WW;
+    }
+    if (WW && check) {
+        int nc = 0;
+        if (!ww_check(P, p, cell, nc)) {
+            code = kRoulette;
+        } else if (nc > 0) {
+            if (!spawn_children(SB, p, nc, b, hid)) *R.overflow = 1;
+            acc.spawned += (unsigned int)nc;
+        }
+    }
+    return code;
+}
+
 // Track one particle of history hid until it terminates; returns the
-// termination code (also ORed into acc.term_mask).  Split progeny go to the
-// split bank.
+// termination code (also ORed into acc.term_mask).
 template <int FM, bool WW>
 __device__ __forceinline__ int track(const DevProblem &P, const RunArgs &R, Particle &p, int b, uint64_t hid,
                                      Acc &acc, const SplitBank &SB) {
-    double *S = R.S + (int64_t)b * P.ntally;
     int cell = cell_index(P, p.ix);
     int since = 0;
-    int code = -1;
-    while (code < 0) {
-        if (since >= kMaxEventsPerStep) {
-            code = kLost;
-            break;
-        }
-        ++since;
-        const Flight f = next_event<FM>(P, p, cell);
-        if (f.d == kInf) {
-            code = kLost;
-            break;
-        }
-        const double sc = p.w * f.d;
-        const int tb = P.cell_tal[cell];
-        if (tb >= 0) {
-            atomic_add_f64(S + ((int64_t)p.k * P.G + p.g) * P.nts + tb, sc);
-            acc.track += sc;
-        }
-        if (P.qoi_on && P.cell_qoi[cell] && P.qoi_groups[p.g]) acc.qoi += sc;
-        move<FM>(P, p, f);
-        bool check = false;
-        if (f.ev == kCensus) {
-            ++acc.n_ev[0];
-            since = 0;
-            p.k += 1;
-            if (p.k == P.K)
-                code = kTime;
-            else
-                check = WW;
-        } else if (f.ev == kSurface) {
-            ++acc.n_ev[1];
-            const int old_ww = WW ? P.cell_ww[cell] : 0;
-            const int face = cross<FM>(P, p, crossing_mask<FM>(P, f));
-            if (face >= 0) {
-                atomic_add_f64(R.L + (((int64_t)b * P.K + p.k) * P.G + p.g) * 6 + face, p.w);
-                code = kLeak;
-            } else {
-                cell = cell_index(P, p.ix);
-                check = WW && (P.cell_ww[cell] != old_ww);
-            }
-        } else {
-            ++acc.n_ev[2];
-            if (!collide<FM>(P, p, f.m))
-                code = kAbsorb;
-            else
-                check = WW;
-        }
-        if (WW && check) {
-            int nc = 0;
-            if (!ww_check(P, p, cell, nc)) {
-                code = kRoulette;
-            } else if (nc > 0) {
-                if (!spawn_children(SB, p, nc, b, hid)) *R.overflow = 1;
-                acc.spawned += (unsigned int)nc;
-            }
-        }
-    }
+    int code;
+    do {
+        code = hstep<FM, WW>(P, R, p, cell, b, hid, acc, SB, since);
+    } while (code < 0);
     acc.term_mask |= 1u << code;
     return code;
 }
 
+// Per-lane totals of the persistent kernel, kept in registers (every
+// index a compile-time constant) and reduced once at the end.
+struct LaneTotals {
+    unsigned int c[kCounters];
+    double q[2];
+    unsigned long long started;
+    __device__ __forceinline__ void init() {
+#pragma unroll
+        for (int j = 0; j < kCounters; ++j) c[j] = 0u;
+        q[0] = q[1] = 0.0;
+        started = 0ull;
+    }
+    __device__ __forceinline__ void term(int code) {
+        if (code == kAbsorb)
+            c[3 + kAbsorb] += 1u;
+        else if (code == kLeak)
+            c[3 + kLeak] += 1u;
+        else if (code == kTime)
+            c[3 + kTime] += 1u;
+        else if (code == kLost)
+            c[3 + kLost] += 1u;
+        else
+            c[3 + kRoulette] += 1u;
+    }
+};
+
+// A history's records once its source particle has terminated (its split
+// progeny, tracked in later launches, add theirs with atomics, so plain
+// stores here come first).
+template <bool WW>
+__device__ __forceinline__ void end_history(const DevProblem &P, const RunArgs &R, const Acc &acc, int code,
+                                            uint64_t i, uint64_t chunk_first, LaneTotals &lt) {
+    lt.term(code);
+    if (R.dbg_counts) {
+        uint32_t *d = R.dbg_counts + i * 5;
+        d[0] = acc.n_ev[0];
+        d[1] = acc.n_ev[1];
+        d[2] = acc.n_ev[2];
+        d[3] = 1u + acc.spawned;
+        d[4] = acc.term_mask;
+    }
+    if (R.dbg_scores) {
+        R.dbg_scores[i * 2 + 0] = acc.track;
+        R.dbg_scores[i * 2 + 1] = acc.qoi;
+    }
+    if (WW) {
+        if (P.qoi_on) R.qoi_hist[i - chunk_first] = acc.qoi;
+    } else if (P.qoi_on) {
+        lt.q[0] += acc.qoi;
+        lt.q[1] += acc.qoi * acc.qoi;
+    }
+    lt.c[0] += acc.n_ev[0];
+    lt.c[1] += acc.n_ev[1];
+    lt.c[2] += acc.n_ev[2];
+    lt.c[8] += acc.spawned;
+}
+
+// Idle lanes that trigger a refill.  The histories a wave takes from the
+// device-wide counter at a time scale with the job (about 16 takes per
+// wave), so short histories do not serialise on that one counter.
+constexpr int kRefillMin = 32;
+
+// Persistent history form: every wave takes chunks of consecutive histories
+// [first, first + count) from a device counter; a lane whose particle has
+// terminated starts the next history of the wave's chunk at once, so a
+// wave is not held back by its longest history.  Every wave exits once the
+// counter has passed the end and its lanes are idle.
 template <int FM, bool WW>
 __global__ void __launch_bounds__(256) k_history(DevProblem P, RunArgs R, uint64_t first, uint64_t count,
-                                                 uint64_t chunk_first, SplitBank SB) {
-    __shared__ BlockCounters bc;
+                                                 uint64_t chunk_first, SplitBank SB, unsigned long long *next,
+                                                 unsigned int wave_chunk) {
+    __shared__ unsigned long long red[kCounters + 1];
     __shared__ double qsum[2];
-    if (threadIdx.x < kCounters) bc.c[threadIdx.x] = 0u;
+    if (threadIdx.x < kCounters + 1) red[threadIdx.x] = 0ull;
     if (threadIdx.x < 2) qsum[threadIdx.x] = 0.0;
     __syncthreads();
 
-    const uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r < count) {
-        const uint64_t i = first + r;
-        const int b = (int)(((i + 1) * (uint64_t)R.B - 1) / R.N);
-        Particle p;
-        Acc acc;
-        if (!birth<FM>(P, history_stream(P, R.seed, i), p)) {
-            acc.term_mask = 1u << kTime;
-            atomicAdd(&bc.c[3 + kTime], 1u);
-        } else {
-            atomicAdd(&bc.c[3 + track<FM, WW>(P, R, p, b, i, acc, SB)], 1u);
+    uint64_t c_pos = 0, c_end = 0;   // the wave's current chunk (wave-uniform)
+    bool drained = false;            // the device counter has passed the end
+    LaneTotals tot;
+    tot.init();
+    Particle p;
+    Acc acc;
+    int b = 0, cell = 0, since = 0;
+    uint64_t i = 0;
+    bool busy = false;
+    for (;;) {
+        // idle lanes start the next histories of the chunk, once enough of
+        // them are idle that the births run at a useful SIMD width
+        uint64_t need = __ballot(!busy);
+        if (__popcll(need) < kRefillMin && need != ~0ull) need = 0;
+        while (need && !drained) {
+            if (c_pos == c_end) {
+                unsigned long long base = 0;
+                if (__lane_id() == 0) base = atomicAdd(next, (unsigned long long)wave_chunk);
+                base = __shfl(base, 0);
+                if (base >= count) {
+                    drained = true;
+                    break;
+                }
+                c_pos = base;
+                c_end = (base + wave_chunk < count) ? base + wave_chunk : count;
+            }
+            const uint64_t avail = c_end - c_pos;
+            const uint32_t rank =
+                __builtin_amdgcn_mbcnt_hi((uint32_t)(need >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)need, 0u));
+            const uint32_t n_need = (uint32_t)__popcll(need);
+            if (!busy && rank < avail) {
+                i = first + c_pos + rank;
+                b = (int)(((i + 1) * (uint64_t)R.B - 1) / R.N);
+                acc = Acc();
+                ++tot.started;
+                if (birth<FM>(P, history_stream(P, R.seed, i), p)) {
+                    cell = cell_index(P, p.ix);
+                    since = 0;
+                    busy = true;
+                } else {
+                    acc.term_mask = 1u << kTime;
+                    end_history<WW>(P, R, acc, kTime, i, chunk_first, tot);
+                }
+            }
+            c_pos += (n_need < avail) ? n_need : avail;
+            need = __ballot(!busy);
         }
-        // children of this history are tracked in later launches, so plain
-        // stores here precede their atomic updates
-        if (R.dbg_counts) {
-            uint32_t *d = R.dbg_counts + i * 5;
-            d[0] = acc.n_ev[0];
-            d[1] = acc.n_ev[1];
-            d[2] = acc.n_ev[2];
-            d[3] = 1u + acc.spawned;
-            d[4] = acc.term_mask;
+        if (!__any(busy)) break;
+        if (busy) {
+            const int code = hstep<FM, WW>(P, R, p, cell, b, i, acc, SB, since);
+            if (code >= 0) {
+                acc.term_mask |= 1u << code;
+                end_history<WW>(P, R, acc, code, i, chunk_first, tot);
+                busy = false;
+            }
         }
-        if (R.dbg_scores) {
-            R.dbg_scores[i * 2 + 0] = acc.track;
-            R.dbg_scores[i * 2 + 1] = acc.qoi;
+    }
+    // totals: wave reductions, then one atomic per counter and workgroup
+#pragma unroll
+    for (int j = 0; j < kCounters; ++j) {
+        unsigned int v = tot.c[j];
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+        if (__lane_id() == 0 && v) atomicAdd(&red[j], (unsigned long long)v);
+    }
+    for (int o = 32; o > 0; o >>= 1) tot.started += __shfl_xor(tot.started, o);
+    if (__lane_id() == 0) atomicAdd(&red[kCounters], tot.started);
+    if (!WW && P.qoi_on) {
+        for (int o = 32; o > 0; o >>= 1) {
+            tot.q[0] += __shfl_xor(tot.q[0], o);
+            tot.q[1] += __shfl_xor(tot.q[1], o);
         }
-        if (WW) {
-            if (P.qoi_on) R.qoi_hist[i - chunk_first] = acc.qoi;
-        } else if (P.qoi_on && acc.qoi != 0.0) {
-            atomicAdd(&qsum[0], acc.qoi);
-            atomicAdd(&qsum[1], acc.qoi * acc.qoi);
+        if (__lane_id() == 0) {
+            atomicAdd(&qsum[0], tot.q[0]);
+            atomicAdd(&qsum[1], tot.q[1]);
         }
-        for (int e = 0; e < 3; ++e)
-            if (acc.n_ev[e]) atomicAdd(&bc.c[e], acc.n_ev[e]);
-        if (acc.spawned) atomicAdd(&bc.c[8], acc.spawned);
     }
     __syncthreads();
-    if (threadIdx.x < kCounters && bc.c[threadIdx.x])
-        atomicAdd(R.counters + threadIdx.x, (unsigned long long)bc.c[threadIdx.x]);
+    if (threadIdx.x < kCounters && red[threadIdx.x]) atomicAdd(R.counters + threadIdx.x, red[threadIdx.x]);
     if (!WW && P.qoi_on && threadIdx.x < 2 && qsum[threadIdx.x] != 0.0)
         atomic_add_f64(R.qoi_sums + threadIdx.x, qsum[threadIdx.x]);
-    if (R.prof && threadIdx.x == 0) {
-        const uint64_t lo = (uint64_t)blockIdx.x * blockDim.x;
-        const uint64_t nb = (count > lo) ? ((count - lo < blockDim.x) ? count - lo : blockDim.x) : 0;
-        atomicAdd(R.prof + 2 * MCDC_PROF_HISTORY, (unsigned long long)nb);
-    }
+    if (R.prof && threadIdx.x == 0) atomicAdd(R.prof + 2 * MCDC_PROF_HISTORY, red[kCounters]);
 }
 
 // One generation of split progeny: each thread tracks one child to death
@@ -191,6 +297,7 @@ __global__ void __launch_bounds__(256) k_history_children(DevProblem P, RunArgs 
 }
 
 __global__ void k_zero_count(unsigned int *c) { *c = 0u; }
+__global__ void k_zero_u64(unsigned long long *c) { *c = 0ull; }
 
 SplitBank carve_split(void *mem, unsigned int cap, unsigned int *count) {
     SplitBank B{};
@@ -216,13 +323,30 @@ SplitBank carve_split(void *mem, unsigned int cap, unsigned int *count) {
 
 size_t split_bytes(unsigned int cap) { return (size_t)cap * (13 * 8 + 8) + 16 * 256; }
 
+// The persistent history kernel: as many workgroups as the GPU holds
+// resident (no more than the work needs), and the work counter cleared.
 template <int FM, bool WW>
-void launch_main(const DevProblem &P, const RunArgs &R, uint64_t first, uint64_t count, uint64_t chunk_first,
-                 const SplitBank &SB, hipStream_t st, Profiler &prof) {
+int launch_main(mcdc_problem *pb, const DevProblem &P, const RunArgs &R, uint64_t first, uint64_t count,
+                uint64_t chunk_first, const SplitBank &SB, hipStream_t st, Profiler &prof) {
     const int bs = 256;
-    const uint64_t grid = (count + bs - 1) / bs;
+    int rc;
+    if ((rc = ensure(pb->work, 256))) return rc;
+    unsigned long long *next = (unsigned long long *)pb->work.p;
+    int per_cu = 0, n_cu = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &per_cu, reinterpret_cast<const void *>(&k_history<FM, WW>), bs, 0);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, pb->device);
+    if (e != hipSuccess) return hip_fail(e, "occupancy query");
+    uint64_t grid = (uint64_t)(per_cu > 0 ? per_cu : 1) * (uint64_t)(n_cu > 0 ? n_cu : 1);
+    const uint64_t waves = grid * (bs / 64);
+    uint64_t wc = count / (waves * 16);
+    wc = (wc < 256) ? 256 : (wc > 65536 ? 65536 : (wc + 63) & ~63ull);
+    const uint64_t grid_needed = ((count + wc - 1) / wc + bs / 64 - 1) / (bs / 64);
+    if (grid > grid_needed) grid = grid_needed;
+    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(1), 0, st, next);
     launch_timed(prof, MCDC_PROF_HISTORY, k_history<FM, WW>, dim3((unsigned)grid), dim3(bs), 0u, st, P, R, first,
-                 count, chunk_first, SB);
+                 count, chunk_first, SB, next, (unsigned int)wc);
+    return MCDC_OK;
 }
 
 // Split progeny of one chunk, generation by generation, until none are left
@@ -271,10 +395,9 @@ int run_history(mcdc_problem *pb, const RunArgs &R0, uint64_t first, uint64_t co
         const uint64_t n = (count - c0 < chunk) ? count - c0 : chunk;
         const uint64_t cfirst = first + c0;
         if (ww) split_reset(SB, st);
-        if (ww)
-            launch_main<FM, true>(P, R, cfirst, n, cfirst, SB[0], st, prof);
-        else
-            launch_main<FM, false>(P, R, cfirst, n, cfirst, SB[0], st, prof);
+        rc = ww ? launch_main<FM, true>(pb, P, R, cfirst, n, cfirst, SB[0], st, prof)
+                : launch_main<FM, false>(pb, P, R, cfirst, n, cfirst, SB[0], st, prof);
+        if (rc) return rc;
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return hip_fail(e, "history kernel launch");
         if (!ww) continue;

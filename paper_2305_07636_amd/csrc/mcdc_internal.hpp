@@ -64,8 +64,10 @@ struct RunArgs {
     uint64_t N;          // histories in the whole run (sets the batch partition)
     uint64_t seed;       // base LCG state (masked to 63 bits)
     int B;               // batches
-    double *S;           // [B][ntally] raw track-length sums per batch
-    double *L;           // [B][K][G][6] leaked weight per batch
+    int X;               // tally copies per batch (power of two): workgroup w adds into copy w mod X
+    double *S;           // [B][X][ntally] raw track-length sums per batch and copy
+    int XL;              // leakage copies per batch (power of two), as X
+    double *L;           // [B][XL][K][G][6] leaked weight per batch and copy
     double *qoi_hist;    // [chunk] per-history detector score (WW runs) or nullptr
     double *qoi_sums;    // [2] sum x, sum x^2
     unsigned long long *counters;  // [kCounters]
@@ -151,7 +153,7 @@ struct mcdc_problem {
         void *p = nullptr;
         size_t bytes = 0;
     };
-    Buf S, L, qoi_hist, qoi_sums, counters, overflow, bank, queues, split, prof, counters_split, tally_part;
+    Buf S, L, qoi_hist, qoi_sums, counters, overflow, bank, queues, split, prof, counters_split, tally_part, work;
     Buf mean, var, raw, leak_mean, leak_var;
     void *graph_cache = nullptr;   // captured census steps of the event form
 };
@@ -167,7 +169,7 @@ int launch_history(mcdc_problem *p, const RunArgs &R, uint64_t first, uint64_t c
                    int block, hipStream_t st, Profiler &prof);
 int launch_event(mcdc_problem *p, const RunArgs &R, uint64_t first, uint64_t count,
                  const mcdc_run_options &opt, hipStream_t st, Profiler &prof);
-int launch_fold(const DevProblem &P, const double *S, const double *L, int B, uint64_t N,
+int launch_fold(const DevProblem &P, const double *S, const double *L, int B, int X, int XL, uint64_t N,
                 const double *bin_norm_dev, const double *time_norm_dev, double *mean,
                 double *var, double *raw, double *leak_mean, double *leak_var,
                 hipStream_t st);

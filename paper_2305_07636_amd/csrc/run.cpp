@@ -101,8 +101,14 @@ int check_options(const mcdc_run_options &opt) {
 int prepare(mcdc_problem *p, uint64_t N, uint64_t seed, const mcdc_run_options &opt, hipStream_t st, RunArgs &R) {
     const DevProblem &P = p->d;
     const int B = (int)((uint64_t)p->h.B < N ? (uint64_t)p->h.B : N);
-    const size_t nS = (size_t)B * P.ntally;
-    const size_t nL = (size_t)B * P.K * P.G * 6;
+    // tally copies per batch: up to 32 while the copies stay within 64 MB
+    int X = 32;
+    while (X > 1 && (double)B * X * (double)P.ntally * sizeof(double) > 64.0 * 1024 * 1024) X >>= 1;
+    const size_t nS = (size_t)B * X * P.ntally;
+    // leakage copies: up to 256 within 16 MB
+    int XL = 256;
+    while (XL > 1 && (double)B * XL * P.K * P.G * 6 * sizeof(double) > 16.0 * 1024 * 1024) XL >>= 1;
+    const size_t nL = (size_t)B * XL * P.K * P.G * 6;
     int rc;
     if ((rc = ensure(p->S, nS * sizeof(double)))) return rc;
     if ((rc = ensure(p->L, nL * sizeof(double)))) return rc;
@@ -122,6 +128,8 @@ int prepare(mcdc_problem *p, uint64_t N, uint64_t seed, const mcdc_run_options &
     R.N = N;
     R.seed = seed;
     R.B = B;
+    R.X = X;
+    R.XL = XL;
     R.S = (double *)p->S.p;
     R.L = (double *)p->L.p;
     R.qoi_sums = (double *)p->qoi_sums.p;
@@ -155,7 +163,7 @@ int fold(mcdc_problem *p, const RunArgs &R, mcdc_result *out, hipStream_t st, Pr
         lvar = lvar ? (double *)p->leak_var.p : nullptr;
     }
     prof.begin(MCDC_PROF_OTHER);
-    rc = launch_fold(P, R.S, R.L, R.B, R.N, P.bin_norm, P.time_norm, mean, var, raw, lmean, lvar, st);
+    rc = launch_fold(P, R.S, R.L, R.B, R.X, R.XL, R.N, P.bin_norm, P.time_norm, mean, var, raw, lmean, lvar, st);
     prof.end();
     return rc ? hip_fail((hipError_t)rc, "fold kernel launch") : MCDC_OK;
 }
