@@ -47,7 +47,6 @@ namespace {
 using namespace dev;
 
 constexpr int kBlock = 512;
-constexpr int kLdsTallyMax = 4096;          // doubles (32 KB)
 constexpr int kLdsTablesMax = 32 * 1024;    // bytes of staged tables
 constexpr uint32_t kHidMask = 0x0FFFFFFFu;  // history index within a chunk (< 2^28)
 

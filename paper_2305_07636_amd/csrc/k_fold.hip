@@ -6,16 +6,29 @@
 namespace mcdc {
 namespace {
 
-// Raw sum of batch b in bin j over its X tally copies (fixed order).
-__device__ __forceinline__ double batch_sum(const double *S, int64_t ntally, int X, int b, int64_t j) {
+// Sum the X copies of every batch into copy 0, in a fixed order (one
+// thread per batch and bin; the fold then reads one copy per batch).
+__global__ void __launch_bounds__(256) k_sum_copies(double *S, int64_t n, int B, int X) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)B * n) return;
+    const int64_t b = t / n, j = t % n;
+    double *base = S + b * X * n + j;
+    double v = base[0];
+    for (int x = 1; x < X; ++x) v += base[(int64_t)x * n];
+    base[0] = v;
+}
+
+// Raw sum of batch b in bin j over the first X of its copies (fixed
+// order); batches lie bstride elements apart, copies n apart.
+__device__ __forceinline__ double batch_sum(const double *S, int64_t bstride, int64_t n, int X, int b, int64_t j) {
     double v = 0.0;
-    for (int x = 0; x < X; ++x) v += S[((int64_t)b * X + x) * ntally + j];
+    for (int x = 0; x < X; ++x) v += S[(int64_t)b * bstride + (int64_t)x * n + j];
     return v;
 }
 
 // One thread per tally bin j: S is [B][X][ntally] raw sums (X copies per
 // batch), norm_j = dt_k * V_s.
-__global__ void __launch_bounds__(256) k_fold(const double *__restrict__ S, int64_t ntally,
+__global__ void __launch_bounds__(256) k_fold(const double *__restrict__ S, int64_t ntally, int64_t bstride,
                                               int B, int X, uint64_t N, int G, int nts,
                                               const double *__restrict__ bin_norm,
                                               const double *__restrict__ time_norm,
@@ -26,20 +39,20 @@ __global__ void __launch_bounds__(256) k_fold(const double *__restrict__ S, int6
     const int s = (int)(j % nts);
     const double norm = time_norm[k] * bin_norm[s];
     double total = 0.0;
-    for (int b = 0; b < B; ++b) total += batch_sum(S, ntally, X, b, j);
+    for (int b = 0; b < B; ++b) total += batch_sum(S, bstride, ntally, X, b, j);
     if (raw) raw[j] = total;
     if (mean) mean[j] = total / ((double)N * norm);
     if (var) {
         double mb_sum = 0.0;
         for (int b = 0; b < B; ++b) {
             const uint64_t nb = ((uint64_t)(b + 1) * N) / B - ((uint64_t)b * N) / B;
-            mb_sum += batch_sum(S, ntally, X, b, j) / ((double)nb * norm);
+            mb_sum += batch_sum(S, bstride, ntally, X, b, j) / ((double)nb * norm);
         }
         const double mbar = mb_sum / B;
         double acc = 0.0;
         for (int b = 0; b < B; ++b) {
             const uint64_t nb = ((uint64_t)(b + 1) * N) / B - ((uint64_t)b * N) / B;
-            const double d = batch_sum(S, ntally, X, b, j) / ((double)nb * norm) - mbar;
+            const double d = batch_sum(S, bstride, ntally, X, b, j) / ((double)nb * norm) - mbar;
             acc += d * d;
         }
         var[j] = (B > 1) ? acc / ((double)B * (double)(B - 1)) : 0.0;
@@ -48,14 +61,14 @@ __global__ void __launch_bounds__(256) k_fold(const double *__restrict__ S, int6
 
 // Leakage per face: same statistics with unit normalisation (L is
 // [B][XL][n], XL copies per batch).
-__global__ void k_fold_leak(const double *__restrict__ L, int n, int B, int XL, uint64_t N,
+__global__ void k_fold_leak(const double *__restrict__ L, int n, int64_t bstride, int B, int XL, uint64_t N,
                             double *mean, double *var) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= n) return;
     double total = 0.0, mb_sum = 0.0;
     for (int b = 0; b < B; ++b) {
         const uint64_t nb = ((uint64_t)(b + 1) * N) / B - ((uint64_t)b * N) / B;
-        const double v = batch_sum(L, n, XL, b, j);
+        const double v = batch_sum(L, bstride, n, XL, b, j);
         total += v;
         mb_sum += v / (double)nb;
     }
@@ -65,7 +78,7 @@ __global__ void k_fold_leak(const double *__restrict__ L, int n, int B, int XL, 
         double acc = 0.0;
         for (int b = 0; b < B; ++b) {
             const uint64_t nb = ((uint64_t)(b + 1) * N) / B - ((uint64_t)b * N) / B;
-            const double d = batch_sum(L, n, XL, b, j) / (double)nb - mbar;
+            const double d = batch_sum(L, bstride, n, XL, b, j) / (double)nb - mbar;
             acc += d * d;
         }
         var[j] = (B > 1) ? acc / ((double)B * (double)(B - 1)) : 0.0;
@@ -102,19 +115,31 @@ __global__ void __launch_bounds__(256) k_qoi_reduce(const double *__restrict__ q
 
 }  // namespace
 
-int launch_fold(const DevProblem &P, const double *S, const double *L, int B, int X, int XL, uint64_t N,
+int launch_fold(const DevProblem &P, double *S, double *L, int B, int X, int XL, uint64_t N,
                 const double *bin_norm_dev, const double *time_norm_dev, double *mean,
                 double *var, double *raw, double *leak_mean, double *leak_var,
                 hipStream_t st) {
     const int bs = 256;
+    const int64_t s_stride = (int64_t)X * P.ntally, l_stride = (int64_t)XL * P.K * P.G * 6;
+    if ((mean || var || raw) && X > 1) {
+        hipLaunchKernelGGL(k_sum_copies, dim3((unsigned)(((int64_t)B * P.ntally + bs - 1) / bs)), dim3(bs), 0, st,
+                           S, P.ntally, B, X);
+        X = 1;
+    }
+    if ((leak_mean || leak_var) && XL > 1) {
+        const int64_t n = (int64_t)P.K * P.G * 6;
+        hipLaunchKernelGGL(k_sum_copies, dim3((unsigned)(((int64_t)B * n + bs - 1) / bs)), dim3(bs), 0, st,
+                           L, n, B, XL);
+        XL = 1;
+    }
     if (mean || var || raw) {
         const unsigned grid = (unsigned)((P.ntally + bs - 1) / bs);
-        hipLaunchKernelGGL(k_fold, dim3(grid), dim3(bs), 0, st, S, P.ntally, B, X, N, P.G, P.nts,
+        hipLaunchKernelGGL(k_fold, dim3(grid), dim3(bs), 0, st, S, P.ntally, s_stride, B, X, N, P.G, P.nts,
                            bin_norm_dev, time_norm_dev, mean, var, raw);
     }
     if (leak_mean || leak_var) {
         const int n = P.K * P.G * 6;
-        hipLaunchKernelGGL(k_fold_leak, dim3((n + bs - 1) / bs), dim3(bs), 0, st, L, n, B, XL, N,
+        hipLaunchKernelGGL(k_fold_leak, dim3((n + bs - 1) / bs), dim3(bs), 0, st, L, n, l_stride, B, XL, N,
                            leak_mean, leak_var);
     }
     return (int)hipGetLastError();

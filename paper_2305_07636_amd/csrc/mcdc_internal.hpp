@@ -15,6 +15,7 @@ namespace mcdc {
 
 constexpr int kMaxGroups = 32;      // outgoing-group search is unrolled over this
 constexpr int kCounters = 9;        // census, surface, collision; 5 terminations; splits
+constexpr int kLdsTallyMax = 4096;  // doubles of the event form's per-step LDS tally slice
 constexpr uint64_t kStride = 152917ULL;
 
 enum Term : int { kAbsorb = 0, kLeak = 1, kTime = 2, kLost = 3, kRoulette = 4 };
@@ -169,7 +170,8 @@ int launch_history(mcdc_problem *p, const RunArgs &R, uint64_t first, uint64_t c
                    int block, hipStream_t st, Profiler &prof);
 int launch_event(mcdc_problem *p, const RunArgs &R, uint64_t first, uint64_t count,
                  const mcdc_run_options &opt, hipStream_t st, Profiler &prof);
-int launch_fold(const DevProblem &P, const double *S, const double *L, int B, int X, int XL, uint64_t N,
+// (sums the tally and leakage copies into copy 0 first, in place)
+int launch_fold(const DevProblem &P, double *S, double *L, int B, int X, int XL, uint64_t N,
                 const double *bin_norm_dev, const double *time_norm_dev, double *mean,
                 double *var, double *raw, double *leak_mean, double *leak_var,
                 hipStream_t st);

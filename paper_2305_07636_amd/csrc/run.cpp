@@ -102,8 +102,11 @@ int prepare(mcdc_problem *p, uint64_t N, uint64_t seed, const mcdc_run_options &
     const DevProblem &P = p->d;
     const int B = (int)((uint64_t)p->h.B < N ? (uint64_t)p->h.B : N);
     // tally copies per batch: up to 32 while the copies stay within 64 MB
+    // (the event form adds a step's scores from its LDS slice once per
+    // workgroup when the slice fits, and needs no copies then)
     int X = 32;
     while (X > 1 && (double)B * X * (double)P.ntally * sizeof(double) > 64.0 * 1024 * 1024) X >>= 1;
+    if (opt.algorithm != MCDC_ALG_HISTORY && 2 * (int64_t)P.G * P.nts <= kLdsTallyMax) X = 1;
     const size_t nS = (size_t)B * X * P.ntally;
     // leakage copies: up to 256 within 16 MB
     int XL = 256;
