@@ -140,7 +140,8 @@ typedef struct {
  *                 kernels of mcdc_run use 256 (history form) and 512
  *                 (event form).
  *  bank_capacity  event form: particles resident at once (0 = auto).  Work
- *                 is processed in chunks of this many histories.
+ *                 is processed in chunks of this many histories.  In
+ *                 mcdc_run_batched's event form: slots per bank segment.
  *  flags          bit 0 (MCDC_FLAG_EAGER): launch the event form's census
  *                 steps one kernel at a time instead of replaying the
  *                 captured step graphs (graphs are also skipped when a
@@ -264,18 +265,24 @@ int mcdc_run(mcdc_problem *p, uint64_t n_histories, uint64_t seed,
 
 /*
  * Batched solve: run n independent problems (any sizes, group counts and
- * history counts) in one persistent launch.  A fixed grid of workgroups
- * pulls chunks of histories from one device-wide work counter over the
- * concatenated history ranges, so large and small problems share the GPU
- * without per-problem launch or tail costs.  Problem j runs n_hist[j]
- * histories with seed seeds[j]; outs[j] is filled exactly as mcdc_run
- * would fill it for that problem, and per-history results are identical to
- * separate mcdc_run calls (tallies differ only in summation order).  The
- * launch shape (workgroup size, histories per pull) is autotuned on the
- * first call for a batch signature (problem shapes and history counts) and
- * reused after that; opt->block_size forces a workgroup size.
- * opt->algorithm must be MCDC_ALG_HISTORY (or the default, which the batched
- * path maps to it); debug arrays and weight windows are not supported here
+ * history counts) together (Section 2 names both algorithm modes; the
+ * batching is this library's).  Problem j runs n_hist[j] histories with
+ * seed seeds[j]; outs[j] is filled exactly as mcdc_run would fill it for
+ * that problem, and per-history results are identical to separate
+ * mcdc_run calls (tallies differ only in summation order).
+ *  MCDC_ALG_EVENT (default): every problem's histories are cut into bank
+ *    segments of one length; all segments of all problems share one set of
+ *    banks, and each census step is one captured graph (advance, events)
+ *    over all of them, replayed up to the largest K.  The segment length
+ *    (queue capacity per workgroup) is opt->bank_capacity if nonzero
+ *    (256..2^24), else autotuned over {2048, 8192, 32768} on the first call
+ *    for a batch signature (problem shapes and history counts) and reused.
+ *    At most 2^28 histories per problem.
+ *  MCDC_ALG_HISTORY: one persistent launch; a fixed grid of workgroups
+ *    pulls chunks of histories from one device-wide counter over the
+ *    concatenated history ranges; workgroup size and histories per pull are
+ *    autotuned the same way (opt->block_size forces a workgroup size).
+ * Debug arrays, profiles and weight windows are not supported here
  * (MCDC_E_UNSUPPORTED).  All problems must live on the same device.
  */
 int mcdc_run_batched(mcdc_problem *const *ps, int32_t n, const uint64_t *n_hist, const uint64_t *seeds,

@@ -386,9 +386,11 @@ def mcdc_mlp_create(seed: int = 1) -> MLP:
     return MLP(seed)
 
 
-def mcdc_run_batched(problems, n_hist, seeds, block_size: int = 0, outputs=("mean", "var")):
-    """Run many problems in one persistent launch (history-based).  Returns
-    one result dict per problem, like mcdc_run."""
+def mcdc_run_batched(problems, n_hist, seeds, block_size: int = 0, outputs=("mean", "var"),
+                     algorithm: str = "event", seg_len: int = 0):
+    """Run many problems together: event form (shared banks, one graph per
+    census step for all problems) or history form (one persistent launch).
+    Returns one result dict per problem, like mcdc_run."""
     import torch
 
     L = lib()
@@ -419,8 +421,9 @@ def mcdc_run_batched(problems, n_hist, seeds, block_size: int = 0, outputs=("mea
                 setattr(res[j], name, t.data_ptr())
         outs.append(o)
     opt = mcdc_run_options()
-    opt.algorithm = MCDC_ALG_HISTORY
+    opt.algorithm = MCDC_ALG_HISTORY if algorithm == "history" else MCDC_ALG_EVENT
     opt.block_size = block_size
+    opt.bank_capacity = seg_len
     opt.stream = torch.cuda.current_stream(dev).cuda_stream
     _check(L.mcdc_run_batched(hs, n, nh, sd, C.byref(opt), res))
     for j, o in enumerate(outs):

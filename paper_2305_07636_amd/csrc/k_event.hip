@@ -326,15 +326,6 @@ __device__ __forceinline__ void score_flight(const DevProblem &P, const RunArgs 
     }
 }
 
-// Tables staged in LDS, behind the tally slice: byte offsets and element
-// counts per table.
-enum TabId : int { kTU0, kTU1, kTU2, kTT, kTSt, kTISt, kTPs, kTCdf, kTV, kTIV, kTMat, kTTal, kTabs };
-struct LdsTables {
-    int off[kTabs];
-    int count[kTabs];
-    int bytes;
-};
-
 template <class T>
 __device__ __forceinline__ const T *stage(const T *src, const LdsTables &lt, int id, char *base) {
     T *dst = reinterpret_cast<T *>(base + lt.off[id]);
@@ -367,19 +358,27 @@ __device__ __forceinline__ DevProblem stage_tables(const DevProblem &P0, const L
 // ---------------------------------------------------------------------------
 // source: workgroup b samples histories [b L, (b + 1) L) of the chunk
 // ---------------------------------------------------------------------------
-template <int FM, bool WW, int CLS = MCDC_PROF_SOURCE>
-__global__ void __launch_bounds__(kBlock) k_source(DevProblem P, RunArgs R, Bank bank, Ctl C, uint64_t count) {
+// (BAT: a batched solve; segment b belongs to problem segs[b].prob and is
+// born with its histories [first, first + count), items holds every
+// problem's tables and run arguments.)
+template <int FM, bool WW, bool BAT, int CLS = MCDC_PROF_SOURCE>
+__global__ void __launch_bounds__(kBlock) k_source(DevProblem P0, RunArgs R0, Bank bank, Ctl C, uint64_t count,
+                                                   const BatchItem *__restrict__ items,
+                                                   const SegInfo *__restrict__ segs) {
     __shared__ unsigned long long red[kCounters + 2];
     Counters cnt;
     __shared__ unsigned int cN;
+    const SegInfo si = BAT ? segs[blockIdx.x] : SegInfo{0, 0u, 0u, 0u};
+    const DevProblem &P = BAT ? items[si.prob].P : P0;
+    const RunArgs &R = BAT ? items[si.prob].R : R0;
     cnt.init(red);
     if (threadIdx.x == 0) cN = 0u;
     const uint64_t first = *C.first;
     const unsigned int seg = blockIdx.x;
-    const uint64_t lo = (uint64_t)seg * C.L;
-    const uint64_t hi = (lo + C.L < count) ? lo + C.L : count;
+    const uint64_t lo = BAT ? (uint64_t)si.first : (uint64_t)seg * C.L;
+    const uint64_t hi = BAT ? lo + si.count : ((lo + C.L < count) ? lo + C.L : count);
     if (threadIdx.x == 0)
-        C.seg_b0[seg] = (lo < count) ? (int)(((first + lo + 1) * (uint64_t)R.B - 1) / R.N) : 0;
+        C.seg_b0[seg] = (lo < hi) ? (int)(((first + lo + 1) * (uint64_t)R.B - 1) / R.N) : 0;
     __syncthreads();
     for (uint64_t base = lo; base < hi; base += kBlock) {
         const uint64_t r = base + threadIdx.x;
@@ -411,9 +410,14 @@ __global__ void __launch_bounds__(kBlock) k_source(DevProblem P, RunArgs R, Bank
 // ---------------------------------------------------------------------------
 enum Outcome : int { kNone = 0, kToNext = 1, kToSurface = 2, kToCollision = 3 };
 
-template <int FM, bool WW, bool LT, int CLS = MCDC_PROF_ADVANCE>
-__global__ void __launch_bounds__(kBlock) k_advance(DevProblem P0, RunArgs R, Bank cur, Bank next, Bank ev, Ctl C,
-                                                    int par, int gn, SplitBank SB, LdsTables tabs) {
+template <int FM, bool WW, bool LT, bool BAT, int CLS = MCDC_PROF_ADVANCE>
+__global__ void __launch_bounds__(kBlock) k_advance(DevProblem P0, RunArgs R0, Bank cur, Bank next, Bank ev, Ctl C,
+                                                    int par, int gn0, SplitBank SB, LdsTables tabs0,
+                                                    const BatchItem *__restrict__ items,
+                                                    const SegInfo *__restrict__ segs) {
+    const int prob = BAT ? segs[blockIdx.x].prob : 0;
+    const RunArgs &R = BAT ? items[prob].R : R0;
+    const int gn = BAT ? items[prob].gn : gn0;
     __shared__ unsigned long long red[kCounters + 2];
     Counters cnt;
     __shared__ unsigned int cN, cS, cC;
@@ -432,7 +436,8 @@ __global__ void __launch_bounds__(kBlock) k_advance(DevProblem P0, RunArgs R, Ba
     }
     StepScore sc;
     init_slice(sc, lt, gn, C.seg_b0[seg]);
-    const DevProblem P = stage_tables<LT>(P0, tabs, reinterpret_cast<char *>(lt + 2 * gn));
+    const DevProblem P =
+        stage_tables<LT>(BAT ? items[prob].P : P0, BAT ? items[prob].tabs : tabs0, reinterpret_cast<char *>(lt + 2 * gn));
     __syncthreads();
     // software pipeline: the next particle's state is in flight while the
     // current one is moved
@@ -518,9 +523,14 @@ __global__ void __launch_bounds__(kBlock) k_advance(DevProblem P0, RunArgs R, Ba
 // left.  Each item starts with its queued event; every later step of it
 // is a flight to the next event and that event.  The event cap counts
 // flights from the item's start.
-template <int FM, bool WW, bool LT, int CLS = MCDC_PROF_EVENTS>
-__global__ void __launch_bounds__(kBlock) k_event(DevProblem P0, RunArgs R, Bank ev, Bank next, Ctl C, int par,
-                                                  int gn, SplitBank SB, LdsTables tabs) {
+template <int FM, bool WW, bool LT, bool BAT, int CLS = MCDC_PROF_EVENTS>
+__global__ void __launch_bounds__(kBlock) k_event(DevProblem P0, RunArgs R0, Bank ev, Bank next, Ctl C, int par,
+                                                  int gn0, SplitBank SB, LdsTables tabs0,
+                                                  const BatchItem *__restrict__ items,
+                                                  const SegInfo *__restrict__ segs) {
+    const int prob = BAT ? segs[blockIdx.x].prob : 0;
+    const RunArgs &R = BAT ? items[prob].R : R0;
+    const int gn = BAT ? items[prob].gn : gn0;
     __shared__ unsigned long long red[kCounters + 2];
     __shared__ unsigned int cN, cW;
     Counters cnt;
@@ -539,7 +549,8 @@ __global__ void __launch_bounds__(kBlock) k_event(DevProblem P0, RunArgs R, Bank
     }
     StepScore sc;
     init_slice(sc, lt, gn, C.seg_b0[seg]);
-    const DevProblem P = stage_tables<LT>(P0, tabs, reinterpret_cast<char *>(lt + 2 * gn));
+    const DevProblem P =
+        stage_tables<LT>(BAT ? items[prob].P : P0, BAT ? items[prob].tabs : tabs0, reinterpret_cast<char *>(lt + 2 * gn));
     __syncthreads();
 
     Particle p;
@@ -774,7 +785,7 @@ int run_event(mcdc_problem *pb, const RunArgs &R0, uint64_t first, uint64_t coun
     } else {
         int per_cu = 0, n_cu = 0;
         hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &per_cu, reinterpret_cast<const void *>(&k_advance<FM, WW, LT>), kBlock, shmem);
+            &per_cu, reinterpret_cast<const void *>(&k_advance<FM, WW, LT, false>), kBlock, shmem);
         if (e == hipSuccess) e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, pb->device);
         if (e != hipSuccess) return hip_fail(e, "occupancy query");
         if (per_cu < 1) per_cu = 1;
@@ -810,10 +821,12 @@ int run_event(mcdc_problem *pb, const RunArgs &R0, uint64_t first, uint64_t coun
     auto enqueue_step = [&](int par, hipStream_t s, Profiler &pr, const RunArgs &Ra) {
         const Bank &cur = L.bank[par];
         const Bank &nxt = L.bank[par ^ 1];
-        launch_timed(pr, MCDC_PROF_ADVANCE, k_advance<FM, WW, LT>, dim3(G), dim3(kBlock), (uint32_t)shmem, s, P, Ra,
-                     cur, nxt, L.ev, L.ctl, par, gn, SB[0], tabs);
-        launch_timed(pr, MCDC_PROF_EVENTS, k_event<FM, WW, LT>, dim3(G), dim3(kBlock), (uint32_t)shmem, s, P, Ra,
-                     L.ev, nxt, L.ctl, par, gn, SB[0], tabs);
+        launch_timed(pr, MCDC_PROF_ADVANCE, k_advance<FM, WW, LT, false>, dim3(G), dim3(kBlock), (uint32_t)shmem, s, P,
+                     Ra, cur, nxt, L.ev, L.ctl, par, gn, SB[0], tabs, (const BatchItem *)nullptr,
+                     (const SegInfo *)nullptr);
+        launch_timed(pr, MCDC_PROF_EVENTS, k_event<FM, WW, LT, false>, dim3(G), dim3(kBlock), (uint32_t)shmem, s, P,
+                     Ra, L.ev, nxt, L.ctl, par, gn, SB[0], tabs, (const BatchItem *)nullptr,
+                     (const SegInfo *)nullptr);
         hipLaunchKernelGGL(k_step_end, dim3(1), dim3(1), 0, s, L.ctl);
     };
 
@@ -859,8 +872,8 @@ int run_event(mcdc_problem *pb, const RunArgs &R0, uint64_t first, uint64_t coun
         hipLaunchKernelGGL(k_ctl_init, dim3(1), dim3(1), 0, st, L.ctl, cfirst);
         if (P.qoi_on && (rc = launch_zero(R.qoi_hist, n * sizeof(double), st))) return hip_fail((hipError_t)rc, "zero");
         if (WW) split_reset(SB, st);
-        launch_timed(prof, MCDC_PROF_SOURCE, k_source<FM, WW>, dim3(G), dim3(kBlock), 0u, st, P, R, L.bank[0], L.ctl,
-                     n);
+        launch_timed(prof, MCDC_PROF_SOURCE, k_source<FM, WW, false>, dim3(G), dim3(kBlock), 0u, st, P, R, L.bank[0],
+                     L.ctl, n, (const BatchItem *)nullptr, (const SegInfo *)nullptr);
         for (int step = 0; step < P.K; ++step) {
             const bool sampled = opt.profile && step % every == opt.profile_phase % every;
             if (Gr && !sampled) {
@@ -887,7 +900,126 @@ int run_event_lt(mcdc_problem *p, const RunArgs &R, uint64_t first, uint64_t cou
               : run_event<FM, WW, false>(p, R, first, count, opt, st, prof, tabs);
 }
 
+// Batched solve: every problem's segments share one set of banks; each
+// census step (advance, events, step end over all segments of all
+// problems) is captured once as a graph and replayed for the largest K.
+template <int FM, bool LT>
+int run_batched_steps(const BatchItem *d_items, const SegInfo *d_segs, unsigned int G, unsigned int Lseg, int Kmax,
+                      size_t shmem, void *bank_mem, void *ctl_mem, hipStream_t st) {
+    const uint64_t slots = (uint64_t)G * Lseg;
+    Layout L = carve(bank_mem, ctl_mem, slots, G, Lseg);
+    const DevProblem P0{};
+    const RunArgs R0{};
+    const LdsTables t0{};
+    const SplitBank none{};
+    hipLaunchKernelGGL(k_ctl_init, dim3(1), dim3(1), 0, st, L.ctl, (uint64_t)0);
+    hipLaunchKernelGGL((k_source<FM, false, true>), dim3(G), dim3(kBlock), 0, st, P0, R0, L.bank[0], L.ctl,
+                       (uint64_t)0, d_items, d_segs);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "batched source launch");
+    hipStream_t cs = nullptr;
+    hipGraph_t graph[2] = {nullptr, nullptr};
+    hipGraphExec_t exec[2] = {nullptr, nullptr};
+    e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    for (int q = 0; q < 2 && e == hipSuccess; ++q) {
+        e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) break;
+        hipLaunchKernelGGL((k_advance<FM, false, LT, true>), dim3(G), dim3(kBlock), shmem, cs, P0, R0, L.bank[q],
+                           L.bank[q ^ 1], L.ev, L.ctl, q, 0, none, t0, d_items, d_segs);
+        hipLaunchKernelGGL((k_event<FM, false, LT, true>), dim3(G), dim3(kBlock), shmem, cs, P0, R0, L.ev,
+                           L.bank[q ^ 1], L.ctl, q, 0, none, t0, d_items, d_segs);
+        hipLaunchKernelGGL(k_step_end, dim3(1), dim3(1), 0, cs, L.ctl);
+        e = hipStreamEndCapture(cs, &graph[q]);
+        if (e == hipSuccess) e = hipGraphInstantiate(&exec[q], graph[q], nullptr, nullptr, 0);
+    }
+    for (int k = 0; k < Kmax && e == hipSuccess; ++k) e = hipGraphLaunch(exec[k & 1], st);
+    hipError_t e2 = hipStreamSynchronize(st);
+    for (int q = 0; q < 2; ++q) {
+        if (exec[q]) (void)hipGraphExecDestroy(exec[q]);
+        if (graph[q]) (void)hipGraphDestroy(graph[q]);
+    }
+    if (cs) (void)hipStreamDestroy(cs);
+    if (e != hipSuccess) return hip_fail(e, "batched census steps");
+    if (e2 != hipSuccess) return hip_fail(e2, "batched census steps");
+    return MCDC_OK;
+}
+
+struct BatchedLayout {
+    size_t items_off, segs_off, ctl_off, bank_off, bytes;
+    unsigned int G;
+};
+
+BatchedLayout batched_layout(const uint64_t *n_hist, int n, unsigned int Lseg) {
+    BatchedLayout b{};
+    uint64_t G = 0;
+    for (int j = 0; j < n; ++j) G += (n_hist[j] + Lseg - 1) / Lseg;
+    if (G == 0) G = 1;
+    b.G = (unsigned int)G;
+    b.items_off = 0;
+    b.segs_off = pad256(sizeof(BatchItem) * n);
+    b.ctl_off = b.segs_off + pad256(sizeof(SegInfo) * G);
+    b.bank_off = b.ctl_off + ctl_bytes((unsigned int)G);
+    b.bytes = b.bank_off + bank_bytes(G * Lseg) * 3 + 64 * 256;
+    return b;
+}
+
 }  // namespace
+
+size_t event_batched_bytes(const uint64_t *n_hist, int n, unsigned int seg_len) {
+    return batched_layout(n_hist, n, seg_len).bytes;
+}
+
+int launch_event_batched(std::vector<BatchItem> &items, const uint64_t *n_hist, unsigned int seg_len, void *mem,
+                         size_t mem_bytes, hipStream_t st) {
+    const int n = (int)items.size();
+    const BatchedLayout lay = batched_layout(n_hist, n, seg_len);
+    if (lay.bytes > mem_bytes) {
+        set_error("batched solve: work memory too small");
+        return MCDC_E_INVALID;
+    }
+    // per-problem slice and table layouts; one template for all problems
+    bool lt_all = true;
+    int fm = -1, Kmax = 0;
+    std::vector<bool> fit(n);
+    for (int j = 0; j < n; ++j) {
+        const DevProblem &P = items[j].P;
+        fit[j] = table_layout(P, items[j].tabs);
+        lt_all = lt_all && fit[j];
+        const int64_t gn64 = (int64_t)P.G * P.nts;
+        items[j].gn = (2 * gn64 <= kLdsTallyMax) ? (int)gn64 : 0;
+        fm = (fm < 0 || fm == P.finite_mask) ? P.finite_mask : 0;
+        if (P.K > Kmax) Kmax = P.K;
+    }
+    size_t shmem = 0;
+    for (int j = 0; j < n; ++j) {
+        const size_t b = (size_t)2 * items[j].gn * sizeof(double) + (lt_all ? (size_t)items[j].tabs.bytes : 0);
+        if (b > shmem) shmem = b;
+    }
+    std::vector<SegInfo> segs;
+    segs.reserve(lay.G);
+    for (int j = 0; j < n; ++j)
+        for (uint64_t f = 0; f < n_hist[j]; f += seg_len) {
+            const uint64_t c = (n_hist[j] - f < seg_len) ? n_hist[j] - f : seg_len;
+            segs.push_back(SegInfo{j, (uint32_t)f, (uint32_t)c, 0u});
+        }
+    if (segs.empty()) segs.push_back(SegInfo{0, 0u, 0u, 0u});
+    char *base = (char *)mem;
+    BatchItem *d_items = (BatchItem *)(base + lay.items_off);
+    SegInfo *d_segs = (SegInfo *)(base + lay.segs_off);
+    hipError_t e = hipMemcpyAsync(d_items, items.data(), sizeof(BatchItem) * n, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(d_segs, segs.data(), sizeof(SegInfo) * segs.size(), hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return hip_fail(e, "batched tables");
+    void *ctl = base + lay.ctl_off, *bank = base + lay.bank_off;
+    if (fm == 1)
+        return lt_all ? run_batched_steps<1, true>(d_items, d_segs, lay.G, seg_len, Kmax, shmem, bank, ctl, st)
+                      : run_batched_steps<1, false>(d_items, d_segs, lay.G, seg_len, Kmax, shmem, bank, ctl, st);
+    if (fm == 7)
+        return lt_all ? run_batched_steps<7, true>(d_items, d_segs, lay.G, seg_len, Kmax, shmem, bank, ctl, st)
+                      : run_batched_steps<7, false>(d_items, d_segs, lay.G, seg_len, Kmax, shmem, bank, ctl, st);
+    return lt_all ? run_batched_steps<0, true>(d_items, d_segs, lay.G, seg_len, Kmax, shmem, bank, ctl, st)
+                  : run_batched_steps<0, false>(d_items, d_segs, lay.G, seg_len, Kmax, shmem, bank, ctl, st);
+}
 
 void destroy_graph_cache(mcdc_problem *p) {
     if (!p->graph_cache) return;

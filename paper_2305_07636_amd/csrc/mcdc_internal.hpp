@@ -78,10 +78,29 @@ struct RunArgs {
     unsigned long long *prof;      // [MCDC_PROF_CLASSES][2] particles, bytes; or nullptr
 };
 
+// Read-only tables the event kernels stage in LDS: byte offsets (behind
+// the tally slice) and element counts per table.
+enum TabId : int { kTU0, kTU1, kTU2, kTT, kTSt, kTISt, kTPs, kTCdf, kTV, kTIV, kTMat, kTTal, kTabs };
+struct LdsTables {
+    int off[kTabs];
+    int count[kTabs];
+    int bytes;
+};
+
 // One problem of a batched solve (device array element).
 struct BatchItem {
     DevProblem P;
     RunArgs R;
+    LdsTables tabs;   // event form: staged-table layout
+    int gn;           // event form: G * nts of the LDS tally slice, 0 = none
+};
+
+// One bank segment of the batched event form: problem, and the histories
+// [first, first + count) of that problem it is born with.
+struct SegInfo {
+    int prob;
+    uint32_t first, count;
+    uint32_t pad;
 };
 
 // Host-side launch profiler: HIP events around each launch of a class.
@@ -180,5 +199,11 @@ void destroy_graph_cache(mcdc_problem *p);
 int launch_batched(const BatchItem *items, const uint64_t *offs, int n_items, uint64_t total,
                    unsigned long long *next, int finite_mask, int block, int per_thread, hipStream_t st);
 int launch_qoi_reduce(const double *qoi_hist, uint64_t n, double *qoi_sums, hipStream_t st);
+// Batched event form (k_event.hip): device memory it needs for segments of
+// seg_len slots, and the run itself (items hold each problem's DevProblem
+// and prepared RunArgs; the launcher fills their table layouts).
+size_t event_batched_bytes(const uint64_t *n_hist, int n, unsigned int seg_len);
+int launch_event_batched(std::vector<BatchItem> &items, const uint64_t *n_hist, unsigned int seg_len, void *mem,
+                         size_t mem_bytes, hipStream_t st);
 
 }  // namespace mcdc

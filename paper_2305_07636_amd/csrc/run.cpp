@@ -2,8 +2,10 @@
 // and result hand-off.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <iterator>
 #include <map>
 #include <string>
 #include <vector>
@@ -278,7 +280,8 @@ extern "C" int mcdc_run(mcdc_problem *p, uint64_t n_histories, uint64_t seed, co
 namespace {
 
 struct Tuned {
-    int block, per_thread;
+    int block, per_thread;   // history form: workgroup size, histories per thread per pull
+    unsigned int seg_len;    // event form: slots per bank segment
 };
 
 std::map<std::string, Tuned> &tune_cache() {
@@ -304,6 +307,108 @@ struct DevMem {
 };
 
 }  // namespace
+
+// Fold and hand back every problem's results after a batched run.
+int finish_batched(mcdc_problem *const *ps, int32_t n, const uint64_t *n_hist, std::vector<BatchItem> &items,
+                   mcdc_result *outs, float ms, hipStream_t st) {
+    int rc;
+    Profiler none;
+    std::vector<Collect> cs(n);
+    for (int j = 0; j < n; ++j) {
+        if (n_hist[j] == 0) continue;
+        if ((rc = fold(ps[j], items[j].R, &outs[j], st, none))) return rc;
+        if ((rc = collect_begin(ps[j], &outs[j], cs[j], st))) return rc;
+    }
+    HIP_CHECK(hipStreamSynchronize(st), "hipStreamSynchronize");
+    for (int j = 0; j < n; ++j) {
+        if (n_hist[j] == 0) {
+            std::memset(outs[j].n_events, 0, sizeof(outs[j].n_events));
+            std::memset(outs[j].n_term, 0, sizeof(outs[j].n_term));
+            outs[j].kernel_ms = ms;
+            continue;
+        }
+        if ((rc = collect_end(ps[j], n_hist[j], cs[j], &outs[j], ms))) return rc;
+    }
+    return MCDC_OK;
+}
+
+// Batched event form: all problems' bank segments in one set of banks, one
+// graph replay per census step for every problem.  Segment length (the
+// queue capacity per workgroup) is forced by bank_capacity or tuned on the
+// first call per batch signature.
+int run_batched_event(mcdc_problem *const *ps, int32_t n, const uint64_t *n_hist, const uint64_t *seeds,
+                      const mcdc_run_options &opt, mcdc_result *outs, hipStream_t st) {
+    for (int j = 0; j < n; ++j)
+        if (n_hist[j] > (1ULL << 28)) {
+            set_error("batched event form: at most 2^28 histories per problem");
+            return MCDC_E_UNSUPPORTED;
+        }
+    if (opt.bank_capacity != 0 && (opt.bank_capacity < 256 || opt.bank_capacity > (1 << 24)))
+        return bad("batched event form: bank_capacity (slots per segment) must be in [256, 2^24]");
+    const unsigned int cands[] = {2048u, 8192u, 32768u};
+    std::vector<unsigned int> tries;
+    Tuned t{0, 0, (unsigned int)opt.bank_capacity};
+    const std::string sig = "event:" + signature(ps, n, n_hist);
+    if (!t.seg_len) {
+        auto it = tune_cache().find(sig);
+        if (it != tune_cache().end())
+            t = it->second;
+        else
+            tries.assign(std::begin(cands), std::end(cands));
+    }
+    size_t bytes = t.seg_len ? event_batched_bytes(n_hist, n, t.seg_len) : 0;
+    for (unsigned int c : tries) bytes = std::max(bytes, event_batched_bytes(n_hist, n, c));
+    DevMem wm;
+    HIP_CHECK(hipMalloc(&wm.mem, bytes), "hipMalloc(batched banks)");
+
+    std::vector<BatchItem> items(n);
+    mcdc_run_options popt = opt;
+    popt.algorithm = MCDC_ALG_EVENT;
+    auto run_once = [&](unsigned int seg_len, float *ms) -> int {
+        Events ev;
+        HIP_CHECK(hipEventCreate(&ev.a), "hipEventCreate");
+        HIP_CHECK(hipEventCreate(&ev.b), "hipEventCreate");
+        HIP_CHECK(hipEventRecord(ev.a, st), "hipEventRecord");
+        for (int j = 0; j < n; ++j) {
+            items[j] = BatchItem{};
+            items[j].P = ps[j]->d;
+            if (n_hist[j] == 0) continue;
+            int r = prepare(ps[j], n_hist[j], seeds[j], popt, st, items[j].R);
+            if (r) return r;
+            if (ps[j]->d.qoi_on) {
+                if ((r = ensure(ps[j]->qoi_hist, n_hist[j] * sizeof(double)))) return r;
+                items[j].R.qoi_hist = (double *)ps[j]->qoi_hist.p;
+                ZERO(items[j].R.qoi_hist, n_hist[j] * sizeof(double));
+            }
+        }
+        int r = launch_event_batched(items, n_hist, seg_len, wm.mem, bytes, st);
+        if (r) return r;
+        for (int j = 0; j < n; ++j)
+            if (n_hist[j] && ps[j]->d.qoi_on &&
+                (r = launch_qoi_reduce(items[j].R.qoi_hist, n_hist[j], items[j].R.qoi_sums, st)))
+                return hip_fail((hipError_t)r, "detector reduce");
+        HIP_CHECK(hipEventRecord(ev.b, st), "hipEventRecord");
+        HIP_CHECK(hipEventSynchronize(ev.b), "hipEventSynchronize");
+        HIP_CHECK(hipEventElapsedTime(ms, ev.a, ev.b), "hipEventElapsedTime");
+        return MCDC_OK;
+    };
+    int rc;
+    float ms = 0.f;
+    if (!tries.empty()) {
+        float best = 1e30f;
+        for (unsigned int c : tries) {
+            float m = 0.f;
+            if ((rc = run_once(c, &m))) return rc;
+            if (m < best) {
+                best = m;
+                t.seg_len = c;
+            }
+        }
+        tune_cache()[sig] = t;
+    }
+    if ((rc = run_once(t.seg_len, &ms))) return rc;
+    return finish_batched(ps, n, n_hist, items, outs, ms, st);
+}
 
 extern "C" int mcdc_run_batched(mcdc_problem *const *ps, int32_t n, const uint64_t *n_hist, const uint64_t *seeds,
                                 const mcdc_run_options *opt_in, mcdc_result *outs) {
@@ -340,6 +445,7 @@ extern "C" int mcdc_run_batched(mcdc_problem *const *ps, int32_t n, const uint64
     if (total == 0) return bad("no histories");
     HIP_CHECK(hipSetDevice(dev), "hipSetDevice");
     hipStream_t st = (hipStream_t)opt.stream;
+    if (opt.algorithm != MCDC_ALG_HISTORY) return run_batched_event(ps, n, n_hist, seeds, opt, outs, st);
 
     // device arrays: items, history offsets, work counter
     std::vector<BatchItem> items(n);
@@ -384,7 +490,7 @@ extern "C" int mcdc_run_batched(mcdc_problem *const *ps, int32_t n, const uint64
     // launch shape: forced, cached, or tuned now over workgroup size and
     // histories per thread per pull (a shape never changes per-history
     // results, only the summation order of the tallies)
-    Tuned t{opt.block_size ? opt.block_size : 256, 4};
+    Tuned t{opt.block_size ? opt.block_size : 256, 4, 0u};
     const std::string sig = signature(ps, n, n_hist);
     float ms = 0.f;
     if (!opt.block_size) {
@@ -401,30 +507,12 @@ extern "C" int mcdc_run_batched(mcdc_problem *const *ps, int32_t n, const uint64
                     if ((rc = run_once(bsz, pt, &m))) return rc;
                     if (m < best) {
                         best = m;
-                        t = Tuned{bsz, pt};
+                        t = Tuned{bsz, pt, 0u};
                     }
                 }
             tune_cache()[sig] = t;
         }
     }
     if ((rc = run_once(t.block, t.per_thread, &ms))) return rc;
-
-    Profiler none;
-    std::vector<Collect> cs(n);
-    for (int j = 0; j < n; ++j) {
-        if (n_hist[j] == 0) continue;
-        if ((rc = fold(ps[j], items[j].R, &outs[j], st, none))) return rc;
-        if ((rc = collect_begin(ps[j], &outs[j], cs[j], st))) return rc;
-    }
-    HIP_CHECK(hipStreamSynchronize(st), "hipStreamSynchronize");
-    for (int j = 0; j < n; ++j) {
-        if (n_hist[j] == 0) {
-            std::memset(outs[j].n_events, 0, sizeof(outs[j].n_events));
-            std::memset(outs[j].n_term, 0, sizeof(outs[j].n_term));
-            outs[j].kernel_ms = ms;
-            continue;
-        }
-        if ((rc = collect_end(ps[j], n_hist[j], cs[j], &outs[j], ms))) return rc;
-    }
-    return MCDC_OK;
+    return finish_batched(ps, n, n_hist, items, outs, ms, st);
 }
