@@ -768,7 +768,9 @@ template <int FM, bool WW, bool LT>
 int run_event(mcdc_problem *pb, const RunArgs &R0, uint64_t first, uint64_t count, const mcdc_run_options &opt,
               hipStream_t st, Profiler &prof, const LdsTables &tabs) {
     const DevProblem &P = pb->d;
-    uint64_t C = opt.bank_capacity ? (uint64_t)opt.bank_capacity : (uint64_t)1 << 24;
+    // (weight-window runs take smaller chunks: their progeny of a chunk must
+    // fit the split bank)
+    uint64_t C = opt.bank_capacity ? (uint64_t)opt.bank_capacity : (WW ? kWindowChunk : (uint64_t)1 << 24);
     if (C > count) C = count;
     if (C > (1ULL << 28)) C = 1ULL << 28;
 

@@ -381,7 +381,7 @@ int run_history(mcdc_problem *pb, const RunArgs &R0, uint64_t first, uint64_t co
     RunArgs R = R0;
     // analog runs keep the detector score in registers; weight-window runs
     // assemble it per history in chunks
-    const uint64_t chunk = ww ? ((count < (1ULL << 24)) ? count : (1ULL << 24)) : count;
+    const uint64_t chunk = ww ? ((count < kWindowChunk) ? count : kWindowChunk) : count;
     SplitBank SB[2]{};
     int rc;
     if (ww) {
@@ -518,7 +518,9 @@ int launch_batched(const BatchItem *items, const uint64_t *offs, int n_items, ui
 }
 
 int split_prepare(mcdc_problem *pb, uint64_t chunk, dev::SplitBank SB[2]) {
-    const unsigned int cap = (unsigned int)((chunk < (1u << 22)) ? (1u << 22) : chunk);
+    // room for eight progeny per history of the chunk in each generation
+    const uint64_t want = 8 * chunk;
+    const unsigned int cap = (unsigned int)((want < (1u << 22)) ? (1u << 22) : (want > (1u << 26) ? (1u << 26) : want));
     int rc;
     if ((rc = ensure(pb->split, 2 * split_bytes(cap) + 256))) return rc;
     if ((rc = ensure(pb->counters_split, 2 * sizeof(unsigned int)))) return rc;

@@ -76,7 +76,7 @@ def compare_full(prob, N, seed, algorithm, ww=None, **kw):
     return g, r, e
 
 
-def compare_sampled(prob, N, seed, algorithm, n_sample=2000, sample_seed=0, **kw):
+def compare_sampled(prob, N, seed, algorithm, n_sample=2000, sample_seed=0, ww=None, **kw):
     """Full-size run on the GPU; the oracle recomputes a seeded sample of
     histories one by one (skip-ahead makes each history independent) and
     their per-history records must agree exactly."""
@@ -88,23 +88,35 @@ def compare_sampled(prob, N, seed, algorithm, n_sample=2000, sample_seed=0, **kw
     ids = np.unique(np.concatenate([rng.integers(0, N, n_sample), [0, N - 1]])).astype(np.uint64)
     p = m.mcdc_problem_create(prob)
     try:
+        if ww is not None:
+            m.mcdc_set_weight_windows(p, ww["centers"], ww.get("ratio", 5.0), ww.get("max_split", 16))
         out = m.mcdc_run(p, N, seed, algorithm=algorithm, debug=True, **kw)
-        idx = torch.as_tensor(ids.astype(np.int64), device=out["debug_counts"].device)
-        dc = out["debug_counts"].index_select(0, idx).cpu().numpy().astype(np.uint32)
+        d = out["debug_counts"]
+        idx = torch.as_tensor(ids.astype(np.int64), device=d.device)
+        dc = d.index_select(0, idx).cpu().numpy().astype(np.uint32)
         ds = out["debug_scores"].index_select(0, idx).cpu().numpy()
-        ev_sum = out["debug_counts"][:, :3].to(torch.int64).sum(dim=0).cpu().numpy()
-        terms_hist = out["debug_counts"][:, 4]
+        ev_sum = d[:, :3].sum(dim=0, dtype=torch.int64).cpu().numpy()
+        terms_hist = d[:, 4]
         n_term_bits = int((terms_hist != 0).sum().item())
         one_bit = int(((terms_hist & (terms_hist - 1)) == 0).sum().item())
+        del d, terms_hist
+        out.pop("debug_counts")
+        out.pop("debug_scores")
     finally:
         p.close()
-    r = oracle.run(prob, N, seed, ids=ids, records=True)
+    if ww is not None:
+        r = oracle.run(prob, N, seed, ids=ids, records=True, ww_center=ww["centers"],
+                       ww_ratio=ww.get("ratio", 5.0), ww_max_split=ww.get("max_split", 16))
+    else:
+        r = oracle.run(prob, N, seed, ids=ids, records=True)
     mism = np.nonzero((dc != r["rec"]).any(axis=1))[0]
     assert mism.size == 0, ("sampled per-history counts differ", ids[mism[:10]], dc[mism[:3]], r["rec"][mism[:3]])
     close(ds, r["trk"], what="sampled per-history scores")
-    # properties at any size: every history terminates exactly once and the
-    # per-history counts add up to the event totals
-    assert int(out["terms"].sum()) == N
-    assert n_term_bits == N and one_bit == N
+    # properties at any size: every history terminates (exactly once without
+    # windows) and the per-history counts add up to the event totals
+    if ww is None:
+        assert int(out["terms"].sum()) == N
+        assert one_bit == N
+    assert n_term_bits == N
     assert np.array_equal(ev_sum, out["events"].astype(np.int64))
     return out

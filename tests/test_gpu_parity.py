@@ -85,8 +85,28 @@ def test_parity_full_size_pulse_sampled(alg):
 @pytest.mark.gpu
 @pytest.mark.parametrize("alg", ALGS)
 def test_parity_lattice_sampled(alg):
-    print(f"[parity] lattice 1e7 sampled alg={alg}", flush=True)
-    compare_sampled(w.cfg3_lattice(), 10_000_000, 3, alg)
+    """The 17 x 17 lattice at its full size, 1e8 histories."""
+    print(f"[parity] lattice 1e8 sampled alg={alg}", flush=True)
+    compare_sampled(w.cfg3_lattice(), 100_000_000, 3, alg)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("alg", ALGS)
+@pytest.mark.parametrize("c", [0.5, 0.0])
+def test_parity_steady_slab_full_size(alg, c):
+    """The steady slab at its full size, 1e5 histories, every history
+    compared (c = 0.5 and the purely absorbing variant)."""
+    print(f"[parity] steady slab c={c} 1e5 alg={alg}", flush=True)
+    compare_full(w.cfg1_slab_steady(c=c, mu_law="cosine"), 100_000, 1, alg)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("alg", ALGS)
+def test_parity_dogleg_analog_full_size_sampled(alg):
+    """The dog-leg duct analog at its full size, 1e9 histories."""
+    print(f"[parity] dog-leg analog 1e9 sampled alg={alg}", flush=True)
+    out = compare_sampled(w.cfg5_dogleg(), 1_000_000_000, 52, alg)
+    assert out["qoi_mean"] > 0
 
 
 @pytest.mark.gpu

@@ -3,8 +3,9 @@ roulette) against the oracle, and the no-window limit."""
 import numpy as np
 import pytest
 
+import oracle
 import workloads as w
-from gpu_common import compare_full
+from gpu_common import compare_full, compare_sampled
 from ww_tables import flux_table
 
 WW_ALGS = ["history", "event"]
@@ -83,3 +84,25 @@ def test_ww_forms_agree_at_full_size():
     assert a["splits"] == b["splits"] > 0
     close(np.array(b["qoi_sum"]), np.array(a["qoi_sum"]))
     close(b["mean"].cpu().numpy(), a["mean"].cpu().numpy())
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("alg", WW_ALGS)
+def test_ww_dogleg_sampled_2e7(alg):
+    """Windowed dog-leg at 2e7 histories (several chunks of the event form's
+    bank), checked on a sample of histories (split progeny included)
+    against the oracle."""
+    from paper_2305_07636_amd import learned_ww as lw
+
+    p = w.cfg5_dogleg(detector=w.LEG_A_DETECTOR)
+    # importance windows from an oracle run of the adjoint problem (forward
+    # flux windows multiply the population a thousandfold here)
+    adj = lw.adjoint_problem(p)
+    e = oracle.estimates(adj, oracle.run(adj, 20000, 77))
+    phi = e["mean"].ravel()
+    ok = phi > 0
+    logI = np.where(ok, np.log10(np.where(ok, phi, 1.0)), -np.inf)
+    table = lw.centres_from_log_importance(logI, float(np.percentile(logI[ok], 70.0)), (1, 2, 10, 10, 40))
+    print(f"[ww] dog-leg 2e7 sampled alg={alg}", flush=True)
+    out = compare_sampled(p, 20_000_000, 51, alg, n_sample=1000, ww={"centers": table})
+    assert out["splits"] > 0
