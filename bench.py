@@ -195,7 +195,7 @@ def main():
     ap.add_argument("--no-fom", action="store_true")
     ap.add_argument("--fom-pilot", type=float, default=1e8)
     ap.add_argument("--fom-analog", type=float, default=4e9)
-    ap.add_argument("--fom-ww", type=float, default=1e8)
+    ap.add_argument("--fom-ww", type=float, default=1e9)
     ap.add_argument("--fom-steps", type=int, default=3000)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 1 GiB device-to-device copy (reference for HBM counters)")
