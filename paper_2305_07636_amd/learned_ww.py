@@ -146,7 +146,7 @@ def _frontier_table(logI, ok, shape, pct):
 
 def learned_windows(prob: dict, n_pilot: int = 100_000_000, seed: int = 50, steps: int = 3000,
                     lr: float = 1e-3, net_seed: int = 1, rel_max: float = 0.3, frontier_pct: float = 5.0,
-                    below: float = 0.0):
+                    below: float = 0.0, extrapolate: float = 1.0, normalise: str = "auto"):
     """Plain pilots -> training set -> network -> window table.
 
     1. forward analog pilot: the flux phi, which is the importance of the
@@ -158,6 +158,12 @@ def learned_windows(prob: dict, n_pilot: int = 100_000_000, seed: int = 50, step
        (weights 1 / (R^2 + 0.01)); BF16 inference gives log10 I on every
        cell; windows w_c = I(source) / I(cell), normalised over the source
        cells when the pilot resolved them, else at the resolved frontier.
+
+    extrapolate: decades the network's prediction may leave the range of
+    the pilot's values (cells the pilot did not resolve).  normalise:
+    "auto" (source if the pilot resolved the source cells, else frontier),
+    "source" (the network's importance at the source cells, resolved or
+    not) or "frontier".
 
     Returns (table [K][G][wz][wy][wx], info dict with the raw-tally table
     and timings)."""
@@ -189,21 +195,22 @@ def learned_windows(prob: dict, n_pilot: int = 100_000_000, seed: int = 50, step
     t_train = time.perf_counter() - t1
     # keep the prediction within the range the pilot saw (no runaway
     # extrapolation into cells the network never observed)
-    yhat = np.clip(yhat, T.min() - 1.0, T.max() + 1.0)
+    yhat = np.clip(yhat, T.min() - extrapolate, T.max() + extrapolate)
     src = source_cells(prob)
     pmf = np.asarray(prob["source"]["group_pmf"], dtype=np.float64)
     ok5 = ok.reshape(shape)
     src_resolved = all(ok5[0, g][src].any() for g in range(shape[1]) if pmf[g] > 0)
     y5 = yhat.reshape(shape)
-    if src_resolved:
+    use_source = normalise == "source" or (normalise == "auto" and src_resolved)
+    if use_source:
         # importance of the source: spectrum-weighted mean over source cells
         I_src = sum(pmf[g] * np.mean(10.0 ** y5[0, g][src]) for g in range(shape[1]) if pmf[g] > 0)
         log_ref = float(np.log10(I_src))
     else:
         log_ref = float(np.percentile(T, frontier_pct))
-    table = centres_from_log_importance(yhat, log_ref, shape, below if src_resolved else 0.0)
+    table = centres_from_log_importance(yhat, log_ref, shape, below if use_source else 0.0)
     raw = centres_from_log_importance(np.where(ok, np.log10(np.where(ok, phi, 1.0)), -np.inf), log_ref, shape,
-                                      below if src_resolved else 0.0)
+                                      below if use_source else 0.0)
     info = {"pilot_s": t_pilot, "train_s": t_train, "n_train": int(ok.sum()), "loss_first": float(losses[0]),
             "loss_last": float(losses[-1]), "raw_table": raw, "adjoint_flux": phi,
             "source_resolved": bool(src_resolved), "log_ref": log_ref}
