@@ -234,8 +234,10 @@ typedef struct {
 } mcdc_result;
 
 /*
- * Validate a descriptor and compile it: merge geometry, tally, detector and
- * weight-window planes per axis into one union grid (exact de-duplication),
+ * Validate a descriptor (the problem statement of Section 3: materials,
+ * box geometry, source, mesh tallies) and compile it: merge geometry,
+ * tally, detector and weight-window planes per axis into one union grid
+ * (exact de-duplication),
  * derive the per-cell material/tally tables and the cross-section tables
  * (1/sigma_t, scattering probability, outgoing-group CDF, 1/speed), and
  * upload them to the current HIP device.  *out is owned by the caller and
@@ -289,8 +291,11 @@ int mcdc_run_batched(mcdc_problem *const *ps, int32_t n, const uint64_t *n_hist,
                      const mcdc_run_options *opt, mcdc_result *outs);
 
 /*
- * Set weight-window centres for later runs: centers[K][G][wz][wy][wx] over
- * the weight-window mesh (0 = no window in that cell); ratio rho > 1 sets
+ * Set weight-window centres for later runs.  The paper runs analog only
+ * (Section 3.3); weight windows are this library's variance reduction,
+ * which changes the variance and never the mean.
+ * centers[K][G][wz][wy][wx] over the weight-window mesh (0 = no window in
+ * that cell); ratio rho > 1 sets
  * the window [2 w_c / (1 + rho), 2 rho w_c / (1 + rho)] with survival weight
  * w_c; a particle above the window splits into min(ceil(w / w_U),
  * max_split) copies.  centers == NULL returns the problem to analog
@@ -300,10 +305,10 @@ int mcdc_set_weight_windows(mcdc_problem *p, const double *centers, double ratio
                             int32_t max_split);
 
 /*
- * Weight-window network: the learned weight-window generator maps a tally
- * cell's features (x, y, z scaled to [0, 1], one-hot group, scaled time,
- * zero-padded to 8) to the log10 of a flux estimate, from which window
- * centres are formed.  Architecture: 8 -> 64 -> 64 -> 64 -> 1, tanh on the
+ * Weight-window network (no counterpart in the paper): the learned
+ * weight-window generator maps a window cell's features (x, y, z scaled to
+ * [0, 1], one-hot group, scaled time, zero-padded to 8) to the log10 of an
+ * importance (adjoint flux) estimate, from which window centres are formed.  Architecture: 8 -> 64 -> 64 -> 64 -> 1, tanh on the
  * hidden layers, linear output (the only supported widths).  Training is
  * FP32 on matrix cores (weighted mean-squared error, full batch, Adam with
  * beta = (0.9, 0.999), eps = 1e-8); inference rounds weights and
