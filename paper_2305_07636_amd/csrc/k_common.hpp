@@ -419,7 +419,56 @@ __device__ __forceinline__ void add_leak(const DevProblem &P, const RunArgs &R, 
     atomic_add_f64(L + ((int64_t)k * P.G + g) * 6 + face, w);
 }
 
+
+// Read-only tables a kernel may copy into LDS at its start: union planes,
+// time edges, cross sections, speeds, per-cell material and tally bin.
+template <int BS, class T>
+__device__ __forceinline__ const T *stage(const T *src, const LdsTables &lt, int id, char *base) {
+    T *dst = reinterpret_cast<T *>(base + lt.off[id]);
+    for (int j = threadIdx.x; j < lt.count[id]; j += BS) dst[j] = src[j];
+    return dst;
+}
+
+// The problem as a kernel sees it: with LT every staged table is read from
+// LDS at base (the copies need a barrier before use), else from P0.
+template <bool LT, int BS>
+__device__ __forceinline__ DevProblem stage_tables(const DevProblem &P0, const LdsTables &lt, char *base) {
+    DevProblem P = P0;
+    if (LT) {
+        P.U[0] = stage<BS>(P0.U[0], lt, kTU0, base);
+        P.U[1] = stage<BS>(P0.U[1], lt, kTU1, base);
+        P.U[2] = stage<BS>(P0.U[2], lt, kTU2, base);
+        P.T = stage<BS>(P0.T, lt, kTT, base);
+        P.sigma_t = stage<BS>(P0.sigma_t, lt, kTSt, base);
+        P.inv_st = stage<BS>(P0.inv_st, lt, kTISt, base);
+        P.ps = stage<BS>(P0.ps, lt, kTPs, base);
+        P.cdf = stage<BS>(P0.cdf, lt, kTCdf, base);
+        P.speed = stage<BS>(P0.speed, lt, kTV, base);
+        P.inv_v = stage<BS>(P0.inv_v, lt, kTIV, base);
+        P.cell_mat = stage<BS>(P0.cell_mat, lt, kTMat, base);
+        P.cell_tal = stage<BS>(P0.cell_tal, lt, kTTal, base);
+    }
+    return P;
+}
+
 }  // namespace dev
+
+// Layout of the staged tables within `budget` bytes; false if they do not
+// fit.
+inline bool table_layout(const DevProblem &P, LdsTables &t, int64_t budget) {
+    const int64_t mg = (int64_t)P.M * P.G;
+    const int64_t cnt[kTabs] = {P.nU[0], P.nU[1], P.nU[2], P.K + 1, mg, mg, mg, mg * P.G, P.G, P.G, P.ncells, P.ncells};
+    const int64_t size[kTabs] = {8, 8, 8, 8, 8, 8, 8, 8, 8, 8, 4, 4};
+    int64_t off = 0;
+    for (int j = 0; j < kTabs; ++j) {
+        t.off[j] = (int)off;
+        t.count[j] = (int)cnt[j];
+        off += (cnt[j] * size[j] + 15) & ~(int64_t)15;
+        if (off > budget) return false;
+    }
+    t.bytes = (int)off;
+    return true;
+}
 
 // Split bank of the weight-window game (k_history.hip): carve two
 // generations' banks for chunks of up to `chunk` histories, clear the first

@@ -326,35 +326,6 @@ __device__ __forceinline__ void score_flight(const DevProblem &P, const RunArgs 
     }
 }
 
-template <class T>
-__device__ __forceinline__ const T *stage(const T *src, const LdsTables &lt, int id, char *base) {
-    T *dst = reinterpret_cast<T *>(base + lt.off[id]);
-    for (int j = threadIdx.x; j < lt.count[id]; j += kBlock) dst[j] = src[j];
-    return dst;
-}
-
-// The problem as the step kernels see it: with LT, every staged table is
-// read from LDS (the copies need a barrier before use).
-template <bool LT>
-__device__ __forceinline__ DevProblem stage_tables(const DevProblem &P0, const LdsTables &lt, char *base) {
-    DevProblem P = P0;
-    if (LT) {
-        P.U[0] = stage(P0.U[0], lt, kTU0, base);
-        P.U[1] = stage(P0.U[1], lt, kTU1, base);
-        P.U[2] = stage(P0.U[2], lt, kTU2, base);
-        P.T = stage(P0.T, lt, kTT, base);
-        P.sigma_t = stage(P0.sigma_t, lt, kTSt, base);
-        P.inv_st = stage(P0.inv_st, lt, kTISt, base);
-        P.ps = stage(P0.ps, lt, kTPs, base);
-        P.cdf = stage(P0.cdf, lt, kTCdf, base);
-        P.speed = stage(P0.speed, lt, kTV, base);
-        P.inv_v = stage(P0.inv_v, lt, kTIV, base);
-        P.cell_mat = stage(P0.cell_mat, lt, kTMat, base);
-        P.cell_tal = stage(P0.cell_tal, lt, kTTal, base);
-    }
-    return P;
-}
-
 // ---------------------------------------------------------------------------
 // source: workgroup b samples histories [b L, (b + 1) L) of the chunk
 // ---------------------------------------------------------------------------
@@ -437,7 +408,7 @@ __global__ void __launch_bounds__(kBlock) k_advance(DevProblem P0, RunArgs R0, B
     StepScore sc;
     init_slice(sc, lt, gn, C.seg_b0[seg]);
     const DevProblem P =
-        stage_tables<LT>(BAT ? items[prob].P : P0, BAT ? items[prob].tabs : tabs0, reinterpret_cast<char *>(lt + 2 * gn));
+        stage_tables<LT, kBlock>(BAT ? items[prob].P : P0, BAT ? items[prob].tabs : tabs0, reinterpret_cast<char *>(lt + 2 * gn));
     __syncthreads();
     // software pipeline: the next particle's state is in flight while the
     // current one is moved
@@ -550,7 +521,7 @@ __global__ void __launch_bounds__(kBlock) k_event(DevProblem P0, RunArgs R0, Ban
     StepScore sc;
     init_slice(sc, lt, gn, C.seg_b0[seg]);
     const DevProblem P =
-        stage_tables<LT>(BAT ? items[prob].P : P0, BAT ? items[prob].tabs : tabs0, reinterpret_cast<char *>(lt + 2 * gn));
+        stage_tables<LT, kBlock>(BAT ? items[prob].P : P0, BAT ? items[prob].tabs : tabs0, reinterpret_cast<char *>(lt + 2 * gn));
     __syncthreads();
 
     Particle p;
@@ -747,22 +718,6 @@ void key_add(std::vector<char> &k, const T &v) {
 // and the lattice workloads (four 256-thread ones: 5 % slower; segment
 // counts that are not a multiple of the CU count: 10-20 % slower).
 constexpr int kSegmentsPerCU = 2;
-
-// Layout of the staged tables; false if they do not fit the LDS budget.
-bool table_layout(const DevProblem &P, LdsTables &t) {
-    const int64_t mg = (int64_t)P.M * P.G;
-    const int64_t cnt[kTabs] = {P.nU[0], P.nU[1], P.nU[2], P.K + 1, mg, mg, mg, mg * P.G, P.G, P.G, P.ncells, P.ncells};
-    const int64_t size[kTabs] = {8, 8, 8, 8, 8, 8, 8, 8, 8, 8, 4, 4};
-    int64_t off = 0;
-    for (int j = 0; j < kTabs; ++j) {
-        t.off[j] = (int)off;
-        t.count[j] = (int)cnt[j];
-        off += (cnt[j] * size[j] + 15) & ~(int64_t)15;
-        if (off > kLdsTablesMax) return false;
-    }
-    t.bytes = (int)off;
-    return true;
-}
 
 template <int FM, bool WW, bool LT>
 int run_event(mcdc_problem *pb, const RunArgs &R0, uint64_t first, uint64_t count, const mcdc_run_options &opt,
@@ -985,7 +940,7 @@ int launch_event_batched(std::vector<BatchItem> &items, const uint64_t *n_hist, 
     std::vector<bool> fit(n);
     for (int j = 0; j < n; ++j) {
         const DevProblem &P = items[j].P;
-        fit[j] = table_layout(P, items[j].tabs);
+        fit[j] = table_layout(P, items[j].tabs, kLdsTablesMax);
         lt_all = lt_all && fit[j];
         const int64_t gn64 = (int64_t)P.G * P.nts;
         items[j].gn = (2 * gn64 <= kLdsTallyMax) ? (int)gn64 : 0;
@@ -1040,7 +995,7 @@ int launch_event(mcdc_problem *p, const RunArgs &R, uint64_t first, uint64_t cou
         return MCDC_E_UNSUPPORTED;
     }
     LdsTables tabs{};
-    const bool lt = table_layout(P, tabs);
+    const bool lt = table_layout(P, tabs, kLdsTablesMax);
     if (P.ww_center != nullptr) {
         if (P.finite_mask == 1) return run_event_lt<1, true>(p, R, first, count, opt, st, prof, tabs, lt);
         if (P.finite_mask == 7) return run_event_lt<7, true>(p, R, first, count, opt, st, prof, tabs, lt);

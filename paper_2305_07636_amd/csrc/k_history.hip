@@ -159,20 +159,26 @@ __device__ __forceinline__ void end_history(const DevProblem &P, const RunArgs &
 // device-wide counter at a time scale with the job (about 16 takes per
 // wave), so short histories do not serialise on that one counter.
 constexpr int kRefillMin = 32;
+// LDS budget for the persistent kernel's staged tables.
+constexpr int64_t kHistoryTablesMax = 40 * 1024;
 
 // Persistent history form: every wave takes chunks of consecutive histories
 // [first, first + count) from a device counter; a lane whose particle has
 // terminated starts the next history of the wave's chunk at once, so a
 // wave is not held back by its longest history.  Every wave exits once the
 // counter has passed the end and its lanes are idle.
-template <int FM, bool WW>
-__global__ void __launch_bounds__(256) k_history(DevProblem P, RunArgs R, uint64_t first, uint64_t count,
+// (LT: the flight tables are copied into LDS first; the workgroups live
+// for the whole run, so the copy is paid once per workgroup.)
+template <int FM, bool WW, bool LT>
+__global__ void __launch_bounds__(256) k_history(DevProblem P0, RunArgs R, uint64_t first, uint64_t count,
                                                  uint64_t chunk_first, SplitBank SB, unsigned long long *next,
-                                                 unsigned int wave_chunk) {
+                                                 unsigned int wave_chunk, LdsTables tabs) {
     __shared__ unsigned long long red[kCounters + 1];
     __shared__ double qsum[2];
+    extern __shared__ double lds_tables[];
     if (threadIdx.x < kCounters + 1) red[threadIdx.x] = 0ull;
     if (threadIdx.x < 2) qsum[threadIdx.x] = 0.0;
+    const DevProblem P = stage_tables<LT, 256>(P0, tabs, reinterpret_cast<char *>(lds_tables));
     __syncthreads();
 
     uint64_t c_pos = 0, c_end = 0;   // the wave's current chunk (wave-uniform)
@@ -332,9 +338,13 @@ int launch_main(mcdc_problem *pb, const DevProblem &P, const RunArgs &R, uint64_
     int rc;
     if ((rc = ensure(pb->work, 256))) return rc;
     unsigned long long *next = (unsigned long long *)pb->work.p;
+    LdsTables tabs{};
+    const bool lt = table_layout(P, tabs, kHistoryTablesMax);
+    const size_t shmem = lt ? (size_t)tabs.bytes : 0;
     int per_cu = 0, n_cu = 0;
     hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &per_cu, reinterpret_cast<const void *>(&k_history<FM, WW>), bs, 0);
+        &per_cu, lt ? reinterpret_cast<const void *>(&k_history<FM, WW, true>)
+                    : reinterpret_cast<const void *>(&k_history<FM, WW, false>), bs, shmem);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, pb->device);
     if (e != hipSuccess) return hip_fail(e, "occupancy query");
     uint64_t grid = (uint64_t)(per_cu > 0 ? per_cu : 1) * (uint64_t)(n_cu > 0 ? n_cu : 1);
@@ -344,8 +354,12 @@ int launch_main(mcdc_problem *pb, const DevProblem &P, const RunArgs &R, uint64_
     const uint64_t grid_needed = ((count + wc - 1) / wc + bs / 64 - 1) / (bs / 64);
     if (grid > grid_needed) grid = grid_needed;
     hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(1), 0, st, next);
-    launch_timed(prof, MCDC_PROF_HISTORY, k_history<FM, WW>, dim3((unsigned)grid), dim3(bs), 0u, st, P, R, first,
-                 count, chunk_first, SB, next, (unsigned int)wc);
+    if (lt)
+        launch_timed(prof, MCDC_PROF_HISTORY, k_history<FM, WW, true>, dim3((unsigned)grid), dim3(bs),
+                     (uint32_t)shmem, st, P, R, first, count, chunk_first, SB, next, (unsigned int)wc, tabs);
+    else
+        launch_timed(prof, MCDC_PROF_HISTORY, k_history<FM, WW, false>, dim3((unsigned)grid), dim3(bs), 0u, st, P, R,
+                     first, count, chunk_first, SB, next, (unsigned int)wc, tabs);
     return MCDC_OK;
 }
 

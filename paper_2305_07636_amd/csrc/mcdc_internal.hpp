@@ -16,7 +16,7 @@ namespace mcdc {
 constexpr int kMaxGroups = 32;      // outgoing-group search is unrolled over this
 constexpr int kCounters = 9;        // census, surface, collision; 5 terminations; splits
 constexpr int kLdsTallyMax = 4096;  // doubles of the event form's per-step LDS tally slice
-constexpr uint64_t kWindowChunk = 1ULL << 21;  // histories per chunk of a weight-window run
+constexpr uint64_t kWindowChunk = 1ULL << 23;  // histories per chunk of a weight-window run
 constexpr uint64_t kStride = 152917ULL;
 
 enum Term : int { kAbsorb = 0, kLeak = 1, kTime = 2, kLost = 3, kRoulette = 4 };
