@@ -50,13 +50,32 @@ constexpr int kBlock = 512;
 constexpr int kLdsTablesMax = 32 * 1024;    // bytes of staged tables
 constexpr uint32_t kHidMask = 0x0FFFFFFFu;  // history index within a chunk (< 2^28)
 
+// A bank of particle states in tiles of 64 slots (one wavefront): inside a
+// tile every field is one contiguous run of 64 values, so a wave's access
+// to a field is one contiguous run and its whole state one contiguous
+// block of HBM (one DRAM stream per wave instead of one per field array).
+// Fields: x, u per stored axis, t, tau, (w), RNG state (8 B each), then
+// the packed cell ix | iy << 11 | iz << 22, g | batch << 5 | k << 15 and
+// the history index within the chunk | crossing axes << 29 (surface queue)
+// (4 B each).
 struct Bank {
-    double *x[3], *u[3], *t, *tau, *w;
-    uint64_t *s;
-    uint32_t *ixyz;   // ix | iy << 11 | iz << 22
-    uint32_t *gk;     // g | batch << 5 | k << 15
-    uint32_t *hid;    // history index within the chunk | crossing axes << 29 (surface queue)
+    char *base;                // tile 0
+    uint32_t tile;             // bytes per tile: 64 * bytes per particle
+    uint32_t ox[3], ou[3];     // byte offset of each field's run within a tile
+    uint32_t ot, otau, ow, os, oc, ogk, ohid;
 };
+
+// Field access: byte offset of slot's value in its tile's run of the field.
+__device__ __forceinline__ uint64_t tile_off8(const Bank &B, uint32_t slot) {
+    return (uint64_t)(slot >> 6) * B.tile + (slot & 63u) * 8u;
+}
+__device__ __forceinline__ uint64_t tile_off4(const Bank &B, uint32_t slot) {
+    return (uint64_t)(slot >> 6) * B.tile + (slot & 63u) * 4u;
+}
+template <class T>
+__device__ __forceinline__ T &fld(const Bank &B, uint32_t field, uint64_t off) {
+    return *reinterpret_cast<T *>(B.base + field + off);
+}
 
 // Per-segment fill counts of the banks and queues, plus the step index.
 // Only workgroup b reads or writes the entries of segment b.
@@ -156,23 +175,24 @@ __device__ __forceinline__ void hist_term(const RunArgs &R, uint64_t i, int code
 template <int FM, bool WW>
 __device__ __forceinline__ void load_state(const DevProblem &P, const Bank &B, uint32_t slot, Particle &p,
                                            uint32_t &gk, uint32_t &hidw) {
+    const uint64_t o8 = tile_off8(B, slot), o4 = tile_off4(B, slot);
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         if (finite_axis<FM>(P, a)) {
-            p.x[a] = B.x[a][slot];
-            p.u[a] = B.u[a][slot];
+            p.x[a] = fld<double>(B, B.ox[a], o8);
+            p.u[a] = fld<double>(B, B.ou[a], o8);
         } else {
             p.x[a] = 0.0;   // stays 0 in flight; copied whole to split progeny
             p.u[a] = 0.0;
         }
     }
-    p.t = B.t[slot];
-    p.tau = B.tau[slot];
-    p.w = WW ? B.w[slot] : 1.0;
-    p.s = B.s[slot];
-    const uint32_t c = B.ixyz[slot];
-    gk = B.gk[slot];
-    hidw = B.hid[slot];
+    p.t = fld<double>(B, B.ot, o8);
+    p.tau = fld<double>(B, B.otau, o8);
+    p.w = WW ? fld<double>(B, B.ow, o8) : 1.0;
+    p.s = fld<uint64_t>(B, B.os, o8);
+    const uint32_t c = fld<uint32_t>(B, B.oc, o4);
+    gk = fld<uint32_t>(B, B.ogk, o4);
+    hidw = fld<uint32_t>(B, B.ohid, o4);
     set_inverse<FM>(P, p);
     p.ix[0] = c & 2047u;
     p.ix[1] = (c >> 11) & 2047u;
@@ -192,20 +212,21 @@ struct RawState {
 
 template <int FM, bool WW>
 __device__ __forceinline__ void load_raw(const DevProblem &P, const Bank &B, uint32_t slot, RawState &r) {
+    const uint64_t o8 = tile_off8(B, slot), o4 = tile_off4(B, slot);
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         if (finite_axis<FM>(P, a)) {
-            r.x[a] = B.x[a][slot];
-            r.u[a] = B.u[a][slot];
+            r.x[a] = fld<double>(B, B.ox[a], o8);
+            r.u[a] = fld<double>(B, B.ou[a], o8);
         }
     }
-    r.t = B.t[slot];
-    r.tau = B.tau[slot];
-    if (WW) r.w = B.w[slot];
-    r.s = B.s[slot];
-    r.c = B.ixyz[slot];
-    r.gk = B.gk[slot];
-    r.hidw = B.hid[slot];
+    r.t = fld<double>(B, B.ot, o8);
+    r.tau = fld<double>(B, B.otau, o8);
+    if (WW) r.w = fld<double>(B, B.ow, o8);
+    r.s = fld<uint64_t>(B, B.os, o8);
+    r.c = fld<uint32_t>(B, B.oc, o4);
+    r.gk = fld<uint32_t>(B, B.ogk, o4);
+    r.hidw = fld<uint32_t>(B, B.ohid, o4);
 }
 
 template <int FM, bool WW>
@@ -230,20 +251,21 @@ __device__ __forceinline__ void unpack(const DevProblem &P, const RawState &r, P
 template <int FM, bool WW>
 __device__ __forceinline__ void store_state(const DevProblem &P, const Bank &B, uint32_t slot,
                                             const Particle &p, uint32_t gk, uint32_t hidw) {
+    const uint64_t o8 = tile_off8(B, slot), o4 = tile_off4(B, slot);
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         if (finite_axis<FM>(P, a)) {
-            B.x[a][slot] = p.x[a];
-            B.u[a][slot] = p.u[a];
+            fld<double>(B, B.ox[a], o8) = p.x[a];
+            fld<double>(B, B.ou[a], o8) = p.u[a];
         }
     }
-    B.t[slot] = p.t;
-    B.tau[slot] = p.tau;
-    if (WW) B.w[slot] = p.w;
-    B.s[slot] = p.s;
-    B.ixyz[slot] = pack_ix(p.ix);
-    B.gk[slot] = gk;
-    B.hid[slot] = hidw;
+    fld<double>(B, B.ot, o8) = p.t;
+    fld<double>(B, B.otau, o8) = p.tau;
+    if (WW) fld<double>(B, B.ow, o8) = p.w;
+    fld<uint64_t>(B, B.os, o8) = p.s;
+    fld<uint32_t>(B, B.oc, o4) = pack_ix(p.ix);
+    fld<uint32_t>(B, B.ogk, o4) = gk;
+    fld<uint32_t>(B, B.ohid, o4) = hidw;
 }
 
 __device__ __forceinline__ uint32_t with_gk(uint32_t gk, const Particle &p) {
@@ -650,11 +672,49 @@ struct Layout {
 
 size_t pad256(size_t b) { return (b + 255) & ~size_t(255); }
 
-size_t bank_bytes(uint64_t slots) { return 10 * pad256(slots * 8) + 3 * pad256(slots * 4); }
+// Tile layout of a bank for the axes in fmask (all three if 0) and, with
+// ww, the weight field.
+Bank bank_layout(int fmask, bool ww) {
+    Bank B{};
+    const int axes = fmask ? fmask : 7;
+    uint32_t o = 0;
+    for (int a = 0; a < 3; ++a)
+        if ((axes >> a) & 1) {
+            B.ox[a] = o;
+            o += 512;
+        }
+    for (int a = 0; a < 3; ++a)
+        if ((axes >> a) & 1) {
+            B.ou[a] = o;
+            o += 512;
+        }
+    B.ot = o;
+    o += 512;
+    B.otau = o;
+    o += 512;
+    if (ww) {
+        B.ow = o;
+        o += 512;
+    }
+    B.os = o;
+    o += 512;
+    B.oc = o;
+    o += 256;
+    B.ogk = o;
+    o += 256;
+    B.ohid = o;
+    o += 256;
+    B.tile = o;
+    return B;
+}
+
+// Bytes of one bank of `slots` slots (whole tiles).
+size_t bank_bytes(uint64_t slots, int fmask, bool ww) { return ((slots + 63) / 64) * bank_layout(fmask, ww).tile; }
 
 size_t ctl_bytes(unsigned int G) { return pad256(2 * G * 4) + 3 * pad256(G * 4) + 2 * 256; }
 
-Layout carve(void *bank_mem, void *ctl_mem, uint64_t slots, unsigned int G, unsigned int Lseg) {
+Layout carve(void *bank_mem, void *ctl_mem, uint64_t slots, unsigned int G, unsigned int Lseg, int fmask,
+             bool ww) {
     Layout Lo{};
     char *p = (char *)bank_mem;
     auto take = [&](size_t bytes) {
@@ -664,15 +724,8 @@ Layout carve(void *bank_mem, void *ctl_mem, uint64_t slots, unsigned int G, unsi
     };
     for (int k = 0; k < 3; ++k) {
         Bank &B = (k < 2) ? Lo.bank[k] : Lo.ev;
-        for (int a = 0; a < 3; ++a) B.x[a] = (double *)take(slots * 8);
-        for (int a = 0; a < 3; ++a) B.u[a] = (double *)take(slots * 8);
-        B.t = (double *)take(slots * 8);
-        B.tau = (double *)take(slots * 8);
-        B.w = (double *)take(slots * 8);
-        B.s = (uint64_t *)take(slots * 8);
-        B.ixyz = (uint32_t *)take(slots * 4);
-        B.gk = (uint32_t *)take(slots * 4);
-        B.hid = (uint32_t *)take(slots * 4);
+        B = bank_layout(fmask, ww);
+        B.base = take(bank_bytes(slots, fmask, ww));
     }
     p = (char *)ctl_mem;
     Ctl &C = Lo.ctl;
@@ -752,13 +805,14 @@ int run_event(mcdc_problem *pb, const RunArgs &R0, uint64_t first, uint64_t coun
     const uint64_t g_need = (C + kBlock - 1) / kBlock;
     if (G > g_need) G = (unsigned int)g_need;
     if (G < 1) G = 1;
-    const unsigned int Lseg = (unsigned int)((C + G - 1) / G);
+    // (segments are whole tiles of 64 slots)
+    const unsigned int Lseg = (unsigned int)(((C + G - 1) / G + 63) & ~(uint64_t)63);
     const uint64_t slots = (uint64_t)G * Lseg;
     int rc;
-    if ((rc = ensure(pb->bank, bank_bytes(slots) * 3 + 64 * 256))) return rc;
+    if ((rc = ensure(pb->bank, pad256(bank_bytes(slots, FM, WW)) * 3 + 64 * 256))) return rc;
     if ((rc = ensure(pb->queues, ctl_bytes(G)))) return rc;
     if (P.qoi_on && (rc = ensure(pb->qoi_hist, C * sizeof(double)))) return rc;
-    Layout L = carve(pb->bank.p, pb->queues.p, slots, G, Lseg);
+    Layout L = carve(pb->bank.p, pb->queues.p, slots, G, Lseg, FM ? FM : P.finite_mask, WW);
     RunArgs R = R0;
     R.qoi_hist = (double *)pb->qoi_hist.p;
     // weight windows: split progeny of a chunk go to the split bank and are
@@ -864,7 +918,7 @@ template <int FM, bool LT>
 int run_batched_steps(const BatchItem *d_items, const SegInfo *d_segs, unsigned int G, unsigned int Lseg, int Kmax,
                       size_t shmem, void *bank_mem, void *ctl_mem, hipStream_t st) {
     const uint64_t slots = (uint64_t)G * Lseg;
-    Layout L = carve(bank_mem, ctl_mem, slots, G, Lseg);
+    Layout L = carve(bank_mem, ctl_mem, slots, G, Lseg, FM, false);
     const DevProblem P0{};
     const RunArgs R0{};
     const LdsTables t0{};
@@ -916,7 +970,7 @@ BatchedLayout batched_layout(const uint64_t *n_hist, int n, unsigned int Lseg) {
     b.segs_off = pad256(sizeof(BatchItem) * n);
     b.ctl_off = b.segs_off + pad256(sizeof(SegInfo) * G);
     b.bank_off = b.ctl_off + ctl_bytes((unsigned int)G);
-    b.bytes = b.bank_off + bank_bytes(G * Lseg) * 3 + 64 * 256;
+    b.bytes = b.bank_off + pad256(bank_bytes(G * Lseg, 0, false)) * 3 + 64 * 256;
     return b;
 }
 
