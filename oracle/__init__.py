@@ -59,6 +59,7 @@ class _Problem(C.Structure):
         ("qoi_groups", _IP),
         ("n_ww", C.c_int32 * 3), ("ww", _DP * 3),
         ("ww_center", _DP), ("ww_ratio", C.c_double), ("ww_max_split", C.c_int32),
+        ("time_crossing", C.c_int32),
     ]
 
 
@@ -82,7 +83,8 @@ def lib():
         _lib.oracle_run.restype = C.c_int
         _lib.oracle_run.argtypes = [C.c_void_p, C.c_uint64, C.c_uint64, C.c_void_p,
                                     C.c_uint64, C.c_uint64, C.c_void_p, C.c_void_p,
-                                    C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+                                    C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                    C.c_void_p]
         _lib.oracle_trace.restype = C.c_int
         _lib.oracle_trace.argtypes = [C.c_void_p, C.c_uint64, C.c_uint64, C.c_uint64,
                                       C.c_void_p, C.c_int]
@@ -156,6 +158,8 @@ class OracleProblem:
             s.ww_center = _dp(arr(ww_center))
             s.ww_ratio = float(ww_ratio)
             s.ww_max_split = int(ww_max_split)
+        s.time_crossing = 1 if tal.get("time_crossing", False) else 0
+        self.time_crossing = bool(s.time_crossing)
         self.struct = s
         self._keep = keep
         self.G, self.M = G, M
@@ -204,7 +208,9 @@ def run(prob, N: int, seed: int, ids=None, first: int = 0, count=None,
         records: bool = False, ww_center=None, ww_ratio=5.0, ww_max_split=16):
     """Run histories of an N-history job through the oracle.
 
-    Returns raw per-batch sums 'S' [B, ntally], leak sums 'L' [B, K, G, 6],
+    Returns raw per-batch sums 'S' [B, ntally], time-crossing sums 'X'
+    [B, ntally] (zeros unless the problem's tally asks for them), leak sums
+    'L' [B, K, G, 6],
     detector sums 'q' = (sum x, sum x^2), totals 'tot' (census, surface,
     collision events; absorb, leak, time, lost, roulette terminations;
     splits), and if records: per-history 'rec' [n, 5] = (census, surface,
@@ -223,6 +229,7 @@ def run(prob, N: int, seed: int, ids=None, first: int = 0, count=None,
         if first < 0 or n < 0 or first + n > N:
             raise ValueError(f"histories [{first}, {first + n}) outside the {N}-history job")
     S = np.zeros((B, op.ntally))
+    X = np.zeros((B, op.ntally))
     L = np.zeros((B, op.K, op.G, 6))
     q = np.zeros(2)
     tot = np.zeros(9, dtype=np.uint64)
@@ -232,10 +239,11 @@ def run(prob, N: int, seed: int, ids=None, first: int = 0, count=None,
                           first, n, S.ctypes.data, L.ctypes.data, q.ctypes.data,
                           tot.ctypes.data,
                           rec.ctypes.data if records else None,
-                          trk.ctypes.data if records else None)
+                          trk.ctypes.data if records else None,
+                          X.ctypes.data)
     if rc != 0:
         raise RuntimeError(f"oracle_run failed with code {rc}")
-    out = {"S": S, "L": L, "q": q, "tot": tot, "N": N, "B": B, "op": op}
+    out = {"S": S, "X": X, "L": L, "q": q, "tot": tot, "N": N, "B": B, "op": op}
     if records:
         out["rec"] = rec
         out["trk"] = trk
@@ -286,6 +294,17 @@ def estimates(prob, res) -> dict:
     out = {"mean": mean.reshape(op.tally_shape), "var": var.reshape(op.tally_shape),
            "raw": total.reshape(op.tally_shape),
            "leak_mean": leak_mean, "leak_var": leak_var}
+    if op.time_crossing:
+        # time-crossing flux at the edges T_1..T_K: sum_b X_b / (N V), no
+        # time width; batch variance as for the bin fluxes
+        vnorm = (bin_volumes(prob)[None, None, :, :, :] *
+                 np.ones((op.K, op.G, 1, 1, 1))).reshape(-1)
+        X = res["X"]
+        xt = X.sum(axis=0)
+        xb = X / (Nb[:, None] * vnorm[None, :])
+        xvar = (((xb - xb.mean(axis=0)) ** 2).sum(axis=0) / (B * (B - 1))) if B > 1 else np.zeros_like(xt)
+        out["tc_mean"] = (xt / (N * vnorm)).reshape(op.tally_shape)
+        out["tc_var"] = xvar.reshape(op.tally_shape)
     q = prob.get("qoi")
     if q is not None:
         vol = 1.0

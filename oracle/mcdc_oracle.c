@@ -43,6 +43,13 @@
  *       cell); bounds w_L = 2 w_c / (1 + rho), w_U = rho w_L, survival weight
  *       w_c; split into n = min(ceil(w / w_U), max_split) copies; children
  *       take streams SplitMix64(parent state xor j) masked to 63 bits.
+ *   R11 Time-crossing estimator (optional; Section 3, verification with the
+ *       multigroup pulse, names it without formulas): the scalar flux at
+ *       the time edge T_{k+1} (k = 0..K-1) is estimated by every particle
+ *       that reaches that edge alive, scoring w * v_g into the spatial bin
+ *       of its cell at that instant, before the weight-window check;
+ *       normalised by N V (no time width).  A particle born exactly on an
+ *       edge does not cross it.
  *
  * Build: gcc -O2 -ffp-contract=off -fPIC -shared -o liboracle.so mcdc_oracle.c -lm
  */
@@ -86,6 +93,8 @@ typedef struct {
     const double *ww_center; /* [K][G][wz][wy][wx] or NULL (analog) */
     double ww_ratio;
     int32_t ww_max_split;
+    /* time-crossing estimator of the flux at the time edges (R11) */
+    int32_t time_crossing;
 } oracle_problem;
 
 enum { EV_CENSUS = 0, EV_SURFACE = 1, EV_COLLISION = 2 };
@@ -285,6 +294,7 @@ typedef struct {
     double *src_cdf;    /* [G] */
     /* outputs */
     double *S, *Sc;     /* [B][ntally] raw sums + compensation */
+    double *X, *Xc;     /* [B][ntally] time-crossing sums (edge T_{k+1} at k) */
     double *L, *Lc;     /* [B][K][G][6] leak sums */
     double q[2], qc[2]; /* detector: sum x, sum x^2 over histories */
     uint64_t tot[9];    /* events: census, surface, collision; terminations
@@ -489,6 +499,13 @@ static int step(ctx *C, particle *pt, int b, particle *stack, int *sp, hist_rec 
     if (ev == EV_CENSUS) {
         h->n_census++;
         C->tot[0]++;
+        /* R11: the particle is at the edge T_{k+1} now */
+        if (p->time_crossing) {
+            int64_t jx = tally_bin(C, pt);
+            if (jx >= 0)
+                csum(&C->X[(int64_t)b * C->ntally + jx], &C->Xc[(int64_t)b * C->ntally + jx],
+                     pt->w * p->speed[pt->g]);
+        }
         pt->since = 0;
         pt->k++;
         if (pt->k == C->K) {
@@ -678,6 +695,8 @@ static void ctx_free(ctx *C)
     free(C->src_cdf);
     free(C->S);
     free(C->Sc);
+    free(C->X);
+    free(C->Xc);
     free(C->L);
     free(C->Lc);
 }
@@ -709,16 +728,17 @@ int oracle_union_planes(const oracle_problem *p, int axis, double *out, int cap)
  * the contiguous range first..first+n_ids-1).  Accumulates raw per-batch
  * tally sums S[B][ntally] and leak sums L[B][K][G][6] (both may be NULL),
  * detector sums q[2] = (sum x, sum x^2), event and termination totals
- * tot[9], and per-history records rec[n_ids][5] = (census, surface,
- * collision, particles, termination mask) and per-history track and
- * detector scores trk[n_ids][2].  Returns 0, or -1 on an invalid problem,
+ * tot[9], per-history records rec[n_ids][5] = (census, surface,
+ * collision, particles, termination mask), per-history track and
+ * detector scores trk[n_ids][2], and time-crossing sums X[B][ntally] (R11;
+ * zeros unless the problem asks for them).  Returns 0, or -1 on an invalid problem,
  * -4 if split progeny overflow the per-history stack, -5 if a history
  * index is not below N.
  */
 int oracle_run(const oracle_problem *p, uint64_t N, uint64_t seed,
                const uint64_t *ids, uint64_t first, uint64_t n_ids,
                double *S_out, double *L_out, double *q_out, uint64_t *tot_out,
-               uint32_t *rec, double *trk)
+               uint32_t *rec, double *trk, double *X_out)
 {
     ctx C;
     if (ctx_init(&C, p) != 0) {
@@ -731,6 +751,8 @@ int oracle_run(const oracle_problem *p, uint64_t N, uint64_t seed,
     const int G = p->G;
     C.S = (double *)calloc((size_t)(B * C.ntally), sizeof(double));
     C.Sc = (double *)calloc((size_t)(B * C.ntally), sizeof(double));
+    C.X = (double *)calloc((size_t)(B * C.ntally), sizeof(double));
+    C.Xc = (double *)calloc((size_t)(B * C.ntally), sizeof(double));
     C.L = (double *)calloc((size_t)(B * C.K * G * 6), sizeof(double));
     C.Lc = (double *)calloc((size_t)(B * C.K * G * 6), sizeof(double));
     particle *stack = (particle *)malloc(sizeof(particle) * STACK_MAX);
@@ -774,6 +796,8 @@ int oracle_run(const oracle_problem *p, uint64_t N, uint64_t seed,
     }
     if (S_out)
         for (int64_t j = 0; j < B * C.ntally; j++) S_out[j] += C.S[j] + C.Sc[j];
+    if (X_out)
+        for (int64_t j = 0; j < B * C.ntally; j++) X_out[j] += C.X[j] + C.Xc[j];
     if (L_out)
         for (int64_t j = 0; j < B * C.K * G * 6; j++) L_out[j] += C.L[j] + C.Lc[j];
     if (q_out) {
@@ -803,6 +827,8 @@ int oracle_trace(const oracle_problem *p, uint64_t N, uint64_t seed, uint64_t i,
     if ((uint64_t)B > N) B = (int64_t)N;
     C.S = (double *)calloc((size_t)(B * C.ntally), sizeof(double));
     C.Sc = (double *)calloc((size_t)(B * C.ntally), sizeof(double));
+    C.X = (double *)calloc((size_t)(B * C.ntally), sizeof(double));
+    C.Xc = (double *)calloc((size_t)(B * C.ntally), sizeof(double));
     C.L = (double *)calloc((size_t)(B * C.K * p->G * 6), sizeof(double));
     C.Lc = (double *)calloc((size_t)(B * C.K * p->G * 6), sizeof(double));
     int b = (int)(((i + 1) * (uint64_t)B - 1) / N);

@@ -115,6 +115,25 @@ def infinite_medium_pulse_bins(sigma_t, sigma_s, speed, edges, volume):
     return np.array(out)
 
 
+def infinite_medium_pulse_points(sigma_t, sigma_s, speed, times, volume):
+    """Point values phi(t) = V exp(-M V t) n0 at the given times (n0 = one
+    particle in group 0 per volume).  Returns [len(times), G]."""
+    G = len(sigma_t)
+    V = np.diag(speed)
+    A = removal_matrix(sigma_t, sigma_s) @ V
+    n0 = np.zeros(G)
+    n0[0] = 1.0 / volume
+    return np.array([V @ (linalg.expm(-A * t) @ n0) for t in times])
+
+
+def plane_pulse_uncollided_point(x0, sigma_t, v, xa, xb, t):
+    """Average over [xa, xb] of the uncollided flux of an isotropic plane
+    pulse at x0 at time t > 0: e^{-St v t} / (2 t) on |x - x0| < v t."""
+    lo = max(xa, x0 - v * t)
+    hi = min(xb, x0 + v * t)
+    return math.exp(-sigma_t * v * t) * max(0.0, hi - lo) / (2.0 * t * (xb - xa))
+
+
 def pulse_population(c, t):
     """Particle population of an infinite one-group medium after a unit
     pulse, time in mean free times: exp((c - 1) t)."""

@@ -29,7 +29,9 @@ Problem dict schema (all floats are float64, all ints int32):
               (axis, sign = direction of the inward normal, mu_law in
               'beam' | 'uniform' | 'cosine')
     tally     dict: mesh list of 3 arrays (empty = one bin spanning the
-              axis), time_edges[K+1] (last may be +inf), n_batches
+              axis), time_edges[K+1] (last may be +inf), n_batches,
+              time_crossing (bool: also tally the flux at the time edges
+              T_1..T_K with the time-crossing estimator)
     qoi       None or dict: lo[3], hi[3], group_mask[G]
     ww_mesh   None or list of 3 arrays of weight-window mesh planes
 
@@ -95,6 +97,7 @@ def make_problem(sigma_t, sigma_s, speed, planes, material, bc, source, tally,
     tal["mesh"] = [_f64(m) for m in tal["mesh"]]
     tal["time_edges"] = _f64(tal["time_edges"])
     tal.setdefault("n_batches", 32)
+    tal["time_crossing"] = bool(tal.get("time_crossing", False))
     p = {
         "sigma_t": sigma_t,
         "sigma_s": _f64(sigma_s).reshape(M, G, G),
