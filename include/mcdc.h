@@ -35,7 +35,7 @@
 extern "C" {
 #endif
 
-#define MCDC_ABI_VERSION 1
+#define MCDC_ABI_VERSION 2
 
 /* return codes */
 #define MCDC_OK 0
@@ -98,6 +98,14 @@ typedef struct mcdc_problem mcdc_problem;
  *
  * Weight-window mesh (optional): planes per axis (0 = one window cell);
  * the window centres are set with mcdc_set_weight_windows.
+ *
+ * Time-crossing estimator (optional, time_crossing = 1; Section 3 tallies
+ * the flux on a time grid this way in its multigroup pulse verification):
+ * the scalar flux at each time edge T_1 .. T_K in the tally's space and
+ * group bins, estimated from every particle that reaches the edge alive
+ * (score w v_g in the bin of its position at that instant), per source
+ * particle and unit bin volume.  Shape [K][G][nz][ny][nx], entry k for
+ * edge T_{k+1} (an infinite last edge stays 0).  0 = off.
  */
 typedef struct {
     int32_t abi_version; /* MCDC_ABI_VERSION */
@@ -130,6 +138,7 @@ typedef struct {
     const int32_t *qoi_group_mask;
     int32_t n_ww_planes[3];
     const double *ww_planes[3];
+    int32_t time_crossing;
 } mcdc_problem_desc;
 
 /*
@@ -206,6 +215,11 @@ typedef struct {
  *  raw[ntally]                 unnormalised sum of w*d per bin.
  *  leak_mean/leak_var[K][G][6] weight leaked through each face per source
  *                              particle, and its batch variance.
+ *  tc_mean[ntally], tc_var[ntally]
+ *                              time-crossing flux at the time edges (problems
+ *                              with time_crossing = 1; else left untouched):
+ *                              mean = sum_b C_b / (N V), variance of the
+ *                              batch means C_b / (N_b V).
  *  qoi_sum[2]                  detector sum x and sum x^2 over histories
  *                              (x = the history's track in the detector).
  *  qoi_mean, qoi_var           detector flux per source particle and the
@@ -231,6 +245,8 @@ typedef struct {
     uint64_t n_term[5];
     uint64_t n_splits;
     double kernel_ms;
+    double *tc_mean;
+    double *tc_var;
 } mcdc_result;
 
 /*

@@ -16,7 +16,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libmcdc_hip.so")
 
-MCDC_ABI_VERSION = 1
+MCDC_ABI_VERSION = 2
 MCDC_OK, MCDC_E_INVALID, MCDC_E_HIP, MCDC_E_NOMEM, MCDC_E_OVERFLOW, MCDC_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5
 MCDC_ALG_EVENT, MCDC_ALG_HISTORY = 0, 1
 MCDC_SRC_ISOTROPIC, MCDC_SRC_SURFACE = 0, 1
@@ -48,6 +48,7 @@ class mcdc_problem_desc(C.Structure):
         ("qoi_enabled", C.c_int32), ("qoi_lo", C.c_double * 3), ("qoi_hi", C.c_double * 3),
         ("qoi_group_mask", _IP),
         ("n_ww_planes", C.c_int32 * 3), ("ww_planes", _DP * 3),
+        ("time_crossing", C.c_int32),
     ]
 
 
@@ -72,6 +73,7 @@ class mcdc_result(C.Structure):
         ("qoi_sum", C.c_double * 2), ("qoi_mean", C.c_double), ("qoi_var", C.c_double),
         ("n_events", C.c_uint64 * 3), ("n_term", C.c_uint64 * 5), ("n_splits", C.c_uint64),
         ("kernel_ms", C.c_double),
+        ("tc_mean", C.c_void_p), ("tc_var", C.c_void_p),
     ]
 
 
@@ -174,6 +176,7 @@ def make_desc(prob: dict):
         m = arr(ww[a] if ww is not None else np.zeros(0))
         d.n_ww_planes[a] = m.size
         d.ww_planes[a] = _dp(m)
+    d.time_crossing = 1 if prob["tally"].get("time_crossing", False) else 0
     return d, keep
 
 
@@ -186,6 +189,7 @@ class Problem:
         _check(lib().mcdc_problem_create(C.byref(d), C.byref(h)))
         self.handle = h
         self.prob = prob
+        self.time_crossing = bool(prob["tally"].get("time_crossing", False))
         shape = (C.c_int64 * 5)()
         n = C.c_int64()
         _check(lib().mcdc_problem_tally_shape(h, shape, C.byref(n)))
@@ -233,7 +237,9 @@ def mcdc_run(p: Problem, n_histories: int, seed: int, algorithm: str = "event",
              profile_phase: int = 0):
     """Run n_histories through the GPU tracker.  Returns a dict of torch
     CUDA tensors (mean, var, raw [K, G, nz, ny, nx]; leak_mean, leak_var
-    [K, G, 6]; debug_counts [N, 5] and debug_scores [N, 2] if debug) plus
+    [K, G, 6]; tc_mean, tc_var [K, G, nz, ny, nx] for a problem with the
+    time-crossing tally; debug_counts [N, 5] and debug_scores [N, 2] if
+    debug) plus
     host scalars (events, terminations, splits, detector sums, kernel_ms).
     profile: optional float64 array [8, 4] that accumulates per kernel class
     (ms, launches, particles, algorithmic bytes)."""
@@ -242,8 +248,8 @@ def mcdc_run(p: Problem, n_histories: int, seed: int, algorithm: str = "event",
     dev = torch.device("cuda", torch.cuda.current_device())
     res = mcdc_result()
     out = {}
-    for name in ("mean", "var", "raw"):
-        if name in outputs:
+    for name in ("mean", "var", "raw") + (("tc_mean", "tc_var") if p.time_crossing else ()):
+        if name in outputs or (name.startswith("tc_") and name[3:] in outputs):
             t = torch.empty(p.tally_shape, dtype=torch.float64, device=dev)
             out[name] = t
             setattr(res, name, t.data_ptr())
@@ -409,8 +415,8 @@ def mcdc_run_batched(problems, n_hist, seeds, block_size: int = 0, outputs=("mea
     outs = []
     for j, p in enumerate(problems):
         o = {}
-        for name in ("mean", "var", "raw"):
-            if name in outputs:
+        for name in ("mean", "var", "raw") + (("tc_mean", "tc_var") if p.time_crossing else ()):
+            if name in outputs or (name.startswith("tc_") and name[3:] in outputs):
                 t = torch.empty(p.tally_shape, dtype=torch.float64, device=dev)
                 o[name] = t
                 setattr(res[j], name, t.data_ptr())

@@ -406,8 +406,9 @@ __device__ __forceinline__ void atomic_add_f64(double *a, double v) {
 // workgroups go to different XCDs, so with X a multiple of 8 each copy is
 // touched by one XCD's L2 only, and concurrent flights of the same batch
 // spread their atomics over X addresses per bin.
+// (The copy holds the track-length tally, then the time-crossing tally.)
 __device__ __forceinline__ double *tally_copy(const DevProblem &P, const RunArgs &R, int b) {
-    return R.S + ((int64_t)b * R.X + (int64_t)(blockIdx.x & (unsigned)(R.X - 1))) * P.ntally;
+    return R.S + ((int64_t)b * R.X + (int64_t)(blockIdx.x & (unsigned)(R.X - 1))) * P.tstride;
 }
 
 // Weight leaked through a face, into this workgroup's copy of the leakage

@@ -293,31 +293,43 @@ __device__ __forceinline__ bool ww_point(const DevProblem &P, const RunArgs &R, 
     return true;
 }
 
-// Track-length score of one flight: into the workgroup's LDS slice when the
-// particle's batch is one of the segment's two, else straight to HBM.
+// Scores of one census step: into the workgroup's LDS slice when the
+// particle's batch is one of the segment's two, else straight to HBM.  The
+// slice holds [2][gn] track-length bins and, with the time-crossing tally,
+// [2][gn] bins of the flux at the step's closing edge behind them.
 struct StepScore {
-    double *lt;     // LDS [2][gn]
+    double *lt;     // LDS [parts][2][gn]
     int gn;         // G * nts of the slice (0 = no LDS slice)
     int b0;         // first batch of the segment
     bool scored;
-    __device__ __forceinline__ void add(const DevProblem &P, const RunArgs &R, int b, int g, int k, int tb,
-                                        double v) {
+    __device__ __forceinline__ void put(const DevProblem &P, const RunArgs &R, int part, int b, int g, int k,
+                                        int tb, double v) {
         const int rel = b - b0;
         if (gn && rel >= 0 && rel < 2) {
-            atomicAdd(&lt[rel * gn + g * P.nts + tb], v);
+            atomicAdd(&lt[(2 * part + rel) * gn + g * P.nts + tb], v);
             scored = true;
         } else {
-            atomic_add_f64(tally_copy(P, R, b) + ((int64_t)k * P.G + g) * P.nts + tb, v);
+            atomic_add_f64(tally_copy(P, R, b) + part * P.ntally + ((int64_t)k * P.G + g) * P.nts + tb, v);
         }
+    }
+    // track length w d of a flight in time bin k
+    __device__ __forceinline__ void add(const DevProblem &P, const RunArgs &R, int b, int g, int k, int tb,
+                                        double v) {
+        put(P, R, 0, b, g, k, tb, v);
+    }
+    // time-crossing score w v_g of an arrival at the edge T_{k+1}
+    __device__ __forceinline__ void cross(const DevProblem &P, const RunArgs &R, int b, int g, int k, int tb,
+                                          double v) {
+        put(P, R, 1, b, g, k, tb, v);
     }
 };
 
-__device__ __forceinline__ void init_slice(StepScore &sc, double *lt, int gn, int b0) {
+__device__ __forceinline__ void init_slice(const DevProblem &P, StepScore &sc, double *lt, int gn, int b0) {
     sc.lt = lt;
     sc.gn = gn;
     sc.b0 = b0;
     sc.scored = false;
-    for (int j = threadIdx.x; j < 2 * gn; j += kBlock) lt[j] = 0.0;
+    for (int j = threadIdx.x; j < slice_mult(P) * gn; j += kBlock) lt[j] = 0.0;
 }
 
 // End of a scoring kernel: add the workgroup's slice into the tally (one
@@ -325,12 +337,23 @@ __device__ __forceinline__ void init_slice(StepScore &sc, double *lt, int gn, in
 __device__ __forceinline__ void flush_slice(const DevProblem &P, const RunArgs &R, const StepScore &sc, int step) {
     const int any = __syncthreads_or(sc.scored ? 1 : 0);
     if (!sc.gn || !any) return;
-    for (int j = threadIdx.x; j < 2 * sc.gn; j += kBlock) {
+    const int per_part = 2 * sc.gn;
+    for (int j = threadIdx.x; j < slice_mult(P) * sc.gn; j += kBlock) {
         const double v = sc.lt[j];
-        const int b = sc.b0 + j / sc.gn;
+        const int part = j / per_part, r = j % per_part;
+        const int b = sc.b0 + r / sc.gn;
         if (v != 0.0 && b < R.B)
-            atomic_add_f64(tally_copy(P, R, b) + (int64_t)step * sc.gn + (j % sc.gn), v);
+            atomic_add_f64(tally_copy(P, R, b) + part * P.ntally + (int64_t)step * sc.gn + (r % sc.gn), v);
     }
+}
+
+// Time-crossing score of a particle that has just reached the edge
+// T_{k+1} (before its time bin moves on).
+__device__ __forceinline__ void score_crossing(const DevProblem &P, const RunArgs &R, StepScore &sc,
+                                               const Particle &p, int cell, int b) {
+    if (!P.tc_on) return;
+    const int tb = P.cell_tal[cell];
+    if (tb >= 0) sc.cross(P, R, b, p.g, p.k, tb, p.w * P.speed[p.g]);
 }
 
 // Score one flight (tally bin and detector) before the move.
@@ -428,9 +451,10 @@ __global__ void __launch_bounds__(kBlock) k_advance(DevProblem P0, RunArgs R0, B
         cC = 0u;
     }
     StepScore sc;
-    init_slice(sc, lt, gn, C.seg_b0[seg]);
-    const DevProblem P =
-        stage_tables<LT, kBlock>(BAT ? items[prob].P : P0, BAT ? items[prob].tabs : tabs0, reinterpret_cast<char *>(lt + 2 * gn));
+    const DevProblem &Pin = BAT ? items[prob].P : P0;
+    init_slice(Pin, sc, lt, gn, C.seg_b0[seg]);
+    const DevProblem P = stage_tables<LT, kBlock>(Pin, BAT ? items[prob].tabs : tabs0,
+                                                  reinterpret_cast<char *>(lt + slice_mult(Pin) * gn));
     __syncthreads();
     // software pipeline: the next particle's state is in flight while the
     // current one is moved
@@ -465,6 +489,7 @@ __global__ void __launch_bounds__(kBlock) k_advance(DevProblem P0, RunArgs R0, B
                     if (f.ev == kCensus) {
                         cnt.add(0);
                         hist_event(R, i, 0);
+                        score_crossing(P, R, sc, p, cell, b);
                         p.k += 1;
                         if (p.k == P.K) {
                             cnt.add(3 + kTime);
@@ -541,9 +566,10 @@ __global__ void __launch_bounds__(kBlock) k_event(DevProblem P0, RunArgs R0, Ban
         cW = 0u;
     }
     StepScore sc;
-    init_slice(sc, lt, gn, C.seg_b0[seg]);
-    const DevProblem P =
-        stage_tables<LT, kBlock>(BAT ? items[prob].P : P0, BAT ? items[prob].tabs : tabs0, reinterpret_cast<char *>(lt + 2 * gn));
+    const DevProblem &Pin = BAT ? items[prob].P : P0;
+    init_slice(Pin, sc, lt, gn, C.seg_b0[seg]);
+    const DevProblem P = stage_tables<LT, kBlock>(Pin, BAT ? items[prob].tabs : tabs0,
+                                                  reinterpret_cast<char *>(lt + slice_mult(Pin) * gn));
     __syncthreads();
 
     Particle p;
@@ -609,6 +635,7 @@ __global__ void __launch_bounds__(kBlock) k_event(DevProblem P0, RunArgs R0, Ban
             queued = kCensus;   // from here on: flights
             if (flown) {
                 if (evt == kCensus) {
+                    score_crossing(P, R, sc, p, cell, b);
                     p.k += 1;
                     if (p.k == P.K) {
                         cnt.add(3 + kTime);
@@ -785,8 +812,8 @@ int run_event(mcdc_problem *pb, const RunArgs &R0, uint64_t first, uint64_t coun
     // per-step tally slice [2 batches][G][nts] in LDS when it fits, then
     // the staged tables
     const int64_t gn64 = (int64_t)P.G * P.nts;
-    const int gn = (2 * gn64 <= kLdsTallyMax) ? (int)gn64 : 0;
-    const size_t shmem = (size_t)2 * gn * sizeof(double) + (LT ? (size_t)tabs.bytes : 0);
+    const int gn = (slice_mult(P) * gn64 <= kLdsTallyMax) ? (int)gn64 : 0;
+    const size_t shmem = (size_t)slice_mult(P) * gn * sizeof(double) + (LT ? (size_t)tabs.bytes : 0);
 
     // segments: one per workgroup
     unsigned int G;
@@ -997,13 +1024,14 @@ int launch_event_batched(std::vector<BatchItem> &items, const uint64_t *n_hist, 
         fit[j] = table_layout(P, items[j].tabs, kLdsTablesMax);
         lt_all = lt_all && fit[j];
         const int64_t gn64 = (int64_t)P.G * P.nts;
-        items[j].gn = (2 * gn64 <= kLdsTallyMax) ? (int)gn64 : 0;
+        items[j].gn = (slice_mult(P) * gn64 <= kLdsTallyMax) ? (int)gn64 : 0;
         fm = (fm < 0 || fm == P.finite_mask) ? P.finite_mask : 0;
         if (P.K > Kmax) Kmax = P.K;
     }
     size_t shmem = 0;
     for (int j = 0; j < n; ++j) {
-        const size_t b = (size_t)2 * items[j].gn * sizeof(double) + (lt_all ? (size_t)items[j].tabs.bytes : 0);
+        const size_t b = (size_t)slice_mult(items[j].P) * items[j].gn * sizeof(double) +
+                         (lt_all ? (size_t)items[j].tabs.bytes : 0);
         if (b > shmem) shmem = b;
     }
     std::vector<SegInfo> segs;

@@ -19,17 +19,19 @@ __global__ void __launch_bounds__(256) k_sum_copies(double *S, int64_t n, int B,
 }
 
 // Raw sum of batch b in bin j over the first X of its copies (fixed
-// order); batches lie bstride elements apart, copies n apart.
+// order); batches lie bstride elements apart, copies n apart (n = doubles
+// per copy).
 __device__ __forceinline__ double batch_sum(const double *S, int64_t bstride, int64_t n, int X, int b, int64_t j) {
     double v = 0.0;
     for (int x = 0; x < X; ++x) v += S[(int64_t)b * bstride + (int64_t)x * n + j];
     return v;
 }
 
-// One thread per tally bin j: S is [B][X][ntally] raw sums (X copies per
-// batch), norm_j = dt_k * V_s.
-__global__ void __launch_bounds__(256) k_fold(const double *__restrict__ S, int64_t ntally, int64_t bstride,
-                                              int B, int X, uint64_t N, int G, int nts,
+// One thread per tally bin j: S points at bin 0 of batch 0, copy 0 of
+// [B][X][cstride] raw sums (X copies per batch); norm_j = dt_k * V_s, or
+// V_s alone without time_norm (the flux at an instant).
+__global__ void __launch_bounds__(256) k_fold(const double *__restrict__ S, int64_t ntally, int64_t cstride,
+                                              int64_t bstride, int B, int X, uint64_t N, int G, int nts,
                                               const double *__restrict__ bin_norm,
                                               const double *__restrict__ time_norm,
                                               double *mean, double *var, double *raw) {
@@ -37,22 +39,22 @@ __global__ void __launch_bounds__(256) k_fold(const double *__restrict__ S, int6
     if (j >= ntally) return;
     const int64_t k = j / ((int64_t)G * nts);
     const int s = (int)(j % nts);
-    const double norm = time_norm[k] * bin_norm[s];
+    const double norm = (time_norm ? time_norm[k] : 1.0) * bin_norm[s];
     double total = 0.0;
-    for (int b = 0; b < B; ++b) total += batch_sum(S, bstride, ntally, X, b, j);
+    for (int b = 0; b < B; ++b) total += batch_sum(S, bstride, cstride, X, b, j);
     if (raw) raw[j] = total;
     if (mean) mean[j] = total / ((double)N * norm);
     if (var) {
         double mb_sum = 0.0;
         for (int b = 0; b < B; ++b) {
             const uint64_t nb = ((uint64_t)(b + 1) * N) / B - ((uint64_t)b * N) / B;
-            mb_sum += batch_sum(S, bstride, ntally, X, b, j) / ((double)nb * norm);
+            mb_sum += batch_sum(S, bstride, cstride, X, b, j) / ((double)nb * norm);
         }
         const double mbar = mb_sum / B;
         double acc = 0.0;
         for (int b = 0; b < B; ++b) {
             const uint64_t nb = ((uint64_t)(b + 1) * N) / B - ((uint64_t)b * N) / B;
-            const double d = batch_sum(S, bstride, ntally, X, b, j) / ((double)nb * norm) - mbar;
+            const double d = batch_sum(S, bstride, cstride, X, b, j) / ((double)nb * norm) - mbar;
             acc += d * d;
         }
         var[j] = (B > 1) ? acc / ((double)B * (double)(B - 1)) : 0.0;
@@ -118,12 +120,13 @@ __global__ void __launch_bounds__(256) k_qoi_reduce(const double *__restrict__ q
 int launch_fold(const DevProblem &P, double *S, double *L, int B, int X, int XL, uint64_t N,
                 const double *bin_norm_dev, const double *time_norm_dev, double *mean,
                 double *var, double *raw, double *leak_mean, double *leak_var,
-                hipStream_t st) {
+                double *tc_mean, double *tc_var, hipStream_t st) {
     const int bs = 256;
-    const int64_t s_stride = (int64_t)X * P.ntally, l_stride = (int64_t)XL * P.K * P.G * 6;
-    if ((mean || var || raw) && X > 1) {
-        hipLaunchKernelGGL(k_sum_copies, dim3((unsigned)(((int64_t)B * P.ntally + bs - 1) / bs)), dim3(bs), 0, st,
-                           S, P.ntally, B, X);
+    const int64_t s_stride = (int64_t)X * P.tstride, l_stride = (int64_t)XL * P.K * P.G * 6;
+    if (!P.tc_on) tc_mean = tc_var = nullptr;
+    if ((mean || var || raw || tc_mean || tc_var) && X > 1) {
+        hipLaunchKernelGGL(k_sum_copies, dim3((unsigned)(((int64_t)B * P.tstride + bs - 1) / bs)), dim3(bs), 0,
+                           st, S, P.tstride, B, X);
         X = 1;
     }
     if ((leak_mean || leak_var) && XL > 1) {
@@ -134,8 +137,15 @@ int launch_fold(const DevProblem &P, double *S, double *L, int B, int X, int XL,
     }
     if (mean || var || raw) {
         const unsigned grid = (unsigned)((P.ntally + bs - 1) / bs);
-        hipLaunchKernelGGL(k_fold, dim3(grid), dim3(bs), 0, st, S, P.ntally, s_stride, B, X, N, P.G, P.nts,
-                           bin_norm_dev, time_norm_dev, mean, var, raw);
+        hipLaunchKernelGGL(k_fold, dim3(grid), dim3(bs), 0, st, S, P.ntally, P.tstride, s_stride, B, X, N, P.G,
+                           P.nts, bin_norm_dev, time_norm_dev, mean, var, raw);
+    }
+    if (tc_mean || tc_var) {
+        // the time-crossing part of each copy: flux at an instant, no dt
+        const unsigned grid = (unsigned)((P.ntally + bs - 1) / bs);
+        hipLaunchKernelGGL(k_fold, dim3(grid), dim3(bs), 0, st, (const double *)(S + P.ntally), P.ntally,
+                           P.tstride, s_stride, B, X, N, P.G, P.nts, bin_norm_dev, (const double *)nullptr,
+                           tc_mean, tc_var, (double *)nullptr);
     }
     if (leak_mean || leak_var) {
         const int n = P.K * P.G * 6;

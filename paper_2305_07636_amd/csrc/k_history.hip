@@ -47,6 +47,10 @@ __device__ __forceinline__ int hstep(const DevProblem &P, const RunArgs &R, Part
     int code = -1;
     if (f.ev == kCensus) {
         ++acc.n_ev[0];
+        // time-crossing flux at the edge T_{k+1} the particle has reached
+        if (P.tc_on && tb >= 0)
+            atomic_add_f64(tally_copy(P, R, b) + P.ntally + ((int64_t)p.k * P.G + p.g) * P.nts + tb,
+                           p.w * P.speed[p.g]);
         since = 0;
         p.k += 1;
         if (p.k == P.K)

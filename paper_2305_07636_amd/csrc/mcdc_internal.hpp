@@ -31,6 +31,9 @@ struct DevProblem {
     int ncells;            // nc[0] * nc[1] * nc[2]
     int nts;               // tally spatial bins nz * ny * nx
     int64_t ntally;        // K * G * nts
+    int tc_on;             // 1: time-crossing tally at the edges T_1..T_K as well
+    int64_t tstride;       // doubles per tally copy: the track-length tally, then
+                           // the time-crossing tally (entry k for edge T_{k+1})
     const double *U[3];    // union planes
     const int32_t *cell_mat;   // [ncells] material of each union cell
     const int32_t *cell_tal;   // [ncells] spatial tally bin, -1 outside the mesh
@@ -61,13 +64,17 @@ struct DevProblem {
     double ww_ratio;
 };
 
+// Doubles per bin of the event form's per-step LDS slice: two batches of
+// the track-length tally, and two of the time-crossing tally when it is on.
+__host__ __device__ inline int slice_mult(const DevProblem &P) { return P.tc_on ? 4 : 2; }
+
 // Per-launch arguments shared by the tracking kernels.
 struct RunArgs {
     uint64_t N;          // histories in the whole run (sets the batch partition)
     uint64_t seed;       // base LCG state (masked to 63 bits)
     int B;               // batches
     int X;               // tally copies per batch (power of two): workgroup w adds into copy w mod X
-    double *S;           // [B][X][ntally] raw track-length sums per batch and copy
+    double *S;           // [B][X][tstride] raw track-length (and time-crossing) sums per batch and copy
     int XL;              // leakage copies per batch (power of two), as X
     double *L;           // [B][XL][K][G][6] leaked weight per batch and copy
     double *qoi_hist;    // [chunk] per-history detector score (WW runs) or nullptr
@@ -175,7 +182,7 @@ struct mcdc_problem {
         size_t bytes = 0;
     };
     Buf S, L, qoi_hist, qoi_sums, counters, overflow, bank, queues, split, prof, counters_split, tally_part, work;
-    Buf mean, var, raw, leak_mean, leak_var;
+    Buf mean, var, raw, leak_mean, leak_var, tc_mean, tc_var;
     void *graph_cache = nullptr;   // captured census steps of the event form
 };
 
@@ -194,7 +201,7 @@ int launch_event(mcdc_problem *p, const RunArgs &R, uint64_t first, uint64_t cou
 int launch_fold(const DevProblem &P, double *S, double *L, int B, int X, int XL, uint64_t N,
                 const double *bin_norm_dev, const double *time_norm_dev, double *mean,
                 double *var, double *raw, double *leak_mean, double *leak_var,
-                hipStream_t st);
+                double *tc_mean, double *tc_var, hipStream_t st);
 int launch_zero(void *p, size_t bytes, hipStream_t st);
 void destroy_graph_cache(mcdc_problem *p);
 int launch_batched(const BatchItem *items, const uint64_t *offs, int n_items, uint64_t total,

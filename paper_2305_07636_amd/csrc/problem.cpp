@@ -199,6 +199,7 @@ int compile(const mcdc_problem_desc *d, HostProblem &h) {
     if (d->src_t_lo < h.T[0]) return invalid("source emits before the first time edge");
     if (d->n_batches < 1) return invalid("n_batches must be >= 1");
     h.B = d->n_batches;
+    if (d->time_crossing != 0 && d->time_crossing != 1) return invalid("time_crossing must be 0 or 1");
 
     // tally, window and detector planes; union grid per axis
     if (d->qoi_enabled) {
@@ -353,6 +354,8 @@ int upload(mcdc_problem *p) {
     D.ncells = h.nc[0] * h.nc[1] * h.nc[2];
     D.nts = h.nt[0] * h.nt[1] * h.nt[2];
     D.ntally = (int64_t)h.K * h.G * D.nts;
+    D.tc_on = h.desc.time_crossing ? 1 : 0;
+    D.tstride = D.ntally * (1 + D.tc_on);
     D.cell_mat = (const int32_t *)(base + o_mat);
     D.cell_tal = (const int32_t *)(base + o_tal);
     D.cell_ww = (const int32_t *)(base + o_ww);
@@ -429,7 +432,7 @@ extern "C" int mcdc_problem_destroy(mcdc_problem *p) {
     mcdc_problem::Buf *bufs[] = {&p->S, &p->L, &p->qoi_hist, &p->qoi_sums, &p->counters,
                                  &p->overflow, &p->bank, &p->queues, &p->split, &p->prof,
                                  &p->counters_split, &p->tally_part, &p->mean,
-                                 &p->var, &p->raw, &p->leak_mean, &p->leak_var, &p->work};
+                                 &p->var, &p->raw, &p->leak_mean, &p->leak_var, &p->tc_mean, &p->tc_var, &p->work};
     for (auto *b : bufs) free_buf(*b);
     delete p;
     return MCDC_OK;

@@ -107,9 +107,9 @@ int prepare(mcdc_problem *p, uint64_t N, uint64_t seed, const mcdc_run_options &
     // (the event form adds a step's scores from its LDS slice once per
     // workgroup when the slice fits, and needs no copies then)
     int X = 32;
-    while (X > 1 && (double)B * X * (double)P.ntally * sizeof(double) > 64.0 * 1024 * 1024) X >>= 1;
-    if (opt.algorithm != MCDC_ALG_HISTORY && 2 * (int64_t)P.G * P.nts <= kLdsTallyMax) X = 1;
-    const size_t nS = (size_t)B * X * P.ntally;
+    while (X > 1 && (double)B * X * (double)P.tstride * sizeof(double) > 64.0 * 1024 * 1024) X >>= 1;
+    if (opt.algorithm != MCDC_ALG_HISTORY && slice_mult(P) * (int64_t)P.G * P.nts <= kLdsTallyMax) X = 1;
+    const size_t nS = (size_t)B * X * P.tstride;
     // leakage copies: up to 256 within 16 MB
     int XL = 256;
     while (XL > 1 && (double)B * XL * P.K * P.G * 6 * sizeof(double) > 16.0 * 1024 * 1024) XL >>= 1;
@@ -153,9 +153,14 @@ int fold(mcdc_problem *p, const RunArgs &R, mcdc_result *out, hipStream_t st, Pr
     const DevProblem &P = p->d;
     double *mean = out->mean, *var = out->var, *raw = out->raw;
     double *lmean = out->leak_mean, *lvar = out->leak_var;
+    double *tmean = P.tc_on ? out->tc_mean : nullptr, *tvar = P.tc_on ? out->tc_var : nullptr;
     const size_t nleak = (size_t)P.K * P.G * 6;
     int rc;
     if (out->host_outputs) {
+        if (tmean && (rc = ensure(p->tc_mean, P.ntally * sizeof(double)))) return rc;
+        if (tvar && (rc = ensure(p->tc_var, P.ntally * sizeof(double)))) return rc;
+        tmean = tmean ? (double *)p->tc_mean.p : nullptr;
+        tvar = tvar ? (double *)p->tc_var.p : nullptr;
         if (mean && (rc = ensure(p->mean, P.ntally * sizeof(double)))) return rc;
         if (var && (rc = ensure(p->var, P.ntally * sizeof(double)))) return rc;
         if (raw && (rc = ensure(p->raw, P.ntally * sizeof(double)))) return rc;
@@ -168,7 +173,8 @@ int fold(mcdc_problem *p, const RunArgs &R, mcdc_result *out, hipStream_t st, Pr
         lvar = lvar ? (double *)p->leak_var.p : nullptr;
     }
     prof.begin(MCDC_PROF_OTHER);
-    rc = launch_fold(P, R.S, R.L, R.B, R.X, R.XL, R.N, P.bin_norm, P.time_norm, mean, var, raw, lmean, lvar, st);
+    rc = launch_fold(P, R.S, R.L, R.B, R.X, R.XL, R.N, P.bin_norm, P.time_norm, mean, var, raw, lmean, lvar, tmean,
+                     tvar, st);
     prof.end();
     return rc ? hip_fail((hipError_t)rc, "fold kernel launch") : MCDC_OK;
 }
@@ -195,6 +201,10 @@ int collect_begin(mcdc_problem *p, mcdc_result *out, Collect &c, hipStream_t st)
             HIP_CHECK(hipMemcpyAsync(out->leak_mean, p->leak_mean.p, nl, hipMemcpyDeviceToHost, st), "copy leak");
         if (out->leak_var)
             HIP_CHECK(hipMemcpyAsync(out->leak_var, p->leak_var.p, nl, hipMemcpyDeviceToHost, st), "copy leak var");
+        if (P.tc_on && out->tc_mean)
+            HIP_CHECK(hipMemcpyAsync(out->tc_mean, p->tc_mean.p, nt, hipMemcpyDeviceToHost, st), "copy tc mean");
+        if (P.tc_on && out->tc_var)
+            HIP_CHECK(hipMemcpyAsync(out->tc_var, p->tc_var.p, nt, hipMemcpyDeviceToHost, st), "copy tc var");
     }
     return MCDC_OK;
 }

@@ -69,6 +69,11 @@ def compare_full(prob, N, seed, algorithm, ww=None, **kw):
     close(g["var"], e["var"], rtol=VAR_RTOL, what="var")
     close(g["leak_mean"], e["leak_mean"], what="leak mean")
     close(g["leak_var"], e["leak_var"], rtol=VAR_RTOL, what="leak var")
+    if prob["tally"].get("time_crossing", False):
+        close(g["tc_mean"], e["tc_mean"], what="time-crossing mean")
+        close(g["tc_var"], e["tc_var"], rtol=VAR_RTOL, what="time-crossing var")
+    else:
+        assert "tc_mean" not in g
     if prob.get("qoi") is not None:
         close(g["qoi_sum"], r["q"], what="detector sums")
         close([g["qoi_mean"]], [e["qoi_mean"]], what="detector mean")
