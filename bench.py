@@ -193,6 +193,7 @@ def main():
     ap.add_argument("--no-history-form", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-fom", action="store_true")
+    ap.add_argument("--no-time-crossing", action="store_true")
     ap.add_argument("--fom-pilot", type=float, default=1e8)
     ap.add_argument("--fom-analog", type=float, default=4e9)
     ap.add_argument("--fom-ww", type=float, default=1e9)
@@ -295,6 +296,27 @@ def main():
         torch.cuda.synchronize()
         extra["history_form_histories_per_s"] = N * args.steps / (time.perf_counter() - t1)
         log("history form timed")
+    if not args.no_time_crossing:
+        # the same workload with the time-crossing tally (flux at the 100
+        # time edges) as well: its cost in both forms, against runs without
+        # it timed the same way (no per-launch events)
+        prob_tc = w.cfg2_slab_pulse()
+        prob_tc["tally"]["time_crossing"] = True
+        ptc = m.mcdc_problem_create(prob_tc)
+        tc = {}
+        for alg in ("event", "history"):
+            for tag, h in (("without", p), ("with", ptc)):
+                m.mcdc_run(h, N, seed, algorithm=alg, outputs=outs)
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                for s in range(args.steps):
+                    m.mcdc_run(h, N, seed + s, algorithm=alg, outputs=outs)
+                torch.cuda.synchronize()
+                tc[f"{alg}_{tag}_histories_per_s"] = N * args.steps / (time.perf_counter() - t1)
+            tc[f"{alg}_time_ratio"] = tc[f"{alg}_without_histories_per_s"] / tc[f"{alg}_with_histories_per_s"]
+        ptc.close()
+        extra["time_crossing_tally"] = tc
+        log("time-crossing tally timed")
     p.close()
     if not args.no_batched:
         extra["batched"] = batched_section(m, w)
