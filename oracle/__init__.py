@@ -60,6 +60,7 @@ class _Problem(C.Structure):
         ("n_ww", C.c_int32 * 3), ("ww", _DP * 3),
         ("ww_center", _DP), ("ww_ratio", C.c_double), ("ww_max_split", C.c_int32),
         ("time_crossing", C.c_int32),
+        ("sigma_f", _DP), ("nu", _DP), ("chi", _DP),
     ]
 
 
@@ -159,6 +160,11 @@ class OracleProblem:
             s.ww_ratio = float(ww_ratio)
             s.ww_max_split = int(ww_max_split)
         s.time_crossing = 1 if tal.get("time_crossing", False) else 0
+        fis = prob.get("fission")
+        if fis is not None:
+            s.sigma_f = _dp(arr(fis["sigma_f"]))
+            s.nu = _dp(arr(fis["nu"]))
+            s.chi = _dp(arr(fis["chi"]))
         self.time_crossing = bool(s.time_crossing)
         self.struct = s
         self._keep = keep
@@ -213,7 +219,7 @@ def run(prob, N: int, seed: int, ids=None, first: int = 0, count=None,
     'L' [B, K, G, 6],
     detector sums 'q' = (sum x, sum x^2), totals 'tot' (census, surface,
     collision events; absorb, leak, time, lost, roulette terminations;
-    splits), and if records: per-history 'rec' [n, 5] = (census, surface,
+    splits; fission neutrons beyond the colliding one), and if records: per-history 'rec' [n, 5] = (census, surface,
     collision, particles, termination mask) and 'trk' [n, 2] = (scored track,
     detector score)."""
     op = prob if isinstance(prob, OracleProblem) else OracleProblem(
@@ -232,7 +238,7 @@ def run(prob, N: int, seed: int, ids=None, first: int = 0, count=None,
     X = np.zeros((B, op.ntally))
     L = np.zeros((B, op.K, op.G, 6))
     q = np.zeros(2)
-    tot = np.zeros(9, dtype=np.uint64)
+    tot = np.zeros(10, dtype=np.uint64)
     rec = np.zeros((n, 5), dtype=np.uint32) if records else None
     trk = np.zeros((n, 2)) if records else None
     rc = lib().oracle_run(op.ptr(), N, seed, ids.ctypes.data if ids is not None else None,

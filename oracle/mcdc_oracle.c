@@ -11,7 +11,8 @@
  * What it computes.  The paper (Section 3) describes the method in words: MC
  * transport of neutrons through multigroup materials (group-wise total cross
  * section, isotropic scattering through a group-to-group transfer matrix, no
- * fission here), on box geometry, with a time-dependent source, time census,
+ * fission unless the problem gives fission data, R12), on box geometry, with a
+ * time-dependent source, time census,
  * time-dependent mesh tallies, and the track-length estimator of the
  * time-averaged flux (Section 3.1); analog mode means uniform weight and no
  * variance reduction (Section 3.3).  The paper prints no equations and no
@@ -50,6 +51,18 @@
  *       of its cell at that instant, before the weight-window check;
  *       normalised by N V (no time width).  A particle born exactly on an
  *       edge does not cross it.
+ *   R12 Fission (optional; Section 3 runs the supercritical AZURV1 with
+ *       fission added, prompt neutrons only): a collision draws one number
+ *       xi for the reaction: scatter if xi < Sigma_s/Sigma_t, fission if
+ *       xi < (Sigma_s + Sigma_f)/Sigma_t, else capture.  A fission draws
+ *       one more number and emits n = floor(nu + xi) neutrons at the
+ *       collision point and time (n = 0 ends the particle as absorbed).
+ *       Neutron 0 is the colliding particle itself; neutron j >= 1 takes
+ *       the stream SplitMix64(s ^ j) masked to 63 bits of the state s
+ *       after that draw.  Each neutron then draws from its own stream its
+ *       group from the material's spectrum chi, an isotropic direction and
+ *       an optical depth; the colliding particle then takes the window
+ *       check as after a scatter.
  *
  * Build: gcc -O2 -ffp-contract=off -fPIC -shared -o liboracle.so mcdc_oracle.c -lm
  */
@@ -95,6 +108,10 @@ typedef struct {
     int32_t ww_max_split;
     /* time-crossing estimator of the flux at the time edges (R11) */
     int32_t time_crossing;
+    /* fission (R12): all three NULL for a non-multiplying problem */
+    const double *sigma_f;   /* [M][G] */
+    const double *nu;        /* [M][G] mean neutrons per fission */
+    const double *chi;       /* [M][G] fission spectrum (sums to 1 per material) */
 } oracle_problem;
 
 enum { EV_CENSUS = 0, EV_SURFACE = 1, EV_COLLISION = 2 };
@@ -297,8 +314,11 @@ typedef struct {
     double *X, *Xc;     /* [B][ntally] time-crossing sums (edge T_{k+1} at k) */
     double *L, *Lc;     /* [B][K][G][6] leak sums */
     double q[2], qc[2]; /* detector: sum x, sum x^2 over histories */
-    uint64_t tot[9];    /* events: census, surface, collision; terminations
-                           absorb, leak, time, lost, roulette; splits */
+    uint64_t tot[10];   /* events: census, surface, collision; terminations
+                           absorb, leak, time, lost, roulette; splits;
+                           fission neutrons beyond the colliding one */
+    double *pf;         /* [M][G] (Sigma_s,g + Sigma_f,g) / Sigma_t,g (fission only) */
+    double *chi_cdf;    /* [M][G] fission-spectrum CDF (fission only) */
 } ctx;
 
 static void isotropic(uint64_t *s, double u[3])
@@ -412,6 +432,46 @@ static void terminate(ctx *C, hist_rec *h, int code)
 {
     h->term_mask |= 1u << code;
     C->tot[3 + code]++;
+}
+
+/* R12: a fission neutron takes its group from the spectrum, an isotropic
+ * direction and an optical depth, all from its own stream. */
+static void emit(const ctx *C, particle *pt, int m)
+{
+    const int G = C->p->G;
+    double xg = rn(&pt->s);
+    int g = 0;
+    while (!(xg < C->chi_cdf[m * G + g])) g++;
+    pt->g = g;
+    isotropic(&pt->s, pt->u);
+    set_inv(pt);
+    pt->tau = -log(1.0 - rn(&pt->s));
+}
+
+/* R12: fission at a collision in material m.  Returns 1 if the colliding
+ * particle goes on as neutron 0, 0 if no neutron is emitted, -1 if the
+ * progeny overflow the stack. */
+static int fission(ctx *C, particle *pt, int m, particle *stack, int *sp, hist_rec *h)
+{
+    const int G = C->p->G;
+    double nu = C->p->nu[m * G + pt->g];
+    int n = (int)floor(nu + rn(&pt->s));
+    if (n == 0) {
+        terminate(C, h, T_ABSORB);
+        return 0;
+    }
+    uint64_t sf = pt->s;
+    for (int j = 1; j < n; j++) {
+        if (*sp >= STACK_MAX) return -1;
+        particle c = *pt;
+        c.s = splitmix64(sf ^ (uint64_t)j) & MASK63;
+        emit(C, &c, m);
+        stack[(*sp)++] = c;
+        h->n_particles++;
+        C->tot[9]++;
+    }
+    emit(C, pt, m);
+    return 1;
 }
 
 /* One flight plus the event that ends it.  Returns 1 if the particle lives
@@ -549,10 +609,17 @@ static int step(ctx *C, particle *pt, int b, particle *stack, int *sp, hist_rec 
     } else {
         h->n_coll++;
         C->tot[2]++;
-        /* analog collision: scatter with probability Sigma_s,g / Sigma_t,g */
-        if (!(rn(&pt->s) < C->ps[m * G + pt->g])) {
-            terminate(C, h, T_ABSORB);
-            alive = 0;
+        /* analog collision: scatter with probability Sigma_s,g / Sigma_t,g,
+         * fission with probability Sigma_f,g / Sigma_t,g (R12) */
+        double xr = rn(&pt->s);
+        if (!(xr < C->ps[m * G + pt->g])) {
+            if (C->pf && xr < C->pf[m * G + pt->g]) {
+                alive = fission(C, pt, m, stack, sp, h);
+                if (alive > 0) alive = ww_game(C, pt, stack, sp, h);
+            } else {
+                terminate(C, h, T_ABSORB);
+                alive = 0;
+            }
         } else {
             double xg = rn(&pt->s);
             const double *cdf = &C->cdf[((int64_t)m * G + pt->g) * G];
@@ -673,6 +740,28 @@ static int ctx_init(ctx *C, const oracle_problem *p)
             }
             for (int g2 = (last < 0 ? 0 : last); g2 < G; g2++) C->cdf[((int64_t)m * G + g) * G + g2] = 1.0;
         }
+    if (p->sigma_f) {
+        if (!p->nu || !p->chi) return -1;
+        C->pf = (double *)calloc((size_t)M * G, sizeof(double));
+        C->chi_cdf = (double *)calloc((size_t)M * G, sizeof(double));
+        for (int m = 0; m < M; m++) {
+            for (int g = 0; g < G; g++) {
+                const double *row = &p->sigma_s[((int64_t)m * G + g) * G];
+                double ss = 0.0;
+                for (int g2 = 0; g2 < G; g2++) ss += row[g2];
+                double st = p->sigma_t[m * G + g];
+                C->pf[m * G + g] = (st > 0.0) ? (ss + p->sigma_f[m * G + g]) / st : 0.0;
+            }
+            double run = 0.0;
+            int last = -1;
+            for (int g = 0; g < G; g++) {
+                run += p->chi[m * G + g];
+                C->chi_cdf[m * G + g] = run;
+                if (p->chi[m * G + g] > 0.0) last = g;
+            }
+            for (int g = (last < 0 ? 0 : last); g < G; g++) C->chi_cdf[m * G + g] = 1.0;
+        }
+    }
     {
         double run = 0.0;
         int last = -1;
@@ -692,6 +781,8 @@ static void ctx_free(ctx *C)
     for (int a = 0; a < 3; a++) free_axis(&C->ax[a]);
     free(C->ps);
     free(C->cdf);
+    free(C->pf);
+    free(C->chi_cdf);
     free(C->src_cdf);
     free(C->S);
     free(C->Sc);
@@ -728,7 +819,7 @@ int oracle_union_planes(const oracle_problem *p, int axis, double *out, int cap)
  * the contiguous range first..first+n_ids-1).  Accumulates raw per-batch
  * tally sums S[B][ntally] and leak sums L[B][K][G][6] (both may be NULL),
  * detector sums q[2] = (sum x, sum x^2), event and termination totals
- * tot[9], per-history records rec[n_ids][5] = (census, surface,
+ * tot[10], per-history records rec[n_ids][5] = (census, surface,
  * collision, particles, termination mask), per-history track and
  * detector scores trk[n_ids][2], and time-crossing sums X[B][ntally] (R11;
  * zeros unless the problem asks for them).  Returns 0, or -1 on an invalid problem,
@@ -805,7 +896,7 @@ int oracle_run(const oracle_problem *p, uint64_t N, uint64_t seed,
         q_out[1] += C.q[1] + C.qc[1];
     }
     if (tot_out)
-        for (int j = 0; j < 9; j++) tot_out[j] += C.tot[j];
+        for (int j = 0; j < 10; j++) tot_out[j] += C.tot[j];
     free(stack);
     ctx_free(&C);
     return rc;
@@ -814,12 +905,12 @@ int oracle_run(const oracle_problem *p, uint64_t N, uint64_t seed,
 /* Event-by-event trace of history i (brute-force comparison on tiny inputs):
  * one row of 9 doubles per event, (type, d, x, y, z, t, g, k, tau) after the
  * event, then a final row (type = 10 + termination code).  Analog problems
- * only.  Returns the row count, or -1 if the buffer is too small or the
+ * without fission only.  Returns the row count, or -1 if the buffer is too small or the
  * problem is invalid. */
 int oracle_trace(const oracle_problem *p, uint64_t N, uint64_t seed, uint64_t i, double *rows, int cap)
 {
     ctx C;
-    if (ctx_init(&C, p) != 0 || cap < 1) {
+    if (ctx_init(&C, p) != 0 || cap < 1 || p->sigma_f) {
         ctx_free(&C);
         return -1;
     }

@@ -83,28 +83,33 @@ def slab_absorber_transmission(L, sigma_t, law):
             "cosine": float(2.0 * En(3, tau))}[law]
 
 
-def removal_matrix(sigma_t, sigma_s):
+def removal_matrix(sigma_t, sigma_s, fission=None):
     """M[g, g'] = Sigma_t,g delta_gg' - Sigma_s(g' -> g) for one material;
-    sigma_s is indexed [from, to]."""
-    return np.diag(sigma_t) - np.asarray(sigma_s).T
+    sigma_s is indexed [from, to].  With fission = (sigma_f, nu, chi) the
+    prompt production chi_g nu_g' Sigma_f,g' is subtracted as well."""
+    M = np.diag(sigma_t) - np.asarray(sigma_s).T
+    if fission is not None:
+        sf, nu, chi = (np.asarray(a, dtype=float).ravel() for a in fission)
+        M = M - np.outer(chi, nu * sf)
+    return M
 
 
-def infinite_medium_steady(sigma_t, sigma_s, volume):
+def infinite_medium_steady(sigma_t, sigma_s, volume, fission=None):
     """Scalar flux per group in an infinite medium with a uniform source of
     one particle in group 0 spread over the given volume: phi = M^-1 S."""
     G = len(sigma_t)
     S = np.zeros(G)
     S[0] = 1.0 / volume
-    return np.linalg.solve(removal_matrix(sigma_t, sigma_s), S)
+    return np.linalg.solve(removal_matrix(sigma_t, sigma_s, fission), S)
 
 
-def infinite_medium_pulse_bins(sigma_t, sigma_s, speed, edges, volume):
+def infinite_medium_pulse_bins(sigma_t, sigma_s, speed, edges, volume, fission=None):
     """Time-bin averages of phi(t) = V exp(-M V t) n0 with n0 = one particle
     in group 0 per volume:  V (M V)^-1 (e^{-MV ta} - e^{-MV tb}) n0 / dt.
     Returns [K, G]."""
     G = len(sigma_t)
     V = np.diag(speed)
-    A = removal_matrix(sigma_t, sigma_s) @ V
+    A = removal_matrix(sigma_t, sigma_s, fission) @ V
     n0 = np.zeros(G)
     n0[0] = 1.0 / volume
     out = []
@@ -115,12 +120,12 @@ def infinite_medium_pulse_bins(sigma_t, sigma_s, speed, edges, volume):
     return np.array(out)
 
 
-def infinite_medium_pulse_points(sigma_t, sigma_s, speed, times, volume):
+def infinite_medium_pulse_points(sigma_t, sigma_s, speed, times, volume, fission=None):
     """Point values phi(t) = V exp(-M V t) n0 at the given times (n0 = one
     particle in group 0 per volume).  Returns [len(times), G]."""
     G = len(sigma_t)
     V = np.diag(speed)
-    A = removal_matrix(sigma_t, sigma_s) @ V
+    A = removal_matrix(sigma_t, sigma_s, fission) @ V
     n0 = np.zeros(G)
     n0[0] = 1.0 / volume
     return np.array([V @ (linalg.expm(-A * t) @ n0) for t in times])
@@ -132,6 +137,23 @@ def plane_pulse_uncollided_point(x0, sigma_t, v, xa, xb, t):
     lo = max(xa, x0 - v * t)
     hi = min(xb, x0 + v * t)
     return math.exp(-sigma_t * v * t) * max(0.0, hi - lo) / (2.0 * t * (xb - xa))
+
+
+def plane_pulse_moments(c, t):
+    """Population m00 and second spatial moment m20 = int x^2 n dx of an
+    isotropic plane pulse at x = 0 in an infinite one-group medium with
+    isotropic re-emission c per collision (Sigma_t = v = 1).  Moments
+    m_kl = int int x^k mu^l psi dx dmu of the transport equation obey
+    m_kl' = k m_{k-1,l+1} - m_kl + c a_l m_k0 with a_l = 1/(l+1) for even
+    l, 0 for odd l; the set (m00, m02, m11, m20) is closed:
+      m00' = (c-1) m00, m02' = (c/3) m00 - m02, m11' = m02 - m11,
+      m20' = 2 m11 + (c-1) m20, starting from (1, 1/3, 0, 0)."""
+    A = np.array([[c - 1.0, 0.0, 0.0, 0.0],
+                  [c / 3.0, -1.0, 0.0, 0.0],
+                  [0.0, 1.0, -1.0, 0.0],
+                  [0.0, 0.0, 2.0, c - 1.0]])
+    m = linalg.expm(A * t) @ np.array([1.0, 1.0 / 3.0, 0.0, 0.0])
+    return m[0], m[3]
 
 
 def pulse_population(c, t):

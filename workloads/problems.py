@@ -33,6 +33,8 @@ Problem dict schema (all floats are float64, all ints int32):
               time_crossing (bool: also tally the flux at the time edges
               T_1..T_K with the time-crossing estimator)
     qoi       None or dict: lo[3], hi[3], group_mask[G]
+    fission   None or dict: sigma_f[M, G], nu[M, G] (mean neutrons per
+              fission), chi[M, G] (fission spectrum per material)
     ww_mesh   None or list of 3 arrays of weight-window mesh planes
 
 The workload recipes follow the transport problems the method is exercised
@@ -83,7 +85,7 @@ def _empty():
 
 
 def make_problem(sigma_t, sigma_s, speed, planes, material, bc, source, tally,
-                 qoi=None, ww_mesh=None):
+                 qoi=None, ww_mesh=None, fission=None):
     sigma_t = _f64(sigma_t)
     M, G = sigma_t.shape
     src = dict(source)
@@ -109,7 +111,10 @@ def make_problem(sigma_t, sigma_s, speed, planes, material, bc, source, tally,
         "tally": tal,
         "qoi": None,
         "ww_mesh": None,
+        "fission": None,
     }
+    if fission is not None:
+        p["fission"] = {k: _f64(fission[k]).reshape(M, G) for k in ("sigma_f", "nu", "chi")}
     if qoi is not None:
         p["qoi"] = {"lo": _f64(qoi["lo"]), "hi": _f64(qoi["hi"]),
                     "group_mask": np.asarray(qoi["group_mask"], dtype=np.int32)}
@@ -292,7 +297,7 @@ def cfg5_dogleg(n_batches=32, detector=((29.0, 7.0, 4.0), (30.0, 9.0, 6.0))):
 # ---------------------------------------------------------------------------
 
 def reflective_box(sigma_t, sigma_s, speed, size=(2.0, 2.0, 2.0),
-                   time_edges=None, n_batches=32, pulse=True):
+                   time_edges=None, n_batches=32, pulse=True, fission=None):
     """Homogeneous all-reflective box (an infinite medium), uniform volume
     source in group 0, one tally bin per axis."""
     st = _f64(sigma_t).reshape(1, -1)
@@ -307,7 +312,25 @@ def reflective_box(sigma_t, sigma_s, speed, size=(2.0, 2.0, 2.0),
     tally = {"mesh": [np.array([0.0, s]) for s in size],
              "time_edges": time_edges, "n_batches": n_batches}
     return make_problem(st, _f64(sigma_s).reshape(1, G, G), speed, planes,
-                        np.zeros((1, 1, 1)), [REFLECTIVE] * 6, src, tally)
+                        np.zeros((1, 1, 1)), [REFLECTIVE] * 6, src, tally, fission=fission)
+
+
+def azurv1_supercritical(c_scatter=0.5, sigma_f=0.25, nu=2.4, n_bins=42, n_time_bins=20,
+                         t_end=20.0, n_batches=32):
+    """AZURV1-like supercritical pulse (Section 3 adds fission to reach
+    c = 1.1): one group, Sigma_t = v = 1 (time in mean free times), an
+    isotropic plane pulse at the centre of a 42-mfp slab whose faces no
+    particle reaches before t = 20, scattering c_scatter, fission
+    sigma_f with nu neutrons (c = c_scatter + nu sigma_f), the rest
+    capture.  Flux tallies in n_bins x-bins and n_time_bins time bins with
+    the time-crossing tally at the edges."""
+    half = 21.0
+    p = slab(thickness=2 * half, sigma_t=1.0, sigma_s=c_scatter, n_bins=n_bins, source="plane",
+             x_src=half, time_edges=np.linspace(0.0, t_end, n_time_bins + 1), n_batches=n_batches)
+    p["tally"]["time_crossing"] = True
+    p["fission"] = {"sigma_f": np.array([[sigma_f]]), "nu": np.array([[nu]]),
+                    "chi": np.array([[1.0]])}
+    return p
 
 
 def void_box(size=(3.0, 2.0, 1.0), n_mesh=(3, 2, 1), src_point=(0.5, 0.5, 0.5),
