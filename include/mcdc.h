@@ -106,6 +106,19 @@ typedef struct mcdc_problem mcdc_problem;
  * (score w v_g in the bin of its position at that instant), per source
  * particle and unit bin volume.  Shape [K][G][nz][ny][nx], entry k for
  * edge T_{k+1} (an infinite last edge stays 0).  0 = off.
+ *
+ * Prompt fission (optional; Section 3's supercritical AZURV1 adds it to
+ * the pulse problem): sigma_f[M][G] >= 0 with sum_g' sigma_s + sigma_f <=
+ * sigma_t, nu[M][G] in [0, 64] mean neutrons per fission, chi[M][G] >= 0
+ * the fission spectrum of each material (sums to 1 within 1e-12).  All
+ * three NULL: no fission.  A collision draws one number for the reaction
+ * (scatter, fission, capture in that order of the cumulative
+ * probabilities); a fission emits floor(nu + xi) neutrons at the collision
+ * point and time, neutron 0 continuing the colliding particle, neutrons
+ * j >= 1 on the SplitMix64 child streams of its state; each then draws its
+ * group from chi, an isotropic direction and an optical depth.  The extra
+ * neutrons are tracked like weight-window progeny (split bank, generation
+ * by generation after each chunk of histories).
  */
 typedef struct {
     int32_t abi_version; /* MCDC_ABI_VERSION */
@@ -139,6 +152,9 @@ typedef struct {
     int32_t n_ww_planes[3];
     const double *ww_planes[3];
     int32_t time_crossing;
+    const double *sigma_f;
+    const double *nu;
+    const double *chi;
 } mcdc_problem_desc;
 
 /*
@@ -228,6 +244,8 @@ typedef struct {
  *  n_term                      terminations: absorbed, leaked, time cut-off,
  *                              lost (infinite flight), rouletted.
  *  n_splits                    weight-window split progeny created.
+ *  n_fission                   fission neutrons beyond the colliding one
+ *                              (problems with fission data).
  *  kernel_ms                   device time of the run (HIP events).
  */
 typedef struct {
@@ -247,6 +265,7 @@ typedef struct {
     double kernel_ms;
     double *tc_mean;
     double *tc_var;
+    uint64_t n_fission;
 } mcdc_result;
 
 /*

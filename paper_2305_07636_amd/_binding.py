@@ -49,6 +49,7 @@ class mcdc_problem_desc(C.Structure):
         ("qoi_group_mask", _IP),
         ("n_ww_planes", C.c_int32 * 3), ("ww_planes", _DP * 3),
         ("time_crossing", C.c_int32),
+        ("sigma_f", _DP), ("nu", _DP), ("chi", _DP),
     ]
 
 
@@ -74,6 +75,7 @@ class mcdc_result(C.Structure):
         ("n_events", C.c_uint64 * 3), ("n_term", C.c_uint64 * 5), ("n_splits", C.c_uint64),
         ("kernel_ms", C.c_double),
         ("tc_mean", C.c_void_p), ("tc_var", C.c_void_p),
+        ("n_fission", C.c_uint64),
     ]
 
 
@@ -177,6 +179,11 @@ def make_desc(prob: dict):
         d.n_ww_planes[a] = m.size
         d.ww_planes[a] = _dp(m)
     d.time_crossing = 1 if prob["tally"].get("time_crossing", False) else 0
+    fis = prob.get("fission")
+    if fis is not None:
+        d.sigma_f = _dp(arr(fis["sigma_f"]))
+        d.nu = _dp(arr(fis["nu"]))
+        d.chi = _dp(arr(fis["chi"]))
     return d, keep
 
 
@@ -284,6 +291,7 @@ def mcdc_run(p: Problem, n_histories: int, seed: int, algorithm: str = "event",
     out["events"] = np.array(res.n_events[:], dtype=np.uint64)
     out["terms"] = np.array(res.n_term[:], dtype=np.uint64)
     out["splits"] = int(res.n_splits)
+    out["fission"] = int(res.n_fission)
     out["qoi_sum"] = (res.qoi_sum[0], res.qoi_sum[1])
     out["qoi_mean"] = res.qoi_mean
     out["qoi_var"] = res.qoi_var

@@ -280,13 +280,17 @@ __device__ __forceinline__ int cross(const DevProblem &P, Particle &p, int mask)
     return -1;
 }
 
-// Analog collision in material m: returns false if absorbed; otherwise the
-// particle takes its outgoing group, a new isotropic direction and a new
-// optical depth.
-template <int FM>
-__device__ __forceinline__ bool collide(const DevProblem &P, Particle &p, int m) {
+// Analog collision in material m.  One draw picks the reaction: scatter
+// below sigma_s / sigma_t, fission below (sigma_s + sigma_f) / sigma_t
+// (FIS kernels only), else capture.  Returns 0 on capture; 1 on a scatter,
+// after which the particle has its outgoing group, a new isotropic
+// direction and a new optical depth; 2 on a fission, whose neutrons
+// fission() then emits.
+template <int FM, bool FIS = false>
+__device__ __forceinline__ int collide(const DevProblem &P, Particle &p, int m) {
     const int mg = m * P.G + p.g;
-    if (!(rn(p.s) < P.ps[mg])) return false;
+    const double xr = rn(p.s);
+    if (!(xr < P.ps[mg])) return (FIS && P.fission_on && xr < P.pf[mg]) ? 2 : 0;
     double xg = rn(p.s);
     const double *cdf = P.cdf + (int64_t)mg * P.G;
     int g2 = 0;
@@ -295,7 +299,7 @@ __device__ __forceinline__ bool collide(const DevProblem &P, Particle &p, int m)
     isotropic(p.s, p.u[0], p.u[1], p.u[2]);
     set_inverse<FM>(P, p);
     p.tau = -log(1.0 - rn(p.s));
-    return true;
+    return 1;
 }
 
 // Weight-window centre of a cell for the particle's (k, g), 0 = none.
@@ -341,7 +345,8 @@ struct SplitBank {
     uint64_t *s;
     uint32_t *ixyz, *gk;      // gk = g | batch << 5 | k << 15
     uint64_t *hid;            // global history index
-    unsigned int *count;      // device counter of entries
+    unsigned long long *count;  // device counter of entries asked for (64-bit: it
+                                // keeps counting past cap on overflow, never wraps)
     unsigned int cap;
 };
 
@@ -383,13 +388,55 @@ __device__ __forceinline__ void split_load(const SplitBank &B, unsigned int slot
     hid = B.hid[slot];
 }
 
+// A fission neutron in material m draws from its own stream its group from
+// the fission spectrum, an isotropic direction and an optical depth.
+template <int FM>
+__device__ __forceinline__ void fission_emit(const DevProblem &P, Particle &p, int m) {
+    const double xg = rn(p.s);
+    const double *cdf = P.chi_cdf + (int64_t)m * P.G;
+    int g = 0;
+    while (!(xg < cdf[g])) ++g;
+    p.g = g;
+    isotropic(p.s, p.u[0], p.u[1], p.u[2]);
+    set_inverse<FM>(P, p);
+    p.tau = -log(1.0 - rn(p.s));
+}
+
+// Prompt fission of p (group p.g) in material m: n = floor(nu + xi)
+// neutrons at the collision point and time.  Neutron j = 1..n-1 takes the
+// stream child_stream(s, j) of the state s after that draw and goes whole
+// to the split bank (overflow sets *overflow); neutron 0 is p itself.
+// Returns n (0: p is absorbed).
+template <int FM>
+__device__ __forceinline__ int fission(const DevProblem &P, Particle &p, int m, const SplitBank &SB, int b,
+                                       uint64_t hid, int *overflow) {
+    const int n = (int)floor(P.nu[(int64_t)m * P.G + p.g] + rn(p.s));
+    if (n <= 0) return 0;
+    const uint64_t sf = p.s;
+    if (n > 1) {
+        const unsigned long long base = atomicAdd(SB.count, (unsigned long long)(n - 1));
+        if (base + (unsigned long long)(n - 1) > SB.cap) {
+            *overflow = 1;
+        } else {
+            for (int j = 1; j < n; ++j) {
+                Particle c = p;
+                c.s = child_stream(sf, (uint64_t)j);
+                fission_emit<FM>(P, c, m);
+                split_store(SB, (unsigned int)base + j - 1, c, b, hid);
+            }
+        }
+    }
+    fission_emit<FM>(P, p, m);
+    return n;
+}
+
 // Append the n_children split copies of p (streams child_stream(p.s, j),
 // j = 1..n_children) to the split bank.  Returns false on overflow.
 __device__ __forceinline__ bool spawn_children(const SplitBank &B, const Particle &p, int n_children, int b,
                                                uint64_t hid) {
     if (n_children <= 0) return true;
-    const unsigned int base = atomicAdd(B.count, (unsigned int)n_children);
-    if (base + (unsigned int)n_children > B.cap) return false;
+    const unsigned long long base = atomicAdd(B.count, (unsigned long long)n_children);
+    if (base + (unsigned long long)n_children > B.cap) return false;
     Particle c = p;
     for (int j = 1; j <= n_children; ++j) {
         c.s = child_stream(p.s, (uint64_t)j);

@@ -658,7 +658,18 @@ __global__ void __launch_bounds__(kBlock) k_event(DevProblem P0, RunArgs R0, Ban
                             busy = false;
                     }
                 } else {
-                    if (!collide<FM>(P, p, P.cell_mat[cell])) {
+                    const int m = P.cell_mat[cell];
+                    int r = collide<FM, WW>(P, p, m);
+                    if (WW && r == 2) {
+                        // fission: neutrons 1..n-1 to the split bank
+                        const int nf = fission<FM>(P, p, m, SB, b, i, R.overflow);
+                        if (nf > 1) {
+                            cnt.add(9, (unsigned int)(nf - 1));
+                            if (R.dbg_counts) atomicAdd(R.dbg_counts + i * 5 + 3, (unsigned int)(nf - 1));
+                        }
+                        r = nf > 0 ? 1 : 0;
+                    }
+                    if (r == 0) {
                         cnt.add(3 + kAbsorb);
                         hist_term(R, i, kAbsorb);
                         busy = false;
@@ -805,7 +816,8 @@ int run_event(mcdc_problem *pb, const RunArgs &R0, uint64_t first, uint64_t coun
     const DevProblem &P = pb->d;
     // (weight-window runs take smaller chunks: their progeny of a chunk must
     // fit the split bank)
-    uint64_t C = opt.bank_capacity ? (uint64_t)opt.bank_capacity : (WW ? kWindowChunk : (uint64_t)1 << 24);
+    uint64_t C = opt.bank_capacity ? (uint64_t)opt.bank_capacity
+                                   : (WW ? (P.fission_on ? kFissionChunk : kWindowChunk) : (uint64_t)1 << 24);
     if (C > count) C = count;
     if (C > (1ULL << 28)) C = 1ULL << 28;
 
@@ -842,7 +854,7 @@ int run_event(mcdc_problem *pb, const RunArgs &R0, uint64_t first, uint64_t coun
     Layout L = carve(pb->bank.p, pb->queues.p, slots, G, Lseg, FM ? FM : P.finite_mask, WW);
     RunArgs R = R0;
     R.qoi_hist = (double *)pb->qoi_hist.p;
-    // weight windows: split progeny of a chunk go to the split bank and are
+    // weight windows and fission: progeny of a chunk go to the split bank and are
     // tracked after its census steps
     SplitBank SB[2]{};
     if (WW && (rc = split_prepare(pb, C, SB))) return rc;
@@ -1078,7 +1090,7 @@ int launch_event(mcdc_problem *p, const RunArgs &R, uint64_t first, uint64_t cou
     }
     LdsTables tabs{};
     const bool lt = table_layout(P, tabs, kLdsTablesMax);
-    if (P.ww_center != nullptr) {
+    if (has_progeny(P)) {
         if (P.finite_mask == 1) return run_event_lt<1, true>(p, R, first, count, opt, st, prof, tabs, lt);
         if (P.finite_mask == 7) return run_event_lt<7, true>(p, R, first, count, opt, st, prof, tabs, lt);
         return run_event_lt<0, true>(p, R, first, count, opt, st, prof, tabs, lt);

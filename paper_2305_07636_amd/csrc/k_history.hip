@@ -21,7 +21,8 @@ struct BlockCounters {
 struct Acc {
     unsigned int n_ev[3] = {0u, 0u, 0u};
     unsigned int term_mask = 0u;
-    unsigned int spawned = 0u;
+    unsigned int spawned = 0u;     // window-split progeny
+    unsigned int fissioned = 0u;   // fission neutrons beyond the colliding one
     double track = 0.0, qoi = 0.0;
 };
 
@@ -70,10 +71,20 @@ __device__ __forceinline__ int hstep(const DevProblem &P, const RunArgs &R, Part
         }
     } else {
         ++acc.n_ev[2];
-        if (!collide<FM>(P, p, f.m))
+        const int r = collide<FM, WW>(P, p, f.m);
+        if (r == 0) {
             code = kAbsorb;
-        else
+        } else if (WW && r == 2) {
+            const int n = fission<FM>(P, p, f.m, SB, b, hid, R.overflow);
+            if (n == 0) {
+                code = kAbsorb;
+            } else {
+                acc.fissioned += (unsigned int)(n - 1);
+                check = true;
+            }
+        } else {
             check = WW;
+        }
     }
     if (WW && check) {
         int nc = 0;
@@ -140,7 +151,7 @@ __device__ __forceinline__ void end_history(const DevProblem &P, const RunArgs &
         d[0] = acc.n_ev[0];
         d[1] = acc.n_ev[1];
         d[2] = acc.n_ev[2];
-        d[3] = 1u + acc.spawned;
+        d[3] = 1u + acc.spawned + acc.fissioned;
         d[4] = acc.term_mask;
     }
     if (R.dbg_scores) {
@@ -157,6 +168,7 @@ __device__ __forceinline__ void end_history(const DevProblem &P, const RunArgs &
     lt.c[1] += acc.n_ev[1];
     lt.c[2] += acc.n_ev[2];
     lt.c[8] += acc.spawned;
+    lt.c[9] += acc.fissioned;
 }
 
 // Idle lanes that trigger a refill.  The histories a wave takes from the
@@ -289,7 +301,7 @@ __global__ void __launch_bounds__(256) k_history_children(DevProblem P, RunArgs 
             uint32_t *d = R.dbg_counts + i * 5;
             for (int e = 0; e < 3; ++e)
                 if (acc.n_ev[e]) atomicAdd(d + e, acc.n_ev[e]);
-            if (acc.spawned) atomicAdd(d + 3, acc.spawned);
+            if (acc.spawned + acc.fissioned) atomicAdd(d + 3, acc.spawned + acc.fissioned);
             atomicOr(d + 4, acc.term_mask);
         }
         if (R.dbg_scores) {
@@ -300,16 +312,17 @@ __global__ void __launch_bounds__(256) k_history_children(DevProblem P, RunArgs 
         for (int e = 0; e < 3; ++e)
             if (acc.n_ev[e]) atomicAdd(&bc.c[e], acc.n_ev[e]);
         if (acc.spawned) atomicAdd(&bc.c[8], acc.spawned);
+        if (acc.fissioned) atomicAdd(&bc.c[9], acc.fissioned);
     }
     __syncthreads();
     if (threadIdx.x < kCounters && bc.c[threadIdx.x])
         atomicAdd(R.counters + threadIdx.x, (unsigned long long)bc.c[threadIdx.x]);
 }
 
-__global__ void k_zero_count(unsigned int *c) { *c = 0u; }
+__global__ void k_zero_count(unsigned long long *c) { *c = 0ull; }
 __global__ void k_zero_u64(unsigned long long *c) { *c = 0ull; }
 
-SplitBank carve_split(void *mem, unsigned int cap, unsigned int *count) {
+SplitBank carve_split(void *mem, unsigned int cap, unsigned long long *count) {
     SplitBank B{};
     char *p = (char *)mem;
     auto take = [&](size_t bytes) {
@@ -373,13 +386,14 @@ template <int FM>
 int run_generations(const DevProblem &P, const RunArgs &R, SplitBank SB[2], uint64_t cfirst, hipStream_t st,
                     Profiler &prof) {
     for (int gen = 0;; ++gen) {
-        unsigned int n_in = 0;
-        hipError_t e = hipMemcpyAsync(&n_in, SB[gen & 1].count, sizeof(unsigned int), hipMemcpyDeviceToHost, st);
+        unsigned long long n_in = 0;
+        hipError_t e = hipMemcpyAsync(&n_in, SB[gen & 1].count, sizeof(n_in), hipMemcpyDeviceToHost, st);
         if (e == hipSuccess) e = hipStreamSynchronize(st);
         if (e != hipSuccess) return hip_fail(e, "split count");
         if (n_in == 0) return MCDC_OK;
         if (n_in > SB[gen & 1].cap || gen > 10000) {
-            set_error("split bank overflow (weight windows split too many particles)");
+            set_error("split bank overflow (window splits or fission made too many progeny in one generation; "
+                      "run fewer histories per chunk with bank_capacity)");
             return MCDC_E_OVERFLOW;
         }
         const SplitBank &in = SB[gen & 1], &out = SB[(gen + 1) & 1];
@@ -395,11 +409,12 @@ template <int FM>
 int run_history(mcdc_problem *pb, const RunArgs &R0, uint64_t first, uint64_t count, hipStream_t st,
                 Profiler &prof) {
     const DevProblem &P = pb->d;
-    const bool ww = P.ww_center != nullptr;
+    const bool ww = has_progeny(P);
     RunArgs R = R0;
-    // analog runs keep the detector score in registers; weight-window runs
-    // assemble it per history in chunks
-    const uint64_t chunk = ww ? ((count < kWindowChunk) ? count : kWindowChunk) : count;
+    // analog runs keep the detector score in registers; runs with progeny
+    // (weight windows, fission) assemble it per history in chunks
+    const uint64_t cmax = P.fission_on ? kFissionChunk : kWindowChunk;
+    const uint64_t chunk = ww ? ((count < cmax) ? count : cmax) : count;
     SplitBank SB[2]{};
     int rc;
     if (ww) {
@@ -537,12 +552,13 @@ int launch_batched(const BatchItem *items, const uint64_t *offs, int n_items, ui
 
 int split_prepare(mcdc_problem *pb, uint64_t chunk, dev::SplitBank SB[2]) {
     // room for eight progeny per history of the chunk in each generation
-    const uint64_t want = 8 * chunk;
+    // (64 with fission)
+    const uint64_t want = (pb->d.fission_on ? 64 : 8) * chunk;
     const unsigned int cap = (unsigned int)((want < (1u << 22)) ? (1u << 22) : (want > (1u << 26) ? (1u << 26) : want));
     int rc;
     if ((rc = ensure(pb->split, 2 * split_bytes(cap) + 256))) return rc;
-    if ((rc = ensure(pb->counters_split, 2 * sizeof(unsigned int)))) return rc;
-    unsigned int *cnt = (unsigned int *)pb->counters_split.p;
+    if ((rc = ensure(pb->counters_split, 2 * sizeof(unsigned long long)))) return rc;
+    unsigned long long *cnt = (unsigned long long *)pb->counters_split.p;
     SB[0] = carve_split(pb->split.p, cap, cnt);
     SB[1] = carve_split((char *)pb->split.p + split_bytes(cap), cap, cnt + 1);
     return MCDC_OK;

@@ -14,9 +14,11 @@
 namespace mcdc {
 
 constexpr int kMaxGroups = 32;      // outgoing-group search is unrolled over this
-constexpr int kCounters = 9;        // census, surface, collision; 5 terminations; splits
+constexpr int kCounters = 10;       // census, surface, collision; 5 terminations; splits; fission progeny
 constexpr int kLdsTallyMax = 4096;  // doubles of the event form's per-step LDS tally slice
 constexpr uint64_t kWindowChunk = 1ULL << 23;  // histories per chunk of a weight-window run
+constexpr uint64_t kFissionChunk = 1ULL << 20; // histories per chunk of a run with fission
+constexpr double kMaxNu = 64.0;                // largest mean number of neutrons per fission
 constexpr uint64_t kStride = 152917ULL;
 
 enum Term : int { kAbsorb = 0, kLeak = 1, kTime = 2, kLost = 3, kRoulette = 4 };
@@ -62,7 +64,18 @@ struct DevProblem {
     int nww;
     int ww_max_split;
     double ww_ratio;
+    // prompt fission (fission_on = 0: none)
+    int fission_on;
+    const double *pf;          // [M][G] (sigma_s,g + sigma_f,g) / sigma_t,g
+    const double *nu;          // [M][G] mean neutrons per fission
+    const double *chi_cdf;     // [M][G] fission-spectrum CDF
 };
+
+// Runs whose particles make progeny (window splits, fission neutrons) take
+// the kernels' progeny form: split bank, per-history detector scores.
+__host__ __device__ inline bool has_progeny(const DevProblem &P) {
+    return P.ww_center != nullptr || P.fission_on != 0;
+}
 
 // Doubles per bin of the event form's per-step LDS slice: two batches of
 // the track-length tally, and two of the time-crossing tally when it is on.
@@ -157,6 +170,8 @@ struct HostProblem {
     std::vector<int32_t> cell_mat, cell_tal, cell_ww;
     std::vector<uint8_t> cell_qoi;
     std::vector<double> sigma_t, inv_st, ps, cdf, speed, inv_v, T, src_cdf;
+    bool fission = false;
+    std::vector<double> pf, nu, chi_cdf;   // [M][G] each (fission only)
     std::vector<uint8_t> qoi_groups;
     std::vector<double> bin_norm;      // [nts] V_j (product of bin widths)
     std::vector<double> time_norm;     // [K] dt_k (1 if infinite)

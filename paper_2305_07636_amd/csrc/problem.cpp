@@ -138,6 +138,39 @@ int compile(const mcdc_problem_desc *d, HostProblem &h) {
     h.inv_v.resize(G);
     for (int g = 0; g < G; ++g) h.inv_v[g] = 1.0 / h.speed[g];
 
+    // prompt fission (optional): reaction thresholds, nu, spectrum CDF
+    const int nfis = (d->sigma_f != nullptr) + (d->nu != nullptr) + (d->chi != nullptr);
+    if (nfis != 0 && nfis != 3) return invalid("fission needs sigma_f, nu and chi together");
+    h.fission = nfis == 3;
+    if (h.fission) {
+        h.pf.resize((size_t)M * G);
+        h.nu.assign(d->nu, d->nu + (size_t)M * G);
+        h.chi_cdf.resize((size_t)M * G);
+        for (int m = 0; m < M; ++m) {
+            for (int g = 0; g < G; ++g) {
+                const double st = h.sigma_t[m * G + g], sf = d->sigma_f[m * G + g], nu = h.nu[m * G + g];
+                if (!(sf >= 0.0) || !std::isfinite(sf)) return invalid("sigma_f must be finite and >= 0");
+                if (!(nu >= 0.0) || !(nu <= kMaxNu)) return invalid("nu must be in [0, 64]");
+                const double *row = d->sigma_s + ((size_t)m * G + g) * G;
+                double ss = 0.0;
+                for (int g2 = 0; g2 < G; ++g2) ss += row[g2];
+                if (ss + sf > st * (1.0 + 1e-12)) return invalid("scattering plus fission exceeds sigma_t");
+                h.pf[m * G + g] = (st > 0.0) ? (ss + sf) / st : 0.0;
+            }
+            double run = 0.0;
+            int last = -1;
+            for (int g = 0; g < G; ++g) {
+                const double c = d->chi[m * G + g];
+                if (!(c >= 0.0) || !std::isfinite(c)) return invalid("chi must be finite and >= 0");
+                run += c;
+                h.chi_cdf[m * G + g] = run;
+                if (c > 0.0) last = g;
+            }
+            if (last < 0 || std::fabs(run - 1.0) > 1e-12) return invalid("chi must sum to 1 for every material");
+            for (int g = last; g < G; ++g) h.chi_cdf[m * G + g] = 1.0;
+        }
+    }
+
     // geometry planes and domain
     int ngc[3];
     for (int a = 0; a < 3; ++a) {
@@ -319,7 +352,8 @@ int upload(mcdc_problem *p) {
                  o_q = b.add(h.cell_qoi), o_st = b.add(h.sigma_t), o_ist = b.add(h.inv_st),
                  o_ps = b.add(h.ps), o_cdf = b.add(h.cdf), o_v = b.add(h.speed),
                  o_iv = b.add(h.inv_v), o_T = b.add(h.T), o_sc = b.add(h.src_cdf),
-                 o_qg = b.add(h.qoi_groups), o_bn = b.add(h.bin_norm), o_tn = b.add(h.time_norm);
+                 o_qg = b.add(h.qoi_groups), o_bn = b.add(h.bin_norm), o_tn = b.add(h.time_norm),
+                 o_pf = b.add(h.pf), o_nu = b.add(h.nu), o_chi = b.add(h.chi_cdf);
     std::vector<uint64_t> A(64), C(64);
     lcg_map(kStride, A[0], C[0]);
     for (int j = 1; j < 64; ++j) {
@@ -390,6 +424,10 @@ int upload(mcdc_problem *p) {
     D.nww = h.nw[0] * h.nw[1] * h.nw[2];
     D.ww_max_split = 16;
     D.ww_ratio = 5.0;
+    D.fission_on = h.fission ? 1 : 0;
+    D.pf = h.fission ? (const double *)(base + o_pf) : nullptr;
+    D.nu = h.fission ? (const double *)(base + o_nu) : nullptr;
+    D.chi_cdf = h.fission ? (const double *)(base + o_chi) : nullptr;
     return MCDC_OK;
 }
 

@@ -217,6 +217,7 @@ int collect_end(mcdc_problem *p, uint64_t N, const Collect &c, mcdc_result *out,
     for (int j = 0; j < 3; ++j) out->n_events[j] = c.cnt[j];
     for (int j = 0; j < 5; ++j) out->n_term[j] = c.cnt[3 + j];
     out->n_splits = c.cnt[8];
+    out->n_fission = c.cnt[9];
     out->qoi_sum[0] = c.qs[0];
     out->qoi_sum[1] = c.qs[1];
     const double V = p->h.qoi_volume;
@@ -438,8 +439,8 @@ extern "C" int mcdc_run_batched(mcdc_problem *const *ps, int32_t n, const uint64
     for (int j = 0; j < n; ++j) {
         if (!ps[j]) return bad("NULL problem in batch");
         if (ps[j]->device != dev) return bad("all problems of a batch must be on one device");
-        if (ps[j]->d.ww_center) {
-            set_error("batched solves run analog (no weight windows)");
+        if (has_progeny(ps[j]->d)) {
+            set_error("batched solves run analog (no weight windows, no fission)");
             return MCDC_E_UNSUPPORTED;
         }
         if (ps[j]->h.B > 1023) {

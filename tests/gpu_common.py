@@ -64,6 +64,7 @@ def compare_full(prob, N, seed, algorithm, ww=None, **kw):
     assert np.array_equal(g["events"], tot[0:3]), (g["events"], tot[0:3])
     assert np.array_equal(g["terms"], tot[3:8]), (g["terms"], tot[3:8])
     assert g["splits"] == int(tot[8])
+    assert g["fission"] == int(tot[9])
     close(g["raw"], e["raw"], what="raw")
     close(g["mean"], e["mean"], what="mean")
     close(g["var"], e["var"], rtol=VAR_RTOL, what="var")
@@ -119,7 +120,7 @@ def compare_sampled(prob, N, seed, algorithm, n_sample=2000, sample_seed=0, ww=N
     close(ds, r["trk"], what="sampled per-history scores")
     # properties at any size: every history terminates (exactly once without
     # windows) and the per-history counts add up to the event totals
-    if ww is None:
+    if ww is None and prob.get("fission") is None:
         assert int(out["terms"].sum()) == N
         assert one_bit == N
     assert n_term_bits == N
