@@ -147,6 +147,40 @@ def batched_section(m, w):
             h.close()
 
 
+def fission_section(m, w, n, steps):
+    """Supercritical pulse with prompt fission (c = 1.1, one group, 42-mfp
+    slab, 20 mean free times): histories/s in both forms and the population
+    growth at t = 20 from the time-crossing tally (e^2 = 7.39)."""
+    import numpy as np
+    import torch
+
+    prob = w.azurv1_supercritical()
+    h = m.mcdc_problem_create(prob)
+    res = {"workload": "supercritical pulse: 1 group, Sigma_t = v = 1, c = 0.5 + 2.4 x 0.25 = 1.1, "
+                       "42-mfp slab, 42 x-bins x 20 time bins on [0, 20] plus the time-crossing tally, "
+                       f"{n:.0e} histories", "histories": n}
+    try:
+        for alg in ("event", "history"):
+            out = m.mcdc_run(h, n, 80, algorithm=alg, outputs=("mean",))
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for s in range(steps):
+                out = m.mcdc_run(h, n, 81 + s, algorithm=alg, outputs=("mean",))
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / steps
+            res[f"{alg}_histories_per_s"] = n / dt
+            res[f"{alg}_events_per_s"] = float(sum(out["events"])) / dt
+            log(f"fission {alg} form: {dt * 1e3:.1f} ms per run")
+        res["events_per_history"] = float(sum(out["events"])) / n
+        res["fission_neutrons_per_history"] = out["fission"] / n
+        tc = out["tc_mean"].cpu().numpy()[:, 0, 0, 0, :]
+        res["population_at_t20"] = float(tc[-1].sum())
+        res["population_exact"] = float(np.exp(2.0))
+    finally:
+        h.close()
+    return res
+
+
 def fom_section(w, n_pilot, n_analog, n_ww, steps):
     """Dog-leg duct, detector behind the second bend: analog against learned
     weight windows (pilots, network fit, BF16 inference) and against windows
@@ -194,6 +228,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-fom", action="store_true")
     ap.add_argument("--no-time-crossing", action="store_true")
+    ap.add_argument("--no-fission", action="store_true")
+    ap.add_argument("--fission-histories", type=float, default=1e6)
     ap.add_argument("--fom-pilot", type=float, default=1e8)
     ap.add_argument("--fom-analog", type=float, default=4e9)
     ap.add_argument("--fom-ww", type=float, default=1e9)
@@ -318,6 +354,8 @@ def main():
         extra["time_crossing_tally"] = tc
         log("time-crossing tally timed")
     p.close()
+    if not args.no_fission:
+        extra["fission"] = fission_section(m, w, int(args.fission_histories), args.steps)
     if not args.no_batched:
         extra["batched"] = batched_section(m, w)
     if not args.no_fom:
