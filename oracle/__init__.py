@@ -86,6 +86,9 @@ def lib():
                                     C.c_uint64, C.c_uint64, C.c_void_p, C.c_void_p,
                                     C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                     C.c_void_p]
+        _lib.oracle_eigen.restype = C.c_int
+        _lib.oracle_eigen.argtypes = [C.c_void_p, C.c_uint64, C.c_int, C.c_int, C.c_uint64,
+                                      C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
         _lib.oracle_trace.restype = C.c_int
         _lib.oracle_trace.argtypes = [C.c_void_p, C.c_uint64, C.c_uint64, C.c_uint64,
                                       C.c_void_p, C.c_int]
@@ -330,3 +333,40 @@ def trace(prob, N: int, seed: int, i: int, cap: int = 100000) -> np.ndarray:
     if n < 0:
         raise RuntimeError("trace failed")
     return rows[:n].copy()
+
+
+def eigen(prob, N: int, n_inactive: int, n_active: int, seed: int):
+    """k-eigenvalue power iteration (reading R13 of mcdc_oracle.c): cycles of
+    N particles on a steady-state problem with fission.  Returns raw flux
+    sums 'S' [n_active, ntally] and leak sums 'L' [n_active, K, G, 6] of
+    the active cycles (one batch each), 'k' per cycle, totals 'tot'."""
+    op = prob if isinstance(prob, OracleProblem) else OracleProblem(prob)
+    S = np.zeros((n_active, op.ntally))
+    L = np.zeros((n_active, op.K, op.G, 6))
+    k = np.zeros(n_inactive + n_active)
+    tot = np.zeros(10, dtype=np.uint64)
+    rc = lib().oracle_eigen(op.ptr(), N, n_inactive, n_active, seed, S.ctypes.data, L.ctypes.data,
+                            k.ctypes.data, tot.ctypes.data)
+    if rc != 0:
+        raise RuntimeError(f"oracle_eigen failed with code {rc}")
+    return {"S": S, "L": L, "k": k, "tot": tot, "N": N, "n_inactive": n_inactive,
+            "n_active": n_active, "op": op}
+
+
+def eigen_estimates(prob, res) -> dict:
+    """Flux per cycle-source neutron and leakage, mean over the active
+    cycles and the variance of that mean across cycles; k mean over the
+    active cycles and its standard error."""
+    op = res["op"]
+    N, A = res["N"], res["n_active"]
+    norm = (bin_volumes(prob)[None, None, :, :, :] * np.ones((op.K, op.G, 1, 1, 1))).reshape(-1)
+    mb = res["S"] / (N * norm[None, :])
+    mean = mb.mean(axis=0)
+    var = ((mb - mean) ** 2).sum(axis=0) / (A * (A - 1)) if A > 1 else np.zeros_like(mean)
+    lb = res["L"] / N
+    lmean = lb.mean(axis=0)
+    lvar = ((lb - lmean) ** 2).sum(axis=0) / (A * (A - 1)) if A > 1 else np.zeros_like(lmean)
+    ka = res["k"][res["n_inactive"]:]
+    return {"mean": mean.reshape(op.tally_shape), "var": var.reshape(op.tally_shape),
+            "leak_mean": lmean, "leak_var": lvar, "k_mean": float(ka.mean()),
+            "k_std": float(ka.std(ddof=1) / math.sqrt(A)) if A > 1 else 0.0, "k": res["k"]}

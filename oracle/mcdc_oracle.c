@@ -63,6 +63,19 @@
  *       group from the material's spectrum chi, an isotropic direction and
  *       an optical depth; the colliding particle then takes the window
  *       check as after a scatter.
+ *   R13 k-eigenvalue power iteration (Section 3 runs the C5G7 pin cell and
+ *       core this way; steady state): cycles of N particles.  Cycle c uses
+ *       the stream s_c = SplitMix64(seed ^ c) masked to 63 bits; particle q
+ *       starts at skip(s_c, (q + 1) * stride).  Cycle 0 is born from the
+ *       problem's source; in the cycle loop a fission does not continue the
+ *       particle: it banks floor(nu + xi) sites at the collision point and
+ *       the particle ends (absorbed).  The sites of a cycle, M in all, are
+ *       ordered by (particle, site); particle q of the next cycle is born
+ *       at site floor((q + u) M / N) (a comb with offset u, the first draw
+ *       of s_c) and draws its group from the spectrum of the site's
+ *       material, an isotropic direction and an optical depth.  k of a
+ *       cycle is M / N.  Flux and leakage are tallied in the active cycles
+ *       only, one batch per active cycle.
  *
  * Build: gcc -O2 -ffp-contract=off -fPIC -shared -o liboracle.so mcdc_oracle.c -lm
  */
@@ -318,6 +331,12 @@ typedef struct {
                            absorb, leak, time, lost, roulette; splits;
                            fission neutrons beyond the colliding one */
     double *pf;         /* [M][G] (Sigma_s,g + Sigma_f,g) / Sigma_t,g (fission only) */
+    /* k-eigenvalue cycles (R13) */
+    int eigen;          /* fissions bank sites instead of continuing */
+    int quiet;          /* inactive cycle: no tallies */
+    double site_x[3];   /* fission site of the current particle */
+    int site_ix[3];
+    int site_n;         /* sites banked there (0: none) */
     double *chi_cdf;    /* [M][G] fission-spectrum CDF (fission only) */
 } ctx;
 
@@ -537,12 +556,12 @@ static int step(ctx *C, particle *pt, int b, particle *stack, int *sp, hist_rec 
 
     /* track-length score of the flight */
     double sc = pt->w * d;
-    int64_t j = tally_bin(C, pt);
+    int64_t j = C->quiet ? -1 : tally_bin(C, pt);
     if (j >= 0) {
         csum(&C->S[(int64_t)b * C->ntally + j], &C->Sc[(int64_t)b * C->ntally + j], sc);
         h->track += sc;
     }
-    if (in_qoi(C, pt)) h->qoi += sc;
+    if (!C->quiet && in_qoi(C, pt)) h->qoi += sc;
 
     /* move */
     for (int a = 0; a < 3; a++) pt->x[a] = fma(d, pt->u[a], pt->x[a]);
@@ -595,7 +614,7 @@ static int step(ctx *C, particle *pt, int b, particle *stack, int *sp, hist_rec 
             if (face >= 0) {
                 if (p->bc[face] == 0) {
                     int64_t l = (((int64_t)b * C->K + pt->k) * G + pt->g) * 6 + face;
-                    csum(&C->L[l], &C->Lc[l], pt->w);
+                    if (!C->quiet) csum(&C->L[l], &C->Lc[l], pt->w);
                     terminate(C, h, T_LEAK);
                     alive = 0;
                 } else {
@@ -613,7 +632,16 @@ static int step(ctx *C, particle *pt, int b, particle *stack, int *sp, hist_rec 
          * fission with probability Sigma_f,g / Sigma_t,g (R12) */
         double xr = rn(&pt->s);
         if (!(xr < C->ps[m * G + pt->g])) {
-            if (C->pf && xr < C->pf[m * G + pt->g]) {
+            if (C->pf && xr < C->pf[m * G + pt->g] && C->eigen) {
+                /* R13: bank the sites, end the particle */
+                C->site_n = (int)floor(p->nu[m * G + pt->g] + rn(&pt->s));
+                for (int a = 0; a < 3; a++) {
+                    C->site_x[a] = pt->x[a];
+                    C->site_ix[a] = pt->ix[a];
+                }
+                terminate(C, h, T_ABSORB);
+                alive = 0;
+            } else if (C->pf && xr < C->pf[m * G + pt->g]) {
                 alive = fission(C, pt, m, stack, sp, h);
                 if (alive > 0) alive = ww_game(C, pt, stack, sp, h);
             } else {
@@ -952,4 +980,121 @@ int oracle_trace(const oracle_problem *p, uint64_t N, uint64_t seed, uint64_t i,
     n++;
     ctx_free(&C);
     return n;
+}
+
+/* ------------------------------------------------------------------------ */
+/* k-eigenvalue power iteration (R13)                                         */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * n_inactive + n_active cycles of N particles on a steady-state problem
+ * with fission data (no weight windows).  Outputs: raw flux sums
+ * S[n_active][ntally] and leak sums L[n_active][K][G][6] of the active
+ * cycles (one batch each), k of every cycle k_out[n_inactive + n_active],
+ * event and termination totals over all cycles tot[10] (any may be NULL).
+ * Returns 0, -1 on an invalid problem (or one without fission, or not
+ * steady state), -6 if a cycle banks no site.
+ */
+int oracle_eigen(const oracle_problem *p, uint64_t N, int n_inactive, int n_active, uint64_t seed,
+                 double *S_out, double *L_out, double *k_out, uint64_t *tot_out)
+{
+    ctx C;
+    memset(&C, 0, sizeof(C));
+    if (N == 0 || n_inactive < 0 || n_active < 1 || !p->sigma_f || p->ww_center ||
+        ctx_init(&C, p) != 0 || C.K != 1 || p->time_edges[1] != INFINITY) {
+        ctx_free(&C);
+        return -1;
+    }
+    const int G = p->G, A = n_active;
+    C.eigen = 1;
+    C.S = (double *)calloc((size_t)(A * C.ntally), sizeof(double));
+    C.Sc = (double *)calloc((size_t)(A * C.ntally), sizeof(double));
+    C.X = (double *)calloc((size_t)(A * C.ntally), sizeof(double));
+    C.Xc = (double *)calloc((size_t)(A * C.ntally), sizeof(double));
+    C.L = (double *)calloc((size_t)(A * G * 6), sizeof(double));
+    C.Lc = (double *)calloc((size_t)(A * G * 6), sizeof(double));
+    /* sites of the previous and the current cycle, one record per particle */
+    double *sx[2];
+    int *six[2], *sn[2];
+    uint64_t *cum = (uint64_t *)malloc(sizeof(uint64_t) * N);   /* inclusive prefix of sn[prev] */
+    for (int r = 0; r < 2; r++) {
+        sx[r] = (double *)malloc(sizeof(double) * 3 * N);
+        six[r] = (int *)malloc(sizeof(int) * 3 * N);
+        sn[r] = (int *)malloc(sizeof(int) * N);
+    }
+    int rc = 0, cur = 0;
+    uint64_t M = 0;
+    double u = 0.0;
+    for (int c = 0; c < n_inactive + n_active && rc == 0; c++) {
+        const uint64_t sc = oracle_child_stream(seed & MASK63, (uint64_t)c);
+        const int active = c >= n_inactive;
+        const int b = active ? c - n_inactive : 0;
+        C.quiet = !active;
+        const int prev = cur ^ 1;
+        for (uint64_t q = 0; q < N; q++) {
+            hist_rec h;
+            memset(&h, 0, sizeof(h));
+            particle pt;
+            int alive;
+            const uint64_t s0 = oracle_rng_skip(sc, (q + 1) * LCG_STRIDE);
+            if (c == 0) {
+                alive = birth(&C, s0, &pt, &h);
+            } else {
+                /* comb over the previous cycle's sites */
+                uint64_t idx = (uint64_t)floor(((double)q + u) * (double)M / (double)N);
+                if (idx >= M) idx = M - 1;
+                uint64_t lo = 0, hi = N - 1;   /* first i with cum[i] > idx */
+                while (lo < hi) {
+                    uint64_t mid = lo + (hi - lo) / 2;
+                    if (cum[mid] > idx) hi = mid; else lo = mid + 1;
+                }
+                memset(&pt, 0, sizeof(pt));
+                pt.s = s0;
+                for (int a = 0; a < 3; a++) {
+                    pt.x[a] = sx[prev][3 * lo + a];
+                    pt.ix[a] = six[prev][3 * lo + a];
+                }
+                pt.t = p->time_edges[0];
+                pt.w = 1.0;
+                emit(&C, &pt, material_of(&C, &pt));
+                alive = 1;
+            }
+            C.site_n = 0;
+            if (alive) {
+                int sp = 0;
+                if (track(&C, &pt, b, NULL, &sp, &h) < 0) rc = -4;
+            }
+            sn[cur][q] = C.site_n;
+            for (int a = 0; a < 3; a++) {
+                sx[cur][3 * q + a] = C.site_x[a];
+                six[cur][3 * q + a] = C.site_ix[a];
+            }
+        }
+        M = 0;
+        for (uint64_t q = 0; q < N; q++) {
+            M += (uint64_t)sn[cur][q];
+            cum[q] = M;
+        }
+        if (k_out) k_out[c] = (double)M / (double)N;
+        if (M == 0) rc = -6;
+        uint64_t su = sc;
+        u = rn(&su);
+        cur ^= 1;
+    }
+    if (rc == 0) {
+        if (S_out)
+            for (int64_t j = 0; j < A * C.ntally; j++) S_out[j] += C.S[j] + C.Sc[j];
+        if (L_out)
+            for (int64_t j = 0; j < A * G * 6; j++) L_out[j] += C.L[j] + C.Lc[j];
+        if (tot_out)
+            for (int j = 0; j < 10; j++) tot_out[j] += C.tot[j];
+    }
+    for (int r = 0; r < 2; r++) {
+        free(sx[r]);
+        free(six[r]);
+        free(sn[r]);
+    }
+    free(cum);
+    ctx_free(&C);
+    return rc;
 }

@@ -232,6 +232,51 @@ def sn_slab(L, sigma_t, sigma_s, n_cells=4000, n_mu=64, tol=1e-12, law="cosine")
     return xe, phi, bins
 
 
+def sn_slab_k(L, sigma_t, sigma_s, nu_sigma_f, n_cells=2000, n_mu=64, tol=1e-11):
+    """One-group bare slab [0, L] (vacuum faces), isotropic scattering and
+    fission: k-eigenvalue by power iteration on the fission source, each
+    transport solve by source iteration with diamond differencing and
+    Gauss-Legendre angles.  Returns (k, cell edges, cell-average flux per
+    unit fission source: the fission source nu Sigma_f phi / k integrates
+    to 1)."""
+    h = L / n_cells
+    xe = np.linspace(0.0, L, n_cells + 1)
+    mu, wt = np.polynomial.legendre.leggauss(n_mu)
+
+    def sweep(q):
+        out = np.zeros(n_cells)
+        for m, w in zip(mu, wt):
+            am = abs(m)
+            a = (am / h - sigma_t / 2.0) / (am / h + sigma_t / 2.0)
+            b = 1.0 / (am / h + sigma_t / 2.0)
+            src = q if m > 0 else q[::-1]
+            edge_out = lfilter([b], [1.0, -a], src)
+            edge_in = np.concatenate([[0.0], edge_out[:-1]])
+            avg = 0.5 * (edge_in + edge_out)
+            out += w * (avg if m > 0 else avg[::-1])
+        return out
+
+    phi = np.ones(n_cells)
+    k = 1.0
+    for _ in range(500):
+        fis = nu_sigma_f * phi / k
+        new = phi.copy()
+        for _ in range(5000):
+            nxt = sweep(0.5 * (sigma_s * new + fis))
+            d = np.max(np.abs(nxt - new)) / np.max(np.abs(nxt))
+            new = nxt
+            if d < tol:
+                break
+        k_new = k * (nu_sigma_f * new).sum() / (nu_sigma_f * phi).sum()
+        phi = new
+        if abs(k_new - k) < tol:
+            k = k_new
+            break
+        k = k_new
+    phi = phi / ((nu_sigma_f * phi / k).sum() * h)
+    return k, xe, phi
+
+
 # ---------------------------------------------------------------------------
 # Pure-Python tracer (bit-level brute force on tiny inputs)
 # ---------------------------------------------------------------------------

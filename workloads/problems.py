@@ -315,6 +315,17 @@ def reflective_box(sigma_t, sigma_s, speed, size=(2.0, 2.0, 2.0),
                         np.zeros((1, 1, 1)), [REFLECTIVE] * 6, src, tally, fission=fission)
 
 
+def bare_slab_eigen(thickness=6.0, sigma_s=0.6, sigma_f=0.2, nu=2.5, n_bins=24):
+    """One-group bare slab for the k-eigenvalue power iteration: Sigma_t = 1,
+    scattering sigma_s, fission sigma_f with nu neutrons (the rest
+    capture), vacuum faces, steady state; the first cycle starts from an
+    isotropic plane source at the centre; flux tally in n_bins x-bins."""
+    p = slab(thickness=thickness, sigma_t=1.0, sigma_s=sigma_s, n_bins=n_bins, source="plane",
+             x_src=0.5 * thickness)
+    p["fission"] = {"sigma_f": np.array([[sigma_f]]), "nu": np.array([[nu]]), "chi": np.array([[1.0]])}
+    return p
+
+
 def azurv1_supercritical(c_scatter=0.5, sigma_f=0.25, nu=2.4, n_bins=42, n_time_bins=20,
                          t_end=20.0, n_batches=32):
     """AZURV1-like supercritical pulse (Section 3 adds fission to reach
