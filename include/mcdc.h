@@ -246,6 +246,8 @@ typedef struct {
  *  n_splits                    weight-window split progeny created.
  *  n_fission                   fission neutrons beyond the colliding one
  *                              (problems with fission data).
+ *  k_mean, k_std               mcdc_run_eigenvalue: k over the active cycles
+ *                              and its standard error (else untouched).
  *  kernel_ms                   device time of the run (HIP events).
  */
 typedef struct {
@@ -266,6 +268,8 @@ typedef struct {
     double *tc_mean;
     double *tc_var;
     uint64_t n_fission;
+    double k_mean;
+    double k_std;
 } mcdc_result;
 
 /*
@@ -324,6 +328,32 @@ int mcdc_run(mcdc_problem *p, uint64_t n_histories, uint64_t seed,
  */
 int mcdc_run_batched(mcdc_problem *const *ps, int32_t n, const uint64_t *n_hist, const uint64_t *seeds,
                      const mcdc_run_options *opt, mcdc_result *outs);
+
+/*
+ * k-eigenvalue power iteration (Section 3 solves its C5G7 pin-cell and
+ * core problems as k-eigenvalue cycles; the cycle scheme here is this
+ * library's): n_inactive + n_active cycles of n_per_cycle particles on a
+ * steady-state problem (time edges [T0, +inf)) with fission data.  Cycle c
+ * uses the stream SplitMix64(seed ^ c) (63 bits); particle q starts at it
+ * skipped (q + 1) strides.  Cycle 0 starts from the problem's source.  In
+ * a cycle a fission ends the particle and banks floor(nu + xi) sites at
+ * the collision point; the cycle's M sites, ordered by (particle, site),
+ * give the next cycle's sources by a comb: particle q starts at site
+ * floor((q + u) M / n_per_cycle) with u the first draw of the cycle's
+ * stream, taking its group from the site material's spectrum, an
+ * isotropic direction and an optical depth.  k of a cycle = M / n_per_cycle.
+ * Outputs: out->mean/var/raw and leak_mean/leak_var over the active cycles
+ * (one batch per cycle; per cycle-source particle), event and termination
+ * totals over all cycles, out->k_mean and out->k_std (standard error over
+ * the active cycles), and k of every cycle in the host array
+ * k_cycle[n_inactive + n_active] (or NULL).  n_per_cycle in [1, 2^30],
+ * n_active in [1, 1023].  Errors: MCDC_E_INVALID for a problem without
+ * fission or not steady state, or a cycle that banks no site;
+ * MCDC_E_UNSUPPORTED with weight windows, a detector, debug or profile
+ * arrays.  opt->algorithm is not used (one thread per particle).
+ */
+int mcdc_run_eigenvalue(mcdc_problem *p, uint64_t n_per_cycle, int32_t n_inactive, int32_t n_active,
+                        uint64_t seed, const mcdc_run_options *opt, mcdc_result *out, double *k_cycle);
 
 /*
  * Set weight-window centres for later runs.  The paper runs analog only

@@ -7,4 +7,4 @@ device memory and the stream, and nothing else.
 """
 from ._binding import (MCDCError, MLP, Problem, lib, mcdc_mlp_create,  # noqa: F401
                        mcdc_problem_create, mcdc_problem_destroy, mcdc_problem_tally_shape,
-                       mcdc_run, mcdc_run_batched, mcdc_set_weight_windows)
+                       mcdc_run, mcdc_run_batched, mcdc_run_eigenvalue, mcdc_set_weight_windows)

@@ -23,7 +23,7 @@ MCDC_SRC_ISOTROPIC, MCDC_SRC_SURFACE = 0, 1
 MU_LAWS = {"beam": 0, "uniform": 1, "cosine": 2}
 
 EXPORTS = ["mcdc_problem_create", "mcdc_problem_destroy", "mcdc_problem_tally_shape",
-           "mcdc_run", "mcdc_run_batched", "mcdc_set_weight_windows", "mcdc_last_error", "mcdc_mlp_create",
+           "mcdc_run", "mcdc_run_batched", "mcdc_run_eigenvalue", "mcdc_set_weight_windows", "mcdc_last_error", "mcdc_mlp_create",
            "mcdc_mlp_destroy", "mcdc_mlp_get_params", "mcdc_mlp_set_params", "mcdc_mlp_grad",
            "mcdc_mlp_train", "mcdc_mlp_infer"]
 
@@ -76,6 +76,7 @@ class mcdc_result(C.Structure):
         ("kernel_ms", C.c_double),
         ("tc_mean", C.c_void_p), ("tc_var", C.c_void_p),
         ("n_fission", C.c_uint64),
+        ("k_mean", C.c_double), ("k_std", C.c_double),
     ]
 
 
@@ -449,3 +450,43 @@ def mcdc_run_batched(problems, n_hist, seeds, block_size: int = 0, outputs=("mea
         o["qoi_var"] = r.qoi_var
         o["kernel_ms"] = r.kernel_ms
     return outs
+
+
+def mcdc_run_eigenvalue(p: Problem, n_per_cycle: int, n_inactive: int, n_active: int, seed: int,
+                        outputs=("mean", "var", "leak_mean", "leak_var")):
+    """k-eigenvalue power iteration on the GPU.  Returns a dict like
+    mcdc_run (flux and leakage over the active cycles, totals over all
+    cycles) plus 'k' (every cycle), 'k_mean' and 'k_std'."""
+    import torch
+
+    L = lib()
+    if not getattr(L, "_eigen_ready", False):
+        L.mcdc_run_eigenvalue.argtypes = [C.c_void_p, C.c_uint64, C.c_int32, C.c_int32, C.c_uint64,
+                                          C.POINTER(mcdc_run_options), C.POINTER(mcdc_result), _DP]
+        L.mcdc_run_eigenvalue.restype = C.c_int
+        L._eigen_ready = True
+    dev = torch.device("cuda", torch.cuda.current_device())
+    res = mcdc_result()
+    out = {}
+    for name in ("mean", "var", "raw"):
+        if name in outputs:
+            t = torch.empty(p.tally_shape, dtype=torch.float64, device=dev)
+            out[name] = t
+            setattr(res, name, t.data_ptr())
+    for name in ("leak_mean", "leak_var"):
+        if name in outputs:
+            t = torch.empty(p.leak_shape, dtype=torch.float64, device=dev)
+            out[name] = t
+            setattr(res, name, t.data_ptr())
+    opt = mcdc_run_options()
+    opt.stream = torch.cuda.current_stream(dev).cuda_stream
+    k = np.zeros(n_inactive + n_active)
+    _check(L.mcdc_run_eigenvalue(p.handle, int(n_per_cycle), int(n_inactive), int(n_active), int(seed),
+                                 C.byref(opt), C.byref(res), _dp(k)))
+    out["events"] = np.array(res.n_events[:], dtype=np.uint64)
+    out["terms"] = np.array(res.n_term[:], dtype=np.uint64)
+    out["k"] = k
+    out["k_mean"] = res.k_mean
+    out["k_std"] = res.k_std
+    out["kernel_ms"] = res.kernel_ms
+    return out

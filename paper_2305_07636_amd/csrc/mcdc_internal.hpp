@@ -226,6 +226,12 @@ int launch_qoi_reduce(const double *qoi_hist, uint64_t n, double *qoi_sums, hipS
 // seg_len slots, and the run itself (items hold each problem's DevProblem
 // and prepared RunArgs; the launcher fills their table layouts).
 size_t event_batched_bytes(const uint64_t *n_hist, int n, unsigned int seg_len);
+// k-eigenvalue cycles (k_eigen.hip): device memory for N particles per
+// cycle, and the cycle loop (M of every cycle into m_dev[cycles]; *no_sites
+// set if a cycle banked no site).
+size_t eigen_bytes(uint64_t N);
+int launch_eigen(const DevProblem &P, const RunArgs &R, uint64_t N, int n_inactive, int n_active, uint64_t seed,
+                 void *mem, uint64_t *m_dev, int *no_sites, hipStream_t st);
 int launch_event_batched(std::vector<BatchItem> &items, const uint64_t *n_hist, unsigned int seg_len, void *mem,
                          size_t mem_bytes, hipStream_t st);
 

@@ -100,9 +100,11 @@ int check_options(const mcdc_run_options &opt) {
 }
 
 // Allocate and clear the per-run device buffers of a problem; fill R.
-int prepare(mcdc_problem *p, uint64_t N, uint64_t seed, const mcdc_run_options &opt, hipStream_t st, RunArgs &R) {
+// (B_force > 0: that many batches instead of the problem's.)
+int prepare(mcdc_problem *p, uint64_t N, uint64_t seed, const mcdc_run_options &opt, hipStream_t st, RunArgs &R,
+            int B_force = 0) {
     const DevProblem &P = p->d;
-    const int B = (int)((uint64_t)p->h.B < N ? (uint64_t)p->h.B : N);
+    const int B = B_force > 0 ? B_force : (int)((uint64_t)p->h.B < N ? (uint64_t)p->h.B : N);
     // tally copies per batch: up to 32 while the copies stay within 64 MB
     // (the event form adds a step's scores from its LDS slice once per
     // workgroup when the slice fits, and needs no copies then)
@@ -526,4 +528,73 @@ extern "C" int mcdc_run_batched(mcdc_problem *const *ps, int32_t n, const uint64
     }
     if ((rc = run_once(t.block, t.per_thread, &ms))) return rc;
     return finish_batched(ps, n, n_hist, items, outs, ms, st);
+}
+
+// ---------------------------------------------------------------------------
+// k-eigenvalue power iteration
+// ---------------------------------------------------------------------------
+extern "C" int mcdc_run_eigenvalue(mcdc_problem *p, uint64_t n_per_cycle, int32_t n_inactive, int32_t n_active,
+                                   uint64_t seed, const mcdc_run_options *opt_in, mcdc_result *out,
+                                   double *k_cycle) {
+    if (!p) return bad("problem is NULL");
+    if (!out) return bad("result is NULL");
+    if (n_per_cycle == 0 || n_per_cycle > (1ULL << 30)) return bad("n_per_cycle must be in [1, 2^30]");
+    if (n_inactive < 0 || n_active < 1 || n_active > 1023 || n_inactive > 100000)
+        return bad("n_inactive must be >= 0 and n_active in [1, 1023]");
+    mcdc_run_options opt{};
+    if (opt_in) opt = *opt_in;
+    int rc = check_options(opt);
+    if (rc) return rc;
+    const DevProblem &P = p->d;
+    if (!P.fission_on) return bad("the eigenvalue problem needs fission data");
+    if (P.K != 1 || std::isfinite(p->h.T[1])) return bad("the eigenvalue problem is steady state: time edges [T0, inf)");
+    if (P.ww_center || P.qoi_on || opt.debug_counts || opt.debug_scores || opt.profile) {
+        set_error("eigenvalue runs take no weight windows, detector, debug or profile arrays");
+        return MCDC_E_UNSUPPORTED;
+    }
+    HIP_CHECK(hipSetDevice(p->device), "hipSetDevice");
+    hipStream_t st = (hipStream_t)opt.stream;
+    Events ev;
+    HIP_CHECK(hipEventCreate(&ev.a), "hipEventCreate");
+    HIP_CHECK(hipEventCreate(&ev.b), "hipEventCreate");
+    HIP_CHECK(hipEventRecord(ev.a, st), "hipEventRecord");
+    // the active cycles are the batches: N per batch in order
+    const uint64_t n_tally = n_per_cycle * (uint64_t)n_active;
+    RunArgs R;
+    if ((rc = prepare(p, n_tally, seed, opt, st, R, n_active))) return rc;
+    const int C = n_inactive + n_active;
+    const size_t mb = eigen_bytes(n_per_cycle);
+    if ((rc = ensure(p->work, mb + (size_t)C * sizeof(uint64_t) + 256))) return rc;
+    uint64_t *m_dev = (uint64_t *)((char *)p->work.p + mb);
+    int *no_sites = R.overflow;
+    if ((rc = launch_eigen(P, R, n_per_cycle, n_inactive, n_active, seed, p->work.p, m_dev, no_sites, st))) return rc;
+    Profiler none;
+    if ((rc = fold(p, R, out, st, none))) return rc;
+    HIP_CHECK(hipEventRecord(ev.b, st), "hipEventRecord");
+    Collect c{};
+    if ((rc = collect_begin(p, out, c, st))) return rc;
+    std::vector<uint64_t> m(C);
+    HIP_CHECK(hipMemcpyAsync(m.data(), m_dev, C * sizeof(uint64_t), hipMemcpyDeviceToHost, st), "copy sites");
+    HIP_CHECK(hipStreamSynchronize(st), "hipStreamSynchronize");
+    if (c.ovf) {
+        set_error("a cycle banked no fission site");
+        return MCDC_E_INVALID;
+    }
+    float ms = 0.f;
+    HIP_CHECK(hipEventElapsedTime(&ms, ev.a, ev.b), "hipEventElapsedTime");
+    if ((rc = collect_end(p, n_tally, c, out, ms))) return rc;
+    double sum = 0.0;
+    for (int j = 0; j < C; ++j) {
+        const double k = (double)m[j] / (double)n_per_cycle;
+        if (k_cycle) k_cycle[j] = k;
+        if (j >= n_inactive) sum += k;
+    }
+    out->k_mean = sum / n_active;
+    double acc = 0.0;
+    for (int j = n_inactive; j < C; ++j) {
+        const double d = (double)m[j] / (double)n_per_cycle - out->k_mean;
+        acc += d * d;
+    }
+    out->k_std = n_active > 1 ? std::sqrt(acc / ((double)(n_active - 1) * n_active)) : 0.0;
+    return MCDC_OK;
 }

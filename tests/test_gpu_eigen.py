@@ -1,0 +1,110 @@
+"""GPU parity of the k-eigenvalue power iteration against the oracle: k of
+every cycle bit-exact (an integer count of sites over N), event and
+termination totals bit-exact, flux and leakage over the active cycles to
+the tolerances of gpu_common; at 1e6 particles per cycle, k and flux of a
+multiplying infinite medium against the closed form."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as w
+from gpu_common import VAR_RTOL, close
+from refs import removal_matrix
+
+MG_ST = [1.0, 1.5, 2.0]
+MG_SS = [[0.3, 0.4, 0.1], [0.0, 0.6, 0.5], [0.0, 0.2, 1.2]]
+MG_FIS = {"sigma_f": [[0.05, 0.1, 0.3]], "nu": [[2.6, 2.5, 2.43]], "chi": [[0.7, 0.3, 0.0]]}
+
+
+def fissile_lattice():
+    p = w.lattice(n=5, n_groups=3, gen_seed=31, n_time_bins=1, t_end=1.0, n_batches=8)
+    p["tally"]["time_edges"] = np.array([0.0, np.inf])
+    M, G = p["sigma_t"].shape
+    sf = np.zeros((M, G))
+    sf[0] = 0.7 * (p["sigma_t"][0] - p["sigma_s"][0].sum(axis=1))
+    p["fission"] = {"sigma_f": sf, "nu": np.full((M, G), 2.6), "chi": np.tile([0.8, 0.2, 0.0], (M, 1))}
+    return p
+
+
+CASES = {
+    "infinite_1g": (lambda: w.reflective_box([1.0], [[0.5]], [1.0],
+                                             fission={"sigma_f": [[0.2]], "nu": [[2.5]], "chi": [[1.0]]}),
+                    3001, 3, 6, 91),
+    "infinite_mg": (lambda: w.reflective_box(MG_ST, MG_SS, [3.0, 2.0, 1.0], size=(1.0, 1.0, 2.0),
+                                             fission=MG_FIS), 2503, 2, 5, 92),
+    "bare_slab": (lambda: w.bare_slab_eigen(), 4001, 4, 6, 93),
+    "fissile_lattice": (fissile_lattice, 2001, 3, 4, 94),
+}
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("case", list(CASES))
+def test_eigen_parity(case):
+    import paper_2305_07636_amd as m
+
+    make, N, ni, na, seed = CASES[case]
+    p = make()
+    print(f"[eigen] {case} N={N} cycles={ni}+{na}", flush=True)
+    h = m.mcdc_problem_create(p)
+    try:
+        g = m.mcdc_run_eigenvalue(h, N, ni, na, seed)
+        g = {k: (v.cpu().numpy() if hasattr(v, "cpu") else v) for k, v in g.items()}
+    finally:
+        h.close()
+    r = oracle.eigen(p, N, ni, na, seed)
+    e = oracle.eigen_estimates(p, r)
+    assert np.array_equal(g["k"], r["k"]), (g["k"], r["k"])
+    assert np.array_equal(g["events"], r["tot"][0:3]), (g["events"], r["tot"][0:3])
+    assert np.array_equal(g["terms"], r["tot"][3:8]), (g["terms"], r["tot"][3:8])
+    close(g["mean"], e["mean"], what="flux")
+    close(g["var"], e["var"], rtol=VAR_RTOL, what="flux var")
+    close(g["leak_mean"], e["leak_mean"], what="leak")
+    close(g["leak_var"], e["leak_var"], rtol=VAR_RTOL, what="leak var")
+    close([g["k_mean"], g["k_std"]], [e["k_mean"], e["k_std"]], rtol=1e-12, what="k statistics")
+
+
+@pytest.mark.gpu
+def test_eigen_rejects_bad_problems():
+    import paper_2305_07636_amd as m
+
+    for prob, code in ((w.cfg1_slab_steady(), -1), (w.cfg2_slab_pulse(), -1)):
+        h = m.mcdc_problem_create(prob)
+        try:
+            with pytest.raises(m.MCDCError) as ei:
+                m.mcdc_run_eigenvalue(h, 100, 1, 2, 1)
+            assert ei.value.code == code
+        finally:
+            h.close()
+    # a medium whose cycles bank no site: fission data with sigma_f = 0
+    p = w.reflective_box([1.0], [[0.5]], [1.0], fission={"sigma_f": [[0.0]], "nu": [[2.5]], "chi": [[1.0]]})
+    h = m.mcdc_problem_create(p)
+    try:
+        with pytest.raises(m.MCDCError) as ei:
+            m.mcdc_run_eigenvalue(h, 500, 1, 2, 1)
+        assert ei.value.code == -1 and "site" in str(ei.value)
+    finally:
+        h.close()
+
+
+@pytest.mark.gpu
+def test_eigen_large_infinite_medium_closed_form():
+    """1e6 particles per cycle, 5 + 40 cycles: k = (nu Sigma_f)^T M^-1 chi and
+    flux M^-1 chi / V within 4.5 sigma."""
+    import paper_2305_07636_amd as m
+
+    p = w.reflective_box(MG_ST, MG_SS, [3.0, 2.0, 1.0], size=(1.0, 1.0, 2.0), fission=MG_FIS)
+    h = m.mcdc_problem_create(p)
+    try:
+        print("[eigen] 1e6 per cycle", flush=True)
+        g = m.mcdc_run_eigenvalue(h, 1_000_000, 5, 40, 95)
+        mean = g["mean"].cpu().numpy().ravel()
+        var = g["var"].cpu().numpy().ravel()
+    finally:
+        h.close()
+    chi = np.array(MG_FIS["chi"][0])
+    nsf = np.array(MG_FIS["nu"][0]) * np.array(MG_FIS["sigma_f"][0])
+    Minv_chi = np.linalg.solve(removal_matrix(MG_ST, MG_SS), chi)
+    k_exact = float(nsf @ Minv_chi)
+    assert abs(g["k_mean"] - k_exact) <= 4.5 * g["k_std"], (g["k_mean"], k_exact, g["k_std"])
+    assert (np.abs(mean - Minv_chi / 2.0) <= 4.5 * np.sqrt(var)).all()
+    assert g["k_std"] < 3e-4
