@@ -181,6 +181,31 @@ def fission_section(m, w, n, steps):
     return res
 
 
+def eigen_section(m, w, n_per_cycle, n_inactive, n_active):
+    """k-eigenvalue power iteration on the box pin cell (7 groups, fuel in
+    moderator, reflected), with the cycle counts of Section 3's pin-cell
+    test by default (50 inactive + 100 active cycles of 1e5)."""
+    import torch
+
+    prob = w.pin_cell_eigen()
+    h = m.mcdc_problem_create(prob)
+    try:
+        m.mcdc_run_eigenvalue(h, n_per_cycle, 2, 2, 90)     # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = m.mcdc_run_eigenvalue(h, n_per_cycle, n_inactive, n_active, 91)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+    finally:
+        h.close()
+    n = n_per_cycle * (n_inactive + n_active)
+    log(f"eigenvalue: {dt:.3f} s for {n:.2e} histories, k = {out['k_mean']:.5f} +- {out['k_std']:.5f}")
+    return {"workload": f"box pin cell (7 groups, fuel square in moderator, reflective), {n_per_cycle:.0e} "
+                        f"per cycle, {n_inactive} inactive + {n_active} active cycles",
+            "seconds": dt, "histories_per_s": n / dt, "events_per_s": float(sum(out["events"])) / dt,
+            "k_mean": out["k_mean"], "k_std": out["k_std"]}
+
+
 def fom_section(w, n_pilot, n_analog, n_ww, steps):
     """Dog-leg duct, detector behind the second bend: analog against learned
     weight windows (pilots, network fit, BF16 inference) and against windows
@@ -229,6 +254,8 @@ def main():
     ap.add_argument("--no-fom", action="store_true")
     ap.add_argument("--no-time-crossing", action="store_true")
     ap.add_argument("--no-fission", action="store_true")
+    ap.add_argument("--no-eigen", action="store_true")
+    ap.add_argument("--eigen-per-cycle", type=float, default=1e5)
     ap.add_argument("--fission-histories", type=float, default=1e6)
     ap.add_argument("--fom-pilot", type=float, default=1e8)
     ap.add_argument("--fom-analog", type=float, default=4e9)
@@ -356,6 +383,8 @@ def main():
     p.close()
     if not args.no_fission:
         extra["fission"] = fission_section(m, w, int(args.fission_histories), args.steps)
+    if not args.no_eigen:
+        extra["eigenvalue"] = eigen_section(m, w, int(args.eigen_per_cycle), 50, 100)
     if not args.no_batched:
         extra["batched"] = batched_section(m, w)
     if not args.no_fom:

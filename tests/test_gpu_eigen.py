@@ -34,6 +34,7 @@ CASES = {
                                              fission=MG_FIS), 2503, 2, 5, 92),
     "bare_slab": (lambda: w.bare_slab_eigen(), 4001, 4, 6, 93),
     "fissile_lattice": (fissile_lattice, 2001, 3, 4, 94),
+    "pin_cell": (lambda: w.pin_cell_eigen(), 3001, 3, 5, 96),
 }
 
 

@@ -315,6 +315,41 @@ def reflective_box(sigma_t, sigma_s, speed, size=(2.0, 2.0, 2.0),
                         np.zeros((1, 1, 1)), [REFLECTIVE] * 6, src, tally, fission=fission)
 
 
+def pin_cell_eigen(n_groups=7, gen_seed=9, fine=3):
+    """Box stand-in for a reflected pin cell (Section 3's k-eigenvalue
+    performance test uses a C5G7 pin cell, whose data is not used here): a
+    1.26-wide square cell, infinite in z, reflective on every side, with a
+    0.84-wide square fuel region in the middle and moderator around it.
+    Synthetic 7-group cross sections: fuel absorbs more and fissions in all
+    groups (80 % of its absorption; nu = 2.45, chi in the two fastest
+    groups), the moderator
+    scatters more.  The first cycle starts from a uniform source in the
+    fuel in group 0.  Flux tally on a (3 fine) x (3 fine) mesh."""
+    rng = SplitMix64(gen_seed)
+    G = n_groups
+    st = np.zeros((2, G))
+    ss = np.zeros((2, G, G))
+    for m in range(2):
+        st[m], ss[m] = synthetic_xs(rng, G)
+    ss[1] = ss[1] * np.minimum(1.0, 0.95 * st[1][:, None] / np.maximum(ss[1].sum(axis=1, keepdims=True), 1e-300))
+    sf = 0.8 * (st[0] - ss[0].sum(axis=1))      # 80 % of the fuel's absorption fissions
+    chi = np.zeros(G)
+    chi[0], chi[1] = 0.7, 0.3
+    planes = [np.array([0.0, 0.21, 1.05, 1.26])] * 2 + [_empty()]
+    mat = np.ones((1, 3, 3), dtype=np.int32)
+    mat[0, 1, 1] = 0
+    pmf = np.zeros(G)
+    pmf[0] = 1.0
+    src = {"kind": "isotropic", "lo": [0.21, 0.21, 0.0], "hi": [1.05, 1.05, 0.0], "group_pmf": pmf}
+    mesh = np.concatenate([np.linspace(0.0, 0.21, fine + 1)[:-1], np.linspace(0.21, 1.05, fine + 1)[:-1],
+                           np.linspace(1.05, 1.26, fine + 1)])
+    tally = {"mesh": [mesh, mesh, _empty()], "time_edges": [0.0, math.inf], "n_batches": 8}
+    return make_problem(st, ss, [float(G - g) for g in range(G)], planes, mat,
+                        [REFLECTIVE] * 4 + [VACUUM, VACUUM], src, tally,
+                        fission={"sigma_f": np.stack([sf, np.zeros(G)]), "nu": np.full((2, G), 2.45),
+                                 "chi": np.stack([chi, chi])})
+
+
 def bare_slab_eigen(thickness=6.0, sigma_s=0.6, sigma_f=0.2, nu=2.5, n_bins=24):
     """One-group bare slab for the k-eigenvalue power iteration: Sigma_t = 1,
     scattering sigma_s, fission sigma_f with nu neutrons (the rest
