@@ -14,10 +14,6 @@ namespace {
 
 using namespace dev;
 
-struct BlockCounters {
-    unsigned int c[kCounters];
-};
-
 struct Acc {
     unsigned int n_ev[3] = {0u, 0u, 0u};
     unsigned int term_mask = 0u;
@@ -280,43 +276,104 @@ __global__ void __launch_bounds__(256) k_history(DevProblem P0, RunArgs R, uint6
     if (R.prof && threadIdx.x == 0) atomicAdd(R.prof + 2 * MCDC_PROF_HISTORY, red[kCounters]);
 }
 
-// One generation of split progeny: each thread tracks one child to death
-// and adds its records to its history with atomics.
-template <int FM>
-__global__ void __launch_bounds__(256) k_history_children(DevProblem P, RunArgs R, SplitBank in, unsigned int n,
-                                                          uint64_t chunk_first, SplitBank out) {
-    __shared__ BlockCounters bc;
-    if (threadIdx.x < kCounters) bc.c[threadIdx.x] = 0u;
-    __syncthreads();
-    const unsigned int r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r < n) {
-        Particle p;
-        int b;
-        uint64_t i;
-        split_load(in, r, p, b, i);
-        set_inverse<FM>(P, p);
-        Acc acc;
-        atomicAdd(&bc.c[3 + track<FM, true>(P, R, p, b, i, acc, out)], 1u);
-        if (R.dbg_counts) {
-            uint32_t *d = R.dbg_counts + i * 5;
-            for (int e = 0; e < 3; ++e)
-                if (acc.n_ev[e]) atomicAdd(d + e, acc.n_ev[e]);
-            if (acc.spawned + acc.fissioned) atomicAdd(d + 3, acc.spawned + acc.fissioned);
-            atomicOr(d + 4, acc.term_mask);
-        }
-        if (R.dbg_scores) {
-            if (acc.track != 0.0) atomic_add_f64(R.dbg_scores + i * 2, acc.track);
-            if (acc.qoi != 0.0) atomic_add_f64(R.dbg_scores + i * 2 + 1, acc.qoi);
-        }
-        if (P.qoi_on && acc.qoi != 0.0) atomic_add_f64(R.qoi_hist + (i - chunk_first), acc.qoi);
+// A progeny particle of history i has ended: its records go to the history
+// with atomics (a history's progeny may run on any lane of any launch).
+__device__ __forceinline__ void child_done(const DevProblem &P, const RunArgs &R, const Acc &acc, int code,
+                                           uint64_t i, uint64_t chunk_first, LaneTotals &lt) {
+    lt.term(code);
+    if (R.dbg_counts) {
+        uint32_t *d = R.dbg_counts + i * 5;
         for (int e = 0; e < 3; ++e)
-            if (acc.n_ev[e]) atomicAdd(&bc.c[e], acc.n_ev[e]);
-        if (acc.spawned) atomicAdd(&bc.c[8], acc.spawned);
-        if (acc.fissioned) atomicAdd(&bc.c[9], acc.fissioned);
+            if (acc.n_ev[e]) atomicAdd(d + e, acc.n_ev[e]);
+        if (acc.spawned + acc.fissioned) atomicAdd(d + 3, acc.spawned + acc.fissioned);
+        atomicOr(d + 4, acc.term_mask);
+    }
+    if (R.dbg_scores) {
+        if (acc.track != 0.0) atomic_add_f64(R.dbg_scores + i * 2, acc.track);
+        if (acc.qoi != 0.0) atomic_add_f64(R.dbg_scores + i * 2 + 1, acc.qoi);
+    }
+    if (P.qoi_on && acc.qoi != 0.0) atomic_add_f64(R.qoi_hist + (i - chunk_first), acc.qoi);
+    lt.c[0] += acc.n_ev[0];
+    lt.c[1] += acc.n_ev[1];
+    lt.c[2] += acc.n_ev[2];
+    lt.c[8] += acc.spawned;
+    lt.c[9] += acc.fissioned;
+}
+
+// One generation of progeny (window splits, fission neutrons), persistent
+// like k_history: waves take chunks of the generation's entries [0, n) from
+// a device counter, and a lane whose particle has ended loads the next entry
+// of the wave's chunk once enough lanes are idle, so a wave is not held back
+// by its longest-lived particle.  Their own progeny go to the next
+// generation's bank.  (LT: flight tables in LDS.)
+template <int FM, bool LT>
+__global__ void __launch_bounds__(256) k_history_children(DevProblem P0, RunArgs R, SplitBank in,
+                                                          unsigned long long n, uint64_t chunk_first, SplitBank out,
+                                                          unsigned long long *next, unsigned int wave_chunk,
+                                                          LdsTables tabs) {
+    __shared__ unsigned long long red[kCounters];
+    extern __shared__ double lds_tables[];
+    if (threadIdx.x < kCounters) red[threadIdx.x] = 0ull;
+    const DevProblem P = stage_tables<LT, 256>(P0, tabs, reinterpret_cast<char *>(lds_tables));
+    __syncthreads();
+
+    uint64_t c_pos = 0, c_end = 0;   // the wave's current chunk (wave-uniform)
+    bool drained = false;
+    LaneTotals tot;
+    tot.init();
+    Particle p;
+    Acc acc;
+    int b = 0, cell = 0, since = 0;
+    uint64_t i = 0;
+    bool busy = false;
+    for (;;) {
+        uint64_t need = __ballot(!busy);
+        if (__popcll(need) < kRefillMin && need != ~0ull) need = 0;
+        while (need && !drained) {
+            if (c_pos == c_end) {
+                unsigned long long base = 0;
+                if (__lane_id() == 0) base = atomicAdd(next, (unsigned long long)wave_chunk);
+                base = __shfl(base, 0);
+                if (base >= n) {
+                    drained = true;
+                    break;
+                }
+                c_pos = base;
+                c_end = (base + wave_chunk < n) ? base + wave_chunk : n;
+            }
+            const uint64_t avail = c_end - c_pos;
+            const uint32_t rank =
+                __builtin_amdgcn_mbcnt_hi((uint32_t)(need >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)need, 0u));
+            const uint32_t n_need = (uint32_t)__popcll(need);
+            if (!busy && rank < avail) {
+                split_load(in, (unsigned int)(c_pos + rank), p, b, i);
+                set_inverse<FM>(P, p);
+                cell = cell_index(P, p.ix);
+                since = 0;
+                acc = Acc();
+                busy = true;
+            }
+            c_pos += (n_need < avail) ? n_need : avail;
+            need = __ballot(!busy);
+        }
+        if (!__any(busy)) break;
+        if (busy) {
+            const int code = hstep<FM, true>(P, R, p, cell, b, i, acc, out, since);
+            if (code >= 0) {
+                acc.term_mask |= 1u << code;
+                child_done(P, R, acc, code, i, chunk_first, tot);
+                busy = false;
+            }
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < kCounters; ++j) {
+        unsigned int v = tot.c[j];
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+        if (__lane_id() == 0 && v) atomicAdd(&red[j], (unsigned long long)v);
     }
     __syncthreads();
-    if (threadIdx.x < kCounters && bc.c[threadIdx.x])
-        atomicAdd(R.counters + threadIdx.x, (unsigned long long)bc.c[threadIdx.x]);
+    if (threadIdx.x < kCounters && red[threadIdx.x]) atomicAdd(R.counters + threadIdx.x, red[threadIdx.x]);
 }
 
 __global__ void k_zero_count(unsigned long long *c) { *c = 0ull; }
@@ -383,8 +440,22 @@ int launch_main(mcdc_problem *pb, const DevProblem &P, const RunArgs &R, uint64_
 // Split progeny of one chunk, generation by generation, until none are left
 // (the count of each generation is read back to size the next launch).
 template <int FM>
-int run_generations(const DevProblem &P, const RunArgs &R, SplitBank SB[2], uint64_t cfirst, hipStream_t st,
+int run_generations(mcdc_problem *pb, const RunArgs &R, SplitBank SB[2], uint64_t cfirst, hipStream_t st,
                     Profiler &prof) {
+    const DevProblem &P = pb->d;
+    // the persistent children kernel: its launch shape and staged tables
+    unsigned long long *next = (unsigned long long *)pb->counters_split.p + 2;
+    const int bs = 256;
+    LdsTables tabs{};
+    const bool lt = table_layout(P, tabs, kHistoryTablesMax);
+    const size_t shmem = lt ? (size_t)tabs.bytes : 0;
+    int per_cu = 0, n_cu = 0;
+    hipError_t e0 = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &per_cu, lt ? reinterpret_cast<const void *>(&k_history_children<FM, true>)
+                    : reinterpret_cast<const void *>(&k_history_children<FM, false>), bs, shmem);
+    if (e0 == hipSuccess) e0 = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, pb->device);
+    if (e0 != hipSuccess) return hip_fail(e0, "occupancy query");
+    const uint64_t grid_max = (uint64_t)(per_cu > 0 ? per_cu : 1) * (uint64_t)(n_cu > 0 ? n_cu : 1);
     for (int gen = 0;; ++gen) {
         unsigned long long n_in = 0;
         hipError_t e = hipMemcpyAsync(&n_in, SB[gen & 1].count, sizeof(n_in), hipMemcpyDeviceToHost, st);
@@ -398,8 +469,18 @@ int run_generations(const DevProblem &P, const RunArgs &R, SplitBank SB[2], uint
         }
         const SplitBank &in = SB[gen & 1], &out = SB[(gen + 1) & 1];
         hipLaunchKernelGGL(k_zero_count, dim3(1), dim3(1), 0, st, out.count);
-        launch_timed(prof, MCDC_PROF_HISTORY, k_history_children<FM>, dim3((n_in + 255) / 256), dim3(256), 0u, st,
-                     P, R, in, n_in, cfirst, out);
+        hipLaunchKernelGGL(k_zero_count, dim3(1), dim3(1), 0, st, next);
+        // entries per wave take: about 16 takes per wave, 64..65536
+        uint64_t wc = n_in / (grid_max * (bs / 64) * 16);
+        wc = (wc < 64) ? 64 : (wc > 65536 ? 65536 : (wc + 63) & ~63ull);
+        uint64_t grid = ((n_in + wc - 1) / wc + bs / 64 - 1) / (bs / 64);
+        if (grid > grid_max) grid = grid_max;
+        if (lt)
+            launch_timed(prof, MCDC_PROF_HISTORY, k_history_children<FM, true>, dim3((unsigned)grid), dim3(bs),
+                         (uint32_t)shmem, st, P, R, in, n_in, cfirst, out, next, (unsigned int)wc, tabs);
+        else
+            launch_timed(prof, MCDC_PROF_HISTORY, k_history_children<FM, false>, dim3((unsigned)grid), dim3(bs), 0u,
+                         st, P, R, in, n_in, cfirst, out, next, (unsigned int)wc, tabs);
         e = hipGetLastError();
         if (e != hipSuccess) return hip_fail(e, "history children launch");
     }
@@ -434,7 +515,7 @@ int run_history(mcdc_problem *pb, const RunArgs &R0, uint64_t first, uint64_t co
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return hip_fail(e, "history kernel launch");
         if (!ww) continue;
-        if ((rc = run_generations<FM>(P, R, SB, cfirst, st, prof))) return rc;
+        if ((rc = run_generations<FM>(pb, R, SB, cfirst, st, prof))) return rc;
         if (P.qoi_on && (rc = launch_qoi_reduce(R.qoi_hist, n, R.qoi_sums, st)))
             return hip_fail((hipError_t)rc, "detector reduce");
     }
@@ -557,7 +638,8 @@ int split_prepare(mcdc_problem *pb, uint64_t chunk, dev::SplitBank SB[2]) {
     const unsigned int cap = (unsigned int)((want < (1u << 22)) ? (1u << 22) : (want > (1u << 26) ? (1u << 26) : want));
     int rc;
     if ((rc = ensure(pb->split, 2 * split_bytes(cap) + 256))) return rc;
-    if ((rc = ensure(pb->counters_split, 2 * sizeof(unsigned long long)))) return rc;
+    // (two bank counters, then the children kernel's work counter)
+    if ((rc = ensure(pb->counters_split, 3 * sizeof(unsigned long long)))) return rc;
     unsigned long long *cnt = (unsigned long long *)pb->counters_split.p;
     SB[0] = carve_split(pb->split.p, cap, cnt);
     SB[1] = carve_split((char *)pb->split.p + split_bytes(cap), cap, cnt + 1);
@@ -571,9 +653,9 @@ void split_reset(const dev::SplitBank SB[2], hipStream_t st) {
 int split_generations(mcdc_problem *pb, const RunArgs &R, dev::SplitBank SB[2], uint64_t cfirst, hipStream_t st,
                       Profiler &prof) {
     const int fm = pb->d.finite_mask;
-    if (fm == 1) return run_generations<1>(pb->d, R, SB, cfirst, st, prof);
-    if (fm == 7) return run_generations<7>(pb->d, R, SB, cfirst, st, prof);
-    return run_generations<0>(pb->d, R, SB, cfirst, st, prof);
+    if (fm == 1) return run_generations<1>(pb, R, SB, cfirst, st, prof);
+    if (fm == 7) return run_generations<7>(pb, R, SB, cfirst, st, prof);
+    return run_generations<0>(pb, R, SB, cfirst, st, prof);
 }
 
 int launch_history(mcdc_problem *p, const RunArgs &R, uint64_t first, uint64_t count, int block, hipStream_t st,
