@@ -127,6 +127,13 @@ def batched_section(m, w):
             res[f"batched_{alg}_s"] = t_b
             res[f"batched_{alg}_histories_per_s"] = sum(nh) / t_b
             log(f"batched {alg} form: {t_b:.3f} s")
+        m.mcdc_run_batched(hs, nh, seeds, algorithm="auto")      # times both forms, caches the faster
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        m.mcdc_run_batched(hs, nh, seeds, algorithm="auto")
+        torch.cuda.synchronize()
+        res["batched_auto_s"] = time.perf_counter() - t0
+        log(f"batched auto form: {res['batched_auto_s']:.3f} s")
         for alg in ("event", "history"):
             m.mcdc_run(hs[0], nh[0], seeds[0], algorithm=alg)
             torch.cuda.synchronize()

@@ -59,6 +59,7 @@ extern "C" {
 /* tracking algorithms */
 #define MCDC_ALG_EVENT 0
 #define MCDC_ALG_HISTORY 1
+#define MCDC_ALG_AUTO 2   /* mcdc_run_batched only: the faster form, timed on the first call */
 
 typedef struct mcdc_problem mcdc_problem;
 
@@ -323,6 +324,9 @@ int mcdc_run(mcdc_problem *p, uint64_t n_histories, uint64_t seed,
  *    pulls chunks of histories from one device-wide counter over the
  *    concatenated history ranges; workgroup size and histories per pull are
  *    autotuned the same way (opt->block_size forces a workgroup size).
+ *  MCDC_ALG_AUTO: the first call for a batch signature runs both forms
+ *    (each tuned as above) and caches the one with the shorter run; later
+ *    calls run that form only.  outs hold the results of the last run.
  * Debug arrays, profiles and weight windows are not supported here
  * (MCDC_E_UNSUPPORTED).  All problems must live on the same device.
  */

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "libmcdc_hip.so")
 
 MCDC_ABI_VERSION = 2
 MCDC_OK, MCDC_E_INVALID, MCDC_E_HIP, MCDC_E_NOMEM, MCDC_E_OVERFLOW, MCDC_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5
-MCDC_ALG_EVENT, MCDC_ALG_HISTORY = 0, 1
+MCDC_ALG_EVENT, MCDC_ALG_HISTORY, MCDC_ALG_AUTO = 0, 1, 2
 MCDC_SRC_ISOTROPIC, MCDC_SRC_SURFACE = 0, 1
 MU_LAWS = {"beam": 0, "uniform": 1, "cosine": 2}
 
@@ -404,8 +404,9 @@ def mcdc_mlp_create(seed: int = 1) -> MLP:
 def mcdc_run_batched(problems, n_hist, seeds, block_size: int = 0, outputs=("mean", "var"),
                      algorithm: str = "event", seg_len: int = 0):
     """Run many problems together: event form (shared banks, one graph per
-    census step for all problems) or history form (one persistent launch).
-    Returns one result dict per problem, like mcdc_run."""
+    census step for all problems), history form (one persistent launch) or
+    "auto" (both timed on the first call for a batch signature, the faster
+    one cached).  Returns one result dict per problem, like mcdc_run."""
     import torch
 
     L = lib()
@@ -436,7 +437,7 @@ def mcdc_run_batched(problems, n_hist, seeds, block_size: int = 0, outputs=("mea
                 setattr(res[j], name, t.data_ptr())
         outs.append(o)
     opt = mcdc_run_options()
-    opt.algorithm = MCDC_ALG_HISTORY if algorithm == "history" else MCDC_ALG_EVENT
+    opt.algorithm = {"history": MCDC_ALG_HISTORY, "auto": MCDC_ALG_AUTO}.get(algorithm, MCDC_ALG_EVENT)
     opt.block_size = block_size
     opt.bank_capacity = seg_len
     opt.stream = torch.cuda.current_stream(dev).cuda_stream

@@ -428,6 +428,27 @@ extern "C" int mcdc_run_batched(mcdc_problem *const *ps, int32_t n, const uint64
     if (!ps || !n_hist || !seeds || !outs || n <= 0) return bad("NULL argument or n <= 0");
     mcdc_run_options opt{};
     if (opt_in) opt = *opt_in;
+    if (opt.algorithm == MCDC_ALG_AUTO) {
+        // the faster form for this batch signature, timed once and cached
+        static std::map<std::string, int> form_cache;
+        for (int j = 0; j < n; ++j)
+            if (!ps[j]) return bad("NULL problem in batch");
+        const std::string sig = signature(ps, n, n_hist);
+        auto it = form_cache.find(sig);
+        mcdc_run_options o = opt;
+        if (it != form_cache.end()) {
+            o.algorithm = it->second;
+            return mcdc_run_batched(ps, n, n_hist, seeds, &o, outs);
+        }
+        o.algorithm = MCDC_ALG_EVENT;
+        int r = mcdc_run_batched(ps, n, n_hist, seeds, &o, outs);
+        if (r) return r;
+        const double t_event = outs[0].kernel_ms;
+        o.algorithm = MCDC_ALG_HISTORY;
+        if ((r = mcdc_run_batched(ps, n, n_hist, seeds, &o, outs))) return r;
+        form_cache[sig] = (outs[0].kernel_ms < t_event) ? MCDC_ALG_HISTORY : MCDC_ALG_EVENT;
+        return MCDC_OK;
+    }
     int rc = check_options(opt);
     if (rc) return rc;
     if (opt.debug_counts || opt.debug_scores || opt.profile) {

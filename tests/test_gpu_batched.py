@@ -98,3 +98,27 @@ def test_batched_launch_shape_does_not_change_counts(block):
     finally:
         for h in hs:
             h.close()
+
+
+@pytest.mark.gpu
+def test_batched_auto_form_choice():
+    """algorithm="auto": the first call runs both tuned forms and keeps the
+    faster; every call gives the separate runs' counts."""
+    import paper_2305_07636_amd as m
+
+    probs, nh = small_batch(8, 6000)
+    seeds = [300 + j for j in range(len(probs))]
+    hs = [m.mcdc_problem_create(p) for p in probs]
+    try:
+        print("[batched] auto", flush=True)
+        first = m.mcdc_run_batched(hs, nh, seeds, outputs=("mean",), algorithm="auto")
+        second = m.mcdc_run_batched(hs, nh, seeds, outputs=("mean",), algorithm="auto")
+        for j, h in enumerate(hs):
+            ref = m.mcdc_run(h, nh[j], seeds[j], algorithm="history", outputs=("mean",))
+            for o in (first[j], second[j]):
+                assert np.array_equal(o["events"], ref["events"])
+                assert np.array_equal(o["terms"], ref["terms"])
+                close(o["mean"].cpu().numpy(), ref["mean"].cpu().numpy())
+    finally:
+        for h in hs:
+            h.close()
