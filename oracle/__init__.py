@@ -61,6 +61,7 @@ class _Problem(C.Structure):
         ("ww_center", _DP), ("ww_ratio", C.c_double), ("ww_max_split", C.c_int32),
         ("time_crossing", C.c_int32),
         ("sigma_f", _DP), ("nu", _DP), ("chi", _DP),
+        ("implicit_capture", C.c_int32), ("roulette_w", C.c_double), ("roulette_ws", C.c_double),
     ]
 
 
@@ -168,6 +169,11 @@ class OracleProblem:
             s.sigma_f = _dp(arr(fis["sigma_f"]))
             s.nu = _dp(arr(fis["nu"]))
             s.chi = _dp(arr(fis["chi"]))
+        ic = prob.get("implicit_capture")
+        if ic is not None:
+            s.implicit_capture = 1
+            s.roulette_w = float(ic["w_min"])
+            s.roulette_ws = float(ic["w_survive"])
         self.time_crossing = bool(s.time_crossing)
         self.struct = s
         self._keep = keep

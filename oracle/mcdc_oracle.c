@@ -76,6 +76,13 @@
  *       material, an isotropic direction and an optical depth.  k of a
  *       cycle is M / N.  Flux and leakage are tallied in the active cycles
  *       only, one batch per active cycle.
+ *   R14 Implicit capture (optional; Section 3 runs the time-dependent
+ *       dog-leg duct with it): a collision never absorbs; the weight is
+ *       multiplied by Sigma_s/Sigma_t.  If it falls below w_min a draw
+ *       decides a roulette: survive with probability w/w_s at weight w_s,
+ *       else the particle ends (rouletted).  Then the scatter draws as in
+ *       the analog game (group, direction, optical depth) and the window
+ *       check follows.  Not combined with fission; 0 < w_min <= w_s.
  *
  * Build: gcc -O2 -ffp-contract=off -fPIC -shared -o liboracle.so mcdc_oracle.c -lm
  */
@@ -125,6 +132,9 @@ typedef struct {
     const double *sigma_f;   /* [M][G] */
     const double *nu;        /* [M][G] mean neutrons per fission */
     const double *chi;       /* [M][G] fission spectrum (sums to 1 per material) */
+    /* implicit capture with weight roulette (R14) */
+    int32_t implicit_capture;
+    double roulette_w, roulette_ws;
 } oracle_problem;
 
 enum { EV_CENSUS = 0, EV_SURFACE = 1, EV_COLLISION = 2 };
@@ -629,9 +639,26 @@ static int step(ctx *C, particle *pt, int b, particle *stack, int *sp, hist_rec 
         h->n_coll++;
         C->tot[2]++;
         /* analog collision: scatter with probability Sigma_s,g / Sigma_t,g,
-         * fission with probability Sigma_f,g / Sigma_t,g (R12) */
-        double xr = rn(&pt->s);
-        if (!(xr < C->ps[m * G + pt->g])) {
+         * fission with probability Sigma_f,g / Sigma_t,g (R12); with implicit
+         * capture every collision scatters at reduced weight (R14) */
+        double xr = 0.0;
+        if (p->implicit_capture) {
+            pt->w = pt->w * C->ps[m * G + pt->g];
+            if (pt->w < p->roulette_w) {
+                double xw = rn(&pt->s);
+                if (xw < pt->w / p->roulette_ws) {
+                    pt->w = p->roulette_ws;
+                } else {
+                    terminate(C, h, T_ROULETTE);
+                    alive = 0;
+                }
+            }
+        } else {
+            xr = rn(&pt->s);
+        }
+        if (!alive) {
+            /* rouletted */
+        } else if (!p->implicit_capture && !(xr < C->ps[m * G + pt->g])) {
             if (C->pf && xr < C->pf[m * G + pt->g] && C->eigen) {
                 /* R13: bank the sites, end the particle */
                 C->site_n = (int)floor(p->nu[m * G + pt->g] + rn(&pt->s));
@@ -742,6 +769,9 @@ static int ctx_init(ctx *C, const oracle_problem *p)
     const int G = p->G, M = p->M;
     C->K = p->n_time_edges - 1;
     if (G < 1 || M < 1 || C->K < 1 || p->n_batches < 1) return -1;
+    if (p->implicit_capture &&
+        (p->sigma_f || !(p->roulette_w > 0.0) || !(p->roulette_ws >= p->roulette_w)))
+        return -1;
     for (int a = 0; a < 3; a++) {
         if (build_axis(p, a, &C->ax[a]) != 0) return -1;
         C->nc[a] = (p->n_planes[a] == 0) ? 1 : p->n_planes[a] - 1;
@@ -1000,7 +1030,7 @@ int oracle_eigen(const oracle_problem *p, uint64_t N, int n_inactive, int n_acti
 {
     ctx C;
     memset(&C, 0, sizeof(C));
-    if (N == 0 || n_inactive < 0 || n_active < 1 || !p->sigma_f || p->ww_center ||
+    if (N == 0 || n_inactive < 0 || n_active < 1 || !p->sigma_f || p->ww_center || p->implicit_capture ||
         ctx_init(&C, p) != 0 || C.K != 1 || p->time_edges[1] != INFINITY) {
         ctx_free(&C);
         return -1;

@@ -35,6 +35,9 @@ Problem dict schema (all floats are float64, all ints int32):
     qoi       None or dict: lo[3], hi[3], group_mask[G]
     fission   None or dict: sigma_f[M, G], nu[M, G] (mean neutrons per
               fission), chi[M, G] (fission spectrum per material)
+    implicit_capture
+              None or dict: w_min (roulette threshold > 0), w_survive
+              (roulette survival weight >= w_min)
     ww_mesh   None or list of 3 arrays of weight-window mesh planes
 
 The workload recipes follow the transport problems the method is exercised
@@ -112,6 +115,7 @@ def make_problem(sigma_t, sigma_s, speed, planes, material, bc, source, tally,
         "qoi": None,
         "ww_mesh": None,
         "fission": None,
+        "implicit_capture": None,
     }
     if fission is not None:
         p["fission"] = {k: _f64(fission[k]).reshape(M, G) for k in ("sigma_f", "nu", "chi")}
