@@ -120,6 +120,14 @@ typedef struct mcdc_problem mcdc_problem;
  * group from chi, an isotropic direction and an optical depth.  The extra
  * neutrons are tracked like weight-window progeny (split bank, generation
  * by generation after each chunk of histories).
+ *
+ * Implicit capture (optional, implicit_capture = 1; Section 3 runs the
+ * time-dependent dog-leg duct with it): collisions never absorb; the weight
+ * is multiplied by sigma_s / sigma_t and, when it falls below roulette_w,
+ * one draw keeps the particle with probability w / roulette_ws at weight
+ * roulette_ws (else it ends, counted as rouletted); then the scatter draws
+ * group, direction and optical depth.  0 < roulette_w <= roulette_ws; not
+ * combined with fission; not in batched solves or eigenvalue runs.
  */
 typedef struct {
     int32_t abi_version; /* MCDC_ABI_VERSION */
@@ -156,6 +164,9 @@ typedef struct {
     const double *sigma_f;
     const double *nu;
     const double *chi;
+    int32_t implicit_capture;
+    double roulette_w;
+    double roulette_ws;
 } mcdc_problem_desc;
 
 /*

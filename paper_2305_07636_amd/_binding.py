@@ -50,6 +50,7 @@ class mcdc_problem_desc(C.Structure):
         ("n_ww_planes", C.c_int32 * 3), ("ww_planes", _DP * 3),
         ("time_crossing", C.c_int32),
         ("sigma_f", _DP), ("nu", _DP), ("chi", _DP),
+        ("implicit_capture", C.c_int32), ("roulette_w", C.c_double), ("roulette_ws", C.c_double),
     ]
 
 
@@ -185,6 +186,11 @@ def make_desc(prob: dict):
         d.sigma_f = _dp(arr(fis["sigma_f"]))
         d.nu = _dp(arr(fis["nu"]))
         d.chi = _dp(arr(fis["chi"]))
+    ic = prob.get("implicit_capture")
+    if ic is not None:
+        d.implicit_capture = 1
+        d.roulette_w = float(ic["w_min"])
+        d.roulette_ws = float(ic["w_survive"])
     return d, keep
 
 

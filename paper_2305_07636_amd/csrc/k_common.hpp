@@ -280,17 +280,30 @@ __device__ __forceinline__ int cross(const DevProblem &P, Particle &p, int mask)
     return -1;
 }
 
-// Analog collision in material m.  One draw picks the reaction: scatter
+// Collision in material m.  Analog: one draw picks the reaction: scatter
 // below sigma_s / sigma_t, fission below (sigma_s + sigma_f) / sigma_t
-// (FIS kernels only), else capture.  Returns 0 on capture; 1 on a scatter,
-// after which the particle has its outgoing group, a new isotropic
-// direction and a new optical depth; 2 on a fission, whose neutrons
-// fission() then emits.
+// (FIS kernels only), else capture.  Implicit capture (FIS kernels only):
+// no capture; the weight is multiplied by sigma_s / sigma_t and, below the
+// roulette threshold, one draw keeps the particle with probability
+// w / w_s at weight w_s.  Returns 0 on capture; 1 on a scatter, after
+// which the particle has its outgoing group, a new isotropic direction and
+// a new optical depth; 2 on a fission, whose neutrons fission() then
+// emits; 3 when the roulette ends the particle.
 template <int FM, bool FIS = false>
 __device__ __forceinline__ int collide(const DevProblem &P, Particle &p, int m) {
     const int mg = m * P.G + p.g;
-    const double xr = rn(p.s);
-    if (!(xr < P.ps[mg])) return (FIS && P.fission_on && xr < P.pf[mg]) ? 2 : 0;
+    if (FIS && P.implicit) {
+        p.w = p.w * P.ps[mg];
+        if (p.w < P.roulette_w) {
+            if (rn(p.s) < p.w / P.roulette_ws)
+                p.w = P.roulette_ws;
+            else
+                return 3;
+        }
+    } else {
+        const double xr = rn(p.s);
+        if (!(xr < P.ps[mg])) return (FIS && P.fission_on && xr < P.pf[mg]) ? 2 : 0;
+    }
     double xg = rn(p.s);
     const double *cdf = P.cdf + (int64_t)mg * P.G;
     int g2 = 0;

@@ -673,6 +673,10 @@ __global__ void __launch_bounds__(kBlock) k_event(DevProblem P0, RunArgs R0, Ban
                         cnt.add(3 + kAbsorb);
                         hist_term(R, i, kAbsorb);
                         busy = false;
+                    } else if (WW && r == 3) {
+                        cnt.add(3 + kRoulette);
+                        hist_term(R, i, kRoulette);
+                        busy = false;
                     } else if (!ww_point<WW>(P, R, SB, p, cell, b, i, cnt)) {
                         busy = false;
                     }

@@ -70,6 +70,8 @@ __device__ __forceinline__ int hstep(const DevProblem &P, const RunArgs &R, Part
         const int r = collide<FM, WW>(P, p, f.m);
         if (r == 0) {
             code = kAbsorb;
+        } else if (WW && r == 3) {
+            code = kRoulette;
         } else if (WW && r == 2) {
             const int n = fission<FM>(P, p, f.m, SB, b, hid, R.overflow);
             if (n == 0) {

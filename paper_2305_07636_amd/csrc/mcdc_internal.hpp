@@ -69,12 +69,16 @@ struct DevProblem {
     const double *pf;          // [M][G] (sigma_s,g + sigma_f,g) / sigma_t,g
     const double *nu;          // [M][G] mean neutrons per fission
     const double *chi_cdf;     // [M][G] fission-spectrum CDF
+    // implicit capture with weight roulette (implicit = 0: analog collisions)
+    int implicit;
+    double roulette_w, roulette_ws;   // threshold, survival weight
 };
 
-// Runs whose particles make progeny (window splits, fission neutrons) take
-// the kernels' progeny form: split bank, per-history detector scores.
+// Runs whose particles make progeny (window splits, fission neutrons) or
+// carry weights (implicit capture) take the kernels' weighted form: weights
+// in the banks, split bank, per-history detector scores.
 __host__ __device__ inline bool has_progeny(const DevProblem &P) {
-    return P.ww_center != nullptr || P.fission_on != 0;
+    return P.ww_center != nullptr || P.fission_on != 0 || P.implicit != 0;
 }
 
 // Doubles per bin of the event form's per-step LDS slice: two batches of

@@ -233,6 +233,12 @@ int compile(const mcdc_problem_desc *d, HostProblem &h) {
     if (d->n_batches < 1) return invalid("n_batches must be >= 1");
     h.B = d->n_batches;
     if (d->time_crossing != 0 && d->time_crossing != 1) return invalid("time_crossing must be 0 or 1");
+    if (d->implicit_capture != 0 && d->implicit_capture != 1) return invalid("implicit_capture must be 0 or 1");
+    if (d->implicit_capture) {
+        if (d->sigma_f) return invalid("implicit capture is not combined with fission");
+        if (!(d->roulette_w > 0.0) || !(d->roulette_ws >= d->roulette_w) || !std::isfinite(d->roulette_ws))
+            return invalid("implicit capture needs 0 < roulette_w <= roulette_ws");
+    }
 
     // tally, window and detector planes; union grid per axis
     if (d->qoi_enabled) {
@@ -425,6 +431,9 @@ int upload(mcdc_problem *p) {
     D.ww_max_split = 16;
     D.ww_ratio = 5.0;
     D.fission_on = h.fission ? 1 : 0;
+    D.implicit = d.implicit_capture ? 1 : 0;
+    D.roulette_w = d.roulette_w;
+    D.roulette_ws = d.roulette_ws;
     D.pf = h.fission ? (const double *)(base + o_pf) : nullptr;
     D.nu = h.fission ? (const double *)(base + o_nu) : nullptr;
     D.chi_cdf = h.fission ? (const double *)(base + o_chi) : nullptr;

@@ -463,7 +463,7 @@ extern "C" int mcdc_run_batched(mcdc_problem *const *ps, int32_t n, const uint64
         if (!ps[j]) return bad("NULL problem in batch");
         if (ps[j]->device != dev) return bad("all problems of a batch must be on one device");
         if (has_progeny(ps[j]->d)) {
-            set_error("batched solves run analog (no weight windows, no fission)");
+            set_error("batched solves run analog (no weight windows, fission or implicit capture)");
             return MCDC_E_UNSUPPORTED;
         }
         if (ps[j]->h.B > 1023) {
@@ -569,8 +569,8 @@ extern "C" int mcdc_run_eigenvalue(mcdc_problem *p, uint64_t n_per_cycle, int32_
     const DevProblem &P = p->d;
     if (!P.fission_on) return bad("the eigenvalue problem needs fission data");
     if (P.K != 1 || std::isfinite(p->h.T[1])) return bad("the eigenvalue problem is steady state: time edges [T0, inf)");
-    if (P.ww_center || P.qoi_on || opt.debug_counts || opt.debug_scores || opt.profile) {
-        set_error("eigenvalue runs take no weight windows, detector, debug or profile arrays");
+    if (P.ww_center || P.implicit || P.qoi_on || opt.debug_counts || opt.debug_scores || opt.profile) {
+        set_error("eigenvalue runs take no weight windows, implicit capture, detector, debug or profile arrays");
         return MCDC_E_UNSUPPORTED;
     }
     HIP_CHECK(hipSetDevice(p->device), "hipSetDevice");
