@@ -230,6 +230,11 @@ def fom_section(w, n_pilot, n_analog, n_ww, steps):
     log(f"fom: learned {b}")
     c = lw.figure_of_merit(p, n_ww, 53, table=info["raw_table"])
     log(f"fom: raw-tally windows {c}")
+    # implicit capture (Section 3 runs the time-dependent duct with it),
+    # roulette below weight 0.25 to weight 1
+    pic = dict(p, implicit_capture={"w_min": 0.25, "w_survive": 1.0})
+    d = lw.figure_of_merit(pic, n_ww, 54)
+    log(f"fom: implicit capture {d}")
 
     def diff(x, y):
         s = math.hypot(x["sigma"], y["sigma"])
@@ -240,7 +245,9 @@ def fom_section(w, n_pilot, n_analog, n_ww, steps):
                     "[29,30]x[7,9]x[4,6]",
         "pilot_histories": n_pilot, "train_steps": steps, "window_build_s": t_build,
         "pilot_s": info["pilot_s"], "train_s": info["train_s"], "loss": [info["loss_first"], info["loss_last"]],
-        "analog": a, "learned": b, "raw_tally_windows": c,
+        "analog": a, "learned": b, "raw_tally_windows": c, "implicit_capture": d,
+        "fom_gain_implicit_vs_analog": (d["fom"] / a["fom"]) if a["fom"] > 0 else None,
+        "mean_diff_sigma_implicit_vs_analog": diff(a, d),
         "fom_gain_learned_vs_analog": (b["fom"] / a["fom"]) if a["fom"] > 0 else None,
         "fom_gain_learned_vs_raw": (b["fom"] / c["fom"]) if c["fom"] > 0 else None,
         "mean_diff_sigma_learned_vs_analog": diff(a, b),
