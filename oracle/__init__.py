@@ -62,6 +62,7 @@ class _Problem(C.Structure):
         ("time_crossing", C.c_int32),
         ("sigma_f", _DP), ("nu", _DP), ("chi", _DP),
         ("implicit_capture", C.c_int32), ("roulette_w", C.c_double), ("roulette_ws", C.c_double),
+        ("pin_radius", _DP), ("pin_material", _IP),
     ]
 
 
@@ -174,6 +175,10 @@ class OracleProblem:
             s.implicit_capture = 1
             s.roulette_w = float(ic["w_min"])
             s.roulette_ws = float(ic["w_survive"])
+        pins = prob.get("pins")
+        if pins is not None:
+            s.pin_radius = _dp(arr(pins["radius"]))
+            s.pin_material = arr(pins["material"], np.int32).ctypes.data_as(_IP)
         self.time_crossing = bool(s.time_crossing)
         self.struct = s
         self._keep = keep

@@ -83,6 +83,17 @@
  *       else the particle ends (rouletted).  Then the scatter draws as in
  *       the analog game (group, direction, optical depth) and the window
  *       check follows.  Not combined with fission; 0 < w_min <= w_s.
+ *   R15 Cylindrical pins (optional; Section 3's pin cells and cores, on
+ *       quadric-surface geometry): a geometry cell may hold one cylinder
+ *       parallel to z, centred on the cell's x-y midpoint (0.5 (lo + hi)
+ *       per axis), radius r below half the cell's x and y widths, with its
+ *       own material.  A particle carries an inside flag.  Distance: with
+ *       dx = x - xc, dy = y - yc, a = u^2 + v^2, b = dx u + dy v,
+ *       c = (dx^2 + dy^2) - r^2: inside, (-b + sqrt(max(b^2 - a c, 0))) / a;
+ *       outside, if b < 0 and b^2 - a c > 0, (-b - sqrt(b^2 - a c)) / a;
+ *       else (or a = 0) none; clipped at 0.  Tie order: census, planes,
+ *       cylinder, collision.  A cylinder crossing is a surface event that
+ *       crosses no plane and flips the flag.  Birth: inside iff c < 0.
  *
  * Build: gcc -O2 -ffp-contract=off -fPIC -shared -o liboracle.so mcdc_oracle.c -lm
  */
@@ -135,6 +146,9 @@ typedef struct {
     /* implicit capture with weight roulette (R14) */
     int32_t implicit_capture;
     double roulette_w, roulette_ws;
+    /* cylindrical pins (R15): per geometry cell, or NULL */
+    const double *pin_radius;     /* [cz][cy][cx], 0 = no pin */
+    const int32_t *pin_material;  /* [cz][cy][cx] */
 } oracle_problem;
 
 enum { EV_CENSUS = 0, EV_SURFACE = 1, EV_COLLISION = 2 };
@@ -311,6 +325,7 @@ typedef struct {
     double t, tau, w;
     int ix[3];
     int g, k;
+    int inpin;      /* R15: inside the cell's pin */
     int since;      /* events since birth or the last census */
     uint64_t s;
 } particle;
@@ -346,6 +361,7 @@ typedef struct {
     int quiet;          /* inactive cycle: no tallies */
     double site_x[3];   /* fission site of the current particle */
     int site_ix[3];
+    int site_inpin;
     int site_n;         /* sites banked there (0: none) */
     double *chi_cdf;    /* [M][G] fission-spectrum CDF (fission only) */
 } ctx;
@@ -371,11 +387,33 @@ static void set_inv(particle *pt)
     for (int a = 0; a < 3; a++) pt->inv_u[a] = 1.0 / pt->u[a];
 }
 
+static int64_t geo_cell(const ctx *C, const particle *pt, int c[3])
+{
+    for (int a = 0; a < 3; a++) c[a] = (C->ax[a].n == 0) ? 0 : C->ax[a].geo[pt->ix[a]];
+    return ((int64_t)c[2] * C->nc[1] + c[1]) * C->nc[0] + c[0];
+}
+
 static int material_of(const ctx *C, const particle *pt)
 {
     int c[3];
-    for (int a = 0; a < 3; a++) c[a] = (C->ax[a].n == 0) ? 0 : C->ax[a].geo[pt->ix[a]];
-    return C->p->material[((int64_t)c[2] * C->nc[1] + c[1]) * C->nc[0] + c[0]];
+    int64_t g = geo_cell(C, pt, c);
+    if (pt->inpin) return C->p->pin_material[g];
+    return C->p->material[g];
+}
+
+/* R15: the pin of the particle's geometry cell (centre, r^2); 0 if none */
+static int pin_of(const ctx *C, const particle *pt, double *xc, double *yc, double *r2)
+{
+    const oracle_problem *p = C->p;
+    if (!p->pin_radius) return 0;
+    int c[3];
+    int64_t g = geo_cell(C, pt, c);
+    double r = p->pin_radius[g];
+    if (!(r > 0.0)) return 0;
+    *xc = 0.5 * (p->planes[0][c[0]] + p->planes[0][c[0] + 1]);
+    *yc = 0.5 * (p->planes[1][c[1]] + p->planes[1][c[1] + 1]);
+    *r2 = r * r;
+    return 1;
 }
 
 /* tally bin of the particle's union cell in the current (k, g), or -1 */
@@ -535,6 +573,28 @@ static int step(ctx *C, particle *pt, int b, particle *stack, int *sp, hist_rec 
         da[a] = d;
         if (d < ds) ds = d;
     }
+    /* R15: distance to the cell's pin surface */
+    double dcyl = INFINITY;
+    {
+        double xc, yc, r2;
+        if (pin_of(C, pt, &xc, &yc, &r2)) {
+            double dx = pt->x[0] - xc, dy = pt->x[1] - yc;
+            double a = pt->u[0] * pt->u[0] + pt->u[1] * pt->u[1];
+            double b = dx * pt->u[0] + dy * pt->u[1];
+            double c = (dx * dx + dy * dy) - r2;
+            if (a > 0.0) {
+                if (pt->inpin) {
+                    double disc = b * b - a * c;
+                    if (disc < 0.0) disc = 0.0;
+                    dcyl = (-b + sqrt(disc)) / a;
+                } else if (b < 0.0) {
+                    double disc = b * b - a * c;
+                    if (disc > 0.0) dcyl = (-b - sqrt(disc)) / a;
+                }
+                if (dcyl < 0.0) dcyl = 0.0;
+            }
+        }
+    }
     /* distance to the next time-census edge */
     double Tn = p->time_edges[pt->k + 1];
     double dt = INFINITY;
@@ -542,15 +602,19 @@ static int step(ctx *C, particle *pt, int b, particle *stack, int *sp, hist_rec 
         dt = (Tn - pt->t) * p->speed[pt->g];
         if (dt < 0.0) dt = 0.0;
     }
-    /* R3 */
-    int ev;
+    /* R3, R15 */
+    int ev, cyl = 0;
     double d;
-    if (dt <= ds && dt <= dc) {
+    if (dt <= ds && dt <= dcyl && dt <= dc) {
         ev = EV_CENSUS;
         d = dt;
-    } else if (ds <= dc) {
+    } else if (ds <= dcyl && ds <= dc) {
         ev = EV_SURFACE;
         d = ds;
+    } else if (dcyl <= dc) {
+        ev = EV_SURFACE;
+        d = dcyl;
+        cyl = 1;
     } else {
         ev = EV_COLLISION;
         d = dc;
@@ -634,6 +698,7 @@ static int step(ctx *C, particle *pt, int b, particle *stack, int *sp, hist_rec 
             }
             if (pt->ix[a] != old && C->ax[a].wwc[pt->ix[a]] != C->ax[a].wwc[old]) wcell_changed = 1;
         }
+        if (cyl) pt->inpin ^= 1;
         if (alive && wcell_changed) alive = ww_game(C, pt, stack, sp, h);
     } else {
         h->n_coll++;
@@ -666,6 +731,7 @@ static int step(ctx *C, particle *pt, int b, particle *stack, int *sp, hist_rec 
                     C->site_x[a] = pt->x[a];
                     C->site_ix[a] = pt->ix[a];
                 }
+                C->site_inpin = pt->inpin;
                 terminate(C, h, T_ABSORB);
                 alive = 0;
             } else if (C->pf && xr < C->pf[m * G + pt->g]) {
@@ -747,6 +813,13 @@ static int birth(ctx *C, uint64_t s0, particle *pt, hist_rec *h)
     pt->tau = -log(1.0 - rn(&pt->s));
     pt->w = 1.0;
     for (int a = 0; a < 3; a++) pt->ix[a] = (C->ax[a].n == 0) ? 0 : locate(&C->ax[a], pt->x[a], pt->u[a]);
+    {
+        double xc, yc, r2;
+        if (pin_of(C, pt, &xc, &yc, &r2)) {
+            double dx = pt->x[0] - xc, dy = pt->x[1] - yc;
+            pt->inpin = ((dx * dx + dy * dy) - r2) < 0.0;
+        }
+    }
     /* time bin */
     if (pt->t >= p->time_edges[C->K]) {
         terminate(C, h, T_TIME);
@@ -779,6 +852,21 @@ static int ctx_init(ctx *C, const oracle_problem *p)
         C->nw[a] = (p->n_ww[a] == 0) ? 1 : p->n_ww[a] - 1;
     }
     C->ntally = (int64_t)C->K * G * C->nt[0] * C->nt[1] * C->nt[2];
+    if (p->pin_radius) {
+        /* R15: pins need finite x and y axes and must fit their cells */
+        if (p->n_planes[0] == 0 || p->n_planes[1] == 0 || !p->pin_material) return -1;
+        for (int cz = 0; cz < C->nc[2]; cz++)
+            for (int cy = 0; cy < C->nc[1]; cy++)
+                for (int cx = 0; cx < C->nc[0]; cx++) {
+                    int64_t g = ((int64_t)cz * C->nc[1] + cy) * C->nc[0] + cx;
+                    double r = p->pin_radius[g];
+                    if (!(r >= 0.0)) return -1;
+                    if (r == 0.0) continue;
+                    double hx = 0.5 * (p->planes[0][cx + 1] - p->planes[0][cx]);
+                    double hy = 0.5 * (p->planes[1][cy + 1] - p->planes[1][cy]);
+                    if (!(r < hx) || !(r < hy) || p->pin_material[g] < 0 || p->pin_material[g] >= M) return -1;
+                }
+    }
     C->ps = (double *)calloc((size_t)M * G, sizeof(double));
     C->cdf = (double *)calloc((size_t)M * G * G, sizeof(double));
     C->src_cdf = (double *)calloc((size_t)G, sizeof(double));
@@ -1045,12 +1133,13 @@ int oracle_eigen(const oracle_problem *p, uint64_t N, int n_inactive, int n_acti
     C.Lc = (double *)calloc((size_t)(A * G * 6), sizeof(double));
     /* sites of the previous and the current cycle, one record per particle */
     double *sx[2];
-    int *six[2], *sn[2];
+    int *six[2], *sn[2], *sin[2];
     uint64_t *cum = (uint64_t *)malloc(sizeof(uint64_t) * N);   /* inclusive prefix of sn[prev] */
     for (int r = 0; r < 2; r++) {
         sx[r] = (double *)malloc(sizeof(double) * 3 * N);
         six[r] = (int *)malloc(sizeof(int) * 3 * N);
         sn[r] = (int *)malloc(sizeof(int) * N);
+        sin[r] = (int *)malloc(sizeof(int) * N);
     }
     int rc = 0, cur = 0;
     uint64_t M = 0;
@@ -1084,6 +1173,7 @@ int oracle_eigen(const oracle_problem *p, uint64_t N, int n_inactive, int n_acti
                     pt.x[a] = sx[prev][3 * lo + a];
                     pt.ix[a] = six[prev][3 * lo + a];
                 }
+                pt.inpin = sin[prev][lo];
                 pt.t = p->time_edges[0];
                 pt.w = 1.0;
                 emit(&C, &pt, material_of(&C, &pt));
@@ -1095,6 +1185,7 @@ int oracle_eigen(const oracle_problem *p, uint64_t N, int n_inactive, int n_acti
                 if (track(&C, &pt, b, NULL, &sp, &h) < 0) rc = -4;
             }
             sn[cur][q] = C.site_n;
+            sin[cur][q] = C.site_inpin;
             for (int a = 0; a < 3; a++) {
                 sx[cur][3 * q + a] = C.site_x[a];
                 six[cur][3 * q + a] = C.site_ix[a];
@@ -1123,6 +1214,7 @@ int oracle_eigen(const oracle_problem *p, uint64_t N, int n_inactive, int n_acti
         free(sx[r]);
         free(six[r]);
         free(sn[r]);
+        free(sin[r]);
     }
     free(cum);
     ctx_free(&C);

@@ -38,6 +38,9 @@ Problem dict schema (all floats are float64, all ints int32):
     implicit_capture
               None or dict: w_min (roulette threshold > 0), w_survive
               (roulette survival weight >= w_min)
+    pins      None or dict: radius [nz, ny, nx] (a cylinder parallel to z
+              centred in each geometry cell's x-y rectangle, 0 = none) and
+              material [nz, ny, nx] (the material inside it)
     ww_mesh   None or list of 3 arrays of weight-window mesh planes
 
 The workload recipes follow the transport problems the method is exercised
@@ -116,6 +119,7 @@ def make_problem(sigma_t, sigma_s, speed, planes, material, bc, source, tally,
         "ww_mesh": None,
         "fission": None,
         "implicit_capture": None,
+        "pins": None,
     }
     if fission is not None:
         p["fission"] = {k: _f64(fission[k]).reshape(M, G) for k in ("sigma_f", "nu", "chi")}
@@ -352,6 +356,49 @@ def pin_cell_eigen(n_groups=7, gen_seed=9, fine=3):
                         [REFLECTIVE] * 4 + [VACUUM, VACUUM], src, tally,
                         fission={"sigma_f": np.stack([sf, np.zeros(G)]), "nu": np.full((2, G), 2.45),
                                  "chi": np.stack([chi, chi])})
+
+
+def beam_through_pin(y0=1.2, sigma_pin=1.5, radius=0.6, n_bins=20, mu_law="beam"):
+    """A 2 x 2 (x, y) void box, infinite in z, with one purely absorbing
+    pin of the given radius centred at (1, 1).  Surface source on the x-
+    face at the point (0, y0), entering along +x with the given angular
+    law; the particles that miss or cross the pin leak through the far
+    faces.  Flux tally in n_bins x-bins."""
+    planes = [np.array([0.0, 2.0]), np.array([0.0, 2.0]), _empty()]
+    src = {"kind": "surface", "axis": 0, "sign": 1, "mu_law": mu_law, "lo": [0.0, y0, 0.0],
+           "hi": [0.0, y0, 0.0], "group_pmf": [1.0]}
+    tally = {"mesh": [np.linspace(0.0, 2.0, n_bins + 1), np.array([0.0, 2.0]), _empty()],
+             "time_edges": [0.0, math.inf], "n_batches": 32}
+    p = make_problem([[0.0], [sigma_pin]], [[[0.0]], [[0.0]]], [1.0], planes, np.zeros((1, 1, 1)),
+                     [VACUUM] * 6, src, tally)
+    p["pins"] = {"radius": np.array([[[radius]]]), "material": np.array([[[1]]], dtype=np.int32)}
+    return p
+
+
+def pin_lattice(n=3, pitch=1.26, radius=0.54, height=10.0, n_groups=3, gen_seed=17, n_z_bins=4,
+                n_time_bins=5, t_end=5.0, bc_xy=REFLECTIVE, bc_z=VACUUM, n_batches=16, fine=1):
+    """n x n lattice of square cells of the given pitch, each holding a
+    cylindrical fuel pin (material 0) of the given radius in moderator
+    (material 1); synthetic cross sections; uniform volume pulse source in
+    group 0 at t = 0; tally mesh fine x fine per cell in x-y, n_z_bins in z."""
+    rng = SplitMix64(gen_seed)
+    G = n_groups
+    st = np.zeros((2, G))
+    ss = np.zeros((2, G, G))
+    for m in range(2):
+        st[m], ss[m] = synthetic_xs(rng, G)
+    px = np.arange(n + 1) * pitch
+    pz = np.array([0.0, height])
+    mesh_xy = np.linspace(0.0, px[-1], n * fine + 1)
+    pmf = np.zeros(G)
+    pmf[0] = 1.0
+    src = {"kind": "isotropic", "lo": [0.0, 0.0, 0.0], "hi": [px[-1], px[-1], height], "group_pmf": pmf}
+    tally = {"mesh": [mesh_xy, mesh_xy, np.linspace(0.0, height, n_z_bins + 1)],
+             "time_edges": np.linspace(0.0, t_end, n_time_bins + 1), "n_batches": n_batches}
+    p = make_problem(st, ss, [float(G - g) for g in range(G)], [px, px, pz], np.ones((1, n, n), dtype=np.int32),
+                     [bc_xy] * 4 + [bc_z] * 2, src, tally)
+    p["pins"] = {"radius": np.full((1, n, n), radius), "material": np.zeros((1, n, n), dtype=np.int32)}
+    return p
 
 
 def bare_slab_eigen(thickness=6.0, sigma_s=0.6, sigma_f=0.2, nu=2.5, n_bins=24):
