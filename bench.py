@@ -188,6 +188,48 @@ def fission_section(m, w, n, steps):
     return res
 
 
+def pins_section(m, w, n, steps):
+    """Cylindrical-pin geometry: the 17 x 17 lattice of the lattice workload
+    with a 0.54-radius fuel pin in every 1.26 cell (7 groups, 17 x 17 x 10 x
+    20 bins), both forms; and k-eigenvalue cycles of a reflected pin cell
+    with a cylindrical pin (50 inactive + 100 active cycles of 1e5)."""
+    import torch
+
+    prob = w.pin_lattice(n=17, n_groups=7, gen_seed=3, height=50.0, n_z_bins=10, n_time_bins=20, t_end=20.0,
+                         n_batches=32)
+    h = m.mcdc_problem_create(prob)
+    res = {"workload": f"17 x 17 pin lattice (pitch 1.26, pin radius 0.54, 7 groups), {n:.0e} histories"}
+    try:
+        for alg in ("event", "history"):
+            out = m.mcdc_run(h, n, 70, algorithm=alg, outputs=("mean",))
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for s in range(steps):
+                out = m.mcdc_run(h, n, 71 + s, algorithm=alg, outputs=("mean",))
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / steps
+            res[f"{alg}_histories_per_s"] = n / dt
+            res[f"{alg}_ms"] = dt * 1e3
+            log(f"pins: lattice {alg} form {dt * 1e3:.2f} ms")
+        res["events_per_history"] = float(sum(out["events"])) / n
+    finally:
+        h.close()
+    h = m.mcdc_problem_create(w.pin_cell_eigen_cylinder())
+    try:
+        m.mcdc_run_eigenvalue(h, 100000, 2, 2, 90)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = m.mcdc_run_eigenvalue(h, 100000, 50, 100, 91)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+    finally:
+        h.close()
+    res["eigen_cylinder_pin_cell"] = {"seconds": dt, "histories_per_s": 1.5e7 / dt, "k_mean": out["k_mean"],
+                                      "k_std": out["k_std"]}
+    log(f"pins: eigenvalue pin cell {dt:.3f} s, k = {out['k_mean']:.5f} +- {out['k_std']:.5f}")
+    return res
+
+
 def eigen_section(m, w, n_per_cycle, n_inactive, n_active):
     """k-eigenvalue power iteration on the box pin cell (7 groups, fuel in
     moderator, reflected), with the cycle counts of Section 3's pin-cell
@@ -269,6 +311,7 @@ def main():
     ap.add_argument("--no-time-crossing", action="store_true")
     ap.add_argument("--no-fission", action="store_true")
     ap.add_argument("--no-eigen", action="store_true")
+    ap.add_argument("--no-pins", action="store_true")
     ap.add_argument("--eigen-per-cycle", type=float, default=1e5)
     ap.add_argument("--fission-histories", type=float, default=1e6)
     ap.add_argument("--fom-pilot", type=float, default=1e8)
@@ -399,6 +442,8 @@ def main():
         extra["fission"] = fission_section(m, w, int(args.fission_histories), args.steps)
     if not args.no_eigen:
         extra["eigenvalue"] = eigen_section(m, w, int(args.eigen_per_cycle), 50, 100)
+    if not args.no_pins:
+        extra["pins"] = pins_section(m, w, int(args.histories), args.steps)
     if not args.no_batched:
         extra["batched"] = batched_section(m, w)
     if not args.no_fom:

@@ -128,6 +128,17 @@ typedef struct mcdc_problem mcdc_problem;
  * roulette_ws (else it ends, counted as rouletted); then the scatter draws
  * group, direction and optical depth.  0 < roulette_w <= roulette_ws; not
  * combined with fission; not in batched solves or eigenvalue runs.
+ *
+ * Cylindrical pins (optional; Section 3's pin cells and cores use
+ * quadric-surface geometry): pin_radius[cz][cy][cx] >= 0 over the geometry
+ * cells (0 = no pin) and pin_material[cz][cy][cx].  A pin is the cylinder
+ * parallel to z centred on its cell's x-y midpoint, radius below half the
+ * cell's x and y widths (x and y must be finite axes), filled with its own
+ * material; tally, window and detector bins stay those of the box mesh.  A
+ * particle carries an inside flag; the distance to the pin surface solves
+ * the x-y quadratic (far root from inside, near root from outside when
+ * closing in), ties go census, planes, pin, collision, and a pin crossing
+ * is a surface event that crosses no plane.  Both NULL: no pins.
  */
 typedef struct {
     int32_t abi_version; /* MCDC_ABI_VERSION */
@@ -167,6 +178,8 @@ typedef struct {
     int32_t implicit_capture;
     double roulette_w;
     double roulette_ws;
+    const double *pin_radius;
+    const int32_t *pin_material;
 } mcdc_problem_desc;
 
 /*

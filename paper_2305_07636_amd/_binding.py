@@ -51,6 +51,7 @@ class mcdc_problem_desc(C.Structure):
         ("time_crossing", C.c_int32),
         ("sigma_f", _DP), ("nu", _DP), ("chi", _DP),
         ("implicit_capture", C.c_int32), ("roulette_w", C.c_double), ("roulette_ws", C.c_double),
+        ("pin_radius", _DP), ("pin_material", _IP),
     ]
 
 
@@ -191,6 +192,10 @@ def make_desc(prob: dict):
         d.implicit_capture = 1
         d.roulette_w = float(ic["w_min"])
         d.roulette_ws = float(ic["w_survive"])
+    pins = prob.get("pins")
+    if pins is not None:
+        d.pin_radius = _dp(arr(pins["radius"]))
+        d.pin_material = arr(pins["material"], np.int32).ctypes.data_as(_IP)
     return d, keep
 
 

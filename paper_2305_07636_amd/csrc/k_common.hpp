@@ -75,8 +75,14 @@ struct Particle {
     double t, tau, w;
     int ix[3];
     int g, k;
+    int inpin;                  // inside the cell's cylindrical pin
     uint64_t s;
 };
+
+// Material at the particle's place: the cell's, or its pin's inside it.
+__device__ __forceinline__ int material_of(const DevProblem &P, const Particle &p, int cell) {
+    return (P.pins_on && p.inpin) ? P.pin_mat[cell] : P.cell_mat[cell];
+}
 
 template <int FM>
 __device__ __forceinline__ bool finite_axis(const DevProblem &P, int a) {
@@ -158,6 +164,15 @@ __device__ __forceinline__ bool birth(const DevProblem &P, uint64_t s0, Particle
 #pragma unroll
     for (int a = 0; a < 3; ++a)
         p.ix[a] = finite_axis<FM>(P, a) ? locate(P.U[a], P.nU[a], p.x[a], p.u[a]) : 0;
+    p.inpin = 0;
+    if (FM != 1 && P.pins_on) {
+        const int cell = cell_index(P, p.ix);
+        const double r2 = P.pin_r2[cell];
+        if (r2 > 0.0) {
+            const double dx = p.x[0] - P.pin_xc[cell], dy = p.x[1] - P.pin_yc[cell];
+            p.inpin = ((dx * dx + dy * dy) - r2) < 0.0;
+        }
+    }
     if (p.t >= P.T[P.K]) {
         p.k = P.K;
         return false;
@@ -181,7 +196,7 @@ struct Flight {
 template <int FM>
 __device__ __forceinline__ Flight next_event(const DevProblem &P, const Particle &p, int cell) {
     Flight f;
-    f.m = P.cell_mat[cell];
+    f.m = (FM != 1) ? material_of(P, p, cell) : P.cell_mat[cell];
     const int mg = f.m * P.G + p.g;
     f.st = P.sigma_t[mg];
     double dc = (f.st == 0.0) ? kInf : p.tau * P.inv_st[mg];
@@ -196,18 +211,46 @@ __device__ __forceinline__ Flight next_event(const DevProblem &P, const Particle
         f.da[a] = d;
         if (d < ds) ds = d;
     }
+    // the cell's pin (x-y quadratic; a slab has none): from inside, the far
+    // root; from outside, the near root if the flight closes in on the axis
+    double dcyl = kInf;
+    if (FM != 1 && P.pins_on) {
+        const double r2 = P.pin_r2[cell];
+        if (r2 > 0.0) {
+            const double dx = p.x[0] - P.pin_xc[cell], dy = p.x[1] - P.pin_yc[cell];
+            const double a = p.u[0] * p.u[0] + p.u[1] * p.u[1];
+            const double b = dx * p.u[0] + dy * p.u[1];
+            const double c = (dx * dx + dy * dy) - r2;
+            if (a > 0.0) {
+                if (p.inpin) {
+                    double disc = b * b - a * c;
+                    if (disc < 0.0) disc = 0.0;
+                    dcyl = (-b + sqrt(disc)) / a;
+                } else if (b < 0.0) {
+                    const double disc = b * b - a * c;
+                    if (disc > 0.0) dcyl = (-b - sqrt(disc)) / a;
+                }
+                if (dcyl < 0.0) dcyl = 0.0;
+            }
+        }
+    }
     double Tn = P.T[p.k + 1];
     double dt = kInf;
     if (Tn != kInf) {
         dt = (Tn - p.t) * P.speed[p.g];
         if (dt < 0.0) dt = 0.0;
     }
-    if (dt <= ds && dt <= dc) {
+    // tie order: census, planes, pin, collision (a pin crossing is a
+    // surface event that crosses no plane)
+    if (dt <= ds && dt <= dcyl && dt <= dc) {
         f.ev = kCensus;
         f.d = dt;
-    } else if (ds <= dc) {
+    } else if (ds <= dcyl && ds <= dc) {
         f.ev = kSurface;
         f.d = ds;
+    } else if (dcyl <= dc) {
+        f.ev = kSurface;
+        f.d = dcyl;
     } else {
         f.ev = kCollision;
         f.d = dc;
@@ -247,6 +290,10 @@ __device__ __forceinline__ int crossing_mask(const DevProblem &P, const Flight &
 // face crossed (the particle leaks; later axes are not processed), or -1.
 template <int FM>
 __device__ __forceinline__ int cross(const DevProblem &P, Particle &p, int mask) {
+    if (FM != 1 && mask == 0) {   // the cell's pin surface (a slab has none)
+        p.inpin ^= 1;
+        return -1;
+    }
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         if (!finite_axis<FM>(P, a) || !((mask >> a) & 1)) continue;
@@ -356,7 +403,7 @@ __device__ __forceinline__ bool ww_check(const DevProblem &P, Particle &p, int c
 struct SplitBank {
     double *x[3], *u[3], *t, *tau, *w;
     uint64_t *s;
-    uint32_t *ixyz, *gk;      // gk = g | batch << 5 | k << 15
+    uint32_t *ixyz, *gk;      // gk = g | batch << 5 | k << 15 | inside pin << 31
     uint64_t *hid;            // global history index
     unsigned long long *count;  // device counter of entries asked for (64-bit: it
                                 // keeps counting past cap on overflow, never wraps)
@@ -375,7 +422,7 @@ __device__ __forceinline__ void split_store(const SplitBank &B, unsigned int slo
     B.w[slot] = p.w;
     B.s[slot] = p.s;
     B.ixyz[slot] = (uint32_t)p.ix[0] | ((uint32_t)p.ix[1] << 11) | ((uint32_t)p.ix[2] << 22);
-    B.gk[slot] = (uint32_t)p.g | ((uint32_t)b << 5) | ((uint32_t)p.k << 15);
+    B.gk[slot] = (uint32_t)p.g | ((uint32_t)b << 5) | ((uint32_t)p.k << 15) | ((uint32_t)p.inpin << 31);
     B.hid[slot] = hid;
 }
 
@@ -397,7 +444,8 @@ __device__ __forceinline__ void split_load(const SplitBank &B, unsigned int slot
     const uint32_t gk = B.gk[slot];
     p.g = gk & 31u;
     b = (gk >> 5) & 1023u;
-    p.k = gk >> 15;
+    p.k = (gk >> 15) & 0xFFFFu;
+    p.inpin = (int)(gk >> 31);
     hid = B.hid[slot];
 }
 

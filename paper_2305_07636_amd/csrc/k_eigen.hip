@@ -27,7 +27,7 @@ using namespace dev;
 struct Sites {
     double *x;        // [N][3] collision point of the particle's fission
     uint32_t *ixyz;   // [N] its union cell, ix | iy << 11 | iz << 22
-    uint32_t *n;      // [N] sites banked there (0: no fission)
+    uint32_t *n;      // [N] sites banked there (0: no fission) | inside pin << 31
     uint64_t *cum;    // [N] inclusive prefix sum of n
 };
 
@@ -75,14 +75,15 @@ __global__ void __launch_bounds__(256) k_eigen_cycle(DevProblem P, RunArgs R, ui
                 p.ix[0] = c & 2047u;
                 p.ix[1] = (c >> 11) & 2047u;
                 p.ix[2] = c >> 22;
+                p.inpin = (int)(prev.n[lo] >> 31);
                 p.t = P.T[0];
                 p.w = 1.0;
                 p.k = 0;
                 p.s = s0;
-                fission_emit<FM>(P, p, P.cell_mat[cell_index(P, p.ix)]);
+                fission_emit<FM>(P, p, material_of(P, p, cell_index(P, p.ix)));
             }
         }
-        uint32_t n_sites = 0;
+        uint32_t n_sites = 0, site_pin = 0;
         int code = kTime;
         unsigned int ev[3] = {0u, 0u, 0u};
         if (alive) {
@@ -123,6 +124,7 @@ __global__ void __launch_bounds__(256) k_eigen_cycle(DevProblem P, RunArgs R, ui
 #pragma unroll
                         for (int a = 0; a < 3; ++a) cur.x[q * 3 + a] = p.x[a];
                         cur.ixyz[q] = (uint32_t)p.ix[0] | ((uint32_t)p.ix[1] << 11) | ((uint32_t)p.ix[2] << 22);
+                        site_pin = (uint32_t)p.inpin;
                         code = kAbsorb;
                     } else if (r == 0) {
                         code = kAbsorb;
@@ -135,7 +137,7 @@ __global__ void __launch_bounds__(256) k_eigen_cycle(DevProblem P, RunArgs R, ui
                 }
             }
         }
-        cur.n[q] = n_sites;
+        cur.n[q] = n_sites | (site_pin << 31);
         if (alive || cycle == 0) {
             atomicAdd(&bc.c[3 + code], 1u);
             for (int e = 0; e < 3; ++e)
@@ -156,7 +158,7 @@ __global__ void __launch_bounds__(kScanBlock) k_scan_blocks(const uint32_t *__re
                                                             uint64_t *totals, uint64_t n) {
     __shared__ uint64_t buf[kScanBlock];
     const uint64_t i = (uint64_t)blockIdx.x * kScanBlock + threadIdx.x;
-    buf[threadIdx.x] = (i < n) ? (uint64_t)in[i] : 0ull;
+    buf[threadIdx.x] = (i < n) ? (uint64_t)(in[i] & 0x7FFFFFFFu) : 0ull;   // (bit 31: pin flag)
     __syncthreads();
     for (int off = 1; off < kScanBlock; off <<= 1) {
         const uint64_t v = (threadIdx.x >= (unsigned)off) ? buf[threadIdx.x - off] : 0ull;

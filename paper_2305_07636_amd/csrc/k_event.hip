@@ -55,7 +55,8 @@ constexpr uint32_t kHidMask = 0x0FFFFFFFu;  // history index within a chunk (< 2
 // to a field is one contiguous run and its whole state one contiguous
 // block of HBM (one DRAM stream per wave instead of one per field array).
 // Fields: x, u per stored axis, t, tau, (w), RNG state (8 B each), then
-// the packed cell ix | iy << 11 | iz << 22, g | batch << 5 | k << 15 and
+// the packed cell ix | iy << 11 | iz << 22, g | batch << 5 | k << 15 |
+// inside pin << 31 and
 // the history index within the chunk | crossing axes << 29 (surface queue)
 // (4 B each).
 struct Bank {
@@ -89,8 +90,8 @@ struct Ctl {
     unsigned int G, L;      // segments (= workgroups), slots per segment
 };
 
-__device__ __forceinline__ uint32_t pack_gk(int g, int b, int k) {
-    return (uint32_t)g | ((uint32_t)b << 5) | ((uint32_t)k << 15);
+__device__ __forceinline__ uint32_t pack_gk(int g, int b, int k, int inpin) {
+    return (uint32_t)g | ((uint32_t)b << 5) | ((uint32_t)k << 15) | ((uint32_t)inpin << 31);
 }
 __device__ __forceinline__ uint32_t pack_ix(const int ix[3]) {
     return (uint32_t)ix[0] | ((uint32_t)ix[1] << 11) | ((uint32_t)ix[2] << 22);
@@ -198,7 +199,9 @@ __device__ __forceinline__ void load_state(const DevProblem &P, const Bank &B, u
     p.ix[1] = (c >> 11) & 2047u;
     p.ix[2] = c >> 22;
     p.g = gk & 31u;
-    p.k = gk >> 15;
+    // (a slab has no pins: bit 31 stays clear)
+    p.k = (FM == 1) ? (int)(gk >> 15) : (int)((gk >> 15) & 0xFFFFu);
+    p.inpin = (FM == 1) ? 0 : (int)(gk >> 31);
 }
 
 // The state of one particle as loaded, before any arithmetic on it: lets
@@ -245,7 +248,8 @@ __device__ __forceinline__ void unpack(const DevProblem &P, const RawState &r, P
     p.ix[1] = (r.c >> 11) & 2047u;
     p.ix[2] = r.c >> 22;
     p.g = r.gk & 31u;
-    p.k = r.gk >> 15;
+    p.k = (FM == 1) ? (int)(r.gk >> 15) : (int)((r.gk >> 15) & 0xFFFFu);
+    p.inpin = (FM == 1) ? 0 : (int)(r.gk >> 31);
 }
 
 template <int FM, bool WW>
@@ -269,7 +273,7 @@ __device__ __forceinline__ void store_state(const DevProblem &P, const Bank &B, 
 }
 
 __device__ __forceinline__ uint32_t with_gk(uint32_t gk, const Particle &p) {
-    return (uint32_t)p.g | (gk & (1023u << 5)) | ((uint32_t)p.k << 15);
+    return (uint32_t)p.g | (gk & (1023u << 5)) | ((uint32_t)p.k << 15) | ((uint32_t)p.inpin << 31);
 }
 
 // Weight-window check point of the event kernels: roulette (returns false)
@@ -413,7 +417,7 @@ __global__ void __launch_bounds__(kBlock) k_source(DevProblem P0, RunArgs R0, Ba
             }
         }
         const uint32_t off = block_append(valid && alive, &cN);
-        if (valid && alive) store_state<FM, WW>(P, bank, seg * C.L + off, p, pack_gk(p.g, b, p.k), (uint32_t)r);
+        if (valid && alive) store_state<FM, WW>(P, bank, seg * C.L + off, p, pack_gk(p.g, b, p.k, p.inpin), (uint32_t)r);
         if (R.prof) cnt.prof(valid ? 1u : 0u, (valid && alive) ? state_bytes<FM, WW>(P) : 0u);
     }
     __syncthreads();
@@ -658,7 +662,7 @@ __global__ void __launch_bounds__(kBlock) k_event(DevProblem P0, RunArgs R0, Ban
                             busy = false;
                     }
                 } else {
-                    const int m = P.cell_mat[cell];
+                    const int m = (FM == 1) ? P.cell_mat[cell] : material_of(P, p, cell);
                     int r = collide<FM, WW>(P, p, m);
                     if (WW && r == 2) {
                         // fission: neutrons 1..n-1 to the split bank
@@ -1088,8 +1092,8 @@ void destroy_graph_cache(mcdc_problem *p) {
 int launch_event(mcdc_problem *p, const RunArgs &R, uint64_t first, uint64_t count, const mcdc_run_options &opt,
                  hipStream_t st, Profiler &prof) {
     const DevProblem &P = p->d;
-    if (p->h.B > 1023 || P.K > 131071) {
-        set_error("event form supports at most 1023 batches and 131071 time bins");
+    if (p->h.B > 1023 || P.K > 65535) {
+        set_error("event form supports at most 1023 batches and 65535 time bins");
         return MCDC_E_UNSUPPORTED;
     }
     LdsTables tabs{};

@@ -72,6 +72,12 @@ struct DevProblem {
     // implicit capture with weight roulette (implicit = 0: analog collisions)
     int implicit;
     double roulette_w, roulette_ws;   // threshold, survival weight
+    // cylindrical pins parallel to z, per union cell (pins_on = 0: none)
+    int pins_on;
+    const double *pin_r2;      // [ncells] squared radius of the cell's pin, 0 = none
+    const double *pin_xc;      // [ncells] its centre (the geometry cell's x-y midpoint)
+    const double *pin_yc;
+    const int32_t *pin_mat;    // [ncells] material inside it
 };
 
 // Runs whose particles make progeny (window splits, fission neutrons) or
@@ -176,6 +182,9 @@ struct HostProblem {
     std::vector<double> sigma_t, inv_st, ps, cdf, speed, inv_v, T, src_cdf;
     bool fission = false;
     std::vector<double> pf, nu, chi_cdf;   // [M][G] each (fission only)
+    bool pins = false;
+    std::vector<double> pin_r2, pin_xc, pin_yc;   // [ncells] (pins only)
+    std::vector<int32_t> pin_mat;
     std::vector<uint8_t> qoi_groups;
     std::vector<double> bin_norm;      // [nts] V_j (product of bin widths)
     std::vector<double> time_norm;     // [K] dt_k (1 if infinite)

@@ -325,6 +325,39 @@ int compile(const mcdc_problem_desc *d, HostProblem &h) {
                 h.cell_ww[c] = (wx < 0 || wy < 0 || wz < 0) ? -1 : (wz * h.nw[1] + wy) * h.nw[0] + wx;
                 h.cell_qoi[c] = (q_of[0][ix] && q_of[1][iy] && q_of[2][iz]) ? 1 : 0;
             }
+    // cylindrical pins: per union cell, the pin of its geometry cell
+    if (d->pin_radius) {
+        if (!d->pin_material) return invalid("pins need pin_material");
+        if (d->n_planes[0] == 0 || d->n_planes[1] == 0) return invalid("pins need finite x and y axes");
+        for (size_t g = 0; g < ngeo; ++g) {
+            const int gx = (int)(g % ngc[0]), gy = (int)((g / ngc[0]) % ngc[1]);
+            const double r = d->pin_radius[g];
+            if (!(r >= 0.0) || !std::isfinite(r)) return invalid("pin radius must be finite and >= 0");
+            if (r == 0.0) continue;
+            const double hx = 0.5 * (d->planes[0][gx + 1] - d->planes[0][gx]);
+            const double hy = 0.5 * (d->planes[1][gy + 1] - d->planes[1][gy]);
+            if (!(r < hx) || !(r < hy)) return invalid("a pin must fit inside its cell");
+            if (d->pin_material[g] < 0 || d->pin_material[g] >= M) return invalid("pin material out of range");
+        }
+        h.pins = true;
+        h.pin_r2.assign(ncells, 0.0);
+        h.pin_xc.assign(ncells, 0.0);
+        h.pin_yc.assign(ncells, 0.0);
+        h.pin_mat.assign(ncells, 0);
+        for (int iz = 0; iz < h.nc[2]; ++iz)
+            for (int iy = 0; iy < h.nc[1]; ++iy)
+                for (int ix = 0; ix < h.nc[0]; ++ix) {
+                    const size_t c = ((size_t)iz * h.nc[1] + iy) * h.nc[0] + ix;
+                    const int gx = geo_of[0][ix], gy = geo_of[1][iy], gz = geo_of[2][iz];
+                    const size_t g = ((size_t)gz * ngc[1] + gy) * ngc[0] + gx;
+                    const double r = d->pin_radius[g];
+                    if (!(r > 0.0)) continue;
+                    h.pin_r2[c] = r * r;
+                    h.pin_xc[c] = 0.5 * (d->planes[0][gx] + d->planes[0][gx + 1]);
+                    h.pin_yc[c] = 0.5 * (d->planes[1][gy] + d->planes[1][gy + 1]);
+                    h.pin_mat[c] = d->pin_material[g];
+                }
+    }
 
     // normalisation: bin volume (product of the widths of meshed axes) and
     // time-bin width (1 for an infinite bin)
@@ -359,7 +392,9 @@ int upload(mcdc_problem *p) {
                  o_ps = b.add(h.ps), o_cdf = b.add(h.cdf), o_v = b.add(h.speed),
                  o_iv = b.add(h.inv_v), o_T = b.add(h.T), o_sc = b.add(h.src_cdf),
                  o_qg = b.add(h.qoi_groups), o_bn = b.add(h.bin_norm), o_tn = b.add(h.time_norm),
-                 o_pf = b.add(h.pf), o_nu = b.add(h.nu), o_chi = b.add(h.chi_cdf);
+                 o_pf = b.add(h.pf), o_nu = b.add(h.nu), o_chi = b.add(h.chi_cdf),
+                 o_pr2 = b.add(h.pin_r2), o_pxc = b.add(h.pin_xc), o_pyc = b.add(h.pin_yc),
+                 o_pm = b.add(h.pin_mat);
     std::vector<uint64_t> A(64), C(64);
     lcg_map(kStride, A[0], C[0]);
     for (int j = 1; j < 64; ++j) {
@@ -431,6 +466,11 @@ int upload(mcdc_problem *p) {
     D.ww_max_split = 16;
     D.ww_ratio = 5.0;
     D.fission_on = h.fission ? 1 : 0;
+    D.pins_on = h.pins ? 1 : 0;
+    D.pin_r2 = h.pins ? (const double *)(base + o_pr2) : nullptr;
+    D.pin_xc = h.pins ? (const double *)(base + o_pxc) : nullptr;
+    D.pin_yc = h.pins ? (const double *)(base + o_pyc) : nullptr;
+    D.pin_mat = h.pins ? (const int32_t *)(base + o_pm) : nullptr;
     D.implicit = d.implicit_capture ? 1 : 0;
     D.roulette_w = d.roulette_w;
     D.roulette_ws = d.roulette_ws;

@@ -323,6 +323,20 @@ def reflective_box(sigma_t, sigma_s, speed, size=(2.0, 2.0, 2.0),
                         np.zeros((1, 1, 1)), [REFLECTIVE] * 6, src, tally, fission=fission)
 
 
+def pin_cell_eigen_cylinder(n_groups=7, gen_seed=9, fine=4):
+    """The pin cell of pin_cell_eigen with a cylindrical fuel pin (radius
+    0.54 in the 1.26-wide reflected cell) in place of the square one."""
+    p = pin_cell_eigen(n_groups, gen_seed)
+    planes = [np.array([0.0, 1.26]), np.array([0.0, 1.26]), _empty()]
+    mesh = np.linspace(0.0, 1.26, fine + 1)
+    src = dict(p["source"], lo=_f64([0.63 - 0.3, 0.63 - 0.3, 0.0]), hi=_f64([0.63 + 0.3, 0.63 + 0.3, 0.0]))
+    q = make_problem(p["sigma_t"], p["sigma_s"], p["speed"], planes, np.ones((1, 1, 1), dtype=np.int32),
+                     p["bc"], src, {"mesh": [mesh, mesh, _empty()], "time_edges": [0.0, math.inf],
+                                    "n_batches": 8}, fission=p["fission"])
+    q["pins"] = {"radius": np.array([[[0.54]]]), "material": np.zeros((1, 1, 1), dtype=np.int32)}
+    return q
+
+
 def pin_cell_eigen(n_groups=7, gen_seed=9, fine=3):
     """Box stand-in for a reflected pin cell (Section 3's k-eigenvalue
     performance test uses a C5G7 pin cell, whose data is not used here): a
