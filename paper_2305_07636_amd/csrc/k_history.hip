@@ -635,8 +635,9 @@ int launch_batched(const BatchItem *items, const uint64_t *offs, int n_items, ui
 
 int split_prepare(mcdc_problem *pb, uint64_t chunk, dev::SplitBank SB[2]) {
     // room for eight progeny per history of the chunk in each generation
-    // (64 with fission)
-    const uint64_t want = (pb->d.fission_on ? 64 : 8) * chunk;
+    // (64 with fission; implicit capture alone makes none: the minimum)
+    const uint64_t per = pb->d.fission_on ? 64 : (pb->d.ww_center ? 8 : 0);
+    const uint64_t want = per * chunk;
     const unsigned int cap = (unsigned int)((want < (1u << 22)) ? (1u << 22) : (want > (1u << 26) ? (1u << 26) : want));
     int rc;
     if ((rc = ensure(pb->split, 2 * split_bytes(cap) + 256))) return rc;

@@ -99,3 +99,58 @@ def test_run_rejects_bad_arguments():
     res = b.mcdc_result()
     assert b.lib().mcdc_run(None, 10, 1, None, C.byref(res)) == -1
     assert b.lib().mcdc_problem_destroy(None) == 0
+
+
+def _fis(sf, nu, chi):
+    return {"sigma_f": np.array([[sf]]), "nu": np.array([[nu]]), "chi": np.array([[chi]])}
+
+
+@pytest.mark.parametrize("fission,needle", [
+    (_fis(0.6, 2.0, 1.0), "exceeds"),          # sigma_s 0.5 + sigma_f 0.6 > sigma_t 1
+    (_fis(0.1, 65.0, 1.0), "nu"),
+    (_fis(-0.1, 2.0, 1.0), "sigma_f"),
+    (_fis(0.1, 2.0, 0.9), "chi"),
+])
+def test_invalid_fission_rejected(fission, needle):
+    p = w.reflective_box([1.0], [[0.5]], [1.0], fission=fission)
+    rc, msg = _create(p)
+    assert rc == -1 and needle in msg, (rc, msg)
+
+
+@pytest.mark.parametrize("ic,needle", [
+    ({"w_min": 0.0, "w_survive": 1.0}, "roulette"),
+    ({"w_min": 0.5, "w_survive": 0.25}, "roulette"),
+])
+def test_invalid_implicit_capture_rejected(ic, needle):
+    p = w.reflective_box([1.0], [[0.5]], [1.0])
+    p["implicit_capture"] = ic
+    rc, msg = _create(p)
+    assert rc == -1 and needle in msg, (rc, msg)
+    p = w.reflective_box([1.0], [[0.5]], [1.0], fission=_fis(0.1, 2.0, 1.0))
+    p["implicit_capture"] = {"w_min": 0.25, "w_survive": 1.0}
+    rc, msg = _create(p)
+    assert rc == -1 and "fission" in msg, (rc, msg)
+
+
+def test_invalid_pins_rejected():
+    p = w.pin_lattice(n=1, radius=0.63)                     # wider than half the 1.26 pitch
+    rc, msg = _create(p)
+    assert rc == -1 and "fit" in msg, (rc, msg)
+    p = w.pin_lattice(n=2)
+    p["pins"]["material"] = np.full((1, 2, 2), 7, dtype=np.int32)
+    rc, msg = _create(p)
+    assert rc == -1 and "pin material" in msg, (rc, msg)
+    p = w.cfg2_slab_pulse()                                 # y is not a finite axis
+    p["pins"] = {"radius": np.array([[[0.1] * 50]]), "material": np.zeros((1, 1, 50), dtype=np.int32)}
+    rc, msg = _create(p)
+    assert rc == -1 and "finite" in msg, (rc, msg)
+
+
+def test_invalid_time_crossing_flag_rejected():
+    from paper_2305_07636_amd import _binding as b
+
+    d, keep = b.make_desc(w.cfg2_slab_pulse())
+    d.time_crossing = 2
+    h = C.c_void_p()
+    rc = b.lib().mcdc_problem_create(C.byref(d), C.byref(h))
+    assert rc == -1 and "time_crossing" in b.lib().mcdc_last_error().decode()
