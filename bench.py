@@ -27,7 +27,7 @@ METRIC = "histories/sec + figure of merit 1/(σ²T), plain analog vs learned-WW,
 WORKLOAD = ("pulsed slab: 1 group, Sigma_t=1, c=0.9, v=1, 40 mfp, isotropic centre pulse at t=0, "
             "50 x-bins x 100 time bins on [0,20], 1e7 histories, FP64")
 HBM_PEAK_GBS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_advance_pulsed_slab_1e7_traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_event_step_pulsed_slab_1e7_traffic.json")
 KERNEL_SOURCES = ["paper_2305_07636_amd/csrc/k_event.hip", "paper_2305_07636_amd/csrc/k_common.hpp",
                   "paper_2305_07636_amd/csrc/mcdc_internal.hpp", "paper_2305_07636_amd/build.py"]
 T_START = time.perf_counter()
@@ -92,8 +92,9 @@ def kernel_source_hash():
 
 
 def measured_traffic():
-    """HBM bytes per k_advance launch from the committed FETCH_SIZE /
-    WRITE_SIZE summary, or None if the kernel sources changed since."""
+    """HBM bytes per census-step kernel launch (the event form's k_event
+    over the step's bank) from the committed FETCH_SIZE / WRITE_SIZE
+    summary, or None if the kernel sources changed since."""
     try:
         with open(TRAFFIC_FILE) as fh:
             rec = json.load(fh)
@@ -382,11 +383,12 @@ def main():
     ms, launches, items, nbytes = prof[cls]
     if args.algorithm == "event":
         achieved = nbytes / (ms * 1e-3) / 1e9
-        tr = measured_traffic() if names[cls] == "advance" and N == 10_000_000 else None
+        tr = measured_traffic() if names[cls] == "events" and N == 10_000_000 else None
         roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": achieved / HBM_PEAK_GBS,
                     "traffic": tr["hbm_bytes_per_launch"] if tr else None,
-                    "kernel": f"k_{names[cls]}",
+                    "kernel": "k_event (one census step: every particle of the step's bank to census or death)"
+                              if names[cls] == "events" else f"k_{names[cls]}",
                     "launches": int(launches), "avg_launch_ms": ms / launches,
                     "algorithmic_bytes_per_launch": nbytes / launches,
                     "particles_per_launch": items / launches,
@@ -416,6 +418,15 @@ def main():
         torch.cuda.synchronize()
         extra["history_form_histories_per_s"] = N * args.steps / (time.perf_counter() - t1)
         log("history form timed")
+        # the earlier two-kernel census step (advance, then events), for comparison
+        m.mcdc_run(p, N, seed, algorithm="event", outputs=outs, two_kernel_step=True)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for s in range(args.steps):
+            m.mcdc_run(p, N, seed + s, algorithm="event", outputs=outs, two_kernel_step=True)
+        torch.cuda.synchronize()
+        extra["two_kernel_step_histories_per_s"] = N * args.steps / (time.perf_counter() - t1)
+        log("two-kernel step timed")
     if not args.no_time_crossing:
         # the same workload with the time-crossing tally (flux at the 100
         # time edges) as well: its cost in both forms, against runs without

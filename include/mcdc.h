@@ -196,6 +196,14 @@ typedef struct {
  *                 steps one kernel at a time instead of replaying the
  *                 captured step graphs (graphs are also skipped when a
  *                 profile or debug array is given).
+ *                 bit 1 (MCDC_FLAG_TWO_KERNEL_STEP): event form, run each
+ *                 census step as an advance kernel (one flight for every
+ *                 particle, sorting them into census, surface and
+ *                 collision queues) followed by an events kernel, instead
+ *                 of the default single kernel that takes every particle
+ *                 of the step's bank through its flights to census or
+ *                 death with lane refill.  Same results; kept for
+ *                 comparison.
  *  stream         hipStream_t to run on (NULL = the null stream).  mcdc_run
  *                 synchronises this stream before it returns.
  *  debug_counts   device array [N][5] (census, surface, collision events,
@@ -225,6 +233,7 @@ typedef struct {
  *                 Results do not depend on it beyond summation order.
  */
 #define MCDC_FLAG_EAGER 1
+#define MCDC_FLAG_TWO_KERNEL_STEP 2
 #define MCDC_PROF_CLASSES 5
 #define MCDC_PROF_SOURCE 0     /* event form: source sampling */
 #define MCDC_PROF_ADVANCE 1    /* event form: one flight over the census bank */

@@ -253,7 +253,7 @@ def mcdc_run(p: Problem, n_histories: int, seed: int, algorithm: str = "event",
              block_size: int = 0, bank_capacity: int = 0, segments: int = 0,
              debug: bool = False, outputs=("mean", "var", "raw", "leak_mean", "leak_var"),
              profile=None, eager: bool = False, profile_classes=None, profile_every: int = 0,
-             profile_phase: int = 0):
+             profile_phase: int = 0, two_kernel_step: bool = False):
     """Run n_histories through the GPU tracker.  Returns a dict of torch
     CUDA tensors (mean, var, raw [K, G, nz, ny, nx]; leak_mean, leak_var
     [K, G, 6]; tc_mean, tc_var [K, G, nz, ny, nx] for a problem with the
@@ -282,7 +282,7 @@ def mcdc_run(p: Problem, n_histories: int, seed: int, algorithm: str = "event",
     opt.block_size = block_size
     opt.bank_capacity = bank_capacity
     opt.segments = segments
-    opt.flags = 1 if eager else 0
+    opt.flags = (1 if eager else 0) | (2 if two_kernel_step else 0)
     opt.stream = torch.cuda.current_stream(dev).cuda_stream
     if debug:
         dc = torch.empty((n_histories, 5), dtype=torch.int32, device=dev)

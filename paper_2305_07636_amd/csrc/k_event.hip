@@ -1,32 +1,30 @@
 // Event-based tracking (the second algorithm mode the paper names, Section 2;
-// it gives no design).  Particles live in structure-of-arrays banks in HBM
-// and are sorted after every flight into per-event queues (census, surface,
-// collision) built from wavefront ballots and mbcnt prefix counts.
+// it gives no design).  Particles live in structure-of-arrays banks in HBM,
+// in tiles of one wavefront, and time advances census step by census step
+// (the census grid is the tally time grid, Section 3): the particles alive
+// at the start of a step are one bank, and the census crossers of the step
+// are filed into the next bank.
 //
 // Segment-private pipelines.  Every bank is cut into G segments of L slots,
 // one per workgroup: workgroup b of every kernel works only on segment b,
 // and a particle never leaves the segment it was born in.  Queue appends
-// therefore need no device-wide atomics (one LDS atomic per wave, no
-// contention across the 8 XCDs), and each segment holds a contiguous range
-// of histories, so its particles belong to at most two tally batches.
+// therefore need no device-wide atomics (ballots, mbcnt prefix counts, one
+// LDS atomic per wave; no contention across the 8 XCDs), and each segment
+// holds a contiguous range of histories, so its particles belong to at
+// most two tally batches.
 //
-// Dense queues.  A queue is not a list of slot indices into a big bank (that
-// turns every later read into a sparse gather that pulls whole cache lines
-// for a few bytes): a particle filed into a queue is written whole and
-// contiguously.  The census queue is the next step's bank; the surface and
-// collision queues share one event bank, surface particles filling each
-// segment from the front and collision particles from the back.
-//
-// Time is advanced census step by census step (the census grid is the tally
-// time grid, Section 3).  One step is a fixed kernel sequence, captured once
-// as a graph and replayed:
-//   advance(bank) -> events(event bank: surface queue, then collision queue)
-// advance moves each particle to its next event, scores the track-length
-// tally and files it.  The events kernel applies each queued event (surface
-// crossing or collision) and takes the survivors on to their census or
-// death in registers (the few further events of the step), filing census
-// crossers into the next bank; its lanes refill from the work list as
-// their particles finish.
+// One kernel per census step (default): the events kernel takes the step's
+// bank as its work list; each lane follows its particle through its
+// flights and events (surface crossing, collision) in registers until it
+// reaches the census edge or dies, files census crossers whole into the
+// next bank, and takes the next particle of the list at once, so a wave is
+// never held back by its longest-lived particle.  The step is captured
+// once per bank parity as a graph and replayed K times.  The earlier
+// two-kernel form (kept behind a run flag) first moved every particle one
+// flight (advance), filing it whole into census, surface or collision
+// queues (the surface and collision queues share an event bank, from the
+// front and from the back of each segment), and then applied the queued
+// events; the single kernel saves the event bank's write and re-read.
 //
 // Tally: every particle scored in step k lies in time bin k, so a
 // workgroup touches only the slice [2 batches][G][nts] of the step; when that
@@ -545,7 +543,10 @@ __global__ void __launch_bounds__(kBlock) k_advance(DevProblem P0, RunArgs R0, B
 // left.  Each item starts with its queued event; every later step of it
 // is a flight to the next event and that event.  The event cap counts
 // flights from the item's start.
-template <int FM, bool WW, bool LT, bool BAT, int CLS = MCDC_PROF_EVENTS>
+// (STEP: the whole census step in this one kernel: the work list is the
+// step's bank itself, every item starting with a flight, and particles
+// born in a later time bin pass straight on to the next bank.)
+template <int FM, bool WW, bool LT, bool BAT, int CLS = MCDC_PROF_EVENTS, bool STEP = false>
 __global__ void __launch_bounds__(kBlock) k_event(DevProblem P0, RunArgs R0, Bank ev, Bank next, Ctl C, int par,
                                                   int gn0, SplitBank SB, LdsTables tabs0,
                                                   const BatchItem *__restrict__ items,
@@ -560,13 +561,13 @@ __global__ void __launch_bounds__(kBlock) k_event(DevProblem P0, RunArgs R0, Ban
     const unsigned int seg = blockIdx.x;
     const uint32_t seg0 = seg * C.L;
     const uint32_t seg_end = seg0 + C.L - 1;
-    const unsigned int n_s = C.n_s[seg];
-    const unsigned int n = n_s + C.n_c[seg];
+    const unsigned int n_s = STEP ? 0u : C.n_s[seg];
+    const unsigned int n = STEP ? C.n_bank[par * C.G + seg] : n_s + C.n_c[seg];
     const int step = *C.step;
     const uint64_t first = *C.first;
     cnt.init(red);
     if (threadIdx.x == 0) {
-        cN = C.n_bank[(par ^ 1) * C.G + seg];   // after the advance kernel's census crossers
+        cN = STEP ? 0u : C.n_bank[(par ^ 1) * C.G + seg];   // after the advance kernel's census crossers
         cW = 0u;
     }
     StepScore sc;
@@ -580,7 +581,7 @@ __global__ void __launch_bounds__(kBlock) k_event(DevProblem P0, RunArgs R0, Ban
     uint32_t gk = 0, hid = 0;
     int cell = 0, b = 0, queued = kCensus, mask = 0, since = 0;
     uint64_t i = 0;
-    bool busy = false, exhausted = false;
+    bool busy = false, exhausted = false, waiting = false;
     for (;;) {
         // idle lanes take the next items of the work list
         if (!exhausted) {
@@ -588,10 +589,11 @@ __global__ void __launch_bounds__(kBlock) k_event(DevProblem P0, RunArgs R0, Ban
             const uint32_t w = block_append(need, &cW);
             if (need && w < n) {
                 uint32_t hidw;
-                load_state<FM, WW>(P, ev, (w < n_s) ? seg0 + w : seg_end - (w - n_s), p, gk, hidw);
+                load_state<FM, WW>(P, ev, (STEP || w < n_s) ? seg0 + w : seg_end - (w - n_s), p, gk, hidw);
                 hid = hidw & kHidMask;
-                mask = (int)(hidw >> 29);
-                queued = (w < n_s) ? kSurface : kCollision;
+                mask = STEP ? 0 : (int)(hidw >> 29);
+                queued = STEP ? kCensus : ((w < n_s) ? kSurface : kCollision);
+                waiting = STEP && p.k > step;   // born in a later time bin
                 i = first + hid;
                 b = (gk >> 5) & 1023u;
                 cell = cell_index(P, p.ix);
@@ -603,7 +605,11 @@ __global__ void __launch_bounds__(kBlock) k_event(DevProblem P0, RunArgs R0, Ban
         }
         if (!__any(busy)) break;
         bool to_next = false;
-        if (busy) {
+        if (STEP && busy && waiting) {
+            to_next = true;
+            busy = false;
+            waiting = false;
+        } else if (busy) {
             int evt = queued;
             bool flown = true;
             if (queued == kCensus) {
@@ -876,9 +882,18 @@ int run_event(mcdc_problem *pb, const RunArgs &R0, uint64_t first, uint64_t coun
     Rs.prof = nullptr;
     const int every = opt.profile_every > 1 ? opt.profile_every : 1;
 
+    // one kernel per census step (default), or the advance / events pair
+    const bool one_kernel = (opt.flags & MCDC_FLAG_TWO_KERNEL_STEP) == 0;
     auto enqueue_step = [&](int par, hipStream_t s, Profiler &pr, const RunArgs &Ra) {
         const Bank &cur = L.bank[par];
         const Bank &nxt = L.bank[par ^ 1];
+        if (one_kernel) {
+            launch_timed(pr, MCDC_PROF_EVENTS, k_event<FM, WW, LT, false, MCDC_PROF_EVENTS, true>, dim3(G),
+                         dim3(kBlock), (uint32_t)shmem, s, P, Ra, cur, nxt, L.ctl, par, gn, SB[0], tabs,
+                         (const BatchItem *)nullptr, (const SegInfo *)nullptr);
+            hipLaunchKernelGGL(k_step_end, dim3(1), dim3(1), 0, s, L.ctl);
+            return;
+        }
         launch_timed(pr, MCDC_PROF_ADVANCE, k_advance<FM, WW, LT, false>, dim3(G), dim3(kBlock), (uint32_t)shmem, s, P,
                      Ra, cur, nxt, L.ev, L.ctl, par, gn, SB[0], tabs, (const BatchItem *)nullptr,
                      (const SegInfo *)nullptr);
@@ -904,6 +919,7 @@ int run_event(mcdc_problem *pb, const RunArgs &R0, uint64_t first, uint64_t coun
         key_add(key, SB[0]);
         key_add(key, tabs);
         key_add(key, LT);
+        key_add(key, one_kernel);
         if (key != Gr->key) {
             Gr->clear();
             hipError_t e = hipSuccess;
@@ -982,10 +998,8 @@ int run_batched_steps(const BatchItem *d_items, const SegInfo *d_segs, unsigned 
     for (int q = 0; q < 2 && e == hipSuccess; ++q) {
         e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) break;
-        hipLaunchKernelGGL((k_advance<FM, false, LT, true>), dim3(G), dim3(kBlock), shmem, cs, P0, R0, L.bank[q],
-                           L.bank[q ^ 1], L.ev, L.ctl, q, 0, none, t0, d_items, d_segs);
-        hipLaunchKernelGGL((k_event<FM, false, LT, true>), dim3(G), dim3(kBlock), shmem, cs, P0, R0, L.ev,
-                           L.bank[q ^ 1], L.ctl, q, 0, none, t0, d_items, d_segs);
+        hipLaunchKernelGGL((k_event<FM, false, LT, true, MCDC_PROF_EVENTS, true>), dim3(G), dim3(kBlock), shmem,
+                           cs, P0, R0, L.bank[q], L.bank[q ^ 1], L.ctl, q, 0, none, t0, d_items, d_segs);
         hipLaunchKernelGGL(k_step_end, dim3(1), dim3(1), 0, cs, L.ctl);
         e = hipStreamEndCapture(cs, &graph[q]);
         if (e == hipSuccess) e = hipGraphInstantiate(&exec[q], graph[q], nullptr, nullptr, 0);

@@ -190,7 +190,7 @@ def test_sampled_profile_mixes_graph_and_eager_steps():
 
     p = w.cfg2_slab_pulse()
     h = m.mcdc_problem_create(p)
-    adv = m._binding.PROF_CLASSES.index("advance")
+    adv = m._binding.PROF_CLASSES.index("events")   # the census-step kernel
     try:
         a = m.mcdc_run(h, 200003, 21, algorithm="event")
         full = np.zeros((len(m._binding.PROF_CLASSES), 4))
@@ -198,7 +198,7 @@ def test_sampled_profile_mixes_graph_and_eager_steps():
         total = np.zeros_like(full)
         for phase in range(10):
             prof = np.zeros_like(full)
-            b = m.mcdc_run(h, 200003, 21, algorithm="event", profile=prof, profile_classes=["advance"],
+            b = m.mcdc_run(h, 200003, 21, algorithm="event", profile=prof, profile_classes=["events"],
                            profile_every=10, profile_phase=phase)
             assert prof[adv, 1] == 10 and prof[adv, 0] > 0
             assert np.array_equal(a["events"], b["events"]) and np.array_equal(a["terms"], b["terms"])
@@ -209,3 +209,40 @@ def test_sampled_profile_mixes_graph_and_eager_steps():
     assert np.array_equal(a["events"], c["events"]) and np.array_equal(a["terms"], c["terms"])
     assert full[adv, 1] == 100 and total[adv, 1] == 100
     assert total[adv, 2] == full[adv, 2] and total[adv, 3] == full[adv, 3]
+
+
+TWO_KERNEL = {
+    "pulse_c09": SMALL["pulse_c09"],
+    "lattice17": SMALL["lattice17"],
+    "dogleg": SMALL["dogleg"],
+    "census_heavy": SMALL["census_heavy"],
+    "pins": (lambda: w.pin_lattice(n=3, n_groups=3, gen_seed=22), 3001, 83),
+}
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("case", list(TWO_KERNEL))
+def test_two_kernel_step_parity(case):
+    """The earlier census step (advance, then events), kept behind a flag,
+    against the oracle."""
+    make, N, seed = TWO_KERNEL[case]
+    print(f"[parity] two-kernel step {case} N={N}", flush=True)
+    compare_full(make(), N, seed, "event", two_kernel_step=True)
+
+
+@pytest.mark.gpu
+def test_step_forms_agree_at_full_size():
+    """1e7-history pulsed slab: the one- and two-kernel census steps give the
+    same event and termination totals and the same tallies to rounding."""
+    import paper_2305_07636_amd as m
+    from gpu_common import close
+
+    h = m.mcdc_problem_create(w.cfg2_slab_pulse())
+    try:
+        print("[parity] step forms at 1e7", flush=True)
+        a = m.mcdc_run(h, 10_000_000, 2, algorithm="event", outputs=("mean",))
+        b = m.mcdc_run(h, 10_000_000, 2, algorithm="event", outputs=("mean",), two_kernel_step=True)
+        assert np.array_equal(a["events"], b["events"]) and np.array_equal(a["terms"], b["terms"])
+        close(a["mean"].cpu().numpy(), b["mean"].cpu().numpy())
+    finally:
+        h.close()
