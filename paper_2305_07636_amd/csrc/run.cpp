@@ -7,6 +7,7 @@
 #include <cstring>
 #include <iterator>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -297,9 +298,41 @@ struct Tuned {
     unsigned int seg_len;    // event form: slots per bank segment
 };
 
+// Launch shapes and form choices of batched solves, per batch signature,
+// shared by every thread of the process (lookups and inserts locked).
+std::mutex &cache_mutex() {
+    static std::mutex m;
+    return m;
+}
 std::map<std::string, Tuned> &tune_cache() {
     static std::map<std::string, Tuned> m;
     return m;
+}
+bool tuned_get(const std::string &sig, Tuned &t) {
+    std::lock_guard<std::mutex> g(cache_mutex());
+    auto it = tune_cache().find(sig);
+    if (it == tune_cache().end()) return false;
+    t = it->second;
+    return true;
+}
+void tuned_put(const std::string &sig, const Tuned &t) {
+    std::lock_guard<std::mutex> g(cache_mutex());
+    tune_cache()[sig] = t;
+}
+std::map<std::string, int> &form_cache() {
+    static std::map<std::string, int> m;
+    return m;
+}
+bool form_get(const std::string &sig, int &alg) {
+    std::lock_guard<std::mutex> g(cache_mutex());
+    auto it = form_cache().find(sig);
+    if (it == form_cache().end()) return false;
+    alg = it->second;
+    return true;
+}
+void form_put(const std::string &sig, int alg) {
+    std::lock_guard<std::mutex> g(cache_mutex());
+    form_cache()[sig] = alg;
 }
 
 std::string signature(mcdc_problem *const *ps, int32_t n, const uint64_t *n_hist) {
@@ -363,11 +396,7 @@ int run_batched_event(mcdc_problem *const *ps, int32_t n, const uint64_t *n_hist
     Tuned t{0, 0, (unsigned int)opt.bank_capacity};
     const std::string sig = "event:" + signature(ps, n, n_hist);
     if (!t.seg_len) {
-        auto it = tune_cache().find(sig);
-        if (it != tune_cache().end())
-            t = it->second;
-        else
-            tries.assign(std::begin(cands), std::end(cands));
+        if (!tuned_get(sig, t)) tries.assign(std::begin(cands), std::end(cands));
     }
     size_t bytes = t.seg_len ? event_batched_bytes(n_hist, n, t.seg_len) : 0;
     for (unsigned int c : tries) bytes = std::max(bytes, event_batched_bytes(n_hist, n, c));
@@ -417,7 +446,7 @@ int run_batched_event(mcdc_problem *const *ps, int32_t n, const uint64_t *n_hist
                 t.seg_len = c;
             }
         }
-        tune_cache()[sig] = t;
+        tuned_put(sig, t);
     }
     if ((rc = run_once(t.seg_len, &ms))) return rc;
     return finish_batched(ps, n, n_hist, items, outs, ms, st);
@@ -430,14 +459,13 @@ extern "C" int mcdc_run_batched(mcdc_problem *const *ps, int32_t n, const uint64
     if (opt_in) opt = *opt_in;
     if (opt.algorithm == MCDC_ALG_AUTO) {
         // the faster form for this batch signature, timed once and cached
-        static std::map<std::string, int> form_cache;
         for (int j = 0; j < n; ++j)
             if (!ps[j]) return bad("NULL problem in batch");
         const std::string sig = signature(ps, n, n_hist);
-        auto it = form_cache.find(sig);
         mcdc_run_options o = opt;
-        if (it != form_cache.end()) {
-            o.algorithm = it->second;
+        int alg = 0;
+        if (form_get(sig, alg)) {
+            o.algorithm = alg;
             return mcdc_run_batched(ps, n, n_hist, seeds, &o, outs);
         }
         o.algorithm = MCDC_ALG_EVENT;
@@ -446,7 +474,7 @@ extern "C" int mcdc_run_batched(mcdc_problem *const *ps, int32_t n, const uint64
         const double t_event = outs[0].kernel_ms;
         o.algorithm = MCDC_ALG_HISTORY;
         if ((r = mcdc_run_batched(ps, n, n_hist, seeds, &o, outs))) return r;
-        form_cache[sig] = (outs[0].kernel_ms < t_event) ? MCDC_ALG_HISTORY : MCDC_ALG_EVENT;
+        form_put(sig, (outs[0].kernel_ms < t_event) ? MCDC_ALG_HISTORY : MCDC_ALG_EVENT);
         return MCDC_OK;
     }
     int rc = check_options(opt);
@@ -528,10 +556,7 @@ extern "C" int mcdc_run_batched(mcdc_problem *const *ps, int32_t n, const uint64
     const std::string sig = signature(ps, n, n_hist);
     float ms = 0.f;
     if (!opt.block_size) {
-        auto it = tune_cache().find(sig);
-        if (it != tune_cache().end()) {
-            t = it->second;
-        } else {
+        if (!tuned_get(sig, t)) {
             float best = 1e30f;
             const int blocks[] = {128, 256, 512};
             const int pts[] = {1, 4, 16};
@@ -544,7 +569,7 @@ extern "C" int mcdc_run_batched(mcdc_problem *const *ps, int32_t n, const uint64
                         t = Tuned{bsz, pt, 0u};
                     }
                 }
-            tune_cache()[sig] = t;
+            tuned_put(sig, t);
         }
     }
     if ((rc = run_once(t.block, t.per_thread, &ms))) return rc;
