@@ -59,7 +59,7 @@ extern "C" {
 /* tracking algorithms */
 #define MCDC_ALG_EVENT 0
 #define MCDC_ALG_HISTORY 1
-#define MCDC_ALG_AUTO 2   /* mcdc_run_batched only: the faster form, timed on the first call */
+#define MCDC_ALG_AUTO 2   /* the faster form, timed on the first call (per history count or batch signature) */
 
 typedef struct mcdc_problem mcdc_problem;
 
@@ -184,7 +184,11 @@ typedef struct {
 
 /*
  * Run options (all-zero = defaults).
- *  algorithm      MCDC_ALG_EVENT (default) or MCDC_ALG_HISTORY.
+ *  algorithm      MCDC_ALG_EVENT (default), MCDC_ALG_HISTORY, or
+ *                 MCDC_ALG_AUTO: mcdc_run runs both forms on its first call
+ *                 for a history count (results of the history-form run)
+ *                 and keeps the faster on the problem handle; batched
+ *                 solves keep it per batch signature.
  *  block_size     mcdc_run_batched: threads per block of the persistent
  *                 launch (64..1024, multiple of 64; 0 = autotuned).  The
  *                 kernels of mcdc_run use 256 (history form) and 512

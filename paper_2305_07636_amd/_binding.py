@@ -278,7 +278,7 @@ def mcdc_run(p: Problem, n_histories: int, seed: int, algorithm: str = "event",
             out[name] = t
             setattr(res, name, t.data_ptr())
     opt = mcdc_run_options()
-    opt.algorithm = MCDC_ALG_HISTORY if algorithm == "history" else MCDC_ALG_EVENT
+    opt.algorithm = {"history": MCDC_ALG_HISTORY, "auto": MCDC_ALG_AUTO}.get(algorithm, MCDC_ALG_EVENT)
     opt.block_size = block_size
     opt.bank_capacity = bank_capacity
     opt.segments = segments

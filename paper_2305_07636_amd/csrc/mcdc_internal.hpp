@@ -212,6 +212,9 @@ struct mcdc_problem {
     Buf S, L, qoi_hist, qoi_sums, counters, overflow, bank, queues, split, prof, counters_split, tally_part, work;
     Buf mean, var, raw, leak_mean, leak_var, tc_mean, tc_var;
     void *graph_cache = nullptr;   // captured census steps of the event form
+    // MCDC_ALG_AUTO: the faster form for one history count, once timed
+    uint64_t auto_n = 0;
+    int auto_alg = -1;
 };
 
 namespace mcdc {

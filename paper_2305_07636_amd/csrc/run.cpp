@@ -249,6 +249,25 @@ extern "C" int mcdc_run(mcdc_problem *p, uint64_t n_histories, uint64_t seed, co
     if (n_histories == 0) return bad("n_histories must be > 0");
     mcdc_run_options opt{};
     if (opt_in) opt = *opt_in;
+    if (opt.algorithm == MCDC_ALG_AUTO) {
+        // the faster form for this problem and history count: both forms
+        // run (and are timed) on the first call, the choice is kept on the
+        // handle; the result is the last run's
+        mcdc_run_options o = opt;
+        if (p->auto_alg >= 0 && p->auto_n == n_histories) {
+            o.algorithm = p->auto_alg;
+            return mcdc_run(p, n_histories, seed, &o, out);
+        }
+        o.algorithm = MCDC_ALG_EVENT;
+        int r = mcdc_run(p, n_histories, seed, &o, out);
+        if (r) return r;
+        const double t_event = out->kernel_ms;
+        o.algorithm = MCDC_ALG_HISTORY;
+        if ((r = mcdc_run(p, n_histories, seed, &o, out))) return r;
+        p->auto_alg = (out->kernel_ms < t_event) ? MCDC_ALG_HISTORY : MCDC_ALG_EVENT;
+        p->auto_n = n_histories;
+        return MCDC_OK;
+    }
     int rc = check_options(opt);
     if (rc) return rc;
     HIP_CHECK(hipSetDevice(p->device), "hipSetDevice");

@@ -246,3 +246,28 @@ def test_step_forms_agree_at_full_size():
         close(a["mean"].cpu().numpy(), b["mean"].cpu().numpy())
     finally:
         h.close()
+
+
+@pytest.mark.gpu
+def test_auto_form_choice_single_problem():
+    """algorithm="auto": the first call runs both forms (the result is the
+    history form's) and keeps the faster; later calls with the same history
+    count run that form; every result agrees with the oracle."""
+    import paper_2305_07636_amd as m
+    from gpu_common import close
+
+    p = w.cfg3_lattice()
+    h = m.mcdc_problem_create(p)
+    try:
+        print("[parity] auto form", flush=True)
+        first = m.mcdc_run(h, 20011, 3, algorithm="auto", debug=True)
+        second = m.mcdc_run(h, 20011, 3, algorithm="auto", debug=True)
+        ev = m.mcdc_run(h, 20011, 3, algorithm="event", debug=True)
+        for o in (first, second):
+            assert np.array_equal(o["debug_counts"].cpu().numpy(), ev["debug_counts"].cpu().numpy())
+            close(o["mean"].cpu().numpy(), ev["mean"].cpu().numpy())
+    finally:
+        h.close()
+    import oracle
+    r = oracle.run(p, 20011, 3)
+    assert np.array_equal(first["events"], r["tot"][0:3])
