@@ -90,7 +90,7 @@ def lib():
                                     C.c_void_p]
         _lib.oracle_eigen.restype = C.c_int
         _lib.oracle_eigen.argtypes = [C.c_void_p, C.c_uint64, C.c_int, C.c_int, C.c_uint64,
-                                      C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+                                      C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
         _lib.oracle_trace.restype = C.c_int
         _lib.oracle_trace.argtypes = [C.c_void_p, C.c_uint64, C.c_uint64, C.c_uint64,
                                       C.c_void_p, C.c_int]
@@ -356,12 +356,27 @@ def eigen(prob, N: int, n_inactive: int, n_active: int, seed: int):
     L = np.zeros((n_active, op.K, op.G, 6))
     k = np.zeros(n_inactive + n_active)
     tot = np.zeros(10, dtype=np.uint64)
+    nts = op.ntally // (op.K * op.G)
+    hist = np.zeros((n_inactive + n_active, nts), dtype=np.uint64)
     rc = lib().oracle_eigen(op.ptr(), N, n_inactive, n_active, seed, S.ctypes.data, L.ctypes.data,
-                            k.ctypes.data, tot.ctypes.data)
+                            k.ctypes.data, tot.ctypes.data, hist.ctypes.data)
     if rc != 0:
         raise RuntimeError(f"oracle_eigen failed with code {rc}")
-    return {"S": S, "L": L, "k": k, "tot": tot, "N": N, "n_inactive": n_inactive,
+    return {"S": S, "L": L, "k": k, "tot": tot, "hist": hist, "N": N, "n_inactive": n_inactive,
             "n_active": n_active, "op": op}
+
+
+def source_entropy(hist) -> np.ndarray:
+    """Shannon entropy (bits) of each cycle's fission source over the
+    spatial tally bins: -sum p log2 p over the bins with sites."""
+    hist = np.asarray(hist, dtype=np.float64)
+    out = np.zeros(hist.shape[0])
+    for c, h in enumerate(hist):
+        tot = h.sum()
+        if tot > 0:
+            p = h[h > 0] / tot
+            out[c] = float(-(p * np.log2(p)).sum())
+    return out
 
 
 def eigen_estimates(prob, res) -> dict:

@@ -75,7 +75,9 @@
  *       of s_c) and draws its group from the spectrum of the site's
  *       material, an isotropic direction and an optical depth.  k of a
  *       cycle is M / N.  Flux and leakage are tallied in the active cycles
- *       only, one batch per active cycle.
+ *       only, one batch per active cycle.  Source diagnostic: the sites of
+ *       each cycle counted per spatial tally bin (Shannon entropy of the
+ *       fission source, -sum p log2 p over the bins with sites).
  *   R14 Implicit capture (optional; Section 3 runs the time-dependent
  *       dog-leg duct with it): a collision never absorbs; the weight is
  *       multiplied by Sigma_s/Sigma_t.  If it falls below w_min a draw
@@ -1109,12 +1111,13 @@ int oracle_trace(const oracle_problem *p, uint64_t N, uint64_t seed, uint64_t i,
  * with fission data (no weight windows).  Outputs: raw flux sums
  * S[n_active][ntally] and leak sums L[n_active][K][G][6] of the active
  * cycles (one batch each), k of every cycle k_out[n_inactive + n_active],
- * event and termination totals over all cycles tot[10] (any may be NULL).
+ * event and termination totals over all cycles tot[10], and the sites of
+ * every cycle per spatial tally bin hist[cycles][nts] (any may be NULL).
  * Returns 0, -1 on an invalid problem (or one without fission, or not
  * steady state), -6 if a cycle banks no site.
  */
 int oracle_eigen(const oracle_problem *p, uint64_t N, int n_inactive, int n_active, uint64_t seed,
-                 double *S_out, double *L_out, double *k_out, uint64_t *tot_out)
+                 double *S_out, double *L_out, double *k_out, uint64_t *tot_out, uint64_t *hist)
 {
     ctx C;
     memset(&C, 0, sizeof(C));
@@ -1195,6 +1198,20 @@ int oracle_eigen(const oracle_problem *p, uint64_t N, int n_inactive, int n_acti
         for (uint64_t q = 0; q < N; q++) {
             M += (uint64_t)sn[cur][q];
             cum[q] = M;
+        }
+        if (hist) {
+            const int64_t nts = (int64_t)C.nt[0] * C.nt[1] * C.nt[2];
+            for (uint64_t q = 0; q < N; q++) {
+                if (sn[cur][q] == 0) continue;
+                int t[3], inside = 1;
+                for (int a = 0; a < 3; a++) {
+                    t[a] = (C.ax[a].n == 0) ? 0 : C.ax[a].tal[six[cur][3 * q + a]];
+                    if (t[a] < 0) inside = 0;
+                }
+                if (inside)
+                    hist[(int64_t)c * nts + ((int64_t)t[2] * C.nt[1] + t[1]) * C.nt[0] + t[0]] +=
+                        (uint64_t)sn[cur][q];
+            }
         }
         if (k_out) k_out[c] = (double)M / (double)N;
         if (M == 0) rc = -6;

@@ -8,6 +8,8 @@ k = (nu Sigma_f)^T M^-1 chi with M = diag(Sigma_t) - Sigma_s^T, and the
 flux per source neutron is M^-1 chi / V.  Bare slab: the discrete-ordinates
 power iteration of refs.sn_slab_k (2 000 cells, S64; refinement moves k by
 3e-6)."""
+import math
+
 import numpy as np
 import pytest
 
@@ -82,3 +84,26 @@ def test_eigen_rejects_non_steady_or_non_fissile():
         oracle.eigen(w.cfg2_slab_pulse(), 100, 1, 2, 1)
     with pytest.raises(RuntimeError):
         oracle.eigen(w.cfg1_slab_steady(), 100, 1, 2, 1)
+
+
+def test_source_entropy():
+    """Sites per spatial bin: they add up to k N in every cycle; one bin
+    gives entropy 0 exactly; a uniform infinite medium on a 2 x 2 x 2 mesh
+    gives log2(8) = 3 bits up to the small-sample bias (8 - 1) / (2 M ln 2);
+    in the bare slab the first cycle (a point source at the centre) is less
+    spread than the converged source."""
+    p = w.reflective_box([1.0], [[0.5]], [1.0], fission={"sigma_f": [[0.2]], "nu": [[2.5]], "chi": [[1.0]]})
+    r = oracle.eigen(p, 20000, 2, 3, 84)
+    assert np.array_equal(r["hist"].sum(axis=1), np.round(r["k"] * 20000).astype(np.uint64))
+    assert (oracle.source_entropy(r["hist"]) == 0.0).all()          # the box has one tally bin
+    for a in range(3):
+        p["tally"]["mesh"][a] = np.array([0.0, 1.0, 2.0])
+    r = oracle.eigen(p, 20000, 2, 3, 85)
+    H = oracle.source_entropy(r["hist"])
+    M = r["hist"].sum(axis=1)
+    bias = 7.0 / (2.0 * M * math.log(2.0))
+    assert (np.abs(H - (3.0 - bias)) < 5e-3).all(), H
+    p = w.bare_slab_eigen()
+    r = oracle.eigen(p, 20000, 10, 5, 86)
+    H = oracle.source_entropy(r["hist"])
+    assert H[0] < H[-1] - 0.5, H
