@@ -386,15 +386,20 @@ int mcdc_run_batched(mcdc_problem *const *ps, int32_t n, const uint64_t *n_hist,
  * Outputs: out->mean/var/raw and leak_mean/leak_var over the active cycles
  * (one batch per cycle; per cycle-source particle), event and termination
  * totals over all cycles, out->k_mean and out->k_std (standard error over
- * the active cycles), and k of every cycle in the host array
- * k_cycle[n_inactive + n_active] (or NULL).  n_per_cycle in [1, 2^30],
+ * the active cycles), k of every cycle in the host array
+ * k_cycle[n_inactive + n_active] (or NULL), and, as the source diagnostic,
+ * the sites of every cycle per spatial tally bin in the host array
+ * source_hist[n_inactive + n_active][nz][ny][nx] and their Shannon entropy
+ * -sum p log2 p (bits) in entropy[n_inactive + n_active] (either may be
+ * NULL; sites outside the mesh are not counted).  n_per_cycle in [1, 2^30],
  * n_active in [1, 1023].  Errors: MCDC_E_INVALID for a problem without
  * fission or not steady state, or a cycle that banks no site;
  * MCDC_E_UNSUPPORTED with weight windows, a detector, debug or profile
  * arrays.  opt->algorithm is not used (one thread per particle).
  */
 int mcdc_run_eigenvalue(mcdc_problem *p, uint64_t n_per_cycle, int32_t n_inactive, int32_t n_active,
-                        uint64_t seed, const mcdc_run_options *opt, mcdc_result *out, double *k_cycle);
+                        uint64_t seed, const mcdc_run_options *opt, mcdc_result *out, double *k_cycle,
+                        uint64_t *source_hist, double *entropy);
 
 /*
  * Set weight-window centres for later runs.  The paper runs analog only

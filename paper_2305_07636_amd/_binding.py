@@ -468,13 +468,16 @@ def mcdc_run_eigenvalue(p: Problem, n_per_cycle: int, n_inactive: int, n_active:
                         outputs=("mean", "var", "leak_mean", "leak_var")):
     """k-eigenvalue power iteration on the GPU.  Returns a dict like
     mcdc_run (flux and leakage over the active cycles, totals over all
-    cycles) plus 'k' (every cycle), 'k_mean' and 'k_std'."""
+    cycles) plus 'k' (every cycle), 'k_mean', 'k_std', and the fission
+    source per cycle: 'source_hist' (sites per spatial tally bin) and its
+    Shannon 'entropy' (bits)."""
     import torch
 
     L = lib()
     if not getattr(L, "_eigen_ready", False):
         L.mcdc_run_eigenvalue.argtypes = [C.c_void_p, C.c_uint64, C.c_int32, C.c_int32, C.c_uint64,
-                                          C.POINTER(mcdc_run_options), C.POINTER(mcdc_result), _DP]
+                                          C.POINTER(mcdc_run_options), C.POINTER(mcdc_result), _DP,
+                                          C.c_void_p, _DP]
         L.mcdc_run_eigenvalue.restype = C.c_int
         L._eigen_ready = True
     dev = torch.device("cuda", torch.cuda.current_device())
@@ -493,8 +496,13 @@ def mcdc_run_eigenvalue(p: Problem, n_per_cycle: int, n_inactive: int, n_active:
     opt = mcdc_run_options()
     opt.stream = torch.cuda.current_stream(dev).cuda_stream
     k = np.zeros(n_inactive + n_active)
+    nts = p.tally_shape[2] * p.tally_shape[3] * p.tally_shape[4]
+    hist = np.zeros((n_inactive + n_active, nts), dtype=np.uint64)
+    ent = np.zeros(n_inactive + n_active)
     _check(L.mcdc_run_eigenvalue(p.handle, int(n_per_cycle), int(n_inactive), int(n_active), int(seed),
-                                 C.byref(opt), C.byref(res), _dp(k)))
+                                 C.byref(opt), C.byref(res), _dp(k), hist.ctypes.data, _dp(ent)))
+    out["source_hist"] = hist
+    out["entropy"] = ent
     out["events"] = np.array(res.n_events[:], dtype=np.uint64)
     out["terms"] = np.array(res.n_term[:], dtype=np.uint64)
     out["k"] = k

@@ -37,7 +37,8 @@ struct EigenCounters {
 
 template <int FM>
 __global__ void __launch_bounds__(256) k_eigen_cycle(DevProblem P, RunArgs R, uint64_t N, uint64_t seed, int cycle,
-                                                     int active, int b, Sites prev, Sites cur, int *no_sites) {
+                                                     int active, int b, Sites prev, Sites cur, int *no_sites,
+                                                     unsigned long long *hist) {
     __shared__ EigenCounters bc;
     if (threadIdx.x < kCounters) bc.c[threadIdx.x] = 0u;
     __syncthreads();
@@ -125,6 +126,10 @@ __global__ void __launch_bounds__(256) k_eigen_cycle(DevProblem P, RunArgs R, ui
                         for (int a = 0; a < 3; ++a) cur.x[q * 3 + a] = p.x[a];
                         cur.ixyz[q] = (uint32_t)p.ix[0] | ((uint32_t)p.ix[1] << 11) | ((uint32_t)p.ix[2] << 22);
                         site_pin = (uint32_t)p.inpin;
+                        // the cycle's sites per spatial tally bin (integer: exact in any order)
+                        const int tb = P.cell_tal[cell];
+                        if (n_sites && tb >= 0)
+                            atomicAdd(hist + (int64_t)cycle * P.nts + tb, (unsigned long long)n_sites);
                         code = kAbsorb;
                     } else if (r == 0) {
                         code = kAbsorb;
@@ -218,7 +223,7 @@ Sites carve_sites(char *&p, uint64_t N) {
 
 template <int FM>
 int run_eigen(const DevProblem &P, const RunArgs &R, uint64_t N, int n_inactive, int n_active, uint64_t seed,
-              void *mem, uint64_t *m_dev, int *no_sites, hipStream_t st) {
+              void *mem, uint64_t *m_dev, int *no_sites, unsigned long long *hist, hipStream_t st) {
     char *p = (char *)mem;
     Sites s[2] = {carve_sites(p, N), carve_sites(p, N)};
     uint64_t *totals = (uint64_t *)p;
@@ -228,7 +233,7 @@ int run_eigen(const DevProblem &P, const RunArgs &R, uint64_t N, int n_inactive,
         const Sites &prev = s[(c + 1) & 1], &cur = s[c & 1];
         const int active = c >= n_inactive;
         hipLaunchKernelGGL(k_eigen_cycle<FM>, dim3(grid), dim3(256), 0, st, P, R, N, seed, c, active,
-                           active ? c - n_inactive : 0, prev, cur, no_sites);
+                           active ? c - n_inactive : 0, prev, cur, no_sites, hist);
         hipLaunchKernelGGL(k_scan_blocks, dim3((unsigned)nb), dim3(kScanBlock), 0, st, (const uint32_t *)cur.n,
                            cur.cum, totals, N);
         hipLaunchKernelGGL(k_scan_totals, dim3(1), dim3(kScanBlock), 0, st, totals, nb);
@@ -248,10 +253,10 @@ size_t eigen_bytes(uint64_t N) {
 }
 
 int launch_eigen(const DevProblem &P, const RunArgs &R, uint64_t N, int n_inactive, int n_active, uint64_t seed,
-                 void *mem, uint64_t *m_dev, int *no_sites, hipStream_t st) {
-    if (P.finite_mask == 1) return run_eigen<1>(P, R, N, n_inactive, n_active, seed, mem, m_dev, no_sites, st);
-    if (P.finite_mask == 7) return run_eigen<7>(P, R, N, n_inactive, n_active, seed, mem, m_dev, no_sites, st);
-    return run_eigen<0>(P, R, N, n_inactive, n_active, seed, mem, m_dev, no_sites, st);
+                 void *mem, uint64_t *m_dev, int *no_sites, unsigned long long *hist, hipStream_t st) {
+    if (P.finite_mask == 1) return run_eigen<1>(P, R, N, n_inactive, n_active, seed, mem, m_dev, no_sites, hist, st);
+    if (P.finite_mask == 7) return run_eigen<7>(P, R, N, n_inactive, n_active, seed, mem, m_dev, no_sites, hist, st);
+    return run_eigen<0>(P, R, N, n_inactive, n_active, seed, mem, m_dev, no_sites, hist, st);
 }
 
 }  // namespace mcdc

@@ -243,11 +243,12 @@ int launch_qoi_reduce(const double *qoi_hist, uint64_t n, double *qoi_sums, hipS
 // and prepared RunArgs; the launcher fills their table layouts).
 size_t event_batched_bytes(const uint64_t *n_hist, int n, unsigned int seg_len);
 // k-eigenvalue cycles (k_eigen.hip): device memory for N particles per
-// cycle, and the cycle loop (M of every cycle into m_dev[cycles]; *no_sites
-// set if a cycle banked no site).
+// cycle, and the cycle loop (M of every cycle into m_dev[cycles]; the
+// sites of every cycle per spatial tally bin added into hist[cycles][nts];
+// *no_sites set if a cycle banked no site).
 size_t eigen_bytes(uint64_t N);
 int launch_eigen(const DevProblem &P, const RunArgs &R, uint64_t N, int n_inactive, int n_active, uint64_t seed,
-                 void *mem, uint64_t *m_dev, int *no_sites, hipStream_t st);
+                 void *mem, uint64_t *m_dev, int *no_sites, unsigned long long *hist, hipStream_t st);
 int launch_event_batched(std::vector<BatchItem> &items, const uint64_t *n_hist, unsigned int seg_len, void *mem,
                          size_t mem_bytes, hipStream_t st);
 

@@ -600,7 +600,7 @@ extern "C" int mcdc_run_batched(mcdc_problem *const *ps, int32_t n, const uint64
 // ---------------------------------------------------------------------------
 extern "C" int mcdc_run_eigenvalue(mcdc_problem *p, uint64_t n_per_cycle, int32_t n_inactive, int32_t n_active,
                                    uint64_t seed, const mcdc_run_options *opt_in, mcdc_result *out,
-                                   double *k_cycle) {
+                                   double *k_cycle, uint64_t *source_hist, double *entropy) {
     if (!p) return bad("problem is NULL");
     if (!out) return bad("result is NULL");
     if (n_per_cycle == 0 || n_per_cycle > (1ULL << 30)) return bad("n_per_cycle must be in [1, 2^30]");
@@ -629,17 +629,23 @@ extern "C" int mcdc_run_eigenvalue(mcdc_problem *p, uint64_t n_per_cycle, int32_
     if ((rc = prepare(p, n_tally, seed, opt, st, R, n_active))) return rc;
     const int C = n_inactive + n_active;
     const size_t mb = eigen_bytes(n_per_cycle);
-    if ((rc = ensure(p->work, mb + (size_t)C * sizeof(uint64_t) + 256))) return rc;
+    const size_t mbytes = ((size_t)C * sizeof(uint64_t) + 255) & ~size_t(255);
+    const size_t hbytes = (size_t)C * P.nts * sizeof(uint64_t);
+    if ((rc = ensure(p->work, mb + mbytes + hbytes + 256))) return rc;
     uint64_t *m_dev = (uint64_t *)((char *)p->work.p + mb);
+    unsigned long long *hist = (unsigned long long *)((char *)p->work.p + mb + mbytes);
+    ZERO(hist, hbytes);
     int *no_sites = R.overflow;
-    if ((rc = launch_eigen(P, R, n_per_cycle, n_inactive, n_active, seed, p->work.p, m_dev, no_sites, st))) return rc;
+    if ((rc = launch_eigen(P, R, n_per_cycle, n_inactive, n_active, seed, p->work.p, m_dev, no_sites, hist, st)))
+        return rc;
     Profiler none;
     if ((rc = fold(p, R, out, st, none))) return rc;
     HIP_CHECK(hipEventRecord(ev.b, st), "hipEventRecord");
     Collect c{};
     if ((rc = collect_begin(p, out, c, st))) return rc;
-    std::vector<uint64_t> m(C);
+    std::vector<uint64_t> m(C), h((size_t)C * P.nts);
     HIP_CHECK(hipMemcpyAsync(m.data(), m_dev, C * sizeof(uint64_t), hipMemcpyDeviceToHost, st), "copy sites");
+    HIP_CHECK(hipMemcpyAsync(h.data(), hist, hbytes, hipMemcpyDeviceToHost, st), "copy source histogram");
     HIP_CHECK(hipStreamSynchronize(st), "hipStreamSynchronize");
     if (c.ovf) {
         set_error("a cycle banked no fission site");
@@ -661,5 +667,20 @@ extern "C" int mcdc_run_eigenvalue(mcdc_problem *p, uint64_t n_per_cycle, int32_
         acc += d * d;
     }
     out->k_std = n_active > 1 ? std::sqrt(acc / ((double)(n_active - 1) * n_active)) : 0.0;
+    if (source_hist) std::memcpy(source_hist, h.data(), hbytes);
+    if (entropy)
+        for (int j = 0; j < C; ++j) {
+            // Shannon entropy of the cycle's sites over the spatial bins
+            const uint64_t *hj = h.data() + (size_t)j * P.nts;
+            double tot = 0.0;
+            for (int t = 0; t < P.nts; ++t) tot += (double)hj[t];
+            double e = 0.0;
+            for (int t = 0; t < P.nts && tot > 0.0; ++t)
+                if (hj[t]) {
+                    const double q = (double)hj[t] / tot;
+                    e -= q * std::log2(q);
+                }
+            entropy[j] = e;
+        }
     return MCDC_OK;
 }

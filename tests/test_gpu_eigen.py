@@ -62,6 +62,9 @@ def test_eigen_parity(case):
     close(g["leak_mean"], e["leak_mean"], what="leak")
     close(g["leak_var"], e["leak_var"], rtol=VAR_RTOL, what="leak var")
     close([g["k_mean"], g["k_std"]], [e["k_mean"], e["k_std"]], rtol=1e-12, what="k statistics")
+    # the fission source per cycle: sites per bin bit-exact, entropy to rounding
+    assert np.array_equal(g["source_hist"], r["hist"])
+    close(g["entropy"], oracle.source_entropy(r["hist"]), rtol=1e-12, what="source entropy")
 
 
 @pytest.mark.gpu

@@ -92,6 +92,7 @@ def test_pin_cell_eigenvalue_parity():
     e = oracle.eigen_estimates(p, r)
     assert np.array_equal(g["k"], r["k"])
     assert np.array_equal(g["events"], r["tot"][0:3])
+    assert np.array_equal(g["source_hist"], r["hist"])
     close(g["mean"], e["mean"], what="flux")
     close(g["var"], e["var"], rtol=VAR_RTOL, what="flux var")
 
