@@ -154,3 +154,20 @@ def test_invalid_time_crossing_flag_rejected():
     h = C.c_void_p()
     rc = b.lib().mcdc_problem_create(C.byref(d), C.byref(h))
     assert rc == -1 and "time_crossing" in b.lib().mcdc_last_error().decode()
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    """Without the built HIP library the binding raises instead of falling
+    back to any CPU path (a fresh interpreter, so the loaded library of this
+    session is not reused)."""
+    import subprocess
+    import sys
+
+    code = ("import paper_2305_07636_amd._binding as b\n"
+            f"b.LIB_PATH = {str(tmp_path / 'absent.so')!r}\n"
+            "try:\n"
+            "    b.lib()\n"
+            "except ImportError as e:\n"
+            "    print('raised', e)\n")
+    r = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True, timeout=120)
+    assert "raised" in r.stdout and "is not built" in r.stdout, (r.stdout, r.stderr)
