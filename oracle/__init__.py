@@ -91,6 +91,12 @@ def lib():
         _lib.oracle_eigen.restype = C.c_int
         _lib.oracle_eigen.argtypes = [C.c_void_p, C.c_uint64, C.c_int, C.c_int, C.c_uint64,
                                       C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
+        _lib.oracle_run_pc.restype = C.c_int
+        _lib.oracle_run_pc.argtypes = [C.c_void_p, C.c_uint64, C.c_uint64, C.c_uint64,
+                                       C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                       C.c_void_p]
+        _lib.oracle_q64_sum.restype = C.c_int
+        _lib.oracle_q64_sum.argtypes = [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]
         _lib.oracle_trace.restype = C.c_int
         _lib.oracle_trace.argtypes = [C.c_void_p, C.c_uint64, C.c_uint64, C.c_uint64,
                                       C.c_void_p, C.c_int]
@@ -268,6 +274,37 @@ def run(prob, N: int, seed: int, ids=None, first: int = 0, count=None,
         out["rec"] = rec
         out["trk"] = trk
     return out
+
+
+def run_pc(prob, N: int, seed: int, target: int):
+    """An N-history run with population control at every census edge
+    (splitting-roulette to `target` particles, the oracle's reading R16).
+    Returns the dict of ``run`` (no detector, no records) plus 'pop' [K]:
+    particles alive at each edge T_k after the control (pop[0]: born)."""
+    op = prob if isinstance(prob, OracleProblem) else OracleProblem(prob)
+    B = max(1, min(op.B, N))
+    S = np.zeros((B, op.ntally))
+    X = np.zeros((B, op.ntally))
+    L = np.zeros((B, op.K, op.G, 6))
+    tot = np.zeros(10, dtype=np.uint64)
+    pop = np.zeros(op.K, dtype=np.uint64)
+    rc = lib().oracle_run_pc(op.ptr(), N, seed, target, S.ctypes.data, L.ctypes.data,
+                             tot.ctypes.data, X.ctypes.data, pop.ctypes.data)
+    if rc != 0:
+        raise RuntimeError(f"oracle_run_pc failed with code {rc}")
+    return {"S": S, "X": X, "L": L, "q": np.zeros(2), "tot": tot, "N": N, "B": B, "op": op,
+            "pop": pop}
+
+
+def q64_sum(w) -> tuple:
+    """The oracle's exact fixed-point weight sum (R16): ((hi, lo), value)."""
+    w = np.ascontiguousarray(np.asarray(w, dtype=np.float64))
+    out = np.zeros(2, dtype=np.uint64)
+    val = C.c_double(0.0)
+    rc = lib().oracle_q64_sum(w.ctypes.data, w.size, out.ctypes.data, C.byref(val))
+    if rc != 0:
+        raise ValueError("weight of 2^32 or more, or not a finite non-negative number")
+    return (int(out[0]), int(out[1])), val.value
 
 
 def bin_volumes(prob) -> np.ndarray:

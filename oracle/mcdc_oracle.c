@@ -96,6 +96,22 @@
  *       else (or a = 0) none; clipped at 0.  Tie order: census, planes,
  *       cylinder, collision.  A cylinder crossing is a surface event that
  *       crosses no plane and flips the flag.  Birth: inside iff c < 0.
+ *   R16 Population control at census (optional; Section 2 lists population
+ *       control among the time-dependent features, without a method):
+ *       splitting-roulette to a target population N_t.  The run tracks all
+ *       particles census step by census step.  At each census edge T_k
+ *       (k < K) the particles that just crossed it are controlled together;
+ *       particles born later are not touched.  Their total weight W is
+ *       summed exactly, order-free, in 128-bit fixed point with 64
+ *       fractional bits (each weight truncated to a multiple of 2^-64; a
+ *       weight of 2^32 or more is an error).  W becomes a double as
+ *       hi + ((lo >> 32) 2^-32 + (lo mod 2^32) 2^-64), and w_t = W / N_t.
+ *       Each crosser, in any order, draws xi and makes
+ *       n = floor(w / w_t + xi) copies of weight w_t (n = 0: the particle
+ *       ends, rouletted).  Copy 0 keeps the stream after the draw; copy
+ *       j >= 1 takes child_stream of that state and j (as R10's splits) and
+ *       counts as a split.  W = 0: nothing happens.  Analog tracking with
+ *       optional implicit capture only (no windows, fission or detector).
  *
  * Build: gcc -O2 -ffp-contract=off -fPIC -shared -o liboracle.so mcdc_oracle.c -lm
  */
@@ -1045,6 +1061,190 @@ int oracle_run(const oracle_problem *p, uint64_t N, uint64_t seed,
     }
     if (tot_out)
         for (int j = 0; j < 10; j++) tot_out[j] += C.tot[j];
+    free(stack);
+    ctx_free(&C);
+    return rc;
+}
+
+/* R16: w truncated to a multiple of 2^-64, as a 128-bit integer (hi, lo),
+ * added to (*hi, *lo).  Returns 0, or -1 if w is 2^32 or more (or not a
+ * finite non-negative number). */
+static int q64_add(uint64_t *hi, uint64_t *lo, double w)
+{
+    if (!(w >= 0.0) || !(w < 4294967296.0)) return -1;
+    uint64_t bits;
+    memcpy(&bits, &w, sizeof bits);
+    int e = (int)((bits >> 52) & 0x7FF);
+    if (e == 0) return 0;  /* zero or below 2^-1022: truncates to 0 */
+    uint64_t m = (bits & ((1ULL << 52) - 1)) | (1ULL << 52);
+    /* w = m 2^(e - 1075), so w 2^64 = m 2^(e - 1011) */
+    int sh = e - 1011;
+    uint64_t h = 0, l = 0;
+    if (sh >= 64) {
+        h = m << (sh - 64);
+    } else if (sh > 0) {
+        h = m >> (64 - sh);
+        l = m << sh;
+    } else if (sh == 0) {
+        l = m;
+    } else if (sh > -64) {
+        l = m >> (-sh);
+    }
+    uint64_t nl = *lo + l;
+    *hi += h + (nl < *lo ? 1u : 0u);
+    *lo = nl;
+    return 0;
+}
+
+/* R16: the exact fixed-point sum of n weights (out[0] = hi, out[1] = lo)
+ * and its double value.  Returns 0, or -1 as q64_add. */
+int oracle_q64_sum(const double *w, int64_t n, uint64_t *out, double *value)
+{
+    uint64_t hi = 0, lo = 0;
+    for (int64_t i = 0; i < n; i++)
+        if (q64_add(&hi, &lo, w[i]) != 0) return -1;
+    out[0] = hi;
+    out[1] = lo;
+    *value = (double)hi + ((double)(lo >> 32) * 0x1p-32 + (double)(lo & 0xFFFFFFFFULL) * 0x1p-64);
+    return 0;
+}
+
+typedef struct {
+    particle pt;
+    int b;
+} pc_entry;
+
+typedef struct {
+    pc_entry *e;
+    size_t n, cap;
+} pc_list;
+
+static int pc_push(pc_list *L, const particle *pt, int b)
+{
+    if (L->n == L->cap) {
+        size_t cap = L->cap ? 2 * L->cap : 1024;
+        pc_entry *e = (pc_entry *)realloc(L->e, cap * sizeof(pc_entry));
+        if (!e) return -1;
+        L->e = e;
+        L->cap = cap;
+    }
+    L->e[L->n].pt = *pt;
+    L->e[L->n].b = b;
+    L->n++;
+    return 0;
+}
+
+/* R16: an N-history run with population control to `target` particles at
+ * every census edge.  Outputs as oracle_run (totals: roulette terminations
+ * include the controlled-away particles, splits the extra copies); pop[k]
+ * (k = 0..K-1, may be NULL) receives the particles alive at T_k after the
+ * control (pop[0]: particles born).  Returns 0, -1 invalid problem, -3 a
+ * problem with windows, fission or a detector, -4 a weight of 2^32 or more,
+ * -2 out of memory. */
+int oracle_run_pc(const oracle_problem *p, uint64_t N, uint64_t seed, uint64_t target,
+                  double *S_out, double *L_out, uint64_t *tot_out, double *X_out, uint64_t *pop)
+{
+    if (p->ww_center || p->sigma_f || p->qoi_on || target == 0) return -3;
+    ctx C;
+    if (ctx_init(&C, p) != 0) {
+        ctx_free(&C);
+        return -1;
+    }
+    int64_t B = p->n_batches;
+    if ((uint64_t)B > N) B = (int64_t)N;
+    if (B < 1) B = 1;
+    const int G = p->G;
+    C.S = (double *)calloc((size_t)(B * C.ntally), sizeof(double));
+    C.Sc = (double *)calloc((size_t)(B * C.ntally), sizeof(double));
+    C.X = (double *)calloc((size_t)(B * C.ntally), sizeof(double));
+    C.Xc = (double *)calloc((size_t)(B * C.ntally), sizeof(double));
+    C.L = (double *)calloc((size_t)(B * C.K * G * 6), sizeof(double));
+    C.Lc = (double *)calloc((size_t)(B * C.K * G * 6), sizeof(double));
+    particle *stack = (particle *)malloc(sizeof(particle) * STACK_MAX);
+    pc_list cur = {0}, nxt = {0};
+    int rc = 0;
+    hist_rec h;
+    uint64_t s0 = seed & MASK63;
+    if (pop)
+        for (int k = 0; k < C.K; k++) pop[k] = 0;
+    /* every history is born first, in order */
+    for (uint64_t i = 0; i < N && rc == 0; i++) {
+        int b = (int)(((i + 1) * (uint64_t)B - 1) / N);
+        memset(&h, 0, sizeof(h));
+        particle pt;
+        if (birth(&C, oracle_rng_skip(s0, i * LCG_STRIDE), &pt, &h)) {
+            if (pc_push(&cur, &pt, b)) rc = -2;
+            if (pop) pop[0]++;
+        }
+    }
+    for (int k = 0; k < C.K && rc == 0; k++) {
+        nxt.n = 0;
+        /* census step k: track every particle of time bin k to T_{k+1} */
+        for (size_t r = 0; r < cur.n && rc == 0; r++) {
+            particle pt = cur.e[r].pt;
+            const int b = cur.e[r].b;
+            if (pt.k == k) {
+                int sp = 0, alive;
+                memset(&h, 0, sizeof(h));
+                do {
+                    alive = step(&C, &pt, b, stack, &sp, &h, NULL);
+                } while (alive > 0 && pt.k == k);
+                if (alive < 0 || sp != 0) rc = -3;
+                if (alive <= 0) continue;
+            }
+            if (pc_push(&nxt, &pt, b)) rc = -2;
+        }
+        if (rc) break;
+        /* control at T_{k+1} over its crossers (those with clock k + 1) */
+        uint64_t hi = 0, lo = 0;
+        for (size_t r = 0; r < nxt.n; r++)
+            if (nxt.e[r].pt.k == k + 1 && q64_add(&hi, &lo, nxt.e[r].pt.w) != 0) rc = -4;
+        if (rc) break;
+        cur.n = 0;
+        const double W = (double)hi + ((double)(lo >> 32) * 0x1p-32 + (double)(lo & 0xFFFFFFFFULL) * 0x1p-64);
+        const double wt = W / (double)target;
+        uint64_t alive_at = 0;
+        for (size_t r = 0; r < nxt.n && rc == 0; r++) {
+            particle pt = nxt.e[r].pt;
+            const int b = nxt.e[r].b;
+            if (pt.k != k + 1 || (hi == 0 && lo == 0)) {
+                if (pc_push(&cur, &pt, b)) rc = -2;
+                if (pt.k == k + 1) alive_at++;
+                continue;
+            }
+            double xi = rn(&pt.s);
+            double nr = floor(pt.w / wt + xi);
+            uint64_t n = (uint64_t)nr;
+            if (n == 0) {
+                C.tot[3 + T_ROULETTE]++;
+                continue;
+            }
+            pt.w = wt;
+            const uint64_t sf = pt.s;
+            for (uint64_t j = 0; j < n && rc == 0; j++) {
+                particle c = pt;
+                if (j > 0) {
+                    c.s = splitmix64(sf ^ j) & MASK63;
+                    C.tot[8]++;
+                }
+                if (pc_push(&cur, &c, b)) rc = -2;
+            }
+            alive_at += n;
+        }
+        if (pop && k + 1 < C.K) pop[k + 1] = alive_at;
+    }
+    if (rc == 0) {
+        if (S_out)
+            for (int64_t j = 0; j < B * C.ntally; j++) S_out[j] += C.S[j] + C.Sc[j];
+        if (X_out)
+            for (int64_t j = 0; j < B * C.ntally; j++) X_out[j] += C.X[j] + C.Xc[j];
+        if (L_out)
+            for (int64_t j = 0; j < B * C.K * G * 6; j++) L_out[j] += C.L[j] + C.Lc[j];
+        if (tot_out)
+            for (int j = 0; j < 10; j++) tot_out[j] += C.tot[j];
+    }
+    free(cur.e);
+    free(nxt.e);
     free(stack);
     ctx_free(&C);
     return rc;
