@@ -35,7 +35,7 @@
 extern "C" {
 #endif
 
-#define MCDC_ABI_VERSION 2
+#define MCDC_ABI_VERSION 3
 
 /* return codes */
 #define MCDC_OK 0
@@ -235,6 +235,25 @@ typedef struct {
  *                 event kernel (0 = auto: 2 per compute unit, or fewer if
  *                 the advance kernel cannot hold that many resident).
  *                 Results do not depend on it beyond summation order.
+ *  pc_target      event form: population control at census (0 = off).  The
+ *                 paper lists population control among the time-dependent
+ *                 features (Section 2) without a method; this is
+ *                 splitting-roulette to pc_target particles at every census
+ *                 edge T_k, k < K, over the particles that just crossed it:
+ *                 their total weight W is summed exactly (128-bit fixed
+ *                 point, 64 fractional bits, each weight truncated to a
+ *                 multiple of 2^-64), w_t = W / pc_target, and each crosser
+ *                 draws xi and goes on as n = floor(w / w_t + xi) copies of
+ *                 weight w_t (copy 0 keeps the stream after the draw, copy
+ *                 j >= 1 takes the child stream j of it; n = 0 counts as
+ *                 rouletted, the extra copies as splits).  The run is one
+ *                 bank chunk: n_histories and pc_target <= 2^26.  Not with weight
+ *                 windows, fission or a detector, nor in the history form
+ *                 (MCDC_E_UNSUPPORTED); MCDC_ALG_AUTO runs the event form.
+ *                 The controlled particles are spread evenly over the
+ *                 bank segments.  A weight of 2^32 or more, or more
+ *                 copies than the banks hold (about n_histories +
+ *                 pc_target), ends the run with MCDC_E_OVERFLOW.
  */
 #define MCDC_FLAG_EAGER 1
 #define MCDC_FLAG_TWO_KERNEL_STEP 2
@@ -257,6 +276,8 @@ typedef struct {
     int32_t profile_every;
     int32_t profile_phase;
     int32_t segments;
+    int32_t reserved;
+    uint64_t pc_target;
 } mcdc_run_options;
 
 /*

@@ -16,7 +16,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libmcdc_hip.so")
 
-MCDC_ABI_VERSION = 2
+MCDC_ABI_VERSION = 3
 MCDC_OK, MCDC_E_INVALID, MCDC_E_HIP, MCDC_E_NOMEM, MCDC_E_OVERFLOW, MCDC_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5
 MCDC_ALG_EVENT, MCDC_ALG_HISTORY, MCDC_ALG_AUTO = 0, 1, 2
 MCDC_SRC_ISOTROPIC, MCDC_SRC_SURFACE = 0, 1
@@ -61,7 +61,7 @@ class mcdc_run_options(C.Structure):
         ("flags", C.c_int32), ("stream", C.c_void_p),
         ("debug_counts", C.c_void_p), ("debug_scores", C.c_void_p),
         ("profile", C.c_void_p), ("profile_mask", C.c_uint32), ("profile_every", C.c_int32), ("profile_phase", C.c_int32),
-        ("segments", C.c_int32),
+        ("segments", C.c_int32), ("reserved", C.c_int32), ("pc_target", C.c_uint64),
     ]
 
 
@@ -91,6 +91,9 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+        # torch first: the library then binds to the HIP runtime torch has
+        # loaded (loaded the other way round, torch later finds no GPU)
+        import torch  # noqa: F401
         L = C.CDLL(LIB_PATH)
         L.mcdc_problem_create.argtypes = [C.POINTER(mcdc_problem_desc), C.POINTER(C.c_void_p)]
         L.mcdc_problem_create.restype = C.c_int
@@ -253,7 +256,7 @@ def mcdc_run(p: Problem, n_histories: int, seed: int, algorithm: str = "event",
              block_size: int = 0, bank_capacity: int = 0, segments: int = 0,
              debug: bool = False, outputs=("mean", "var", "raw", "leak_mean", "leak_var"),
              profile=None, eager: bool = False, profile_classes=None, profile_every: int = 0,
-             profile_phase: int = 0, two_kernel_step: bool = False):
+             profile_phase: int = 0, two_kernel_step: bool = False, pc_target: int = 0):
     """Run n_histories through the GPU tracker.  Returns a dict of torch
     CUDA tensors (mean, var, raw [K, G, nz, ny, nx]; leak_mean, leak_var
     [K, G, 6]; tc_mean, tc_var [K, G, nz, ny, nx] for a problem with the
@@ -261,7 +264,9 @@ def mcdc_run(p: Problem, n_histories: int, seed: int, algorithm: str = "event",
     debug) plus
     host scalars (events, terminations, splits, detector sums, kernel_ms).
     profile: optional float64 array [8, 4] that accumulates per kernel class
-    (ms, launches, particles, algorithmic bytes)."""
+    (ms, launches, particles, algorithmic bytes).
+    pc_target: population control at every census edge (splitting-roulette
+    to that many particles; event form; 0 = off)."""
     import torch
 
     dev = torch.device("cuda", torch.cuda.current_device())
@@ -282,6 +287,7 @@ def mcdc_run(p: Problem, n_histories: int, seed: int, algorithm: str = "event",
     opt.block_size = block_size
     opt.bank_capacity = bank_capacity
     opt.segments = segments
+    opt.pc_target = pc_target
     opt.flags = (1 if eager else 0) | (2 if two_kernel_step else 0)
     opt.stream = torch.cuda.current_stream(dev).cuda_stream
     if debug:

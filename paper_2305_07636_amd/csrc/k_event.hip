@@ -85,7 +85,10 @@ struct Ctl {
     int *seg_b0;            // [G] batch of the segment's first history
     int *step;              // current census step
     uint64_t *first;        // global index of the chunk's first history
+    unsigned long long *pc_w;  // [G][2] population control: fixed-point weight sum per segment
+    unsigned long long *pc_cnt;  // [G] population control: copies made from each segment
     unsigned int G, L;      // segments (= workgroups), slots per segment
+    unsigned int Lh;        // histories per segment (L, or L / 2 with population control)
 };
 
 __device__ __forceinline__ uint32_t pack_gk(int g, int b, int k, int inpin) {
@@ -393,8 +396,8 @@ __global__ void __launch_bounds__(kBlock) k_source(DevProblem P0, RunArgs R0, Ba
     if (threadIdx.x == 0) cN = 0u;
     const uint64_t first = *C.first;
     const unsigned int seg = blockIdx.x;
-    const uint64_t lo = BAT ? (uint64_t)si.first : (uint64_t)seg * C.L;
-    const uint64_t hi = BAT ? lo + si.count : ((lo + C.L < count) ? lo + C.L : count);
+    const uint64_t lo = BAT ? (uint64_t)si.first : (uint64_t)seg * C.Lh;
+    const uint64_t hi = BAT ? lo + si.count : ((lo + C.Lh < count) ? lo + C.Lh : count);
     if (threadIdx.x == 0)
         C.seg_b0[seg] = (lo < hi) ? (int)(((first + lo + 1) * (uint64_t)R.B - 1) / R.N) : 0;
     __syncthreads();
@@ -705,6 +708,237 @@ __global__ void __launch_bounds__(kBlock) k_event(DevProblem P0, RunArgs R0, Ban
 }
 
 // ---------------------------------------------------------------------------
+// population control at census: splitting-roulette to a target population
+// ---------------------------------------------------------------------------
+// (Section 2 lists population control among the time-dependent features
+// without giving a method.)  After the step kernel has filed the census
+// crossers of edge T_{k+1} into the next bank, two kernels control them:
+// k_pc_sum forms each segment's exact weight sum (128-bit fixed point, 64
+// fractional bits, so the total does not depend on the order of the
+// particles); every workgroup of the next two adds the G partial sums in
+// segment order and sets w_t = W / target.  k_pc_count counts the copies
+// each segment makes; k_pc_apply copies every particle of the next bank
+// back into the step's input bank, spread evenly over all segments: a
+// crosser as n = floor(w / w_t + xi) copies of weight w_t (copy 0 keeps the
+// stream after the draw, copy j >= 1 takes child_stream(s, j)), a particle
+// of a later time bin unchanged.
+
+// w truncated to a multiple of 2^-64, as the 128-bit integer (hi, lo),
+// added to (hi, lo); false if w is 2^32 or more, negative or not a number.
+__device__ __forceinline__ bool fixed_add(unsigned long long &hi, unsigned long long &lo, double w) {
+    if (!(w >= 0.0) || !(w < 4294967296.0)) return false;
+    const unsigned long long bits = (unsigned long long)__double_as_longlong(w);
+    const int e = (int)((bits >> 52) & 0x7FFu);
+    if (e == 0) return true;   // zero or subnormal: below 2^-64
+    const unsigned long long m = (bits & ((1ull << 52) - 1ull)) | (1ull << 52);
+    const int sh = e - 1011;   // w 2^64 = m 2^(e - 1011)
+    unsigned long long h = 0ull, l = 0ull;
+    if (sh >= 64) {
+        h = m << (sh - 64);
+    } else if (sh > 0) {
+        h = m >> (64 - sh);
+        l = m << sh;
+    } else if (sh == 0) {
+        l = m;
+    } else if (sh > -64) {
+        l = m >> (-sh);
+    }
+    const unsigned long long nl = lo + l;
+    hi += h + (nl < lo ? 1ull : 0ull);
+    lo = nl;
+    return true;
+}
+__device__ __forceinline__ void fixed_merge(unsigned long long &hi, unsigned long long &lo, unsigned long long h2,
+                                            unsigned long long l2) {
+    const unsigned long long nl = lo + l2;
+    hi += h2 + (nl < lo ? 1ull : 0ull);
+    lo = nl;
+}
+
+__device__ __forceinline__ uint32_t clock_of(uint32_t gk) { return (gk >> 15) & 0xFFFFu; }
+
+// overflow flag values of population control (1: particle or split bank)
+constexpr int kOvfWeight = 2, kOvfCopies = 3, kOvfSegment = 4;
+
+__global__ void __launch_bounds__(kBlock) k_pc_sum(Bank next, Ctl C, int par, int *overflow) {
+    __shared__ unsigned long long part[kBlock / 64][2];
+    const unsigned int seg = blockIdx.x;
+    const unsigned int n = C.n_bank[(par ^ 1) * C.G + seg];
+    const uint32_t edge = (uint32_t)(*C.step + 1);
+    const uint32_t seg0 = seg * C.L;
+    unsigned long long hi = 0ull, lo = 0ull;
+    bool ok = true;
+    for (uint32_t r = threadIdx.x; r < n; r += kBlock) {
+        const uint32_t slot = seg0 + r;
+        if (clock_of(fld<uint32_t>(next, next.ogk, tile_off4(next, slot))) != edge) continue;
+        ok = fixed_add(hi, lo, fld<double>(next, next.ow, tile_off8(next, slot))) && ok;
+    }
+    if (!ok) *overflow = kOvfWeight;
+    for (int o = 32; o > 0; o >>= 1) {
+        const unsigned long long h2 = __shfl_xor(hi, o), l2 = __shfl_xor(lo, o);
+        fixed_merge(hi, lo, h2, l2);
+    }
+    if (__lane_id() == 0) {
+        part[threadIdx.x >> 6][0] = hi;
+        part[threadIdx.x >> 6][1] = lo;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long H = 0ull, L = 0ull;
+        for (int w = 0; w < kBlock / 64; ++w) fixed_merge(H, L, part[w][0], part[w][1]);
+        C.pc_w[2 * seg] = H;
+        C.pc_w[2 * seg + 1] = L;
+    }
+}
+
+// w_t and whether the control acts (W > 0), from the segments' fixed-point
+// sums, added in segment order.
+__device__ __forceinline__ void pc_weight(const Ctl &C, uint64_t target, double &wt, int &on) {
+    unsigned long long hi = 0ull, lo = 0ull;
+    for (unsigned int j = 0; j < C.G; ++j) fixed_merge(hi, lo, C.pc_w[2 * j], C.pc_w[2 * j + 1]);
+    const double W = (double)hi + ((double)(lo >> 32) * 0x1p-32 + (double)(lo & 0xFFFFFFFFull) * 0x1p-64);
+    wt = W / (double)target;
+    on = (hi | lo) != 0ull;
+}
+
+// Copies of particle p at the control of edge `edge`: floor(w / w_t + xi)
+// for a crosser (its stream advances by the draw), 1 for a particle of a
+// later time bin.  More than `cap` copies: overflow, none made.
+__device__ __forceinline__ uint64_t pc_copies(Particle &p, int edge, bool on, double wt, double cap,
+                                              const RunArgs &R) {
+    if (!on || p.k != edge) return 1ull;
+    const double nr = floor(p.w / wt + rn(p.s));
+    if (nr > cap) {
+        *R.overflow = kOvfCopies;
+        return 0ull;
+    }
+    return (uint64_t)nr;
+}
+
+// Pass 2: copies per segment (the draws are repeated, not kept, by pass 3).
+template <int FM>
+__global__ void __launch_bounds__(kBlock) k_pc_count(DevProblem P, RunArgs R, Bank next, Ctl C, int par,
+                                                     uint64_t target) {
+    __shared__ unsigned long long part[kBlock / 64];
+    __shared__ double s_wt;
+    __shared__ int s_on;
+    const unsigned int seg = blockIdx.x;
+    if (threadIdx.x == 0) pc_weight(C, target, s_wt, s_on);
+    __syncthreads();
+    const double wt = s_wt;
+    const bool on = s_on != 0;
+    const double cap = (double)C.G * (double)C.L;
+    const unsigned int n = C.n_bank[(par ^ 1) * C.G + seg];
+    const int edge = *C.step + 1;
+    const uint32_t seg0 = seg * C.L;
+    unsigned long long tot = 0ull;
+    for (uint32_t r = threadIdx.x; r < n; r += kBlock) {
+        Particle p;
+        uint32_t gk, hidw;
+        load_state<FM, true>(P, next, seg0 + r, p, gk, hidw);
+        tot += pc_copies(p, edge, on, wt, cap, R);
+    }
+    for (int o = 32; o > 0; o >>= 1) tot += __shfl_xor(tot, o);
+    if (__lane_id() == 0) part[threadIdx.x >> 6] = tot;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t = 0ull;
+        for (int w = 0; w < kBlock / 64; ++w) t += part[w];
+        C.pc_cnt[seg] = t;
+    }
+}
+
+// Pass 3: the copies.  Segment seg's copies take the global positions
+// [sum of the earlier segments' counts, + its count), and position q goes
+// to slot q mod Lq of segment q / Lq, Lq = ceil(T / G) for T copies in all:
+// the controlled population is spread evenly over the segments again (a
+// segment's share would otherwise drift from step to step).
+template <int FM>
+__global__ void __launch_bounds__(kBlock) k_pc_apply(DevProblem P, RunArgs R, Bank next, Bank cur, Ctl C, int par,
+                                                     uint64_t target) {
+    __shared__ unsigned long long red[kCounters + 2];
+    __shared__ unsigned int cN;
+    __shared__ double s_wt;
+    __shared__ int s_on;
+    __shared__ unsigned long long s_base, s_total;
+    Counters cnt;
+    cnt.init(red);
+    const unsigned int seg = blockIdx.x;
+    if (threadIdx.x == 0) {
+        pc_weight(C, target, s_wt, s_on);
+        unsigned long long base = 0ull, total = 0ull;
+        for (unsigned int j = 0; j < C.G; ++j) {
+            if (j == seg) base = total;
+            total += C.pc_cnt[j];
+        }
+        s_base = base;
+        s_total = total;
+        cN = 0u;
+    }
+    __syncthreads();
+    const double wt = s_wt;
+    const bool on = s_on != 0;
+    const double cap = (double)C.G * (double)C.L;
+    const unsigned long long T = s_total, base = s_base;
+    const unsigned long long Lq = (T + C.G - 1) / C.G;   // copies per output segment
+    if (threadIdx.x == 0) {
+        const unsigned long long lo = (unsigned long long)seg * Lq;
+        const unsigned long long cnt_out = (T > lo) ? ((T - lo < Lq) ? T - lo : Lq) : 0ull;
+        C.n_bank[par * C.G + seg] = (unsigned int)((cnt_out < C.L) ? cnt_out : C.L);
+        if (Lq > C.L) *R.overflow = kOvfSegment;
+    }
+    const unsigned int n = C.n_bank[(par ^ 1) * C.G + seg];
+    const int edge = *C.step + 1;
+    const uint64_t first = *C.first;
+    const uint32_t seg0 = seg * C.L;
+    for (uint32_t b0 = 0; b0 < n; b0 += kBlock) {
+        const uint32_t r = b0 + threadIdx.x;
+        const bool valid = r < n;
+        Particle p;
+        uint32_t gk = 0u, hidw = 0u;
+        uint64_t copies = 0ull, sf = 0ull;
+        if (valid) {
+            load_state<FM, true>(P, next, seg0 + r, p, gk, hidw);
+            const bool ctl = on && p.k == edge;
+            copies = pc_copies(p, edge, on, wt, cap, R);
+            if (ctl) {
+                const uint64_t i = first + (hidw & kHidMask);
+                if (copies == 0ull) {
+                    cnt.add(3 + kRoulette);
+                    hist_term(R, i, kRoulette);
+                } else {
+                    p.w = wt;
+                    cnt.add(8, (unsigned int)(copies - 1ull));
+                    if (R.dbg_counts && copies > 1ull)
+                        atomicAdd(R.dbg_counts + i * 5 + 3, (unsigned int)(copies - 1ull));
+                }
+            }
+            sf = p.s;
+        }
+        // one copy per lane and round
+        uint64_t j = 0ull;
+        for (;;) {
+            const bool put = valid && j < copies;
+            if (!__any(put)) break;
+            const uint32_t off = block_append(put, &cN);
+            if (put) {
+                const unsigned long long q = base + off;
+                const unsigned long long os = q / Lq, oslot = q - os * Lq;
+                if (os < C.G && oslot < C.L) {
+                    p.s = (j > 0ull) ? child_stream(sf, j) : sf;
+                    store_state<FM, true>(P, cur, (uint32_t)(os * C.L + oslot), p, gk, hidw);
+                } else {
+                    *R.overflow = kOvfSegment;
+                }
+                ++j;
+            }
+        }
+        if (R.prof) cnt.prof(valid ? 1u : 0u, valid ? (unsigned int)((copies + 1ull) * state_bytes<FM, true>(P)) : 0u);
+    }
+    cnt.flush(R, MCDC_PROF_OTHER, red);
+}
+
+// ---------------------------------------------------------------------------
 // control
 // ---------------------------------------------------------------------------
 __global__ void k_ctl_init(Ctl C, uint64_t first) {
@@ -763,7 +997,9 @@ Bank bank_layout(int fmask, bool ww) {
 // Bytes of one bank of `slots` slots (whole tiles).
 size_t bank_bytes(uint64_t slots, int fmask, bool ww) { return ((slots + 63) / 64) * bank_layout(fmask, ww).tile; }
 
-size_t ctl_bytes(unsigned int G) { return pad256(2 * G * 4) + 3 * pad256(G * 4) + 2 * 256; }
+size_t ctl_bytes(unsigned int G) {
+    return pad256(2 * G * 4) + 3 * pad256(G * 4) + 2 * 256 + pad256(G * 16) + pad256(G * 8);
+}
 
 Layout carve(void *bank_mem, void *ctl_mem, uint64_t slots, unsigned int G, unsigned int Lseg, int fmask,
              bool ww) {
@@ -787,8 +1023,11 @@ Layout carve(void *bank_mem, void *ctl_mem, uint64_t slots, unsigned int G, unsi
     C.seg_b0 = (int *)take(G * 4);
     C.step = (int *)take(64);
     C.first = (uint64_t *)take(64);
+    C.pc_w = (unsigned long long *)take(G * 16);
+    C.pc_cnt = (unsigned long long *)take(G * 8);
     C.G = G;
     C.L = Lseg;
+    C.Lh = Lseg;
     return Lo;
 }
 
@@ -830,8 +1069,15 @@ int run_event(mcdc_problem *pb, const RunArgs &R0, uint64_t first, uint64_t coun
     const DevProblem &P = pb->d;
     // (weight-window runs take smaller chunks: their progeny of a chunk must
     // fit the split bank)
+    // (population control runs the whole job as one chunk)
+    const uint64_t pc = opt.pc_target;
+    if (pc && !WW) {
+        set_error("population control needs the weighted event form");
+        return MCDC_E_UNSUPPORTED;
+    }
     uint64_t C = opt.bank_capacity ? (uint64_t)opt.bank_capacity
                                    : (WW ? (P.fission_on ? kFissionChunk : kWindowChunk) : (uint64_t)1 << 24);
+    if (pc) C = count;
     if (C > count) C = count;
     if (C > (1ULL << 28)) C = 1ULL << 28;
 
@@ -858,14 +1104,18 @@ int run_event(mcdc_problem *pb, const RunArgs &R0, uint64_t first, uint64_t coun
     const uint64_t g_need = (C + kBlock - 1) / kBlock;
     if (G > g_need) G = (unsigned int)g_need;
     if (G < 1) G = 1;
-    // (segments are whole tiles of 64 slots)
-    const unsigned int Lseg = (unsigned int)(((C + G - 1) / G + 63) & ~(uint64_t)63);
+    // (segments are whole tiles of 64 slots; with population control a
+    // segment also holds its even share of the target population, plus a
+    // tile for the control's noise)
+    const unsigned int Lh = (unsigned int)(((C + G - 1) / G + 63) & ~(uint64_t)63);
+    const unsigned int Lseg = pc ? Lh + (unsigned int)(((pc + G - 1) / G + 63) & ~(uint64_t)63) + 64u : Lh;
     const uint64_t slots = (uint64_t)G * Lseg;
     int rc;
     if ((rc = ensure(pb->bank, pad256(bank_bytes(slots, FM, WW)) * 3 + 64 * 256))) return rc;
     if ((rc = ensure(pb->queues, ctl_bytes(G)))) return rc;
     if (P.qoi_on && (rc = ensure(pb->qoi_hist, C * sizeof(double)))) return rc;
     Layout L = carve(pb->bank.p, pb->queues.p, slots, G, Lseg, FM ? FM : P.finite_mask, WW);
+    L.ctl.Lh = Lh;
     RunArgs R = R0;
     R.qoi_hist = (double *)pb->qoi_hist.p;
     // weight windows and fission: progeny of a chunk go to the split bank and are
@@ -884,22 +1134,33 @@ int run_event(mcdc_problem *pb, const RunArgs &R0, uint64_t first, uint64_t coun
 
     // one kernel per census step (default), or the advance / events pair
     const bool one_kernel = (opt.flags & MCDC_FLAG_TWO_KERNEL_STEP) == 0;
-    auto enqueue_step = [&](int par, hipStream_t s, Profiler &pr, const RunArgs &Ra) {
+    // (with population control the controlled particles go back into the
+    // step's input bank, so every step runs on bank 0)
+    auto enqueue_step = [&](int par_in, hipStream_t s, Profiler &pr, const RunArgs &Ra) {
+        const int par = pc ? 0 : par_in;
         const Bank &cur = L.bank[par];
         const Bank &nxt = L.bank[par ^ 1];
         if (one_kernel) {
             launch_timed(pr, MCDC_PROF_EVENTS, k_event<FM, WW, LT, false, MCDC_PROF_EVENTS, true>, dim3(G),
                          dim3(kBlock), (uint32_t)shmem, s, P, Ra, cur, nxt, L.ctl, par, gn, SB[0], tabs,
                          (const BatchItem *)nullptr, (const SegInfo *)nullptr);
-            hipLaunchKernelGGL(k_step_end, dim3(1), dim3(1), 0, s, L.ctl);
-            return;
+        } else {
+            launch_timed(pr, MCDC_PROF_ADVANCE, k_advance<FM, WW, LT, false>, dim3(G), dim3(kBlock), (uint32_t)shmem,
+                         s, P, Ra, cur, nxt, L.ev, L.ctl, par, gn, SB[0], tabs, (const BatchItem *)nullptr,
+                         (const SegInfo *)nullptr);
+            launch_timed(pr, MCDC_PROF_EVENTS, k_event<FM, WW, LT, false>, dim3(G), dim3(kBlock), (uint32_t)shmem, s,
+                         P, Ra, L.ev, nxt, L.ctl, par, gn, SB[0], tabs, (const BatchItem *)nullptr,
+                         (const SegInfo *)nullptr);
         }
-        launch_timed(pr, MCDC_PROF_ADVANCE, k_advance<FM, WW, LT, false>, dim3(G), dim3(kBlock), (uint32_t)shmem, s, P,
-                     Ra, cur, nxt, L.ev, L.ctl, par, gn, SB[0], tabs, (const BatchItem *)nullptr,
-                     (const SegInfo *)nullptr);
-        launch_timed(pr, MCDC_PROF_EVENTS, k_event<FM, WW, LT, false>, dim3(G), dim3(kBlock), (uint32_t)shmem, s, P,
-                     Ra, L.ev, nxt, L.ctl, par, gn, SB[0], tabs, (const BatchItem *)nullptr,
-                     (const SegInfo *)nullptr);
+        if constexpr (WW) {
+            if (pc) {
+                launch_timed(pr, MCDC_PROF_OTHER, k_pc_sum, dim3(G), dim3(kBlock), 0u, s, nxt, L.ctl, par, Ra.overflow);
+                launch_timed(pr, MCDC_PROF_OTHER, k_pc_count<FM>, dim3(G), dim3(kBlock), 0u, s, P, Ra, nxt, L.ctl,
+                             par, pc);
+                launch_timed(pr, MCDC_PROF_OTHER, k_pc_apply<FM>, dim3(G), dim3(kBlock), 0u, s, P, Ra, nxt, cur, L.ctl,
+                             par, pc);
+            }
+        }
         hipLaunchKernelGGL(k_step_end, dim3(1), dim3(1), 0, s, L.ctl);
     };
 
@@ -920,6 +1181,7 @@ int run_event(mcdc_problem *pb, const RunArgs &R0, uint64_t first, uint64_t coun
         key_add(key, tabs);
         key_add(key, LT);
         key_add(key, one_kernel);
+        key_add(key, pc);
         if (key != Gr->key) {
             Gr->clear();
             hipError_t e = hipSuccess;
@@ -951,7 +1213,7 @@ int run_event(mcdc_problem *pb, const RunArgs &R0, uint64_t first, uint64_t coun
         for (int step = 0; step < P.K; ++step) {
             const bool sampled = opt.profile && step % every == opt.profile_phase % every;
             if (Gr && !sampled) {
-                hipError_t e = hipGraphLaunch(Gr->exec[step & 1], st);
+                hipError_t e = hipGraphLaunch(Gr->exec[pc ? 0 : (step & 1)], st);
                 if (e != hipSuccess) return hip_fail(e, "census step replay");
             } else {
                 Profiler none;
@@ -1112,7 +1374,7 @@ int launch_event(mcdc_problem *p, const RunArgs &R, uint64_t first, uint64_t cou
     }
     LdsTables tabs{};
     const bool lt = table_layout(P, tabs, kLdsTablesMax);
-    if (has_progeny(P)) {
+    if (has_progeny(P) || opt.pc_target) {
         if (P.finite_mask == 1) return run_event_lt<1, true>(p, R, first, count, opt, st, prof, tabs, lt);
         if (P.finite_mask == 7) return run_event_lt<7, true>(p, R, first, count, opt, st, prof, tabs, lt);
         return run_event_lt<0, true>(p, R, first, count, opt, st, prof, tabs, lt);

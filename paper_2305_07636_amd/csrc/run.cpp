@@ -214,7 +214,11 @@ int collect_begin(mcdc_problem *p, mcdc_result *out, Collect &c, hipStream_t st)
 
 int collect_end(mcdc_problem *p, uint64_t N, const Collect &c, mcdc_result *out, double ms) {
     if (c.ovf) {
-        set_error("particle bank or split bank overflow");
+        static const char *what[] = {"particle bank or split bank overflow",
+                                     "population control: a weight of 2^32 or more (or not a number)",
+                                     "population control: more copies of a particle than its bank segment holds",
+                                     "population control: a bank segment overflowed"};
+        set_error(what[(c.ovf >= 1 && c.ovf <= 4) ? c.ovf - 1 : 0]);
         return MCDC_E_OVERFLOW;
     }
     for (int j = 0; j < 3; ++j) out->n_events[j] = c.cnt[j];
@@ -249,6 +253,22 @@ extern "C" int mcdc_run(mcdc_problem *p, uint64_t n_histories, uint64_t seed, co
     if (n_histories == 0) return bad("n_histories must be > 0");
     mcdc_run_options opt{};
     if (opt_in) opt = *opt_in;
+    if (opt.pc_target) {
+        // population control synchronises all particles at census: event form only
+        if (opt.algorithm == MCDC_ALG_AUTO) opt.algorithm = MCDC_ALG_EVENT;
+        if (opt.algorithm == MCDC_ALG_HISTORY) {
+            set_error("population control runs in the event form only");
+            return MCDC_E_UNSUPPORTED;
+        }
+        if (p->d.ww_center || p->d.fission_on || p->d.qoi_on) {
+            set_error("population control is not combined with weight windows, fission or a detector");
+            return MCDC_E_UNSUPPORTED;
+        }
+        if (n_histories > (1ULL << 26) || opt.pc_target > (1ULL << 26)) {
+            set_error("population control runs at most 2^26 histories per call, to at most 2^26 particles");
+            return MCDC_E_UNSUPPORTED;
+        }
+    }
     if (opt.algorithm == MCDC_ALG_AUTO) {
         // the faster form for this problem and history count: both forms
         // run (and are timed) on the first call, the choice is kept on the
@@ -476,6 +496,10 @@ extern "C" int mcdc_run_batched(mcdc_problem *const *ps, int32_t n, const uint64
     if (!ps || !n_hist || !seeds || !outs || n <= 0) return bad("NULL argument or n <= 0");
     mcdc_run_options opt{};
     if (opt_in) opt = *opt_in;
+    if (opt.pc_target) {
+        set_error("population control is not supported in batched solves");
+        return MCDC_E_UNSUPPORTED;
+    }
     if (opt.algorithm == MCDC_ALG_AUTO) {
         // the faster form for this batch signature, timed once and cached
         for (int j = 0; j < n; ++j)
@@ -608,6 +632,10 @@ extern "C" int mcdc_run_eigenvalue(mcdc_problem *p, uint64_t n_per_cycle, int32_
         return bad("n_inactive must be >= 0 and n_active in [1, 1023]");
     mcdc_run_options opt{};
     if (opt_in) opt = *opt_in;
+    if (opt.pc_target) {
+        set_error("population control is not supported in eigenvalue cycles");
+        return MCDC_E_UNSUPPORTED;
+    }
     int rc = check_options(opt);
     if (rc) return rc;
     const DevProblem &P = p->d;
