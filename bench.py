@@ -189,6 +189,53 @@ def fission_section(m, w, n, steps):
     return res
 
 
+def population_control_section(m, w, n, steps):
+    """The pulsed slab with population control at every census edge
+    (splitting-roulette back to n particles; event form): histories/s, the
+    control kernels' share, and the figure of merit 1/(R^2 T) of the
+    spatially integrated flux in the last time bin against the analog run
+    (the population otherwise decays by e^-2 over the 100 steps)."""
+    import numpy as np
+    import torch
+
+    prob = w.cfg2_slab_pulse()
+    h = m.mcdc_problem_create(prob)
+    res = {"workload": "40-mfp slab, c = 0.9, plane pulse at x = 20, 50 x-bins x 100 time bins on [0, 20], "
+                       f"{n:.0e} histories, population held at {n:.0e} at each of the 99 inner census edges",
+           "histories": n}
+    try:
+        for tag, kw in (("analog", {}), ("controlled", {"pc_target": n})):
+            out = m.mcdc_run(h, n, 90, outputs=("mean", "var"), **kw)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for s in range(steps):
+                out = m.mcdc_run(h, n, 91 + s, outputs=("mean", "var"), **kw)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / steps
+            last = out["mean"].cpu().numpy()[-1].sum()
+            var = out["var"].cpu().numpy()[-1].sum()
+            rel2 = var / (last * last)
+            res[f"{tag}_histories_per_s"] = n / dt
+            res[f"{tag}_ms"] = dt * 1e3
+            res[f"{tag}_events_per_history"] = float(sum(out["events"])) / n
+            res[f"{tag}_last_bin_rel_err"] = float(np.sqrt(rel2))
+            res[f"{tag}_last_bin_fom"] = float(1.0 / (rel2 * dt))
+            if tag == "controlled":
+                res["splits_per_history"] = out["splits"] / n
+                res["rouletted_per_history"] = float(out["terms"][4]) / n
+            log(f"population control {tag}: {dt * 1e3:.1f} ms per run")
+        res["last_bin_fom_gain"] = res["controlled_last_bin_fom"] / res["analog_last_bin_fom"]
+        prof = np.zeros((len(m._binding.PROF_CLASSES), 4))
+        m.mcdc_run(h, n, 99, outputs=("mean",), pc_target=n, profile=prof, profile_classes=["events", "other"])
+        torch.cuda.synchronize()
+        ev, ot = m._binding.PROF_CLASSES.index("events"), m._binding.PROF_CLASSES.index("other")
+        res["step_kernel_ms"] = float(prof[ev, 0])
+        res["control_and_fill_kernels_ms"] = float(prof[ot, 0])
+    finally:
+        h.close()
+    return res
+
+
 def pins_section(m, w, n, steps):
     """Cylindrical-pin geometry: the 17 x 17 lattice of the lattice workload
     with a 0.54-radius fuel pin in every 1.26 cell (7 groups, 17 x 17 x 10 x
@@ -313,6 +360,7 @@ def main():
     ap.add_argument("--no-fission", action="store_true")
     ap.add_argument("--no-eigen", action="store_true")
     ap.add_argument("--no-pins", action="store_true")
+    ap.add_argument("--no-pc", action="store_true")
     ap.add_argument("--eigen-per-cycle", type=float, default=1e5)
     ap.add_argument("--fission-histories", type=float, default=1e6)
     ap.add_argument("--fom-pilot", type=float, default=1e8)
@@ -455,6 +503,8 @@ def main():
         extra["eigenvalue"] = eigen_section(m, w, int(args.eigen_per_cycle), 50, 100)
     if not args.no_pins:
         extra["pins"] = pins_section(m, w, int(args.histories), args.steps)
+    if not args.no_pc:
+        extra["population_control"] = population_control_section(m, w, int(args.histories), args.steps)
     if not args.no_batched:
         extra["batched"] = batched_section(m, w)
     if not args.no_fom:

@@ -3,7 +3,8 @@ target population, exact fixed-point total weight) against the oracle's
 census-synchronous run: every event, termination and split count agrees
 exactly and the tallies within the stated tolerances (gpu_common).  Cases:
 the decaying pulsed slab (analog and implicit capture), a void reflective
-box whose population doubles exactly, a multigroup reflective box with the
+box whose population doubles exactly, the same box with births spread over
+its time bins (later births wait for their own edge), a multigroup reflective box with the
 time-crossing tally, a ragged history count with a target above and below
 it, both step forms; then the 1e7-history pulsed slab at full size against
 the closed form of its spatially integrated flux."""
@@ -27,6 +28,12 @@ def _void_reflective():
                       time_edges=list(np.linspace(0.0, 4.0, 5)), bc=[w.REFLECTIVE] * 6)
 
 
+def _void_spread():
+    p = _void_reflective()
+    p["source"]["t_lo"], p["source"]["t_hi"] = 0.0, 4.0
+    return p
+
+
 def _mg_box():
     p = w.reflective_box([1.0, 1.5, 2.0], [[0.3, 0.4, 0.1], [0.0, 0.6, 0.5], [0.0, 0.2, 1.2]], [3.0, 2.0, 1.0],
                          time_edges=[0.0, 0.25, 0.5, 1.0, 2.0, 4.0])
@@ -44,6 +51,7 @@ CASES = {
     "slab_c09_implicit": (lambda: _ic(_slab_pulse(0.9), 0.2, 0.6), 6007, 1.0, 62),
     "void_double": (_void_reflective, 3000, 2.0, 63),
     "mg_box_tc": (_mg_box, 4099, 1.0, 64),
+    "void_spread_births": (_void_spread, 4000, 1.0, 68),
     "ragged_up": (lambda: _slab_pulse(0.7, K=13, batches=7), 12345, 1.5, 65),
     "ragged_down": (lambda: _slab_pulse(0.7, K=13, batches=7), 12345, 0.4, 66),
 }

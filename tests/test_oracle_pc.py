@@ -136,3 +136,23 @@ def test_rejects_what_it_does_not_model():
         oracle.run_pc(prob, 100, 1, target=100)
     with pytest.raises(RuntimeError):
         oracle.run_pc(_void_reflective(), 100, 1, target=0)
+
+
+def test_later_births_wait_for_their_own_edge():
+    """Births spread over all four time bins of a void reflective box,
+    target N.  The first edge controls the particles of bins 0 and 1 only
+    (about N/2 of weight 1, so about N/2 extra copies); a control over every
+    particle alive would leave all N of weight 1 as they are (no copies)."""
+    prob = _void_reflective()
+    prob["source"]["t_lo"], prob["source"]["t_hi"] = 0.0, 4.0
+    N = 4000
+    pc = oracle.run_pc(prob, N, 17, target=N)
+    an = oracle.run(prob, N, 17)
+    assert int(pc["tot"][8]) > N // 4
+    assert abs(int(pc["pop"][1]) - N) < 5 * math.sqrt(N)
+    born = int(pc["pop"][0])
+    assert born + int(pc["tot"][8]) == int(pc["tot"][3 + oracle.T_ROULETTE]) + int(pc["tot"][3 + oracle.T_TIME])
+    # unbiased: the total track per time bin matches the uncontrolled run
+    tk = pc["S"].sum(axis=0).reshape(4, -1).sum(axis=1)
+    ta = an["S"].sum(axis=0).reshape(4, -1).sum(axis=1)
+    np.testing.assert_allclose(tk, ta, rtol=0.05)
