@@ -791,14 +791,56 @@ __global__ void __launch_bounds__(kBlock) k_pc_sum(Bank next, Ctl C, int par, in
     }
 }
 
-// w_t and whether the control acts (W > 0), from the segments' fixed-point
-// sums, added in segment order.
-__device__ __forceinline__ void pc_weight(const Ctl &C, uint64_t target, double &wt, int &on) {
-    unsigned long long hi = 0ull, lo = 0ull;
-    for (unsigned int j = 0; j < C.G; ++j) fixed_merge(hi, lo, C.pc_w[2 * j], C.pc_w[2 * j + 1]);
-    const double W = (double)hi + ((double)(lo >> 32) * 0x1p-32 + (double)(lo & 0xFFFFFFFFull) * 0x1p-64);
-    wt = W / (double)target;
-    on = (hi | lo) != 0ull;
+// Workgroup-wide sums over the segments' partials (integers, so the order
+// of the additions does not matter): the fixed-point weight W, then w_t =
+// W / target and whether the control acts (W > 0); with counts, also the
+// copies of all segments and of the segments before `seg`.  Every thread
+// returns the same values.
+struct PcSums {
+    double wt;
+    int on;
+    unsigned long long total, before;
+};
+__device__ PcSums pc_sums(const Ctl &C, uint64_t target, unsigned int seg, bool counts) {
+    __shared__ unsigned long long part[kBlock / 64][4];
+    __shared__ PcSums res;
+    unsigned long long hi = 0ull, lo = 0ull, tot = 0ull, bef = 0ull;
+    for (unsigned int j = threadIdx.x; j < C.G; j += kBlock) {
+        fixed_merge(hi, lo, C.pc_w[2 * j], C.pc_w[2 * j + 1]);
+        if (counts) {
+            const unsigned long long c = C.pc_cnt[j];
+            tot += c;
+            if (j < seg) bef += c;
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        const unsigned long long h2 = __shfl_xor(hi, o), l2 = __shfl_xor(lo, o);
+        fixed_merge(hi, lo, h2, l2);
+        tot += __shfl_xor(tot, o);
+        bef += __shfl_xor(bef, o);
+    }
+    if (__lane_id() == 0) {
+        part[threadIdx.x >> 6][0] = hi;
+        part[threadIdx.x >> 6][1] = lo;
+        part[threadIdx.x >> 6][2] = tot;
+        part[threadIdx.x >> 6][3] = bef;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long H = 0ull, L = 0ull, T = 0ull, Bf = 0ull;
+        for (int w = 0; w < kBlock / 64; ++w) {
+            fixed_merge(H, L, part[w][0], part[w][1]);
+            T += part[w][2];
+            Bf += part[w][3];
+        }
+        const double W = (double)H + ((double)(L >> 32) * 0x1p-32 + (double)(L & 0xFFFFFFFFull) * 0x1p-64);
+        res.wt = W / (double)target;
+        res.on = (H | L) != 0ull;
+        res.total = T;
+        res.before = Bf;
+    }
+    __syncthreads();
+    return res;
 }
 
 // Copies of particle p at the control of edge `edge`: floor(w / w_t + xi)
@@ -816,26 +858,24 @@ __device__ __forceinline__ uint64_t pc_copies(Particle &p, int edge, bool on, do
 }
 
 // Pass 2: copies per segment (the draws are repeated, not kept, by pass 3).
-template <int FM>
-__global__ void __launch_bounds__(kBlock) k_pc_count(DevProblem P, RunArgs R, Bank next, Ctl C, int par,
-                                                     uint64_t target) {
+// (it reads only the weight, stream and clock of each particle)
+__global__ void __launch_bounds__(kBlock) k_pc_count(RunArgs R, Bank next, Ctl C, int par, uint64_t target) {
     __shared__ unsigned long long part[kBlock / 64];
-    __shared__ double s_wt;
-    __shared__ int s_on;
     const unsigned int seg = blockIdx.x;
-    if (threadIdx.x == 0) pc_weight(C, target, s_wt, s_on);
-    __syncthreads();
-    const double wt = s_wt;
-    const bool on = s_on != 0;
+    const PcSums S = pc_sums(C, target, seg, false);
+    const double wt = S.wt;
+    const bool on = S.on != 0;
     const double cap = (double)C.G * (double)C.L;
     const unsigned int n = C.n_bank[(par ^ 1) * C.G + seg];
     const int edge = *C.step + 1;
     const uint32_t seg0 = seg * C.L;
     unsigned long long tot = 0ull;
     for (uint32_t r = threadIdx.x; r < n; r += kBlock) {
+        const uint32_t slot = seg0 + r;
         Particle p;
-        uint32_t gk, hidw;
-        load_state<FM, true>(P, next, seg0 + r, p, gk, hidw);
+        p.k = (int)clock_of(fld<uint32_t>(next, next.ogk, tile_off4(next, slot)));
+        p.w = fld<double>(next, next.ow, tile_off8(next, slot));
+        p.s = fld<uint64_t>(next, next.os, tile_off8(next, slot));
         tot += pc_copies(p, edge, on, wt, cap, R);
     }
     for (int o = 32; o > 0; o >>= 1) tot += __shfl_xor(tot, o);
@@ -858,28 +898,15 @@ __global__ void __launch_bounds__(kBlock) k_pc_apply(DevProblem P, RunArgs R, Ba
                                                      uint64_t target) {
     __shared__ unsigned long long red[kCounters + 2];
     __shared__ unsigned int cN;
-    __shared__ double s_wt;
-    __shared__ int s_on;
-    __shared__ unsigned long long s_base, s_total;
     Counters cnt;
     cnt.init(red);
     const unsigned int seg = blockIdx.x;
-    if (threadIdx.x == 0) {
-        pc_weight(C, target, s_wt, s_on);
-        unsigned long long base = 0ull, total = 0ull;
-        for (unsigned int j = 0; j < C.G; ++j) {
-            if (j == seg) base = total;
-            total += C.pc_cnt[j];
-        }
-        s_base = base;
-        s_total = total;
-        cN = 0u;
-    }
-    __syncthreads();
-    const double wt = s_wt;
-    const bool on = s_on != 0;
+    if (threadIdx.x == 0) cN = 0u;
+    const PcSums S = pc_sums(C, target, seg, true);
+    const double wt = S.wt;
+    const bool on = S.on != 0;
     const double cap = (double)C.G * (double)C.L;
-    const unsigned long long T = s_total, base = s_base;
+    const unsigned long long T = S.total, base = S.before;
     const unsigned long long Lq = (T + C.G - 1) / C.G;   // copies per output segment
     if (threadIdx.x == 0) {
         const unsigned long long lo = (unsigned long long)seg * Lq;
@@ -1155,8 +1182,7 @@ int run_event(mcdc_problem *pb, const RunArgs &R0, uint64_t first, uint64_t coun
         if constexpr (WW) {
             if (pc) {
                 launch_timed(pr, MCDC_PROF_OTHER, k_pc_sum, dim3(G), dim3(kBlock), 0u, s, nxt, L.ctl, par, Ra.overflow);
-                launch_timed(pr, MCDC_PROF_OTHER, k_pc_count<FM>, dim3(G), dim3(kBlock), 0u, s, P, Ra, nxt, L.ctl,
-                             par, pc);
+                launch_timed(pr, MCDC_PROF_OTHER, k_pc_count, dim3(G), dim3(kBlock), 0u, s, Ra, nxt, L.ctl, par, pc);
                 launch_timed(pr, MCDC_PROF_OTHER, k_pc_apply<FM>, dim3(G), dim3(kBlock), 0u, s, P, Ra, nxt, cur, L.ctl,
                              par, pc);
             }
