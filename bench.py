@@ -189,7 +189,7 @@ def fission_section(m, w, n, steps):
     return res
 
 
-def population_control_section(m, w, n, steps):
+def population_control_section(m, w, n, steps, cpu=True):
     """The pulsed slab with population control at every census edge
     (splitting-roulette back to n particles; event form): histories/s, the
     control kernels' share, and the figure of merit 1/(R^2 T) of the
@@ -231,8 +231,24 @@ def population_control_section(m, w, n, steps):
         ev, ot = m._binding.PROF_CLASSES.index("events"), m._binding.PROF_CLASSES.index("other")
         res["step_kernel_ms"] = float(prof[ev, 0])
         res["control_and_fill_kernels_ms"] = float(prof[ot, 0])
+        # the apply pass's particle-state bytes over the time of every
+        # control and fill kernel: a lower bound of the control's bandwidth
+        res["control_apply_bytes"] = float(prof[ot, 3])
+        res["control_GBps_lower_bound"] = float(prof[ot, 3] / (prof[ot, 0] * 1e-3) / 1e9) if prof[ot, 0] else None
+        res["control_hbm_peak_GBps"] = 8000.0
     finally:
         h.close()
+    if cpu:
+        # the oracle's census-synchronous run on a bounded sample, one core
+        import oracle
+        ns = 1_000_000
+        oracle.run_pc(prob, 2000, 1, 2000)
+        t0 = time.perf_counter()
+        oracle.run_pc(prob, ns, 92, ns)
+        dt = time.perf_counter() - t0
+        res["cpu_baseline"] = {"value": ns / dt, "unit": "histories/s", "cores": 1, "kind": "oracle",
+                               "sample": f"{ns} histories of the same workload with the population held at {ns}"}
+        log(f"population control oracle: {dt:.1f} s for {ns} histories")
     return res
 
 
@@ -504,7 +520,8 @@ def main():
     if not args.no_pins:
         extra["pins"] = pins_section(m, w, int(args.histories), args.steps)
     if not args.no_pc:
-        extra["population_control"] = population_control_section(m, w, int(args.histories), args.steps)
+        extra["population_control"] = population_control_section(m, w, int(args.histories), args.steps,
+                                                                 cpu=not args.no_cpu_baseline)
     if not args.no_batched:
         extra["batched"] = batched_section(m, w)
     if not args.no_fom:

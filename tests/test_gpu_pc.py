@@ -113,6 +113,11 @@ def test_population_control_rejections():
         # auto picks the event form
         g = m.mcdc_run(p, 2000, 1, algorithm="auto", pc_target=2000)
         assert g["splits"] > 0
+        # per-history debug counts follow each history's copies
+        g = m.mcdc_run(p, 2000, 1, pc_target=2000, debug=True)
+        dc = g["debug_counts"].cpu().numpy().astype(np.int64)
+        assert np.array_equal(dc[:, :3].sum(axis=0), np.asarray(g["events"], dtype=np.int64))
+        assert int(dc[:, 3].sum()) == 2000 + g["splits"]
     finally:
         p.close()
     q = m.mcdc_problem_create(w.azurv1_supercritical())
