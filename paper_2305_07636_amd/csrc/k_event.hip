@@ -1058,19 +1058,28 @@ Layout carve(void *bank_mem, void *ctl_mem, uint64_t slots, unsigned int G, unsi
     return Lo;
 }
 
-// Captured census steps (one graph per bank parity), cached per problem and
-// re-captured when any kernel argument changes.
+// Captured census steps, cached per problem and re-captured when any
+// kernel argument changes: one step per bank parity, and a stretch of
+// consecutive steps starting at either parity (all K steps of a chunk, or
+// with sampled profiling the steps between two sampled ones) so that a
+// stretch costs one graph launch instead of one per step.
 struct StepGraphs {
     std::vector<char> key;
     hipGraphExec_t exec[2] = {nullptr, nullptr};
     hipGraph_t graph[2] = {nullptr, nullptr};
+    hipGraphExec_t exec_run[2] = {nullptr, nullptr};
+    hipGraph_t graph_run[2] = {nullptr, nullptr};
     hipStream_t cs = nullptr;
     void clear() {
         for (int q = 0; q < 2; ++q) {
             if (exec[q]) (void)hipGraphExecDestroy(exec[q]);
             if (graph[q]) (void)hipGraphDestroy(graph[q]);
+            if (exec_run[q]) (void)hipGraphExecDestroy(exec_run[q]);
+            if (graph_run[q]) (void)hipGraphDestroy(graph_run[q]);
             exec[q] = nullptr;
             graph[q] = nullptr;
+            exec_run[q] = nullptr;
+            graph_run[q] = nullptr;
         }
         key.clear();
     }
@@ -1195,6 +1204,9 @@ int run_event(mcdc_problem *pb, const RunArgs &R0, uint64_t first, uint64_t coun
     const bool use_graph = !(opt.flags & MCDC_FLAG_EAGER) && !(opt.profile && every == 1) && !R.dbg_counts &&
                            !R.dbg_scores && P.K > 1;
     StepGraphs *Gr = nullptr;
+    // stretch of unsampled steps captured as one graph (none below 2 steps)
+    const int span = opt.profile ? every - 1 : P.K;
+    const int n_run = (span >= 2 && span <= 4096) ? (opt.profile ? 2 : 1) : 0;
     if (use_graph) {
         if (!pb->graph_cache) pb->graph_cache = new StepGraphs();
         Gr = (StepGraphs *)pb->graph_cache;
@@ -1208,6 +1220,8 @@ int run_event(mcdc_problem *pb, const RunArgs &R0, uint64_t first, uint64_t coun
         key_add(key, LT);
         key_add(key, one_kernel);
         key_add(key, pc);
+        key_add(key, span);
+        key_add(key, n_run);
         if (key != Gr->key) {
             Gr->clear();
             hipError_t e = hipSuccess;
@@ -1219,6 +1233,13 @@ int run_event(mcdc_problem *pb, const RunArgs &R0, uint64_t first, uint64_t coun
                 enqueue_step(q, Gr->cs, none, Rs);
                 e = hipStreamEndCapture(Gr->cs, &Gr->graph[q]);
                 if (e == hipSuccess) e = hipGraphInstantiate(&Gr->exec[q], Gr->graph[q], nullptr, nullptr, 0);
+            }
+            for (int q = 0; q < n_run && e == hipSuccess; ++q) {
+                e = hipStreamBeginCapture(Gr->cs, hipStreamCaptureModeThreadLocal);
+                if (e != hipSuccess) break;
+                for (int j = 0; j < span; ++j) enqueue_step((q + j) & 1, Gr->cs, none, Rs);
+                e = hipStreamEndCapture(Gr->cs, &Gr->graph_run[q]);
+                if (e == hipSuccess) e = hipGraphInstantiate(&Gr->exec_run[q], Gr->graph_run[q], nullptr, nullptr, 0);
             }
             if (e != hipSuccess) {
                 Gr->clear();
@@ -1236,8 +1257,18 @@ int run_event(mcdc_problem *pb, const RunArgs &R0, uint64_t first, uint64_t coun
         if (WW) split_reset(SB, st);
         launch_timed(prof, MCDC_PROF_SOURCE, k_source<FM, WW, false>, dim3(G), dim3(kBlock), 0u, st, P, R, L.bank[0],
                      L.ctl, n, (const BatchItem *)nullptr, (const SegInfo *)nullptr);
-        for (int step = 0; step < P.K; ++step) {
+        for (int step = 0; step < P.K;) {
             const bool sampled = opt.profile && step % every == opt.profile_phase % every;
+            // a whole stretch of unsampled steps from here: from step 0
+            // without profiling, else right after a sampled step
+            const bool stretch = Gr && n_run > 0 && step + span <= P.K &&
+                                 (opt.profile ? step % every == (opt.profile_phase % every + 1) % every : step == 0);
+            if (stretch) {
+                hipError_t e = hipGraphLaunch(Gr->exec_run[(pc || n_run == 1) ? 0 : (step & 1)], st);
+                if (e != hipSuccess) return hip_fail(e, "census steps replay");
+                step += span;
+                continue;
+            }
             if (Gr && !sampled) {
                 hipError_t e = hipGraphLaunch(Gr->exec[pc ? 0 : (step & 1)], st);
                 if (e != hipSuccess) return hip_fail(e, "census step replay");
@@ -1245,6 +1276,7 @@ int run_event(mcdc_problem *pb, const RunArgs &R0, uint64_t first, uint64_t coun
                 Profiler none;
                 enqueue_step(step & 1, st, sampled ? prof : none, sampled ? Rp : Rs);
             }
+            ++step;
         }
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return hip_fail(e, "event kernel launch");
