@@ -7,11 +7,13 @@
 //
 // Segment-private pipelines.  Every bank is cut into G segments of L slots,
 // one per workgroup: workgroup b of every kernel works only on segment b,
-// and a particle never leaves the segment it was born in.  Queue appends
-// therefore need no device-wide atomics (ballots, mbcnt prefix counts, one
-// LDS atomic per wave; no contention across the 8 XCDs), and each segment
-// holds a contiguous range of histories, so its particles belong to at
-// most two tally batches.
+// and a particle never leaves the segment it was born in (except under
+// population control, whose copies are spread over all segments).  Queue
+// appends therefore need no device-wide atomics (ballots, mbcnt prefix
+// counts, one LDS atomic per wave; no contention across the 8 XCDs), and
+// each segment holds a contiguous range of histories, so its particles
+// belong to at most two tally batches (scores of any other batch go to
+// HBM directly).
 //
 // One kernel per census step (default): the events kernel takes the step's
 // bank as its work list; each lane follows its particle through its
@@ -88,7 +90,7 @@ struct Ctl {
     unsigned long long *pc_w;  // [G][2] population control: fixed-point weight sum per segment
     unsigned long long *pc_cnt;  // [G] population control: copies made from each segment
     unsigned int G, L;      // segments (= workgroups), slots per segment
-    unsigned int Lh;        // histories per segment (L, or L / 2 with population control)
+    unsigned int Lh;        // histories per segment (L, or fewer with population control)
 };
 
 __device__ __forceinline__ uint32_t pack_gk(int g, int b, int k, int inpin) {
