@@ -239,10 +239,11 @@ typedef struct {
  *                 paper lists population control among the time-dependent
  *                 features (Section 2) without a method; this is
  *                 splitting-roulette to pc_target particles at every census
- *                 edge T_k, k < K, over the particles that just crossed it:
+ *                 edge T_k, k < K, over the particles whose clock stands at
+ *                 T_k (those that just crossed it and those born in bin k):
  *                 their total weight W is summed exactly (128-bit fixed
  *                 point, 64 fractional bits, each weight truncated to a
- *                 multiple of 2^-64), w_t = W / pc_target, and each crosser
+ *                 multiple of 2^-64), w_t = W / pc_target, and each of them
  *                 draws xi and goes on as n = floor(w / w_t + xi) copies of
  *                 weight w_t (copy 0 keeps the stream after the draw, copy
  *                 j >= 1 takes the child stream j of it; n = 0 counts as

@@ -100,13 +100,14 @@
  *       control among the time-dependent features, without a method):
  *       splitting-roulette to a target population N_t.  The run tracks all
  *       particles census step by census step.  At each census edge T_k
- *       (k < K) the particles that just crossed it are controlled together;
- *       particles born later are not touched.  Their total weight W is
- *       summed exactly, order-free, in 128-bit fixed point with 64
+ *       (k < K) the particles whose clock stands at T_k (those that just
+ *       crossed it, and those born in time bin k) are controlled together;
+ *       particles born in later bins are not touched.  Their total weight W
+ *       is summed exactly, order-free, in 128-bit fixed point with 64
  *       fractional bits (each weight truncated to a multiple of 2^-64; a
  *       weight of 2^32 or more is an error).  W becomes a double as
  *       hi + ((lo >> 32) 2^-32 + (lo mod 2^32) 2^-64), and w_t = W / N_t.
- *       Each crosser, in any order, draws xi and makes
+ *       Each of them, in any order, draws xi and makes
  *       n = floor(w / w_t + xi) copies of weight w_t (n = 0: the particle
  *       ends, rouletted).  Copy 0 keeps the stream after the draw; copy
  *       j >= 1 takes child_stream of that state and j (as R10's splits) and
