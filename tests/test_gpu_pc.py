@@ -4,7 +4,8 @@ census-synchronous run: every event, termination and split count agrees
 exactly and the tallies within the stated tolerances (gpu_common).  Cases:
 the decaying pulsed slab (analog and implicit capture), a void reflective
 box whose population doubles exactly, the same box with births spread over
-its time bins (later births wait for their own edge), a multigroup reflective box with the
+its time bins (later births wait for their own edge), a steady-state
+problem with no inner edge, a target of one particle, a multigroup reflective box with the
 time-crossing tally, a ragged history count with a target above and below
 it, both step forms; then the 1e7-history pulsed slab at full size against
 the closed form of its spatially integrated flux."""
@@ -54,6 +55,8 @@ CASES = {
     "void_spread_births": (_void_spread, 4000, 1.0, 68),
     "ragged_up": (lambda: _slab_pulse(0.7, K=13, batches=7), 12345, 1.5, 65),
     "ragged_down": (lambda: _slab_pulse(0.7, K=13, batches=7), 12345, 0.4, 66),
+    "steady_no_edge": (lambda: w.cfg1_slab_steady(c=0.5), 3000, 1.0 / 3.0, 69),
+    "target_one": (_void_reflective, 2000, 1.0 / 2000, 70),
 }
 
 

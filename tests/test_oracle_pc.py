@@ -156,3 +156,28 @@ def test_later_births_wait_for_their_own_edge():
     tk = pc["S"].sum(axis=0).reshape(4, -1).sum(axis=1)
     ta = an["S"].sum(axis=0).reshape(4, -1).sum(axis=1)
     np.testing.assert_allclose(tk, ta, rtol=0.05)
+
+
+def test_steady_state_has_no_edge_to_control():
+    """One time bin [0, inf): no inner census edge, so the controlled run is
+    the uncontrolled one (same events, same tallies)."""
+    prob = W.cfg1_slab_steady(c=0.5)
+    N = 3000
+    pc = oracle.run_pc(prob, N, 23, target=N // 3)
+    an = oracle.run(prob, N, 23)
+    assert np.array_equal(pc["tot"], an["tot"])
+    np.testing.assert_allclose(pc["S"], an["S"], rtol=1e-13, atol=0)
+    assert list(pc["pop"]) == [N]
+
+
+def test_target_of_one_particle():
+    """Target 1: every edge keeps about one particle of the whole weight; the
+    run stays balanced and unbiased in expectation (a single edge: the
+    expected number of survivors is exactly 1)."""
+    prob = _void_reflective()
+    N = 2000
+    pc = oracle.run_pc(prob, N, 29, target=1)
+    born = int(pc["pop"][0])
+    t = pc["tot"].astype(np.int64)
+    assert born + t[8] == t[3 + oracle.T_ROULETTE] + t[3 + oracle.T_TIME]
+    assert all(int(x) <= 10 for x in pc["pop"][1:])
