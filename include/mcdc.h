@@ -258,12 +258,13 @@ typedef struct {
  */
 #define MCDC_FLAG_EAGER 1
 #define MCDC_FLAG_TWO_KERNEL_STEP 2
-#define MCDC_PROF_CLASSES 5
+#define MCDC_PROF_CLASSES 6
 #define MCDC_PROF_SOURCE 0     /* event form: source sampling */
 #define MCDC_PROF_ADVANCE 1    /* event form: one flight over the census bank */
 #define MCDC_PROF_EVENTS 2     /* event form: surface and collision queues, on to census */
 #define MCDC_PROF_HISTORY 3    /* history form (and weight-window progeny) */
 #define MCDC_PROF_OTHER 4      /* fills, control, batch statistics */
+#define MCDC_PROF_CONTROL 5    /* event form: population control at census */
 typedef struct {
     int32_t algorithm;
     int32_t block_size;

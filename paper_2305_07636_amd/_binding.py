@@ -65,7 +65,7 @@ class mcdc_run_options(C.Structure):
     ]
 
 
-PROF_CLASSES = ["source", "advance", "events", "history", "other"]
+PROF_CLASSES = ["source", "advance", "events", "history", "other", "control"]
 
 
 class mcdc_result(C.Structure):

@@ -762,20 +762,37 @@ __device__ __forceinline__ uint32_t clock_of(uint32_t gk) { return (gk >> 15) & 
 // overflow flag values of population control (1: particle or split bank)
 constexpr int kOvfWeight = 2, kOvfCopies = 3, kOvfSegment = 4;
 
-__global__ void __launch_bounds__(kBlock) k_pc_sum(Bank next, Ctl C, int par, int *overflow) {
+// profile tallies of a control kernel: particles and bytes, per wave
+__device__ __forceinline__ void pc_prof(const RunArgs &R, unsigned long long items, unsigned long long bytes) {
+    if (!R.prof) return;
+    for (int o = 32; o > 0; o >>= 1) {
+        items += __shfl_xor(items, o);
+        bytes += __shfl_xor(bytes, o);
+    }
+    if (__lane_id() == 0 && (items | bytes)) {
+        atomicAdd(R.prof + 2 * MCDC_PROF_CONTROL, items);
+        atomicAdd(R.prof + 2 * MCDC_PROF_CONTROL + 1, bytes);
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_pc_sum(RunArgs R, Bank next, Ctl C, int par) {
     __shared__ unsigned long long part[kBlock / 64][2];
     const unsigned int seg = blockIdx.x;
     const unsigned int n = C.n_bank[(par ^ 1) * C.G + seg];
     const uint32_t edge = (uint32_t)(*C.step + 1);
     const uint32_t seg0 = seg * C.L;
-    unsigned long long hi = 0ull, lo = 0ull;
+    unsigned long long hi = 0ull, lo = 0ull, items = 0ull, bytes = 0ull;
     bool ok = true;
     for (uint32_t r = threadIdx.x; r < n; r += kBlock) {
         const uint32_t slot = seg0 + r;
+        items += 1ull;
+        bytes += 4ull;
         if (clock_of(fld<uint32_t>(next, next.ogk, tile_off4(next, slot))) != edge) continue;
+        bytes += 8ull;
         ok = fixed_add(hi, lo, fld<double>(next, next.ow, tile_off8(next, slot))) && ok;
     }
-    if (!ok) *overflow = kOvfWeight;
+    pc_prof(R, items, bytes);
+    if (!ok) *R.overflow = kOvfWeight;
     for (int o = 32; o > 0; o >>= 1) {
         const unsigned long long h2 = __shfl_xor(hi, o), l2 = __shfl_xor(lo, o);
         fixed_merge(hi, lo, h2, l2);
@@ -871,15 +888,17 @@ __global__ void __launch_bounds__(kBlock) k_pc_count(RunArgs R, Bank next, Ctl C
     const unsigned int n = C.n_bank[(par ^ 1) * C.G + seg];
     const int edge = *C.step + 1;
     const uint32_t seg0 = seg * C.L;
-    unsigned long long tot = 0ull;
+    unsigned long long tot = 0ull, items = 0ull;
     for (uint32_t r = threadIdx.x; r < n; r += kBlock) {
         const uint32_t slot = seg0 + r;
+        items += 1ull;
         Particle p;
         p.k = (int)clock_of(fld<uint32_t>(next, next.ogk, tile_off4(next, slot)));
         p.w = fld<double>(next, next.ow, tile_off8(next, slot));
         p.s = fld<uint64_t>(next, next.os, tile_off8(next, slot));
         tot += pc_copies(p, edge, on, wt, cap, R);
     }
+    pc_prof(R, items, 20ull * items);   // clock word, weight, stream
     for (int o = 32; o > 0; o >>= 1) tot += __shfl_xor(tot, o);
     if (__lane_id() == 0) part[threadIdx.x >> 6] = tot;
     __syncthreads();
@@ -964,7 +983,7 @@ __global__ void __launch_bounds__(kBlock) k_pc_apply(DevProblem P, RunArgs R, Ba
         }
         if (R.prof) cnt.prof(valid ? 1u : 0u, valid ? (unsigned int)((copies + 1ull) * state_bytes<FM, true>(P)) : 0u);
     }
-    cnt.flush(R, MCDC_PROF_OTHER, red);
+    cnt.flush(R, MCDC_PROF_CONTROL, red);
 }
 
 // ---------------------------------------------------------------------------
@@ -1192,9 +1211,9 @@ int run_event(mcdc_problem *pb, const RunArgs &R0, uint64_t first, uint64_t coun
         }
         if constexpr (WW) {
             if (pc) {
-                launch_timed(pr, MCDC_PROF_OTHER, k_pc_sum, dim3(G), dim3(kBlock), 0u, s, nxt, L.ctl, par, Ra.overflow);
-                launch_timed(pr, MCDC_PROF_OTHER, k_pc_count, dim3(G), dim3(kBlock), 0u, s, Ra, nxt, L.ctl, par, pc);
-                launch_timed(pr, MCDC_PROF_OTHER, k_pc_apply<FM>, dim3(G), dim3(kBlock), 0u, s, P, Ra, nxt, cur, L.ctl,
+                launch_timed(pr, MCDC_PROF_CONTROL, k_pc_sum, dim3(G), dim3(kBlock), 0u, s, Ra, nxt, L.ctl, par);
+                launch_timed(pr, MCDC_PROF_CONTROL, k_pc_count, dim3(G), dim3(kBlock), 0u, s, Ra, nxt, L.ctl, par, pc);
+                launch_timed(pr, MCDC_PROF_CONTROL, k_pc_apply<FM>, dim3(G), dim3(kBlock), 0u, s, P, Ra, nxt, cur, L.ctl,
                              par, pc);
             }
         }
