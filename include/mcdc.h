@@ -263,7 +263,7 @@ typedef struct {
 #define MCDC_PROF_ADVANCE 1    /* event form: one flight over the census bank */
 #define MCDC_PROF_EVENTS 2     /* event form: surface and collision queues, on to census */
 #define MCDC_PROF_HISTORY 3    /* history form (and weight-window progeny) */
-#define MCDC_PROF_OTHER 4      /* fills, control, batch statistics */
+#define MCDC_PROF_OTHER 4      /* fills, step counters, batch statistics */
 #define MCDC_PROF_CONTROL 5    /* event form: population control at census */
 typedef struct {
     int32_t algorithm;
