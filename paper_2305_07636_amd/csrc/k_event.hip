@@ -762,16 +762,26 @@ __device__ __forceinline__ uint32_t clock_of(uint32_t gk) { return (gk >> 15) & 
 // overflow flag values of population control (1: particle or split bank)
 constexpr int kOvfWeight = 2, kOvfCopies = 3, kOvfSegment = 4;
 
-// profile tallies of a control kernel: particles and bytes, per wave
-__device__ __forceinline__ void pc_prof(const RunArgs &R, unsigned long long items, unsigned long long bytes) {
+// profile tallies of a control kernel (particles, bytes): reduced per wave,
+// then per workgroup in LDS, one global atomic per workgroup and counter;
+// called by every thread of the workgroup
+__device__ void pc_prof(const RunArgs &R, unsigned long long items, unsigned long long bytes) {
+    __shared__ unsigned long long acc[2];
     if (!R.prof) return;
+    if (threadIdx.x == 0) acc[0] = acc[1] = 0ull;
+    __syncthreads();
     for (int o = 32; o > 0; o >>= 1) {
         items += __shfl_xor(items, o);
         bytes += __shfl_xor(bytes, o);
     }
-    if (__lane_id() == 0 && (items | bytes)) {
-        atomicAdd(R.prof + 2 * MCDC_PROF_CONTROL, items);
-        atomicAdd(R.prof + 2 * MCDC_PROF_CONTROL + 1, bytes);
+    if (__lane_id() == 0) {
+        atomicAdd(&acc[0], items);
+        atomicAdd(&acc[1], bytes);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        atomicAdd(R.prof + 2 * MCDC_PROF_CONTROL, acc[0]);
+        atomicAdd(R.prof + 2 * MCDC_PROF_CONTROL + 1, acc[1]);
     }
 }
 
