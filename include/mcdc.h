@@ -10,8 +10,14 @@
  * time-averaged flux (Section 3.1).  Analog tracking means uniform particle
  * weight and no variance reduction (Section 3.3).  The tracking runs in two
  * forms the paper names (Section 2): history-based (one GPU thread follows
- * one particle to its death) and event-based (particles are sorted into
- * per-event queues and processed event kernel by event kernel).
+ * one particle to its death) and event-based (the particles of a census
+ * step live in a structure-of-arrays bank; by default one kernel per census
+ * step takes every particle of the step's bank through its events in
+ * registers, refilling idle lanes from the bank, and files the census
+ * crossers into the next step's bank with wave-ballot appends; with
+ * MCDC_FLAG_TWO_KERNEL_STEP an advance kernel sorts the particles into
+ * per-event census, surface and collision queues and an events kernel
+ * works the queues).
  *
  * Conventions shared by every entry point
  *  - Units are arbitrary but consistent (length, 1/length, length/time,

@@ -725,36 +725,29 @@ __global__ void __launch_bounds__(kBlock) k_event(DevProblem P0, RunArgs R0, Ban
 // stream after the draw, copy j >= 1 takes child_stream(s, j)), a particle
 // of a later time bin unchanged.
 
-// w truncated to a multiple of 2^-64, as the 128-bit integer (hi, lo),
-// added to (hi, lo); false if w is 2^32 or more, negative or not a number.
+// 128-bit fixed-point weight sums with 64 fractional bits: a weight w is
+// truncated to a multiple of 2^-64 and added to the accumulator (hi, lo).
+// floor(w) is exact in binary64 and so is the fraction w - floor(w); the
+// fraction times 2^64 (a power-of-two scaling, below 2^64) truncated to an
+// integer is the low word.  False if w is 2^32 or more, negative or not a
+// number.
 __device__ __forceinline__ bool fixed_add(unsigned long long &hi, unsigned long long &lo, double w) {
     if (!(w >= 0.0) || !(w < 4294967296.0)) return false;
-    const unsigned long long bits = (unsigned long long)__double_as_longlong(w);
-    const int e = (int)((bits >> 52) & 0x7FFu);
-    if (e == 0) return true;   // zero or subnormal: below 2^-64
-    const unsigned long long m = (bits & ((1ull << 52) - 1ull)) | (1ull << 52);
-    const int sh = e - 1011;   // w 2^64 = m 2^(e - 1011)
-    unsigned long long h = 0ull, l = 0ull;
-    if (sh >= 64) {
-        h = m << (sh - 64);
-    } else if (sh > 0) {
-        h = m >> (64 - sh);
-        l = m << sh;
-    } else if (sh == 0) {
-        l = m;
-    } else if (sh > -64) {
-        l = m >> (-sh);
-    }
-    const unsigned long long nl = lo + l;
-    hi += h + (nl < lo ? 1ull : 0ull);
-    lo = nl;
+    const double whole = floor(w);
+    const double frac = w - whole;
+    const unsigned long long fbits = __double2ull_rz(frac * 18446744073709551616.0);
+    unsigned __int128 acc = ((unsigned __int128)hi << 64) | lo;
+    acc += ((unsigned __int128)(unsigned long long)whole << 64) + fbits;
+    hi = (unsigned long long)(acc >> 64);
+    lo = (unsigned long long)acc;
     return true;
 }
 __device__ __forceinline__ void fixed_merge(unsigned long long &hi, unsigned long long &lo, unsigned long long h2,
                                             unsigned long long l2) {
-    const unsigned long long nl = lo + l2;
-    hi += h2 + (nl < lo ? 1ull : 0ull);
-    lo = nl;
+    unsigned __int128 acc = ((unsigned __int128)hi << 64) | lo;
+    acc += ((unsigned __int128)h2 << 64) | l2;
+    hi = (unsigned long long)(acc >> 64);
+    lo = (unsigned long long)acc;
 }
 
 __device__ __forceinline__ uint32_t clock_of(uint32_t gk) { return (gk >> 15) & 0xFFFFu; }

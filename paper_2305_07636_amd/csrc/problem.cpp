@@ -308,7 +308,17 @@ int compile(const mcdc_problem_desc *d, HostProblem &h) {
             q_of[a][i] = d->qoi_enabled ? (left >= d->qoi_lo[a] && right <= d->qoi_hi[a]) : 1;
         }
     }
-    const size_t ncells = (size_t)h.nc[0] * h.nc[1] * h.nc[2];
+    // Union-cell, tally-bin and window-cell indices are 32-bit in the device
+    // tables and kernels; a grid whose cell count exceeds that is refused
+    // before anything is allocated (tally and window meshes never have more
+    // cells per axis than the union grid, so one bound covers all three).
+    const uint64_t ncells64 = (uint64_t)h.nc[0] * (uint64_t)h.nc[1] * (uint64_t)h.nc[2];
+    if (ncells64 > (uint64_t)INT32_MAX) {
+        set_error("union grid has more than 2^31 - 1 cells (" + std::to_string(h.nc[0]) + " x " +
+                  std::to_string(h.nc[1]) + " x " + std::to_string(h.nc[2]) + ")");
+        return MCDC_E_UNSUPPORTED;
+    }
+    const size_t ncells = (size_t)ncells64;
     h.cell_mat.resize(ncells);
     h.cell_tal.resize(ncells);
     h.cell_ww.resize(ncells);

@@ -144,7 +144,7 @@ def _frontier_table(logI, ok, shape, pct):
     return centres_from_log_importance(np.where(ok, logI, -np.inf), log_ref, shape)
 
 
-def learned_windows(prob: dict, n_pilot: int = 100_000_000, seed: int = 50, steps: int = 3000,
+def learned_windows(prob: dict, n_pilot: int = 100_000_000, seed: int = 1000, steps: int = 3000,
                     lr: float = 1e-3, net_seed: int = 1, rel_max: float = 0.3, frontier_pct: float = 5.0,
                     below: float = 0.0, extrapolate: float = 1.0, normalise: str = "auto"):
     """Plain pilots -> training set -> network -> window table.
@@ -165,8 +165,13 @@ def learned_windows(prob: dict, n_pilot: int = 100_000_000, seed: int = 50, step
     "source" (the network's importance at the source cells, resolved or
     not) or "frontier".
 
-    Returns (table [K][G][wz][wy][wx], info dict with the raw-tally table
-    and timings)."""
+    The pilots run with seeds `seed` (forward) and `seed + 1` (adjoint),
+    returned as info["pilot_seeds"]: a run judged with these windows should
+    take other seeds, so that the table does not depend on the very
+    histories it is judged on.
+
+    Returns (table [K][G][wz][wy][wx], info dict with the raw-tally table,
+    the pilot seeds and timings)."""
     import torch
 
     adj = adjoint_problem(prob)
@@ -213,7 +218,7 @@ def learned_windows(prob: dict, n_pilot: int = 100_000_000, seed: int = 50, step
                                       below if use_source else 0.0)
     info = {"pilot_s": t_pilot, "train_s": t_train, "n_train": int(ok.sum()), "loss_first": float(losses[0]),
             "loss_last": float(losses[-1]), "raw_table": raw, "adjoint_flux": phi,
-            "source_resolved": bool(src_resolved), "log_ref": log_ref}
+            "source_resolved": bool(src_resolved), "log_ref": log_ref, "pilot_seeds": (seed, seed + 1)}
     return table, info
 
 

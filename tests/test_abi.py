@@ -171,3 +171,21 @@ def test_missing_library_fails_loudly(tmp_path):
             "    print('raised', e)\n")
     r = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True, timeout=120)
     assert "raised" in r.stdout and "is not built" in r.stdout, (r.stdout, r.stderr)
+
+
+def test_union_grid_beyond_32bit_cell_count_refused():
+    """A grid of 2047 x 2047 x 600 union cells (2.5e9 > 2^31 - 1) passes the
+    per-axis limits but its cell indices do not fit the device's 32-bit
+    tables: it is refused with MCDC_E_UNSUPPORTED before the per-cell tables
+    (tens of GB) are built or anything reaches a device."""
+    p = w.reflective_box([1.0], [[0.5]], [1.0], size=(20.47, 20.47, 6.0))
+    p["tally"]["mesh"] = [np.linspace(0.0, 20.47, 2048), np.linspace(0.0, 20.47, 2048),
+                          np.linspace(0.0, 6.0, 601)]
+    rc, msg = _create(p)
+    assert rc == -5 and "2^31" in msg, (rc, msg)
+    # one z-cell fewer than the bound along each axis is still accepted by the
+    # per-axis check: 2047 x 2047 x 1 cells compiles past the cell bound
+    # (it is the 32-bit product, not an axis, that is refused)
+    p["tally"]["mesh"][2] = np.array([0.0, 6.0])
+    rc, msg = _create(p)
+    assert "2^31" not in msg, (rc, msg)
