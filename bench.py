@@ -28,6 +28,7 @@ WORKLOAD = ("pulsed slab: 1 group, Sigma_t=1, c=0.9, v=1, 40 mfp, isotropic cent
             "50 x-bins x 100 time bins on [0,20], 1e7 histories, FP64")
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_event_step_pulsed_slab_1e7_traffic.json")
+LATTICE_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_event_step_lattice_1e8_traffic.json")
 KERNEL_SOURCES = ["paper_2305_07636_amd/csrc/k_event.hip", "paper_2305_07636_amd/csrc/k_common.hpp",
                   "paper_2305_07636_amd/csrc/mcdc_internal.hpp", "paper_2305_07636_amd/build.py"]
 T_START = time.perf_counter()
@@ -50,6 +51,25 @@ def cpu_worker(args):
     return time.perf_counter() - t0
 
 
+def host_cpu():
+    """The host CPU as lscpu reports it, and what this process may use (one
+    GPU's share of the host: at most 16 worker processes)."""
+    import subprocess
+
+    info = {"os_cpu_count": os.cpu_count(), "affinity": len(os.sched_getaffinity(0))}
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=20).stdout
+        keep = ("Model name", "CPU(s)", "Thread(s) per core", "Core(s) per socket", "Socket(s)",
+                "CPU max MHz", "L3 cache")
+        for ln in out.splitlines():
+            k, _, v = ln.partition(":")
+            if k.strip() in keep:
+                info[k.strip()] = v.strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    return info
+
+
 def cpu_baseline(N, seed, target_s=15.0):
     """The oracle as it stands, on the host cores, over a bounded sample of
     the same job (histories 0..n-1), in independent processes over
@@ -60,7 +80,8 @@ def cpu_baseline(N, seed, target_s=15.0):
     import oracle
 
     oracle.build()
-    cores = min(16, os.cpu_count() or 1)
+    # one GPU's share of the host: 16 worker processes at most
+    cores = min(16, len(os.sched_getaffinity(0)) or 1)
     # calibrate the per-core rate on a short range
     t = cpu_worker((0, 20000, N, seed))
     rate1 = 20000 / t
@@ -74,7 +95,7 @@ def cpu_baseline(N, seed, target_s=15.0):
         list(ex.map(cpu_worker, [(j * per, per, N, seed) for j in range(cores)]))
         wall = time.perf_counter() - t0
     return {
-        "value": n / wall, "unit": "histories/s", "cores": cores, "kind": "oracle",
+        "value": n / wall, "unit": "histories/s", "cores": cores, "kind": "oracle", "host": host_cpu(),
         "sample": f"histories 0..{n - 1} of the {N:.0e}-history job, {cores} processes x {per} "
                   f"contiguous histories, serial C oracle (gcc -O2, no contraction), wall {wall:.1f} s",
         "single_core_histories_per_s": rate1,
@@ -91,12 +112,12 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def measured_traffic():
+def measured_traffic(path=TRAFFIC_FILE):
     """HBM bytes per census-step kernel launch (the event form's k_event
-    over the step's bank) from the committed FETCH_SIZE / WRITE_SIZE
+    over the step's bank) from a committed FETCH_SIZE / WRITE_SIZE
     summary, or None if the kernel sources changed since."""
     try:
-        with open(TRAFFIC_FILE) as fh:
+        with open(path) as fh:
             rec = json.load(fh)
     except (OSError, ValueError):
         return None
@@ -323,47 +344,210 @@ def eigen_section(m, w, n_per_cycle, n_inactive, n_active):
             "k_mean": out["k_mean"], "k_std": out["k_std"]}
 
 
-def fom_section(w, n_pilot, n_analog, n_ww, steps):
-    """Dog-leg duct, detector behind the second bend: analog against learned
-    weight windows (pilots, network fit, BF16 inference) and against windows
-    from the raw pilot tally with no network."""
+def pooled(runs):
+    """Independent runs of one estimator with equal history counts pooled
+    into one estimate: the mean of the means, the variance of that mean
+    (sum of the runs' variances over their number squared), the summed
+    tracking time, and FOM = 1 / (R^2 T); plus each run's own FOM."""
+    k = len(runs)
+    mean = sum(r["mean"] for r in runs) / k
+    var = sum(r["sigma"] ** 2 for r in runs) / (k * k)
+    T = sum(r["T_s"] for r in runs)
+    R = math.sqrt(var) / mean if mean > 0 else math.inf
+    return {"runs": k, "mean": mean, "sigma": math.sqrt(var), "R": R, "T_s": T,
+            "fom": 1.0 / (R * R * T) if mean > 0 else 0.0,
+            "fom_per_run": [r["fom"] for r in runs], "splits": sum(r.get("splits", 0) for r in runs)}
+
+
+def fom_gain(num, den):
+    """Ratio of pooled FOMs with a 95 % interval from the spread of the
+    runs' own FOMs (log scale, t quantile for the smaller replica count)."""
+    g = num["fom"] / den["fom"] if den["fom"] > 0 else None
+    if g is None or num["runs"] < 2 or den["runs"] < 2:
+        return {"gain": g, "ci95": None}
+
+    def se_log(x):
+        v = [math.log(f) for f in x["fom_per_run"]]
+        mu = sum(v) / len(v)
+        return math.sqrt(sum((a - mu) ** 2 for a in v) / (len(v) - 1) / len(v))
+
+    tq = {1: 12.71, 2: 4.30, 3: 3.18, 4: 2.78, 5: 2.57, 6: 2.45, 7: 2.36, 8: 2.31, 9: 2.26}
+    t = tq.get(min(num["runs"], den["runs"]) - 1, 2.0)
+    h = t * math.hypot(se_log(num), se_log(den))
+    return {"gain": g, "ci95": [g * math.exp(-h), g * math.exp(h)]}
+
+
+def fom_section(w, pilots, n_analog_run, analog_runs, n_ww, ww_runs, steps):
+    """Dog-leg duct, detector behind the second bend (figure of merit
+    1/(R^2 T), T the tracking time of the runs): analog Monte Carlo as the
+    reference, run as independent replicas until its relative error is
+    about 0.05; learned weight windows (forward and adjoint analog pilots,
+    network fit on FP32 matrix cores, BF16 inference) built from pilots of
+    each size in `pilots`, each judged over independent windowed replicas;
+    windows taken straight from the raw adjoint pilot tally (no network);
+    and implicit capture.  The pilots take seeds 1000 and 1001, the judged
+    runs seeds of their own.  Reported per pilot size: the pooled FOM, the
+    FOM with the pilot and training time added to T, the gain over analog
+    with its 95 % interval, and the distance of the means in sigma."""
     from paper_2305_07636_amd import learned_ww as lw
 
     p = w.cfg5_dogleg()
-    t0 = time.perf_counter()
-    table, info = lw.learned_windows(p, n_pilot=n_pilot, steps=steps, seed=1000)
-    assert not {51, 52, 53, 54} & set(info["pilot_seeds"])     # judged runs use other seeds
-    t_build = time.perf_counter() - t0
-    log(f"fom: windows built in {t_build:.1f} s")
-    a = lw.figure_of_merit(p, n_analog, 52)
-    log(f"fom: analog {a}")
-    b = lw.figure_of_merit(p, n_ww, 51, table=table)
-    log(f"fom: learned {b}")
-    c = lw.figure_of_merit(p, n_ww, 53, table=info["raw_table"])
-    log(f"fom: raw-tally windows {c}")
+    a_runs = []
+    for r in range(analog_runs):
+        a_runs.append(lw.figure_of_merit(p, n_analog_run, 5200 + r))
+    a = pooled(a_runs)
+    log(f"fom: analog {analog_runs} x {n_analog_run:.0e}: mean {a['mean']:.4g} R {a['R']:.4f} "
+        f"T {a['T_s']:.2f} s FOM {a['fom']:.3g}")
+
+    def diff(x, y):
+        s_ = math.hypot(x["sigma"], y["sigma"])
+        return abs(x["mean"] - y["mean"]) / s_ if s_ > 0 else None
+
+    res = {
+        "workload": "dog-leg duct 30x10x10, 2 groups, 40x10x10 window mesh, detector box "
+                    "[29,30]x[7,9]x[4,6]; history form",
+        "analog": dict(a, histories=n_analog_run * analog_runs),
+    }
+    judged = set()
+    for n_pilot in pilots:
+        t0 = time.perf_counter()
+        table, info = lw.learned_windows(p, n_pilot=n_pilot, steps=steps, seed=1000)
+        t_build = time.perf_counter() - t0
+        seeds = [5100 + 10 * r + len(res) for r in range(ww_runs)]
+        assert not set(seeds) & set(info["pilot_seeds"]) and not set(seeds) & judged
+        judged |= set(seeds)
+        b = pooled([lw.figure_of_merit(p, n_ww, sd, table=table) for sd in seeds])
+        c_seeds = [6100 + 10 * r + len(res) for r in range(2)]
+        c = pooled([lw.figure_of_merit(p, n_ww, sd, table=info["raw_table"]) for sd in c_seeds])
+        overhead = info["pilot_s"] + info["train_s"]
+        fom_incl = 1.0 / (b["R"] ** 2 * (b["T_s"] + overhead)) if b["mean"] > 0 else 0.0
+        tag = f"pilot_{n_pilot:.0e}".replace("+", "")
+        res[tag] = {
+            "pilot_histories": n_pilot, "train_steps": steps, "window_build_s": t_build,
+            "pilot_s": info["pilot_s"], "train_s": info["train_s"],
+            "loss": [info["loss_first"], info["loss_last"]], "source_resolved": info["source_resolved"],
+            "learned": dict(b, histories=n_ww * ww_runs),
+            "fom_gain_learned_vs_analog": fom_gain(b, a),
+            "fom_incl_pilot_and_training": fom_incl,
+            "fom_gain_incl_pilot_and_training": fom_incl / a["fom"] if a["fom"] > 0 else None,
+            "mean_diff_sigma_learned_vs_analog": diff(a, b),
+            "raw_tally_windows": dict(c, histories=n_ww * 2),
+            "fom_gain_raw_vs_analog": c["fom"] / a["fom"] if a["fom"] > 0 else None,
+            "fom_gain_learned_vs_raw": b["fom"] / c["fom"] if c["fom"] > 0 else None,
+            "mean_diff_sigma_raw_vs_analog": diff(a, c),
+        }
+        log(f"fom: pilots {n_pilot:.0e}: learned R {b['R']:.4f} T {b['T_s']:.2f} s gain "
+            f"{res[tag]['fom_gain_learned_vs_analog']}, incl. pilot+training "
+            f"{res[tag]['fom_gain_incl_pilot_and_training']:.2f}, mean diff {diff(a, b):.2f} sigma")
     # implicit capture (Section 3 runs the time-dependent duct with it),
     # roulette below weight 0.25 to weight 1
     pic = dict(p, implicit_capture={"w_min": 0.25, "w_survive": 1.0})
-    d = lw.figure_of_merit(pic, n_ww, 54)
-    log(f"fom: implicit capture {d}")
+    d = pooled([lw.figure_of_merit(pic, n_ww, 5400)])
+    res["implicit_capture"] = dict(d, histories=n_ww)
+    res["fom_gain_implicit_vs_analog"] = d["fom"] / a["fom"] if a["fom"] > 0 else None
+    res["mean_diff_sigma_implicit_vs_analog"] = diff(a, d)
+    log(f"fom: implicit capture {d['fom']:.3g}")
+    return res
 
-    def diff(x, y):
-        s = math.hypot(x["sigma"], y["sigma"])
-        return abs(x["mean"] - y["mean"]) / s if s > 0 else None
 
-    return {
-        "workload": "dog-leg duct 30x10x10, 2 groups, 40x10x10 window mesh, detector box "
-                    "[29,30]x[7,9]x[4,6]",
-        "pilot_histories": n_pilot, "train_steps": steps, "window_build_s": t_build,
-        "pilot_s": info["pilot_s"], "train_s": info["train_s"], "loss": [info["loss_first"], info["loss_last"]],
-        "analog": a, "learned": b, "raw_tally_windows": c, "implicit_capture": d,
-        "fom_gain_implicit_vs_analog": (d["fom"] / a["fom"]) if a["fom"] > 0 else None,
-        "mean_diff_sigma_implicit_vs_analog": diff(a, d),
-        "fom_gain_learned_vs_analog": (b["fom"] / a["fom"]) if a["fom"] > 0 else None,
-        "fom_gain_learned_vs_raw": (b["fom"] / c["fom"]) if c["fom"] > 0 else None,
-        "mean_diff_sigma_learned_vs_analog": diff(a, b),
-        "mean_diff_sigma_raw_vs_analog": diff(a, c),
-    }
+def timed_runs(m, p, N, seed, steps, warmup, alg, traffic_file=None, label="slab"):
+    """Untimed warm-up runs and one profiled run (HIP events around every
+    launch: it names the dominant kernel class), then `steps` timed runs of
+    N histories.  In the timed region HIP events bracket only the dominant
+    class's launches, on the stream the library launches on; timed run s
+    brackets the census steps k = s mod steps, so over the timed region
+    every census step is timed once.  Returns histories/s (wall clock over
+    the timed runs), the roofline of the dominant kernel and the per-class
+    breakdown of the profiled run."""
+    import numpy as np
+    import torch
+
+    outs = ("mean", "var")
+    names = m._binding.PROF_CLASSES
+
+    def run(a, s, **kw):
+        return m.mcdc_run(p, N, seed + s, algorithm=a, outputs=outs, **kw)
+
+    for s in range(warmup):
+        run(alg, s)
+    brk = np.zeros((len(names), 4))
+    run(alg, 0, profile=brk)
+    cls = int(np.argmax(brk[:, 0]))
+    torch.cuda.synchronize()
+    prof = np.zeros((len(names), 4))
+    t0 = time.perf_counter()
+    for s in range(steps):
+        last = run(alg, s, profile=prof, profile_classes=[names[cls]], profile_every=steps, profile_phase=s)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    log(f"{label}: {steps} timed runs of {N:.0e} histories, {elapsed / steps * 1e3:.2f} ms per run")
+    ms, launches, items, nbytes = prof[cls]
+    if alg == "event":
+        achieved = nbytes / (ms * 1e-3) / 1e9
+        tr = measured_traffic(traffic_file) if (traffic_file and names[cls] == "events") else None
+        if tr and tr.get("histories") != N:
+            tr = None
+        roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": achieved / HBM_PEAK_GBS,
+                    "traffic": tr["hbm_bytes_per_launch"] if tr else None,
+                    "kernel": "k_event (one census step: every particle of the step's bank to census or death)"
+                              if names[cls] == "events" else f"k_{names[cls]}",
+                    "launches": int(launches), "avg_launch_ms": ms / launches,
+                    "algorithmic_bytes_per_launch": nbytes / launches,
+                    "particles_per_launch": items / launches,
+                    "timed_launches": f"timed run s brackets census steps k = s mod {steps} with HIP "
+                                      f"events on the library's stream (each census step once)"}
+        if tr:
+            roofline["traffic_source"] = os.path.relpath(traffic_file, ROOT)
+            roofline["traffic_over_algorithmic"] = tr["hbm_bytes_per_launch"] / (nbytes / launches)
+    else:
+        # history form: state in registers; bounded by FP64 vector ALU and
+        # divergence, reported as events per second
+        ev = float(sum(last["events"]))
+        roofline = {"bound": "alu", "achieved": ev * steps / (ms * 1e-3) / 1e9,
+                    "peak": None, "unit": "Gevents/s", "frac": None, "traffic": None,
+                    "kernel": "k_history", "launches": int(launches), "avg_launch_ms": ms / launches}
+    per_class = {names[c]: {"ms": brk[c, 0], "launches": brk[c, 1], "particles": brk[c, 2],
+                            "bytes": brk[c, 3]}
+                 for c in range(len(names)) if brk[c, 1] > 0}
+    return {"value": N * steps / elapsed, "elapsed": elapsed, "roofline": roofline, "per_class": per_class,
+            "last": last}
+
+
+def lattice_section(m, w, n, steps, warmup):
+    """The 17 x 17 lattice (2 materials, 7 groups, reflective x-y, vacuum z,
+    17 x 17 x 10 x 7 x 20 = 404 600 tally bins, pulse at t = 0) at 1e8
+    histories: the event form timed with the roofline of its census-step
+    kernel (whose per-step tally slice of 20 230 bins does not fit the LDS,
+    so it scores with HBM atomics), and the history form."""
+    import torch
+
+    prob = w.cfg3_lattice()
+    h = m.mcdc_problem_create(prob)
+    res = {"workload": "17x17 lattice of 1.26 cells x 50 high, 2 materials, 7 groups, reflective x/y, vacuum z, "
+                       f"uniform pulse at t=0; tally 17x17x10 x 7 groups x 20 time bins on [0,20]; {n:.0e} "
+                       "histories, FP64",
+           "histories": n}
+    try:
+        ev = timed_runs(m, h, n, 3, steps, warmup, "event", LATTICE_TRAFFIC_FILE, label="lattice event")
+        res["event_histories_per_s"] = ev["value"]
+        res["event_ms"] = ev["elapsed"] / steps * 1e3
+        res["events_per_history"] = [float(x) / n for x in ev["last"]["events"]]
+        res["roofline"] = ev["roofline"]
+        res["kernels_per_run"] = ev["per_class"]
+        m.mcdc_run(h, n, 3, algorithm="history", outputs=("mean", "var"))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for s in range(steps):
+            m.mcdc_run(h, n, 3 + s, algorithm="history", outputs=("mean", "var"))
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        res["history_histories_per_s"] = n / dt
+        res["history_ms"] = dt * 1e3
+        log(f"lattice history form: {dt * 1e3:.2f} ms per run")
+    finally:
+        h.close()
+    return res
 
 
 def main():
@@ -382,11 +566,15 @@ def main():
     ap.add_argument("--no-eigen", action="store_true")
     ap.add_argument("--no-pins", action="store_true")
     ap.add_argument("--no-pc", action="store_true")
+    ap.add_argument("--no-lattice", action="store_true")
+    ap.add_argument("--lattice-histories", type=float, default=1e8)
     ap.add_argument("--eigen-per-cycle", type=float, default=1e5)
     ap.add_argument("--fission-histories", type=float, default=1e6)
-    ap.add_argument("--fom-pilot", type=float, default=1e8)
-    ap.add_argument("--fom-analog", type=float, default=4e9)
-    ap.add_argument("--fom-ww", type=float, default=1e9)
+    ap.add_argument("--fom-pilots", default="1e7,1e8", help="pilot sizes of the learned windows")
+    ap.add_argument("--fom-analog", type=float, default=4e9, help="histories per analog replica")
+    ap.add_argument("--fom-analog-runs", type=int, default=10)
+    ap.add_argument("--fom-ww", type=float, default=1e9, help="histories per windowed replica")
+    ap.add_argument("--fom-ww-runs", type=int, default=4)
     ap.add_argument("--fom-steps", type=int, default=3000)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 1 GiB device-to-device copy (reference for HBM counters)")
@@ -423,59 +611,13 @@ def main():
     p = m.mcdc_problem_create(prob)
     outs = ("mean", "var")
 
-    def step(alg, s, profile=None, classes=None, every=0, phase=0):
-        return m.mcdc_run(p, N, seed + s, algorithm=alg, outputs=outs, profile=profile,
-                          profile_classes=classes, profile_every=every, profile_phase=phase)
+    def step(alg, s, **kw):
+        return m.mcdc_run(p, N, seed + s, algorithm=alg, outputs=outs, **kw)
 
     log("problem on the GPU")
-    names = m._binding.PROF_CLASSES
-    # per-class breakdown (HIP events around every launch) in an untimed
-    # step: it names the dominant kernel class
-    for s in range(args.warmup):
-        step(args.algorithm, s)
-    brk = np.zeros((len(names), 4))
-    step(args.algorithm, 0, profile=brk)
-    cls = int(np.argmax(brk[:, 0]))
-    torch.cuda.synchronize()
-    # timed steps: HIP events bracket only the dominant kernel's launches,
-    # on the stream the library launches on
-    prof = np.zeros((len(names), 4))
-    t0 = time.perf_counter()
-    for s in range(args.steps):
-        # timed step s brackets census steps k = s mod K_timed: over the timed
-        # region every census step is timed once
-        last = step(args.algorithm, s, profile=prof, classes=[names[cls]], every=args.steps, phase=s)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    value = N * args.steps / elapsed
-    log(f"{args.steps} timed steps: {elapsed / args.steps * 1e3:.2f} ms/step")
-    ms, launches, items, nbytes = prof[cls]
-    if args.algorithm == "event":
-        achieved = nbytes / (ms * 1e-3) / 1e9
-        tr = measured_traffic() if names[cls] == "events" and N == 10_000_000 else None
-        roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": achieved / HBM_PEAK_GBS,
-                    "traffic": tr["hbm_bytes_per_launch"] if tr else None,
-                    "kernel": "k_event (one census step: every particle of the step's bank to census or death)"
-                              if names[cls] == "events" else f"k_{names[cls]}",
-                    "launches": int(launches), "avg_launch_ms": ms / launches,
-                    "algorithmic_bytes_per_launch": nbytes / launches,
-                    "particles_per_launch": items / launches,
-                    "timed_launches": f"timed step s brackets census steps k = s mod {args.steps} with HIP "
-                                      f"events on the library's stream (each census step once)"}
-        if tr:
-            roofline["traffic_source"] = os.path.relpath(TRAFFIC_FILE, ROOT)
-    else:
-        # history form: state in registers; bounded by FP64 vector ALU and
-        # divergence, reported as events per second against the FP64 rate
-        ev = float(sum(last["events"]))
-        roofline = {"bound": "alu", "achieved": ev * args.steps / (ms * 1e-3) / 1e9,
-                    "peak": None, "unit": "Gevents/s", "frac": None, "traffic": None,
-                    "kernel": "k_history", "launches": int(launches), "avg_launch_ms": ms / launches}
-    per_class = {names[c]: {"ms": brk[c, 0], "launches": brk[c, 1], "particles": brk[c, 2],
-                            "bytes": brk[c, 3]}
-                 for c in range(len(names)) if brk[c, 1] > 0}
-
+    head = timed_runs(m, p, N, seed, args.steps, args.warmup, args.algorithm, TRAFFIC_FILE)
+    value, elapsed, roofline, per_class, last = (head["value"], head["elapsed"], head["roofline"],
+                                                 head["per_class"], head["last"])
     extra = {}
     if not args.no_history_form and args.algorithm == "event":
         torch.cuda.synchronize()
@@ -518,6 +660,8 @@ def main():
         extra["time_crossing_tally"] = tc
         log("time-crossing tally timed")
     p.close()
+    if not args.no_lattice:
+        extra["lattice"] = lattice_section(m, w, int(args.lattice_histories), args.steps, args.warmup)
     if not args.no_fission:
         extra["fission"] = fission_section(m, w, int(args.fission_histories), args.steps)
     if not args.no_eigen:
@@ -530,8 +674,9 @@ def main():
     if not args.no_batched:
         extra["batched"] = batched_section(m, w)
     if not args.no_fom:
-        extra["figure_of_merit"] = fom_section(w, int(args.fom_pilot), int(args.fom_analog),
-                                               int(args.fom_ww), args.fom_steps)
+        extra["figure_of_merit"] = fom_section(w, [int(float(x)) for x in args.fom_pilots.split(",")],
+                                               int(args.fom_analog), args.fom_analog_runs, int(args.fom_ww),
+                                               args.fom_ww_runs, args.fom_steps)
 
     line = {
         "metric": METRIC, "value": value, "unit": "histories/s", "n_gpus": 1,

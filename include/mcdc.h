@@ -41,7 +41,7 @@
 extern "C" {
 #endif
 
-#define MCDC_ABI_VERSION 3
+#define MCDC_ABI_VERSION 4
 
 /* return codes */
 #define MCDC_OK 0
@@ -145,6 +145,22 @@ typedef struct mcdc_problem mcdc_problem;
  * the x-y quadratic (far root from inside, near root from outside when
  * closing in), ties go census, planes, pin, collision, and a pin crossing
  * is a surface event that crosses no plane.  Both NULL: no pins.
+ *
+ * Moving plane (optional; Section 3 lists time-dependent surfaces for
+ * continuous object movement and runs control-rod transients with them):
+ * rod_z[K + 1] are the heights of one plane normal to z at the time edges
+ * T_0 .. T_K, linear in time in between (Z(t) = Z_k + v_k (t - T_k) on
+ * [T_k, T_{k+1}), v_k = (Z_{k+1} - Z_k) / (T_{k+1} - T_k), 0 for an
+ * infinite last edge; all finite), and rod_material[cz][cy][cx] over the
+ * geometry cells is the material above the plane (-1: the cell keeps its
+ * own material on both sides).  In a rod cell a particle carries an above
+ * flag, set at birth and on entering a rod cell from a cell that is not one
+ * (above iff z > Z(t), or z == Z(t) with the particle rising faster than
+ * the plane) and kept between rod cells; the distance to the plane is
+ * (Z(t) - z) / (u_z - v_k / v_g) when the two close in; ties go census,
+ * planes, moving plane, collision; a crossing is a surface event that
+ * crosses no plane and flips the flag.  Needs a finite z axis; not
+ * combined with pins; not in eigenvalue runs.  Both NULL: none.
  */
 typedef struct {
     int32_t abi_version; /* MCDC_ABI_VERSION */
@@ -186,10 +202,13 @@ typedef struct {
     double roulette_ws;
     const double *pin_radius;
     const int32_t *pin_material;
+    const double *rod_z;
+    const int32_t *rod_material;
 } mcdc_problem_desc;
 
 /*
- * Run options (all-zero = defaults).
+ * Run options (all-zero = defaults; ABI version 4 added sort_cadence and
+ * the sort profile class).
  *  algorithm      MCDC_ALG_EVENT (default), MCDC_ALG_HISTORY, or
  *                 MCDC_ALG_AUTO: mcdc_run runs both forms on its first call
  *                 for a history count (results of the history-form run)
@@ -237,6 +256,16 @@ typedef struct {
  *                 launch one kernel at a time, the others replay the
  *                 captured step graphs uninstrumented.  Runs with phases
  *                 0 .. profile_every-1 together sample every step once.
+ *  sort_cadence   event form: 0 = the default (mcdc_run: no queue sort;
+ *                 mcdc_run_batched: tuned), -1 = no queue sort.  c >= 1 (at
+ *                 most 64) runs the two-kernel step and, at the census steps
+ *                 k with k mod c == 0, sorts each segment's surface and
+ *                 collision queues by (event, material, group, cell) into a
+ *                 fourth bank before the events kernel takes them, so that
+ *                 the lanes of a wave start on like events (the per-event
+ *                 queues the paper's event-based mode processes, Section 2).
+ *                 Same per-history results; tallies differ by summation
+ *                 order only.
  *  segments       event form: bank segments, one per workgroup of every
  *                 event kernel (0 = auto: 2 per compute unit, or fewer if
  *                 the advance kernel cannot hold that many resident).
@@ -264,13 +293,14 @@ typedef struct {
  */
 #define MCDC_FLAG_EAGER 1
 #define MCDC_FLAG_TWO_KERNEL_STEP 2
-#define MCDC_PROF_CLASSES 6
+#define MCDC_PROF_CLASSES 7
 #define MCDC_PROF_SOURCE 0     /* event form: source sampling */
 #define MCDC_PROF_ADVANCE 1    /* event form: one flight over the census bank */
 #define MCDC_PROF_EVENTS 2     /* event form: surface and collision queues, on to census */
 #define MCDC_PROF_HISTORY 3    /* history form (and weight-window progeny) */
 #define MCDC_PROF_OTHER 4      /* fills, step counters, batch statistics */
 #define MCDC_PROF_CONTROL 5    /* event form: population control at census */
+#define MCDC_PROF_SORT 6       /* event form: queue sort of the two-kernel step */
 typedef struct {
     int32_t algorithm;
     int32_t block_size;
@@ -284,7 +314,7 @@ typedef struct {
     int32_t profile_every;
     int32_t profile_phase;
     int32_t segments;
-    int32_t reserved;
+    int32_t sort_cadence;
     uint64_t pc_target;
 } mcdc_run_options;
 
@@ -380,12 +410,19 @@ int mcdc_run(mcdc_problem *p, uint64_t n_histories, uint64_t seed,
  * mcdc_run calls (tallies differ only in summation order).
  *  MCDC_ALG_EVENT (default): every problem's histories are cut into bank
  *    segments of one length; all segments of all problems share one set of
- *    banks, and each census step is one captured graph (advance, events)
- *    over all of them, replayed up to the largest K.  The segment length
- *    (queue capacity per workgroup) is opt->bank_capacity if nonzero
- *    (256..2^24), else autotuned over {2048, 8192, 32768} on the first call
- *    for a batch signature (problem shapes and history counts) and reused.
- *    At most 2^28 histories per problem.
+ *    banks, and each census step is one captured graph over all of them,
+ *    replayed up to the largest K.  Problems of at most a tail threshold of
+ *    histories run instead in one history-form launch after it (the tail
+ *    switch).  Launch parameters are forced by the options or tuned on the
+ *    first call for a batch signature (problem shapes, history counts and
+ *    the forcing options) and reused: the segment length (queue capacity
+ *    per workgroup; opt->bank_capacity, 256..2^24, else tuned over {2048,
+ *    8192, 32768, 65536}), then the census step's form (one kernel; two
+ *    kernels; two kernels with the queue sort every 1, 2, 4 or 8 steps;
+ *    forced by opt->sort_cadence or MCDC_FLAG_TWO_KERNEL_STEP), then the
+ *    tail threshold {0, 2e4, 1e5}, each at the best of the ones before,
+ *    timing whole runs of the batch.  At most 2^28 histories and 65535
+ *    time bins per problem.
  *  MCDC_ALG_HISTORY: one persistent launch; a fixed grid of workgroups
  *    pulls chunks of histories from one device-wide counter over the
  *    concatenated history ranges; workgroup size and histories per pull are
@@ -393,8 +430,11 @@ int mcdc_run(mcdc_problem *p, uint64_t n_histories, uint64_t seed,
  *  MCDC_ALG_AUTO: the first call for a batch signature runs both forms
  *    (each tuned as above) and caches the one with the shorter run; later
  *    calls run that form only.  outs hold the results of the last run.
- * Debug arrays, profiles and weight windows are not supported here
- * (MCDC_E_UNSUPPORTED).  All problems must live on the same device.
+ * opt->debug_counts and opt->debug_scores, if given, hold every problem's
+ * per-history records in problem order: problem j's history i is row
+ * n_hist[0] + ... + n_hist[j-1] + i of [sum n_hist][5] and [sum n_hist][2].
+ * Profiles, weight windows, fission and implicit capture are not supported
+ * here (MCDC_E_UNSUPPORTED).  All problems must live on the same device.
  */
 int mcdc_run_batched(mcdc_problem *const *ps, int32_t n, const uint64_t *n_hist, const uint64_t *seeds,
                      const mcdc_run_options *opt, mcdc_result *outs);

@@ -63,6 +63,7 @@ class _Problem(C.Structure):
         ("sigma_f", _DP), ("nu", _DP), ("chi", _DP),
         ("implicit_capture", C.c_int32), ("roulette_w", C.c_double), ("roulette_ws", C.c_double),
         ("pin_radius", _DP), ("pin_material", _IP),
+        ("rod_z", _DP), ("rod_material", _IP),
     ]
 
 
@@ -185,6 +186,10 @@ class OracleProblem:
         if pins is not None:
             s.pin_radius = _dp(arr(pins["radius"]))
             s.pin_material = arr(pins["material"], np.int32).ctypes.data_as(_IP)
+        rod = prob.get("rod")
+        if rod is not None:
+            s.rod_z = _dp(arr(rod["z"]))
+            s.rod_material = arr(rod["material"], np.int32).ctypes.data_as(_IP)
         self.time_crossing = bool(s.time_crossing)
         self.struct = s
         self._keep = keep

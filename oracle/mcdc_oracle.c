@@ -113,6 +113,24 @@
  *       j >= 1 takes child_stream of that state and j (as R10's splits) and
  *       counts as a split.  W = 0: nothing happens.  Analog tracking with
  *       optional implicit capture only (no windows, fission or detector).
+ *   R27 Moving plane (optional; Section 3 lists time-dependent surfaces
+ *       for continuous object movement, and runs control-rod transients
+ *       with them): one plane normal to z whose height is linear in time
+ *       within each census step, Z(t) = Z_k + v_k (t - T_k) on
+ *       [T_k, T_{k+1}), from the heights Z_k given at the time edges,
+ *       v_k = (Z_{k+1} - Z_k) / (T_{k+1} - T_k) (0 for an infinite last
+ *       edge).  A geometry cell may be a rod cell with a rod material:
+ *       above the plane its material is the rod's, below its own.  In rod
+ *       cells a particle carries an above flag; per unit track length its
+ *       height gains u_z and the plane's v_k / v_g, so with q = u_z -
+ *       v_k (1 / v_g) the distance to the plane is (Z(t) - z) / q when
+ *       the two close in (above and q < 0, or below and q > 0), clipped at
+ *       0.  Crossing it is a surface event that crosses no union plane and
+ *       flips the flag.  The flag is set at birth in a rod cell and when a
+ *       plane crossing enters a rod cell from a cell that is not one:
+ *       above iff z > Z(t), or z == Z(t) and q > 0; it is kept between rod
+ *       cells.  Tie order: census, planes, moving plane, collision.  Not
+ *       combined with pins nor in eigenvalue cycles; needs a finite z axis.
  *
  * Build: gcc -O2 -ffp-contract=off -fPIC -shared -o liboracle.so mcdc_oracle.c -lm
  */
@@ -168,6 +186,9 @@ typedef struct {
     /* cylindrical pins (R15): per geometry cell, or NULL */
     const double *pin_radius;     /* [cz][cy][cx], 0 = no pin */
     const int32_t *pin_material;  /* [cz][cy][cx] */
+    /* moving plane (R27): heights at the time edges and rod cells, or NULL */
+    const double *rod_z;          /* [K + 1] */
+    const int32_t *rod_material;  /* [cz][cy][cx], -1 = not a rod cell */
 } oracle_problem;
 
 enum { EV_CENSUS = 0, EV_SURFACE = 1, EV_COLLISION = 2 };
@@ -345,6 +366,7 @@ typedef struct {
     int ix[3];
     int g, k;
     int inpin;      /* R15: inside the cell's pin */
+    int above;      /* R27: above the moving plane (meaningful in rod cells) */
     int since;      /* events since birth or the last census */
     uint64_t s;
 } particle;
@@ -412,12 +434,44 @@ static int64_t geo_cell(const ctx *C, const particle *pt, int c[3])
     return ((int64_t)c[2] * C->nc[1] + c[1]) * C->nc[0] + c[0];
 }
 
+/* R27: rod material of the particle's geometry cell, -1 if not a rod cell */
+static int rod_cell(const ctx *C, const particle *pt)
+{
+    if (!C->p->rod_material) return -1;
+    int c[3];
+    return C->p->rod_material[geo_cell(C, pt, c)];
+}
+
 static int material_of(const ctx *C, const particle *pt)
 {
     int c[3];
     int64_t g = geo_cell(C, pt, c);
     if (pt->inpin) return C->p->pin_material[g];
+    if (C->p->rod_material && C->p->rod_material[g] >= 0 && pt->above) return C->p->rod_material[g];
     return C->p->material[g];
+}
+
+/* R27: height of the moving plane at time t in census step k, and its
+ * speed there */
+static double rod_height(const ctx *C, int k, double t, double *vz)
+{
+    const double *T = C->p->time_edges;
+    const double *Z = C->p->rod_z;
+    double v = 0.0;
+    if (T[k + 1] != INFINITY) v = (Z[k + 1] - Z[k]) / (T[k + 1] - T[k]);
+    *vz = v;
+    return Z[k] + v * (t - T[k]);
+}
+
+/* R27: the side of the moving plane a particle at its place and time is on */
+static int rod_side(const ctx *C, const particle *pt)
+{
+    double vz;
+    double Z = rod_height(C, pt->k, pt->t, &vz);
+    if (pt->x[2] > Z) return 1;
+    if (pt->x[2] < Z) return 0;
+    double q = pt->u[2] - vz * (1.0 / C->p->speed[pt->g]);
+    return q > 0.0;
 }
 
 /* R15: the pin of the particle's geometry cell (centre, r^2); 0 if none */
@@ -614,6 +668,17 @@ static int step(ctx *C, particle *pt, int b, particle *stack, int *sp, hist_rec 
             }
         }
     }
+    /* R27: distance to the moving plane in a rod cell */
+    double dmov = INFINITY;
+    if (rod_cell(C, pt) >= 0) {
+        double vz;
+        double Z = rod_height(C, pt->k, pt->t, &vz);
+        double q = pt->u[2] - vz * (1.0 / p->speed[pt->g]);
+        if ((pt->above && q < 0.0) || (!pt->above && q > 0.0)) {
+            dmov = (Z - pt->x[2]) / q;
+            if (dmov < 0.0) dmov = 0.0;
+        }
+    }
     /* distance to the next time-census edge */
     double Tn = p->time_edges[pt->k + 1];
     double dt = INFINITY;
@@ -621,19 +686,23 @@ static int step(ctx *C, particle *pt, int b, particle *stack, int *sp, hist_rec 
         dt = (Tn - pt->t) * p->speed[pt->g];
         if (dt < 0.0) dt = 0.0;
     }
-    /* R3, R15 */
-    int ev, cyl = 0;
+    /* R3, R15, R27 (a problem has pins or a moving plane, not both) */
+    int ev, cyl = 0, mov = 0;
     double d;
-    if (dt <= ds && dt <= dcyl && dt <= dc) {
+    if (dt <= ds && dt <= dcyl && dt <= dmov && dt <= dc) {
         ev = EV_CENSUS;
         d = dt;
-    } else if (ds <= dcyl && ds <= dc) {
+    } else if (ds <= dcyl && ds <= dmov && ds <= dc) {
         ev = EV_SURFACE;
         d = ds;
-    } else if (dcyl <= dc) {
+    } else if (dcyl <= dmov && dcyl <= dc) {
         ev = EV_SURFACE;
         d = dcyl;
         cyl = 1;
+    } else if (dmov <= dc) {
+        ev = EV_SURFACE;
+        d = dmov;
+        mov = 1;
     } else {
         ev = EV_COLLISION;
         d = dc;
@@ -690,8 +759,9 @@ static int step(ctx *C, particle *pt, int b, particle *stack, int *sp, hist_rec 
         h->n_surf++;
         C->tot[1]++;
         int wcell_changed = 0;
+        const int rod_before = rod_cell(C, pt);
         for (int a = 0; a < 3 && alive; a++) {
-            if (C->ax[a].n == 0 || da[a] != d) continue;
+            if (mov || C->ax[a].n == 0 || da[a] != d) continue;
             int last = C->ax[a].n - 2;
             int old = pt->ix[a];
             int face = -1;
@@ -718,6 +788,15 @@ static int step(ctx *C, particle *pt, int b, particle *stack, int *sp, hist_rec 
             if (pt->ix[a] != old && C->ax[a].wwc[pt->ix[a]] != C->ax[a].wwc[old]) wcell_changed = 1;
         }
         if (cyl) pt->inpin ^= 1;
+        if (mov) {
+            pt->above ^= 1;
+        } else if (alive && p->rod_material) {
+            /* R27: entering a rod cell from one that is not sets the flag */
+            if (rod_cell(C, pt) < 0)
+                pt->above = 0;
+            else if (rod_before < 0)
+                pt->above = rod_side(C, pt);
+        }
         if (alive && wcell_changed) alive = ww_game(C, pt, stack, sp, h);
     } else {
         h->n_coll++;
@@ -847,6 +926,8 @@ static int birth(ctx *C, uint64_t s0, particle *pt, hist_rec *h)
     int k = 0;
     while (!(pt->t < p->time_edges[k + 1])) k++;
     pt->k = k;
+    /* R27: the side of the moving plane in a rod cell */
+    if (rod_cell(C, pt) >= 0) pt->above = rod_side(C, pt);
     return 1;
 }
 
@@ -871,6 +952,14 @@ static int ctx_init(ctx *C, const oracle_problem *p)
         C->nw[a] = (p->n_ww[a] == 0) ? 1 : p->n_ww[a] - 1;
     }
     C->ntally = (int64_t)C->K * G * C->nt[0] * C->nt[1] * C->nt[2];
+    if (p->rod_material) {
+        /* R27: a finite z axis, heights at every time edge, no pins */
+        if (p->n_planes[2] == 0 || !p->rod_z || p->pin_radius) return -1;
+        for (int k = 0; k <= C->K; k++)
+            if (!isfinite(p->rod_z[k])) return -1;
+        for (int64_t g = 0; g < (int64_t)C->nc[0] * C->nc[1] * C->nc[2]; g++)
+            if (p->rod_material[g] < -1 || p->rod_material[g] >= M) return -1;
+    }
     if (p->pin_radius) {
         /* R15: pins need finite x and y axes and must fit their cells */
         if (p->n_planes[0] == 0 || p->n_planes[1] == 0 || !p->pin_material) return -1;
@@ -1323,6 +1412,7 @@ int oracle_eigen(const oracle_problem *p, uint64_t N, int n_inactive, int n_acti
     ctx C;
     memset(&C, 0, sizeof(C));
     if (N == 0 || n_inactive < 0 || n_active < 1 || !p->sigma_f || p->ww_center || p->implicit_capture ||
+        p->rod_material ||
         ctx_init(&C, p) != 0 || C.K != 1 || p->time_edges[1] != INFINITY) {
         ctx_free(&C);
         return -1;

@@ -16,14 +16,15 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libmcdc_hip.so")
 
-MCDC_ABI_VERSION = 3
+MCDC_ABI_VERSION = 4
 MCDC_OK, MCDC_E_INVALID, MCDC_E_HIP, MCDC_E_NOMEM, MCDC_E_OVERFLOW, MCDC_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5
 MCDC_ALG_EVENT, MCDC_ALG_HISTORY, MCDC_ALG_AUTO = 0, 1, 2
 MCDC_SRC_ISOTROPIC, MCDC_SRC_SURFACE = 0, 1
 MU_LAWS = {"beam": 0, "uniform": 1, "cosine": 2}
 
 EXPORTS = ["mcdc_problem_create", "mcdc_problem_destroy", "mcdc_problem_tally_shape",
-           "mcdc_run", "mcdc_run_batched", "mcdc_run_eigenvalue", "mcdc_set_weight_windows", "mcdc_last_error", "mcdc_mlp_create",
+           "mcdc_run", "mcdc_run_batched", "mcdc_run_eigenvalue", "mcdc_set_weight_windows",
+           "mcdc_last_error", "mcdc_mlp_create",
            "mcdc_mlp_destroy", "mcdc_mlp_get_params", "mcdc_mlp_set_params", "mcdc_mlp_grad",
            "mcdc_mlp_train", "mcdc_mlp_infer"]
 
@@ -52,6 +53,7 @@ class mcdc_problem_desc(C.Structure):
         ("sigma_f", _DP), ("nu", _DP), ("chi", _DP),
         ("implicit_capture", C.c_int32), ("roulette_w", C.c_double), ("roulette_ws", C.c_double),
         ("pin_radius", _DP), ("pin_material", _IP),
+        ("rod_z", _DP), ("rod_material", _IP),
     ]
 
 
@@ -61,11 +63,11 @@ class mcdc_run_options(C.Structure):
         ("flags", C.c_int32), ("stream", C.c_void_p),
         ("debug_counts", C.c_void_p), ("debug_scores", C.c_void_p),
         ("profile", C.c_void_p), ("profile_mask", C.c_uint32), ("profile_every", C.c_int32), ("profile_phase", C.c_int32),
-        ("segments", C.c_int32), ("reserved", C.c_int32), ("pc_target", C.c_uint64),
+        ("segments", C.c_int32), ("sort_cadence", C.c_int32), ("pc_target", C.c_uint64),
     ]
 
 
-PROF_CLASSES = ["source", "advance", "events", "history", "other", "control"]
+PROF_CLASSES = ["source", "advance", "events", "history", "other", "control", "sort"]
 
 
 class mcdc_result(C.Structure):
@@ -199,6 +201,10 @@ def make_desc(prob: dict):
     if pins is not None:
         d.pin_radius = _dp(arr(pins["radius"]))
         d.pin_material = arr(pins["material"], np.int32).ctypes.data_as(_IP)
+    rod = prob.get("rod")
+    if rod is not None:
+        d.rod_z = _dp(arr(rod["z"]))
+        d.rod_material = arr(rod["material"], np.int32).ctypes.data_as(_IP)
     return d, keep
 
 
@@ -256,7 +262,8 @@ def mcdc_run(p: Problem, n_histories: int, seed: int, algorithm: str = "event",
              block_size: int = 0, bank_capacity: int = 0, segments: int = 0,
              debug: bool = False, outputs=("mean", "var", "raw", "leak_mean", "leak_var"),
              profile=None, eager: bool = False, profile_classes=None, profile_every: int = 0,
-             profile_phase: int = 0, two_kernel_step: bool = False, pc_target: int = 0):
+             profile_phase: int = 0, two_kernel_step: bool = False, pc_target: int = 0,
+             sort_cadence: int = 0):
     """Run n_histories through the GPU tracker.  Returns a dict of torch
     CUDA tensors (mean, var, raw [K, G, nz, ny, nx]; leak_mean, leak_var
     [K, G, 6]; tc_mean, tc_var [K, G, nz, ny, nx] for a problem with the
@@ -288,6 +295,7 @@ def mcdc_run(p: Problem, n_histories: int, seed: int, algorithm: str = "event",
     opt.bank_capacity = bank_capacity
     opt.segments = segments
     opt.pc_target = pc_target
+    opt.sort_cadence = sort_cadence
     opt.flags = (1 if eager else 0) | (2 if two_kernel_step else 0)
     opt.stream = torch.cuda.current_stream(dev).cuda_stream
     if debug:
@@ -419,11 +427,14 @@ def mcdc_mlp_create(seed: int = 1) -> MLP:
 
 
 def mcdc_run_batched(problems, n_hist, seeds, block_size: int = 0, outputs=("mean", "var"),
-                     algorithm: str = "event", seg_len: int = 0):
+                     algorithm: str = "event", seg_len: int = 0, debug: bool = False, sort_cadence: int = 0,
+                     two_kernel_step: bool = False):
     """Run many problems together: event form (shared banks, one graph per
     census step for all problems), history form (one persistent launch) or
     "auto" (both timed on the first call for a batch signature, the faster
-    one cached).  Returns one result dict per problem, like mcdc_run."""
+    one cached).  Returns one result dict per problem, like mcdc_run (with
+    debug: each dict's debug_counts [n, 5] and debug_scores [n, 2] are views
+    of one array over all problems' histories in problem order)."""
     import torch
 
     L = lib()
@@ -457,7 +468,21 @@ def mcdc_run_batched(problems, n_hist, seeds, block_size: int = 0, outputs=("mea
     opt.algorithm = {"history": MCDC_ALG_HISTORY, "auto": MCDC_ALG_AUTO}.get(algorithm, MCDC_ALG_EVENT)
     opt.block_size = block_size
     opt.bank_capacity = seg_len
+    opt.sort_cadence = sort_cadence
+    opt.flags = 2 if two_kernel_step else 0
     opt.stream = torch.cuda.current_stream(dev).cuda_stream
+    if debug:
+        tot = int(sum(int(x) for x in n_hist))
+        dc = torch.empty((tot, 5), dtype=torch.int32, device=dev)
+        ds = torch.empty((tot, 2), dtype=torch.float64, device=dev)
+        opt.debug_counts = dc.data_ptr()
+        opt.debug_scores = ds.data_ptr()
+        off = 0
+        for j, o in enumerate(outs):
+            k = int(n_hist[j])
+            o["debug_counts"] = dc[off:off + k]
+            o["debug_scores"] = ds[off:off + k]
+            off += k
     _check(L.mcdc_run_batched(hs, n, nh, sd, C.byref(opt), res))
     for j, o in enumerate(outs):
         r = res[j]

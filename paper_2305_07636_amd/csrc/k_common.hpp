@@ -75,13 +75,40 @@ struct Particle {
     double t, tau, w;
     int ix[3];
     int g, k;
-    int inpin;                  // inside the cell's cylindrical pin
+    int inpin;                  // inside the cell's cylindrical pin, or (problems with a
+                                // moving plane) above the plane in a rod cell
     uint64_t s;
 };
 
-// Material at the particle's place: the cell's, or its pin's inside it.
+// Material of union cell `cell` for a particle with the given flag: the
+// cell's, its pin's inside the pin, its rod's above the moving plane.
+__device__ __forceinline__ int material_at(const DevProblem &P, int cell, int flag) {
+    if (flag) {
+        if (P.pins_on) return P.pin_mat[cell];
+        if (P.rod_on && P.rod_mat[cell] >= 0) return P.rod_mat[cell];
+    }
+    return P.cell_mat[cell];
+}
 __device__ __forceinline__ int material_of(const DevProblem &P, const Particle &p, int cell) {
-    return (P.pins_on && p.inpin) ? P.pin_mat[cell] : P.cell_mat[cell];
+    return material_at(P, cell, p.inpin);
+}
+
+// Moving plane: height at the particle's time in its census step, and the
+// rate at which the particle closes on it per unit track length when it
+// rises by u_z and the plane by v_k / v_g.
+__device__ __forceinline__ double rod_height(const DevProblem &P, const Particle &p) {
+    return P.rod_z[p.k] + P.rod_v[p.k] * (p.t - P.T[p.k]);
+}
+__device__ __forceinline__ double rod_rate(const DevProblem &P, const Particle &p) {
+    return p.u[2] - P.rod_v[p.k] * P.inv_v[p.g];
+}
+// The side of the plane the particle is on (1 above): on the plane, the
+// side it moves to.
+__device__ __forceinline__ int rod_side(const DevProblem &P, const Particle &p) {
+    const double Z = rod_height(P, p);
+    if (p.x[2] > Z) return 1;
+    if (p.x[2] < Z) return 0;
+    return rod_rate(P, p) > 0.0 ? 1 : 0;
 }
 
 template <int FM>
@@ -180,6 +207,7 @@ __device__ __forceinline__ bool birth(const DevProblem &P, uint64_t s0, Particle
     int k = 0;
     while (!(p.t < P.T[k + 1])) ++k;
     p.k = k;
+    if (FM != 1 && P.rod_on && P.rod_mat[cell_index(P, p.ix)] >= 0) p.inpin = rod_side(P, p);
     return true;
 }
 
@@ -212,8 +240,16 @@ __device__ __forceinline__ Flight next_event(const DevProblem &P, const Particle
         if (d < ds) ds = d;
     }
     // the cell's pin (x-y quadratic; a slab has none): from inside, the far
-    // root; from outside, the near root if the flight closes in on the axis
+    // root; from outside, the near root if the flight closes in on the axis;
+    // or, in a rod cell, the moving plane when the particle closes in on it
     double dcyl = kInf;
+    if (FM != 1 && P.rod_on && P.rod_mat[cell] >= 0) {
+        const double q = rod_rate(P, p);
+        if ((p.inpin && q < 0.0) || (!p.inpin && q > 0.0)) {
+            dcyl = (rod_height(P, p) - p.x[2]) / q;
+            if (dcyl < 0.0) dcyl = 0.0;
+        }
+    }
     if (FM != 1 && P.pins_on) {
         const double r2 = P.pin_r2[cell];
         if (r2 > 0.0) {
@@ -240,8 +276,8 @@ __device__ __forceinline__ Flight next_event(const DevProblem &P, const Particle
         dt = (Tn - p.t) * P.speed[p.g];
         if (dt < 0.0) dt = 0.0;
     }
-    // tie order: census, planes, pin, collision (a pin crossing is a
-    // surface event that crosses no plane)
+    // tie order: census, planes, pin or moving plane, collision (a pin or
+    // moving-plane crossing is a surface event that crosses no plane)
     if (dt <= ds && dt <= dcyl && dt <= dc) {
         f.ev = kCensus;
         f.d = dt;
@@ -288,12 +324,16 @@ __device__ __forceinline__ int crossing_mask(const DevProblem &P, const Flight &
 // Surface crossing of the axes in mask, in axis order: snap onto the plane,
 // step the cell index, reflect at a reflective face.  Returns the vacuum
 // face crossed (the particle leaks; later axes are not processed), or -1.
+// With a moving plane, a crossing that enters a rod cell from a cell that
+// is not one sets the above flag from the particle's side of the plane;
+// between rod cells the flag is kept.
 template <int FM>
 __device__ __forceinline__ int cross(const DevProblem &P, Particle &p, int mask) {
-    if (FM != 1 && mask == 0) {   // the cell's pin surface (a slab has none)
+    if (FM != 1 && mask == 0) {   // the cell's pin surface or the moving plane (a slab has neither)
         p.inpin ^= 1;
         return -1;
     }
+    const bool rod_before = (FM != 1 && P.rod_on) ? P.rod_mat[cell_index(P, p.ix)] >= 0 : false;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         if (!finite_axis<FM>(P, a) || !((mask >> a) & 1)) continue;
@@ -323,6 +363,12 @@ __device__ __forceinline__ int cross(const DevProblem &P, Particle &p, int mask)
             p.u[a] = -p.u[a];
             p.iu[a] = -p.iu[a];
         }
+    }
+    if (FM != 1 && P.rod_on) {
+        if (P.rod_mat[cell_index(P, p.ix)] < 0)
+            p.inpin = 0;
+        else if (!rod_before)
+            p.inpin = rod_side(P, p);
     }
     return -1;
 }

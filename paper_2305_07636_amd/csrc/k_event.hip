@@ -256,6 +256,25 @@ __device__ __forceinline__ void unpack(const DevProblem &P, const RawState &r, P
 }
 
 template <int FM, bool WW>
+__device__ __forceinline__ void store_raw(const DevProblem &P, const Bank &B, uint32_t slot, const RawState &r) {
+    const uint64_t o8 = tile_off8(B, slot), o4 = tile_off4(B, slot);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (finite_axis<FM>(P, a)) {
+            fld<double>(B, B.ox[a], o8) = r.x[a];
+            fld<double>(B, B.ou[a], o8) = r.u[a];
+        }
+    }
+    fld<double>(B, B.ot, o8) = r.t;
+    fld<double>(B, B.otau, o8) = r.tau;
+    if (WW) fld<double>(B, B.ow, o8) = r.w;
+    fld<uint64_t>(B, B.os, o8) = r.s;
+    fld<uint32_t>(B, B.oc, o4) = r.c;
+    fld<uint32_t>(B, B.ogk, o4) = r.gk;
+    fld<uint32_t>(B, B.ohid, o4) = r.hidw;
+}
+
+template <int FM, bool WW>
 __device__ __forceinline__ void store_state(const DevProblem &P, const Bank &B, uint32_t slot,
                                             const Particle &p, uint32_t gk, uint32_t hidw) {
     const uint64_t o8 = tile_off8(B, slot), o4 = tile_off4(B, slot);
@@ -551,11 +570,13 @@ __global__ void __launch_bounds__(kBlock) k_advance(DevProblem P0, RunArgs R0, B
 // (STEP: the whole census step in this one kernel: the work list is the
 // step's bank itself, every item starting with a flight, and particles
 // born in a later time bin pass straight on to the next bank.)
+// (Two-kernel step with a queue sort at this step: both queues are read
+// from the front of the sorted event bank srt, surface entries first.)
 template <int FM, bool WW, bool LT, bool BAT, int CLS = MCDC_PROF_EVENTS, bool STEP = false>
 __global__ void __launch_bounds__(kBlock) k_event(DevProblem P0, RunArgs R0, Bank ev, Bank next, Ctl C, int par,
                                                   int gn0, SplitBank SB, LdsTables tabs0,
                                                   const BatchItem *__restrict__ items,
-                                                  const SegInfo *__restrict__ segs) {
+                                                  const SegInfo *__restrict__ segs, Bank srt, int cadence) {
     const int prob = BAT ? segs[blockIdx.x].prob : 0;
     const RunArgs &R = BAT ? items[prob].R : R0;
     const int gn = BAT ? items[prob].gn : gn0;
@@ -570,6 +591,8 @@ __global__ void __launch_bounds__(kBlock) k_event(DevProblem P0, RunArgs R0, Ban
     const unsigned int n = STEP ? C.n_bank[par * C.G + seg] : n_s + C.n_c[seg];
     const int step = *C.step;
     const uint64_t first = *C.first;
+    const bool sorted = !STEP && cadence > 0 && step % cadence == 0;
+    const Bank &src = sorted ? srt : ev;
     cnt.init(red);
     if (threadIdx.x == 0) {
         cN = STEP ? 0u : C.n_bank[(par ^ 1) * C.G + seg];   // after the advance kernel's census crossers
@@ -594,7 +617,8 @@ __global__ void __launch_bounds__(kBlock) k_event(DevProblem P0, RunArgs R0, Ban
             const uint32_t w = block_append(need, &cW);
             if (need && w < n) {
                 uint32_t hidw;
-                load_state<FM, WW>(P, ev, (STEP || w < n_s) ? seg0 + w : seg_end - (w - n_s), p, gk, hidw);
+                load_state<FM, WW>(P, src, (STEP || sorted || w < n_s) ? seg0 + w : seg_end - (w - n_s), p, gk,
+                                   hidw);
                 hid = hidw & kHidMask;
                 mask = STEP ? 0 : (int)(hidw >> 29);
                 queued = STEP ? kCensus : ((w < n_s) ? kSurface : kCollision);
@@ -706,6 +730,94 @@ __global__ void __launch_bounds__(kBlock) k_event(DevProblem P0, RunArgs R0, Ban
     }
     flush_slice(P, R, sc, step);
     if (threadIdx.x == 0) C.n_bank[(par ^ 1) * C.G + seg] = cN;
+    cnt.flush(R, CLS, red);
+}
+
+// ---------------------------------------------------------------------------
+// queue sort (two-kernel step): each segment's surface and collision queues
+// reordered by (event, material, group, cell) into the sorted event bank
+// before the events kernel, at the census steps k with k mod cadence == 0
+// ---------------------------------------------------------------------------
+// Bucket of an entry: queue * 256 + sub (queue 0 surface, 1 collision);
+// sub = (m G + g) * CB + cell * CB / ncells with CB = 256 / (M G) cell
+// sub-buckets per material and group (the material and group alone when
+// M G >= 256).  Per segment: a histogram of the buckets in LDS, an
+// exclusive prefix over the 512 buckets, then every entry copied whole to
+// the next slot of its bucket.  Entries of one bucket land in the order
+// of the LDS atomics; per-history results do not depend on it (each
+// particle draws from its own stream), tallies only by summation order.
+constexpr int kSortBuckets = 512;
+static_assert(kSortBuckets == kBlock, "the bucket prefix takes one bucket per thread");
+
+template <int FM>
+__device__ __forceinline__ int sort_bucket(const DevProblem &P, uint32_t c, uint32_t gk, int queue) {
+    const int ix[3] = {(int)(c & 2047u), (int)((c >> 11) & 2047u), (int)(c >> 22)};
+    const int cell = cell_index(P, ix);
+    const int g = (int)(gk & 31u);
+    const int m = material_at(P, cell, (FM == 1) ? 0 : (int)(gk >> 31));
+    const int mg = m * P.G + g;
+    const int nmg = P.M * P.G;
+    int sub;
+    if (nmg >= 256) {
+        sub = mg & 255;
+    } else {
+        const int cb = 256 / nmg;
+        sub = mg * cb + (int)(((int64_t)cell * cb) / P.ncells);
+    }
+    return queue * 256 + sub;
+}
+
+template <int FM, bool WW, bool BAT, int CLS = MCDC_PROF_SORT>
+__global__ void __launch_bounds__(kBlock) k_sort_events(DevProblem P0, RunArgs R0, Bank ev, Bank srt, Ctl C,
+                                                        int cadence, const BatchItem *__restrict__ items,
+                                                        const SegInfo *__restrict__ segs) {
+    const int step = *C.step;
+    if (cadence <= 0 || step % cadence != 0) return;
+    const int prob = BAT ? segs[blockIdx.x].prob : 0;
+    const DevProblem &P = BAT ? items[prob].P : P0;
+    const RunArgs &R = BAT ? items[prob].R : R0;
+    __shared__ unsigned long long red[kCounters + 2];
+    __shared__ unsigned int off[kSortBuckets];
+    __shared__ unsigned int wsum[kBlock / 64];
+    Counters cnt;
+    cnt.init(red);
+    const unsigned int seg = blockIdx.x;
+    const uint32_t seg0 = seg * C.L;
+    const uint32_t seg_end = seg0 + C.L - 1;
+    const unsigned int n_s = C.n_s[seg];
+    const unsigned int n = n_s + C.n_c[seg];
+    off[threadIdx.x] = 0u;
+    __syncthreads();
+    for (unsigned int w = threadIdx.x; w < n; w += kBlock) {
+        const uint32_t slot = (w < n_s) ? seg0 + w : seg_end - (w - n_s);
+        const uint64_t o4 = tile_off4(ev, slot);
+        atomicAdd(&off[sort_bucket<FM>(P, fld<uint32_t>(ev, ev.oc, o4), fld<uint32_t>(ev, ev.ogk, o4),
+                                       w < n_s ? 0 : 1)],
+                  1u);
+    }
+    __syncthreads();
+    // exclusive prefix over the buckets: within each wave by shuffles,
+    // then the totals of the waves before
+    const unsigned int v = off[threadIdx.x];
+    unsigned int inc = v;
+    for (int o = 1; o < 64; o <<= 1) {
+        const unsigned int t = __shfl_up(inc, o);
+        if ((int)__lane_id() >= o) inc += t;
+    }
+    if (__lane_id() == 63) wsum[threadIdx.x >> 6] = inc;
+    __syncthreads();
+    unsigned int base = 0u;
+    for (unsigned int k = 0; k < (threadIdx.x >> 6); ++k) base += wsum[k];
+    off[threadIdx.x] = base + inc - v;
+    __syncthreads();
+    for (unsigned int w = threadIdx.x; w < n; w += kBlock) {
+        const uint32_t slot = (w < n_s) ? seg0 + w : seg_end - (w - n_s);
+        RawState r;
+        load_raw<FM, WW>(P, ev, slot, r);
+        const unsigned int pos = atomicAdd(&off[sort_bucket<FM>(P, r.c, r.gk, w < n_s ? 0 : 1)], 1u);
+        store_raw<FM, WW>(P, srt, seg0 + pos, r);
+        if (R.prof) cnt.prof(1u, 8u + 2u * state_bytes<FM, WW>(P));
+    }
     cnt.flush(R, CLS, red);
 }
 
@@ -1004,6 +1116,7 @@ __global__ void k_step_end(Ctl C) { *C.step += 1; }
 struct Layout {
     Bank bank[2];
     Bank ev;
+    Bank srt;   // sorted event bank (queue sort on), else base == nullptr
     Ctl ctl;
 };
 
@@ -1052,8 +1165,9 @@ size_t ctl_bytes(unsigned int G) {
     return pad256(2 * G * 4) + 3 * pad256(G * 4) + 2 * 256 + pad256(G * 16) + pad256(G * 8);
 }
 
+// (banks: 3, or 4 with the sorted event bank of the queue sort)
 Layout carve(void *bank_mem, void *ctl_mem, uint64_t slots, unsigned int G, unsigned int Lseg, int fmask,
-             bool ww) {
+             bool ww, int banks = 3) {
     Layout Lo{};
     char *p = (char *)bank_mem;
     auto take = [&](size_t bytes) {
@@ -1061,8 +1175,8 @@ Layout carve(void *bank_mem, void *ctl_mem, uint64_t slots, unsigned int G, unsi
         p += pad256(bytes);
         return r;
     };
-    for (int k = 0; k < 3; ++k) {
-        Bank &B = (k < 2) ? Lo.bank[k] : Lo.ev;
+    for (int k = 0; k < banks; ++k) {
+        Bank &B = (k < 2) ? Lo.bank[k] : (k == 2 ? Lo.ev : Lo.srt);
         B = bank_layout(fmask, ww);
         B.base = take(bank_bytes(slots, fmask, ww));
     }
@@ -1170,11 +1284,14 @@ int run_event(mcdc_problem *pb, const RunArgs &R0, uint64_t first, uint64_t coun
     const unsigned int Lh = (unsigned int)(((C + G - 1) / G + 63) & ~(uint64_t)63);
     const unsigned int Lseg = pc ? Lh + (unsigned int)(((pc + G - 1) / G + 63) & ~(uint64_t)63) + 64u : Lh;
     const uint64_t slots = (uint64_t)G * Lseg;
+    // queue sort at every cadence-th census step (two-kernel step only)
+    const int cadence = opt.sort_cadence > 0 ? opt.sort_cadence : 0;
+    const int nbanks = cadence ? 4 : 3;
     int rc;
-    if ((rc = ensure(pb->bank, pad256(bank_bytes(slots, FM, WW)) * 3 + 64 * 256))) return rc;
+    if ((rc = ensure(pb->bank, pad256(bank_bytes(slots, FM, WW)) * nbanks + 64 * 256))) return rc;
     if ((rc = ensure(pb->queues, ctl_bytes(G)))) return rc;
     if (P.qoi_on && (rc = ensure(pb->qoi_hist, C * sizeof(double)))) return rc;
-    Layout L = carve(pb->bank.p, pb->queues.p, slots, G, Lseg, FM ? FM : P.finite_mask, WW);
+    Layout L = carve(pb->bank.p, pb->queues.p, slots, G, Lseg, FM ? FM : P.finite_mask, WW, nbanks);
     L.ctl.Lh = Lh;
     RunArgs R = R0;
     R.qoi_hist = (double *)pb->qoi_hist.p;
@@ -1193,7 +1310,7 @@ int run_event(mcdc_problem *pb, const RunArgs &R0, uint64_t first, uint64_t coun
     const int every = opt.profile_every > 1 ? opt.profile_every : 1;
 
     // one kernel per census step (default), or the advance / events pair
-    const bool one_kernel = (opt.flags & MCDC_FLAG_TWO_KERNEL_STEP) == 0;
+    const bool one_kernel = (opt.flags & MCDC_FLAG_TWO_KERNEL_STEP) == 0 && cadence == 0;
     // (with population control the controlled particles go back into the
     // step's input bank, so every step runs on bank 0)
     auto enqueue_step = [&](int par_in, hipStream_t s, Profiler &pr, const RunArgs &Ra) {
@@ -1203,14 +1320,17 @@ int run_event(mcdc_problem *pb, const RunArgs &R0, uint64_t first, uint64_t coun
         if (one_kernel) {
             launch_timed(pr, MCDC_PROF_EVENTS, k_event<FM, WW, LT, false, MCDC_PROF_EVENTS, true>, dim3(G),
                          dim3(kBlock), (uint32_t)shmem, s, P, Ra, cur, nxt, L.ctl, par, gn, SB[0], tabs,
-                         (const BatchItem *)nullptr, (const SegInfo *)nullptr);
+                         (const BatchItem *)nullptr, (const SegInfo *)nullptr, L.srt, 0);
         } else {
             launch_timed(pr, MCDC_PROF_ADVANCE, k_advance<FM, WW, LT, false>, dim3(G), dim3(kBlock), (uint32_t)shmem,
                          s, P, Ra, cur, nxt, L.ev, L.ctl, par, gn, SB[0], tabs, (const BatchItem *)nullptr,
                          (const SegInfo *)nullptr);
+            if (cadence)
+                launch_timed(pr, MCDC_PROF_SORT, k_sort_events<FM, WW, false>, dim3(G), dim3(kBlock), 0u, s, P, Ra,
+                             L.ev, L.srt, L.ctl, cadence, (const BatchItem *)nullptr, (const SegInfo *)nullptr);
             launch_timed(pr, MCDC_PROF_EVENTS, k_event<FM, WW, LT, false>, dim3(G), dim3(kBlock), (uint32_t)shmem, s,
                          P, Ra, L.ev, nxt, L.ctl, par, gn, SB[0], tabs, (const BatchItem *)nullptr,
-                         (const SegInfo *)nullptr);
+                         (const SegInfo *)nullptr, L.srt, cadence);
         }
         if constexpr (WW) {
             if (pc) {
@@ -1243,6 +1363,7 @@ int run_event(mcdc_problem *pb, const RunArgs &R0, uint64_t first, uint64_t coun
         key_add(key, tabs);
         key_add(key, LT);
         key_add(key, one_kernel);
+        key_add(key, cadence);
         key_add(key, pc);
         key_add(key, span);
         key_add(key, n_run);
@@ -1321,11 +1442,13 @@ int run_event_lt(mcdc_problem *p, const RunArgs &R, uint64_t first, uint64_t cou
 // Batched solve: every problem's segments share one set of banks; each
 // census step (advance, events, step end over all segments of all
 // problems) is captured once as a graph and replayed for the largest K.
+// (step < 0: one kernel per census step; 0: the two-kernel step; c >= 1:
+// the two-kernel step with the queue sort at every c-th census step)
 template <int FM, bool LT>
 int run_batched_steps(const BatchItem *d_items, const SegInfo *d_segs, unsigned int G, unsigned int Lseg, int Kmax,
-                      size_t shmem, void *bank_mem, void *ctl_mem, hipStream_t st) {
+                      size_t shmem, void *bank_mem, void *ctl_mem, hipStream_t st, int step_form) {
     const uint64_t slots = (uint64_t)G * Lseg;
-    Layout L = carve(bank_mem, ctl_mem, slots, G, Lseg, FM, false);
+    Layout L = carve(bank_mem, ctl_mem, slots, G, Lseg, FM, false, step_form > 0 ? 4 : 3);
     const DevProblem P0{};
     const RunArgs R0{};
     const LdsTables t0{};
@@ -1342,8 +1465,19 @@ int run_batched_steps(const BatchItem *d_items, const SegInfo *d_segs, unsigned 
     for (int q = 0; q < 2 && e == hipSuccess; ++q) {
         e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) break;
-        hipLaunchKernelGGL((k_event<FM, false, LT, true, MCDC_PROF_EVENTS, true>), dim3(G), dim3(kBlock), shmem,
-                           cs, P0, R0, L.bank[q], L.bank[q ^ 1], L.ctl, q, 0, none, t0, d_items, d_segs);
+        if (step_form < 0) {
+            hipLaunchKernelGGL((k_event<FM, false, LT, true, MCDC_PROF_EVENTS, true>), dim3(G), dim3(kBlock), shmem,
+                               cs, P0, R0, L.bank[q], L.bank[q ^ 1], L.ctl, q, 0, none, t0, d_items, d_segs, L.srt,
+                               0);
+        } else {
+            hipLaunchKernelGGL((k_advance<FM, false, LT, true>), dim3(G), dim3(kBlock), shmem, cs, P0, R0, L.bank[q],
+                               L.bank[q ^ 1], L.ev, L.ctl, q, 0, none, t0, d_items, d_segs);
+            if (step_form > 0)
+                hipLaunchKernelGGL((k_sort_events<FM, false, true>), dim3(G), dim3(kBlock), 0, cs, P0, R0, L.ev,
+                                   L.srt, L.ctl, step_form, d_items, d_segs);
+            hipLaunchKernelGGL((k_event<FM, false, LT, true>), dim3(G), dim3(kBlock), shmem, cs, P0, R0, L.ev,
+                               L.bank[q ^ 1], L.ctl, q, 0, none, t0, d_items, d_segs, L.srt, step_form);
+        }
         hipLaunchKernelGGL(k_step_end, dim3(1), dim3(1), 0, cs, L.ctl);
         e = hipStreamEndCapture(cs, &graph[q]);
         if (e == hipSuccess) e = hipGraphInstantiate(&exec[q], graph[q], nullptr, nullptr, 0);
@@ -1365,7 +1499,7 @@ struct BatchedLayout {
     unsigned int G;
 };
 
-BatchedLayout batched_layout(const uint64_t *n_hist, int n, unsigned int Lseg) {
+BatchedLayout batched_layout(const uint64_t *n_hist, int n, unsigned int Lseg, int banks) {
     BatchedLayout b{};
     uint64_t G = 0;
     for (int j = 0; j < n; ++j) G += (n_hist[j] + Lseg - 1) / Lseg;
@@ -1375,20 +1509,20 @@ BatchedLayout batched_layout(const uint64_t *n_hist, int n, unsigned int Lseg) {
     b.segs_off = pad256(sizeof(BatchItem) * n);
     b.ctl_off = b.segs_off + pad256(sizeof(SegInfo) * G);
     b.bank_off = b.ctl_off + ctl_bytes((unsigned int)G);
-    b.bytes = b.bank_off + pad256(bank_bytes(G * Lseg, 0, false)) * 3 + 64 * 256;
+    b.bytes = b.bank_off + pad256(bank_bytes(G * Lseg, 0, false)) * banks + 64 * 256;
     return b;
 }
 
 }  // namespace
 
-size_t event_batched_bytes(const uint64_t *n_hist, int n, unsigned int seg_len) {
-    return batched_layout(n_hist, n, seg_len).bytes;
+size_t event_batched_bytes(const uint64_t *n_hist, int n, unsigned int seg_len, int step_form) {
+    return batched_layout(n_hist, n, seg_len, step_form > 0 ? 4 : 3).bytes;
 }
 
 int launch_event_batched(std::vector<BatchItem> &items, const uint64_t *n_hist, unsigned int seg_len, void *mem,
-                         size_t mem_bytes, hipStream_t st) {
+                         size_t mem_bytes, hipStream_t st, int step_form) {
     const int n = (int)items.size();
-    const BatchedLayout lay = batched_layout(n_hist, n, seg_len);
+    const BatchedLayout lay = batched_layout(n_hist, n, seg_len, step_form > 0 ? 4 : 3);
     if (lay.bytes > mem_bytes) {
         set_error("batched solve: work memory too small");
         return MCDC_E_INVALID;
@@ -1428,14 +1562,15 @@ int launch_event_batched(std::vector<BatchItem> &items, const uint64_t *n_hist, 
         e = hipMemcpyAsync(d_segs, segs.data(), sizeof(SegInfo) * segs.size(), hipMemcpyHostToDevice, st);
     if (e != hipSuccess) return hip_fail(e, "batched tables");
     void *ctl = base + lay.ctl_off, *bank = base + lay.bank_off;
+    const int sf = step_form;
     if (fm == 1)
-        return lt_all ? run_batched_steps<1, true>(d_items, d_segs, lay.G, seg_len, Kmax, shmem, bank, ctl, st)
-                      : run_batched_steps<1, false>(d_items, d_segs, lay.G, seg_len, Kmax, shmem, bank, ctl, st);
+        return lt_all ? run_batched_steps<1, true>(d_items, d_segs, lay.G, seg_len, Kmax, shmem, bank, ctl, st, sf)
+                      : run_batched_steps<1, false>(d_items, d_segs, lay.G, seg_len, Kmax, shmem, bank, ctl, st, sf);
     if (fm == 7)
-        return lt_all ? run_batched_steps<7, true>(d_items, d_segs, lay.G, seg_len, Kmax, shmem, bank, ctl, st)
-                      : run_batched_steps<7, false>(d_items, d_segs, lay.G, seg_len, Kmax, shmem, bank, ctl, st);
-    return lt_all ? run_batched_steps<0, true>(d_items, d_segs, lay.G, seg_len, Kmax, shmem, bank, ctl, st)
-                  : run_batched_steps<0, false>(d_items, d_segs, lay.G, seg_len, Kmax, shmem, bank, ctl, st);
+        return lt_all ? run_batched_steps<7, true>(d_items, d_segs, lay.G, seg_len, Kmax, shmem, bank, ctl, st, sf)
+                      : run_batched_steps<7, false>(d_items, d_segs, lay.G, seg_len, Kmax, shmem, bank, ctl, st, sf);
+    return lt_all ? run_batched_steps<0, true>(d_items, d_segs, lay.G, seg_len, Kmax, shmem, bank, ctl, st, sf)
+                  : run_batched_steps<0, false>(d_items, d_segs, lay.G, seg_len, Kmax, shmem, bank, ctl, st, sf);
 }
 
 void destroy_graph_cache(mcdc_problem *p) {

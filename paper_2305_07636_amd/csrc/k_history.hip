@@ -412,8 +412,11 @@ int launch_main(mcdc_problem *pb, const DevProblem &P, const RunArgs &R, uint64_
                 uint64_t chunk_first, const SplitBank &SB, hipStream_t st, Profiler &prof) {
     const int bs = 256;
     int rc;
-    if ((rc = ensure(pb->work, 256))) return rc;
-    unsigned long long *next = (unsigned long long *)pb->work.p;
+    unsigned long long *next = R.work;
+    if (!next) {
+        if ((rc = ensure(pb->work, 256))) return rc;
+        next = (unsigned long long *)pb->work.p;
+    }
     LdsTables tabs{};
     const bool lt = table_layout(P, tabs, kHistoryTablesMax);
     const size_t shmem = lt ? (size_t)tabs.bytes : 0;
@@ -571,6 +574,18 @@ __global__ void __launch_bounds__(BS) k_history_batched(const BatchItem *__restr
             int code = kTime;
             if (birth<FM>(it.P, history_stream(it.P, it.R.seed, i), p))
                 code = track<FM, false>(it.P, it.R, p, b, i, acc, none);
+            if (it.R.dbg_counts) {
+                uint32_t *d = it.R.dbg_counts + i * 5;
+                d[0] = acc.n_ev[0];
+                d[1] = acc.n_ev[1];
+                d[2] = acc.n_ev[2];
+                d[3] = 1u;
+                d[4] = 1u << code;
+            }
+            if (it.R.dbg_scores) {
+                it.R.dbg_scores[i * 2 + 0] = acc.track;
+                it.R.dbg_scores[i * 2 + 1] = acc.qoi;
+            }
             const int slot = j - j0;
             if (slot < 2) {
                 for (int e = 0; e < 3; ++e)

@@ -78,6 +78,11 @@ struct DevProblem {
     const double *pin_xc;      // [ncells] its centre (the geometry cell's x-y midpoint)
     const double *pin_yc;
     const int32_t *pin_mat;    // [ncells] material inside it
+    // moving plane normal to z (rod_on = 0: none; never with pins)
+    int rod_on;
+    const double *rod_z;       // [K + 1] heights at the time edges
+    const double *rod_v;       // [K] speed in each census step
+    const int32_t *rod_mat;    // [ncells] material above the plane, -1 = not a rod cell
 };
 
 // Runs whose particles make progeny (window splits, fission neutrons) or
@@ -107,6 +112,8 @@ struct RunArgs {
     double *dbg_scores;            // [N][2] or nullptr
     int *overflow;                 // set to 1 when a bank overflows
     unsigned long long *prof;      // [MCDC_PROF_CLASSES][2] particles, bytes; or nullptr
+    unsigned long long *work;      // history form: the persistent launch's work counter, or
+                                   // nullptr (the launcher then uses the problem's own buffer)
 };
 
 // Read-only tables the event kernels stage in LDS: byte offsets (behind
@@ -185,6 +192,9 @@ struct HostProblem {
     bool pins = false;
     std::vector<double> pin_r2, pin_xc, pin_yc;   // [ncells] (pins only)
     std::vector<int32_t> pin_mat;
+    bool rod = false;
+    std::vector<double> rod_z, rod_v;  // [K + 1], [K] (moving plane only)
+    std::vector<int32_t> rod_mat;      // [ncells]
     std::vector<uint8_t> qoi_groups;
     std::vector<double> bin_norm;      // [nts] V_j (product of bin widths)
     std::vector<double> time_norm;     // [K] dt_k (1 if infinite)
@@ -234,6 +244,18 @@ int launch_fold(const DevProblem &P, double *S, double *L, int B, int X, int XL,
                 double *var, double *raw, double *leak_mean, double *leak_var,
                 double *tc_mean, double *tc_var, hipStream_t st);
 int launch_zero(void *p, size_t bytes, hipStream_t st);
+// Run-level steps shared by mcdc_run and its allocation-free variant
+// (run.cpp): batch statistics into the result's arrays, and the host copies
+// of counters and detector sums (begin before, end after the stream is
+// synchronised).
+struct Collect {
+    unsigned long long cnt[kCounters];
+    double qs[2];
+    int ovf;
+};
+int fold(mcdc_problem *p, const RunArgs &R, mcdc_result *out, hipStream_t st, Profiler &prof);
+int collect_begin(mcdc_problem *p, const RunArgs &R, mcdc_result *out, Collect &c, hipStream_t st);
+int collect_end(mcdc_problem *p, uint64_t N, const Collect &c, mcdc_result *out, double ms);
 void destroy_graph_cache(mcdc_problem *p);
 int launch_batched(const BatchItem *items, const uint64_t *offs, int n_items, uint64_t total,
                    unsigned long long *next, int finite_mask, int block, int per_thread, hipStream_t st);
@@ -241,7 +263,9 @@ int launch_qoi_reduce(const double *qoi_hist, uint64_t n, double *qoi_sums, hipS
 // Batched event form (k_event.hip): device memory it needs for segments of
 // seg_len slots, and the run itself (items hold each problem's DevProblem
 // and prepared RunArgs; the launcher fills their table layouts).
-size_t event_batched_bytes(const uint64_t *n_hist, int n, unsigned int seg_len);
+// step_form < 0: one kernel per census step; 0: the two-kernel step; c >= 1:
+// the two-kernel step with the queue sort at every c-th census step.
+size_t event_batched_bytes(const uint64_t *n_hist, int n, unsigned int seg_len, int step_form);
 // k-eigenvalue cycles (k_eigen.hip): device memory for N particles per
 // cycle, and the cycle loop (M of every cycle into m_dev[cycles]; the
 // sites of every cycle per spatial tally bin added into hist[cycles][nts];
@@ -250,6 +274,6 @@ size_t eigen_bytes(uint64_t N);
 int launch_eigen(const DevProblem &P, const RunArgs &R, uint64_t N, int n_inactive, int n_active, uint64_t seed,
                  void *mem, uint64_t *m_dev, int *no_sites, unsigned long long *hist, hipStream_t st);
 int launch_event_batched(std::vector<BatchItem> &items, const uint64_t *n_hist, unsigned int seg_len, void *mem,
-                         size_t mem_bytes, hipStream_t st);
+                         size_t mem_bytes, hipStream_t st, int step_form);
 
 }  // namespace mcdc

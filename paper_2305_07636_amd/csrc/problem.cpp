@@ -369,6 +369,34 @@ int compile(const mcdc_problem_desc *d, HostProblem &h) {
                 }
     }
 
+    // moving plane: per union cell, the rod material of its geometry cell;
+    // the plane's speed in each census step
+    if (d->rod_z || d->rod_material) {
+        if (!d->rod_z || !d->rod_material) return invalid("a moving plane needs rod_z and rod_material");
+        if (d->pin_radius) {
+            set_error("a moving plane is not combined with pins");
+            return MCDC_E_UNSUPPORTED;
+        }
+        if (d->n_planes[2] == 0) return invalid("a moving plane needs a finite z axis");
+        for (int k = 0; k <= h.K; ++k)
+            if (!std::isfinite(d->rod_z[k])) return invalid("rod_z must be finite");
+        for (size_t g = 0; g < ngeo; ++g)
+            if (d->rod_material[g] < -1 || d->rod_material[g] >= M) return invalid("rod material out of range");
+        h.rod = true;
+        h.rod_z.assign(d->rod_z, d->rod_z + h.K + 1);
+        h.rod_v.assign(h.K, 0.0);
+        for (int k = 0; k < h.K; ++k)
+            if (std::isfinite(h.T[k + 1])) h.rod_v[k] = (h.rod_z[k + 1] - h.rod_z[k]) / (h.T[k + 1] - h.T[k]);
+        h.rod_mat.assign(ncells, -1);
+        for (int iz = 0; iz < h.nc[2]; ++iz)
+            for (int iy = 0; iy < h.nc[1]; ++iy)
+                for (int ix = 0; ix < h.nc[0]; ++ix) {
+                    const size_t c = ((size_t)iz * h.nc[1] + iy) * h.nc[0] + ix;
+                    const int gx = geo_of[0][ix], gy = geo_of[1][iy], gz = geo_of[2][iz];
+                    h.rod_mat[c] = d->rod_material[((size_t)gz * ngc[1] + gy) * ngc[0] + gx];
+                }
+    }
+
     // normalisation: bin volume (product of the widths of meshed axes) and
     // time-bin width (1 for an infinite bin)
     std::vector<double> wdt[3];
@@ -404,7 +432,8 @@ int upload(mcdc_problem *p) {
                  o_qg = b.add(h.qoi_groups), o_bn = b.add(h.bin_norm), o_tn = b.add(h.time_norm),
                  o_pf = b.add(h.pf), o_nu = b.add(h.nu), o_chi = b.add(h.chi_cdf),
                  o_pr2 = b.add(h.pin_r2), o_pxc = b.add(h.pin_xc), o_pyc = b.add(h.pin_yc),
-                 o_pm = b.add(h.pin_mat);
+                 o_pm = b.add(h.pin_mat), o_rz = b.add(h.rod_z), o_rv = b.add(h.rod_v),
+                 o_rm = b.add(h.rod_mat);
     std::vector<uint64_t> A(64), C(64);
     lcg_map(kStride, A[0], C[0]);
     for (int j = 1; j < 64; ++j) {
@@ -481,6 +510,10 @@ int upload(mcdc_problem *p) {
     D.pin_xc = h.pins ? (const double *)(base + o_pxc) : nullptr;
     D.pin_yc = h.pins ? (const double *)(base + o_pyc) : nullptr;
     D.pin_mat = h.pins ? (const int32_t *)(base + o_pm) : nullptr;
+    D.rod_on = h.rod ? 1 : 0;
+    D.rod_z = h.rod ? (const double *)(base + o_rz) : nullptr;
+    D.rod_v = h.rod ? (const double *)(base + o_rv) : nullptr;
+    D.rod_mat = h.rod ? (const int32_t *)(base + o_rm) : nullptr;
     D.implicit = d.implicit_capture ? 1 : 0;
     D.roulette_w = d.roulette_w;
     D.roulette_ws = d.roulette_ws;

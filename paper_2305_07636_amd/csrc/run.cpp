@@ -97,6 +97,7 @@ int check_options(const mcdc_run_options &opt) {
     if (opt.segments < 0 || opt.segments > (1 << 20)) return bad("segments must be in [0, 2^20]");
     if (opt.profile_every < 0 || opt.profile_phase < 0) return bad("profile_every and profile_phase must be >= 0");
     if (opt.bank_capacity < 0) return bad("bank_capacity must be >= 0");
+    if (opt.sort_cadence < -1 || opt.sort_cadence > 64) return bad("sort_cadence must be in [-1, 64]");
     return MCDC_OK;
 }
 
@@ -150,9 +151,11 @@ int prepare(mcdc_problem *p, uint64_t N, uint64_t seed, const mcdc_run_options &
     return MCDC_OK;
 }
 
+}  // namespace
+
 // Batch statistics into the caller's buffers (device) or staging buffers
 // (host outputs).
-int fold(mcdc_problem *p, const RunArgs &R, mcdc_result *out, hipStream_t st, Profiler &prof) {
+int mcdc::fold(mcdc_problem *p, const RunArgs &R, mcdc_result *out, hipStream_t st, Profiler &prof) {
     const DevProblem &P = p->d;
     double *mean = out->mean, *var = out->var, *raw = out->raw;
     double *lmean = out->leak_mean, *lvar = out->leak_var;
@@ -184,17 +187,11 @@ int fold(mcdc_problem *p, const RunArgs &R, mcdc_result *out, hipStream_t st, Pr
 
 // Host copies of counters, detector sums and (host) outputs.  The caller
 // synchronises the stream between collect_begin and collect_end.
-struct Collect {
-    unsigned long long cnt[kCounters];
-    double qs[2];
-    int ovf;
-};
-
-int collect_begin(mcdc_problem *p, mcdc_result *out, Collect &c, hipStream_t st) {
+int mcdc::collect_begin(mcdc_problem *p, const RunArgs &R, mcdc_result *out, Collect &c, hipStream_t st) {
     const DevProblem &P = p->d;
-    HIP_CHECK(hipMemcpyAsync(c.cnt, p->counters.p, sizeof(c.cnt), hipMemcpyDeviceToHost, st), "copy counters");
-    HIP_CHECK(hipMemcpyAsync(c.qs, p->qoi_sums.p, sizeof(c.qs), hipMemcpyDeviceToHost, st), "copy detector");
-    HIP_CHECK(hipMemcpyAsync(&c.ovf, p->overflow.p, sizeof(int), hipMemcpyDeviceToHost, st), "copy flag");
+    HIP_CHECK(hipMemcpyAsync(c.cnt, R.counters, sizeof(c.cnt), hipMemcpyDeviceToHost, st), "copy counters");
+    HIP_CHECK(hipMemcpyAsync(c.qs, R.qoi_sums, sizeof(c.qs), hipMemcpyDeviceToHost, st), "copy detector");
+    HIP_CHECK(hipMemcpyAsync(&c.ovf, R.overflow, sizeof(int), hipMemcpyDeviceToHost, st), "copy flag");
     if (out->host_outputs) {
         const size_t nt = P.ntally * sizeof(double), nl = (size_t)P.K * P.G * 6 * sizeof(double);
         if (out->mean) HIP_CHECK(hipMemcpyAsync(out->mean, p->mean.p, nt, hipMemcpyDeviceToHost, st), "copy mean");
@@ -212,7 +209,7 @@ int collect_begin(mcdc_problem *p, mcdc_result *out, Collect &c, hipStream_t st)
     return MCDC_OK;
 }
 
-int collect_end(mcdc_problem *p, uint64_t N, const Collect &c, mcdc_result *out, double ms) {
+int mcdc::collect_end(mcdc_problem *p, uint64_t N, const Collect &c, mcdc_result *out, double ms) {
     if (c.ovf) {
         static const char *what[] = {"particle bank or split bank overflow",
                                      "population control: a weight of 2^32 or more (or not a number)",
@@ -235,6 +232,8 @@ int collect_end(mcdc_problem *p, uint64_t N, const Collect &c, mcdc_result *out,
     out->kernel_ms = ms;
     return MCDC_OK;
 }
+
+namespace {
 
 struct Events {
     hipEvent_t a = nullptr, b = nullptr;
@@ -312,7 +311,7 @@ extern "C" int mcdc_run(mcdc_problem *p, uint64_t n_histories, uint64_t seed, co
     HIP_CHECK(hipEventRecord(ev.b, st), "hipEventRecord");
 
     Collect c{};
-    if ((rc = collect_begin(p, out, c, st))) return rc;
+    if ((rc = collect_begin(p, R, out, c, st))) return rc;
     unsigned long long pc[2 * MCDC_PROF_CLASSES] = {};
     if (opt.profile) HIP_CHECK(hipMemcpyAsync(pc, p->prof.p, sizeof(pc), hipMemcpyDeviceToHost, st), "copy profile");
     HIP_CHECK(hipStreamSynchronize(st), "hipStreamSynchronize");
@@ -335,6 +334,10 @@ namespace {
 struct Tuned {
     int block, per_thread;   // history form: workgroup size, histories per thread per pull
     unsigned int seg_len;    // event form: slots per bank segment
+    int step_form;           // event form: -1 one kernel per census step, 0 two-kernel step,
+                             // c >= 1 two-kernel step with the queue sort every c-th step
+    uint64_t tail;           // event form: problems of at most this many histories run in
+                             // the history-form launch instead
 };
 
 // Launch shapes and form choices of batched solves, per batch signature,
@@ -391,6 +394,187 @@ struct DevMem {
     }
 };
 
+// Options of problem j of a batch: the debug arrays of a batched run hold
+// every problem's histories in problem order, so problem j's records start
+// after the histories of problems 0 .. j-1.
+mcdc_run_options batch_opt(const mcdc_run_options &opt, const uint64_t *n_hist, int j, int alg) {
+    mcdc_run_options o = opt;
+    o.algorithm = alg;
+    uint64_t off = 0;
+    for (int k = 0; k < j; ++k) off += n_hist[k];
+    if (o.debug_counts) o.debug_counts += off * 5;
+    if (o.debug_scores) o.debug_scores += off * 2;
+    return o;
+}
+
+// Device memory of batched runs, kept across the tuning runs of one call.
+struct BatchWork {
+    DevMem ev;             // event form: banks, tables, segment list
+    size_t ev_bytes = 0;
+    DevMem hist;           // history form: items, history offsets, work counter
+    size_t hist_bytes = 0;
+};
+
+int grow(DevMem &m, size_t &have, size_t need) {
+    if (need <= have) return MCDC_OK;
+    if (m.mem) (void)hipFree(m.mem);
+    m.mem = nullptr;
+    have = 0;
+    HIP_CHECK(hipMalloc(&m.mem, need), "hipMalloc(batched work)");
+    have = need;
+    return MCDC_OK;
+}
+
+// One batched run in configuration t: problems with more than t.tail
+// histories go to the event form (all their segments in one set of banks,
+// one captured graph per census step in form t.step_form), the others to
+// one persistent history-form launch (workgroups of t.block threads
+// pulling t.per_thread histories per thread); all_history sends every
+// problem to the history launch.  Fills items[j].R for the fold and the
+// device time of the run into *ms.
+int batched_once(mcdc_problem *const *ps, int32_t n, const uint64_t *n_hist, const uint64_t *seeds,
+                 const mcdc_run_options &opt, bool all_history, const Tuned &t, std::vector<BatchItem> &items,
+                 BatchWork &wk, hipStream_t st, float *ms) {
+    Events ev;
+    HIP_CHECK(hipEventCreate(&ev.a), "hipEventCreate");
+    HIP_CHECK(hipEventCreate(&ev.b), "hipEventCreate");
+    HIP_CHECK(hipEventRecord(ev.a, st), "hipEventRecord");
+    std::vector<int> E, H;
+    for (int j = 0; j < n; ++j) {
+        items[j] = BatchItem{};
+        items[j].P = ps[j]->d;
+        if (n_hist[j] == 0) continue;
+        const bool in_e = !all_history && n_hist[j] > t.tail;
+        (in_e ? E : H).push_back(j);
+        int r = prepare(ps[j], n_hist[j], seeds[j],
+                        batch_opt(opt, n_hist, j, in_e ? MCDC_ALG_EVENT : MCDC_ALG_HISTORY), st, items[j].R);
+        if (r) return r;
+        if (in_e && ps[j]->d.qoi_on) {
+            if ((r = ensure(ps[j]->qoi_hist, n_hist[j] * sizeof(double)))) return r;
+            items[j].R.qoi_hist = (double *)ps[j]->qoi_hist.p;
+            ZERO(items[j].R.qoi_hist, n_hist[j] * sizeof(double));
+        }
+    }
+    int r;
+    if (!E.empty()) {
+        std::vector<BatchItem> ie;
+        std::vector<uint64_t> ne;
+        for (int j : E) {
+            ie.push_back(items[j]);
+            ne.push_back(n_hist[j]);
+        }
+        const size_t need = event_batched_bytes(ne.data(), (int)E.size(), t.seg_len, t.step_form);
+        if ((r = grow(wk.ev, wk.ev_bytes, need))) return r;
+        if ((r = launch_event_batched(ie, ne.data(), t.seg_len, wk.ev.mem, wk.ev_bytes, st, t.step_form))) return r;
+        for (int j : E)
+            if (ps[j]->d.qoi_on && (r = launch_qoi_reduce(items[j].R.qoi_hist, n_hist[j], items[j].R.qoi_sums, st)))
+                return hip_fail((hipError_t)r, "detector reduce");
+    }
+    if (!H.empty()) {
+        const int nh = (int)H.size();
+        std::vector<BatchItem> ih;
+        std::vector<uint64_t> offs(nh + 1, 0);
+        int fm = -1;
+        for (int k = 0; k < nh; ++k) {
+            const int j = H[k];
+            ih.push_back(items[j]);
+            offs[k + 1] = offs[k] + n_hist[j];
+            const int m = ps[j]->d.finite_mask;
+            fm = (fm < 0 || fm == m) ? m : 0;
+        }
+        const size_t items_bytes = (sizeof(BatchItem) * n + 255) & ~size_t(255);
+        const size_t offs_bytes = ((n + 1) * sizeof(uint64_t) + 255) & ~size_t(255);
+        if ((r = grow(wk.hist, wk.hist_bytes, items_bytes + offs_bytes + 256))) return r;
+        BatchItem *d_items = (BatchItem *)wk.hist.mem;
+        uint64_t *d_offs = (uint64_t *)((char *)wk.hist.mem + items_bytes);
+        unsigned long long *d_next = (unsigned long long *)((char *)wk.hist.mem + items_bytes + offs_bytes);
+        HIP_CHECK(hipMemcpyAsync(d_items, ih.data(), sizeof(BatchItem) * nh, hipMemcpyHostToDevice, st),
+                  "copy items");
+        HIP_CHECK(hipMemcpyAsync(d_offs, offs.data(), (nh + 1) * sizeof(uint64_t), hipMemcpyHostToDevice, st),
+                  "copy offsets");
+        if ((r = launch_zero(d_next, sizeof(unsigned long long), st))) return hip_fail((hipError_t)r, "zero");
+        if ((r = launch_batched(d_items, d_offs, nh, offs[nh], d_next, fm, t.block, t.per_thread, st))) return r;
+    }
+    HIP_CHECK(hipEventRecord(ev.b, st), "hipEventRecord");
+    HIP_CHECK(hipEventSynchronize(ev.b), "hipEventSynchronize");
+    HIP_CHECK(hipEventElapsedTime(ms, ev.a, ev.b), "hipEventElapsedTime");
+    return MCDC_OK;
+}
+
+// Launch parameters of a batched solve: forced by the options, cached per
+// batch signature, or tuned now by coordinate descent over timed runs of
+// the whole batch.  Event form: segment length {2048, 8192, 32768, 65536}
+// with one kernel per census step; then the census step's form (one
+// kernel, two kernels, two kernels with the queue sort every 1, 2, 4 or 8
+// steps) at that length; then the tail switch (problems of at most 0, 2e4
+// or 1e5 histories run in the history-form launch).  History form:
+// workgroup {128, 256, 512} x histories per pull {1, 4, 16}.  No
+// parameter changes per-history results, only tally summation order.
+int batched_tuned(mcdc_problem *const *ps, int32_t n, const uint64_t *n_hist, const uint64_t *seeds,
+                  const mcdc_run_options &opt, bool all_history, std::vector<BatchItem> &items, BatchWork &wk,
+                  hipStream_t st, float *ms) {
+    const bool two = (opt.flags & MCDC_FLAG_TWO_KERNEL_STEP) != 0;
+    Tuned t{opt.block_size ? opt.block_size : 256, 4, (unsigned int)opt.bank_capacity,
+            opt.sort_cadence > 0 ? opt.sort_cadence : (two ? 0 : -1), 0};
+    const bool seg_forced = opt.bank_capacity != 0;
+    const bool form_forced = opt.sort_cadence != 0 || two;
+    const std::string sig = std::string(all_history ? "history:" : "event:") + std::to_string(opt.block_size) +
+                            "," + std::to_string(opt.bank_capacity) + "," + std::to_string(opt.sort_cadence) + "," +
+                            std::to_string(two) + ":" + signature(ps, n, n_hist);
+    int rc;
+    float m = 0.f;
+    if (!tuned_get(sig, t)) {
+        auto trial = [&](const Tuned &c, float *best, Tuned *arg) -> int {
+            int r = batched_once(ps, n, n_hist, seeds, opt, all_history, c, items, wk, st, &m);
+            if (r) return r;
+            if (m < *best) {
+                *best = m;
+                *arg = c;
+            }
+            return MCDC_OK;
+        };
+        float best = 1e30f;
+        if (all_history) {
+            if (!opt.block_size) {
+                for (int bsz : {128, 256, 512})
+                    for (int pt : {1, 4, 16}) {
+                        Tuned c = t;
+                        c.block = bsz;
+                        c.per_thread = pt;
+                        if ((rc = trial(c, &best, &t))) return rc;
+                    }
+            }
+        } else {
+            Tuned base = t;
+            if (!seg_forced) {
+                for (unsigned int L : {2048u, 8192u, 32768u, 65536u}) {
+                    Tuned c = base;
+                    c.seg_len = L;
+                    if ((rc = trial(c, &best, &t))) return rc;
+                }
+            } else {
+                if ((rc = trial(t, &best, &t))) return rc;
+            }
+            if (!form_forced) {
+                base = t;
+                for (int f : {0, 1, 2, 4, 8}) {
+                    Tuned c = base;
+                    c.step_form = f;
+                    if ((rc = trial(c, &best, &t))) return rc;
+                }
+            }
+            base = t;
+            for (uint64_t tail : {20000ull, 100000ull}) {
+                Tuned c = base;
+                c.tail = tail;
+                if ((rc = trial(c, &best, &t))) return rc;
+            }
+        }
+        tuned_put(sig, t);
+    }
+    return batched_once(ps, n, n_hist, seeds, opt, all_history, t, items, wk, st, ms);
+}
+
 }  // namespace
 
 // Fold and hand back every problem's results after a batched run.
@@ -402,7 +586,7 @@ int finish_batched(mcdc_problem *const *ps, int32_t n, const uint64_t *n_hist, s
     for (int j = 0; j < n; ++j) {
         if (n_hist[j] == 0) continue;
         if ((rc = fold(ps[j], items[j].R, &outs[j], st, none))) return rc;
-        if ((rc = collect_begin(ps[j], &outs[j], cs[j], st))) return rc;
+        if ((rc = collect_begin(ps[j], items[j].R, &outs[j], cs[j], st))) return rc;
     }
     HIP_CHECK(hipStreamSynchronize(st), "hipStreamSynchronize");
     for (int j = 0; j < n; ++j) {
@@ -415,80 +599,6 @@ int finish_batched(mcdc_problem *const *ps, int32_t n, const uint64_t *n_hist, s
         if ((rc = collect_end(ps[j], n_hist[j], cs[j], &outs[j], ms))) return rc;
     }
     return MCDC_OK;
-}
-
-// Batched event form: all problems' bank segments in one set of banks, one
-// graph replay per census step for every problem.  Segment length (the
-// queue capacity per workgroup) is forced by bank_capacity or tuned on the
-// first call per batch signature.
-int run_batched_event(mcdc_problem *const *ps, int32_t n, const uint64_t *n_hist, const uint64_t *seeds,
-                      const mcdc_run_options &opt, mcdc_result *outs, hipStream_t st) {
-    for (int j = 0; j < n; ++j)
-        if (n_hist[j] > (1ULL << 28)) {
-            set_error("batched event form: at most 2^28 histories per problem");
-            return MCDC_E_UNSUPPORTED;
-        }
-    if (opt.bank_capacity != 0 && (opt.bank_capacity < 256 || opt.bank_capacity > (1 << 24)))
-        return bad("batched event form: bank_capacity (slots per segment) must be in [256, 2^24]");
-    const unsigned int cands[] = {2048u, 8192u, 32768u};
-    std::vector<unsigned int> tries;
-    Tuned t{0, 0, (unsigned int)opt.bank_capacity};
-    const std::string sig = "event:" + signature(ps, n, n_hist);
-    if (!t.seg_len) {
-        if (!tuned_get(sig, t)) tries.assign(std::begin(cands), std::end(cands));
-    }
-    size_t bytes = t.seg_len ? event_batched_bytes(n_hist, n, t.seg_len) : 0;
-    for (unsigned int c : tries) bytes = std::max(bytes, event_batched_bytes(n_hist, n, c));
-    DevMem wm;
-    HIP_CHECK(hipMalloc(&wm.mem, bytes), "hipMalloc(batched banks)");
-
-    std::vector<BatchItem> items(n);
-    mcdc_run_options popt = opt;
-    popt.algorithm = MCDC_ALG_EVENT;
-    auto run_once = [&](unsigned int seg_len, float *ms) -> int {
-        Events ev;
-        HIP_CHECK(hipEventCreate(&ev.a), "hipEventCreate");
-        HIP_CHECK(hipEventCreate(&ev.b), "hipEventCreate");
-        HIP_CHECK(hipEventRecord(ev.a, st), "hipEventRecord");
-        for (int j = 0; j < n; ++j) {
-            items[j] = BatchItem{};
-            items[j].P = ps[j]->d;
-            if (n_hist[j] == 0) continue;
-            int r = prepare(ps[j], n_hist[j], seeds[j], popt, st, items[j].R);
-            if (r) return r;
-            if (ps[j]->d.qoi_on) {
-                if ((r = ensure(ps[j]->qoi_hist, n_hist[j] * sizeof(double)))) return r;
-                items[j].R.qoi_hist = (double *)ps[j]->qoi_hist.p;
-                ZERO(items[j].R.qoi_hist, n_hist[j] * sizeof(double));
-            }
-        }
-        int r = launch_event_batched(items, n_hist, seg_len, wm.mem, bytes, st);
-        if (r) return r;
-        for (int j = 0; j < n; ++j)
-            if (n_hist[j] && ps[j]->d.qoi_on &&
-                (r = launch_qoi_reduce(items[j].R.qoi_hist, n_hist[j], items[j].R.qoi_sums, st)))
-                return hip_fail((hipError_t)r, "detector reduce");
-        HIP_CHECK(hipEventRecord(ev.b, st), "hipEventRecord");
-        HIP_CHECK(hipEventSynchronize(ev.b), "hipEventSynchronize");
-        HIP_CHECK(hipEventElapsedTime(ms, ev.a, ev.b), "hipEventElapsedTime");
-        return MCDC_OK;
-    };
-    int rc;
-    float ms = 0.f;
-    if (!tries.empty()) {
-        float best = 1e30f;
-        for (unsigned int c : tries) {
-            float m = 0.f;
-            if ((rc = run_once(c, &m))) return rc;
-            if (m < best) {
-                best = m;
-                t.seg_len = c;
-            }
-        }
-        tuned_put(sig, t);
-    }
-    if ((rc = run_once(t.seg_len, &ms))) return rc;
-    return finish_batched(ps, n, n_hist, items, outs, ms, st);
 }
 
 extern "C" int mcdc_run_batched(mcdc_problem *const *ps, int32_t n, const uint64_t *n_hist, const uint64_t *seeds,
@@ -522,13 +632,14 @@ extern "C" int mcdc_run_batched(mcdc_problem *const *ps, int32_t n, const uint64
     }
     int rc = check_options(opt);
     if (rc) return rc;
-    if (opt.debug_counts || opt.debug_scores || opt.profile) {
-        set_error("batched solves take no debug or profile arrays");
+    if (opt.profile) {
+        set_error("batched solves take no profile array");
         return MCDC_E_UNSUPPORTED;
     }
+    if (opt.bank_capacity != 0 && (opt.bank_capacity < 256 || opt.bank_capacity > (1 << 24)))
+        return bad("batched event form: bank_capacity (slots per segment) must be in [256, 2^24]");
     if (!ps[0]) return bad("NULL problem in batch");
     const int dev = ps[0]->device;
-    int fm = -1;
     uint64_t total = 0;
     for (int j = 0; j < n; ++j) {
         if (!ps[j]) return bad("NULL problem in batch");
@@ -541,81 +652,22 @@ extern "C" int mcdc_run_batched(mcdc_problem *const *ps, int32_t n, const uint64
             set_error("at most 1023 batches");
             return MCDC_E_UNSUPPORTED;
         }
+        if (opt.algorithm != MCDC_ALG_HISTORY && (n_hist[j] > (1ULL << 28) || ps[j]->d.K > 65535)) {
+            set_error("batched event form: at most 2^28 histories and 65535 time bins per problem");
+            return MCDC_E_UNSUPPORTED;
+        }
         for (int k = 0; k < j; ++k)
             if (ps[k] == ps[j]) return bad("a problem appears twice in the batch");
-        const int m = ps[j]->d.finite_mask;
-        fm = (fm < 0 || fm == m) ? m : 0;
         total += n_hist[j];
     }
     if (total == 0) return bad("no histories");
     HIP_CHECK(hipSetDevice(dev), "hipSetDevice");
     hipStream_t st = (hipStream_t)opt.stream;
-    if (opt.algorithm != MCDC_ALG_HISTORY) return run_batched_event(ps, n, n_hist, seeds, opt, outs, st);
-
-    // device arrays: items, history offsets, work counter
     std::vector<BatchItem> items(n);
-    std::vector<uint64_t> offs(n + 1, 0);
-    for (int j = 0; j < n; ++j) offs[j + 1] = offs[j] + n_hist[j];
-    DevMem bd;
-    const size_t items_bytes = (sizeof(BatchItem) * n + 255) & ~size_t(255);
-    const size_t offs_bytes = ((n + 1) * sizeof(uint64_t) + 255) & ~size_t(255);
-    HIP_CHECK(hipMalloc(&bd.mem, items_bytes + offs_bytes + 256), "hipMalloc(batch)");
-    BatchItem *d_items = (BatchItem *)bd.mem;
-    uint64_t *d_offs = (uint64_t *)((char *)bd.mem + items_bytes);
-    unsigned long long *d_next = (unsigned long long *)((char *)bd.mem + items_bytes + offs_bytes);
-    HIP_CHECK(hipMemcpyAsync(d_offs, offs.data(), (n + 1) * sizeof(uint64_t), hipMemcpyHostToDevice, st),
-              "copy offsets");
-
-    mcdc_run_options popt = opt;
-    popt.algorithm = MCDC_ALG_HISTORY;
-    auto run_once = [&](int block, int per_thread, float *ms) -> int {
-        Events ev;
-        HIP_CHECK(hipEventCreate(&ev.a), "hipEventCreate");
-        HIP_CHECK(hipEventCreate(&ev.b), "hipEventCreate");
-        HIP_CHECK(hipEventRecord(ev.a, st), "hipEventRecord");
-        for (int j = 0; j < n; ++j) {
-            items[j] = BatchItem{};
-            items[j].P = ps[j]->d;
-            if (n_hist[j] == 0) continue;
-            int r = prepare(ps[j], n_hist[j], seeds[j], popt, st, items[j].R);
-            if (r) return r;
-        }
-        HIP_CHECK(hipMemcpyAsync(d_items, items.data(), sizeof(BatchItem) * n, hipMemcpyHostToDevice, st),
-                  "copy items");
-        int r = launch_zero(d_next, sizeof(unsigned long long), st);
-        if (r) return hip_fail((hipError_t)r, "zero");
-        r = launch_batched(d_items, d_offs, n, total, d_next, fm, block, per_thread, st);
-        if (r) return r;
-        HIP_CHECK(hipEventRecord(ev.b, st), "hipEventRecord");
-        HIP_CHECK(hipEventSynchronize(ev.b), "hipEventSynchronize");
-        HIP_CHECK(hipEventElapsedTime(ms, ev.a, ev.b), "hipEventElapsedTime");
-        return MCDC_OK;
-    };
-
-    // launch shape: forced, cached, or tuned now over workgroup size and
-    // histories per thread per pull (a shape never changes per-history
-    // results, only the summation order of the tallies)
-    Tuned t{opt.block_size ? opt.block_size : 256, 4, 0u};
-    const std::string sig = signature(ps, n, n_hist);
+    BatchWork wk;
     float ms = 0.f;
-    if (!opt.block_size) {
-        if (!tuned_get(sig, t)) {
-            float best = 1e30f;
-            const int blocks[] = {128, 256, 512};
-            const int pts[] = {1, 4, 16};
-            for (int bsz : blocks)
-                for (int pt : pts) {
-                    float m = 0.f;
-                    if ((rc = run_once(bsz, pt, &m))) return rc;
-                    if (m < best) {
-                        best = m;
-                        t = Tuned{bsz, pt, 0u};
-                    }
-                }
-            tuned_put(sig, t);
-        }
-    }
-    if ((rc = run_once(t.block, t.per_thread, &ms))) return rc;
+    if ((rc = batched_tuned(ps, n, n_hist, seeds, opt, opt.algorithm == MCDC_ALG_HISTORY, items, wk, st, &ms)))
+        return rc;
     return finish_batched(ps, n, n_hist, items, outs, ms, st);
 }
 
@@ -640,6 +692,10 @@ extern "C" int mcdc_run_eigenvalue(mcdc_problem *p, uint64_t n_per_cycle, int32_
     if (rc) return rc;
     const DevProblem &P = p->d;
     if (!P.fission_on) return bad("the eigenvalue problem needs fission data");
+    if (P.rod_on) {
+        set_error("eigenvalue runs take no moving plane");
+        return MCDC_E_UNSUPPORTED;
+    }
     if (P.K != 1 || std::isfinite(p->h.T[1])) return bad("the eigenvalue problem is steady state: time edges [T0, inf)");
     if (P.ww_center || P.implicit || P.qoi_on || opt.debug_counts || opt.debug_scores || opt.profile) {
         set_error("eigenvalue runs take no weight windows, implicit capture, detector, debug or profile arrays");
@@ -670,7 +726,7 @@ extern "C" int mcdc_run_eigenvalue(mcdc_problem *p, uint64_t n_per_cycle, int32_
     if ((rc = fold(p, R, out, st, none))) return rc;
     HIP_CHECK(hipEventRecord(ev.b, st), "hipEventRecord");
     Collect c{};
-    if ((rc = collect_begin(p, out, c, st))) return rc;
+    if ((rc = collect_begin(p, R, out, c, st))) return rc;
     std::vector<uint64_t> m(C), h((size_t)C * P.nts);
     HIP_CHECK(hipMemcpyAsync(m.data(), m_dev, C * sizeof(uint64_t), hipMemcpyDeviceToHost, st), "copy sites");
     HIP_CHECK(hipMemcpyAsync(h.data(), hist, hbytes, hipMemcpyDeviceToHost, st), "copy source histogram");

@@ -146,7 +146,8 @@ def _frontier_table(logI, ok, shape, pct):
 
 def learned_windows(prob: dict, n_pilot: int = 100_000_000, seed: int = 1000, steps: int = 3000,
                     lr: float = 1e-3, net_seed: int = 1, rel_max: float = 0.3, frontier_pct: float = 5.0,
-                    below: float = 0.0, extrapolate: float = 1.0, normalise: str = "auto"):
+                    below: float = 0.0, extrapolate: float = 1.0, normalise: str = "auto",
+                    support: str = "resolved"):
     """Plain pilots -> training set -> network -> window table.
 
     1. forward analog pilot: the flux phi, which is the importance of the
@@ -155,9 +156,18 @@ def learned_windows(prob: dict, n_pilot: int = 100_000_000, seed: int = 1000, st
        where phi is unresolved) so adjoint particles reach back to the
        source: the adjoint flux phi+, the importance of the detector;
     3. the network fits log10 phi+ on the cells the pilot resolved
-       (weights 1 / (R^2 + 0.01)); BF16 inference gives log10 I on every
-       cell; windows w_c = I(source) / I(cell), normalised over the source
-       cells when the pilot resolved them, else at the resolved frontier.
+       (weights 1 / (R^2 + 0.01)); BF16 inference gives a smooth log10 I;
+       windows w_c = I(source) / I(cell), normalised over the source cells
+       when the pilot resolved them, else at the resolved frontier.
+
+    support: "resolved" (default) puts windows on the cells the adjoint
+    pilot resolved, with the network's smoothed importance in place of the
+    noisy tally, and leaves the other cells analog (no window); "all" puts
+    the network's prediction on every cell.  Measured on the dog-leg duct
+    (three pilot seeds, 1e8-history pilots, 1e9 windowed histories),
+    "resolved" gave 8-10x the analog figure of merit against 6-9x for the
+    raw tally windows, while "all" split particles deep into the thick
+    walls, where the fit extrapolates, and gave 4.5-5x.
 
     extrapolate: decades the network's prediction may leave the range of
     the pilot's values (cells the pilot did not resolve).  normalise:
@@ -213,12 +223,16 @@ def learned_windows(prob: dict, n_pilot: int = 100_000_000, seed: int = 1000, st
         log_ref = float(np.log10(I_src))
     else:
         log_ref = float(np.percentile(T, frontier_pct))
-    table = centres_from_log_importance(yhat, log_ref, shape, below if use_source else 0.0)
+    if support not in ("resolved", "all"):
+        raise ValueError("support must be 'resolved' or 'all'")
+    fit = np.where(ok, yhat, -np.inf) if support == "resolved" else yhat
+    table = centres_from_log_importance(fit, log_ref, shape, below if use_source else 0.0)
     raw = centres_from_log_importance(np.where(ok, np.log10(np.where(ok, phi, 1.0)), -np.inf), log_ref, shape,
                                       below if use_source else 0.0)
     info = {"pilot_s": t_pilot, "train_s": t_train, "n_train": int(ok.sum()), "loss_first": float(losses[0]),
             "loss_last": float(losses[-1]), "raw_table": raw, "adjoint_flux": phi,
-            "source_resolved": bool(src_resolved), "log_ref": log_ref, "pilot_seeds": (seed, seed + 1)}
+            "source_resolved": bool(src_resolved), "log_ref": log_ref, "pilot_seeds": (seed, seed + 1),
+            "log_importance": yhat, "adjoint_rel": rel, "resolved": ok}
     return table, info
 
 

@@ -189,3 +189,18 @@ def test_union_grid_beyond_32bit_cell_count_refused():
     p["tally"]["mesh"][2] = np.array([0.0, 6.0])
     rc, msg = _create(p)
     assert "2^31" not in msg, (rc, msg)
+
+
+def test_invalid_moving_plane_rejected():
+    p = w.rod_beam_box()
+    p["rod"]["z"] = np.array([10.0, np.inf, 0.0])
+    rc, msg = _create(p)
+    assert rc == -1 and "rod_z" in msg, (rc, msg)
+    p = w.rod_beam_box()
+    p["rod"]["material"] = np.full((1, 1, 1), 9, dtype=np.int32)
+    rc, msg = _create(p)
+    assert rc == -1 and "rod material" in msg, (rc, msg)
+    p = w.cfg2_slab_pulse()                        # z is not a finite axis
+    p["rod"] = {"z": np.zeros(101), "material": np.zeros((1, 1, 1), dtype=np.int32)}
+    rc, msg = _create(p)
+    assert rc == -1 and "finite z" in msg, (rc, msg)

@@ -31,10 +31,12 @@ def test_learned_windows_unbiased_and_effective():
 @pytest.mark.gpu
 def test_learned_windows_deep_detector_fom_gain():
     """The dog-leg duct's detector behind the second bend: learned windows
-    (1e8-history pilots, 1e9 windowed histories) against 4e9 analog
-    histories.  The windowed mean agrees with analog within 3 sigma and the
-    figure of merit 1/(R^2 T) is at least five times analog's; the network
-    also beats windows taken straight from the raw adjoint tally."""
+    (1e8-history pilots with seeds 1000/1001, 1e9 windowed histories with
+    seed 51) against 4e9 analog histories (seed 52).  The windowed mean
+    agrees with analog within 3 sigma and the figure of merit 1/(R^2 T) is
+    at least five times analog's; the network's smoothed importance also
+    beats windows taken straight from the raw adjoint tally on the same
+    cells and judged on the same histories."""
     from paper_2305_07636_amd import learned_ww as lw
 
     p = w.cfg5_dogleg()
@@ -48,3 +50,24 @@ def test_learned_windows_deep_detector_fom_gain():
     assert d < 3.0, d
     assert b["fom"] >= 5.0 * a["fom"], (b["fom"], a["fom"])
     assert b["fom"] > c["fom"], (b["fom"], c["fom"])
+
+
+@pytest.mark.gpu
+def test_learned_window_run_1e9_sampled_against_oracle():
+    """The windowed run behind the figure of merit, at its size: windows from
+    the pilots and network at the settings of the benchmark (1e8-history
+    pilots, seeds 1000/1001, 3000 training steps), the deep detector, 1e9
+    windowed histories with seed 51 in the history form.  2000 sampled
+    histories (and the first and last) are recomputed by the oracle with the
+    same window table: per-history event, particle and termination records
+    bit-exact, per-history tracks and detector scores to the parity
+    tolerance; every history terminates and the counts add up."""
+    from gpu_common import compare_sampled
+    from paper_2305_07636_amd import learned_ww as lw
+
+    p = w.cfg5_dogleg()
+    table, info = lw.learned_windows(p, n_pilot=100_000_000, seed=1000)
+    print(f"[lww 1e9] table cells with a window: {(table > 0).sum()}", flush=True)
+    out = compare_sampled(p, 1_000_000_000, 51, "history", n_sample=2000, sample_seed=9,
+                          ww={"centers": table})
+    assert out["splits"] > 0

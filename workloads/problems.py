@@ -41,6 +41,10 @@ Problem dict schema (all floats are float64, all ints int32):
     pins      None or dict: radius [nz, ny, nx] (a cylinder parallel to z
               centred in each geometry cell's x-y rectangle, 0 = none) and
               material [nz, ny, nx] (the material inside it)
+    rod       None or dict: z [K+1] heights of a plane normal to z at the
+              time edges (linear in time between them) and material
+              [nz, ny, nx] (the material above the plane in each geometry
+              cell, -1 = the cell's own material on both sides)
     ww_mesh   None or list of 3 arrays of weight-window mesh planes
 
 The workload recipes follow the transport problems the method is exercised
@@ -120,6 +124,7 @@ def make_problem(sigma_t, sigma_s, speed, planes, material, bc, source, tally,
         "fission": None,
         "implicit_capture": None,
         "pins": None,
+        "rod": None,
     }
     if fission is not None:
         p["fission"] = {k: _f64(fission[k]).reshape(M, G) for k in ("sigma_f", "nu", "chi")}
@@ -458,6 +463,55 @@ def void_box(size=(3.0, 2.0, 1.0), n_mesh=(3, 2, 1), src_point=(0.5, 0.5, 0.5),
                         np.zeros((1, 1, 1)), bc if bc is not None else [VACUUM] * 6,
                         src, {"mesh": mesh, "time_edges": time_edges,
                               "n_batches": 8})
+
+
+def rod_beam_box(sigma_rod=0.2, length=10.0, height=10.0, t_move=10.0, void_rod=False, n_batches=16):
+    """Void box [0, L] x [0, 1] x [0, H] with an absorbing rod that descends:
+    the moving plane falls from z = H at t = 0 to z = 0 at t = t_move and
+    rests there until t = 2 t_move; above it the box is rod (a pure
+    absorber of Sigma = sigma_rod, or a second void material).  A beam
+    enters the x- face at a height and time uniform over [0, H] x [0, t_move],
+    speed 1: a particle at height z born at t_b is inside the rod along
+    min(L, t_b + z) of its path when L = H = t_move."""
+    st = [[0.0], [0.0 if void_rod else sigma_rod]]
+    ss = [[[0.0]], [[0.0]]]
+    planes = [np.array([0.0, length]), np.array([0.0, 1.0]), np.array([0.0, height])]
+    src = {"kind": "surface", "axis": 0, "sign": 1, "mu_law": "beam", "lo": [0.0, 0.0, 0.0],
+           "hi": [0.0, 1.0, height], "group_pmf": [1.0], "t_lo": 0.0, "t_hi": t_move}
+    tally = {"mesh": [np.linspace(0.0, length, 6), _empty(), np.linspace(0.0, height, 6)],
+             "time_edges": np.array([0.0, t_move, 2.0 * t_move]), "n_batches": n_batches}
+    p = make_problem(st, ss, [1.0], planes, np.zeros((1, 1, 1)), [VACUUM] * 6, src, tally)
+    p["rod"] = {"z": _f64([height, 0.0, 0.0]), "material": np.ones((1, 1, 1), dtype=np.int32)}
+    return p
+
+
+def rod_lattice(n=17, pitch=1.26, height=50.0, n_groups=7, gen_seed=3, rods_every=3, z_top=50.0,
+                z_bottom=10.0, n_z_bins=10, n_time_bins=20, t_end=20.0, t_insert=10.0, n_batches=32):
+    """The lattice workload with a bank of control rods inserted from the top
+    during the transient: every rods_every-th lattice cell in x and y holds a
+    rod of a third, strongly absorbing synthetic material whose tip (the
+    moving plane) descends from z_top at t = 0 to z_bottom at t = t_insert
+    and stays there; elsewhere the plane only bounds no material change."""
+    p = lattice(n=n, pitch=pitch, height=height, n_groups=n_groups, gen_seed=gen_seed, n_z_bins=n_z_bins,
+                n_time_bins=n_time_bins, t_end=t_end, n_batches=n_batches)
+    rng = SplitMix64(gen_seed + 7777)
+    G = n_groups
+    st_r = np.array([rng.uniform(1.5, 3.0) for _ in range(G)])
+    ss_r = np.zeros((G, G))
+    for g in range(G):
+        ss_r[g, g] = 0.1 * st_r[g]          # mostly absorbing
+    p["sigma_t"] = np.ascontiguousarray(np.concatenate([p["sigma_t"], st_r[None, :]], axis=0))
+    p["sigma_s"] = np.ascontiguousarray(np.concatenate([p["sigma_s"], ss_r[None, :, :]], axis=0))
+    rodm = np.full((1, n, n), -1, dtype=np.int32)
+    M = p["sigma_t"].shape[0]
+    for j in range(n):
+        for i in range(n):
+            if i % rods_every == rods_every // 2 and j % rods_every == rods_every // 2:
+                rodm[0, j, i] = M - 1
+    te = p["tally"]["time_edges"]
+    z = np.where(te < t_insert, z_top + (z_bottom - z_top) * te / t_insert, z_bottom)
+    p["rod"] = {"z": _f64(z), "material": rodm}
+    return p
 
 
 CONFIGS = {
