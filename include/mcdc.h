@@ -402,6 +402,32 @@ int mcdc_run(mcdc_problem *p, uint64_t n_histories, uint64_t seed,
              const mcdc_run_options *opt, mcdc_result *out);
 
 /*
+ * Allocation-free run, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments and results as mcdc_run in the history form,
+ * and the same kernels; every per-run device buffer (per-batch tally and
+ * leakage sums and their copies, detector sums, event counters, overflow
+ * flag, the persistent launch's work counter) lives in one static device
+ * array of MCDC_NOALLOC_SCRATCH_BYTES that the library holds on each GPU it
+ * runs on until the process ends.  The call allocates no device memory;
+ * its first call on a device looks up that GPU's copy of the array and
+ * creates two timing events.  Every call on one GPU shares that GPU's
+ * array: calls that overlap on one GPU (other threads, or streams not
+ * synchronised with each other) race.  Each call clears the part it uses.
+ * Requirements: opt->algorithm == MCDC_ALG_HISTORY; out->host_outputs == 0
+ * (device output arrays); no debug arrays, profile or population control;
+ * an analog problem (no weight windows, fission or implicit capture); a
+ * tally that fits: batches x tally doubles x 8 bytes plus the leakage sums
+ * within the array (the tally copies per batch are reduced to fit; a
+ * 17 x 17 x 10 x 7-group x 20-bin tally with 32 batches, 104 MB, still
+ * fits).  Otherwise MCDC_E_UNSUPPORTED with a message naming the limit;
+ * other errors as mcdc_run.
+ */
+#define MCDC_NOALLOC_SCRATCH_BYTES (128u * 1024u * 1024u)
+int mcdc_run_noalloc(mcdc_problem *p, uint64_t n_histories, uint64_t seed, const mcdc_run_options *opt,
+                     mcdc_result *out);
+
+/*
  * Batched solve: run n independent problems (any sizes, group counts and
  * history counts) together (Section 2 names both algorithm modes; the
  * batching is this library's).  Problem j runs n_hist[j] histories with

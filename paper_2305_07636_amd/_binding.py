@@ -23,7 +23,7 @@ MCDC_SRC_ISOTROPIC, MCDC_SRC_SURFACE = 0, 1
 MU_LAWS = {"beam": 0, "uniform": 1, "cosine": 2}
 
 EXPORTS = ["mcdc_problem_create", "mcdc_problem_destroy", "mcdc_problem_tally_shape",
-           "mcdc_run", "mcdc_run_batched", "mcdc_run_eigenvalue", "mcdc_set_weight_windows",
+           "mcdc_run", "mcdc_run_noalloc", "mcdc_run_batched", "mcdc_run_eigenvalue", "mcdc_set_weight_windows",
            "mcdc_last_error", "mcdc_mlp_create",
            "mcdc_mlp_destroy", "mcdc_mlp_get_params", "mcdc_mlp_set_params", "mcdc_mlp_grad",
            "mcdc_mlp_train", "mcdc_mlp_infer"]
@@ -106,6 +106,8 @@ def lib():
         L.mcdc_run.argtypes = [C.c_void_p, C.c_uint64, C.c_uint64, C.POINTER(mcdc_run_options),
                                C.POINTER(mcdc_result)]
         L.mcdc_run.restype = C.c_int
+        L.mcdc_run_noalloc.argtypes = L.mcdc_run.argtypes
+        L.mcdc_run_noalloc.restype = C.c_int
         L.mcdc_set_weight_windows.argtypes = [C.c_void_p, _DP, C.c_double, C.c_int32]
         L.mcdc_set_weight_windows.restype = C.c_int
         L.mcdc_last_error.argtypes = []
@@ -263,7 +265,7 @@ def mcdc_run(p: Problem, n_histories: int, seed: int, algorithm: str = "event",
              debug: bool = False, outputs=("mean", "var", "raw", "leak_mean", "leak_var"),
              profile=None, eager: bool = False, profile_classes=None, profile_every: int = 0,
              profile_phase: int = 0, two_kernel_step: bool = False, pc_target: int = 0,
-             sort_cadence: int = 0):
+             noalloc: bool = False, sort_cadence: int = 0):
     """Run n_histories through the GPU tracker.  Returns a dict of torch
     CUDA tensors (mean, var, raw [K, G, nz, ny, nx]; leak_mean, leak_var
     [K, G, 6]; tc_mean, tc_var [K, G, nz, ny, nx] for a problem with the
@@ -273,7 +275,9 @@ def mcdc_run(p: Problem, n_histories: int, seed: int, algorithm: str = "event",
     profile: optional float64 array [8, 4] that accumulates per kernel class
     (ms, launches, particles, algorithmic bytes).
     pc_target: population control at every census edge (splitting-roulette
-    to that many particles; event form; 0 = off)."""
+    to that many particles; event form; 0 = off).
+    noalloc: call mcdc_run_noalloc (history form, device outputs, no
+    debug arrays or profile) instead of mcdc_run."""
     import torch
 
     dev = torch.device("cuda", torch.cuda.current_device())
@@ -313,7 +317,8 @@ def mcdc_run(p: Problem, n_histories: int, seed: int, algorithm: str = "event",
             opt.profile_mask = sum(1 << PROF_CLASSES.index(c) for c in profile_classes)
         opt.profile_every = profile_every
         opt.profile_phase = profile_phase
-    _check(lib().mcdc_run(p.handle, int(n_histories), int(seed), C.byref(opt), C.byref(res)))
+    run = lib().mcdc_run_noalloc if noalloc else lib().mcdc_run
+    _check(run(p.handle, int(n_histories), int(seed), C.byref(opt), C.byref(res)))
     out["events"] = np.array(res.n_events[:], dtype=np.uint64)
     out["terms"] = np.array(res.n_term[:], dtype=np.uint64)
     out["splits"] = int(res.n_splits)
