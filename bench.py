@@ -246,6 +246,24 @@ def population_control_section(m, w, n, steps, cpu=True):
                 res["rouletted_per_history"] = float(out["terms"][4]) / n
             log(f"population control {tag}: {dt * 1e3:.1f} ms per run")
         res["last_bin_fom_gain"] = res["controlled_last_bin_fom"] / res["analog_last_bin_fom"]
+        # the controlled batches share the weight w_t of every edge, so the
+        # batch variance is not that of independent batches: the relative
+        # error of one run from the spread of independent replicas instead
+        reps = 16
+        for tag, kw in (("analog", {}), ("controlled", {"pc_target": n})):
+            xs = []
+            t0 = time.perf_counter()
+            for r in range(reps):
+                out = m.mcdc_run(h, n, 300 + r, outputs=("mean",), **kw)
+                xs.append(float(out["mean"][-1].sum().item()))
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / reps
+            xs = np.array(xs)
+            rel = float(xs.std(ddof=1) / xs.mean())
+            res[f"{tag}_last_bin_rel_err_replicas"] = rel
+            res[f"{tag}_last_bin_fom_replicas"] = float(1.0 / (rel * rel * dt))
+        res["replicas"] = reps
+        res["last_bin_fom_gain_replicas"] = res["controlled_last_bin_fom_replicas"] / res["analog_last_bin_fom_replicas"]
         prof = np.zeros((len(m._binding.PROF_CLASSES), 4))
         m.mcdc_run(h, n, 99, outputs=("mean",), pc_target=n, profile=prof, profile_classes=["events", "control"])
         torch.cuda.synchronize()
@@ -514,6 +532,101 @@ def timed_runs(m, p, N, seed, steps, warmup, alg, traffic_file=None, label="slab
             "last": last}
 
 
+def sort_section(m, w, n_lattice, steps):
+    """The event form's queue sort (two-kernel step, queues reordered by
+    event, material, group and cell every c-th census step) against the
+    unsorted two-kernel step and the default one-kernel step: the 1e8
+    lattice and the 256-problem batch with each step form forced."""
+    import torch
+
+    forms = [("one_kernel", {"sort_cadence": -1}), ("two_kernel", {"two_kernel_step": True, "sort_cadence": -1})] + \
+        [(f"sorted_every_{c}", {"sort_cadence": c}) for c in (1, 2, 4, 8)]
+    res = {"lattice_histories": n_lattice}
+    h = m.mcdc_problem_create(w.cfg3_lattice())
+    try:
+        for tag, kw in forms:
+            m.mcdc_run(h, n_lattice, 3, outputs=("mean",), **kw)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for s in range(steps):
+                m.mcdc_run(h, n_lattice, 3 + s, outputs=("mean",), **kw)
+            torch.cuda.synchronize()
+            res[f"lattice_{tag}_ms"] = (time.perf_counter() - t0) / steps * 1e3
+            log(f"sort: lattice {tag} {res[f'lattice_{tag}_ms']:.2f} ms")
+    finally:
+        h.close()
+    probs, nh = w.cfg4_batch()
+    seeds = [2000 + j for j in range(len(probs))]
+    hs = [m.mcdc_problem_create(p) for p in probs]
+    try:
+        for tag, kw in forms:
+            for L in (8192, 32768):
+                m.mcdc_run_batched(hs, nh, seeds, seg_len=L, **kw)      # tail switch tuned and cached
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                m.mcdc_run_batched(hs, nh, seeds, seg_len=L, **kw)
+                torch.cuda.synchronize()
+                res[f"batched_{tag}_seg{L}_s"] = time.perf_counter() - t0
+            log(f"sort: batched {tag} {res[f'batched_{tag}_seg8192_s']:.3f} / {res[f'batched_{tag}_seg32768_s']:.3f} s")
+    finally:
+        for x in hs:
+            x.close()
+    return res
+
+
+def rods_section(m, w, n, steps):
+    """A control-rod transient on the lattice workload: the rod bank's tip
+    (a moving plane normal to z) descends from z = 50 to z = 10 over the
+    first 10 of the 20 time units in every third lattice cell; both forms,
+    against the same lattice without rods."""
+    import torch
+
+    res = {"workload": "17x17 lattice (7 groups, 17x17x10x20 tally) with a rod bank in every third cell whose tip "
+                       f"falls from z=50 to z=10 over t in [0,10]; {n:.0e} histories"}
+    for tag, prob in (("rodded", w.rod_lattice()), ("unrodded", w.cfg3_lattice())):
+        h = m.mcdc_problem_create(prob)
+        try:
+            for alg in ("event", "history"):
+                out = m.mcdc_run(h, n, 40, algorithm=alg, outputs=("mean",))
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for s in range(steps):
+                    out = m.mcdc_run(h, n, 41 + s, algorithm=alg, outputs=("mean",))
+                torch.cuda.synchronize()
+                dt = (time.perf_counter() - t0) / steps
+                res[f"{tag}_{alg}_histories_per_s"] = n / dt
+                res[f"{tag}_{alg}_ms"] = dt * 1e3
+            res[f"{tag}_events_per_history"] = [float(x) / n for x in out["events"]]
+            res[f"{tag}_absorbed_fraction"] = float(out["terms"][0]) / n
+        finally:
+            h.close()
+        log(f"rods: {tag} event {res[f'{tag}_event_ms']:.2f} ms, history {res[f'{tag}_history_ms']:.2f} ms")
+    return res
+
+
+def block_section(m, w, n_slab, n_lattice, steps):
+    """The event form's census-step kernels at workgroup sizes 256, 512
+    and 1024 on the pulsed slab and the lattice."""
+    import torch
+
+    res = {}
+    for tag, prob, n in (("slab", w.cfg2_slab_pulse(), n_slab), ("lattice", w.cfg3_lattice(), n_lattice)):
+        h = m.mcdc_problem_create(prob)
+        try:
+            for bs in (256, 512, 1024):
+                m.mcdc_run(h, n, 2, outputs=("mean",), block_size=bs)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for s in range(steps):
+                    m.mcdc_run(h, n, 2 + s, outputs=("mean",), block_size=bs)
+                torch.cuda.synchronize()
+                res[f"{tag}_block{bs}_ms"] = (time.perf_counter() - t0) / steps * 1e3
+            log(f"block: {tag} " + " ".join(f"{bs}: {res[f'{tag}_block{bs}_ms']:.2f}" for bs in (256, 512, 1024)))
+        finally:
+            h.close()
+    return res
+
+
 def lattice_section(m, w, n, steps, warmup):
     """The 17 x 17 lattice (2 materials, 7 groups, reflective x-y, vacuum z,
     17 x 17 x 10 x 7 x 20 = 404 600 tally bins, pulse at t = 0) at 1e8
@@ -567,6 +680,9 @@ def main():
     ap.add_argument("--no-pins", action="store_true")
     ap.add_argument("--no-pc", action="store_true")
     ap.add_argument("--no-lattice", action="store_true")
+    ap.add_argument("--no-sort", action="store_true")
+    ap.add_argument("--no-rods", action="store_true")
+    ap.add_argument("--no-block", action="store_true")
     ap.add_argument("--lattice-histories", type=float, default=1e8)
     ap.add_argument("--eigen-per-cycle", type=float, default=1e5)
     ap.add_argument("--fission-histories", type=float, default=1e6)
@@ -662,6 +778,12 @@ def main():
     p.close()
     if not args.no_lattice:
         extra["lattice"] = lattice_section(m, w, int(args.lattice_histories), args.steps, args.warmup)
+    if not args.no_rods:
+        extra["moving_plane"] = rods_section(m, w, int(args.histories), args.steps)
+    if not args.no_block:
+        extra["block_size"] = block_section(m, w, int(args.histories), int(args.lattice_histories), min(args.steps, 3))
+    if not args.no_sort:
+        extra["queue_sort"] = sort_section(m, w, int(args.lattice_histories), min(args.steps, 3))
     if not args.no_fission:
         extra["fission"] = fission_section(m, w, int(args.fission_histories), args.steps)
     if not args.no_eigen:

@@ -214,10 +214,12 @@ typedef struct {
  *                 for a history count (results of the history-form run)
  *                 and keeps the faster on the problem handle; batched
  *                 solves keep it per batch signature.
- *  block_size     mcdc_run_batched: threads per block of the persistent
- *                 launch (64..1024, multiple of 64; 0 = autotuned).  The
- *                 kernels of mcdc_run use 256 (history form) and 512
- *                 (event form).
+ *  block_size     threads per workgroup.  mcdc_run, event form: the
+ *                 census-step kernels' 256, 512 or 1024 (0 = 512; weighted
+ *                 runs and population control take 512 only); the history
+ *                 form always uses 256.  mcdc_run_batched: the history
+ *                 form's persistent launch 64, 128, 256 or 512, the event
+ *                 form's step kernels 256, 512 or 1024 (0 = autotuned).
  *  bank_capacity  event form: particles resident at once (0 = auto).  Work
  *                 is processed in chunks of this many histories.  In
  *                 mcdc_run_batched's event form: slots per bank segment.
@@ -443,11 +445,12 @@ int mcdc_run_noalloc(mcdc_problem *p, uint64_t n_histories, uint64_t seed, const
  *    first call for a batch signature (problem shapes, history counts and
  *    the forcing options) and reused: the segment length (queue capacity
  *    per workgroup; opt->bank_capacity, 256..2^24, else tuned over {2048,
- *    8192, 32768, 65536}), then the census step's form (one kernel; two
- *    kernels; two kernels with the queue sort every 1, 2, 4 or 8 steps;
- *    forced by opt->sort_cadence or MCDC_FLAG_TWO_KERNEL_STEP), then the
- *    tail threshold {0, 2e4, 1e5}, each at the best of the ones before,
- *    timing whole runs of the batch.  At most 2^28 histories and 65535
+ *    8192, 32768, 65536}), then the step kernels' workgroup size {256,
+ *    512, 1024} (opt->block_size), then the census step's form (one
+ *    kernel; two kernels; two kernels with the queue sort every 1, 2, 4 or
+ *    8 steps; forced by opt->sort_cadence or MCDC_FLAG_TWO_KERNEL_STEP),
+ *    then the tail threshold {0, 2e4, 1e5}, each at the best of the ones
+ *    before, timing whole runs of the batch.  At most 2^28 histories and 65535
  *    time bins per problem.
  *  MCDC_ALG_HISTORY: one persistent launch; a fixed grid of workgroups
  *    pulls chunks of histories from one device-wide counter over the

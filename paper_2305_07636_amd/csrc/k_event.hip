@@ -37,6 +37,7 @@
 // edges, cross sections, speeds, per-cell material and tally bin) are
 // copied into LDS at the start of each step kernel when they fit, so the
 // dependent table lookups of a flight cost LDS latency, not cache latency.
+#include <type_traits>
 #include <vector>
 
 #include "k_common.hpp"
@@ -350,21 +351,23 @@ struct StepScore {
     }
 };
 
+template <int BS = kBlock>
 __device__ __forceinline__ void init_slice(const DevProblem &P, StepScore &sc, double *lt, int gn, int b0) {
     sc.lt = lt;
     sc.gn = gn;
     sc.b0 = b0;
     sc.scored = false;
-    for (int j = threadIdx.x; j < slice_mult(P) * gn; j += kBlock) lt[j] = 0.0;
+    for (int j = threadIdx.x; j < slice_mult(P) * gn; j += BS) lt[j] = 0.0;
 }
 
 // End of a scoring kernel: add the workgroup's slice into the tally (one
 // atomic per nonzero bin).  Contains the barrier the counter flush needs.
+template <int BS = kBlock>
 __device__ __forceinline__ void flush_slice(const DevProblem &P, const RunArgs &R, const StepScore &sc, int step) {
     const int any = __syncthreads_or(sc.scored ? 1 : 0);
     if (!sc.gn || !any) return;
     const int per_part = 2 * sc.gn;
-    for (int j = threadIdx.x; j < slice_mult(P) * sc.gn; j += kBlock) {
+    for (int j = threadIdx.x; j < slice_mult(P) * sc.gn; j += BS) {
         const double v = sc.lt[j];
         const int part = j / per_part, r = j % per_part;
         const int b = sc.b0 + r / sc.gn;
@@ -403,8 +406,8 @@ __device__ __forceinline__ void score_flight(const DevProblem &P, const RunArgs 
 // (BAT: a batched solve; segment b belongs to problem segs[b].prob and is
 // born with its histories [first, first + count), items holds every
 // problem's tables and run arguments.)
-template <int FM, bool WW, bool BAT, int CLS = MCDC_PROF_SOURCE>
-__global__ void __launch_bounds__(kBlock) k_source(DevProblem P0, RunArgs R0, Bank bank, Ctl C, uint64_t count,
+template <int FM, bool WW, bool BAT, int CLS = MCDC_PROF_SOURCE, int BS = kBlock>
+__global__ void __launch_bounds__(BS) k_source(DevProblem P0, RunArgs R0, Bank bank, Ctl C, uint64_t count,
                                                    const BatchItem *__restrict__ items,
                                                    const SegInfo *__restrict__ segs) {
     __shared__ unsigned long long red[kCounters + 2];
@@ -422,7 +425,7 @@ __global__ void __launch_bounds__(kBlock) k_source(DevProblem P0, RunArgs R0, Ba
     if (threadIdx.x == 0)
         C.seg_b0[seg] = (lo < hi) ? (int)(((first + lo + 1) * (uint64_t)R.B - 1) / R.N) : 0;
     __syncthreads();
-    for (uint64_t base = lo; base < hi; base += kBlock) {
+    for (uint64_t base = lo; base < hi; base += BS) {
         const uint64_t r = base + threadIdx.x;
         const bool valid = r < hi;
         Particle p;
@@ -452,8 +455,8 @@ __global__ void __launch_bounds__(kBlock) k_source(DevProblem P0, RunArgs R0, Ba
 // ---------------------------------------------------------------------------
 enum Outcome : int { kNone = 0, kToNext = 1, kToSurface = 2, kToCollision = 3 };
 
-template <int FM, bool WW, bool LT, bool BAT, int CLS = MCDC_PROF_ADVANCE>
-__global__ void __launch_bounds__(kBlock) k_advance(DevProblem P0, RunArgs R0, Bank cur, Bank next, Bank ev, Ctl C,
+template <int FM, bool WW, bool LT, bool BAT, int CLS = MCDC_PROF_ADVANCE, int BS = kBlock>
+__global__ void __launch_bounds__(BS) k_advance(DevProblem P0, RunArgs R0, Bank cur, Bank next, Bank ev, Ctl C,
                                                     int par, int gn0, SplitBank SB, LdsTables tabs0,
                                                     const BatchItem *__restrict__ items,
                                                     const SegInfo *__restrict__ segs) {
@@ -478,15 +481,15 @@ __global__ void __launch_bounds__(kBlock) k_advance(DevProblem P0, RunArgs R0, B
     }
     StepScore sc;
     const DevProblem &Pin = BAT ? items[prob].P : P0;
-    init_slice(Pin, sc, lt, gn, C.seg_b0[seg]);
-    const DevProblem P = stage_tables<LT, kBlock>(Pin, BAT ? items[prob].tabs : tabs0,
+    init_slice<BS>(Pin, sc, lt, gn, C.seg_b0[seg]);
+    const DevProblem P = stage_tables<LT, BS>(Pin, BAT ? items[prob].tabs : tabs0,
                                                   reinterpret_cast<char *>(lt + slice_mult(Pin) * gn));
     __syncthreads();
     // software pipeline: the next particle's state is in flight while the
     // current one is moved
     RawState nx;
     if (threadIdx.x < n) load_raw<FM, WW>(P, cur, seg0 + threadIdx.x, nx);
-    for (unsigned int j0 = 0; j0 < n; j0 += kBlock) {
+    for (unsigned int j0 = 0; j0 < n; j0 += BS) {
         const unsigned int idx = j0 + threadIdx.x;
         const bool valid = idx < n;
         int outcome = kNone;
@@ -494,7 +497,7 @@ __global__ void __launch_bounds__(kBlock) k_advance(DevProblem P0, RunArgs R0, B
         Particle p;
         uint32_t gk = 0, hid = 0;
         const RawState rs = nx;
-        if (idx + kBlock < n) load_raw<FM, WW>(P, cur, seg0 + idx + kBlock, nx);
+        if (idx + BS < n) load_raw<FM, WW>(P, cur, seg0 + idx + BS, nx);
         if (valid) {
             unpack<FM, WW>(P, rs, p);
             gk = rs.gk;
@@ -548,7 +551,7 @@ __global__ void __launch_bounds__(kBlock) k_advance(DevProblem P0, RunArgs R0, B
         if (R.prof && valid)
             cnt.prof(1u, state_bytes<FM, WW>(P) * (outcome == kNone ? 1u : 2u));
     }
-    flush_slice(P, R, sc, step);
+    flush_slice<BS>(P, R, sc, step);
     if (threadIdx.x == 0) {
         C.n_bank[(par ^ 1) * C.G + seg] = cN;
         C.n_s[seg] = cS;
@@ -572,8 +575,8 @@ __global__ void __launch_bounds__(kBlock) k_advance(DevProblem P0, RunArgs R0, B
 // born in a later time bin pass straight on to the next bank.)
 // (Two-kernel step with a queue sort at this step: both queues are read
 // from the front of the sorted event bank srt, surface entries first.)
-template <int FM, bool WW, bool LT, bool BAT, int CLS = MCDC_PROF_EVENTS, bool STEP = false>
-__global__ void __launch_bounds__(kBlock) k_event(DevProblem P0, RunArgs R0, Bank ev, Bank next, Ctl C, int par,
+template <int FM, bool WW, bool LT, bool BAT, int CLS = MCDC_PROF_EVENTS, bool STEP = false, int BS = kBlock>
+__global__ void __launch_bounds__(BS) k_event(DevProblem P0, RunArgs R0, Bank ev, Bank next, Ctl C, int par,
                                                   int gn0, SplitBank SB, LdsTables tabs0,
                                                   const BatchItem *__restrict__ items,
                                                   const SegInfo *__restrict__ segs, Bank srt, int cadence) {
@@ -600,8 +603,8 @@ __global__ void __launch_bounds__(kBlock) k_event(DevProblem P0, RunArgs R0, Ban
     }
     StepScore sc;
     const DevProblem &Pin = BAT ? items[prob].P : P0;
-    init_slice(Pin, sc, lt, gn, C.seg_b0[seg]);
-    const DevProblem P = stage_tables<LT, kBlock>(Pin, BAT ? items[prob].tabs : tabs0,
+    init_slice<BS>(Pin, sc, lt, gn, C.seg_b0[seg]);
+    const DevProblem P = stage_tables<LT, BS>(Pin, BAT ? items[prob].tabs : tabs0,
                                                   reinterpret_cast<char *>(lt + slice_mult(Pin) * gn));
     __syncthreads();
 
@@ -728,7 +731,7 @@ __global__ void __launch_bounds__(kBlock) k_event(DevProblem P0, RunArgs R0, Ban
             if (R.prof) cnt.prof(0u, state_bytes<FM, WW>(P));
         }
     }
-    flush_slice(P, R, sc, step);
+    flush_slice<BS>(P, R, sc, step);
     if (threadIdx.x == 0) C.n_bank[(par ^ 1) * C.G + seg] = cN;
     cnt.flush(R, CLS, red);
 }
@@ -747,7 +750,6 @@ __global__ void __launch_bounds__(kBlock) k_event(DevProblem P0, RunArgs R0, Ban
 // of the LDS atomics; per-history results do not depend on it (each
 // particle draws from its own stream), tallies only by summation order.
 constexpr int kSortBuckets = 512;
-static_assert(kSortBuckets == kBlock, "the bucket prefix takes one bucket per thread");
 
 template <int FM>
 __device__ __forceinline__ int sort_bucket(const DevProblem &P, uint32_t c, uint32_t gk, int queue) {
@@ -767,8 +769,8 @@ __device__ __forceinline__ int sort_bucket(const DevProblem &P, uint32_t c, uint
     return queue * 256 + sub;
 }
 
-template <int FM, bool WW, bool BAT, int CLS = MCDC_PROF_SORT>
-__global__ void __launch_bounds__(kBlock) k_sort_events(DevProblem P0, RunArgs R0, Bank ev, Bank srt, Ctl C,
+template <int FM, bool WW, bool BAT, int CLS = MCDC_PROF_SORT, int BS = kBlock>
+__global__ void __launch_bounds__(BS) k_sort_events(DevProblem P0, RunArgs R0, Bank ev, Bank srt, Ctl C,
                                                         int cadence, const BatchItem *__restrict__ items,
                                                         const SegInfo *__restrict__ segs) {
     const int step = *C.step;
@@ -777,8 +779,9 @@ __global__ void __launch_bounds__(kBlock) k_sort_events(DevProblem P0, RunArgs R
     const DevProblem &P = BAT ? items[prob].P : P0;
     const RunArgs &R = BAT ? items[prob].R : R0;
     __shared__ unsigned long long red[kCounters + 2];
+    constexpr int PER = (kSortBuckets + BS - 1) / BS;   // buckets per thread in the prefix
     __shared__ unsigned int off[kSortBuckets];
-    __shared__ unsigned int wsum[kBlock / 64];
+    __shared__ unsigned int wsum[BS / 64];
     Counters cnt;
     cnt.init(red);
     const unsigned int seg = blockIdx.x;
@@ -786,9 +789,9 @@ __global__ void __launch_bounds__(kBlock) k_sort_events(DevProblem P0, RunArgs R
     const uint32_t seg_end = seg0 + C.L - 1;
     const unsigned int n_s = C.n_s[seg];
     const unsigned int n = n_s + C.n_c[seg];
-    off[threadIdx.x] = 0u;
+    for (int j = threadIdx.x; j < kSortBuckets; j += BS) off[j] = 0u;
     __syncthreads();
-    for (unsigned int w = threadIdx.x; w < n; w += kBlock) {
+    for (unsigned int w = threadIdx.x; w < n; w += BS) {
         const uint32_t slot = (w < n_s) ? seg0 + w : seg_end - (w - n_s);
         const uint64_t o4 = tile_off4(ev, slot);
         atomicAdd(&off[sort_bucket<FM>(P, fld<uint32_t>(ev, ev.oc, o4), fld<uint32_t>(ev, ev.ogk, o4),
@@ -796,9 +799,17 @@ __global__ void __launch_bounds__(kBlock) k_sort_events(DevProblem P0, RunArgs R
                   1u);
     }
     __syncthreads();
-    // exclusive prefix over the buckets: within each wave by shuffles,
-    // then the totals of the waves before
-    const unsigned int v = off[threadIdx.x];
+    // exclusive prefix over the buckets: each thread sums PER consecutive
+    // buckets, a prefix of those sums within each wave by shuffles, then
+    // the totals of the waves before
+    unsigned int mine[PER];
+    unsigned int v = 0u;
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int j = (int)threadIdx.x * PER + q;
+        mine[q] = (j < kSortBuckets) ? off[j] : 0u;
+        v += mine[q];
+    }
     unsigned int inc = v;
     for (int o = 1; o < 64; o <<= 1) {
         const unsigned int t = __shfl_up(inc, o);
@@ -808,9 +819,15 @@ __global__ void __launch_bounds__(kBlock) k_sort_events(DevProblem P0, RunArgs R
     __syncthreads();
     unsigned int base = 0u;
     for (unsigned int k = 0; k < (threadIdx.x >> 6); ++k) base += wsum[k];
-    off[threadIdx.x] = base + inc - v;
+    base += inc - v;
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int j = (int)threadIdx.x * PER + q;
+        if (j < kSortBuckets) off[j] = base;
+        base += mine[q];
+    }
     __syncthreads();
-    for (unsigned int w = threadIdx.x; w < n; w += kBlock) {
+    for (unsigned int w = threadIdx.x; w < n; w += BS) {
         const uint32_t slot = (w < n_s) ? seg0 + w : seg_end - (w - n_s);
         RawState r;
         load_raw<FM, WW>(P, ev, slot, r);
@@ -1237,7 +1254,8 @@ void key_add(std::vector<char> &k, const T &v) {
 // counts that are not a multiple of the CU count: 10-20 % slower).
 constexpr int kSegmentsPerCU = 2;
 
-template <int FM, bool WW, bool LT>
+// (BS: workgroup size of the step kernels; weighted runs use kBlock)
+template <int FM, bool WW, bool LT, int BS>
 int run_event(mcdc_problem *pb, const RunArgs &R0, uint64_t first, uint64_t count, const mcdc_run_options &opt,
               hipStream_t st, Profiler &prof, const LdsTables &tabs) {
     const DevProblem &P = pb->d;
@@ -1268,14 +1286,16 @@ int run_event(mcdc_problem *pb, const RunArgs &R0, uint64_t first, uint64_t coun
     } else {
         int per_cu = 0, n_cu = 0;
         hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &per_cu, reinterpret_cast<const void *>(&k_advance<FM, WW, LT, false>), kBlock, shmem);
+            &per_cu, reinterpret_cast<const void *>(&k_advance<FM, WW, LT, false, MCDC_PROF_ADVANCE, BS>), BS, shmem);
         if (e == hipSuccess) e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, pb->device);
         if (e != hipSuccess) return hip_fail(e, "occupancy query");
         if (per_cu < 1) per_cu = 1;
-        if (per_cu > kSegmentsPerCU) per_cu = kSegmentsPerCU;
+        // (as many waves per CU as two 512-thread workgroups)
+        const int cap = kSegmentsPerCU * kBlock / BS;
+        if (per_cu > cap) per_cu = cap;
         G = (unsigned int)per_cu * (unsigned int)(n_cu > 0 ? n_cu : 1);
     }
-    const uint64_t g_need = (C + kBlock - 1) / kBlock;
+    const uint64_t g_need = (C + BS - 1) / BS;
     if (G > g_need) G = (unsigned int)g_need;
     if (G < 1) G = 1;
     // (segments are whole tiles of 64 slots; with population control a
@@ -1318,17 +1338,20 @@ int run_event(mcdc_problem *pb, const RunArgs &R0, uint64_t first, uint64_t coun
         const Bank &cur = L.bank[par];
         const Bank &nxt = L.bank[par ^ 1];
         if (one_kernel) {
-            launch_timed(pr, MCDC_PROF_EVENTS, k_event<FM, WW, LT, false, MCDC_PROF_EVENTS, true>, dim3(G),
-                         dim3(kBlock), (uint32_t)shmem, s, P, Ra, cur, nxt, L.ctl, par, gn, SB[0], tabs,
+            launch_timed(pr, MCDC_PROF_EVENTS, k_event<FM, WW, LT, false, MCDC_PROF_EVENTS, true, BS>, dim3(G),
+                         dim3(BS), (uint32_t)shmem, s, P, Ra, cur, nxt, L.ctl, par, gn, SB[0], tabs,
                          (const BatchItem *)nullptr, (const SegInfo *)nullptr, L.srt, 0);
         } else {
-            launch_timed(pr, MCDC_PROF_ADVANCE, k_advance<FM, WW, LT, false>, dim3(G), dim3(kBlock), (uint32_t)shmem,
+            launch_timed(pr, MCDC_PROF_ADVANCE, k_advance<FM, WW, LT, false, MCDC_PROF_ADVANCE, BS>, dim3(G), dim3(BS),
+                         (uint32_t)shmem,
                          s, P, Ra, cur, nxt, L.ev, L.ctl, par, gn, SB[0], tabs, (const BatchItem *)nullptr,
                          (const SegInfo *)nullptr);
             if (cadence)
-                launch_timed(pr, MCDC_PROF_SORT, k_sort_events<FM, WW, false>, dim3(G), dim3(kBlock), 0u, s, P, Ra,
+                launch_timed(pr, MCDC_PROF_SORT, k_sort_events<FM, WW, false, MCDC_PROF_SORT, BS>, dim3(G), dim3(BS), 0u, s,
+                             P, Ra,
                              L.ev, L.srt, L.ctl, cadence, (const BatchItem *)nullptr, (const SegInfo *)nullptr);
-            launch_timed(pr, MCDC_PROF_EVENTS, k_event<FM, WW, LT, false>, dim3(G), dim3(kBlock), (uint32_t)shmem, s,
+            launch_timed(pr, MCDC_PROF_EVENTS, k_event<FM, WW, LT, false, MCDC_PROF_EVENTS, false, BS>, dim3(G), dim3(BS),
+                         (uint32_t)shmem, s,
                          P, Ra, L.ev, nxt, L.ctl, par, gn, SB[0], tabs, (const BatchItem *)nullptr,
                          (const SegInfo *)nullptr, L.srt, cadence);
         }
@@ -1400,7 +1423,8 @@ int run_event(mcdc_problem *pb, const RunArgs &R0, uint64_t first, uint64_t coun
         hipLaunchKernelGGL(k_ctl_init, dim3(1), dim3(1), 0, st, L.ctl, cfirst);
         if (P.qoi_on && (rc = launch_zero(R.qoi_hist, n * sizeof(double), st))) return hip_fail((hipError_t)rc, "zero");
         if (WW) split_reset(SB, st);
-        launch_timed(prof, MCDC_PROF_SOURCE, k_source<FM, WW, false>, dim3(G), dim3(kBlock), 0u, st, P, R, L.bank[0],
+        launch_timed(prof, MCDC_PROF_SOURCE, k_source<FM, WW, false, MCDC_PROF_SOURCE, BS>, dim3(G), dim3(BS), 0u, st, P, R,
+                     L.bank[0],
                      L.ctl, n, (const BatchItem *)nullptr, (const SegInfo *)nullptr);
         for (int step = 0; step < P.K;) {
             const bool sampled = opt.profile && step % every == opt.profile_phase % every;
@@ -1432,11 +1456,23 @@ int run_event(mcdc_problem *pb, const RunArgs &R0, uint64_t first, uint64_t coun
     return MCDC_OK;
 }
 
+template <int FM, bool WW, int BS>
+int run_event_bs(mcdc_problem *p, const RunArgs &R, uint64_t first, uint64_t count, const mcdc_run_options &opt,
+                 hipStream_t st, Profiler &prof, const LdsTables &tabs, bool lt) {
+    return lt ? run_event<FM, WW, true, BS>(p, R, first, count, opt, st, prof, tabs)
+              : run_event<FM, WW, false, BS>(p, R, first, count, opt, st, prof, tabs);
+}
+
+// The step kernels' workgroup size: opt.block_size 256 or 1024 for analog
+// runs, else 512 (weighted runs and population control always 512).
 template <int FM, bool WW>
 int run_event_lt(mcdc_problem *p, const RunArgs &R, uint64_t first, uint64_t count, const mcdc_run_options &opt,
                  hipStream_t st, Profiler &prof, const LdsTables &tabs, bool lt) {
-    return lt ? run_event<FM, WW, true>(p, R, first, count, opt, st, prof, tabs)
-              : run_event<FM, WW, false>(p, R, first, count, opt, st, prof, tabs);
+    if constexpr (!WW) {
+        if (opt.block_size == 256) return run_event_bs<FM, WW, 256>(p, R, first, count, opt, st, prof, tabs, lt);
+        if (opt.block_size == 1024) return run_event_bs<FM, WW, 1024>(p, R, first, count, opt, st, prof, tabs, lt);
+    }
+    return run_event_bs<FM, WW, kBlock>(p, R, first, count, opt, st, prof, tabs, lt);
 }
 
 // Batched solve: every problem's segments share one set of banks; each
@@ -1444,7 +1480,7 @@ int run_event_lt(mcdc_problem *p, const RunArgs &R, uint64_t first, uint64_t cou
 // problems) is captured once as a graph and replayed for the largest K.
 // (step < 0: one kernel per census step; 0: the two-kernel step; c >= 1:
 // the two-kernel step with the queue sort at every c-th census step)
-template <int FM, bool LT>
+template <int FM, bool LT, int BS>
 int run_batched_steps(const BatchItem *d_items, const SegInfo *d_segs, unsigned int G, unsigned int Lseg, int Kmax,
                       size_t shmem, void *bank_mem, void *ctl_mem, hipStream_t st, int step_form) {
     const uint64_t slots = (uint64_t)G * Lseg;
@@ -1454,7 +1490,7 @@ int run_batched_steps(const BatchItem *d_items, const SegInfo *d_segs, unsigned 
     const LdsTables t0{};
     const SplitBank none{};
     hipLaunchKernelGGL(k_ctl_init, dim3(1), dim3(1), 0, st, L.ctl, (uint64_t)0);
-    hipLaunchKernelGGL((k_source<FM, false, true>), dim3(G), dim3(kBlock), 0, st, P0, R0, L.bank[0], L.ctl,
+    hipLaunchKernelGGL((k_source<FM, false, true, MCDC_PROF_SOURCE, BS>), dim3(G), dim3(BS), 0, st, P0, R0, L.bank[0], L.ctl,
                        (uint64_t)0, d_items, d_segs);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "batched source launch");
@@ -1466,16 +1502,16 @@ int run_batched_steps(const BatchItem *d_items, const SegInfo *d_segs, unsigned 
         e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) break;
         if (step_form < 0) {
-            hipLaunchKernelGGL((k_event<FM, false, LT, true, MCDC_PROF_EVENTS, true>), dim3(G), dim3(kBlock), shmem,
+            hipLaunchKernelGGL((k_event<FM, false, LT, true, MCDC_PROF_EVENTS, true, BS>), dim3(G), dim3(BS), shmem,
                                cs, P0, R0, L.bank[q], L.bank[q ^ 1], L.ctl, q, 0, none, t0, d_items, d_segs, L.srt,
                                0);
         } else {
-            hipLaunchKernelGGL((k_advance<FM, false, LT, true>), dim3(G), dim3(kBlock), shmem, cs, P0, R0, L.bank[q],
+            hipLaunchKernelGGL((k_advance<FM, false, LT, true, MCDC_PROF_ADVANCE, BS>), dim3(G), dim3(BS), shmem, cs, P0, R0, L.bank[q],
                                L.bank[q ^ 1], L.ev, L.ctl, q, 0, none, t0, d_items, d_segs);
             if (step_form > 0)
-                hipLaunchKernelGGL((k_sort_events<FM, false, true>), dim3(G), dim3(kBlock), 0, cs, P0, R0, L.ev,
+                hipLaunchKernelGGL((k_sort_events<FM, false, true, MCDC_PROF_SORT, BS>), dim3(G), dim3(BS), 0, cs, P0, R0, L.ev,
                                    L.srt, L.ctl, step_form, d_items, d_segs);
-            hipLaunchKernelGGL((k_event<FM, false, LT, true>), dim3(G), dim3(kBlock), shmem, cs, P0, R0, L.ev,
+            hipLaunchKernelGGL((k_event<FM, false, LT, true, MCDC_PROF_EVENTS, false, BS>), dim3(G), dim3(BS), shmem, cs, P0, R0, L.ev,
                                L.bank[q ^ 1], L.ctl, q, 0, none, t0, d_items, d_segs, L.srt, step_form);
         }
         hipLaunchKernelGGL(k_step_end, dim3(1), dim3(1), 0, cs, L.ctl);
@@ -1520,7 +1556,7 @@ size_t event_batched_bytes(const uint64_t *n_hist, int n, unsigned int seg_len, 
 }
 
 int launch_event_batched(std::vector<BatchItem> &items, const uint64_t *n_hist, unsigned int seg_len, void *mem,
-                         size_t mem_bytes, hipStream_t st, int step_form) {
+                         size_t mem_bytes, hipStream_t st, int step_form, int block) {
     const int n = (int)items.size();
     const BatchedLayout lay = batched_layout(n_hist, n, seg_len, step_form > 0 ? 4 : 3);
     if (lay.bytes > mem_bytes) {
@@ -1563,14 +1599,22 @@ int launch_event_batched(std::vector<BatchItem> &items, const uint64_t *n_hist, 
     if (e != hipSuccess) return hip_fail(e, "batched tables");
     void *ctl = base + lay.ctl_off, *bank = base + lay.bank_off;
     const int sf = step_form;
-    if (fm == 1)
-        return lt_all ? run_batched_steps<1, true>(d_items, d_segs, lay.G, seg_len, Kmax, shmem, bank, ctl, st, sf)
-                      : run_batched_steps<1, false>(d_items, d_segs, lay.G, seg_len, Kmax, shmem, bank, ctl, st, sf);
-    if (fm == 7)
-        return lt_all ? run_batched_steps<7, true>(d_items, d_segs, lay.G, seg_len, Kmax, shmem, bank, ctl, st, sf)
-                      : run_batched_steps<7, false>(d_items, d_segs, lay.G, seg_len, Kmax, shmem, bank, ctl, st, sf);
-    return lt_all ? run_batched_steps<0, true>(d_items, d_segs, lay.G, seg_len, Kmax, shmem, bank, ctl, st, sf)
-                  : run_batched_steps<0, false>(d_items, d_segs, lay.G, seg_len, Kmax, shmem, bank, ctl, st, sf);
+    auto go = [&](auto bs_tag) -> int {
+        constexpr int BS = decltype(bs_tag)::value;
+        if (fm == 1)
+            return lt_all ? run_batched_steps<1, true, BS>(d_items, d_segs, lay.G, seg_len, Kmax, shmem, bank, ctl, st, sf)
+                          : run_batched_steps<1, false, BS>(d_items, d_segs, lay.G, seg_len, Kmax, shmem, bank, ctl, st,
+                                                            sf);
+        if (fm == 7)
+            return lt_all ? run_batched_steps<7, true, BS>(d_items, d_segs, lay.G, seg_len, Kmax, shmem, bank, ctl, st, sf)
+                          : run_batched_steps<7, false, BS>(d_items, d_segs, lay.G, seg_len, Kmax, shmem, bank, ctl, st,
+                                                            sf);
+        return lt_all ? run_batched_steps<0, true, BS>(d_items, d_segs, lay.G, seg_len, Kmax, shmem, bank, ctl, st, sf)
+                      : run_batched_steps<0, false, BS>(d_items, d_segs, lay.G, seg_len, Kmax, shmem, bank, ctl, st, sf);
+    };
+    if (block == 256) return go(std::integral_constant<int, 256>{});
+    if (block == 1024) return go(std::integral_constant<int, 1024>{});
+    return go(std::integral_constant<int, kBlock>{});
 }
 
 void destroy_graph_cache(mcdc_problem *p) {

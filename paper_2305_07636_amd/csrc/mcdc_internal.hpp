@@ -273,7 +273,8 @@ size_t event_batched_bytes(const uint64_t *n_hist, int n, unsigned int seg_len, 
 size_t eigen_bytes(uint64_t N);
 int launch_eigen(const DevProblem &P, const RunArgs &R, uint64_t N, int n_inactive, int n_active, uint64_t seed,
                  void *mem, uint64_t *m_dev, int *no_sites, unsigned long long *hist, hipStream_t st);
+// (block: the step kernels' workgroup size, 256, 512 or 1024)
 int launch_event_batched(std::vector<BatchItem> &items, const uint64_t *n_hist, unsigned int seg_len, void *mem,
-                         size_t mem_bytes, hipStream_t st, int step_form);
+                         size_t mem_bytes, hipStream_t st, int step_form, int block);
 
 }  // namespace mcdc

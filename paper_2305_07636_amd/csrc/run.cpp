@@ -289,6 +289,14 @@ extern "C" int mcdc_run(mcdc_problem *p, uint64_t n_histories, uint64_t seed, co
     }
     int rc = check_options(opt);
     if (rc) return rc;
+    if (opt.algorithm == MCDC_ALG_EVENT && opt.block_size != 0 && opt.block_size != 256 && opt.block_size != 512 &&
+        opt.block_size != 1024)
+        return bad("event form: block_size must be 0, 256, 512 or 1024");
+    if (opt.algorithm == MCDC_ALG_EVENT && opt.block_size && opt.block_size != 512 &&
+        (has_progeny(p->d) || opt.pc_target)) {
+        set_error("event form: weighted runs and population control use 512-thread workgroups");
+        return MCDC_E_UNSUPPORTED;
+    }
     HIP_CHECK(hipSetDevice(p->device), "hipSetDevice");
     hipStream_t st = (hipStream_t)opt.stream;
     Profiler prof;
@@ -338,6 +346,7 @@ struct Tuned {
                              // c >= 1 two-kernel step with the queue sort every c-th step
     uint64_t tail;           // event form: problems of at most this many histories run in
                              // the history-form launch instead
+    int ev_block;            // event form: workgroup size of the step kernels
 };
 
 // Launch shapes and form choices of batched solves, per batch signature,
@@ -465,7 +474,8 @@ int batched_once(mcdc_problem *const *ps, int32_t n, const uint64_t *n_hist, con
         }
         const size_t need = event_batched_bytes(ne.data(), (int)E.size(), t.seg_len, t.step_form);
         if ((r = grow(wk.ev, wk.ev_bytes, need))) return r;
-        if ((r = launch_event_batched(ie, ne.data(), t.seg_len, wk.ev.mem, wk.ev_bytes, st, t.step_form))) return r;
+        if ((r = launch_event_batched(ie, ne.data(), t.seg_len, wk.ev.mem, wk.ev_bytes, st, t.step_form, t.ev_block)))
+            return r;
         for (int j : E)
             if (ps[j]->d.qoi_on && (r = launch_qoi_reduce(items[j].R.qoi_hist, n_hist[j], items[j].R.qoi_sums, st)))
                 return hip_fail((hipError_t)r, "detector reduce");
@@ -504,10 +514,11 @@ int batched_once(mcdc_problem *const *ps, int32_t n, const uint64_t *n_hist, con
 // Launch parameters of a batched solve: forced by the options, cached per
 // batch signature, or tuned now by coordinate descent over timed runs of
 // the whole batch.  Event form: segment length {2048, 8192, 32768, 65536}
-// with one kernel per census step; then the census step's form (one
+// with one kernel per census step of 512-thread workgroups; then the
+// workgroup size {256, 512, 1024}; then the census step's form (one
 // kernel, two kernels, two kernels with the queue sort every 1, 2, 4 or 8
-// steps) at that length; then the tail switch (problems of at most 0, 2e4
-// or 1e5 histories run in the history-form launch).  History form:
+// steps); then the tail switch (problems of at most 0, 2e4 or 1e5
+// histories run in the history-form launch), each at the best so far.  History form:
 // workgroup {128, 256, 512} x histories per pull {1, 4, 16}.  No
 // parameter changes per-history results, only tally summation order.
 int batched_tuned(mcdc_problem *const *ps, int32_t n, const uint64_t *n_hist, const uint64_t *seeds,
@@ -515,7 +526,7 @@ int batched_tuned(mcdc_problem *const *ps, int32_t n, const uint64_t *n_hist, co
                   hipStream_t st, float *ms) {
     const bool two = (opt.flags & MCDC_FLAG_TWO_KERNEL_STEP) != 0;
     Tuned t{opt.block_size ? opt.block_size : 256, 4, (unsigned int)opt.bank_capacity,
-            opt.sort_cadence > 0 ? opt.sort_cadence : (two ? 0 : -1), 0};
+            opt.sort_cadence > 0 ? opt.sort_cadence : (two ? 0 : -1), 0, opt.block_size ? opt.block_size : 512};
     const bool seg_forced = opt.bank_capacity != 0;
     const bool form_forced = opt.sort_cadence != 0 || two;
     const std::string sig = std::string(all_history ? "history:" : "event:") + std::to_string(opt.block_size) +
@@ -554,6 +565,14 @@ int batched_tuned(mcdc_problem *const *ps, int32_t n, const uint64_t *n_hist, co
                 }
             } else {
                 if ((rc = trial(t, &best, &t))) return rc;
+            }
+            if (!opt.block_size) {
+                base = t;
+                for (int bsz : {256, 1024}) {
+                    Tuned c = base;
+                    c.ev_block = bsz;
+                    if ((rc = trial(c, &best, &t))) return rc;
+                }
             }
             if (!form_forced) {
                 base = t;
@@ -632,6 +651,13 @@ extern "C" int mcdc_run_batched(mcdc_problem *const *ps, int32_t n, const uint64
     }
     int rc = check_options(opt);
     if (rc) return rc;
+    if (opt.block_size != 0) {
+        const int b = opt.block_size;
+        if (opt.algorithm == MCDC_ALG_HISTORY && b != 64 && b != 128 && b != 256 && b != 512)
+            return bad("batched history form: block_size must be 0, 64, 128, 256 or 512");
+        if (opt.algorithm != MCDC_ALG_HISTORY && b != 256 && b != 512 && b != 1024)
+            return bad("batched event form: block_size must be 0, 256, 512 or 1024");
+    }
     if (opt.profile) {
         set_error("batched solves take no profile array");
         return MCDC_E_UNSUPPORTED;
