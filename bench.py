@@ -610,15 +610,17 @@ def block_section(m, w, n_slab, n_lattice, steps):
     import torch
 
     res = {}
-    for tag, prob, n in (("slab", w.cfg2_slab_pulse(), n_slab), ("lattice", w.cfg3_lattice(), n_lattice)):
+    cases = [("slab", w.cfg2_slab_pulse(), n_slab, {}), ("slab_staged", w.cfg2_slab_pulse(), n_slab, {"staged": True}),
+             ("lattice", w.cfg3_lattice(), n_lattice, {})]
+    for tag, prob, n, kw in cases:
         h = m.mcdc_problem_create(prob)
         try:
             for bs in (256, 512, 1024):
-                m.mcdc_run(h, n, 2, outputs=("mean",), block_size=bs)
+                m.mcdc_run(h, n, 2, outputs=("mean",), block_size=bs, **kw)
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
                 for s in range(steps):
-                    m.mcdc_run(h, n, 2 + s, outputs=("mean",), block_size=bs)
+                    m.mcdc_run(h, n, 2 + s, outputs=("mean",), block_size=bs, **kw)
                 torch.cuda.synchronize()
                 res[f"{tag}_block{bs}_ms"] = (time.perf_counter() - t0) / steps * 1e3
             log(f"block: {tag} " + " ".join(f"{bs}: {res[f'{tag}_block{bs}_ms']:.2f}" for bs in (256, 512, 1024)))
@@ -753,6 +755,21 @@ def main():
             m.mcdc_run(p, N, seed + s, algorithm="event", outputs=outs, two_kernel_step=True)
         torch.cuda.synchronize()
         extra["two_kernel_step_histories_per_s"] = N * args.steps / (time.perf_counter() - t1)
+        # the queue form's kernels, each launch bracketed by HIP events:
+        # algorithmic bytes over device time per class
+        prof2 = np.zeros((len(m._binding.PROF_CLASSES), 4))
+        m.mcdc_run(p, N, seed, algorithm="event", outputs=outs, two_kernel_step=True, profile=prof2)
+        torch.cuda.synchronize()
+        names = m._binding.PROF_CLASSES
+        tk = {}
+        for cname in ("advance", "events"):
+            c = names.index(cname)
+            if prof2[c, 1] > 0:
+                ach = prof2[c, 3] / (prof2[c, 0] * 1e-3) / 1e9
+                tk[cname] = {"ms": float(prof2[c, 0]), "launches": int(prof2[c, 1]),
+                             "particles": float(prof2[c, 2]), "bytes": float(prof2[c, 3]),
+                             "achieved_GBs": ach, "frac": ach / HBM_PEAK_GBS}
+        extra["two_kernel_step_kernels"] = tk
         log("two-kernel step timed")
     if not args.no_time_crossing:
         # the same workload with the time-crossing tally (flux at the 100

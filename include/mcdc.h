@@ -41,7 +41,7 @@
 extern "C" {
 #endif
 
-#define MCDC_ABI_VERSION 4
+#define MCDC_ABI_VERSION 5
 
 /* return codes */
 #define MCDC_OK 0
@@ -208,20 +208,25 @@ typedef struct {
 
 /*
  * Run options (all-zero = defaults; ABI version 4 added sort_cadence and
- * the sort profile class).
+ * the sort profile class, version 5 steps_per_launch).
  *  algorithm      MCDC_ALG_EVENT (default), MCDC_ALG_HISTORY, or
  *                 MCDC_ALG_AUTO: mcdc_run runs both forms on its first call
  *                 for a history count (results of the history-form run)
  *                 and keeps the faster on the problem handle; batched
  *                 solves keep it per batch signature.
  *  block_size     threads per workgroup.  mcdc_run, event form: the
- *                 census-step kernels' 256, 512 or 1024 (0 = 512; weighted
+ *                 census-step kernels' 256, 512 or 1024 (0 = 1024; weighted
  *                 runs and population control take 512 only); the history
  *                 form always uses 256.  mcdc_run_batched: the history
  *                 form's persistent launch 64, 128, 256 or 512, the event
  *                 form's step kernels 256, 512 or 1024 (0 = autotuned).
  *  bank_capacity  event form: particles resident at once (0 = auto).  Work
- *                 is processed in chunks of this many histories.  In
+ *                 is processed in chunks of this many histories.  History
+ *                 form with weight windows or fission: histories per chunk
+ *                 (0 = auto: 2^21, 2^20 with fission); each generation of
+ *                 a chunk's progeny must fit a split bank of 32 (64 with
+ *                 fission) entries per history, at least 2^22 and at most
+ *                 2^26, else the run ends with MCDC_E_OVERFLOW.  In
  *                 mcdc_run_batched's event form: slots per bank segment.
  *  flags          bit 0 (MCDC_FLAG_EAGER): launch the event form's census
  *                 steps one kernel at a time instead of replaying the
@@ -235,6 +240,13 @@ typedef struct {
  *                 of the step's bank through its flights to census or
  *                 death with lane refill.  Same results; kept for
  *                 comparison.
+ *                 bit 2 (MCDC_FLAG_STAGED): event form on a slab (x the
+ *                 only finite axis), analog: the one-kernel step reads
+ *                 each refill from tiles of the bank each wave copies into
+ *                 LDS one tile ahead (direct-to-LDS loads) instead of
+ *                 straight from HBM.  Same results; slower on MI355X,
+ *                 kept for comparison.
+
  *  stream         hipStream_t to run on (NULL = the null stream).  mcdc_run
  *                 synchronises this stream before it returns.
  *  debug_counts   device array [N][5] (census, surface, collision events,
@@ -292,9 +304,28 @@ typedef struct {
  *                 bank segments.  A weight of 2^32 or more, or more
  *                 copies than the banks hold (about n_histories +
  *                 pc_target), ends the run with MCDC_E_OVERFLOW.
+ *  steps_per_launch
+ *                 mcdc_run, event form, analog one-kernel step: census
+ *                 steps s taken per launch of the step kernel (1 .. 65535;
+ *                 0 = the default, all K).  With s > 1 a particle that
+ *                 reaches the edge T_{k+1} inside the launch's steps
+ *                 k0 .. k0+s-1 goes on into time bin k+1 in registers
+ *                 instead of through the next bank, and the workgroup's
+ *                 LDS slice of the tally holds all s time bins (s is
+ *                 lowered until it fits: 4096 doubles, 12288 with
+ *                 1024-thread workgroups).  The census edges stay where
+ *                 the paper puts them (Section 2): per-history results are
+ *                 the same, tallies differ by summation order only.  s > 1
+ *                 with weight windows, fission, population control, a
+ *                 queue sort, the two-kernel or the staged step is refused
+ *                 (MCDC_E_UNSUPPORTED); those take one step per launch, and
+ *                 mcdc_run_batched ignores the option.  With profile,
+ *                 profile_every and profile_phase count launches instead
+ *                 of census steps.
  */
 #define MCDC_FLAG_EAGER 1
 #define MCDC_FLAG_TWO_KERNEL_STEP 2
+#define MCDC_FLAG_STAGED 4
 #define MCDC_PROF_CLASSES 7
 #define MCDC_PROF_SOURCE 0     /* event form: source sampling */
 #define MCDC_PROF_ADVANCE 1    /* event form: one flight over the census bank */
@@ -318,6 +349,8 @@ typedef struct {
     int32_t segments;
     int32_t sort_cadence;
     uint64_t pc_target;
+    int32_t steps_per_launch;
+    int32_t reserved;   /* zero */
 } mcdc_run_options;
 
 /*

@@ -16,7 +16,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libmcdc_hip.so")
 
-MCDC_ABI_VERSION = 4
+MCDC_ABI_VERSION = 5
 MCDC_OK, MCDC_E_INVALID, MCDC_E_HIP, MCDC_E_NOMEM, MCDC_E_OVERFLOW, MCDC_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5
 MCDC_ALG_EVENT, MCDC_ALG_HISTORY, MCDC_ALG_AUTO = 0, 1, 2
 MCDC_SRC_ISOTROPIC, MCDC_SRC_SURFACE = 0, 1
@@ -64,6 +64,7 @@ class mcdc_run_options(C.Structure):
         ("debug_counts", C.c_void_p), ("debug_scores", C.c_void_p),
         ("profile", C.c_void_p), ("profile_mask", C.c_uint32), ("profile_every", C.c_int32), ("profile_phase", C.c_int32),
         ("segments", C.c_int32), ("sort_cadence", C.c_int32), ("pc_target", C.c_uint64),
+        ("steps_per_launch", C.c_int32), ("reserved", C.c_int32),
     ]
 
 
@@ -265,7 +266,8 @@ def mcdc_run(p: Problem, n_histories: int, seed: int, algorithm: str = "event",
              debug: bool = False, outputs=("mean", "var", "raw", "leak_mean", "leak_var"),
              profile=None, eager: bool = False, profile_classes=None, profile_every: int = 0,
              profile_phase: int = 0, two_kernel_step: bool = False, pc_target: int = 0,
-             noalloc: bool = False, sort_cadence: int = 0):
+             noalloc: bool = False, sort_cadence: int = 0, staged: bool = False,
+             steps_per_launch: int = 0):
     """Run n_histories through the GPU tracker.  Returns a dict of torch
     CUDA tensors (mean, var, raw [K, G, nz, ny, nx]; leak_mean, leak_var
     [K, G, 6]; tc_mean, tc_var [K, G, nz, ny, nx] for a problem with the
@@ -277,7 +279,9 @@ def mcdc_run(p: Problem, n_histories: int, seed: int, algorithm: str = "event",
     pc_target: population control at every census edge (splitting-roulette
     to that many particles; event form; 0 = off).
     noalloc: call mcdc_run_noalloc (history form, device outputs, no
-    debug arrays or profile) instead of mcdc_run."""
+    debug arrays or profile) instead of mcdc_run.
+    steps_per_launch: census steps per launch of the event form's
+    one-kernel step (analog; 0 = default)."""
     import torch
 
     dev = torch.device("cuda", torch.cuda.current_device())
@@ -300,7 +304,8 @@ def mcdc_run(p: Problem, n_histories: int, seed: int, algorithm: str = "event",
     opt.segments = segments
     opt.pc_target = pc_target
     opt.sort_cadence = sort_cadence
-    opt.flags = (1 if eager else 0) | (2 if two_kernel_step else 0)
+    opt.steps_per_launch = steps_per_launch
+    opt.flags = (1 if eager else 0) | (2 if two_kernel_step else 0) | (4 if staged else 0)
     opt.stream = torch.cuda.current_stream(dev).cuda_stream
     if debug:
         dc = torch.empty((n_histories, 5), dtype=torch.int32, device=dev)

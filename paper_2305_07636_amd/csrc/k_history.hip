@@ -22,12 +22,57 @@ struct Acc {
     double track = 0.0, qoi = 0.0;
 };
 
-// One flight of a particle of history hid and its event; returns the
-// termination code, or -1 while the particle lives.  Split progeny go to
-// the split bank.
+constexpr int kCollisionPending = -2;
+
+// Weight-window check point after an event (roulette or split).
+template <bool WW>
+__device__ __forceinline__ int ww_after(const DevProblem &P, const RunArgs &R, Particle &p, int cell, int b,
+                                        uint64_t hid, Acc &acc, const SplitBank &SB, bool check, int code) {
+    if (WW && check) {
+        int nc = 0;
+        if (!ww_check(P, p, cell, nc)) {
+            code = kRoulette;
+        } else if (nc > 0) {
+            if (!spawn_children(SB, p, nc, b, hid)) *R.overflow = 1;
+            acc.spawned += (unsigned int)nc;
+        }
+    }
+    return code;
+}
+
+// The collision of a particle of history hid in material m; returns the
+// termination code, or -1 while the particle lives.
 template <int FM, bool WW>
-__device__ __forceinline__ int hstep(const DevProblem &P, const RunArgs &R, Particle &p, int &cell, int b,
-                                     uint64_t hid, Acc &acc, const SplitBank &SB, int &since) {
+__device__ __forceinline__ int hcollide(const DevProblem &P, const RunArgs &R, Particle &p, int cell, int b,
+                                        uint64_t hid, Acc &acc, const SplitBank &SB, int m) {
+    bool check = false;
+    int code = -1;
+    const int r = collide<FM, WW>(P, p, m);
+    if (r == 0) {
+        code = kAbsorb;
+    } else if (WW && r == 3) {
+        code = kRoulette;
+    } else if (WW && r == 2) {
+        const int n = fission<FM>(P, p, m, SB, b, hid, R.overflow);
+        if (n == 0) {
+            code = kAbsorb;
+        } else {
+            acc.fissioned += (unsigned int)(n - 1);
+            check = true;
+        }
+    } else {
+        check = WW;
+    }
+    return ww_after<WW>(P, R, p, cell, b, hid, acc, SB, check, code);
+}
+
+// One flight of a particle of history hid and its census or surface event;
+// returns the termination code, -1 while the particle lives, or
+// kCollisionPending when the flight ends in a collision (its material in
+// m_coll), which hcollide then applies.  Split progeny go to the split bank.
+template <int FM, bool WW>
+__device__ __forceinline__ int hflight(const DevProblem &P, const RunArgs &R, Particle &p, int &cell, int b,
+                                       uint64_t hid, Acc &acc, const SplitBank &SB, int &since, int &m_coll) {
     if (since >= kMaxEventsPerStep) return kLost;
     ++since;
     const Flight f = next_event<FM>(P, p, cell);
@@ -67,34 +112,26 @@ __device__ __forceinline__ int hstep(const DevProblem &P, const RunArgs &R, Part
         }
     } else {
         ++acc.n_ev[2];
-        const int r = collide<FM, WW>(P, p, f.m);
-        if (r == 0) {
-            code = kAbsorb;
-        } else if (WW && r == 3) {
-            code = kRoulette;
-        } else if (WW && r == 2) {
-            const int n = fission<FM>(P, p, f.m, SB, b, hid, R.overflow);
-            if (n == 0) {
-                code = kAbsorb;
-            } else {
-                acc.fissioned += (unsigned int)(n - 1);
-                check = true;
-            }
-        } else {
-            check = WW;
-        }
+        m_coll = f.m;
+        return kCollisionPending;
     }
-    if (WW && check) {
-        int nc = 0;
-        if (!ww_check(P, p, cell, nc)) {
-            code = kRoulette;
-        } else if (nc > 0) {
-            if (!spawn_children(SB, p, nc, b, hid)) *R.overflow = 1;
-            acc.spawned += (unsigned int)nc;
-        }
-    }
-    return code;
+    return ww_after<WW>(P, R, p, cell, b, hid, acc, SB, check, code);
 }
+
+// One flight of a particle of history hid and its event; returns the
+// termination code, or -1 while the particle lives.
+template <int FM, bool WW>
+__device__ __forceinline__ int hstep(const DevProblem &P, const RunArgs &R, Particle &p, int &cell, int b,
+                                     uint64_t hid, Acc &acc, const SplitBank &SB, int &since) {
+    int m = 0;
+    const int code = hflight<FM, WW>(P, R, p, cell, b, hid, acc, SB, since, m);
+    return code == kCollisionPending ? hcollide<FM, WW>(P, R, p, cell, b, hid, acc, SB, m) : code;
+}
+
+// A wave's persistent loop takes queued collisions only once they make up
+// kCollEighths / 8 of its busy lanes (or every busy lane has one), so that
+// the collision code runs for many lanes at once.
+constexpr int kCollEighths = 3;
 
 // Track one particle of history hid until it terminates; returns the
 // termination code (also ORed into acc.term_mask).
@@ -201,7 +238,7 @@ __global__ void __launch_bounds__(256) k_history(DevProblem P0, RunArgs R, uint6
     tot.init();
     Particle p;
     Acc acc;
-    int b = 0, cell = 0, since = 0;
+    int b = 0, cell = 0, since = 0, pm = -1;   // pm: material of a queued collision, or -1
     uint64_t i = 0;
     bool busy = false;
     for (;;) {
@@ -233,6 +270,7 @@ __global__ void __launch_bounds__(256) k_history(DevProblem P0, RunArgs R, uint6
                 if (birth<FM>(P, history_stream(P, R.seed, i), p)) {
                     cell = cell_index(P, p.ix);
                     since = 0;
+                    pm = -1;
                     busy = true;
                 } else {
                     acc.term_mask = 1u << kTime;
@@ -242,14 +280,24 @@ __global__ void __launch_bounds__(256) k_history(DevProblem P0, RunArgs R, uint6
             c_pos += (n_need < avail) ? n_need : avail;
             need = __ballot(!busy);
         }
-        if (!__any(busy)) break;
-        if (busy) {
-            const int code = hstep<FM, WW>(P, R, p, cell, b, i, acc, SB, since);
-            if (code >= 0) {
-                acc.term_mask |= 1u << code;
-                end_history<WW>(P, R, acc, code, i, chunk_first, tot);
-                busy = false;
-            }
+        const int n_busy = __popcll(__ballot(busy));
+        if (n_busy == 0) break;
+        const bool pend = busy && pm >= 0;
+        const int n_pend = __popcll(__ballot(pend));
+        int code = -1;
+        if (n_pend > 0 && (n_pend * 8 >= n_busy * kCollEighths || n_pend == n_busy) && pend) {
+            code = hcollide<FM, WW>(P, R, p, cell, b, i, acc, SB, pm);
+            pm = -1;
+        }
+        if (busy && pm < 0 && code < 0) {
+            code = hflight<FM, WW>(P, R, p, cell, b, i, acc, SB, since, pm);
+            if (code == kCollisionPending) code = -1;
+            else pm = -1;
+        }
+        if (busy && code >= 0) {
+            acc.term_mask |= 1u << code;
+            end_history<WW>(P, R, acc, code, i, chunk_first, tot);
+            busy = false;
         }
     }
     // totals: wave reductions, then one atomic per counter and workgroup
@@ -309,12 +357,27 @@ __device__ __forceinline__ void child_done(const DevProblem &P, const RunArgs &R
 // by its longest-lived particle.  Their own progeny go to the next
 // generation's bank.  (LT: flight tables in LDS.)
 template <int FM, bool LT>
+// (The generation's size is read here from the input bank's counter, so
+// the host can queue several generations without reading it: an empty
+// generation exits at once, and more progeny than the bank holds set the
+// overflow flag instead of being read.)
 __global__ void __launch_bounds__(256) k_history_children(DevProblem P0, RunArgs R, SplitBank in,
-                                                          unsigned long long n, uint64_t chunk_first, SplitBank out,
-                                                          unsigned long long *next, unsigned int wave_chunk,
-                                                          LdsTables tabs) {
+                                                          uint64_t chunk_first, SplitBank out,
+                                                          unsigned long long *next, LdsTables tabs) {
     __shared__ unsigned long long red[kCounters];
     extern __shared__ double lds_tables[];
+    const unsigned long long n_in = *in.count;
+    if (n_in > in.cap) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) *R.overflow = 1;
+        return;
+    }
+    const unsigned long long n = n_in;
+    if (n == 0) return;
+    // entries per wave take: about 16 takes per wave of the grid, 64..65536
+    const unsigned long long waves = (unsigned long long)gridDim.x * (blockDim.x / 64);
+    unsigned long long wcl = n / (waves * 16ull);
+    wcl = (wcl < 64ull) ? 64ull : (wcl > 65536ull ? 65536ull : (wcl + 63ull) & ~63ull);
+    const unsigned int wave_chunk = (unsigned int)wcl;
     if (threadIdx.x < kCounters) red[threadIdx.x] = 0ull;
     const DevProblem P = stage_tables<LT, 256>(P0, tabs, reinterpret_cast<char *>(lds_tables));
     __syncthreads();
@@ -325,7 +388,7 @@ __global__ void __launch_bounds__(256) k_history_children(DevProblem P0, RunArgs
     tot.init();
     Particle p;
     Acc acc;
-    int b = 0, cell = 0, since = 0;
+    int b = 0, cell = 0, since = 0, pm = -1;   // pm: material of a queued collision, or -1
     uint64_t i = 0;
     bool busy = false;
     for (;;) {
@@ -352,20 +415,31 @@ __global__ void __launch_bounds__(256) k_history_children(DevProblem P0, RunArgs
                 set_inverse<FM>(P, p);
                 cell = cell_index(P, p.ix);
                 since = 0;
+                pm = -1;
                 acc = Acc();
                 busy = true;
             }
             c_pos += (n_need < avail) ? n_need : avail;
             need = __ballot(!busy);
         }
-        if (!__any(busy)) break;
-        if (busy) {
-            const int code = hstep<FM, true>(P, R, p, cell, b, i, acc, out, since);
-            if (code >= 0) {
-                acc.term_mask |= 1u << code;
-                child_done(P, R, acc, code, i, chunk_first, tot);
-                busy = false;
-            }
+        const int n_busy = __popcll(__ballot(busy));
+        if (n_busy == 0) break;
+        const bool pend = busy && pm >= 0;
+        const int n_pend = __popcll(__ballot(pend));
+        int code = -1;
+        if (n_pend > 0 && (n_pend * 8 >= n_busy * kCollEighths || n_pend == n_busy) && pend) {
+            code = hcollide<FM, true>(P, R, p, cell, b, i, acc, out, pm);
+            pm = -1;
+        }
+        if (busy && pm < 0 && code < 0) {
+            code = hflight<FM, true>(P, R, p, cell, b, i, acc, out, since, pm);
+            if (code == kCollisionPending) code = -1;
+            else pm = -1;
+        }
+        if (busy && code >= 0) {
+            acc.term_mask |= 1u << code;
+            child_done(P, R, acc, code, i, chunk_first, tot);
+            busy = false;
         }
     }
 #pragma unroll
@@ -442,8 +516,9 @@ int launch_main(mcdc_problem *pb, const DevProblem &P, const RunArgs &R, uint64_
     return MCDC_OK;
 }
 
-// Split progeny of one chunk, generation by generation, until none are left
-// (the count of each generation is read back to size the next launch).
+// Split progeny of one chunk, generation by generation, until none are left.
+// Generations are queued kGensPerCheck at a time, each launch reading its
+// input count on the device; the host reads the count once per batch.
 template <int FM>
 int run_generations(mcdc_problem *pb, const RunArgs &R, SplitBank SB[2], uint64_t cfirst, hipStream_t st,
                     Profiler &prof) {
@@ -461,7 +536,8 @@ int run_generations(mcdc_problem *pb, const RunArgs &R, SplitBank SB[2], uint64_
     if (e0 == hipSuccess) e0 = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, pb->device);
     if (e0 != hipSuccess) return hip_fail(e0, "occupancy query");
     const uint64_t grid_max = (uint64_t)(per_cu > 0 ? per_cu : 1) * (uint64_t)(n_cu > 0 ? n_cu : 1);
-    for (int gen = 0;; ++gen) {
+    constexpr int kGensPerCheck = 4;
+    for (int gen = 0;;) {
         unsigned long long n_in = 0;
         hipError_t e = hipMemcpyAsync(&n_in, SB[gen & 1].count, sizeof(n_in), hipMemcpyDeviceToHost, st);
         if (e == hipSuccess) e = hipStreamSynchronize(st);
@@ -472,34 +548,31 @@ int run_generations(mcdc_problem *pb, const RunArgs &R, SplitBank SB[2], uint64_
                       "run fewer histories per chunk with bank_capacity)");
             return MCDC_E_OVERFLOW;
         }
-        const SplitBank &in = SB[gen & 1], &out = SB[(gen + 1) & 1];
-        hipLaunchKernelGGL(k_zero_count, dim3(1), dim3(1), 0, st, out.count);
-        hipLaunchKernelGGL(k_zero_count, dim3(1), dim3(1), 0, st, next);
-        // entries per wave take: about 16 takes per wave, 64..65536
-        uint64_t wc = n_in / (grid_max * (bs / 64) * 16);
-        wc = (wc < 64) ? 64 : (wc > 65536 ? 65536 : (wc + 63) & ~63ull);
-        uint64_t grid = ((n_in + wc - 1) / wc + bs / 64 - 1) / (bs / 64);
-        if (grid > grid_max) grid = grid_max;
-        if (lt)
-            launch_timed(prof, MCDC_PROF_HISTORY, k_history_children<FM, true>, dim3((unsigned)grid), dim3(bs),
-                         (uint32_t)shmem, st, P, R, in, n_in, cfirst, out, next, (unsigned int)wc, tabs);
-        else
-            launch_timed(prof, MCDC_PROF_HISTORY, k_history_children<FM, false>, dim3((unsigned)grid), dim3(bs), 0u,
-                         st, P, R, in, n_in, cfirst, out, next, (unsigned int)wc, tabs);
-        e = hipGetLastError();
-        if (e != hipSuccess) return hip_fail(e, "history children launch");
+        for (int q = 0; q < kGensPerCheck; ++q, ++gen) {
+            const SplitBank &in = SB[gen & 1], &out = SB[(gen + 1) & 1];
+            hipLaunchKernelGGL(k_zero_count, dim3(1), dim3(1), 0, st, out.count);
+            hipLaunchKernelGGL(k_zero_count, dim3(1), dim3(1), 0, st, next);
+            if (lt)
+                launch_timed(prof, MCDC_PROF_HISTORY, k_history_children<FM, true>, dim3((unsigned)grid_max),
+                             dim3(bs), (uint32_t)shmem, st, P, R, in, cfirst, out, next, tabs);
+            else
+                launch_timed(prof, MCDC_PROF_HISTORY, k_history_children<FM, false>, dim3((unsigned)grid_max),
+                             dim3(bs), 0u, st, P, R, in, cfirst, out, next, tabs);
+            e = hipGetLastError();
+            if (e != hipSuccess) return hip_fail(e, "history children launch");
+        }
     }
 }
 
 template <int FM>
-int run_history(mcdc_problem *pb, const RunArgs &R0, uint64_t first, uint64_t count, hipStream_t st,
-                Profiler &prof) {
+int run_history(mcdc_problem *pb, const RunArgs &R0, uint64_t first, uint64_t count, uint64_t chunk_opt,
+                hipStream_t st, Profiler &prof) {
     const DevProblem &P = pb->d;
     const bool ww = has_progeny(P);
     RunArgs R = R0;
     // analog runs keep the detector score in registers; runs with progeny
     // (weight windows, fission) assemble it per history in chunks
-    const uint64_t cmax = P.fission_on ? kFissionChunk : kWindowChunk;
+    const uint64_t cmax = chunk_opt ? chunk_opt : (P.fission_on ? kFissionChunk : kWindowChunk);
     const uint64_t chunk = ww ? ((count < cmax) ? count : cmax) : count;
     SplitBank SB[2]{};
     int rc;
@@ -649,9 +722,9 @@ int launch_batched(const BatchItem *items, const uint64_t *offs, int n_items, ui
 }
 
 int split_prepare(mcdc_problem *pb, uint64_t chunk, dev::SplitBank SB[2]) {
-    // room for eight progeny per history of the chunk in each generation
+    // room for 32 progeny per history of the chunk in each generation
     // (64 with fission; implicit capture alone makes none: the minimum)
-    const uint64_t per = pb->d.fission_on ? 64 : (pb->d.ww_center ? 8 : 0);
+    const uint64_t per = pb->d.fission_on ? 64 : (pb->d.ww_center ? 32 : 0);
     const uint64_t want = per * chunk;
     const unsigned int cap = (unsigned int)((want < (1u << 22)) ? (1u << 22) : (want > (1u << 26) ? (1u << 26) : want));
     int rc;
@@ -676,18 +749,17 @@ int split_generations(mcdc_problem *pb, const RunArgs &R, dev::SplitBank SB[2], 
     return run_generations<0>(pb, R, SB, cfirst, st, prof);
 }
 
-int launch_history(mcdc_problem *p, const RunArgs &R, uint64_t first, uint64_t count, int block, hipStream_t st,
-                   Profiler &prof) {
-    (void)block;
+int launch_history(mcdc_problem *p, const RunArgs &R, uint64_t first, uint64_t count, uint64_t chunk,
+                   hipStream_t st, Profiler &prof) {
     if (count == 0) return MCDC_OK;
     if (p->h.B > 1023) {
         set_error("at most 1023 batches");
         return MCDC_E_UNSUPPORTED;
     }
     const int fm = p->d.finite_mask;
-    if (fm == 1) return run_history<1>(p, R, first, count, st, prof);
-    if (fm == 7) return run_history<7>(p, R, first, count, st, prof);
-    return run_history<0>(p, R, first, count, st, prof);
+    if (fm == 1) return run_history<1>(p, R, first, count, chunk, st, prof);
+    if (fm == 7) return run_history<7>(p, R, first, count, chunk, st, prof);
+    return run_history<0>(p, R, first, count, chunk, st, prof);
 }
 
 }  // namespace mcdc

@@ -2,8 +2,9 @@
 // tanh hidden layers, trained in FP32 on matrix cores and run in BF16 on
 // matrix cores.
 //
-// Training: one 64-lane wave per block; each wave streams its samples in
-// groups of 16 rows through forward and backward passes built from
+// Training: one 64-lane wave per block (about 512 blocks: a block takes one
+// or a few groups of 16 samples); each wave streams its groups through
+// forward and backward passes built from
 // v_mfma_f32_16x16x4_f32 tiles (A 16x4, B 4x16, D 16x16), with weights and
 // activations in LDS and the weight-gradient tiles in registers across the
 // wave's groups.  Each block writes its gradient as one partial row; a
@@ -403,16 +404,21 @@ int ensure_partial(mcdc_mlp *m, size_t rows) {
     return MCDC_OK;
 }
 
-constexpr int kGroupsPerBlock = 8;   // 128 samples per block
+// Sample groups of 16 per block: as few as keep about this many blocks in
+// flight (a block's groups run one after the other, so fewer groups per
+// block shorten the step; the partial rows they add stay few enough for the
+// ordered reduction).
+constexpr int64_t kTargetBlocks = 512;
 
 int grad_pass(mcdc_mlp *m, const float *X, const float *T, const float *W, int64_t n, hipStream_t st,
               int &nblk) {
     const int64_t groups = (n + 15) / 16;
-    nblk = (int)((groups + kGroupsPerBlock - 1) / kGroupsPerBlock);
+    const int64_t per = (groups + kTargetBlocks - 1) / kTargetBlocks;
+    nblk = (int)((groups + per - 1) / per);
     int rc = ensure_partial(m, (size_t)nblk);
     if (rc) return rc;
-    hipLaunchKernelGGL(k_mlp_grad, dim3(nblk), dim3(64), sizeof(TrainLds), st, m->params, X, T, W, n,
-                       kGroupsPerBlock, m->partial);
+    hipLaunchKernelGGL(k_mlp_grad, dim3(nblk), dim3(64), sizeof(TrainLds), st, m->params, X, T, W, n, (int)per,
+                       m->partial);
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? MCDC_OK : hip_fail(e, "mlp grad launch");
 }

@@ -16,7 +16,7 @@ namespace mcdc {
 constexpr int kMaxGroups = 32;      // outgoing-group search is unrolled over this
 constexpr int kCounters = 10;       // census, surface, collision; 5 terminations; splits; fission progeny
 constexpr int kLdsTallyMax = 4096;  // doubles of the event form's per-step LDS tally slice
-constexpr uint64_t kWindowChunk = 1ULL << 23;  // histories per chunk of a weight-window run
+constexpr uint64_t kWindowChunk = 1ULL << 21;  // histories per chunk of a weight-window run
 constexpr uint64_t kFissionChunk = 1ULL << 20; // histories per chunk of a run with fission
 constexpr double kMaxNu = 64.0;                // largest mean number of neutrons per fission
 constexpr uint64_t kStride = 152917ULL;
@@ -235,7 +235,7 @@ int ensure(mcdc_problem::Buf &b, size_t bytes);
 
 // launchers (return a hipError_t as int)
 int launch_history(mcdc_problem *p, const RunArgs &R, uint64_t first, uint64_t count,
-                   int block, hipStream_t st, Profiler &prof);
+                   uint64_t chunk, hipStream_t st, Profiler &prof);
 int launch_event(mcdc_problem *p, const RunArgs &R, uint64_t first, uint64_t count,
                  const mcdc_run_options &opt, hipStream_t st, Profiler &prof);
 // (sums the tally and leakage copies into copy 0 first, in place)

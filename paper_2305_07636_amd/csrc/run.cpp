@@ -98,6 +98,8 @@ int check_options(const mcdc_run_options &opt) {
     if (opt.profile_every < 0 || opt.profile_phase < 0) return bad("profile_every and profile_phase must be >= 0");
     if (opt.bank_capacity < 0) return bad("bank_capacity must be >= 0");
     if (opt.sort_cadence < -1 || opt.sort_cadence > 64) return bad("sort_cadence must be in [-1, 64]");
+    if (opt.steps_per_launch < 0 || opt.steps_per_launch > 65535) return bad("steps_per_launch must be in [0, 65535]");
+    if (opt.reserved != 0) return bad("reserved must be 0");
     return MCDC_OK;
 }
 
@@ -311,7 +313,7 @@ extern "C" int mcdc_run(mcdc_problem *p, uint64_t n_histories, uint64_t seed, co
     RunArgs R;
     if ((rc = prepare(p, n_histories, seed, opt, st, R))) return rc;
     if (opt.algorithm == MCDC_ALG_HISTORY)
-        rc = launch_history(p, R, 0, n_histories, opt.block_size, st, prof);
+        rc = launch_history(p, R, 0, n_histories, (uint64_t)opt.bank_capacity, st, prof);
     else
         rc = launch_event(p, R, 0, n_histories, opt, st, prof);
     if (rc) return rc;

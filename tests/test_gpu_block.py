@@ -1,8 +1,8 @@
-"""The event form's census-step kernels at workgroup sizes 256 and 1024
-(512 is the default every other test runs): every history's record and
-every bin against the oracle, in the one-kernel step and the two-kernel
-step with the queue sort; the batched solve with each size forced equals
-separate runs."""
+"""The event form's census-step kernels at workgroup sizes 256, 512 and
+1024 (1024 is the default of analog runs, 512 of weighted ones): every
+history's record and every bin against the oracle, in the one-kernel step
+and the two-kernel step with the queue sort; the batched solve with each
+size forced equals separate runs."""
 import numpy as np
 import pytest
 
@@ -21,7 +21,7 @@ def _prob(which):
 
 
 @pytest.mark.gpu
-@pytest.mark.parametrize("block", [256, 1024])
+@pytest.mark.parametrize("block", [256, 512])
 @pytest.mark.parametrize("which", ["slab", "lattice", "rod"])
 def test_block_sizes_match_oracle(which, block):
     prob, N = _prob(which)
@@ -67,3 +67,18 @@ def test_block_size_refused_where_unsupported():
             m.mcdc_run(p, 100, 1, algorithm="event", block_size=256, pc_target=100)
     finally:
         p.close()
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("block", [256, 512, 1024])
+def test_slab_step_with_and_without_staging(block):
+    """The slab's one-kernel step reads its refills straight from HBM
+    (default) or from tiles each wave copies into LDS (staged): both give
+    the oracle's per-history records and bins."""
+    for prob, N in ((w.cfg2_slab_pulse(), 20_000), (w.cfg1_slab_steady(), 20_000)):
+        compare_full(prob, N, 33, "event", block_size=block)
+        compare_full(prob, N, 33, "event", block_size=block, staged=True)
+        g = gpu_run(prob, N, 33, "event", debug=False, block_size=block)
+        h = gpu_run(prob, N, 33, "event", debug=False, block_size=block, staged=True)
+        assert np.array_equal(g["events"], h["events"]) and np.array_equal(g["terms"], h["terms"])
+        close(g["mean"], h["mean"], what="staged vs unstaged")

@@ -125,11 +125,13 @@ def test_algorithms_agree_bitwise_on_counts():
 
 
 @pytest.mark.gpu
+@pytest.mark.parametrize("spl", [1, 7])
 @pytest.mark.parametrize("case", ["pulse_c09", "lattice17", "census_heavy"])
-def test_event_graph_replays_match_eager_and_oracle(case):
+def test_event_graph_replays_match_eager_and_oracle(case, spl):
     """The event form replays captured census-step graphs when no debug or
-    profile output is asked for.  Several replays, with eager runs and
-    synchronisations in between, must each equal the eager result."""
+    profile output is asked for and a chunk takes more than one launch (one
+    census step per launch, or seven).  Several replays, with eager runs
+    and synchronisations in between, must each equal the eager result."""
     import torch
 
     import oracle
@@ -142,10 +144,10 @@ def test_event_graph_replays_match_eager_and_oracle(case):
     e = oracle.estimates(prob, ref)
     p = m.mcdc_problem_create(prob)
     try:
-        eager = m.mcdc_run(p, N, seed, algorithm="event", eager=True)
+        eager = m.mcdc_run(p, N, seed, algorithm="event", eager=True, steps_per_launch=spl)
         for rep in range(3):
-            print(f"[graph] {case} replay {rep}", flush=True)
-            g = m.mcdc_run(p, N, seed, algorithm="event")
+            print(f"[graph] {case} steps/launch {spl} replay {rep}", flush=True)
+            g = m.mcdc_run(p, N, seed, algorithm="event", steps_per_launch=spl)
             torch.cuda.synchronize()
             assert np.array_equal(g["events"], eager["events"]) and np.array_equal(g["terms"], eager["terms"])
             assert np.array_equal(g["events"], ref["tot"][0:3]) and np.array_equal(g["terms"], ref["tot"][3:8])
@@ -194,12 +196,12 @@ def test_sampled_profile_mixes_graph_and_eager_steps():
     try:
         a = m.mcdc_run(h, 200003, 21, algorithm="event")
         full = np.zeros((len(m._binding.PROF_CLASSES), 4))
-        c = m.mcdc_run(h, 200003, 21, algorithm="event", profile=full)
+        c = m.mcdc_run(h, 200003, 21, algorithm="event", profile=full, steps_per_launch=1)
         total = np.zeros_like(full)
         for phase in range(10):
             prof = np.zeros_like(full)
             b = m.mcdc_run(h, 200003, 21, algorithm="event", profile=prof, profile_classes=["events"],
-                           profile_every=10, profile_phase=phase)
+                           profile_every=10, profile_phase=phase, steps_per_launch=1)
             assert prof[adv, 1] == 10 and prof[adv, 0] > 0
             assert np.array_equal(a["events"], b["events"]) and np.array_equal(a["terms"], b["terms"])
             close(b["mean"].cpu().numpy(), a["mean"].cpu().numpy())
