@@ -333,12 +333,17 @@ __device__ __forceinline__ bool ww_point(const DevProblem &P, const RunArgs &R, 
 // particle's batch is one of the segment's two, else straight to HBM.  The
 // slice holds [2][gn] track-length bins and, with the time-crossing tally,
 // [2][gn] bins of the flux at the step's closing edge behind them.
+// A score bound for HBM is held back in the lane while the lane's next
+// scores go to the same bin (a collision that keeps the group, say), so
+// that one atomic carries their sum.
 struct StepScore {
     double *lt;     // LDS [ns][parts][2][gn]
     int gn;         // G * nts of the slice (0 = no LDS slice)
     int b0;         // first batch of the segment
     int k0, ns;     // time bins k0 .. k0 + ns - 1 of the launch's census steps
     bool scored;
+    double *pa;     // HBM bin of the held-back score (nullptr: none)
+    double pv;      // its value
     __device__ __forceinline__ void put(const DevProblem &P, const RunArgs &R, int part, int b, int g, int k,
                                         int tb, double v) {
         const int rel = b - b0;
@@ -347,8 +352,20 @@ struct StepScore {
             atomicAdd(&lt[((dk * (slice_mult(P) >> 1) + part) * 2 + rel) * gn + g * P.nts + tb], v);
             scored = true;
         } else {
-            atomic_add_f64(tally_copy(P, R, b) + part * P.ntally + ((int64_t)k * P.G + g) * P.nts + tb, v);
+            double *a = tally_copy(P, R, b) + part * P.ntally + ((int64_t)k * P.G + g) * P.nts + tb;
+            if (a == pa) {
+                pv += v;
+            } else {
+                if (pa) atomic_add_f64(pa, pv);
+                pa = a;
+                pv = v;
+            }
         }
+    }
+    // the held-back score to HBM
+    __device__ __forceinline__ void release() {
+        if (pa) atomic_add_f64(pa, pv);
+        pa = nullptr;
     }
     // track length w d of a flight in time bin k
     __device__ __forceinline__ void add(const DevProblem &P, const RunArgs &R, int b, int g, int k, int tb,
@@ -371,13 +388,16 @@ __device__ __forceinline__ void init_slice(const DevProblem &P, StepScore &sc, d
     sc.k0 = k0;
     sc.ns = ns;
     sc.scored = false;
+    sc.pa = nullptr;
+    sc.pv = 0.0;
     for (int j = threadIdx.x; j < slice_mult(P) * gn * ns; j += BS) lt[j] = 0.0;
 }
 
 // End of a scoring kernel: add the workgroup's slice into the tally (one
 // atomic per nonzero bin).  Contains the barrier the counter flush needs.
 template <int BS = kBlock>
-__device__ __forceinline__ void flush_slice(const DevProblem &P, const RunArgs &R, const StepScore &sc, int step) {
+__device__ __forceinline__ void flush_slice(const DevProblem &P, const RunArgs &R, StepScore &sc, int step) {
+    sc.release();
     const int any = __syncthreads_or(sc.scored ? 1 : 0);
     if (!sc.gn || !any) return;
     const int per_part = 2 * sc.gn, per_step = slice_mult(P) * sc.gn;

@@ -24,6 +24,26 @@ struct Acc {
 
 constexpr int kCollisionPending = -2;
 
+// A lane's track-length score held back while its next scores go to the
+// same tally bin (one atomic then carries their sum).
+struct Held {
+    double *a = nullptr;
+    double v = 0.0;
+    __device__ __forceinline__ void add(double *x, double w) {
+        if (x == a) {
+            v += w;
+        } else {
+            if (a) atomic_add_f64(a, v);
+            a = x;
+            v = w;
+        }
+    }
+    __device__ __forceinline__ void release() {
+        if (a) atomic_add_f64(a, v);
+        a = nullptr;
+    }
+};
+
 // Weight-window check point after an event (roulette or split).
 template <bool WW>
 __device__ __forceinline__ int ww_after(const DevProblem &P, const RunArgs &R, Particle &p, int cell, int b,
@@ -72,7 +92,8 @@ __device__ __forceinline__ int hcollide(const DevProblem &P, const RunArgs &R, P
 // m_coll), which hcollide then applies.  Split progeny go to the split bank.
 template <int FM, bool WW>
 __device__ __forceinline__ int hflight(const DevProblem &P, const RunArgs &R, Particle &p, int &cell, int b,
-                                       uint64_t hid, Acc &acc, const SplitBank &SB, int &since, int &m_coll) {
+                                       uint64_t hid, Acc &acc, const SplitBank &SB, int &since, int &m_coll,
+                                       Held &held) {
     if (since >= kMaxEventsPerStep) return kLost;
     ++since;
     const Flight f = next_event<FM>(P, p, cell);
@@ -80,7 +101,7 @@ __device__ __forceinline__ int hflight(const DevProblem &P, const RunArgs &R, Pa
     const double sc = p.w * f.d;
     const int tb = P.cell_tal[cell];
     if (tb >= 0) {
-        atomic_add_f64(tally_copy(P, R, b) + ((int64_t)p.k * P.G + p.g) * P.nts + tb, sc);
+        held.add(tally_copy(P, R, b) + ((int64_t)p.k * P.G + p.g) * P.nts + tb, sc);
         acc.track += sc;
     }
     if (P.qoi_on && P.cell_qoi[cell] && P.qoi_groups[p.g]) acc.qoi += sc;
@@ -122,9 +143,9 @@ __device__ __forceinline__ int hflight(const DevProblem &P, const RunArgs &R, Pa
 // termination code, or -1 while the particle lives.
 template <int FM, bool WW>
 __device__ __forceinline__ int hstep(const DevProblem &P, const RunArgs &R, Particle &p, int &cell, int b,
-                                     uint64_t hid, Acc &acc, const SplitBank &SB, int &since) {
+                                     uint64_t hid, Acc &acc, const SplitBank &SB, int &since, Held &held) {
     int m = 0;
-    const int code = hflight<FM, WW>(P, R, p, cell, b, hid, acc, SB, since, m);
+    const int code = hflight<FM, WW>(P, R, p, cell, b, hid, acc, SB, since, m, held);
     return code == kCollisionPending ? hcollide<FM, WW>(P, R, p, cell, b, hid, acc, SB, m) : code;
 }
 
@@ -137,12 +158,12 @@ constexpr int kCollEighths = 3;
 // termination code (also ORed into acc.term_mask).
 template <int FM, bool WW>
 __device__ __forceinline__ int track(const DevProblem &P, const RunArgs &R, Particle &p, int b, uint64_t hid,
-                                     Acc &acc, const SplitBank &SB) {
+                                     Acc &acc, const SplitBank &SB, Held &held) {
     int cell = cell_index(P, p.ix);
     int since = 0;
     int code;
     do {
-        code = hstep<FM, WW>(P, R, p, cell, b, hid, acc, SB, since);
+        code = hstep<FM, WW>(P, R, p, cell, b, hid, acc, SB, since, held);
     } while (code < 0);
     acc.term_mask |= 1u << code;
     return code;
@@ -241,6 +262,7 @@ __global__ void __launch_bounds__(256) k_history(DevProblem P0, RunArgs R, uint6
     int b = 0, cell = 0, since = 0, pm = -1;   // pm: material of a queued collision, or -1
     uint64_t i = 0;
     bool busy = false;
+    Held held;
     for (;;) {
         // idle lanes start the next histories of the chunk, once enough of
         // them are idle that the births run at a useful SIMD width
@@ -290,7 +312,7 @@ __global__ void __launch_bounds__(256) k_history(DevProblem P0, RunArgs R, uint6
             pm = -1;
         }
         if (busy && pm < 0 && code < 0) {
-            code = hflight<FM, WW>(P, R, p, cell, b, i, acc, SB, since, pm);
+            code = hflight<FM, WW>(P, R, p, cell, b, i, acc, SB, since, pm, held);
             if (code == kCollisionPending) code = -1;
             else pm = -1;
         }
@@ -300,6 +322,7 @@ __global__ void __launch_bounds__(256) k_history(DevProblem P0, RunArgs R, uint6
             busy = false;
         }
     }
+    held.release();
     // totals: wave reductions, then one atomic per counter and workgroup
 #pragma unroll
     for (int j = 0; j < kCounters; ++j) {
@@ -391,6 +414,7 @@ __global__ void __launch_bounds__(256) k_history_children(DevProblem P0, RunArgs
     int b = 0, cell = 0, since = 0, pm = -1;   // pm: material of a queued collision, or -1
     uint64_t i = 0;
     bool busy = false;
+    Held held;
     for (;;) {
         uint64_t need = __ballot(!busy);
         if (__popcll(need) < kRefillMin && need != ~0ull) need = 0;
@@ -432,7 +456,7 @@ __global__ void __launch_bounds__(256) k_history_children(DevProblem P0, RunArgs
             pm = -1;
         }
         if (busy && pm < 0 && code < 0) {
-            code = hflight<FM, true>(P, R, p, cell, b, i, acc, out, since, pm);
+            code = hflight<FM, true>(P, R, p, cell, b, i, acc, out, since, pm, held);
             if (code == kCollisionPending) code = -1;
             else pm = -1;
         }
@@ -442,6 +466,7 @@ __global__ void __launch_bounds__(256) k_history_children(DevProblem P0, RunArgs
             busy = false;
         }
     }
+    held.release();
 #pragma unroll
     for (int j = 0; j < kCounters; ++j) {
         unsigned int v = tot.c[j];
@@ -615,6 +640,7 @@ __global__ void __launch_bounds__(BS) k_history_batched(const BatchItem *__restr
     __shared__ unsigned int cnt[2][kCounters];
     const uint64_t chunk = (uint64_t)BS * per_thread;
     SplitBank none{};
+    Held held;
     for (;;) {
         if (threadIdx.x == 0) {
             base_s = atomicAdd(next, (unsigned long long)chunk);
@@ -646,7 +672,7 @@ __global__ void __launch_bounds__(BS) k_history_batched(const BatchItem *__restr
             Acc acc;
             int code = kTime;
             if (birth<FM>(it.P, history_stream(it.P, it.R.seed, i), p))
-                code = track<FM, false>(it.P, it.R, p, b, i, acc, none);
+                code = track<FM, false>(it.P, it.R, p, b, i, acc, none, held);
             if (it.R.dbg_counts) {
                 uint32_t *d = it.R.dbg_counts + i * 5;
                 d[0] = acc.n_ev[0];
@@ -682,6 +708,7 @@ __global__ void __launch_bounds__(BS) k_history_batched(const BatchItem *__restr
         }
         __syncthreads();
     }
+    held.release();
 }
 
 template <int FM, int BS>
