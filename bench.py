@@ -27,8 +27,12 @@ METRIC = "histories/sec + figure of merit 1/(σ²T), plain analog vs learned-WW,
 WORKLOAD = ("pulsed slab: 1 group, Sigma_t=1, c=0.9, v=1, 40 mfp, isotropic centre pulse at t=0, "
             "50 x-bins x 100 time bins on [0,20], 1e7 histories, FP64")
 HBM_PEAK_GBS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_event_step_pulsed_slab_1e7_traffic.json")
-LATTICE_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_event_step_lattice_1e8_traffic.json")
+# VALU issue: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz lane operations per
+# second (the non-packed vector rate; MI355X's 78.6 TFLOP/s FP64 counts an
+# FMA as two)
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "k_event_pulsed_slab_1e7_counters.json")
+LATTICE_COUNTERS_FILE = os.path.join(ROOT, "profiles", "k_event_lattice_1e8_counters.json")
 KERNEL_SOURCES = ["paper_2305_07636_amd/csrc/k_event.hip", "paper_2305_07636_amd/csrc/k_common.hpp",
                   "paper_2305_07636_amd/csrc/mcdc_internal.hpp", "paper_2305_07636_amd/build.py"]
 T_START = time.perf_counter()
@@ -112,18 +116,42 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def measured_traffic(path=TRAFFIC_FILE):
-    """HBM bytes per census-step kernel launch (the event form's k_event
-    over the step's bank) from a committed FETCH_SIZE / WRITE_SIZE
-    summary, or None if the kernel sources changed since."""
+def measured_counters(path, histories):
+    """Per-launch hardware counters of the event form's step kernel
+    (k_event) from a committed rocprofv3 summary: calibrated HBM bytes
+    (FETCH_SIZE, WRITE_SIZE) and VALU instructions per event.  None if the
+    kernel sources changed since, or the summary is of another size."""
     try:
         with open(path) as fh:
             rec = json.load(fh)
     except (OSError, ValueError):
         return None
-    if rec.get("source_sha256") != kernel_source_hash():
+    if rec.get("source_sha256") != kernel_source_hash() or rec.get("histories") != histories:
         return None
     return rec
+
+
+def atomic_ceiling(n_bins, n_ops=1 << 27):
+    """FP64 atomic adds per second that the device sustains into a table of
+    n_bins doubles at random positions (torch index_add_, one atomic per
+    index): the ceiling of a tally scored with HBM atomics."""
+    import torch
+
+    g = torch.Generator(device="cuda").manual_seed(7)
+    idx = torch.randint(0, n_bins, (n_ops,), device="cuda", generator=g)
+    val = torch.ones(n_ops, dtype=torch.float64, device="cuda")
+    tab = torch.zeros(n_bins, dtype=torch.float64, device="cuda")
+    tab.index_add_(0, idx, val)
+    torch.cuda.synchronize()
+    best = 0.0
+    for _ in range(3):
+        t0 = time.perf_counter()
+        tab.index_add_(0, idx, val)
+        torch.cuda.synchronize()
+        best = max(best, n_ops / (time.perf_counter() - t0))
+    assert float(tab.sum().item()) == 4.0 * n_ops
+    del idx, val, tab
+    return best
 
 
 def batched_section(m, w):
@@ -468,7 +496,7 @@ def fom_section(w, pilots, n_analog_run, analog_runs, n_ww, ww_runs, steps):
     return res
 
 
-def timed_runs(m, p, N, seed, steps, warmup, alg, traffic_file=None, label="slab"):
+def timed_runs(m, p, N, seed, steps, warmup, alg, counters_file=None, label="slab", bound="alu", n_bins=0):
     """Untimed warm-up runs and one profiled run (HIP events around every
     launch: it names the dominant kernel class), then `steps` timed runs of
     N histories.  In the timed region HIP events bracket only the dominant
@@ -501,23 +529,46 @@ def timed_runs(m, p, N, seed, steps, warmup, alg, traffic_file=None, label="slab
     log(f"{label}: {steps} timed runs of {N:.0e} histories, {elapsed / steps * 1e3:.2f} ms per run")
     ms, launches, items, nbytes = prof[cls]
     if alg == "event":
-        achieved = nbytes / (ms * 1e-3) / 1e9
-        tr = measured_traffic(traffic_file) if (traffic_file and names[cls] == "events") else None
-        if tr and tr.get("histories") != N:
-            tr = None
-        roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": achieved / HBM_PEAK_GBS,
-                    "traffic": tr["hbm_bytes_per_launch"] if tr else None,
-                    "kernel": "k_event (one census step: every particle of the step's bank to census or death)"
-                              if names[cls] == "events" else f"k_{names[cls]}",
-                    "launches": int(launches), "avg_launch_ms": ms / launches,
-                    "algorithmic_bytes_per_launch": nbytes / launches,
-                    "particles_per_launch": items / launches,
-                    "timed_launches": f"timed run s brackets census steps k = s mod {steps} with HIP "
-                                      f"events on the library's stream (each census step once)"}
-        if tr:
-            roofline["traffic_source"] = os.path.relpath(traffic_file, ROOT)
-            roofline["traffic_over_algorithmic"] = tr["hbm_bytes_per_launch"] / (nbytes / launches)
+        # the step kernel takes a chunk's census steps in one launch; every
+        # event of the run happens in it
+        t_launch = ms / launches * 1e-3
+        per_run = brk[cls, 1]
+        ev_launch = float(sum(last["events"])) / per_run
+        hbm = nbytes / launches / t_launch / 1e9
+        cn = measured_counters(counters_file, N) if (counters_file and names[cls] == "events") else None
+        traffic = cn["hbm_bytes_per_launch"] if cn else None
+        common = {"kernel": "k_event (a chunk's census steps: every particle to death or the last edge)"
+                            if names[cls] == "events" else f"k_{names[cls]}",
+                  "launches": int(launches), "launches_per_run": int(per_run), "avg_launch_ms": t_launch * 1e3,
+                  "events_per_launch": ev_launch,
+                  "algorithmic_bytes_per_launch": nbytes / launches, "particles_per_launch": items / launches,
+                  "hbm": {"achieved": hbm, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": hbm / HBM_PEAK_GBS},
+                  "timed_launches": f"timed run s brackets the launches j = s mod {steps} of the step kernel "
+                                    f"with HIP events on the library's stream (each launch once)",
+                  "counters_source": os.path.relpath(counters_file, ROOT) if cn else None}
+        if bound == "alu":
+            # VALU issue: the compiled kernel's VALU instructions per event
+            # (SQ_INSTS_VALU over the events of the profiled launches, wave64
+            # instructions of 64 lane slots each) times the events of a launch
+            per_ev = cn["valu_insts_per_event"] if cn else None
+            ach = per_ev * ev_launch * 64 / t_launch / 1e12 if per_ev else None
+            roofline = {"bound": "alu", "achieved": ach, "peak": VALU_PEAK_TOPS,
+                        "unit": "TOP/s (VALU lane-operation issue slots)",
+                        "frac": ach / VALU_PEAK_TOPS if ach else None, "traffic": traffic,
+                        "valu_insts_per_event": per_ev}
+        else:
+            # FP64 atomics to the HBM tally: the atomics of a launch (its
+            # WRITE_SIZE bytes in 32-byte atomic requests) over the device's
+            # atomic ceiling measured here
+            ceil = atomic_ceiling(n_bins)
+            n_at = cn["atomics_per_launch"] if cn else None
+            ach = n_at / t_launch / 1e9 if n_at else None
+            roofline = {"bound": "atomics", "achieved": ach, "peak": ceil / 1e9,
+                        "unit": "G FP64 atomics/s (peak: measured ceiling, torch index_add_ into the "
+                                "same number of bins)",
+                        "frac": ach / (ceil / 1e9) if ach else None, "traffic": traffic,
+                        "atomics_per_launch": n_at}
+        roofline.update(common)
     else:
         # history form: state in registers; bounded by FP64 vector ALU and
         # divergence, reported as events per second
@@ -644,7 +695,8 @@ def lattice_section(m, w, n, steps, warmup):
                        "histories, FP64",
            "histories": n}
     try:
-        ev = timed_runs(m, h, n, 3, steps, warmup, "event", LATTICE_TRAFFIC_FILE, label="lattice event")
+        ev = timed_runs(m, h, n, 3, steps, warmup, "event", LATTICE_COUNTERS_FILE, label="lattice event",
+                        bound="atomics", n_bins=17 * 17 * 10 * 7 * 20 * 32)
         res["event_histories_per_s"] = ev["value"]
         res["event_ms"] = ev["elapsed"] / steps * 1e3
         res["events_per_history"] = [float(x) / n for x in ev["last"]["events"]]
@@ -733,7 +785,7 @@ def main():
         return m.mcdc_run(p, N, seed + s, algorithm=alg, outputs=outs, **kw)
 
     log("problem on the GPU")
-    head = timed_runs(m, p, N, seed, args.steps, args.warmup, args.algorithm, TRAFFIC_FILE)
+    head = timed_runs(m, p, N, seed, args.steps, args.warmup, args.algorithm, COUNTERS_FILE)
     value, elapsed, roofline, per_class, last = (head["value"], head["elapsed"], head["roofline"],
                                                  head["per_class"], head["last"])
     extra = {}

@@ -11,13 +11,15 @@
  * weight and no variance reduction (Section 3.3).  The tracking runs in two
  * forms the paper names (Section 2): history-based (one GPU thread follows
  * one particle to its death) and event-based (the particles of a census
- * step live in a structure-of-arrays bank; by default one kernel per census
- * step takes every particle of the step's bank through its events in
- * registers, refilling idle lanes from the bank, and files the census
- * crossers into the next step's bank with wave-ballot appends; with
+ * step live in a structure-of-arrays bank; by default one launch of the
+ * step kernel takes every particle of a bank chunk through its events and
+ * across the census edges in registers, refilling idle lanes from the
+ * bank, with each wave running queued collisions for many lanes at once;
+ * with fewer census steps per launch the crossers of the launch's last
+ * edge go to the next bank with wave-ballot appends; with
  * MCDC_FLAG_TWO_KERNEL_STEP an advance kernel sorts the particles into
  * per-event census, surface and collision queues and an events kernel
- * works the queues).
+ * works the queues, one census step at a time).
  *
  * Conventions shared by every entry point
  *  - Units are arbitrary but consistent (length, 1/length, length/time,
@@ -223,10 +225,11 @@ typedef struct {
  *  bank_capacity  event form: particles resident at once (0 = auto).  Work
  *                 is processed in chunks of this many histories.  History
  *                 form with weight windows or fission: histories per chunk
- *                 (0 = auto: 2^21, 2^20 with fission); each generation of
- *                 a chunk's progeny must fit a split bank of 32 (64 with
- *                 fission) entries per history, at least 2^22 and at most
- *                 2^26, else the run ends with MCDC_E_OVERFLOW.  In
+ *                 (0 = auto: 2^23, 2^20 with fission).  Each generation
+ *                 of a chunk's progeny (both forms) must fit a split bank
+ *                 of 32 (64 with fission) entries per history of the
+ *                 chunk, at least 2^22 and at most 2^26, else the run ends
+ *                 with MCDC_E_OVERFLOW.  In
  *                 mcdc_run_batched's event form: slots per bank segment.
  *  flags          bit 0 (MCDC_FLAG_EAGER): launch the event form's census
  *                 steps one kernel at a time instead of replaying the

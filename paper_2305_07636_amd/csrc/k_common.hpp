@@ -44,6 +44,18 @@ __device__ __forceinline__ uint64_t history_stream(const DevProblem &P, uint64_t
     return s & kMask63;
 }
 
+// The stream of the history n after the one whose stream is s (the maps
+// compose: history_stream(i + n) = stream_skip(history_stream(i), n)).
+__device__ __forceinline__ uint64_t stream_skip(const DevProblem &P, uint64_t s, uint64_t n) {
+    int j = 0;
+    while (n) {
+        if (n & 1ULL) s = P.skipA[j] * s + P.skipC[j];
+        n >>= 1;
+        ++j;
+    }
+    return s & kMask63;
+}
+
 // SplitMix64 finaliser over parent ^ j (Steele, Lea & Flood, OOPSLA 2014):
 // the stream of the j-th split child, masked to 63 bits.
 __device__ __forceinline__ uint64_t child_stream(uint64_t parent, uint64_t j) {

@@ -460,16 +460,23 @@ __global__ void __launch_bounds__(BS) k_source(DevProblem P0, RunArgs R0, Bank b
     if (threadIdx.x == 0)
         C.seg_b0[seg] = (lo < hi) ? (int)(((first + lo + 1) * (uint64_t)R.B - 1) / R.N) : 0;
     __syncthreads();
+    // the thread's histories are BS apart: one full skip-ahead to the
+    // first, then the map for BS histories (BS a power of two)
+    constexpr int lbs = (BS == 1024) ? 10 : (BS == 512 ? 9 : (BS == 256 ? 8 : (BS == 128 ? 7 : 6)));
+    static_assert((1 << lbs) == BS, "workgroup size must be a power of two");
+    uint64_t s_next = history_stream(P, R.seed, first + lo + threadIdx.x);
     for (uint64_t base = lo; base < hi; base += BS) {
         const uint64_t r = base + threadIdx.x;
         const bool valid = r < hi;
         Particle p;
         bool alive = false;
         int b = 0;
+        const uint64_t s0 = s_next;
+        s_next = (P.skipA[lbs] * s_next + P.skipC[lbs]) & kMask63;
         if (valid) {
             const uint64_t i = first + r;
             b = (int)(((i + 1) * (uint64_t)R.B - 1) / R.N);
-            alive = birth<FM>(P, history_stream(P, R.seed, i), p);
+            alive = birth<FM>(P, s0, p);
             if (R.dbg_counts) R.dbg_counts[i * 5 + 3] = 1u;
             if (!alive) {
                 cnt.add(3 + kTime);
@@ -1813,7 +1820,7 @@ int run_event_lt(mcdc_problem *p, const RunArgs &R, uint64_t first, uint64_t cou
 // the two-kernel step with the queue sort at every c-th census step)
 template <int FM, bool LT, int BS>
 int run_batched_steps(const BatchItem *d_items, const SegInfo *d_segs, unsigned int G, unsigned int Lseg, int Kmax,
-                      size_t shmem, void *bank_mem, void *ctl_mem, hipStream_t st, int step_form) {
+                      size_t shmem, void *bank_mem, void *ctl_mem, hipStream_t st, int step_form, int ns) {
     const uint64_t slots = (uint64_t)G * Lseg;
     Layout L = carve(bank_mem, ctl_mem, slots, G, Lseg, FM, false, step_form > 0 ? 4 : 3);
     const DevProblem P0{};
@@ -1835,7 +1842,7 @@ int run_batched_steps(const BatchItem *d_items, const SegInfo *d_segs, unsigned 
         if (step_form < 0) {
             hipLaunchKernelGGL((k_event<FM, false, LT, true, MCDC_PROF_EVENTS, true, BS>), dim3(G), dim3(BS), shmem,
                                cs, P0, R0, L.bank[q], L.bank[q ^ 1], L.ctl, q, 0, none, t0, d_items, d_segs, L.srt,
-                               0, 1);
+                               0, ns);
         } else {
             hipLaunchKernelGGL((k_advance<FM, false, LT, true, MCDC_PROF_ADVANCE, BS>), dim3(G), dim3(BS), shmem, cs, P0, R0, L.bank[q],
                                L.bank[q ^ 1], L.ev, L.ctl, q, 0, none, t0, d_items, d_segs);
@@ -1845,11 +1852,13 @@ int run_batched_steps(const BatchItem *d_items, const SegInfo *d_segs, unsigned 
             hipLaunchKernelGGL((k_event<FM, false, LT, true, MCDC_PROF_EVENTS, false, BS>), dim3(G), dim3(BS), shmem, cs, P0, R0, L.ev,
                                L.bank[q ^ 1], L.ctl, q, 0, none, t0, d_items, d_segs, L.srt, step_form, 1);
         }
-        hipLaunchKernelGGL(k_step_end, dim3(1), dim3(1), 0, cs, L.ctl, 1);
+        hipLaunchKernelGGL(k_step_end, dim3(1), dim3(1), 0, cs, L.ctl, step_form < 0 ? ns : 1);
         e = hipStreamEndCapture(cs, &graph[q]);
         if (e == hipSuccess) e = hipGraphInstantiate(&exec[q], graph[q], nullptr, nullptr, 0);
     }
-    for (int k = 0; k < Kmax && e == hipSuccess; ++k) e = hipGraphLaunch(exec[k & 1], st);
+    // (one-kernel form: ns census steps per launch)
+    const int launches = step_form < 0 ? (Kmax + ns - 1) / ns : Kmax;
+    for (int k = 0; k < launches && e == hipSuccess; ++k) e = hipGraphLaunch(exec[k & 1], st);
     hipError_t e2 = hipStreamSynchronize(st);
     for (int q = 0; q < 2; ++q) {
         if (exec[q]) (void)hipGraphExecDestroy(exec[q]);
@@ -1907,9 +1916,18 @@ int launch_event_batched(std::vector<BatchItem> &items, const uint64_t *n_hist, 
         fm = (fm < 0 || fm == P.finite_mask) ? P.finite_mask : 0;
         if (P.K > Kmax) Kmax = P.K;
     }
+    // one-kernel form: as many census steps per launch as every problem's
+    // LDS slice holds (all of them when no slice limits it)
+    int ns = 1;
+    if (step_form < 0) {
+        const int64_t lds_max = (block == 1024) ? kLdsStepsMax : kLdsTallyMax;
+        ns = Kmax > 0 ? Kmax : 1;
+        for (int j = 0; j < n; ++j)
+            while (items[j].gn && ns > 1 && slice_mult(items[j].P) * (int64_t)items[j].gn * ns > lds_max) --ns;
+    }
     size_t shmem = 0;
     for (int j = 0; j < n; ++j) {
-        const size_t b = (size_t)slice_mult(items[j].P) * items[j].gn * sizeof(double) +
+        const size_t b = (size_t)slice_mult(items[j].P) * items[j].gn * ns * sizeof(double) +
                          (lt_all ? (size_t)items[j].tabs.bytes : 0);
         if (b > shmem) shmem = b;
     }
@@ -1932,16 +1950,25 @@ int launch_event_batched(std::vector<BatchItem> &items, const uint64_t *n_hist, 
     const int sf = step_form;
     auto go = [&](auto bs_tag) -> int {
         constexpr int BS = decltype(bs_tag)::value;
-        if (fm == 1)
-            return lt_all ? run_batched_steps<1, true, BS>(d_items, d_segs, lay.G, seg_len, Kmax, shmem, bank, ctl, st, sf)
-                          : run_batched_steps<1, false, BS>(d_items, d_segs, lay.G, seg_len, Kmax, shmem, bank, ctl, st,
-                                                            sf);
-        if (fm == 7)
-            return lt_all ? run_batched_steps<7, true, BS>(d_items, d_segs, lay.G, seg_len, Kmax, shmem, bank, ctl, st, sf)
-                          : run_batched_steps<7, false, BS>(d_items, d_segs, lay.G, seg_len, Kmax, shmem, bank, ctl, st,
-                                                            sf);
-        return lt_all ? run_batched_steps<0, true, BS>(d_items, d_segs, lay.G, seg_len, Kmax, shmem, bank, ctl, st, sf)
-                      : run_batched_steps<0, false, BS>(d_items, d_segs, lay.G, seg_len, Kmax, shmem, bank, ctl, st, sf);
+        auto one = [&](auto fm_tag, auto lt_tag) -> int {
+            constexpr int F = decltype(fm_tag)::value;
+            constexpr bool T = decltype(lt_tag)::value;
+            if (shmem > 65536) {
+                hipError_t ea = hipFuncSetAttribute(
+                    reinterpret_cast<const void *>(&k_event<F, false, T, true, MCDC_PROF_EVENTS, true, BS>),
+                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+                if (ea != hipSuccess) return hip_fail(ea, "LDS size of the batched multi-step launch");
+            }
+            return run_batched_steps<F, T, BS>(d_items, d_segs, lay.G, seg_len, Kmax, shmem, bank, ctl, st, sf, ns);
+        };
+        using I1 = std::integral_constant<int, 1>;
+        using I7 = std::integral_constant<int, 7>;
+        using I0 = std::integral_constant<int, 0>;
+        using BT = std::true_type;
+        using BF = std::false_type;
+        if (fm == 1) return lt_all ? one(I1{}, BT{}) : one(I1{}, BF{});
+        if (fm == 7) return lt_all ? one(I7{}, BT{}) : one(I7{}, BF{});
+        return lt_all ? one(I0{}, BT{}) : one(I0{}, BF{});
     };
     if (block == 256) return go(std::integral_constant<int, 256>{});
     if (block == 1024) return go(std::integral_constant<int, 1024>{});

@@ -254,6 +254,7 @@ __global__ void __launch_bounds__(256) k_history(DevProblem P0, RunArgs R, uint6
     __syncthreads();
 
     uint64_t c_pos = 0, c_end = 0;   // the wave's current chunk (wave-uniform)
+    uint64_t s_pos = 0;              // the stream of history first + c_pos
     bool drained = false;            // the device counter has passed the end
     LaneTotals tot;
     tot.init();
@@ -279,17 +280,21 @@ __global__ void __launch_bounds__(256) k_history(DevProblem P0, RunArgs R, uint6
                 }
                 c_pos = base;
                 c_end = (base + wave_chunk < count) ? base + wave_chunk : count;
+                s_pos = history_stream(P, R.seed, first + c_pos);
             }
             const uint64_t avail = c_end - c_pos;
             const uint32_t rank =
                 __builtin_amdgcn_mbcnt_hi((uint32_t)(need >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)need, 0u));
             const uint32_t n_need = (uint32_t)__popcll(need);
+            const uint32_t taken = (n_need < avail) ? n_need : (uint32_t)avail;
             if (!busy && rank < avail) {
                 i = first + c_pos + rank;
                 b = (int)(((i + 1) * (uint64_t)R.B - 1) / R.N);
                 acc = Acc();
                 ++tot.started;
-                if (birth<FM>(P, history_stream(P, R.seed, i), p)) {
+                // (the stream from the wave's position in its chunk: at most
+                // 64 histories ahead)
+                if (birth<FM>(P, stream_skip(P, s_pos, rank), p)) {
                     cell = cell_index(P, p.ix);
                     since = 0;
                     pm = -1;
@@ -299,7 +304,8 @@ __global__ void __launch_bounds__(256) k_history(DevProblem P0, RunArgs R, uint6
                     end_history<WW>(P, R, acc, kTime, i, chunk_first, tot);
                 }
             }
-            c_pos += (n_need < avail) ? n_need : avail;
+            c_pos += taken;
+            if (c_pos < c_end) s_pos = stream_skip(P, s_pos, taken);
             need = __ballot(!busy);
         }
         const int n_busy = __popcll(__ballot(busy));
@@ -749,8 +755,10 @@ int launch_batched(const BatchItem *items, const uint64_t *offs, int n_items, ui
 }
 
 int split_prepare(mcdc_problem *pb, uint64_t chunk, dev::SplitBank SB[2]) {
-    // room for 32 progeny per history of the chunk in each generation
-    // (64 with fission; implicit capture alone makes none: the minimum)
+    // room for 32 progeny per history of the chunk in each generation (64
+    // with fission; implicit capture alone makes none: the minimum), at
+    // most 2^26 entries per bank (7.5 GB): 8 per history at the default
+    // chunk of 2^23 histories
     const uint64_t per = pb->d.fission_on ? 64 : (pb->d.ww_center ? 32 : 0);
     const uint64_t want = per * chunk;
     const unsigned int cap = (unsigned int)((want < (1u << 22)) ? (1u << 22) : (want > (1u << 26) ? (1u << 26) : want));

@@ -16,7 +16,7 @@ namespace mcdc {
 constexpr int kMaxGroups = 32;      // outgoing-group search is unrolled over this
 constexpr int kCounters = 10;       // census, surface, collision; 5 terminations; splits; fission progeny
 constexpr int kLdsTallyMax = 4096;  // doubles of the event form's per-step LDS tally slice
-constexpr uint64_t kWindowChunk = 1ULL << 21;  // histories per chunk of a weight-window run
+constexpr uint64_t kWindowChunk = 1ULL << 23;  // histories per chunk of a weight-window run
 constexpr uint64_t kFissionChunk = 1ULL << 20; // histories per chunk of a run with fission
 constexpr double kMaxNu = 64.0;                // largest mean number of neutrons per fission
 constexpr uint64_t kStride = 152917ULL;

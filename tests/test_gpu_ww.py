@@ -67,8 +67,9 @@ def test_ww_overflow_reported(alg):
 @pytest.mark.gpu
 def test_ww_forms_agree_at_full_size():
     """Windowed runs of the two forms, 1e7 histories of the dog-leg duct
-    (five chunks of 2^21 histories in both forms; the windows split about
-    64 times per history): the same counts, splits and detector sums."""
+    in five chunks of 2^21 histories (the windows split about 64 times per
+    history, more than the default chunk of 2^23 holds): the same counts,
+    splits and detector sums."""
     import paper_2305_07636_amd as m
     from gpu_common import close
 
@@ -77,8 +78,8 @@ def test_ww_forms_agree_at_full_size():
     h = m.mcdc_problem_create(p)
     try:
         m.mcdc_set_weight_windows(h, table, 5.0, 16)
-        a = m.mcdc_run(h, 10_000_000, 12, algorithm="history")
-        b = m.mcdc_run(h, 10_000_000, 12, algorithm="event")
+        a = m.mcdc_run(h, 10_000_000, 12, algorithm="history", bank_capacity=1 << 21)
+        b = m.mcdc_run(h, 10_000_000, 12, algorithm="event", bank_capacity=1 << 21)
     finally:
         h.close()
     assert np.array_equal(a["events"], b["events"]) and np.array_equal(a["terms"], b["terms"])
