@@ -93,9 +93,11 @@ def lib():
         _lib.oracle_eigen.argtypes = [C.c_void_p, C.c_uint64, C.c_int, C.c_int, C.c_uint64,
                                       C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
         _lib.oracle_run_pc.restype = C.c_int
-        _lib.oracle_run_pc.argtypes = [C.c_void_p, C.c_uint64, C.c_uint64, C.c_uint64,
+        _lib.oracle_run_pc.argtypes = [C.c_void_p, C.c_uint64, C.c_uint64, C.c_uint64, C.c_int,
                                        C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                        C.c_void_p]
+        _lib.oracle_comb.restype = C.c_int
+        _lib.oracle_comb.argtypes = [C.c_void_p, C.c_int64, C.c_uint64, C.c_double, C.c_void_p]
         _lib.oracle_q64_sum.restype = C.c_int
         _lib.oracle_q64_sum.argtypes = [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]
         _lib.oracle_trace.restype = C.c_int
@@ -281,11 +283,12 @@ def run(prob, N: int, seed: int, ids=None, first: int = 0, count=None,
     return out
 
 
-def run_pc(prob, N: int, seed: int, target: int):
-    """An N-history run with population control at every census edge
-    (splitting-roulette to `target` particles, the oracle's reading R16).
-    Returns the dict of ``run`` (no detector, no records) plus 'pop' [K]:
-    particles alive at each edge T_k after the control (pop[0]: born)."""
+def run_pc(prob, N: int, seed: int, target: int, method: str = "split"):
+    """An N-history run with population control at every census edge to
+    `target` particles: splitting-roulette (method "split", the oracle's
+    reading R16) or combing ("comb", R28).  Returns the dict of ``run`` (no
+    detector, no records) plus 'pop' [K]: particles alive at each edge T_k
+    after the control (pop[0]: born)."""
     op = prob if isinstance(prob, OracleProblem) else OracleProblem(prob)
     B = max(1, min(op.B, N))
     S = np.zeros((B, op.ntally))
@@ -293,12 +296,24 @@ def run_pc(prob, N: int, seed: int, target: int):
     L = np.zeros((B, op.K, op.G, 6))
     tot = np.zeros(10, dtype=np.uint64)
     pop = np.zeros(op.K, dtype=np.uint64)
-    rc = lib().oracle_run_pc(op.ptr(), N, seed, target, S.ctypes.data, L.ctypes.data,
+    m = {"split": 0, "comb": 1}[method]
+    rc = lib().oracle_run_pc(op.ptr(), N, seed, target, m, S.ctypes.data, L.ctypes.data,
                              tot.ctypes.data, X.ctypes.data, pop.ctypes.data)
     if rc != 0:
         raise RuntimeError(f"oracle_run_pc failed with code {rc}")
     return {"S": S, "X": X, "L": L, "q": np.zeros(2), "tot": tot, "N": N, "B": B, "op": op,
             "pop": pop}
+
+
+def comb(w, M: int, u: float) -> np.ndarray:
+    """R28's copies of the weights w, taken in the given order, for a comb
+    of M teeth at offset u in [0, 1)."""
+    w = np.ascontiguousarray(np.asarray(w, dtype=np.float64))
+    out = np.zeros(w.size, dtype=np.uint64)
+    rc = lib().oracle_comb(w.ctypes.data, w.size, M, float(u), out.ctypes.data)
+    if rc != 0:
+        raise ValueError("weights with a zero total, or a weight of 2^32 or more")
+    return out
 
 
 def q64_sum(w) -> tuple:

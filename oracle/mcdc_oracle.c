@@ -113,6 +113,23 @@
  *       j >= 1 takes child_stream of that state and j (as R10's splits) and
  *       counts as a split.  W = 0: nothing happens.  Analog tracking with
  *       optional implicit capture only (no windows, fission or detector).
+ *   R28 Population control by combing (optional, the other census method
+ *       Section 2's population control names): the same particles as R16
+ *       at each edge T_k, put in one order that depends on nothing but the
+ *       particles -- ascending history index, then ascending stream state
+ *       (two particles agreeing in both are the same particle in every
+ *       respect the control reads, so their order does not matter).  With
+ *       q_r their R16 fixed-point weights, P_r the exact sum of the q before
+ *       r, W the total and D(.) R16's conversion to a double, one draw u of
+ *       the edge's own stream child_stream(seed, 2^62 + k) sets the teeth
+ *       at (u + j) W / M, j = 0 .. M-1, M the target.  The number of teeth
+ *       below a point x is T(x) = ceil((D(x) / D(W)) M - u) clipped to
+ *       [0, M], and particle r becomes n_r = T(P_r + q_r) - T(P_r) copies
+ *       of weight w_t = D(W) / M (n_r = 0: rouletted).  T(0) = 0 and
+ *       T(W) = M, so exactly M particles go on; n_r is the floor or the
+ *       ceiling of M q_r / W, and its mean over u is M q_r / W up to the
+ *       doubles' rounding.  Copy 0 keeps the particle's stream (no draw),
+ *       copy j >= 1 takes child_stream of it and j and counts as a split.
  *   R27 Moving plane (optional; Section 3 lists time-dependent surfaces
  *       for continuous object movement, and runs control-rod transients
  *       with them): one plane normal to z whose height is linear in time
@@ -1202,6 +1219,7 @@ int oracle_q64_sum(const double *w, int64_t n, uint64_t *out, double *value)
 typedef struct {
     particle pt;
     int b;
+    uint64_t i;   /* history index */
 } pc_entry;
 
 typedef struct {
@@ -1209,7 +1227,7 @@ typedef struct {
     size_t n, cap;
 } pc_list;
 
-static int pc_push(pc_list *L, const particle *pt, int b)
+static int pc_push(pc_list *L, const particle *pt, int b, uint64_t i)
 {
     if (L->n == L->cap) {
         size_t cap = L->cap ? 2 * L->cap : 1024;
@@ -1220,21 +1238,66 @@ static int pc_push(pc_list *L, const particle *pt, int b)
     }
     L->e[L->n].pt = *pt;
     L->e[L->n].b = b;
+    L->e[L->n].i = i;
     L->n++;
     return 0;
 }
 
-/* R16: an N-history run with population control to `target` particles at
- * every census edge.  Outputs as oracle_run (totals: roulette terminations
+/* R16's conversion of a fixed-point weight sum to a double. */
+static double q64_value(uint64_t hi, uint64_t lo)
+{
+    return (double)hi + ((double)(lo >> 32) * 0x1p-32 + (double)(lo & 0xFFFFFFFFULL) * 0x1p-64);
+}
+
+/* R28: teeth of the comb below the fixed-point point (hi, lo). */
+static uint64_t comb_teeth(uint64_t hi, uint64_t lo, double dW, uint64_t M, double u)
+{
+    const double y = (q64_value(hi, lo) / dW) * (double)M - u;
+    const double c = ceil(y);
+    if (!(c > 0.0)) return 0;
+    if (c >= (double)M) return M;
+    return (uint64_t)c;
+}
+
+/* R28: copies n[r] of n weights w[r] taken in the given order, for M
+ * teeth at offset u.  Returns 0, or -1 as q64_add (or an empty total). */
+int oracle_comb(const double *w, int64_t n, uint64_t M, double u, uint64_t *out)
+{
+    uint64_t hi = 0, lo = 0;
+    for (int64_t r = 0; r < n; r++)
+        if (q64_add(&hi, &lo, w[r]) != 0) return -1;
+    if (hi == 0 && lo == 0) return -1;
+    const double dW = q64_value(hi, lo);
+    uint64_t ph = 0, pl = 0;
+    for (int64_t r = 0; r < n; r++) {
+        const uint64_t t0 = comb_teeth(ph, pl, dW, M, u);
+        q64_add(&ph, &pl, w[r]);
+        out[r] = comb_teeth(ph, pl, dW, M, u) - t0;
+    }
+    return 0;
+}
+
+static const pc_entry *pc_sort_base;
+static int pc_order(const void *a, const void *b)
+{
+    const pc_entry *x = pc_sort_base + *(const size_t *)a, *y = pc_sort_base + *(const size_t *)b;
+    if (x->i != y->i) return x->i < y->i ? -1 : 1;
+    if (x->pt.s != y->pt.s) return x->pt.s < y->pt.s ? -1 : 1;
+    return 0;
+}
+
+/* R16 / R28: an N-history run with population control to `target`
+ * particles at every census edge (method 0: splitting-roulette, R16; 1:
+ * combing, R28).  Outputs as oracle_run (totals: roulette terminations
  * include the controlled-away particles, splits the extra copies); pop[k]
  * (k = 0..K-1, may be NULL) receives the particles alive at T_k after the
  * control (pop[0]: particles born).  Returns 0, -1 invalid problem, -3 a
  * problem with windows, fission or a detector, -4 a weight of 2^32 or more,
  * -2 out of memory. */
-int oracle_run_pc(const oracle_problem *p, uint64_t N, uint64_t seed, uint64_t target,
+int oracle_run_pc(const oracle_problem *p, uint64_t N, uint64_t seed, uint64_t target, int method,
                   double *S_out, double *L_out, uint64_t *tot_out, double *X_out, uint64_t *pop)
 {
-    if (p->ww_center || p->sigma_f || p->qoi_on || target == 0) return -3;
+    if (p->ww_center || p->sigma_f || p->qoi_on || target == 0 || method < 0 || method > 1) return -3;
     ctx C;
     if (ctx_init(&C, p) != 0) {
         ctx_free(&C);
@@ -1263,7 +1326,7 @@ int oracle_run_pc(const oracle_problem *p, uint64_t N, uint64_t seed, uint64_t t
         memset(&h, 0, sizeof(h));
         particle pt;
         if (birth(&C, oracle_rng_skip(s0, i * LCG_STRIDE), &pt, &h)) {
-            if (pc_push(&cur, &pt, b)) rc = -2;
+            if (pc_push(&cur, &pt, b, i)) rc = -2;
             if (pop) pop[0]++;
         }
     }
@@ -1273,6 +1336,7 @@ int oracle_run_pc(const oracle_problem *p, uint64_t N, uint64_t seed, uint64_t t
         for (size_t r = 0; r < cur.n && rc == 0; r++) {
             particle pt = cur.e[r].pt;
             const int b = cur.e[r].b;
+            const uint64_t hid = cur.e[r].i;
             if (pt.k == k) {
                 int sp = 0, alive;
                 memset(&h, 0, sizeof(h));
@@ -1282,7 +1346,7 @@ int oracle_run_pc(const oracle_problem *p, uint64_t N, uint64_t seed, uint64_t t
                 if (alive < 0 || sp != 0) rc = -3;
                 if (alive <= 0) continue;
             }
-            if (pc_push(&nxt, &pt, b)) rc = -2;
+            if (pc_push(&nxt, &pt, b, hid)) rc = -2;
         }
         if (rc) break;
         /* control at T_{k+1} over its crossers (those with clock k + 1) */
@@ -1291,20 +1355,51 @@ int oracle_run_pc(const oracle_problem *p, uint64_t N, uint64_t seed, uint64_t t
             if (nxt.e[r].pt.k == k + 1 && q64_add(&hi, &lo, nxt.e[r].pt.w) != 0) rc = -4;
         if (rc) break;
         cur.n = 0;
-        const double W = (double)hi + ((double)(lo >> 32) * 0x1p-32 + (double)(lo & 0xFFFFFFFFULL) * 0x1p-64);
+        const double W = q64_value(hi, lo);
         const double wt = W / (double)target;
+        /* R28: the comb's copies of each controlled particle, in the
+           particles' own order */
+        uint64_t *ncomb = NULL;
+        if (method == 1 && (hi != 0 || lo != 0)) {
+            size_t nc = 0;
+            size_t *ord = (size_t *)malloc(sizeof(size_t) * (nxt.n ? nxt.n : 1));
+            ncomb = (uint64_t *)calloc(nxt.n ? nxt.n : 1, sizeof(uint64_t));
+            if (!ord || !ncomb) {
+                free(ord);
+                rc = -2;
+                break;
+            }
+            for (size_t r = 0; r < nxt.n; r++)
+                if (nxt.e[r].pt.k == k + 1) ord[nc++] = r;
+            pc_sort_base = nxt.e;
+            qsort(ord, nc, sizeof(size_t), pc_order);
+            uint64_t su = oracle_child_stream(s0, (1ULL << 62) + (uint64_t)(k + 1));
+            const double u = rn(&su);
+            uint64_t ph = 0, pl = 0;
+            for (size_t q = 0; q < nc; q++) {
+                const uint64_t t0 = comb_teeth(ph, pl, W, target, u);
+                q64_add(&ph, &pl, nxt.e[ord[q]].pt.w);
+                ncomb[ord[q]] = comb_teeth(ph, pl, W, target, u) - t0;
+            }
+            free(ord);
+        }
         uint64_t alive_at = 0;
         for (size_t r = 0; r < nxt.n && rc == 0; r++) {
             particle pt = nxt.e[r].pt;
             const int b = nxt.e[r].b;
+            const uint64_t hid = nxt.e[r].i;
             if (pt.k != k + 1 || (hi == 0 && lo == 0)) {
-                if (pc_push(&cur, &pt, b)) rc = -2;
+                if (pc_push(&cur, &pt, b, hid)) rc = -2;
                 if (pt.k == k + 1) alive_at++;
                 continue;
             }
-            double xi = rn(&pt.s);
-            double nr = floor(pt.w / wt + xi);
-            uint64_t n = (uint64_t)nr;
+            uint64_t n;
+            if (method == 1) {
+                n = ncomb[r];
+            } else {
+                double xi = rn(&pt.s);
+                n = (uint64_t)floor(pt.w / wt + xi);
+            }
             if (n == 0) {
                 C.tot[3 + T_ROULETTE]++;
                 continue;
@@ -1317,10 +1412,11 @@ int oracle_run_pc(const oracle_problem *p, uint64_t N, uint64_t seed, uint64_t t
                     c.s = splitmix64(sf ^ j) & MASK63;
                     C.tot[8]++;
                 }
-                if (pc_push(&cur, &c, b)) rc = -2;
+                if (pc_push(&cur, &c, b, hid)) rc = -2;
             }
             alive_at += n;
         }
+        free(ncomb);
         if (pop && k + 1 < C.K) pop[k + 1] = alive_at;
     }
     if (rc == 0) {
