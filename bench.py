@@ -240,10 +240,11 @@ def fission_section(m, w, n, steps):
 
 def population_control_section(m, w, n, steps, cpu=True):
     """The pulsed slab with population control at every census edge
-    (splitting-roulette back to n particles; event form): histories/s, the
-    control kernels' share, and the figure of merit 1/(R^2 T) of the
-    spatially integrated flux in the last time bin against the analog run
-    (the population otherwise decays by e^-2 over the 100 steps)."""
+    (splitting-roulette, and combing, back to n particles; event form):
+    histories/s, the control kernels' share, and the figure of merit
+    1/(R^2 T) of the spatially integrated flux in the last time bin against
+    the analog run (the population otherwise decays by e^-2 over the 100
+    steps)."""
     import numpy as np
     import torch
 
@@ -253,7 +254,8 @@ def population_control_section(m, w, n, steps, cpu=True):
                        f"{n:.0e} histories, population held at {n:.0e} at each of the 99 inner census edges",
            "histories": n}
     try:
-        for tag, kw in (("analog", {}), ("controlled", {"pc_target": n})):
+        for tag, kw in (("analog", {}), ("controlled", {"pc_target": n}),
+                        ("combed", {"pc_target": n, "pc_method": "comb"})):
             out = m.mcdc_run(h, n, 90, outputs=("mean", "var"), **kw)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -269,16 +271,18 @@ def population_control_section(m, w, n, steps, cpu=True):
             res[f"{tag}_events_per_history"] = float(sum(out["events"])) / n
             res[f"{tag}_last_bin_rel_err"] = float(np.sqrt(rel2))
             res[f"{tag}_last_bin_fom"] = float(1.0 / (rel2 * dt))
-            if tag == "controlled":
-                res["splits_per_history"] = out["splits"] / n
-                res["rouletted_per_history"] = float(out["terms"][4]) / n
+            if tag != "analog":
+                res[f"{tag}_splits_per_history"] = out["splits"] / n
+                res[f"{tag}_rouletted_per_history"] = float(out["terms"][4]) / n
             log(f"population control {tag}: {dt * 1e3:.1f} ms per run")
         res["last_bin_fom_gain"] = res["controlled_last_bin_fom"] / res["analog_last_bin_fom"]
+        res["combed_last_bin_fom_gain"] = res["combed_last_bin_fom"] / res["analog_last_bin_fom"]
         # the controlled batches share the weight w_t of every edge, so the
         # batch variance is not that of independent batches: the relative
         # error of one run from the spread of independent replicas instead
         reps = 16
-        for tag, kw in (("analog", {}), ("controlled", {"pc_target": n})):
+        for tag, kw in (("analog", {}), ("controlled", {"pc_target": n}),
+                        ("combed", {"pc_target": n, "pc_method": "comb"})):
             xs = []
             t0 = time.perf_counter()
             for r in range(reps):
@@ -292,6 +296,8 @@ def population_control_section(m, w, n, steps, cpu=True):
             res[f"{tag}_last_bin_fom_replicas"] = float(1.0 / (rel * rel * dt))
         res["replicas"] = reps
         res["last_bin_fom_gain_replicas"] = res["controlled_last_bin_fom_replicas"] / res["analog_last_bin_fom_replicas"]
+        res["combed_last_bin_fom_gain_replicas"] = (res["combed_last_bin_fom_replicas"]
+                                                    / res["analog_last_bin_fom_replicas"])
         prof = np.zeros((len(m._binding.PROF_CLASSES), 4))
         m.mcdc_run(h, n, 99, outputs=("mean",), pc_target=n, profile=prof, profile_classes=["events", "control"])
         torch.cuda.synchronize()

@@ -210,7 +210,7 @@ typedef struct {
 
 /*
  * Run options (all-zero = defaults; ABI version 4 added sort_cadence and
- * the sort profile class, version 5 steps_per_launch).
+ * the sort profile class, version 5 steps_per_launch and pc_method).
  *  algorithm      MCDC_ALG_EVENT (default), MCDC_ALG_HISTORY, or
  *                 MCDC_ALG_AUTO: mcdc_run runs both forms on its first call
  *                 for a history count (results of the history-form run)
@@ -321,11 +321,32 @@ typedef struct {
  *                 the same, tallies differ by summation order only.  s > 1
  *                 with weight windows, fission, population control, a
  *                 queue sort, the two-kernel or the staged step is refused
- *                 (MCDC_E_UNSUPPORTED); those take one step per launch, and
- *                 mcdc_run_batched ignores the option.  With profile,
- *                 profile_every and profile_phase count launches instead
- *                 of census steps.
+ *                 (MCDC_E_UNSUPPORTED); those take one step per launch.
+ *                 mcdc_run_batched ignores the option: its one-kernel form
+ *                 takes as many steps per launch as every problem's slice
+ *                 holds.  With profile, profile_every and profile_phase
+ *                 count launches instead of census steps.
+ *  pc_method      with pc_target: MCDC_PC_SPLIT (0, the default) for the
+ *                 splitting-roulette above, or MCDC_PC_COMB (1): combing.
+ *                 At each edge the same particles as above are put in one
+ *                 order that depends on nothing but the particles
+ *                 (ascending history index, then ascending stream state),
+ *                 the comb's M = pc_target teeth sit at (u + j) W / M,
+ *                 j = 0 .. M-1, with one draw u per edge from the stream
+ *                 child_stream(seed, 2^62 + k) of edge T_k, and a particle
+ *                 whose stretch [P, P + q) of the cumulative fixed-point
+ *                 weight holds n teeth goes on as n copies of weight
+ *                 w_t = W / M (copy 0 keeps the stream, copy j >= 1 takes
+ *                 child stream j; n = 0 counts as rouletted).  Exactly M
+ *                 particles go on at every edge.  The teeth below a point
+ *                 x are ceil((X / W) M - u) with X, W the fixed-point sums
+ *                 as doubles (hi + (lo >> 32) 2^-32 + (lo mod 2^32) 2^-64),
+ *                 clipped to [0, M].  The order is a radix sort over the
+ *                 next bank; the census steps then launch one kernel at a
+ *                 time (no captured graphs).
  */
+#define MCDC_PC_SPLIT 0
+#define MCDC_PC_COMB 1
 #define MCDC_FLAG_EAGER 1
 #define MCDC_FLAG_TWO_KERNEL_STEP 2
 #define MCDC_FLAG_STAGED 4
@@ -353,7 +374,7 @@ typedef struct {
     int32_t sort_cadence;
     uint64_t pc_target;
     int32_t steps_per_launch;
-    int32_t reserved;   /* zero */
+    int32_t pc_method;
 } mcdc_run_options;
 
 /*

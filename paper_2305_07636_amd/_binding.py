@@ -64,7 +64,7 @@ class mcdc_run_options(C.Structure):
         ("debug_counts", C.c_void_p), ("debug_scores", C.c_void_p),
         ("profile", C.c_void_p), ("profile_mask", C.c_uint32), ("profile_every", C.c_int32), ("profile_phase", C.c_int32),
         ("segments", C.c_int32), ("sort_cadence", C.c_int32), ("pc_target", C.c_uint64),
-        ("steps_per_launch", C.c_int32), ("reserved", C.c_int32),
+        ("steps_per_launch", C.c_int32), ("pc_method", C.c_int32),
     ]
 
 
@@ -267,7 +267,7 @@ def mcdc_run(p: Problem, n_histories: int, seed: int, algorithm: str = "event",
              profile=None, eager: bool = False, profile_classes=None, profile_every: int = 0,
              profile_phase: int = 0, two_kernel_step: bool = False, pc_target: int = 0,
              noalloc: bool = False, sort_cadence: int = 0, staged: bool = False,
-             steps_per_launch: int = 0):
+             steps_per_launch: int = 0, pc_method: str = "split"):
     """Run n_histories through the GPU tracker.  Returns a dict of torch
     CUDA tensors (mean, var, raw [K, G, nz, ny, nx]; leak_mean, leak_var
     [K, G, 6]; tc_mean, tc_var [K, G, nz, ny, nx] for a problem with the
@@ -281,7 +281,9 @@ def mcdc_run(p: Problem, n_histories: int, seed: int, algorithm: str = "event",
     noalloc: call mcdc_run_noalloc (history form, device outputs, no
     debug arrays or profile) instead of mcdc_run.
     steps_per_launch: census steps per launch of the event form's
-    one-kernel step (analog; 0 = default)."""
+    one-kernel step (analog; 0 = default).
+    pc_method: "split" (splitting-roulette) or "comb" (combing) with
+    pc_target."""
     import torch
 
     dev = torch.device("cuda", torch.cuda.current_device())
@@ -305,6 +307,7 @@ def mcdc_run(p: Problem, n_histories: int, seed: int, algorithm: str = "event",
     opt.pc_target = pc_target
     opt.sort_cadence = sort_cadence
     opt.steps_per_launch = steps_per_launch
+    opt.pc_method = {"split": 0, "comb": 1}[pc_method]
     opt.flags = (1 if eager else 0) | (2 if two_kernel_step else 0) | (4 if staged else 0)
     opt.stream = torch.cuda.current_stream(dev).cuda_stream
     if debug:

@@ -40,6 +40,8 @@
 #include <type_traits>
 #include <vector>
 
+#include <hipcub/hipcub.hpp>
+
 #include "k_common.hpp"
 
 namespace mcdc {
@@ -97,6 +99,7 @@ struct Ctl {
     int *seg_b0;            // [G] batch of the segment's first history
     int *step;              // current census step
     uint64_t *first;        // global index of the chunk's first history
+    uint64_t *seed;         // the run's seed (63 bits; the combing offsets' streams)
     unsigned long long *pc_w;  // [G][2] population control: fixed-point weight sum per segment
     unsigned long long *pc_cnt;  // [G] population control: copies made from each segment
     unsigned int G, L;      // segments (= workgroups), slots per segment
@@ -1241,7 +1244,7 @@ __global__ void __launch_bounds__(kBlock) k_pc_sum(RunArgs R, Bank next, Ctl C, 
 // copies of all segments and of the segments before `seg`.  Every thread
 // returns the same values.
 struct PcSums {
-    double wt;
+    double W, wt;
     int on;
     unsigned long long total, before;
 };
@@ -1278,6 +1281,7 @@ __device__ PcSums pc_sums(const Ctl &C, uint64_t target, unsigned int seg, bool 
             Bf += part[w][3];
         }
         const double W = (double)H + ((double)(L >> 32) * 0x1p-32 + (double)(L & 0xFFFFFFFFull) * 0x1p-64);
+        res.W = W;
         res.wt = W / (double)target;
         res.on = (H | L) != 0ull;
         res.total = T;
@@ -1303,7 +1307,9 @@ __device__ __forceinline__ uint64_t pc_copies(Particle &p, int edge, bool on, do
 
 // Pass 2: copies per segment (the draws are repeated, not kept, by pass 3).
 // (it reads only the weight, stream and clock of each particle)
-__global__ void __launch_bounds__(kBlock) k_pc_count(RunArgs R, Bank next, Ctl C, int par, uint64_t target) {
+// (comb: the copies of each controlled particle by slot, from k_comb_count)
+__global__ void __launch_bounds__(kBlock) k_pc_count(RunArgs R, Bank next, Ctl C, int par, uint64_t target,
+                                                     const uint32_t *__restrict__ comb) {
     __shared__ unsigned long long part[kBlock / 64];
     const unsigned int seg = blockIdx.x;
     const PcSums S = pc_sums(C, target, seg, false);
@@ -1319,6 +1325,10 @@ __global__ void __launch_bounds__(kBlock) k_pc_count(RunArgs R, Bank next, Ctl C
         items += 1ull;
         Particle p;
         p.k = (int)clock_of(fld<uint32_t>(next, next.ogk, tile_off4(next, slot)));
+        if (comb) {
+            tot += (on && p.k == edge) ? (unsigned long long)comb[slot] : 1ull;
+            continue;
+        }
         p.w = fld<double>(next, next.ow, tile_off8(next, slot));
         p.s = fld<uint64_t>(next, next.os, tile_off8(next, slot));
         tot += pc_copies(p, edge, on, wt, cap, R);
@@ -1339,9 +1349,11 @@ __global__ void __launch_bounds__(kBlock) k_pc_count(RunArgs R, Bank next, Ctl C
 // to slot q mod Lq of segment q / Lq, Lq = ceil(T / G) for T copies in all:
 // the controlled population is spread evenly over the segments again (a
 // segment's share would otherwise drift from step to step).
+// (comb: the copies by slot from k_comb_count, no draw: copy 0 keeps the
+// stream as it is)
 template <int FM>
 __global__ void __launch_bounds__(kBlock) k_pc_apply(DevProblem P, RunArgs R, Bank next, Bank cur, Ctl C, int par,
-                                                     uint64_t target) {
+                                                     uint64_t target, const uint32_t *__restrict__ comb) {
     __shared__ unsigned long long red[kCounters + 2];
     __shared__ unsigned int cN;
     Counters cnt;
@@ -1373,7 +1385,7 @@ __global__ void __launch_bounds__(kBlock) k_pc_apply(DevProblem P, RunArgs R, Ba
         if (valid) {
             load_state<FM, true>(P, next, seg0 + r, p, gk, hidw);
             const bool ctl = on && p.k == edge;
-            copies = pc_copies(p, edge, on, wt, cap, R);
+            copies = comb ? (ctl ? (uint64_t)comb[seg0 + r] : 1ull) : pc_copies(p, edge, on, wt, cap, R);
             if (ctl) {
                 const uint64_t i = first + (hidw & kHidMask);
                 if (copies == 0ull) {
@@ -1412,11 +1424,101 @@ __global__ void __launch_bounds__(kBlock) k_pc_apply(DevProblem P, RunArgs R, Ba
 }
 
 // ---------------------------------------------------------------------------
+// population control by combing
+// ---------------------------------------------------------------------------
+// (The comb needs the controlled particles in one order that does not
+// depend on the schedule: ascending history index, then ascending stream
+// state.  Over every slot of the next bank, k_comb_keys writes the stream
+// as the first key (all ones for a slot that is empty or not controlled,
+// so those sort last) and the slot as the value; a radix sort by that key,
+// then a stable one by the history index (k_comb_hid), leaves the slots in
+// that order.  k_comb_weights writes their 128-bit fixed-point weights, an
+// exclusive scan gives each particle's stretch [P, P + q) of the
+// cumulative weight, and k_comb_count counts the teeth in it.)
+struct U128 {
+    unsigned long long hi, lo;
+};
+struct AddU128 {
+    __host__ __device__ U128 operator()(const U128 &a, const U128 &b) const {
+        const unsigned long long lo = a.lo + b.lo;
+        return U128{a.hi + b.hi + (lo < a.lo ? 1ull : 0ull), lo};
+    }
+};
+
+// a slot of the next bank: controlled at this edge?
+__device__ __forceinline__ bool comb_member(const Bank &next, const Ctl &C, int par, uint32_t t, uint32_t edge) {
+    const uint32_t seg = t / C.L, r = t - seg * C.L;
+    if (seg >= C.G || r >= C.n_bank[(par ^ 1) * C.G + seg]) return false;
+    return clock_of(fld<uint32_t>(next, next.ogk, tile_off4(next, t))) == edge;
+}
+
+__global__ void __launch_bounds__(kBlock) k_comb_keys(Bank next, Ctl C, int par, uint32_t slots,
+                                                      unsigned long long *key, uint32_t *val) {
+    const uint32_t edge = (uint32_t)(*C.step + 1);
+    for (uint32_t t = blockIdx.x * kBlock + threadIdx.x; t < slots; t += gridDim.x * kBlock) {
+        key[t] = comb_member(next, C, par, t, edge) ? fld<uint64_t>(next, next.os, tile_off8(next, t)) : ~0ull;
+        val[t] = t;
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_comb_hid(Bank next, Ctl C, int par, uint32_t slots,
+                                                     const uint32_t *__restrict__ val, uint32_t *key) {
+    const uint32_t edge = (uint32_t)(*C.step + 1);
+    for (uint32_t r = blockIdx.x * kBlock + threadIdx.x; r < slots; r += gridDim.x * kBlock) {
+        const uint32_t t = val[r];
+        key[r] = comb_member(next, C, par, t, edge) ? (fld<uint32_t>(next, next.ohid, tile_off4(next, t)) & kHidMask)
+                                                    : 0xFFFFFFFFu;
+    }
+}
+
+// the fixed-point weight of a controlled particle (its truncation to a
+// multiple of 2^-64), 0 for any other slot
+__global__ void __launch_bounds__(kBlock) k_comb_weights(Bank next, Ctl C, int par, uint32_t slots,
+                                                         const uint32_t *__restrict__ val, U128 *q) {
+    const uint32_t edge = (uint32_t)(*C.step + 1);
+    for (uint32_t r = blockIdx.x * kBlock + threadIdx.x; r < slots; r += gridDim.x * kBlock) {
+        const uint32_t t = val[r];
+        unsigned long long hi = 0ull, lo = 0ull;
+        if (comb_member(next, C, par, t, edge)) fixed_add(hi, lo, fld<double>(next, next.ow, tile_off8(next, t)));
+        q[r] = U128{hi, lo};
+    }
+}
+
+// teeth of the comb below the fixed-point point x
+__device__ __forceinline__ uint32_t comb_teeth(const U128 &x, double W, uint64_t M, double u) {
+    const double dx = (double)x.hi + ((double)(x.lo >> 32) * 0x1p-32 + (double)(x.lo & 0xFFFFFFFFull) * 0x1p-64);
+    const double c = ceil((dx / W) * (double)M - u);
+    if (!(c > 0.0)) return 0u;
+    if (c >= (double)M) return (uint32_t)M;
+    return (uint32_t)c;
+}
+
+__global__ void __launch_bounds__(kBlock) k_comb_count(Ctl C, uint32_t slots, uint64_t target,
+                                                       const uint32_t *__restrict__ val, const U128 *__restrict__ q,
+                                                       const U128 *__restrict__ pre, uint32_t *copies) {
+    const PcSums S = pc_sums(C, target, 0u, false);
+    if (!S.on) return;
+    const uint32_t edge = (uint32_t)(*C.step + 1);
+    uint64_t su = child_stream(*C.seed, (1ull << 62) + edge);
+    const double u = rn(su);
+    for (uint32_t r = blockIdx.x * kBlock + threadIdx.x; r < slots; r += gridDim.x * kBlock) {
+        const U128 a = pre[r], w = q[r];
+        if ((w.hi | w.lo) == 0ull) {
+            copies[val[r]] = 0u;   // not controlled (or a weight below 2^-64)
+            continue;
+        }
+        const U128 b = AddU128()(a, w);
+        copies[val[r]] = comb_teeth(b, S.W, target, u) - comb_teeth(a, S.W, target, u);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // control
 // ---------------------------------------------------------------------------
-__global__ void k_ctl_init(Ctl C, uint64_t first) {
+__global__ void k_ctl_init(Ctl C, uint64_t first, uint64_t seed) {
     *C.step = 0;
     *C.first = first;
+    *C.seed = seed & kMask63;
 }
 __global__ void k_step_end(Ctl C, int inc) { *C.step += inc; }
 
@@ -1498,6 +1600,7 @@ Layout carve(void *bank_mem, void *ctl_mem, uint64_t slots, unsigned int G, unsi
     C.seg_b0 = (int *)take(G * 4);
     C.step = (int *)take(64);
     C.first = (uint64_t *)take(64);
+    C.seed = C.first + 1;
     C.pc_w = (unsigned long long *)take(G * 16);
     C.pc_cnt = (unsigned long long *)take(G * 8);
     C.G = G;
@@ -1645,6 +1748,51 @@ int run_event(mcdc_problem *pb, const RunArgs &R0, uint64_t first, uint64_t coun
     SplitBank SB[2]{};
     if (WW && (rc = split_prepare(pb, C, SB))) return rc;
 
+    // population control by combing: per slot of a bank, the sort keys and
+    // values (two buffers each), the fixed-point weights and their exclusive
+    // prefix, the copies; then the library sort's and scan's work space
+    const bool comb = pc && opt.pc_method == MCDC_PC_COMB;
+    struct CombWork {
+        unsigned long long *k1[2];
+        uint32_t *k2[2], *v[2], *copies;
+        U128 *q, *pre;
+        void *tmp;
+        size_t tmp_bytes;
+    } cw{};
+    const uint32_t cslots = (uint32_t)slots;
+    if (comb) {
+        size_t b1 = 0, b2 = 0, b3 = 0;
+        hipError_t e = hipcub::DeviceRadixSort::SortPairs(nullptr, b1, (unsigned long long *)nullptr,
+                                                          (unsigned long long *)nullptr, (uint32_t *)nullptr,
+                                                          (uint32_t *)nullptr, (int)cslots, 0, 64, st);
+        if (e == hipSuccess)
+            e = hipcub::DeviceRadixSort::SortPairs(nullptr, b2, (uint32_t *)nullptr, (uint32_t *)nullptr,
+                                                   (uint32_t *)nullptr, (uint32_t *)nullptr, (int)cslots, 0, 32, st);
+        if (e == hipSuccess)
+            e = hipcub::DeviceScan::ExclusiveScan(nullptr, b3, (U128 *)nullptr, (U128 *)nullptr, AddU128(),
+                                                  U128{0ull, 0ull}, (int)cslots, st);
+        if (e != hipSuccess) return hip_fail(e, "comb work size");
+        cw.tmp_bytes = b1 > b2 ? (b1 > b3 ? b1 : b3) : (b2 > b3 ? b2 : b3);
+        const size_t per = pad256((size_t)cslots * 8);
+        const size_t per4 = pad256((size_t)cslots * 4);
+        const size_t per16 = pad256((size_t)cslots * 16);
+        if ((rc = ensure(pb->comb, 2 * per + 5 * per4 + 2 * per16 + pad256(cw.tmp_bytes)))) return rc;
+        char *m = (char *)pb->comb.p;
+        cw.k1[0] = (unsigned long long *)m;
+        cw.k1[1] = (unsigned long long *)(m + per);
+        m += 2 * per;
+        cw.k2[0] = (uint32_t *)m;
+        cw.k2[1] = (uint32_t *)(m + per4);
+        cw.v[0] = (uint32_t *)(m + 2 * per4);
+        cw.v[1] = (uint32_t *)(m + 3 * per4);
+        cw.copies = (uint32_t *)(m + 4 * per4);
+        m += 5 * per4;
+        cw.q = (U128 *)m;
+        cw.pre = (U128 *)(m + per16);
+        cw.tmp = m + 2 * per16;
+    }
+    hipError_t comb_err = hipSuccess;
+
     // the step kernels never read the seed or the history count; Rs is the
     // uninstrumented form the graphs capture, Rp the profiled one
     RunArgs Rs = R;
@@ -1690,9 +1838,32 @@ int run_event(mcdc_problem *pb, const RunArgs &R0, uint64_t first, uint64_t coun
         if constexpr (WW) {
             if (pc) {
                 launch_timed(pr, MCDC_PROF_CONTROL, k_pc_sum, dim3(G), dim3(kBlock), 0u, s, Ra, nxt, L.ctl, par);
-                launch_timed(pr, MCDC_PROF_CONTROL, k_pc_count, dim3(G), dim3(kBlock), 0u, s, Ra, nxt, L.ctl, par, pc);
+                if (comb) {
+                    // the controlled particles in (history, stream) order, their
+                    // stretches of the cumulative weight, the teeth in each
+                    hipLaunchKernelGGL(k_comb_keys, dim3(G), dim3(kBlock), 0, s, nxt, L.ctl, par, cslots, cw.k1[0],
+                                       cw.v[0]);
+                    hipError_t e = hipcub::DeviceRadixSort::SortPairs(cw.tmp, cw.tmp_bytes, cw.k1[0], cw.k1[1],
+                                                                      cw.v[0], cw.v[1], (int)cslots, 0, 64, s);
+                    hipLaunchKernelGGL(k_comb_hid, dim3(G), dim3(kBlock), 0, s, nxt, L.ctl, par, cslots, cw.v[1],
+                                       cw.k2[0]);
+                    if (e == hipSuccess)
+                        e = hipcub::DeviceRadixSort::SortPairs(cw.tmp, cw.tmp_bytes, cw.k2[0], cw.k2[1], cw.v[1],
+                                                               cw.v[0], (int)cslots, 0, 32, s);
+                    hipLaunchKernelGGL(k_comb_weights, dim3(G), dim3(kBlock), 0, s, nxt, L.ctl, par, cslots, cw.v[0],
+                                       cw.q);
+                    if (e == hipSuccess)
+                        e = hipcub::DeviceScan::ExclusiveScan(cw.tmp, cw.tmp_bytes, cw.q, cw.pre, AddU128(),
+                                                              U128{0ull, 0ull}, (int)cslots, s);
+                    launch_timed(pr, MCDC_PROF_CONTROL, k_comb_count, dim3(G), dim3(kBlock), 0u, s, L.ctl, cslots, pc,
+                                 (const uint32_t *)cw.v[0], (const U128 *)cw.q, (const U128 *)cw.pre, cw.copies);
+                    if (e != hipSuccess && comb_err == hipSuccess) comb_err = e;
+                }
+                const uint32_t *cc = comb ? cw.copies : nullptr;
+                launch_timed(pr, MCDC_PROF_CONTROL, k_pc_count, dim3(G), dim3(kBlock), 0u, s, Ra, nxt, L.ctl, par, pc,
+                             cc);
                 launch_timed(pr, MCDC_PROF_CONTROL, k_pc_apply<FM>, dim3(G), dim3(kBlock), 0u, s, P, Ra, nxt, cur, L.ctl,
-                             par, pc);
+                             par, pc, cc);
             }
         }
         hipLaunchKernelGGL(k_step_end, dim3(1), dim3(1), 0, s, L.ctl, ns);
@@ -1701,7 +1872,7 @@ int run_event(mcdc_problem *pb, const RunArgs &R0, uint64_t first, uint64_t coun
     // replay captured steps unless per-history debug output is requested;
     // profiled steps launch eagerly
     const bool use_graph = !(opt.flags & MCDC_FLAG_EAGER) && !(opt.profile && every == 1) && !R.dbg_counts &&
-                           !R.dbg_scores && NL > 1;
+                           !R.dbg_scores && NL > 1 && !comb;
     StepGraphs *Gr = nullptr;
     // stretch of unsampled launches captured as one graph (none below 2)
     const int span = opt.profile ? every - 1 : NL;
@@ -1754,7 +1925,7 @@ int run_event(mcdc_problem *pb, const RunArgs &R0, uint64_t first, uint64_t coun
     for (uint64_t c0 = 0; c0 < count; c0 += C) {
         const uint64_t n = (count - c0 < C) ? count - c0 : C;
         const uint64_t cfirst = first + c0;
-        hipLaunchKernelGGL(k_ctl_init, dim3(1), dim3(1), 0, st, L.ctl, cfirst);
+        hipLaunchKernelGGL(k_ctl_init, dim3(1), dim3(1), 0, st, L.ctl, cfirst, R.seed);
         if (P.qoi_on && (rc = launch_zero(R.qoi_hist, n * sizeof(double), st))) return hip_fail((hipError_t)rc, "zero");
         if (WW) split_reset(SB, st);
         launch_timed(prof, MCDC_PROF_SOURCE, k_source<FM, WW, false, MCDC_PROF_SOURCE, BS>, dim3(G), dim3(BS), 0u, st, P,
@@ -1783,6 +1954,7 @@ int run_event(mcdc_problem *pb, const RunArgs &R0, uint64_t first, uint64_t coun
         }
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return hip_fail(e, "event kernel launch");
+        if (comb_err != hipSuccess) return hip_fail(comb_err, "comb sort or scan");
         if (WW && (rc = split_generations(pb, R, SB, cfirst, st, prof))) return rc;
         if (P.qoi_on && (rc = launch_qoi_reduce(R.qoi_hist, n, R.qoi_sums, st)))
             return hip_fail((hipError_t)rc, "detector reduce");
@@ -1827,7 +1999,7 @@ int run_batched_steps(const BatchItem *d_items, const SegInfo *d_segs, unsigned 
     const RunArgs R0{};
     const LdsTables t0{};
     const SplitBank none{};
-    hipLaunchKernelGGL(k_ctl_init, dim3(1), dim3(1), 0, st, L.ctl, (uint64_t)0);
+    hipLaunchKernelGGL(k_ctl_init, dim3(1), dim3(1), 0, st, L.ctl, (uint64_t)0, (uint64_t)0);
     hipLaunchKernelGGL((k_source<FM, false, true, MCDC_PROF_SOURCE, BS>), dim3(G), dim3(BS), 0, st, P0, R0, L.bank[0], L.ctl,
                        (uint64_t)0, d_items, d_segs);
     hipError_t e = hipGetLastError();

@@ -219,7 +219,7 @@ struct mcdc_problem {
         void *p = nullptr;
         size_t bytes = 0;
     };
-    Buf S, L, qoi_hist, qoi_sums, counters, overflow, bank, queues, split, prof, counters_split, tally_part, work;
+    Buf S, L, qoi_hist, qoi_sums, counters, overflow, bank, queues, split, prof, counters_split, tally_part, work, comb;
     Buf mean, var, raw, leak_mean, leak_var, tc_mean, tc_var;
     void *graph_cache = nullptr;   // captured census steps of the event form
     // MCDC_ALG_AUTO: the faster form for one history count, once timed

@@ -562,7 +562,8 @@ extern "C" int mcdc_problem_destroy(mcdc_problem *p) {
     mcdc_problem::Buf *bufs[] = {&p->S, &p->L, &p->qoi_hist, &p->qoi_sums, &p->counters,
                                  &p->overflow, &p->bank, &p->queues, &p->split, &p->prof,
                                  &p->counters_split, &p->tally_part, &p->mean,
-                                 &p->var, &p->raw, &p->leak_mean, &p->leak_var, &p->tc_mean, &p->tc_var, &p->work};
+                                 &p->var, &p->raw, &p->leak_mean, &p->leak_var, &p->tc_mean, &p->tc_var, &p->work,
+                                 &p->comb};
     for (auto *b : bufs) free_buf(*b);
     delete p;
     return MCDC_OK;

@@ -99,7 +99,9 @@ int check_options(const mcdc_run_options &opt) {
     if (opt.bank_capacity < 0) return bad("bank_capacity must be >= 0");
     if (opt.sort_cadence < -1 || opt.sort_cadence > 64) return bad("sort_cadence must be in [-1, 64]");
     if (opt.steps_per_launch < 0 || opt.steps_per_launch > 65535) return bad("steps_per_launch must be in [0, 65535]");
-    if (opt.reserved != 0) return bad("reserved must be 0");
+    if (opt.pc_method != MCDC_PC_SPLIT && opt.pc_method != MCDC_PC_COMB)
+        return bad("pc_method must be MCDC_PC_SPLIT or MCDC_PC_COMB");
+    if (opt.pc_method == MCDC_PC_COMB && opt.pc_target == 0) return bad("pc_method needs pc_target");
     return MCDC_OK;
 }
 

@@ -60,9 +60,9 @@ CASES = {
 }
 
 
-def compare_pc(prob, N, target, seed, **kw):
-    g = gpu_run(prob, N, seed, "event", debug=False, pc_target=target, **kw)
-    r = oracle.run_pc(prob, N, seed, target)
+def compare_pc(prob, N, target, seed, method="split", **kw):
+    g = gpu_run(prob, N, seed, "event", debug=False, pc_target=target, pc_method=method, **kw)
+    r = oracle.run_pc(prob, N, seed, target, method=method)
     e = oracle.estimates(prob, r)
     tot = r["tot"]
     assert np.array_equal(g["events"], tot[0:3]), (g["events"], tot[0:3])
@@ -94,6 +94,40 @@ def test_population_control_parity(case):
 
 
 @pytest.mark.gpu
+@pytest.mark.parametrize("case", list(CASES))
+def test_population_control_by_combing_parity(case):
+    """Combing (reading R28): the controlled particles sorted by history
+    and stream on the GPU, their teeth counted from an exact 128-bit
+    prefix of their fixed-point weights; every count and tally against the
+    oracle's comb."""
+    make, N, f, seed = CASES[case]
+    target = int(round(f * N))
+    print(f"[pc comb] {case} N={N} target={target}", flush=True)
+    g, r = compare_pc(make(), N, target, seed, method="comb")
+    born = int(r["pop"][0])
+    assert born + g["splits"] == int(np.sum(g["terms"]))
+
+
+@pytest.mark.gpu
+def test_population_control_by_combing_two_kernel_step_and_profile():
+    import paper_2305_07636_amd as m
+
+    print("[pc comb] two-kernel step", flush=True)
+    compare_pc(_slab_pulse(0.5), 20000, 15000, 73, method="comb", two_kernel_step=True)
+    # profiled runs launch the control eagerly too: same results
+    prob = _slab_pulse(0.5)
+    p = m.mcdc_problem_create(prob)
+    try:
+        a = m.mcdc_run(p, 20000, 74, pc_target=15000, pc_method="comb")
+        prof = np.zeros((len(m._binding.PROF_CLASSES), 4))
+        b = m.mcdc_run(p, 20000, 74, pc_target=15000, pc_method="comb", profile=prof)
+        assert np.array_equal(a["events"], b["events"]) and np.array_equal(a["terms"], b["terms"])
+        assert prof[m._binding.PROF_CLASSES.index("control"), 1] > 0
+    finally:
+        p.close()
+
+
+@pytest.mark.gpu
 def test_population_control_two_kernel_step():
     print("[pc] two-kernel step", flush=True)
     compare_pc(_slab_pulse(0.5), 20000, 20000, 67, two_kernel_step=True)
@@ -113,6 +147,10 @@ def test_population_control_rejections():
         with pytest.raises(m.MCDCError) as ei:
             m.mcdc_run(p, (1 << 26) + 1, 1, pc_target=1000)
         assert ei.value.code == MCDC_E_UNSUPPORTED
+        # combing needs a target
+        with pytest.raises(m.MCDCError) as ei:
+            m.mcdc_run(p, 1000, 1, pc_method="comb")
+        assert ei.value.code == m._binding.MCDC_E_INVALID
         # auto picks the event form
         g = m.mcdc_run(p, 2000, 1, algorithm="auto", pc_target=2000)
         assert g["splits"] > 0
