@@ -490,7 +490,7 @@ def fom_section(w, pilots, n_analog_run, analog_runs, n_ww, ww_runs, steps):
         }
         log(f"fom: pilots {n_pilot:.0e}: learned R {b['R']:.4f} T {b['T_s']:.2f} s gain "
             f"{res[tag]['fom_gain_learned_vs_analog']}, incl. pilot+training "
-            f"{res[tag]['fom_gain_incl_pilot_and_training']:.2f}, mean diff {diff(a, b):.2f} sigma")
+            f"{res[tag]['fom_gain_incl_pilot_and_training']}, mean diff {diff(a, b)} sigma")
     # implicit capture (Section 3 runs the time-dependent duct with it),
     # roulette below weight 0.25 to weight 1
     pic = dict(p, implicit_capture={"w_min": 0.25, "w_survive": 1.0})

@@ -641,6 +641,7 @@ inline bool table_layout(const DevProblem &P, LdsTables &t, int64_t budget) {
 // generations' banks for chunks of up to `chunk` histories, clear the first
 // generation's count, and track every generation of progeny of a chunk.
 int split_prepare(mcdc_problem *pb, uint64_t chunk, dev::SplitBank SB[2]);
+int split_prepare_slots(mcdc_problem *pb, uint64_t chunk, dev::SplitBank (*SB)[2], int slots);
 void split_reset(const dev::SplitBank SB[2], hipStream_t st);
 int split_generations(mcdc_problem *pb, const RunArgs &R, dev::SplitBank SB[2], uint64_t cfirst, hipStream_t st,
                       Profiler &prof);

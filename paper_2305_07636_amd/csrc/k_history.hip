@@ -7,6 +7,9 @@
 // tracked in further rounds (one kernel per generation) until none are
 // left; a history's records and detector score then come from several
 // particles and are accumulated per history with atomics.
+#include <chrono>
+#include <thread>
+
 #include "k_common.hpp"
 
 namespace mcdc {
@@ -514,10 +517,11 @@ size_t split_bytes(unsigned int cap) { return (size_t)cap * (13 * 8 + 8) + 16 * 
 // resident (no more than the work needs), and the work counter cleared.
 template <int FM, bool WW>
 int launch_main(mcdc_problem *pb, const DevProblem &P, const RunArgs &R, uint64_t first, uint64_t count,
-                uint64_t chunk_first, const SplitBank &SB, hipStream_t st, Profiler &prof) {
+                uint64_t chunk_first, const SplitBank &SB, hipStream_t st, Profiler &prof,
+                unsigned long long *next_in = nullptr) {
     const int bs = 256;
     int rc;
-    unsigned long long *next = R.work;
+    unsigned long long *next = next_in ? next_in : R.work;
     if (!next) {
         if ((rc = ensure(pb->work, 256))) return rc;
         next = (unsigned long long *)pb->work.p;
@@ -550,49 +554,187 @@ int launch_main(mcdc_problem *pb, const DevProblem &P, const RunArgs &R, uint64_
 // Split progeny of one chunk, generation by generation, until none are left.
 // Generations are queued kGensPerCheck at a time, each launch reading its
 // input count on the device; the host reads the count once per batch.
+// Generations are queued kGensPerCheck at a time, each launch reading its
+// input count on the device; the host reads the count once per batch.
+constexpr int kGensPerCheck = 4;
+
+// Launch shape of the persistent children kernel and its staged tables.
+struct ChildShape {
+    bool lt = false;
+    LdsTables tabs{};
+    size_t shmem = 0;
+    uint64_t grid = 1;
+};
+
+template <int FM>
+int child_shape(mcdc_problem *pb, ChildShape &cs) {
+    const DevProblem &P = pb->d;
+    cs.lt = table_layout(P, cs.tabs, kHistoryTablesMax);
+    cs.shmem = cs.lt ? (size_t)cs.tabs.bytes : 0;
+    int per_cu = 0, n_cu = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &per_cu, cs.lt ? reinterpret_cast<const void *>(&k_history_children<FM, true>)
+                       : reinterpret_cast<const void *>(&k_history_children<FM, false>), 256, cs.shmem);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, pb->device);
+    if (e != hipSuccess) return hip_fail(e, "occupancy query");
+    cs.grid = (uint64_t)(per_cu > 0 ? per_cu : 1) * (uint64_t)(n_cu > 0 ? n_cu : 1);
+    return MCDC_OK;
+}
+
+// Queue generations gen .. gen + kGensPerCheck - 1 of a chunk's progeny on
+// stream st (next: the children kernel's work counter of this bank pair).
+template <int FM>
+int queue_generations(const DevProblem &P, const RunArgs &R, const SplitBank SB[2], uint64_t cfirst, hipStream_t st,
+                      Profiler &prof, int gen, unsigned long long *next, const ChildShape &cs) {
+    for (int q = 0; q < kGensPerCheck; ++q, ++gen) {
+        const SplitBank &in = SB[gen & 1], &out = SB[(gen + 1) & 1];
+        hipLaunchKernelGGL(k_zero_count, dim3(1), dim3(1), 0, st, out.count);
+        hipLaunchKernelGGL(k_zero_count, dim3(1), dim3(1), 0, st, next);
+        if (cs.lt)
+            launch_timed(prof, MCDC_PROF_HISTORY, k_history_children<FM, true>, dim3((unsigned)cs.grid), dim3(256),
+                         (uint32_t)cs.shmem, st, P, R, in, cfirst, out, next, cs.tabs);
+        else
+            launch_timed(prof, MCDC_PROF_HISTORY, k_history_children<FM, false>, dim3((unsigned)cs.grid), dim3(256),
+                         0u, st, P, R, in, cfirst, out, next, cs.tabs);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return hip_fail(e, "history children launch");
+    }
+    return MCDC_OK;
+}
+
+int overflow_error() {
+    set_error("split bank overflow (window splits or fission made too many progeny in one generation; "
+              "run fewer histories per chunk with bank_capacity)");
+    return MCDC_E_OVERFLOW;
+}
+
+// Split progeny of one chunk, generation by generation, until none are
+// left (the event form's weighted chunks).
 template <int FM>
 int run_generations(mcdc_problem *pb, const RunArgs &R, SplitBank SB[2], uint64_t cfirst, hipStream_t st,
                     Profiler &prof) {
-    const DevProblem &P = pb->d;
-    // the persistent children kernel: its launch shape and staged tables
+    ChildShape cs;
+    int rc;
+    if ((rc = child_shape<FM>(pb, cs))) return rc;
     unsigned long long *next = (unsigned long long *)pb->counters_split.p + 2;
-    const int bs = 256;
-    LdsTables tabs{};
-    const bool lt = table_layout(P, tabs, kHistoryTablesMax);
-    const size_t shmem = lt ? (size_t)tabs.bytes : 0;
-    int per_cu = 0, n_cu = 0;
-    hipError_t e0 = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &per_cu, lt ? reinterpret_cast<const void *>(&k_history_children<FM, true>)
-                    : reinterpret_cast<const void *>(&k_history_children<FM, false>), bs, shmem);
-    if (e0 == hipSuccess) e0 = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, pb->device);
-    if (e0 != hipSuccess) return hip_fail(e0, "occupancy query");
-    const uint64_t grid_max = (uint64_t)(per_cu > 0 ? per_cu : 1) * (uint64_t)(n_cu > 0 ? n_cu : 1);
-    constexpr int kGensPerCheck = 4;
-    for (int gen = 0;;) {
+    for (int gen = 0;; gen += kGensPerCheck) {
         unsigned long long n_in = 0;
         hipError_t e = hipMemcpyAsync(&n_in, SB[gen & 1].count, sizeof(n_in), hipMemcpyDeviceToHost, st);
         if (e == hipSuccess) e = hipStreamSynchronize(st);
         if (e != hipSuccess) return hip_fail(e, "split count");
         if (n_in == 0) return MCDC_OK;
-        if (n_in > SB[gen & 1].cap || gen > 10000) {
-            set_error("split bank overflow (window splits or fission made too many progeny in one generation; "
-                      "run fewer histories per chunk with bank_capacity)");
-            return MCDC_E_OVERFLOW;
-        }
-        for (int q = 0; q < kGensPerCheck; ++q, ++gen) {
-            const SplitBank &in = SB[gen & 1], &out = SB[(gen + 1) & 1];
-            hipLaunchKernelGGL(k_zero_count, dim3(1), dim3(1), 0, st, out.count);
-            hipLaunchKernelGGL(k_zero_count, dim3(1), dim3(1), 0, st, next);
-            if (lt)
-                launch_timed(prof, MCDC_PROF_HISTORY, k_history_children<FM, true>, dim3((unsigned)grid_max),
-                             dim3(bs), (uint32_t)shmem, st, P, R, in, cfirst, out, next, tabs);
-            else
-                launch_timed(prof, MCDC_PROF_HISTORY, k_history_children<FM, false>, dim3((unsigned)grid_max),
-                             dim3(bs), 0u, st, P, R, in, cfirst, out, next, tabs);
-            e = hipGetLastError();
-            if (e != hipSuccess) return hip_fail(e, "history children launch");
-        }
+        if (n_in > SB[gen & 1].cap || gen > 10000) return overflow_error();
+        if ((rc = queue_generations<FM>(pb->d, R, SB, cfirst, st, prof, gen, next, cs))) return rc;
     }
+}
+
+// Weighted chunks of the history form, two at a time: chunk c runs on one
+// of two streams with its own split-bank pair, detector accumulator and
+// work counters, so that the last, small generations of one chunk overlap
+// the next chunk's histories.  The host starts a chunk as soon as a pair is
+// free and queues the generations of each running chunk in batches, polling
+// each batch's completion event and its copied count (no stream waits on
+// another stream's progress).
+template <int FM>
+int run_weighted_chunks(mcdc_problem *pb, const RunArgs &R0, uint64_t first, uint64_t count, uint64_t chunk,
+                        hipStream_t st, Profiler &prof) {
+    const DevProblem &P = pb->d;
+    const int NS = count > chunk ? 2 : 1;
+    SplitBank SB[2][2]{};
+    int rc;
+    if ((rc = split_prepare_slots(pb, chunk, SB, NS))) return rc;
+    if (P.qoi_on && (rc = ensure(pb->qoi_hist, (size_t)NS * chunk * sizeof(double)))) return rc;
+    if ((rc = ensure(pb->work, (size_t)NS * 256))) return rc;
+    ChildShape cs;
+    if ((rc = child_shape<FM>(pb, cs))) return rc;
+    hipError_t e = hipSuccess;
+    if (!pb->aux_stream) e = hipStreamCreateWithFlags((hipStream_t *)&pb->aux_stream, hipStreamNonBlocking);
+    for (int j = 0; j < 4 && e == hipSuccess; ++j)
+        if (!pb->aux_events[j]) e = hipEventCreateWithFlags((hipEvent_t *)&pb->aux_events[j], hipEventDisableTiming);
+    if (e == hipSuccess && !pb->host_counts)
+        e = hipHostMalloc((void **)&pb->host_counts, 4 * sizeof(unsigned long long), hipHostMallocDefault);
+    if (e != hipSuccess) return hip_fail(e, "chunk streams");
+    hipStream_t S[2] = {st, (hipStream_t)pb->aux_stream};
+    hipEvent_t done[2] = {(hipEvent_t)pb->aux_events[0], (hipEvent_t)pb->aux_events[1]};
+    hipEvent_t join = (hipEvent_t)pb->aux_events[2];
+    // the second stream starts after everything queued on the caller's
+    if (NS == 2) {
+        e = hipEventRecord(join, st);
+        if (e == hipSuccess) e = hipStreamWaitEvent(S[1], join, 0);
+        if (e != hipSuccess) return hip_fail(e, "chunk streams");
+    }
+    struct Slot {
+        bool busy = false;
+        uint64_t cfirst = 0, n = 0;
+        int gen = 0;
+        RunArgs R;
+        unsigned long long *next_main = nullptr, *next_child = nullptr;
+    } slot[2];
+    for (int q = 0; q < NS; ++q) {
+        slot[q].R = R0;
+        if (P.qoi_on) slot[q].R.qoi_hist = (double *)pb->qoi_hist.p + (size_t)q * chunk;
+        slot[q].next_main = (unsigned long long *)((char *)pb->work.p + (size_t)q * 256);
+        slot[q].next_child = (unsigned long long *)pb->counters_split.p + 3 * q + 2;
+    }
+    volatile unsigned long long *hc = pb->host_counts;
+    // queue the next batch of a running chunk, then its count and event
+    auto batch = [&](int q) -> int {
+        Slot &sl = slot[q];
+        int r = queue_generations<FM>(P, sl.R, SB[q], sl.cfirst, S[q], prof, sl.gen, sl.next_child, cs);
+        if (r) return r;
+        sl.gen += kGensPerCheck;
+        hipError_t ee = hipMemcpyAsync((void *)(hc + q), SB[q][sl.gen & 1].count, sizeof(unsigned long long),
+                                       hipMemcpyDeviceToHost, S[q]);
+        if (ee == hipSuccess) ee = hipEventRecord(done[q], S[q]);
+        return ee == hipSuccess ? MCDC_OK : hip_fail(ee, "split count");
+    };
+    uint64_t c0 = 0;
+    for (;;) {
+        bool progress = false, any = false;
+        for (int q = 0; q < NS; ++q) {
+            Slot &sl = slot[q];
+            if (!sl.busy) {
+                if (c0 >= count) continue;
+                sl.cfirst = first + c0;
+                sl.n = (count - c0 < chunk) ? count - c0 : chunk;
+                sl.gen = 0;
+                c0 += sl.n;
+                split_reset(SB[q], S[q]);
+                if ((rc = launch_main<FM, true>(pb, P, sl.R, sl.cfirst, sl.n, sl.cfirst, SB[q][0], S[q], prof,
+                                                sl.next_main)))
+                    return rc;
+                e = hipGetLastError();
+                if (e != hipSuccess) return hip_fail(e, "history kernel launch");
+                if ((rc = batch(q))) return rc;
+                sl.busy = true;
+                progress = any = true;
+                continue;
+            }
+            any = true;
+            e = hipEventQuery(done[q]);
+            if (e == hipErrorNotReady) continue;
+            if (e != hipSuccess) return hip_fail(e, "split count");
+            progress = true;
+            const unsigned long long n_in = hc[q];
+            if (n_in == 0) {
+                if (P.qoi_on && (rc = launch_qoi_reduce(sl.R.qoi_hist, sl.n, sl.R.qoi_sums, S[q])))
+                    return hip_fail((hipError_t)rc, "detector reduce");
+                sl.busy = false;
+                continue;
+            }
+            if (n_in > SB[q][sl.gen & 1].cap || sl.gen > 10000) return overflow_error();
+            if ((rc = batch(q))) return rc;
+        }
+        if (!any && c0 >= count) break;
+        if (!progress) std::this_thread::sleep_for(std::chrono::microseconds(20));
+    }
+    // the caller's stream waits for the second stream's work
+    if (NS == 2) {
+        e = hipEventRecord(join, S[1]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(st, join, 0);
+        if (e != hipSuccess) return hip_fail(e, "chunk streams");
+    }
+    return MCDC_OK;
 }
 
 template <int FM>
@@ -600,35 +742,17 @@ int run_history(mcdc_problem *pb, const RunArgs &R0, uint64_t first, uint64_t co
                 hipStream_t st, Profiler &prof) {
     const DevProblem &P = pb->d;
     const bool ww = has_progeny(P);
-    RunArgs R = R0;
     // analog runs keep the detector score in registers; runs with progeny
     // (weight windows, fission) assemble it per history in chunks
-    const uint64_t cmax = chunk_opt ? chunk_opt : (P.fission_on ? kFissionChunk : kWindowChunk);
-    const uint64_t chunk = ww ? ((count < cmax) ? count : cmax) : count;
-    SplitBank SB[2]{};
-    int rc;
     if (ww) {
-        if ((rc = split_prepare(pb, chunk, SB))) return rc;
-        if (P.qoi_on) {
-            if ((rc = ensure(pb->qoi_hist, chunk * sizeof(double)))) return rc;
-            R.qoi_hist = (double *)pb->qoi_hist.p;
-        }
+        const uint64_t cmax = chunk_opt ? chunk_opt : (P.fission_on ? kFissionChunk : kWindowChunk);
+        return run_weighted_chunks<FM>(pb, R0, first, count, (count < cmax) ? count : cmax, st, prof);
     }
-    for (uint64_t c0 = 0; c0 < count; c0 += chunk) {
-        const uint64_t n = (count - c0 < chunk) ? count - c0 : chunk;
-        const uint64_t cfirst = first + c0;
-        if (ww) split_reset(SB, st);
-        rc = ww ? launch_main<FM, true>(pb, P, R, cfirst, n, cfirst, SB[0], st, prof)
-                : launch_main<FM, false>(pb, P, R, cfirst, n, cfirst, SB[0], st, prof);
-        if (rc) return rc;
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return hip_fail(e, "history kernel launch");
-        if (!ww) continue;
-        if ((rc = run_generations<FM>(pb, R, SB, cfirst, st, prof))) return rc;
-        if (P.qoi_on && (rc = launch_qoi_reduce(R.qoi_hist, n, R.qoi_sums, st)))
-            return hip_fail((hipError_t)rc, "detector reduce");
-    }
-    return MCDC_OK;
+    SplitBank none[2]{};
+    int rc = launch_main<FM, false>(pb, P, R0, first, count, first, none[0], st, prof);
+    if (rc) return rc;
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? MCDC_OK : hip_fail(e, "history kernel launch");
 }
 
 // ---------------------------------------------------------------------------
@@ -754,7 +878,9 @@ int launch_batched(const BatchItem *items, const uint64_t *offs, int n_items, ui
     return launch_batched_fm<0>(items, offs, n_items, total, next, block, per_thread, st);
 }
 
-int split_prepare(mcdc_problem *pb, uint64_t chunk, dev::SplitBank SB[2]) {
+// (slots: independent bank pairs, for chunks that run at the same time;
+// pair q takes counters 3q, 3q + 1 and its children's work counter 3q + 2)
+int split_prepare_slots(mcdc_problem *pb, uint64_t chunk, dev::SplitBank (*SB)[2], int slots) {
     // room for 32 progeny per history of the chunk in each generation (64
     // with fission; implicit capture alone makes none: the minimum), at
     // most 2^26 entries per bank (7.5 GB): 8 per history at the default
@@ -763,13 +889,24 @@ int split_prepare(mcdc_problem *pb, uint64_t chunk, dev::SplitBank SB[2]) {
     const uint64_t want = per * chunk;
     const unsigned int cap = (unsigned int)((want < (1u << 22)) ? (1u << 22) : (want > (1u << 26) ? (1u << 26) : want));
     int rc;
-    if ((rc = ensure(pb->split, 2 * split_bytes(cap) + 256))) return rc;
+    if ((rc = ensure(pb->split, (size_t)slots * 2 * split_bytes(cap) + 256))) return rc;
     // (two bank counters, then the children kernel's work counter)
-    if ((rc = ensure(pb->counters_split, 3 * sizeof(unsigned long long)))) return rc;
+    if ((rc = ensure(pb->counters_split, (size_t)slots * 3 * sizeof(unsigned long long)))) return rc;
     unsigned long long *cnt = (unsigned long long *)pb->counters_split.p;
-    SB[0] = carve_split(pb->split.p, cap, cnt);
-    SB[1] = carve_split((char *)pb->split.p + split_bytes(cap), cap, cnt + 1);
+    for (int q = 0; q < slots; ++q) {
+        char *base = (char *)pb->split.p + (size_t)q * 2 * split_bytes(cap);
+        SB[q][0] = carve_split(base, cap, cnt + 3 * q);
+        SB[q][1] = carve_split(base + split_bytes(cap), cap, cnt + 3 * q + 1);
+    }
     return MCDC_OK;
+}
+
+int split_prepare(mcdc_problem *pb, uint64_t chunk, dev::SplitBank SB[2]) {
+    dev::SplitBank pair[1][2];
+    const int rc = split_prepare_slots(pb, chunk, pair, 1);
+    SB[0] = pair[0][0];
+    SB[1] = pair[0][1];
+    return rc;
 }
 
 void split_reset(const dev::SplitBank SB[2], hipStream_t st) {

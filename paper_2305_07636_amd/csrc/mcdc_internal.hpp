@@ -222,6 +222,12 @@ struct mcdc_problem {
     Buf S, L, qoi_hist, qoi_sums, counters, overflow, bank, queues, split, prof, counters_split, tally_part, work, comb;
     Buf mean, var, raw, leak_mean, leak_var, tc_mean, tc_var;
     void *graph_cache = nullptr;   // captured census steps of the event form
+    // weighted history-form runs: a second stream (default priority) and
+    // events for overlapping bank chunks, pinned host words for their
+    // generation counts
+    void *aux_stream = nullptr;
+    void *aux_events[4] = {nullptr, nullptr, nullptr, nullptr};
+    unsigned long long *host_counts = nullptr;
     // MCDC_ALG_AUTO: the faster form for one history count, once timed
     uint64_t auto_n = 0;
     int auto_alg = -1;

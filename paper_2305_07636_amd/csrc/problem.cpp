@@ -557,6 +557,10 @@ extern "C" int mcdc_problem_create(const mcdc_problem_desc *desc, mcdc_problem *
 extern "C" int mcdc_problem_destroy(mcdc_problem *p) {
     if (!p) return MCDC_OK;
     destroy_graph_cache(p);
+    if (p->aux_stream) (void)hipStreamDestroy((hipStream_t)p->aux_stream);
+    for (void *e : p->aux_events)
+        if (e) (void)hipEventDestroy((hipEvent_t)e);
+    if (p->host_counts) (void)hipHostFree(p->host_counts);
     if (p->blob) (void)hipFree(p->blob);
     if (p->ww_dev) (void)hipFree(p->ww_dev);
     mcdc_problem::Buf *bufs[] = {&p->S, &p->L, &p->qoi_hist, &p->qoi_sums, &p->counters,
