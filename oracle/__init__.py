@@ -64,6 +64,7 @@ class _Problem(C.Structure):
         ("implicit_capture", C.c_int32), ("roulette_w", C.c_double), ("roulette_ws", C.c_double),
         ("pin_radius", _DP), ("pin_material", _IP),
         ("rod_z", _DP), ("rod_material", _IP),
+        ("quad_coef", _DP), ("quad_material", _IP),
     ]
 
 
@@ -192,6 +193,10 @@ class OracleProblem:
         if rod is not None:
             s.rod_z = _dp(arr(rod["z"]))
             s.rod_material = arr(rod["material"], np.int32).ctypes.data_as(_IP)
+        quad = prob.get("quadrics")
+        if quad is not None:
+            s.quad_coef = _dp(arr(quad["coef"]))
+            s.quad_material = arr(quad["material"], np.int32).ctypes.data_as(_IP)
         self.time_crossing = bool(s.time_crossing)
         self.struct = s
         self._keep = keep

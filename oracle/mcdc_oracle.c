@@ -148,6 +148,32 @@
  *       above iff z > Z(t), or z == Z(t) and q > 0; it is kept between rod
  *       cells.  Tie order: census, planes, moving plane, collision.  Not
  *       combined with pins nor in eigenvalue cycles; needs a finite z axis.
+ *   R29 Quadric surfaces (optional; Section 3's geometry is built from
+ *       quadric surfaces): a geometry cell may carry one quadric
+ *       Q(x) = A x^2 + B y^2 + C z^2 + D x y + E y z + F z x + G x + H y
+ *       + J z + K with a material for its inside (Q < 0); outside it the
+ *       cell keeps its own material.  Along x + d u,
+ *       Q = a d^2 + 2 b d + c with, in this evaluation order,
+ *         a = ((A ux ux + B uy uy) + C uz uz) + ((D ux uy + E uy uz) + F uz ux)
+ *         b = ((A x ux + B y uy) + C z uz) + 0.5 ((((D (x uy + y ux)
+ *             + E (y uz + z uy)) + F (z ux + x uz)) + ((G ux + H uy) + J uz)))
+ *         c = (((A x x + B y y) + C z z) + ((D x y + E y z) + F z x))
+ *             + (((G x + H y) + J z) + K)
+ *       (products left to right).  The particle carries an inside flag;
+ *       with disc = b b - a c, the distance to the surface is: inside,
+ *       a > 0: (-b + sqrt(max(disc, 0))) / a; a < 0: (-b + sqrt(disc)) / a
+ *       if b > 0 and disc > 0; a = 0: -c / (2 b) if b > 0; outside, a > 0:
+ *       (-b - sqrt(disc)) / a if b < 0 and disc > 0; a < 0:
+ *       (-b - sqrt(disc)) / a if disc > 0; a = 0: -c / (2 b) if b < 0;
+ *       else none; clipped at 0.  (These are the first roots ahead at which
+ *       Q changes sign in the flag's direction.)  Crossing it is a surface
+ *       event that crosses no union plane and flips the flag.  The flag is
+ *       set at birth, and when a plane crossing lands in another geometry
+ *       cell (after any reflection), from the particle's side of that
+ *       cell's quadric: inside iff c < 0, or c == 0 and b < 0; 0 in a cell
+ *       without one.  Tie order: census, planes, quadric, collision.  Not
+ *       combined with pins or a moving plane; not in a slab (x the only
+ *       finite axis).
  *
  * Build: gcc -O2 -ffp-contract=off -fPIC -shared -o liboracle.so mcdc_oracle.c -lm
  */
@@ -206,6 +232,9 @@ typedef struct {
     /* moving plane (R27): heights at the time edges and rod cells, or NULL */
     const double *rod_z;          /* [K + 1] */
     const int32_t *rod_material;  /* [cz][cy][cx], -1 = not a rod cell */
+    /* quadric surfaces (R29): per geometry cell, or NULL */
+    const double *quad_coef;      /* [cz][cy][cx][10]: A B C D E F G H J K */
+    const int32_t *quad_material; /* [cz][cy][cx], -1 = no quadric */
 } oracle_problem;
 
 enum { EV_CENSUS = 0, EV_SURFACE = 1, EV_COLLISION = 2 };
@@ -382,7 +411,7 @@ typedef struct {
     double t, tau, w;
     int ix[3];
     int g, k;
-    int inpin;      /* R15: inside the cell's pin */
+    int inpin;      /* R15: inside the cell's pin; R29: inside the cell's quadric */
     int above;      /* R27: above the moving plane (meaningful in rod cells) */
     int since;      /* events since birth or the last census */
     uint64_t s;
@@ -463,7 +492,7 @@ static int material_of(const ctx *C, const particle *pt)
 {
     int c[3];
     int64_t g = geo_cell(C, pt, c);
-    if (pt->inpin) return C->p->pin_material[g];
+    if (pt->inpin) return C->p->pin_radius ? C->p->pin_material[g] : C->p->quad_material[g];
     if (C->p->rod_material && C->p->rod_material[g] >= 0 && pt->above) return C->p->rod_material[g];
     return C->p->material[g];
 }
@@ -504,6 +533,66 @@ static int pin_of(const ctx *C, const particle *pt, double *xc, double *yc, doub
     *yc = 0.5 * (p->planes[1][c[1]] + p->planes[1][c[1] + 1]);
     *r2 = r * r;
     return 1;
+}
+
+/* R29: the quadric of the particle's geometry cell (its coefficients), or
+ * NULL; *gc receives the geometry cell */
+static const double *quad_of(const ctx *C, const particle *pt, int64_t *gc)
+{
+    const oracle_problem *p = C->p;
+    int c[3];
+    int64_t g = geo_cell(C, pt, c);
+    if (gc) *gc = g;
+    if (!p->quad_material || p->quad_material[g] < 0) return NULL;
+    return p->quad_coef + 10 * g;
+}
+
+/* R29: Q(x + d u) = a d^2 + 2 b d + c */
+static void quad_abc(const double *q, const double *x, const double *u, double *a, double *b, double *c)
+{
+    *a = ((q[0] * u[0] * u[0] + q[1] * u[1] * u[1]) + q[2] * u[2] * u[2]) +
+         ((q[3] * u[0] * u[1] + q[4] * u[1] * u[2]) + q[5] * u[2] * u[0]);
+    *b = ((q[0] * x[0] * u[0] + q[1] * x[1] * u[1]) + q[2] * x[2] * u[2]) +
+         0.5 * (((q[3] * (x[0] * u[1] + x[1] * u[0]) + q[4] * (x[1] * u[2] + x[2] * u[1])) +
+                 q[5] * (x[2] * u[0] + x[0] * u[2])) +
+                ((q[6] * u[0] + q[7] * u[1]) + q[8] * u[2]));
+    *c = (((q[0] * x[0] * x[0] + q[1] * x[1] * x[1]) + q[2] * x[2] * x[2]) +
+          ((q[3] * x[0] * x[1] + q[4] * x[1] * x[2]) + q[5] * x[2] * x[0])) +
+         (((q[6] * x[0] + q[7] * x[1]) + q[8] * x[2]) + q[9]);
+}
+
+/* R29: inside the quadric at the particle's place, or on it and moving in */
+static int quad_side(const double *q, const particle *pt)
+{
+    double a, b, c;
+    quad_abc(q, pt->x, pt->u, &a, &b, &c);
+    return c < 0.0 || (c == 0.0 && b < 0.0);
+}
+
+/* R29: distance to the quadric from the side the flag gives, or infinity */
+static double quad_distance(const double *q, const particle *pt)
+{
+    double a, b, c;
+    quad_abc(q, pt->x, pt->u, &a, &b, &c);
+    double d = INFINITY;
+    const double disc = b * b - a * c;
+    if (pt->inpin) {
+        if (a > 0.0)
+            d = (-b + sqrt(disc > 0.0 ? disc : 0.0)) / a;
+        else if (a < 0.0) {
+            if (b > 0.0 && disc > 0.0) d = (-b + sqrt(disc)) / a;
+        } else if (b > 0.0)
+            d = -c / (2.0 * b);
+    } else {
+        if (a > 0.0) {
+            if (b < 0.0 && disc > 0.0) d = (-b - sqrt(disc)) / a;
+        } else if (a < 0.0) {
+            if (disc > 0.0) d = (-b - sqrt(disc)) / a;
+        } else if (b < 0.0)
+            d = -c / (2.0 * b);
+    }
+    if (d < 0.0) d = 0.0;
+    return d;
 }
 
 /* tally bin of the particle's union cell in the current (k, g), or -1 */
@@ -684,6 +773,10 @@ static int step(ctx *C, particle *pt, int b, particle *stack, int *sp, hist_rec 
                 if (dcyl < 0.0) dcyl = 0.0;
             }
         }
+        /* R29: distance to the cell's quadric (a problem has pins or
+           quadrics, not both) */
+        const double *q = quad_of(C, pt, NULL);
+        if (q) dcyl = quad_distance(q, pt);
     }
     /* R27: distance to the moving plane in a rod cell */
     double dmov = INFINITY;
@@ -777,6 +870,8 @@ static int step(ctx *C, particle *pt, int b, particle *stack, int *sp, hist_rec 
         C->tot[1]++;
         int wcell_changed = 0;
         const int rod_before = rod_cell(C, pt);
+        int64_t geo_before = -1;
+        if (p->quad_material) (void)quad_of(C, pt, &geo_before);
         for (int a = 0; a < 3 && alive; a++) {
             if (mov || C->ax[a].n == 0 || da[a] != d) continue;
             int last = C->ax[a].n - 2;
@@ -805,6 +900,13 @@ static int step(ctx *C, particle *pt, int b, particle *stack, int *sp, hist_rec 
             if (pt->ix[a] != old && C->ax[a].wwc[pt->ix[a]] != C->ax[a].wwc[old]) wcell_changed = 1;
         }
         if (cyl) pt->inpin ^= 1;
+        if (!cyl && alive && p->quad_material) {
+            /* R29: landing in another geometry cell sets the flag from that
+               cell's quadric */
+            int64_t geo_now;
+            const double *q = quad_of(C, pt, &geo_now);
+            if (geo_now != geo_before) pt->inpin = q ? quad_side(q, pt) : 0;
+        }
         if (mov) {
             pt->above ^= 1;
         } else if (alive && p->rod_material) {
@@ -934,6 +1036,9 @@ static int birth(ctx *C, uint64_t s0, particle *pt, hist_rec *h)
             double dx = pt->x[0] - xc, dy = pt->x[1] - yc;
             pt->inpin = ((dx * dx + dy * dy) - r2) < 0.0;
         }
+        /* R29 */
+        const double *q = quad_of(C, pt, NULL);
+        if (q) pt->inpin = quad_side(q, pt);
     }
     /* time bin */
     if (pt->t >= p->time_edges[C->K]) {
@@ -976,6 +1081,17 @@ static int ctx_init(ctx *C, const oracle_problem *p)
             if (!isfinite(p->rod_z[k])) return -1;
         for (int64_t g = 0; g < (int64_t)C->nc[0] * C->nc[1] * C->nc[2]; g++)
             if (p->rod_material[g] < -1 || p->rod_material[g] >= M) return -1;
+    }
+    if (p->quad_material) {
+        /* R29: finite coefficients, materials in range, no pins or moving
+           plane, not a slab */
+        if (!p->quad_coef || p->pin_radius || p->rod_material) return -1;
+        if (p->n_planes[1] == 0 && p->n_planes[2] == 0) return -1;
+        for (int64_t g = 0; g < (int64_t)C->nc[0] * C->nc[1] * C->nc[2]; g++) {
+            if (p->quad_material[g] < -1 || p->quad_material[g] >= M) return -1;
+            for (int j = 0; j < 10; j++)
+                if (!isfinite(p->quad_coef[10 * g + j])) return -1;
+        }
     }
     if (p->pin_radius) {
         /* R15: pins need finite x and y axes and must fit their cells */

@@ -45,6 +45,10 @@ Problem dict schema (all floats are float64, all ints int32):
               time edges (linear in time between them) and material
               [nz, ny, nx] (the material above the plane in each geometry
               cell, -1 = the cell's own material on both sides)
+    quadrics  None or dict: coef [nz, ny, nx, 10] (A..K of the quadric
+              A x^2 + B y^2 + C z^2 + D xy + E yz + F zx + G x + H y + J z
+              + K in each geometry cell) and material [nz, ny, nx] (the
+              material where it is negative, -1 = no quadric)
     ww_mesh   None or list of 3 arrays of weight-window mesh planes
 
 The workload recipes follow the transport problems the method is exercised
@@ -125,6 +129,7 @@ def make_problem(sigma_t, sigma_s, speed, planes, material, bc, source, tally,
         "implicit_capture": None,
         "pins": None,
         "rod": None,
+        "quadrics": None,
     }
     if fission is not None:
         p["fission"] = {k: _f64(fission[k]).reshape(M, G) for k in ("sigma_f", "nu", "chi")}
@@ -391,6 +396,78 @@ def beam_through_pin(y0=1.2, sigma_pin=1.5, radius=0.6, n_bins=20, mu_law="beam"
     p = make_problem([[0.0], [sigma_pin]], [[[0.0]], [[0.0]]], [1.0], planes, np.zeros((1, 1, 1)),
                      [VACUUM] * 6, src, tally)
     p["pins"] = {"radius": np.array([[[radius]]]), "material": np.array([[[1]]], dtype=np.int32)}
+    return p
+
+
+def sphere_quadric(center, radius):
+    """Coefficients (A..K) of the sphere |x - c|^2 - r^2."""
+    cx, cy, cz = center
+    return np.array([1.0, 1.0, 1.0, 0.0, 0.0, 0.0, -2.0 * cx, -2.0 * cy, -2.0 * cz,
+                     cx * cx + cy * cy + cz * cz - radius * radius])
+
+
+def cone_quadric(apex):
+    """Coefficients of the double cone (x - x0)^2 + (y - y0)^2 - (z - z0)^2
+    (negative inside the two nappes along z)."""
+    x0, y0, z0 = apex
+    return np.array([1.0, 1.0, -1.0, 0.0, 0.0, 0.0, -2.0 * x0, -2.0 * y0, 2.0 * z0,
+                     x0 * x0 + y0 * y0 - z0 * z0])
+
+
+def plane_quadric(normal, offset):
+    """Coefficients of the plane n . x - offset (a quadric of degree one)."""
+    return np.array([0.0, 0.0, 0.0, 0.0, 0.0, 0.0, normal[0], normal[1], normal[2], -offset])
+
+
+def beam_through_quadric(coef, axis=0, sign=1, point=(0.0, 1.2, 0.9), sigma=1.5, n_bins=20,
+                         scatter=0.0, inside_material=1):
+    """A [0, 2]^3 void box (vacuum faces) whose one geometry cell carries
+    the quadric `coef`, filled inside with an absorber of total cross
+    section sigma (scattering ratio `scatter`).  Surface source at `point`
+    on the face the beam enters through (axis, sign), entering as a beam;
+    flux tally in n_bins bins along the beam axis."""
+    planes = [np.array([0.0, 2.0])] * 3
+    lo = list(point)
+    lo[axis] = 0.0 if sign > 0 else 2.0
+    src = {"kind": "surface", "axis": axis, "sign": sign, "mu_law": "beam", "lo": lo, "hi": lo,
+           "group_pmf": [1.0]}
+    mesh = [np.array([0.0, 2.0])] * 3
+    mesh[axis] = np.linspace(0.0, 2.0, n_bins + 1)
+    tally = {"mesh": mesh, "time_edges": [0.0, math.inf], "n_batches": 32}
+    p = make_problem([[0.0], [sigma]], [[[0.0]], [[scatter * sigma]]], [1.0], planes,
+                     np.zeros((1, 1, 1)), [VACUUM] * 6, src, tally)
+    p["quadrics"] = {"coef": np.asarray(coef, dtype=np.float64).reshape(1, 1, 1, 10),
+                     "material": np.array([[[inside_material]]], dtype=np.int32)}
+    return p
+
+
+def sphere_lattice(n=4, pitch=1.26, radius=0.5, n_layers=4, n_groups=3, gen_seed=23, n_time_bins=5, t_end=5.0,
+                   bc=REFLECTIVE, n_batches=16):
+    """n x n x n_layers lattice of cubic cells of the given pitch, each
+    holding a spherical fuel kernel (material 0) of the given radius in
+    moderator (material 1): quadric-surface geometry; synthetic cross
+    sections; uniform volume pulse in group 0 at t = 0; one tally bin per
+    cell."""
+    rng = SplitMix64(gen_seed)
+    G = n_groups
+    st = np.zeros((2, G))
+    ss = np.zeros((2, G, G))
+    for m in range(2):
+        st[m], ss[m] = synthetic_xs(rng, G)
+    px = np.arange(n + 1) * pitch
+    pz = np.arange(n_layers + 1) * pitch
+    pmf = np.zeros(G)
+    pmf[0] = 1.0
+    src = {"kind": "isotropic", "lo": [0.0, 0.0, 0.0], "hi": [px[-1], px[-1], pz[-1]], "group_pmf": pmf}
+    tally = {"mesh": [px, px, pz], "time_edges": np.linspace(0.0, t_end, n_time_bins + 1), "n_batches": n_batches}
+    p = make_problem(st, ss, [float(G - g) for g in range(G)], [px, px, pz],
+                     np.ones((n_layers, n, n), dtype=np.int32), [bc] * 6, src, tally)
+    coef = np.zeros((n_layers, n, n, 10))
+    for k in range(n_layers):
+        for j in range(n):
+            for i in range(n):
+                coef[k, j, i] = sphere_quadric(((i + 0.5) * pitch, (j + 0.5) * pitch, (k + 0.5) * pitch), radius)
+    p["quadrics"] = {"coef": coef, "material": np.zeros((n_layers, n, n), dtype=np.int32)}
     return p
 
 
