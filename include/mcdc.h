@@ -43,7 +43,7 @@
 extern "C" {
 #endif
 
-#define MCDC_ABI_VERSION 5
+#define MCDC_ABI_VERSION 6
 
 /* return codes */
 #define MCDC_OK 0
@@ -163,6 +163,28 @@ typedef struct mcdc_problem mcdc_problem;
  * planes, moving plane, collision; a crossing is a surface event that
  * crosses no plane and flips the flag.  Needs a finite z axis; not
  * combined with pins; not in eigenvalue runs.  Both NULL: none.
+ *
+ * Quadric surfaces (optional; Section 3 models its geometry with quadric
+ * surfaces; ABI version 6): quadric_coef[cz][cy][cx][10] are the
+ * coefficients A B C D E F G H J K of one second-degree surface
+ *   Q(x, y, z) = A x^2 + B y^2 + C z^2 + D x y + E y z + F z x
+ *                + G x + H y + J z + K
+ * per geometry cell (all finite), and quadric_material[cz][cy][cx] the
+ * material on its negative side (-1: the cell has none).  Along a flight
+ * Q(x + d u) = a d^2 + 2 b d + c.  A particle carries an inside flag (c < 0,
+ * or c == 0 with b < 0), set at birth and whenever a plane crossing lands
+ * it in another geometry cell (0 where that cell has no quadric).  From
+ * inside the distance is the larger root when a > 0 (discriminant clipped
+ * at 0), the root (-b + sqrt(b^2 - a c)) / a when a < 0 and b > 0 with a
+ * positive discriminant, -c / (2 b) when a == 0 and b > 0; from outside the
+ * smaller root when a > 0, b < 0 and the discriminant is positive,
+ * (-b - sqrt(b^2 - a c)) / a when a < 0 with a positive discriminant,
+ * -c / (2 b) when a == 0 and b < 0; otherwise infinite; negative distances
+ * clip at 0.  Ties go census, planes, quadric, collision; a quadric
+ * crossing is a surface event that crosses no plane and flips the flag.
+ * The surface is not clipped to its cell: the cell's planes bound it.  y or
+ * z must be a finite axis (a slab takes none); not combined with pins or a
+ * moving plane.  Both NULL: none.
  */
 typedef struct {
     int32_t abi_version; /* MCDC_ABI_VERSION */
@@ -206,6 +228,8 @@ typedef struct {
     const int32_t *pin_material;
     const double *rod_z;
     const int32_t *rod_material;
+    const double *quadric_coef;
+    const int32_t *quadric_material;
 } mcdc_problem_desc;
 
 /*

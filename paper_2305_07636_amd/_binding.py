@@ -16,7 +16,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libmcdc_hip.so")
 
-MCDC_ABI_VERSION = 5
+MCDC_ABI_VERSION = 6
 MCDC_OK, MCDC_E_INVALID, MCDC_E_HIP, MCDC_E_NOMEM, MCDC_E_OVERFLOW, MCDC_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5
 MCDC_ALG_EVENT, MCDC_ALG_HISTORY, MCDC_ALG_AUTO = 0, 1, 2
 MCDC_SRC_ISOTROPIC, MCDC_SRC_SURFACE = 0, 1
@@ -54,6 +54,7 @@ class mcdc_problem_desc(C.Structure):
         ("implicit_capture", C.c_int32), ("roulette_w", C.c_double), ("roulette_ws", C.c_double),
         ("pin_radius", _DP), ("pin_material", _IP),
         ("rod_z", _DP), ("rod_material", _IP),
+        ("quadric_coef", _DP), ("quadric_material", _IP),
     ]
 
 
@@ -208,6 +209,10 @@ def make_desc(prob: dict):
     if rod is not None:
         d.rod_z = _dp(arr(rod["z"]))
         d.rod_material = arr(rod["material"], np.int32).ctypes.data_as(_IP)
+    quad = prob.get("quadrics")
+    if quad is not None:
+        d.quadric_coef = _dp(arr(quad["coef"]))
+        d.quadric_material = arr(quad["material"], np.int32).ctypes.data_as(_IP)
     return d, keep
 
 

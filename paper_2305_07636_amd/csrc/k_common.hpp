@@ -87,16 +87,19 @@ struct Particle {
     double t, tau, w;
     int ix[3];
     int g, k;
-    int inpin;                  // inside the cell's cylindrical pin, or (problems with a
-                                // moving plane) above the plane in a rod cell
+    int inpin;                  // inside the cell's cylindrical pin or quadric, or
+                                // (problems with a moving plane) above the plane in a
+                                // rod cell
     uint64_t s;
 };
 
 // Material of union cell `cell` for a particle with the given flag: the
-// cell's, its pin's inside the pin, its rod's above the moving plane.
+// cell's, its pin's inside the pin, its quadric's on the negative side,
+// its rod's above the moving plane.
 __device__ __forceinline__ int material_at(const DevProblem &P, int cell, int flag) {
     if (flag) {
         if (P.pins_on) return P.pin_mat[cell];
+        if (P.quad_on) return P.quad_mat[cell];
         if (P.rod_on && P.rod_mat[cell] >= 0) return P.rod_mat[cell];
     }
     return P.cell_mat[cell];
@@ -121,6 +124,59 @@ __device__ __forceinline__ int rod_side(const DevProblem &P, const Particle &p) 
     if (p.x[2] > Z) return 1;
     if (p.x[2] < Z) return 0;
     return rod_rate(P, p) > 0.0 ? 1 : 0;
+}
+
+// Quadric along the flight: Q(x + d u) = a d^2 + 2 b d + c for the
+// coefficients q = A B C D E F G H J K of
+// A x^2 + B y^2 + C z^2 + D x y + E y z + F z x + G x + H y + J z + K.  The
+// sums are taken in one fixed order (square terms, then cross terms, then
+// linear terms), so every form of the kernels rounds them alike.
+struct QuadLine {
+    double a, b, c;
+};
+__device__ __forceinline__ QuadLine quad_line(const double *q, const Particle &p) {
+    const double x = p.x[0], y = p.x[1], z = p.x[2];
+    const double ux = p.u[0], uy = p.u[1], uz = p.u[2];
+    QuadLine l;
+    l.a = ((q[0] * ux * ux + q[1] * uy * uy) + q[2] * uz * uz) + ((q[3] * ux * uy + q[4] * uy * uz) + q[5] * uz * ux);
+    l.b = ((q[0] * x * ux + q[1] * y * uy) + q[2] * z * uz) +
+          0.5 * (((q[3] * (x * uy + y * ux) + q[4] * (y * uz + z * uy)) + q[5] * (z * ux + x * uz)) +
+                 ((q[6] * ux + q[7] * uy) + q[8] * uz));
+    l.c = (((q[0] * x * x + q[1] * y * y) + q[2] * z * z) + ((q[3] * x * y + q[4] * y * z) + q[5] * z * x)) +
+          (((q[6] * x + q[7] * y) + q[8] * z) + q[9]);
+    return l;
+}
+// The side of the quadric the particle is on (1 negative): on it, the side
+// it moves to.
+__device__ __forceinline__ int quad_side(const double *q, const Particle &p) {
+    const QuadLine l = quad_line(q, p);
+    return (l.c < 0.0 || (l.c == 0.0 && l.b < 0.0)) ? 1 : 0;
+}
+// Distance to the quadric from the side the flag names: the root the
+// flight reaches first on leaving (inside) or entering (outside), or
+// infinity when it reaches none.
+__device__ __forceinline__ double quad_distance(const double *q, const Particle &p) {
+    const QuadLine l = quad_line(q, p);
+    const double disc = l.b * l.b - l.a * l.c;
+    double d = kInf;
+    if (p.inpin) {
+        if (l.a > 0.0)
+            d = (-l.b + sqrt(disc > 0.0 ? disc : 0.0)) / l.a;
+        else if (l.a < 0.0) {
+            if (l.b > 0.0 && disc > 0.0) d = (-l.b + sqrt(disc)) / l.a;
+        } else if (l.b > 0.0) {
+            d = -l.c / (2.0 * l.b);
+        }
+    } else {
+        if (l.a > 0.0) {
+            if (l.b < 0.0 && disc > 0.0) d = (-l.b - sqrt(disc)) / l.a;
+        } else if (l.a < 0.0) {
+            if (disc > 0.0) d = (-l.b - sqrt(disc)) / l.a;
+        } else if (l.b < 0.0) {
+            d = -l.c / (2.0 * l.b);
+        }
+    }
+    return d < 0.0 ? 0.0 : d;
 }
 
 template <int FM>
@@ -212,6 +268,10 @@ __device__ __forceinline__ bool birth(const DevProblem &P, uint64_t s0, Particle
             p.inpin = ((dx * dx + dy * dy) - r2) < 0.0;
         }
     }
+    if (FM != 1 && P.quad_on) {
+        const int qi = P.quad_cell[cell_index(P, p.ix)];
+        if (qi >= 0) p.inpin = quad_side(P.quad_coef + 10 * qi, p);
+    }
     if (p.t >= P.T[P.K]) {
         p.k = P.K;
         return false;
@@ -282,14 +342,19 @@ __device__ __forceinline__ Flight next_event(const DevProblem &P, const Particle
             }
         }
     }
+    // the cell's quadric (a problem has pins, quadrics or a moving plane)
+    if (FM != 1 && P.quad_on) {
+        const int qi = P.quad_cell[cell];
+        if (qi >= 0) dcyl = quad_distance(P.quad_coef + 10 * qi, p);
+    }
     double Tn = P.T[p.k + 1];
     double dt = kInf;
     if (Tn != kInf) {
         dt = (Tn - p.t) * P.speed[p.g];
         if (dt < 0.0) dt = 0.0;
     }
-    // tie order: census, planes, pin or moving plane, collision (a pin or
-    // moving-plane crossing is a surface event that crosses no plane)
+    // tie order: census, planes, pin, quadric or moving plane, collision (a
+    // crossing of one of those is a surface event that crosses no plane)
     if (dt <= ds && dt <= dcyl && dt <= dc) {
         f.ev = kCensus;
         f.d = dt;
@@ -338,14 +403,17 @@ __device__ __forceinline__ int crossing_mask(const DevProblem &P, const Flight &
 // face crossed (the particle leaks; later axes are not processed), or -1.
 // With a moving plane, a crossing that enters a rod cell from a cell that
 // is not one sets the above flag from the particle's side of the plane;
-// between rod cells the flag is kept.
+// between rod cells the flag is kept.  With quadrics, a crossing that lands
+// in another geometry cell sets the inside flag from that cell's quadric
+// (0 where it has none); within a geometry cell the flag is kept.
 template <int FM>
 __device__ __forceinline__ int cross(const DevProblem &P, Particle &p, int mask) {
-    if (FM != 1 && mask == 0) {   // the cell's pin surface or the moving plane (a slab has neither)
+    if (FM != 1 && mask == 0) {   // the cell's pin, quadric or moving plane (a slab has none)
         p.inpin ^= 1;
         return -1;
     }
     const bool rod_before = (FM != 1 && P.rod_on) ? P.rod_mat[cell_index(P, p.ix)] >= 0 : false;
+    const int quad_before = (FM != 1 && P.quad_on) ? P.quad_cell[cell_index(P, p.ix)] : -1;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         if (!finite_axis<FM>(P, a) || !((mask >> a) & 1)) continue;
@@ -381,6 +449,10 @@ __device__ __forceinline__ int cross(const DevProblem &P, Particle &p, int mask)
             p.inpin = 0;
         else if (!rod_before)
             p.inpin = rod_side(P, p);
+    }
+    if (FM != 1 && P.quad_on) {
+        const int qi = P.quad_cell[cell_index(P, p.ix)];
+        if (qi != quad_before) p.inpin = (qi >= 0) ? quad_side(P.quad_coef + 10 * qi, p) : 0;
     }
     return -1;
 }

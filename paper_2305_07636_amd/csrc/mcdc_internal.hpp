@@ -83,6 +83,12 @@ struct DevProblem {
     const double *rod_z;       // [K + 1] heights at the time edges
     const double *rod_v;       // [K] speed in each census step
     const int32_t *rod_mat;    // [ncells] material above the plane, -1 = not a rod cell
+    // quadric surfaces, one per geometry cell (quad_on = 0: none; never with
+    // pins or a moving plane)
+    int quad_on;
+    const int32_t *quad_cell;  // [ncells] the quadric of the cell's geometry cell, -1 = none
+    const double *quad_coef;   // [nq][10] A B C D E F G H J K
+    const int32_t *quad_mat;   // [ncells] material on the quadric's negative side
 };
 
 // Runs whose particles make progeny (window splits, fission neutrons) or
@@ -195,6 +201,9 @@ struct HostProblem {
     bool rod = false;
     std::vector<double> rod_z, rod_v;  // [K + 1], [K] (moving plane only)
     std::vector<int32_t> rod_mat;      // [ncells]
+    bool quad = false;
+    std::vector<int32_t> quad_cell, quad_mat;  // [ncells] (quadrics only)
+    std::vector<double> quad_coef;             // [nq][10]
     std::vector<uint8_t> qoi_groups;
     std::vector<double> bin_norm;      // [nts] V_j (product of bin widths)
     std::vector<double> time_norm;     // [K] dt_k (1 if infinite)

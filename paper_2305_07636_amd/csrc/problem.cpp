@@ -397,6 +397,39 @@ int compile(const mcdc_problem_desc *d, HostProblem &h) {
                 }
     }
 
+    // quadric surfaces: one table row per geometry cell that has one; per
+    // union cell, the row of its geometry cell and the material inside
+    if (d->quadric_coef || d->quadric_material) {
+        if (!d->quadric_coef || !d->quadric_material) return invalid("quadrics need quadric_coef and quadric_material");
+        if (d->pin_radius || d->rod_z || d->rod_material) {
+            set_error("quadric surfaces are not combined with pins or a moving plane");
+            return MCDC_E_UNSUPPORTED;
+        }
+        if (d->n_planes[1] == 0 && d->n_planes[2] == 0) return invalid("quadrics need a finite y or z axis");
+        std::vector<int32_t> row(ngeo, -1);
+        for (size_t g = 0; g < ngeo; ++g) {
+            const int32_t m = d->quadric_material[g];
+            if (m < -1 || m >= M) return invalid("quadric material out of range");
+            for (int j = 0; j < 10; ++j)
+                if (!std::isfinite(d->quadric_coef[10 * g + j])) return invalid("quadric coefficients must be finite");
+            if (m < 0) continue;
+            row[g] = (int32_t)(h.quad_coef.size() / 10);
+            h.quad_coef.insert(h.quad_coef.end(), d->quadric_coef + 10 * g, d->quadric_coef + 10 * g + 10);
+        }
+        h.quad = true;
+        if (h.quad_coef.empty()) h.quad_coef.assign(10, 0.0);
+        h.quad_cell.assign(ncells, -1);
+        h.quad_mat.assign(ncells, 0);
+        for (int iz = 0; iz < h.nc[2]; ++iz)
+            for (int iy = 0; iy < h.nc[1]; ++iy)
+                for (int ix = 0; ix < h.nc[0]; ++ix) {
+                    const size_t c = ((size_t)iz * h.nc[1] + iy) * h.nc[0] + ix;
+                    const size_t g = ((size_t)geo_of[2][iz] * ngc[1] + geo_of[1][iy]) * ngc[0] + geo_of[0][ix];
+                    h.quad_cell[c] = row[g];
+                    if (row[g] >= 0) h.quad_mat[c] = d->quadric_material[g];
+                }
+    }
+
     // normalisation: bin volume (product of the widths of meshed axes) and
     // time-bin width (1 for an infinite bin)
     std::vector<double> wdt[3];
@@ -433,7 +466,8 @@ int upload(mcdc_problem *p) {
                  o_pf = b.add(h.pf), o_nu = b.add(h.nu), o_chi = b.add(h.chi_cdf),
                  o_pr2 = b.add(h.pin_r2), o_pxc = b.add(h.pin_xc), o_pyc = b.add(h.pin_yc),
                  o_pm = b.add(h.pin_mat), o_rz = b.add(h.rod_z), o_rv = b.add(h.rod_v),
-                 o_rm = b.add(h.rod_mat);
+                 o_rm = b.add(h.rod_mat), o_qc = b.add(h.quad_cell), o_qk = b.add(h.quad_coef),
+                 o_qm = b.add(h.quad_mat);
     std::vector<uint64_t> A(64), C(64);
     lcg_map(kStride, A[0], C[0]);
     for (int j = 1; j < 64; ++j) {
@@ -514,6 +548,10 @@ int upload(mcdc_problem *p) {
     D.rod_z = h.rod ? (const double *)(base + o_rz) : nullptr;
     D.rod_v = h.rod ? (const double *)(base + o_rv) : nullptr;
     D.rod_mat = h.rod ? (const int32_t *)(base + o_rm) : nullptr;
+    D.quad_on = h.quad ? 1 : 0;
+    D.quad_cell = h.quad ? (const int32_t *)(base + o_qc) : nullptr;
+    D.quad_coef = h.quad ? (const double *)(base + o_qk) : nullptr;
+    D.quad_mat = h.quad ? (const int32_t *)(base + o_qm) : nullptr;
     D.implicit = d.implicit_capture ? 1 : 0;
     D.roulette_w = d.roulette_w;
     D.roulette_ws = d.roulette_ws;

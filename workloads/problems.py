@@ -471,6 +471,70 @@ def sphere_lattice(n=4, pitch=1.26, radius=0.5, n_layers=4, n_groups=3, gen_seed
     return p
 
 
+def mixed_quadric_lattice(n=3, n_layers=2, pitch=1.26, n_groups=3, gen_seed=29, refine=2, n_time_bins=4,
+                          t_end=4.0, bc=REFLECTIVE, n_batches=8):
+    """n x n x n_layers lattice of cubic cells, each geometry cell holding
+    one quadric drawn from: a sphere, a tilted ellipsoid (cross terms), a
+    double cone, a one-sheet hyperboloid, a tilted plane, a quadric holding
+    the cell's own material, or none; the inside material drawn from the
+    three.  Tally mesh `refine` times finer than the cells, so particles
+    cross union-cell planes inside one geometry cell (and its quadric)."""
+    rng = SplitMix64(gen_seed)
+    G = n_groups
+    st = np.zeros((3, G))
+    ss = np.zeros((3, G, G))
+    for m in range(3):
+        st[m], ss[m] = synthetic_xs(rng, G)
+    px = np.arange(n + 1) * pitch
+    pz = np.arange(n_layers + 1) * pitch
+    mat = np.zeros((n_layers, n, n), dtype=np.int32)
+    coef = np.zeros((n_layers, n, n, 10))
+    qmat = np.full((n_layers, n, n), -1, dtype=np.int32)
+    for k in range(n_layers):
+        for j in range(n):
+            for i in range(n):
+                mat[k, j, i] = rng.randint(0, 2)
+                c = np.array([(i + rng.uniform(0.3, 0.7)) * pitch, (j + rng.uniform(0.3, 0.7)) * pitch,
+                              (k + rng.uniform(0.3, 0.7)) * pitch])
+                kind = rng.randint(0, 6)
+                r = rng.uniform(0.2, 0.5) * pitch
+                if kind == 0:
+                    q = sphere_quadric(c, r)
+                elif kind in (1, 5):
+                    # (x - c)^T S (x - c) - r^2 with S = R^T diag R: a rotated ellipsoid
+                    ang = rng.uniform(0.0, math.pi)
+                    ca, sa = math.cos(ang), math.sin(ang)
+                    Rm = np.array([[ca, -sa, 0.0], [sa, ca, 0.0], [0.0, 0.0, 1.0]])
+                    Sm = Rm.T @ np.diag([rng.uniform(0.5, 2.0), rng.uniform(0.5, 2.0), rng.uniform(0.5, 2.0)]) @ Rm
+                    lin = -2.0 * Sm @ c
+                    q = np.array([Sm[0, 0], Sm[1, 1], Sm[2, 2], 2.0 * Sm[0, 1], 2.0 * Sm[1, 2], 2.0 * Sm[2, 0],
+                                  lin[0], lin[1], lin[2], float(c @ Sm @ c) - r * r])
+                elif kind == 2:
+                    q = cone_quadric(c)
+                elif kind == 3:
+                    # one-sheet hyperboloid about z: (x-cx)^2 + (y-cy)^2 - (z-cz)^2 - r^2
+                    q = cone_quadric(c)
+                    q[9] -= r * r
+                elif kind == 4:
+                    nrm = np.array([rng.uniform(-1, 1), rng.uniform(-1, 1), rng.uniform(-1, 1)])
+                    q = plane_quadric(nrm, float(nrm @ c))
+                else:
+                    q = sphere_quadric(c, r)
+                coef[k, j, i] = q
+                if kind == 6:
+                    continue        # no quadric (its coefficients stay unused)
+                qmat[k, j, i] = mat[k, j, i] if kind == 5 else rng.randint(0, 2)
+    pmf = np.zeros(G)
+    pmf[0] = 1.0
+    src = {"kind": "isotropic", "lo": [0.0, 0.0, 0.0], "hi": [px[-1], px[-1], pz[-1]], "group_pmf": pmf}
+    mx = np.linspace(0.0, px[-1], refine * n + 1)
+    mz = np.linspace(0.0, pz[-1], refine * n_layers + 1)
+    tally = {"mesh": [mx, mx, mz], "time_edges": np.linspace(0.0, t_end, n_time_bins + 1), "n_batches": n_batches}
+    p = make_problem(st, ss, [float(G - g) for g in range(G)], [px, px, pz], mat, [bc] * 6, src, tally)
+    p["quadrics"] = {"coef": coef, "material": qmat}
+    return p
+
+
 def pin_lattice(n=3, pitch=1.26, radius=0.54, height=10.0, n_groups=3, gen_seed=17, n_z_bins=4,
                 n_time_bins=5, t_end=5.0, bc_xy=REFLECTIVE, bc_z=VACUUM, n_batches=16, fine=1):
     """n x n lattice of square cells of the given pitch, each holding a
