@@ -371,6 +371,56 @@ def pins_section(m, w, n, steps):
     return res
 
 
+def quadrics_section(m, w, n, steps):
+    """General quadric surfaces: a 17 x 17 x 10 lattice of 1.26 cubic cells,
+    a 0.5-radius spherical fuel kernel in each (7 groups, one tally bin per
+    cell, 20 time bins), both forms; and the k-eigenvalue cycles of the
+    reflected pin cell with its fuel cylinder written as a general quadric
+    (50 inactive + 100 active cycles of 1e5), beside the pin form."""
+    import numpy as np
+    import torch
+
+    prob = w.sphere_lattice(n=17, n_layers=10, n_groups=7, gen_seed=3, n_time_bins=20, t_end=20.0, n_batches=32)
+    h = m.mcdc_problem_create(prob)
+    res = {"workload": f"17 x 17 x 10 sphere lattice (pitch 1.26, radius 0.5, 7 groups), {n:.0e} histories"}
+    try:
+        for alg in ("event", "history"):
+            out = m.mcdc_run(h, n, 80, algorithm=alg, outputs=("mean",))
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for s in range(steps):
+                out = m.mcdc_run(h, n, 81 + s, algorithm=alg, outputs=("mean",))
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / steps
+            res[f"{alg}_histories_per_s"] = n / dt
+            res[f"{alg}_ms"] = dt * 1e3
+            log(f"quadrics: sphere lattice {alg} form {dt * 1e3:.2f} ms")
+        res["events_per_history"] = float(sum(out["events"])) / n
+    finally:
+        h.close()
+    cell = w.pin_cell_eigen_cylinder()
+    cell["pins"] = None
+    c, r = 0.63, 0.54
+    cell["quadrics"] = {"coef": np.array([1.0, 1.0, 0.0, 0.0, 0.0, 0.0, -2.0 * c, -2.0 * c, 0.0,
+                                          2.0 * c * c - r * r]).reshape(1, 1, 1, 10),
+                        "material": np.zeros((1, 1, 1), dtype=np.int32)}
+    h = m.mcdc_problem_create(cell)
+    try:
+        m.mcdc_run_eigenvalue(h, 100000, 2, 2, 90)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = m.mcdc_run_eigenvalue(h, 100000, 50, 100, 91)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+    finally:
+        h.close()
+    res["eigen_quadric_pin_cell"] = {"seconds": dt, "histories_per_s": 1.5e7 / dt, "k_mean": out["k_mean"],
+                                     "k_std": out["k_std"]}
+    log(f"quadrics: eigenvalue pin cell (cylinder as a quadric) {dt:.3f} s, "
+        f"k = {out['k_mean']:.5f} +- {out['k_std']:.5f}")
+    return res
+
+
 def eigen_section(m, w, n_per_cycle, n_inactive, n_active):
     """k-eigenvalue power iteration on the box pin cell (7 groups, fuel in
     moderator, reflected), with the cycle counts of Section 3's pin-cell
@@ -738,6 +788,7 @@ def main():
     ap.add_argument("--no-fission", action="store_true")
     ap.add_argument("--no-eigen", action="store_true")
     ap.add_argument("--no-pins", action="store_true")
+    ap.add_argument("--no-quadrics", action="store_true")
     ap.add_argument("--no-pc", action="store_true")
     ap.add_argument("--no-lattice", action="store_true")
     ap.add_argument("--no-sort", action="store_true")
@@ -865,6 +916,8 @@ def main():
         extra["eigenvalue"] = eigen_section(m, w, int(args.eigen_per_cycle), 50, 100)
     if not args.no_pins:
         extra["pins"] = pins_section(m, w, int(args.histories), args.steps)
+    if not args.no_quadrics:
+        extra["quadrics"] = quadrics_section(m, w, int(args.histories), args.steps)
     if not args.no_pc:
         extra["population_control"] = population_control_section(m, w, int(args.histories), args.steps,
                                                                  cpu=not args.no_cpu_baseline)

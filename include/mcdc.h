@@ -352,10 +352,12 @@ typedef struct {
  *                 count launches instead of census steps.
  *  pc_method      with pc_target: MCDC_PC_SPLIT (0, the default) for the
  *                 splitting-roulette above, or MCDC_PC_COMB (1): combing.
- *                 At each edge the same particles as above are put in one
- *                 order that depends on nothing but the particles
- *                 (ascending history index, then ascending stream state),
- *                 the comb's M = pc_target teeth sit at (u + j) W / M,
+ *                 At each edge the same particles as above are taken in
+ *                 the run's list order, which depends on nothing but the
+ *                 particles' history: it starts with the births in history
+ *                 order, a census step keeps every survivor in its place,
+ *                 and a control replaces every particle in its place by its
+ *                 copies (copy 0 first).  The comb's M = pc_target teeth sit at (u + j) W / M,
  *                 j = 0 .. M-1, with one draw u per edge from the stream
  *                 child_stream(seed, 2^62 + k) of edge T_k, and a particle
  *                 whose stretch [P, P + q) of the cumulative fixed-point
@@ -365,9 +367,12 @@ typedef struct {
  *                 particles go on at every edge.  The teeth below a point
  *                 x are ceil((X / W) M - u) with X, W the fixed-point sums
  *                 as doubles (hi + (lo >> 32) 2^-32 + (lo mod 2^32) 2^-64),
- *                 clipped to [0, M].  The order is a radix sort over the
- *                 next bank; the census steps then launch one kernel at a
- *                 time (no captured graphs).
+ *                 clipped to [0, M].  The banks keep the list order (the
+ *                 step writes each survivor back to its own slot), so the
+ *                 comb is an in-order scan of the fixed-point weights, with
+ *                 no sort.  Combing runs the one-kernel step: with the
+ *                 two-kernel step or a queue sort it is refused
+ *                 (MCDC_E_UNSUPPORTED).
  */
 #define MCDC_PC_SPLIT 0
 #define MCDC_PC_COMB 1

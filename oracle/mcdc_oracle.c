@@ -115,10 +115,14 @@
  *       optional implicit capture only (no windows, fission or detector).
  *   R28 Population control by combing (optional, the other census method
  *       Section 2's population control names): the same particles as R16
- *       at each edge T_k, put in one order that depends on nothing but the
- *       particles -- ascending history index, then ascending stream state
- *       (two particles agreeing in both are the same particle in every
- *       respect the control reads, so their order does not matter).  With
+ *       at each edge T_k, taken in the run's list order, which depends on
+ *       nothing but the particles' history: the list starts with the
+ *       histories' births in history order; a census step keeps each
+ *       survivor in its place (the dead drop out, particles of later bins
+ *       wait in theirs); a control replaces each particle in its place by
+ *       its copies, copy 0 first (an uncontrolled particle by itself).  (A
+ *       code that tracks one history after the other and banks census
+ *       crossers as they arrive keeps exactly this order.)  With
  *       q_r their R16 fixed-point weights, P_r the exact sum of the q before
  *       r, W the total and D(.) R16's conversion to a double, one draw u of
  *       the edge's own stream child_stream(seed, 2^62 + k) sets the teeth
@@ -1393,15 +1397,6 @@ int oracle_comb(const double *w, int64_t n, uint64_t M, double u, uint64_t *out)
     return 0;
 }
 
-static const pc_entry *pc_sort_base;
-static int pc_order(const void *a, const void *b)
-{
-    const pc_entry *x = pc_sort_base + *(const size_t *)a, *y = pc_sort_base + *(const size_t *)b;
-    if (x->i != y->i) return x->i < y->i ? -1 : 1;
-    if (x->pt.s != y->pt.s) return x->pt.s < y->pt.s ? -1 : 1;
-    return 0;
-}
-
 /* R16 / R28: an N-history run with population control to `target`
  * particles at every census edge (method 0: splitting-roulette, R16; 1:
  * combing, R28).  Outputs as oracle_run (totals: roulette terminations
@@ -1473,8 +1468,8 @@ int oracle_run_pc(const oracle_problem *p, uint64_t N, uint64_t seed, uint64_t t
         cur.n = 0;
         const double W = q64_value(hi, lo);
         const double wt = W / (double)target;
-        /* R28: the comb's copies of each controlled particle, in the
-           particles' own order */
+        /* R28: the comb's copies of each controlled particle, in list
+           order (nxt holds the particles in it) */
         uint64_t *ncomb = NULL;
         if (method == 1 && (hi != 0 || lo != 0)) {
             size_t nc = 0;
@@ -1487,8 +1482,6 @@ int oracle_run_pc(const oracle_problem *p, uint64_t N, uint64_t seed, uint64_t t
             }
             for (size_t r = 0; r < nxt.n; r++)
                 if (nxt.e[r].pt.k == k + 1) ord[nc++] = r;
-            pc_sort_base = nxt.e;
-            qsort(ord, nc, sizeof(size_t), pc_order);
             uint64_t su = oracle_child_stream(s0, (1ULL << 62) + (uint64_t)(k + 1));
             const double u = rn(&su);
             uint64_t ph = 0, pl = 0;

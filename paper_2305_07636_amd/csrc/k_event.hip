@@ -40,7 +40,6 @@
 #include <type_traits>
 #include <vector>
 
-#include <hipcub/hipcub.hpp>
 
 #include "k_common.hpp"
 
@@ -104,7 +103,13 @@ struct Ctl {
     unsigned long long *pc_cnt;  // [G] population control: copies made from each segment
     unsigned int G, L;      // segments (= workgroups), slots per segment
     unsigned int Lh;        // histories per segment (L, or fewer with population control)
+    unsigned int ordered;   // 1: the banks keep the run's list order (births in history
+                            // order, a census step keeps every particle in its slot)
 };
+
+// gk word of a bank slot whose particle ended in the census step (banks in
+// list order keep their slots; a control skips these)
+constexpr uint32_t kTombGk = 0xFFFFFFFFu;
 
 __device__ __forceinline__ uint32_t pack_gk(int g, int b, int k, int inpin) {
     return (uint32_t)g | ((uint32_t)b << 5) | ((uint32_t)k << 15) | ((uint32_t)inpin << 31);
@@ -126,6 +131,99 @@ __device__ __forceinline__ uint32_t block_append(bool pred, unsigned int *cnt) {
         base = __builtin_amdgcn_readlane(base, leader);
     }
     return base + prefix;
+}
+
+// 128-bit fixed-point weight sums with 64 fractional bits: a weight w is
+// truncated to a multiple of 2^-64 and added to the accumulator (hi, lo).
+// floor(w) is exact in binary64 and so is the fraction w - floor(w); the
+// fraction times 2^64 (a power-of-two scaling, below 2^64) truncated to an
+// integer is the low word.  False if w is 2^32 or more, negative or not a
+// number.
+__device__ __forceinline__ bool fixed_add(unsigned long long &hi, unsigned long long &lo, double w) {
+    if (!(w >= 0.0) || !(w < 4294967296.0)) return false;
+    const double whole = floor(w);
+    const double frac = w - whole;
+    const unsigned long long fbits = __double2ull_rz(frac * 18446744073709551616.0);
+    unsigned __int128 acc = ((unsigned __int128)hi << 64) | lo;
+    acc += ((unsigned __int128)(unsigned long long)whole << 64) + fbits;
+    hi = (unsigned long long)(acc >> 64);
+    lo = (unsigned long long)acc;
+    return true;
+}
+__device__ __forceinline__ void fixed_merge(unsigned long long &hi, unsigned long long &lo, unsigned long long h2,
+                                            unsigned long long l2) {
+    unsigned __int128 acc = ((unsigned __int128)hi << 64) | lo;
+    acc += ((unsigned __int128)h2 << 64) | l2;
+    hi = (unsigned long long)(acc >> 64);
+    lo = (unsigned long long)acc;
+}
+
+// Exclusive prefix of v over the workgroup in thread order, and the
+// workgroup total (every thread calls it; wtot: LDS [BS / 64]).
+template <int BS>
+__device__ __forceinline__ unsigned long long block_exclusive(unsigned long long v, unsigned long long *wtot,
+                                                              unsigned long long &total) {
+    const int lane = (int)__lane_id(), w = (int)(threadIdx.x >> 6);
+    unsigned long long x = v;
+    for (int d = 1; d < 64; d <<= 1) {
+        const unsigned long long t = __shfl_up(x, d);
+        if (lane >= d) x += t;
+    }
+    if (lane == 63) wtot[w] = x;
+    __syncthreads();
+    unsigned long long before = 0ull, tot = 0ull;
+    for (int j = 0; j < BS / 64; ++j) {
+        const unsigned long long t = wtot[j];
+        if (j < w) before += t;
+        tot += t;
+    }
+    __syncthreads();
+    total = tot;
+    return before + x - v;
+}
+
+// The same for 128-bit fixed-point sums (hi, lo); wtot: LDS [BS / 64][2].
+template <int BS>
+__device__ __forceinline__ void block_exclusive_u128(unsigned long long hi, unsigned long long lo,
+                                                     unsigned long long (*wtot)[2], unsigned long long &ehi,
+                                                     unsigned long long &elo, unsigned long long &thi,
+                                                     unsigned long long &tlo) {
+    const int lane = (int)__lane_id(), w = (int)(threadIdx.x >> 6);
+    unsigned long long xh = hi, xl = lo;
+    for (int d = 1; d < 64; d <<= 1) {
+        const unsigned long long th = __shfl_up(xh, d), tl = __shfl_up(xl, d);
+        if (lane >= d) fixed_merge(xh, xl, th, tl);
+    }
+    if (lane == 63) {
+        wtot[w][0] = xh;
+        wtot[w][1] = xl;
+    }
+    __syncthreads();
+    unsigned long long bh = 0ull, bl = 0ull, sh = 0ull, sl = 0ull;
+    for (int j = 0; j < BS / 64; ++j) {
+        if (j < w) fixed_merge(bh, bl, wtot[j][0], wtot[j][1]);
+        fixed_merge(sh, sl, wtot[j][0], wtot[j][1]);
+    }
+    __syncthreads();
+    // exclusive = before + inclusive - own (exact modulo 2^128)
+    unsigned __int128 e = (((unsigned __int128)bh << 64) | bl) + (((unsigned __int128)xh << 64) | xl) -
+                          (((unsigned __int128)hi << 64) | lo);
+    ehi = (unsigned long long)(e >> 64);
+    elo = (unsigned long long)e;
+    thi = sh;
+    tlo = sl;
+}
+
+// Lanes with pred get consecutive offsets of the workgroup-local counter
+// cnt (LDS) in thread order (every thread calls it; wtot as above).
+template <int BS>
+__device__ __forceinline__ uint32_t block_append_ordered(bool pred, unsigned int *cnt, unsigned long long *wtot) {
+    unsigned long long tot;
+    const unsigned long long ex = block_exclusive<BS>(pred ? 1ull : 0ull, wtot, tot);
+    const uint32_t base = *cnt;
+    __syncthreads();
+    if (threadIdx.x == 0) *cnt = base + (uint32_t)tot;
+    return base + (uint32_t)ex;
 }
 
 // Event / termination counters and profile tallies (particles processed,
@@ -449,6 +547,7 @@ __global__ void __launch_bounds__(BS) k_source(DevProblem P0, RunArgs R0, Bank b
                                                    const BatchItem *__restrict__ items,
                                                    const SegInfo *__restrict__ segs) {
     __shared__ unsigned long long red[kCounters + 2];
+    __shared__ unsigned long long wtot[BS / 64];
     Counters cnt;
     __shared__ unsigned int cN;
     const SegInfo si = BAT ? segs[blockIdx.x] : SegInfo{0, 0u, 0u, 0u};
@@ -486,7 +585,9 @@ __global__ void __launch_bounds__(BS) k_source(DevProblem P0, RunArgs R0, Bank b
                 hist_term(R, i, kTime);
             }
         }
-        const uint32_t off = block_append(valid && alive, &cN);
+        // (banks in list order: the births in history order)
+        const uint32_t off = (!BAT && C.ordered) ? block_append_ordered<BS>(valid && alive, &cN, wtot)
+                                                 : block_append(valid && alive, &cN);
         if (valid && alive) store_state<FM, WW>(P, bank, seg * C.L + off, p, pack_gk(p.g, b, p.k, p.inpin), (uint32_t)r);
         if (R.prof) cnt.prof(valid ? 1u : 0u, (valid && alive) ? state_bytes<FM, WW>(P) : 0u);
     }
@@ -623,7 +724,11 @@ __global__ void __launch_bounds__(BS) k_advance(DevProblem P0, RunArgs R0, Bank 
 // (STEP, ns > 1: census steps step .. step + ns - 1 in one launch; a
 // particle that reaches the edge of one goes on into the next in
 // registers.)
-template <int FM, bool WW, bool LT, bool BAT, int CLS = MCDC_PROF_EVENTS, bool STEP = false, int BS = kBlock>
+// (ORD: banks in list order -- the weighted one-kernel step of a combed
+// run writes every particle that goes on to its own slot of the next bank
+// and a tombstone word to the slot of one that ends)
+template <int FM, bool WW, bool LT, bool BAT, int CLS = MCDC_PROF_EVENTS, bool STEP = false, int BS = kBlock,
+          bool ORD = false>
 __global__ void __launch_bounds__(BS) k_event(DevProblem P0, RunArgs R0, Bank ev, Bank next, Ctl C, int par,
                                                   int gn0, SplitBank SB, LdsTables tabs0,
                                                   const BatchItem *__restrict__ items,
@@ -659,10 +764,11 @@ __global__ void __launch_bounds__(BS) k_event(DevProblem P0, RunArgs R0, Bank ev
     __syncthreads();
 
     Particle p;
-    uint32_t gk = 0, hid = 0;
+    uint32_t gk = 0, hid = 0, src = 0;
     int cell = 0, b = 0, queued = kCensus, mask = 0, since = 0;
     uint64_t i = 0;
     bool busy = false, exhausted = false, waiting = false;
+    constexpr bool in_place = ORD && WW && STEP && !BAT;
     for (;;) {
         // idle lanes take the next items of the work list, once enough of
         // the wave is idle (or all of it)
@@ -672,8 +778,9 @@ __global__ void __launch_bounds__(BS) k_event(DevProblem P0, RunArgs R0, Bank ev
             const uint32_t w = block_append(need, &cW);
             if (need && w < n) {
                 uint32_t hidw;
-                load_state<FM, WW>(P, bsrc, (STEP || sorted || w < n_s) ? seg0 + w : seg_end - (w - n_s), p, gk,
-                                   hidw);
+                const uint32_t at = (STEP || sorted || w < n_s) ? seg0 + w : seg_end - (w - n_s);
+                if constexpr (in_place) src = at;
+                load_state<FM, WW>(P, bsrc, at, p, gk, hidw);
                 hid = hidw & kHidMask;
                 mask = STEP ? 0 : (int)(hidw >> 29);
                 queued = STEP ? kCensus : ((w < n_s) ? kSurface : kCollision);
@@ -689,6 +796,7 @@ __global__ void __launch_bounds__(BS) k_event(DevProblem P0, RunArgs R0, Bank ev
         }
         const int n_busy = __popcll(__ballot(busy));
         if (n_busy == 0) break;
+        const bool had = in_place && busy;
         // collisions wait until a share of the busy lanes has one (or no
         // lane has anything else to do), so that the wave runs the costly
         // collision code for many lanes at once
@@ -794,14 +902,23 @@ __global__ void __launch_bounds__(BS) k_event(DevProblem P0, RunArgs R0, Bank ev
                 }
             }
         }
-        const uint32_t slot = block_append(to_next, &cN);
-        if (to_next) {
-            store_state<FM, WW>(P, next, seg0 + slot, p, with_gk(gk, p), hid);
-            if (R.prof) cnt.prof(0u, state_bytes<FM, WW>(P));
+        if constexpr (in_place) {
+            if (to_next) {
+                store_state<FM, WW>(P, next, src, p, with_gk(gk, p), hid);
+                if (R.prof) cnt.prof(0u, state_bytes<FM, WW>(P));
+            } else if (had && !busy) {
+                fld<uint32_t>(next, next.ogk, tile_off4(next, src)) = kTombGk;
+            }
+        } else {
+            const uint32_t slot = block_append(to_next, &cN);
+            if (to_next) {
+                store_state<FM, WW>(P, next, seg0 + slot, p, with_gk(gk, p), hid);
+                if (R.prof) cnt.prof(0u, state_bytes<FM, WW>(P));
+            }
         }
     }
     flush_slice<BS>(P, R, sc, step);
-    if (threadIdx.x == 0) C.n_bank[(par ^ 1) * C.G + seg] = cN;
+    if (threadIdx.x == 0) C.n_bank[(par ^ 1) * C.G + seg] = in_place ? n : cN;
     cnt.flush(R, CLS, red);
 }
 
@@ -1150,31 +1267,6 @@ __global__ void __launch_bounds__(BS) k_sort_events(DevProblem P0, RunArgs R0, B
 // stream after the draw, copy j >= 1 takes child_stream(s, j)), a particle
 // of a later time bin unchanged.
 
-// 128-bit fixed-point weight sums with 64 fractional bits: a weight w is
-// truncated to a multiple of 2^-64 and added to the accumulator (hi, lo).
-// floor(w) is exact in binary64 and so is the fraction w - floor(w); the
-// fraction times 2^64 (a power-of-two scaling, below 2^64) truncated to an
-// integer is the low word.  False if w is 2^32 or more, negative or not a
-// number.
-__device__ __forceinline__ bool fixed_add(unsigned long long &hi, unsigned long long &lo, double w) {
-    if (!(w >= 0.0) || !(w < 4294967296.0)) return false;
-    const double whole = floor(w);
-    const double frac = w - whole;
-    const unsigned long long fbits = __double2ull_rz(frac * 18446744073709551616.0);
-    unsigned __int128 acc = ((unsigned __int128)hi << 64) | lo;
-    acc += ((unsigned __int128)(unsigned long long)whole << 64) + fbits;
-    hi = (unsigned long long)(acc >> 64);
-    lo = (unsigned long long)acc;
-    return true;
-}
-__device__ __forceinline__ void fixed_merge(unsigned long long &hi, unsigned long long &lo, unsigned long long h2,
-                                            unsigned long long l2) {
-    unsigned __int128 acc = ((unsigned __int128)hi << 64) | lo;
-    acc += ((unsigned __int128)h2 << 64) | l2;
-    hi = (unsigned long long)(acc >> 64);
-    lo = (unsigned long long)acc;
-}
-
 __device__ __forceinline__ uint32_t clock_of(uint32_t gk) { return (gk >> 15) & 0xFFFFu; }
 
 // overflow flag values of population control (1: particle or split bank)
@@ -1307,7 +1399,7 @@ __device__ __forceinline__ uint64_t pc_copies(Particle &p, int edge, bool on, do
 
 // Pass 2: copies per segment (the draws are repeated, not kept, by pass 3).
 // (it reads only the weight, stream and clock of each particle)
-// (comb: the copies of each controlled particle by slot, from k_comb_count)
+// (comb: the copies of each controlled particle by slot, from k_comb_teeth)
 __global__ void __launch_bounds__(kBlock) k_pc_count(RunArgs R, Bank next, Ctl C, int par, uint64_t target,
                                                      const uint32_t *__restrict__ comb) {
     __shared__ unsigned long long part[kBlock / 64];
@@ -1324,7 +1416,9 @@ __global__ void __launch_bounds__(kBlock) k_pc_count(RunArgs R, Bank next, Ctl C
         const uint32_t slot = seg0 + r;
         items += 1ull;
         Particle p;
-        p.k = (int)clock_of(fld<uint32_t>(next, next.ogk, tile_off4(next, slot)));
+        const uint32_t gk = fld<uint32_t>(next, next.ogk, tile_off4(next, slot));
+        if (gk == kTombGk) continue;   // ended in the census step
+        p.k = (int)clock_of(gk);
         if (comb) {
             tot += (on && p.k == edge) ? (unsigned long long)comb[slot] : 1ull;
             continue;
@@ -1349,12 +1443,15 @@ __global__ void __launch_bounds__(kBlock) k_pc_count(RunArgs R, Bank next, Ctl C
 // to slot q mod Lq of segment q / Lq, Lq = ceil(T / G) for T copies in all:
 // the controlled population is spread evenly over the segments again (a
 // segment's share would otherwise drift from step to step).
-// (comb: the copies by slot from k_comb_count, no draw: copy 0 keeps the
+// (comb: the copies by slot from k_comb_teeth, no draw: copy 0 keeps the
 // stream as it is)
-template <int FM>
+// (banks in list order: the copies take their positions in slot order,
+// each particle's copies together, copy 0 first, so the list order holds)
+template <int FM, bool ORD = false>
 __global__ void __launch_bounds__(kBlock) k_pc_apply(DevProblem P, RunArgs R, Bank next, Bank cur, Ctl C, int par,
                                                      uint64_t target, const uint32_t *__restrict__ comb) {
     __shared__ unsigned long long red[kCounters + 2];
+    __shared__ unsigned long long wtot[kBlock / 64];
     __shared__ unsigned int cN;
     Counters cnt;
     cnt.init(red);
@@ -1376,12 +1473,14 @@ __global__ void __launch_bounds__(kBlock) k_pc_apply(DevProblem P, RunArgs R, Ba
     const int edge = *C.step + 1;
     const uint64_t first = *C.first;
     const uint32_t seg0 = seg * C.L;
+    unsigned long long run = 0ull;   // copies placed so far (banks in list order)
     for (uint32_t b0 = 0; b0 < n; b0 += kBlock) {
         const uint32_t r = b0 + threadIdx.x;
-        const bool valid = r < n;
+        bool valid = r < n;
         Particle p;
         uint32_t gk = 0u, hidw = 0u;
         uint64_t copies = 0ull, sf = 0ull;
+        if (ORD && valid && fld<uint32_t>(next, next.ogk, tile_off4(next, seg0 + r)) == kTombGk) valid = false;
         if (valid) {
             load_state<FM, true>(P, next, seg0 + r, p, gk, hidw);
             const bool ctl = on && p.k == edge;
@@ -1400,14 +1499,12 @@ __global__ void __launch_bounds__(kBlock) k_pc_apply(DevProblem P, RunArgs R, Ba
             }
             sf = p.s;
         }
-        // one copy per lane and round
-        uint64_t j = 0ull;
-        for (;;) {
-            const bool put = valid && j < copies;
-            if (!__any(put)) break;
-            const uint32_t off = block_append(put, &cN);
-            if (put) {
-                const unsigned long long q = base + off;
+        if constexpr (ORD) {
+            // the lane's copies at its exclusive prefix of the round's copies
+            unsigned long long tot;
+            const unsigned long long ex = block_exclusive<kBlock>(valid ? copies : 0ull, wtot, tot);
+            for (uint64_t j = 0ull; valid && j < copies; ++j) {
+                const unsigned long long q = base + run + ex + j;
                 const unsigned long long os = q / Lq, oslot = q - os * Lq;
                 if (os < C.G && oslot < C.L) {
                     p.s = (j > 0ull) ? child_stream(sf, j) : sf;
@@ -1415,7 +1512,26 @@ __global__ void __launch_bounds__(kBlock) k_pc_apply(DevProblem P, RunArgs R, Ba
                 } else {
                     *R.overflow = kOvfSegment;
                 }
-                ++j;
+            }
+            run += tot;
+        } else {
+            // one copy per lane and round
+            uint64_t j = 0ull;
+            for (;;) {
+                const bool put = valid && j < copies;
+                if (!__any(put)) break;
+                const uint32_t off = block_append(put, &cN);
+                if (put) {
+                    const unsigned long long q = base + off;
+                    const unsigned long long os = q / Lq, oslot = q - os * Lq;
+                    if (os < C.G && oslot < C.L) {
+                        p.s = (j > 0ull) ? child_stream(sf, j) : sf;
+                        store_state<FM, true>(P, cur, (uint32_t)(os * C.L + oslot), p, gk, hidw);
+                    } else {
+                        *R.overflow = kOvfSegment;
+                    }
+                    ++j;
+                }
             }
         }
         if (R.prof) cnt.prof(valid ? 1u : 0u, valid ? (unsigned int)((copies + 1ull) * state_bytes<FM, true>(P)) : 0u);
@@ -1426,90 +1542,76 @@ __global__ void __launch_bounds__(kBlock) k_pc_apply(DevProblem P, RunArgs R, Ba
 // ---------------------------------------------------------------------------
 // population control by combing
 // ---------------------------------------------------------------------------
-// (The comb needs the controlled particles in one order that does not
-// depend on the schedule: ascending history index, then ascending stream
-// state.  Over every slot of the next bank, k_comb_keys writes the stream
-// as the first key (all ones for a slot that is empty or not controlled,
-// so those sort last) and the slot as the value; a radix sort by that key,
-// then a stable one by the history index (k_comb_hid), leaves the slots in
-// that order.  k_comb_weights writes their 128-bit fixed-point weights, an
-// exclusive scan gives each particle's stretch [P, P + q) of the
-// cumulative weight, and k_comb_count counts the teeth in it.)
-struct U128 {
-    unsigned long long hi, lo;
-};
-struct AddU128 {
-    __host__ __device__ U128 operator()(const U128 &a, const U128 &b) const {
-        const unsigned long long lo = a.lo + b.lo;
-        return U128{a.hi + b.hi + (lo < a.lo ? 1ull : 0ull), lo};
-    }
-};
+// (The comb takes the controlled particles in the run's list order: the
+// banks keep it -- births in history order, survivors in their slots
+// through a census step, copies in their parent's place -- so the order is
+// slot order, segment after segment.  One workgroup per segment scans the
+// 128-bit fixed-point weights of its controlled particles in slot order,
+// from the exact sum of the earlier segments, and counts the teeth in each
+// particle's stretch [P, P + q) of the cumulative weight.)
 
-// a slot of the next bank: controlled at this edge?
-__device__ __forceinline__ bool comb_member(const Bank &next, const Ctl &C, int par, uint32_t t, uint32_t edge) {
-    const uint32_t seg = t / C.L, r = t - seg * C.L;
-    if (seg >= C.G || r >= C.n_bank[(par ^ 1) * C.G + seg]) return false;
-    return clock_of(fld<uint32_t>(next, next.ogk, tile_off4(next, t))) == edge;
-}
-
-__global__ void __launch_bounds__(kBlock) k_comb_keys(Bank next, Ctl C, int par, uint32_t slots,
-                                                      unsigned long long *key, uint32_t *val) {
-    const uint32_t edge = (uint32_t)(*C.step + 1);
-    for (uint32_t t = blockIdx.x * kBlock + threadIdx.x; t < slots; t += gridDim.x * kBlock) {
-        key[t] = comb_member(next, C, par, t, edge) ? fld<uint64_t>(next, next.os, tile_off8(next, t)) : ~0ull;
-        val[t] = t;
-    }
-}
-
-__global__ void __launch_bounds__(kBlock) k_comb_hid(Bank next, Ctl C, int par, uint32_t slots,
-                                                     const uint32_t *__restrict__ val, uint32_t *key) {
-    const uint32_t edge = (uint32_t)(*C.step + 1);
-    for (uint32_t r = blockIdx.x * kBlock + threadIdx.x; r < slots; r += gridDim.x * kBlock) {
-        const uint32_t t = val[r];
-        key[r] = comb_member(next, C, par, t, edge) ? (fld<uint32_t>(next, next.ohid, tile_off4(next, t)) & kHidMask)
-                                                    : 0xFFFFFFFFu;
-    }
-}
-
-// the fixed-point weight of a controlled particle (its truncation to a
-// multiple of 2^-64), 0 for any other slot
-__global__ void __launch_bounds__(kBlock) k_comb_weights(Bank next, Ctl C, int par, uint32_t slots,
-                                                         const uint32_t *__restrict__ val, U128 *q) {
-    const uint32_t edge = (uint32_t)(*C.step + 1);
-    for (uint32_t r = blockIdx.x * kBlock + threadIdx.x; r < slots; r += gridDim.x * kBlock) {
-        const uint32_t t = val[r];
-        unsigned long long hi = 0ull, lo = 0ull;
-        if (comb_member(next, C, par, t, edge)) fixed_add(hi, lo, fld<double>(next, next.ow, tile_off8(next, t)));
-        q[r] = U128{hi, lo};
-    }
-}
-
-// teeth of the comb below the fixed-point point x
-__device__ __forceinline__ uint32_t comb_teeth(const U128 &x, double W, uint64_t M, double u) {
-    const double dx = (double)x.hi + ((double)(x.lo >> 32) * 0x1p-32 + (double)(x.lo & 0xFFFFFFFFull) * 0x1p-64);
+// teeth of the comb below the fixed-point point (hi, lo)
+__device__ __forceinline__ uint32_t comb_teeth(unsigned long long hi, unsigned long long lo, double W, uint64_t M,
+                                               double u) {
+    const double dx = (double)hi + ((double)(lo >> 32) * 0x1p-32 + (double)(lo & 0xFFFFFFFFull) * 0x1p-64);
     const double c = ceil((dx / W) * (double)M - u);
     if (!(c > 0.0)) return 0u;
     if (c >= (double)M) return (uint32_t)M;
     return (uint32_t)c;
 }
 
-__global__ void __launch_bounds__(kBlock) k_comb_count(Ctl C, uint32_t slots, uint64_t target,
-                                                       const uint32_t *__restrict__ val, const U128 *__restrict__ q,
-                                                       const U128 *__restrict__ pre, uint32_t *copies) {
-    const PcSums S = pc_sums(C, target, 0u, false);
+__global__ void __launch_bounds__(kBlock) k_comb_teeth(RunArgs R, Bank next, Ctl C, int par, uint64_t target,
+                                                       uint32_t *copies) {
+    __shared__ unsigned long long wtot[kBlock / 64][2];
+    __shared__ unsigned long long part[kBlock / 64][2];
+    const unsigned int seg = blockIdx.x;
+    const PcSums S = pc_sums(C, target, seg, false);
     if (!S.on) return;
+    // the exact weight of the segments before this one
+    unsigned long long bh = 0ull, bl = 0ull;
+    for (unsigned int j = threadIdx.x; j < seg; j += kBlock) fixed_merge(bh, bl, C.pc_w[2 * j], C.pc_w[2 * j + 1]);
+    for (int o = 32; o > 0; o >>= 1) {
+        const unsigned long long h2 = __shfl_xor(bh, o), l2 = __shfl_xor(bl, o);
+        fixed_merge(bh, bl, h2, l2);
+    }
+    if (__lane_id() == 0) {
+        part[threadIdx.x >> 6][0] = bh;
+        part[threadIdx.x >> 6][1] = bl;
+    }
+    __syncthreads();
+    bh = bl = 0ull;
+    for (int w = 0; w < kBlock / 64; ++w) fixed_merge(bh, bl, part[w][0], part[w][1]);
     const uint32_t edge = (uint32_t)(*C.step + 1);
     uint64_t su = child_stream(*C.seed, (1ull << 62) + edge);
     const double u = rn(su);
-    for (uint32_t r = blockIdx.x * kBlock + threadIdx.x; r < slots; r += gridDim.x * kBlock) {
-        const U128 a = pre[r], w = q[r];
-        if ((w.hi | w.lo) == 0ull) {
-            copies[val[r]] = 0u;   // not controlled (or a weight below 2^-64)
-            continue;
+    const unsigned int n = C.n_bank[(par ^ 1) * C.G + seg];
+    const uint32_t seg0 = seg * C.L;
+    unsigned long long items = 0ull, bytes = 0ull;
+    for (uint32_t b0 = 0; b0 < n; b0 += kBlock) {
+        const uint32_t r = b0 + threadIdx.x;
+        unsigned long long qh = 0ull, ql = 0ull;
+        bool member = false;
+        if (r < n) {
+            items += 1ull;
+            bytes += 8ull;   // clock word; weight and copy count of a member
+            member = clock_of(fld<uint32_t>(next, next.ogk, tile_off4(next, seg0 + r))) == edge;
+            if (member) {
+                bytes += 12ull;
+                fixed_add(qh, ql, fld<double>(next, next.ow, tile_off8(next, seg0 + r)));
+            }
         }
-        const U128 b = AddU128()(a, w);
-        copies[val[r]] = comb_teeth(b, S.W, target, u) - comb_teeth(a, S.W, target, u);
+        unsigned long long eh, el, th, tl;
+        block_exclusive_u128<kBlock>(qh, ql, wtot, eh, el, th, tl);
+        if (member) {
+            unsigned long long ah = bh, al = bl;
+            fixed_merge(ah, al, eh, el);
+            unsigned long long zh = ah, zl = al;
+            fixed_merge(zh, zl, qh, ql);
+            copies[seg0 + r] = comb_teeth(zh, zl, S.W, target, u) - comb_teeth(ah, al, S.W, target, u);
+        }
+        fixed_merge(bh, bl, th, tl);
     }
+    pc_prof(R, items, bytes);
 }
 
 // ---------------------------------------------------------------------------
@@ -1748,50 +1850,21 @@ int run_event(mcdc_problem *pb, const RunArgs &R0, uint64_t first, uint64_t coun
     SplitBank SB[2]{};
     if (WW && (rc = split_prepare(pb, C, SB))) return rc;
 
-    // population control by combing: per slot of a bank, the sort keys and
-    // values (two buffers each), the fixed-point weights and their exclusive
-    // prefix, the copies; then the library sort's and scan's work space
+    // population control by combing: the banks keep the run's list order
+    // (births in history order, survivors in their slots, copies in their
+    // parent's place), and the comb writes each controlled particle's teeth
+    // per slot; the one-kernel step only
     const bool comb = pc && opt.pc_method == MCDC_PC_COMB;
-    struct CombWork {
-        unsigned long long *k1[2];
-        uint32_t *k2[2], *v[2], *copies;
-        U128 *q, *pre;
-        void *tmp;
-        size_t tmp_bytes;
-    } cw{};
-    const uint32_t cslots = (uint32_t)slots;
+    uint32_t *comb_copies = nullptr;
     if (comb) {
-        size_t b1 = 0, b2 = 0, b3 = 0;
-        hipError_t e = hipcub::DeviceRadixSort::SortPairs(nullptr, b1, (unsigned long long *)nullptr,
-                                                          (unsigned long long *)nullptr, (uint32_t *)nullptr,
-                                                          (uint32_t *)nullptr, (int)cslots, 0, 64, st);
-        if (e == hipSuccess)
-            e = hipcub::DeviceRadixSort::SortPairs(nullptr, b2, (uint32_t *)nullptr, (uint32_t *)nullptr,
-                                                   (uint32_t *)nullptr, (uint32_t *)nullptr, (int)cslots, 0, 32, st);
-        if (e == hipSuccess)
-            e = hipcub::DeviceScan::ExclusiveScan(nullptr, b3, (U128 *)nullptr, (U128 *)nullptr, AddU128(),
-                                                  U128{0ull, 0ull}, (int)cslots, st);
-        if (e != hipSuccess) return hip_fail(e, "comb work size");
-        cw.tmp_bytes = b1 > b2 ? (b1 > b3 ? b1 : b3) : (b2 > b3 ? b2 : b3);
-        const size_t per = pad256((size_t)cslots * 8);
-        const size_t per4 = pad256((size_t)cslots * 4);
-        const size_t per16 = pad256((size_t)cslots * 16);
-        if ((rc = ensure(pb->comb, 2 * per + 5 * per4 + 2 * per16 + pad256(cw.tmp_bytes)))) return rc;
-        char *m = (char *)pb->comb.p;
-        cw.k1[0] = (unsigned long long *)m;
-        cw.k1[1] = (unsigned long long *)(m + per);
-        m += 2 * per;
-        cw.k2[0] = (uint32_t *)m;
-        cw.k2[1] = (uint32_t *)(m + per4);
-        cw.v[0] = (uint32_t *)(m + 2 * per4);
-        cw.v[1] = (uint32_t *)(m + 3 * per4);
-        cw.copies = (uint32_t *)(m + 4 * per4);
-        m += 5 * per4;
-        cw.q = (U128 *)m;
-        cw.pre = (U128 *)(m + per16);
-        cw.tmp = m + 2 * per16;
+        if (!one_kernel) {
+            set_error("combing runs the one-kernel census step (no two-kernel step or queue sort)");
+            return MCDC_E_UNSUPPORTED;
+        }
+        if ((rc = ensure(pb->comb, pad256((size_t)slots * 4)))) return rc;
+        comb_copies = (uint32_t *)pb->comb.p;
     }
-    hipError_t comb_err = hipSuccess;
+    L.ctl.ordered = comb ? 1u : 0u;
 
     // the step kernels never read the seed or the history count; Rs is the
     // uninstrumented form the graphs capture, Rp the profiled one
@@ -1817,6 +1890,11 @@ int run_event(mcdc_problem *pb, const RunArgs &R0, uint64_t first, uint64_t coun
             if constexpr (FM == 1 && !WW)
                 launch_timed(pr, MCDC_PROF_EVENTS, k_event_staged<LT, BS>, dim3(G), dim3(BS), (uint32_t)shmem, s, P, Ra,
                              cur, nxt, L.ctl, par, gn, tabs);
+        } else if (one_kernel && WW && comb) {
+            if constexpr (WW)
+                launch_timed(pr, MCDC_PROF_EVENTS, k_event<FM, WW, LT, false, MCDC_PROF_EVENTS, true, BS, true>,
+                             dim3(G), dim3(BS), (uint32_t)shmem, s, P, Ra, cur, nxt, L.ctl, par, gn, SB[0], tabs,
+                             (const BatchItem *)nullptr, (const SegInfo *)nullptr, L.srt, 0, ns);
         } else if (one_kernel) {
             launch_timed(pr, MCDC_PROF_EVENTS, k_event<FM, WW, LT, false, MCDC_PROF_EVENTS, true, BS>, dim3(G),
                          dim3(BS), (uint32_t)shmem, s, P, Ra, cur, nxt, L.ctl, par, gn, SB[0], tabs,
@@ -1838,32 +1916,18 @@ int run_event(mcdc_problem *pb, const RunArgs &R0, uint64_t first, uint64_t coun
         if constexpr (WW) {
             if (pc) {
                 launch_timed(pr, MCDC_PROF_CONTROL, k_pc_sum, dim3(G), dim3(kBlock), 0u, s, Ra, nxt, L.ctl, par);
-                if (comb) {
-                    // the controlled particles in (history, stream) order, their
-                    // stretches of the cumulative weight, the teeth in each
-                    hipLaunchKernelGGL(k_comb_keys, dim3(G), dim3(kBlock), 0, s, nxt, L.ctl, par, cslots, cw.k1[0],
-                                       cw.v[0]);
-                    hipError_t e = hipcub::DeviceRadixSort::SortPairs(cw.tmp, cw.tmp_bytes, cw.k1[0], cw.k1[1],
-                                                                      cw.v[0], cw.v[1], (int)cslots, 0, 64, s);
-                    hipLaunchKernelGGL(k_comb_hid, dim3(G), dim3(kBlock), 0, s, nxt, L.ctl, par, cslots, cw.v[1],
-                                       cw.k2[0]);
-                    if (e == hipSuccess)
-                        e = hipcub::DeviceRadixSort::SortPairs(cw.tmp, cw.tmp_bytes, cw.k2[0], cw.k2[1], cw.v[1],
-                                                               cw.v[0], (int)cslots, 0, 32, s);
-                    hipLaunchKernelGGL(k_comb_weights, dim3(G), dim3(kBlock), 0, s, nxt, L.ctl, par, cslots, cw.v[0],
-                                       cw.q);
-                    if (e == hipSuccess)
-                        e = hipcub::DeviceScan::ExclusiveScan(cw.tmp, cw.tmp_bytes, cw.q, cw.pre, AddU128(),
-                                                              U128{0ull, 0ull}, (int)cslots, s);
-                    launch_timed(pr, MCDC_PROF_CONTROL, k_comb_count, dim3(G), dim3(kBlock), 0u, s, L.ctl, cslots, pc,
-                                 (const uint32_t *)cw.v[0], (const U128 *)cw.q, (const U128 *)cw.pre, cw.copies);
-                    if (e != hipSuccess && comb_err == hipSuccess) comb_err = e;
-                }
-                const uint32_t *cc = comb ? cw.copies : nullptr;
+                if (comb)
+                    launch_timed(pr, MCDC_PROF_CONTROL, k_comb_teeth, dim3(G), dim3(kBlock), 0u, s, Ra, nxt, L.ctl,
+                                 par, pc, comb_copies);
+                const uint32_t *cc = comb_copies;
                 launch_timed(pr, MCDC_PROF_CONTROL, k_pc_count, dim3(G), dim3(kBlock), 0u, s, Ra, nxt, L.ctl, par, pc,
                              cc);
-                launch_timed(pr, MCDC_PROF_CONTROL, k_pc_apply<FM>, dim3(G), dim3(kBlock), 0u, s, P, Ra, nxt, cur, L.ctl,
-                             par, pc, cc);
+                if (comb)
+                    launch_timed(pr, MCDC_PROF_CONTROL, k_pc_apply<FM, true>, dim3(G), dim3(kBlock), 0u, s, P, Ra, nxt,
+                                 cur, L.ctl, par, pc, cc);
+                else
+                    launch_timed(pr, MCDC_PROF_CONTROL, k_pc_apply<FM>, dim3(G), dim3(kBlock), 0u, s, P, Ra, nxt, cur,
+                                 L.ctl, par, pc, cc);
             }
         }
         hipLaunchKernelGGL(k_step_end, dim3(1), dim3(1), 0, s, L.ctl, ns);
@@ -1872,7 +1936,7 @@ int run_event(mcdc_problem *pb, const RunArgs &R0, uint64_t first, uint64_t coun
     // replay captured steps unless per-history debug output is requested;
     // profiled steps launch eagerly
     const bool use_graph = !(opt.flags & MCDC_FLAG_EAGER) && !(opt.profile && every == 1) && !R.dbg_counts &&
-                           !R.dbg_scores && NL > 1 && !comb;
+                           !R.dbg_scores && NL > 1;
     StepGraphs *Gr = nullptr;
     // stretch of unsampled launches captured as one graph (none below 2)
     const int span = opt.profile ? every - 1 : NL;
@@ -1893,6 +1957,7 @@ int run_event(mcdc_problem *pb, const RunArgs &R0, uint64_t first, uint64_t coun
         key_add(key, cadence);
         key_add(key, ns);
         key_add(key, pc);
+        key_add(key, comb_copies);
         key_add(key, span);
         key_add(key, n_run);
         if (key != Gr->key) {
@@ -1954,7 +2019,6 @@ int run_event(mcdc_problem *pb, const RunArgs &R0, uint64_t first, uint64_t coun
         }
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return hip_fail(e, "event kernel launch");
-        if (comb_err != hipSuccess) return hip_fail(comb_err, "comb sort or scan");
         if (WW && (rc = split_generations(pb, R, SB, cfirst, st, prof))) return rc;
         if (P.qoi_on && (rc = launch_qoi_reduce(R.qoi_hist, n, R.qoi_sums, st)))
             return hip_fail((hipError_t)rc, "detector reduce");

@@ -96,8 +96,8 @@ def test_population_control_parity(case):
 @pytest.mark.gpu
 @pytest.mark.parametrize("case", list(CASES))
 def test_population_control_by_combing_parity(case):
-    """Combing (reading R28): the controlled particles sorted by history
-    and stream on the GPU, their teeth counted from an exact 128-bit
+    """Combing (reading R28): the controlled particles in the run's list
+    order (the banks keep it), their teeth counted from an exact 128-bit
     prefix of their fixed-point weights; every count and tally against the
     oracle's comb."""
     make, N, f, seed = CASES[case]
@@ -109,22 +109,71 @@ def test_population_control_by_combing_parity(case):
 
 
 @pytest.mark.gpu
-def test_population_control_by_combing_two_kernel_step_and_profile():
+def test_combing_many_copies_per_history():
+    """200 histories combed to 12 000 particles at the first edge (some 60
+    copies of each, written together in their parent's place), and 300
+    multigroup histories to 9000: list order through every later edge."""
+    print("[pc comb] 60 copies per history", flush=True)
+    compare_pc(_void_reflective(), 200, 12000, 75, method="comb")
+    compare_pc(_mg_box(), 300, 9000, 76, method="comb")
+
+
+@pytest.mark.gpu
+def test_combing_graphs_eager_and_profiled_runs_agree():
+    """Combed runs replay their census steps as captured graphs; eager and
+    profiled launches (every control kernel timed) give the same counts,
+    and the oracle's tallies."""
     import paper_2305_07636_amd as m
 
-    print("[pc comb] two-kernel step", flush=True)
-    compare_pc(_slab_pulse(0.5), 20000, 15000, 73, method="comb", two_kernel_step=True)
-    # profiled runs launch the control eagerly too: same results
     prob = _slab_pulse(0.5)
+    print("[pc comb] graphs, eager, profiled", flush=True)
+    g, r = compare_pc(prob, 20000, 15000, 74, method="comb")
     p = m.mcdc_problem_create(prob)
     try:
-        a = m.mcdc_run(p, 20000, 74, pc_target=15000, pc_method="comb")
+        e = m.mcdc_run(p, 20000, 74, pc_target=15000, pc_method="comb", eager=True)
         prof = np.zeros((len(m._binding.PROF_CLASSES), 4))
-        b = m.mcdc_run(p, 20000, 74, pc_target=15000, pc_method="comb", profile=prof)
-        assert np.array_equal(a["events"], b["events"]) and np.array_equal(a["terms"], b["terms"])
-        assert prof[m._binding.PROF_CLASSES.index("control"), 1] > 0
+        f = m.mcdc_run(p, 20000, 74, pc_target=15000, pc_method="comb", profile=prof)
+        # a second graph run of the same handle replays the cached graphs
+        h = m.mcdc_run(p, 20000, 74, pc_target=15000, pc_method="comb")
+        for o in (e, f, h):
+            assert np.array_equal(o["events"], g["events"]) and np.array_equal(o["terms"], g["terms"])
+            assert o["splits"] == g["splits"]
+            close(o["mean"].cpu().numpy(), g["mean"], what="mean")
+        ct = m._binding.PROF_CLASSES.index("control")
+        assert prof[ct, 1] == 4 * 20 and prof[ct, 3] > 0   # sum, teeth, count, apply after each of 20 steps
     finally:
         p.close()
+
+
+@pytest.mark.gpu
+def test_combing_full_size_pulse():
+    """1e7 histories of the 40-mfp pulsed slab (c = 0.9, 100 census steps)
+    combed to 1e7 at every edge: the spatially integrated flux of every
+    time bin matches the closed form v exp(-v Sigma_a t) averaged over the
+    bin, every particle ends once, and the last bin's error is below that
+    of splitting-roulette to the same population."""
+    import paper_2305_07636_amd as m
+
+    N = 10_000_000
+    prob = w.cfg2_slab_pulse(c=0.9)
+    print(f"[pc comb] full-size pulse N={N}", flush=True)
+    p = m.mcdc_problem_create(prob)
+    try:
+        g = m.mcdc_run(p, N, 72, pc_target=N, pc_method="comb")
+        mean = g["mean"].cpu().numpy().reshape(100, -1)
+        var = g["var"].cpu().numpy().reshape(100, -1)
+    finally:
+        p.close()
+    dx = 40.0 / 50
+    integ = mean.sum(axis=1) * dx
+    ivar = var.sum(axis=1) * dx * dx
+    te = np.linspace(0.0, 20.0, 101)
+    sa = 0.1
+    exact = (np.exp(-sa * te[:-1]) - np.exp(-sa * te[1:])) / (sa * np.diff(te))
+    z = (integ - exact) / np.sqrt(ivar)
+    assert np.all(np.abs(z) < 5.0), z[np.abs(z) >= 5.0]
+    assert N + g["splits"] == int(np.sum(g["terms"]))
+    assert int(g["terms"][3]) == 0
 
 
 @pytest.mark.gpu
@@ -151,6 +200,11 @@ def test_population_control_rejections():
         with pytest.raises(m.MCDCError) as ei:
             m.mcdc_run(p, 1000, 1, pc_method="comb")
         assert ei.value.code == m._binding.MCDC_E_INVALID
+        # combing runs the one-kernel step only
+        for kw in (dict(two_kernel_step=True), dict(sort_cadence=2)):
+            with pytest.raises(m.MCDCError) as ei:
+                m.mcdc_run(p, 1000, 1, pc_target=1000, pc_method="comb", **kw)
+            assert ei.value.code == MCDC_E_UNSUPPORTED, kw
         # auto picks the event form
         g = m.mcdc_run(p, 2000, 1, algorithm="auto", pc_target=2000)
         assert g["splits"] > 0

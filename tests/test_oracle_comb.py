@@ -1,7 +1,7 @@
 """Pins of the oracle's population control by combing (reading R28: the
-controlled particles in history-then-stream order, M teeth spaced W / M at
-one random offset per edge, each particle copied once per tooth in its
-stretch of the cumulative fixed-point weight).
+controlled particles in the run's list order, M teeth spaced W / M at one
+random offset per edge, each particle copied once per tooth in its stretch
+of the cumulative fixed-point weight).
 
 The comb itself is pinned against exact rational arithmetic: every count
 is the floor or the ceiling of M q / W (q the fixed-point weight, W their
