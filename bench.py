@@ -801,7 +801,7 @@ def main():
     ap.add_argument("--fom-analog", type=float, default=4e9, help="histories per analog replica")
     ap.add_argument("--fom-analog-runs", type=int, default=10)
     ap.add_argument("--fom-ww", type=float, default=1e9, help="histories per windowed replica")
-    ap.add_argument("--fom-ww-runs", type=int, default=4)
+    ap.add_argument("--fom-ww-runs", type=int, default=8)
     ap.add_argument("--fom-steps", type=int, default=3000)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 1 GiB device-to-device copy (reference for HBM counters)")
