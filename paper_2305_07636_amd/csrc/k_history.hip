@@ -232,8 +232,12 @@ __device__ __forceinline__ void end_history(const DevProblem &P, const RunArgs &
 
 // Idle lanes that trigger a refill.  The histories a wave takes from the
 // device-wide counter at a time scale with the job (about 16 takes per
-// wave), so short histories do not serialise on that one counter.
-constexpr int kRefillMin = 32;
+// wave), so short histories do not serialise on that one counter.  The
+// history kernel refills once half the wave is idle (each refill's loads
+// then serve many lanes); the progeny kernel, whose particles end at
+// scattered times and which waits on memory most of the time, refills as
+// soon as a few lanes are idle.
+constexpr int kRefillMin = 32, kRefillMinProgeny = 4;
 // LDS budget for the persistent kernel's staged tables.
 constexpr int64_t kHistoryTablesMax = 40 * 1024;
 
@@ -426,7 +430,7 @@ __global__ void __launch_bounds__(256) k_history_children(DevProblem P0, RunArgs
     Held held;
     for (;;) {
         uint64_t need = __ballot(!busy);
-        if (__popcll(need) < kRefillMin && need != ~0ull) need = 0;
+        if (__popcll(need) < kRefillMinProgeny && need != ~0ull) need = 0;
         while (need && !drained) {
             if (c_pos == c_end) {
                 unsigned long long base = 0;
