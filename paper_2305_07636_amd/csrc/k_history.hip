@@ -154,8 +154,13 @@ __device__ __forceinline__ int hstep(const DevProblem &P, const RunArgs &R, Part
 
 // A wave's persistent loop takes queued collisions only once they make up
 // kCollEighths / 8 of its busy lanes (or every busy lane has one), so that
-// the collision code runs for many lanes at once.
+// the collision code runs for many lanes at once.  The progeny kernel
+// waits for every busy lane when fission makes its collisions costly (each
+// may bank neutrons) and takes them at 2/8 otherwise (measured on the
+// supercritical pulse: 3/8 34.8 ms, 5/8 29.2, 8/8 26.3; on the windowed
+// dog-leg: 0-2/8 1142 ms, 3/8 1173, 8/8 1684).
 constexpr int kCollEighths = 3;
+__device__ __forceinline__ int progeny_coll_eighths(const DevProblem &P) { return P.fission_on ? 8 : 2; }
 
 // Track one particle of history hid until it terminates; returns the
 // termination code (also ORed into acc.term_mask).
@@ -416,6 +421,7 @@ __global__ void __launch_bounds__(256) k_history_children(DevProblem P0, RunArgs
     const unsigned int wave_chunk = (unsigned int)wcl;
     if (threadIdx.x < kCounters) red[threadIdx.x] = 0ull;
     const DevProblem P = stage_tables<LT, 256>(P0, tabs, reinterpret_cast<char *>(lds_tables));
+    const int coll_eighths = progeny_coll_eighths(P0);
     __syncthreads();
 
     uint64_t c_pos = 0, c_end = 0;   // the wave's current chunk (wave-uniform)
@@ -464,7 +470,7 @@ __global__ void __launch_bounds__(256) k_history_children(DevProblem P0, RunArgs
         const bool pend = busy && pm >= 0;
         const int n_pend = __popcll(__ballot(pend));
         int code = -1;
-        if (n_pend > 0 && (n_pend * 8 >= n_busy * kCollEighths || n_pend == n_busy) && pend) {
+        if (n_pend > 0 && (n_pend * 8 >= n_busy * coll_eighths || n_pend == n_busy) && pend) {
             code = hcollide<FM, true>(P, R, p, cell, b, i, acc, out, pm);
             pm = -1;
         }
