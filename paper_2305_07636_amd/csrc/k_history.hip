@@ -414,9 +414,11 @@ __global__ void __launch_bounds__(256) k_history_children(DevProblem P0, RunArgs
     }
     const unsigned long long n = n_in;
     if (n == 0) return;
-    // entries per wave take: about 16 takes per wave of the grid, 64..65536
+    // entries per wave take: about 4 takes per wave of the grid, 64..65536
+    // (measured on the supercritical pulse: 16 takes 25.2 ms, 4 takes 23.2;
+    // 1 to 4 take the same time on both workloads tried)
     const unsigned long long waves = (unsigned long long)gridDim.x * (blockDim.x / 64);
-    unsigned long long wcl = n / (waves * 16ull);
+    unsigned long long wcl = n / (waves * 4ull);
     wcl = (wcl < 64ull) ? 64ull : (wcl > 65536ull ? 65536ull : (wcl + 63ull) & ~63ull);
     const unsigned int wave_chunk = (unsigned int)wcl;
     if (threadIdx.x < kCounters) red[threadIdx.x] = 0ull;
