@@ -523,7 +523,9 @@ SplitBank carve_split(void *mem, unsigned int cap, unsigned long long *count) {
     return B;
 }
 
-size_t split_bytes(unsigned int cap) { return (size_t)cap * (13 * 8 + 8) + 16 * 256; }
+// (nine doubles and the stream, 8 bytes each; ixyz and gk, 4 each; the
+// history index, 8: 96 bytes an entry; each of the 13 arrays padded to 256)
+size_t split_bytes(unsigned int cap) { return (size_t)cap * 96 + 13 * 256; }
 
 // The persistent history kernel: as many workgroups as the GPU holds
 // resident (no more than the work needs), and the work counter cleared.
@@ -640,39 +642,67 @@ int run_generations(mcdc_problem *pb, const RunArgs &R, SplitBank SB[2], uint64_
     }
 }
 
-// Weighted chunks of the history form, two at a time: chunk c runs on one
-// of two streams with its own split-bank pair, detector accumulator and
-// work counters, so that the last, small generations of one chunk overlap
-// the next chunk's histories.  The host starts a chunk as soon as a pair is
-// free and queues the generations of each running chunk in batches, polling
-// each batch's completion event and its copied count (no stream waits on
-// another stream's progress).
+// Weighted chunks of the history form, kChunkStreams at a time: chunk c
+// runs on one of the streams with its own split-bank pair, detector
+// accumulator and work counters, so that the last, small generations of
+// one chunk overlap the other chunks' histories.  The host starts a chunk
+// as soon as a pair is free and queues the generations of each running
+// chunk in batches, polling each batch's completion event and its copied
+// count (no stream waits on another stream's progress).
+// (measured against 2: 3 streams about the same, 4 streams 5 % faster on a
+// windowed 1e8-history run in 48 chunks and 18 % on a 1e7-history fission
+// run in 10; each stream holds two split banks of up to 2^26 entries)
+constexpr int kChunkStreams = 4;
+static_assert(kChunkStreams >= 1 && kChunkStreams <= kMaxChunkStreams, "chunk streams");
+
+// The chunk streams of a weighted run of `count` histories in chunks of
+// `chunk`, and the device memory they need (split banks, detector
+// accumulators, work counters); allocating it twice is a no-op.
+int weighted_streams(uint64_t count, uint64_t chunk) {
+    const uint64_t n_chunks = (count + chunk - 1) / chunk;
+    return (int)((n_chunks < (uint64_t)kChunkStreams) ? n_chunks : (uint64_t)kChunkStreams);
+}
+int weighted_reserve(mcdc_problem *pb, uint64_t chunk, int NS, SplitBank (*SB)[2]) {
+    int rc;
+    if ((rc = split_prepare_slots(pb, chunk, SB, NS))) return rc;
+    if (pb->d.qoi_on && (rc = ensure(pb->qoi_hist, (size_t)NS * chunk * sizeof(double)))) return rc;
+    return ensure(pb->work, (size_t)NS * 256);
+}
+uint64_t weighted_chunk(const DevProblem &P, uint64_t count, uint64_t chunk_opt) {
+    const uint64_t cmax = chunk_opt ? chunk_opt : (P.fission_on ? kFissionChunk : kWindowChunk);
+    return (count < cmax) ? count : cmax;
+}
+
 template <int FM>
 int run_weighted_chunks(mcdc_problem *pb, const RunArgs &R0, uint64_t first, uint64_t count, uint64_t chunk,
                         hipStream_t st, Profiler &prof) {
     const DevProblem &P = pb->d;
-    const int NS = count > chunk ? 2 : 1;
-    SplitBank SB[2][2]{};
+    const int NS = weighted_streams(count, chunk);
+    SplitBank SB[kMaxChunkStreams][2]{};
     int rc;
-    if ((rc = split_prepare_slots(pb, chunk, SB, NS))) return rc;
-    if (P.qoi_on && (rc = ensure(pb->qoi_hist, (size_t)NS * chunk * sizeof(double)))) return rc;
-    if ((rc = ensure(pb->work, (size_t)NS * 256))) return rc;
+    if ((rc = weighted_reserve(pb, chunk, NS, SB))) return rc;
     ChildShape cs;
     if ((rc = child_shape<FM>(pb, cs))) return rc;
     hipError_t e = hipSuccess;
-    if (!pb->aux_stream) e = hipStreamCreateWithFlags((hipStream_t *)&pb->aux_stream, hipStreamNonBlocking);
-    for (int j = 0; j < 4 && e == hipSuccess; ++j)
+    for (int j = 0; j + 1 < NS && e == hipSuccess; ++j)
+        if (!pb->aux_streams[j]) e = hipStreamCreateWithFlags((hipStream_t *)&pb->aux_streams[j], hipStreamNonBlocking);
+    for (int j = 0; j < 2 * kMaxChunkStreams && e == hipSuccess; ++j)
         if (!pb->aux_events[j]) e = hipEventCreateWithFlags((hipEvent_t *)&pb->aux_events[j], hipEventDisableTiming);
     if (e == hipSuccess && !pb->host_counts)
-        e = hipHostMalloc((void **)&pb->host_counts, 4 * sizeof(unsigned long long), hipHostMallocDefault);
+        e = hipHostMalloc((void **)&pb->host_counts, kMaxChunkStreams * sizeof(unsigned long long),
+                          hipHostMallocDefault);
     if (e != hipSuccess) return hip_fail(e, "chunk streams");
-    hipStream_t S[2] = {st, (hipStream_t)pb->aux_stream};
-    hipEvent_t done[2] = {(hipEvent_t)pb->aux_events[0], (hipEvent_t)pb->aux_events[1]};
-    hipEvent_t join = (hipEvent_t)pb->aux_events[2];
-    // the second stream starts after everything queued on the caller's
-    if (NS == 2) {
-        e = hipEventRecord(join, st);
-        if (e == hipSuccess) e = hipStreamWaitEvent(S[1], join, 0);
+    hipStream_t S[kMaxChunkStreams];
+    hipEvent_t done[kMaxChunkStreams], joined[kMaxChunkStreams];
+    for (int q = 0; q < kMaxChunkStreams; ++q) {
+        S[q] = q == 0 ? st : (hipStream_t)pb->aux_streams[q - 1];
+        done[q] = (hipEvent_t)pb->aux_events[q];
+        joined[q] = (hipEvent_t)pb->aux_events[kMaxChunkStreams + q];
+    }
+    // the other streams start after everything queued on the caller's
+    if (NS > 1) {
+        e = hipEventRecord(joined[0], st);
+        for (int q = 1; q < NS && e == hipSuccess; ++q) e = hipStreamWaitEvent(S[q], joined[0], 0);
         if (e != hipSuccess) return hip_fail(e, "chunk streams");
     }
     struct Slot {
@@ -681,7 +711,7 @@ int run_weighted_chunks(mcdc_problem *pb, const RunArgs &R0, uint64_t first, uin
         int gen = 0;
         RunArgs R;
         unsigned long long *next_main = nullptr, *next_child = nullptr;
-    } slot[2];
+    } slot[kMaxChunkStreams];
     for (int q = 0; q < NS; ++q) {
         slot[q].R = R0;
         if (P.qoi_on) slot[q].R.qoi_hist = (double *)pb->qoi_hist.p + (size_t)q * chunk;
@@ -740,10 +770,10 @@ int run_weighted_chunks(mcdc_problem *pb, const RunArgs &R0, uint64_t first, uin
         if (!any && c0 >= count) break;
         if (!progress) std::this_thread::sleep_for(std::chrono::microseconds(20));
     }
-    // the caller's stream waits for the second stream's work
-    if (NS == 2) {
-        e = hipEventRecord(join, S[1]);
-        if (e == hipSuccess) e = hipStreamWaitEvent(st, join, 0);
+    // the caller's stream waits for the other streams' work
+    for (int q = 1; q < NS; ++q) {
+        e = hipEventRecord(joined[q], S[q]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(st, joined[q], 0);
         if (e != hipSuccess) return hip_fail(e, "chunk streams");
     }
     return MCDC_OK;
@@ -756,10 +786,7 @@ int run_history(mcdc_problem *pb, const RunArgs &R0, uint64_t first, uint64_t co
     const bool ww = has_progeny(P);
     // analog runs keep the detector score in registers; runs with progeny
     // (weight windows, fission) assemble it per history in chunks
-    if (ww) {
-        const uint64_t cmax = chunk_opt ? chunk_opt : (P.fission_on ? kFissionChunk : kWindowChunk);
-        return run_weighted_chunks<FM>(pb, R0, first, count, (count < cmax) ? count : cmax, st, prof);
-    }
+    if (ww) return run_weighted_chunks<FM>(pb, R0, first, count, weighted_chunk(P, count, chunk_opt), st, prof);
     SplitBank none[2]{};
     int rc = launch_main<FM, false>(pb, P, R0, first, count, first, none[0], st, prof);
     if (rc) return rc;
@@ -901,12 +928,17 @@ int split_prepare_slots(mcdc_problem *pb, uint64_t chunk, dev::SplitBank (*SB)[2
     const uint64_t want = per * chunk;
     const unsigned int cap = (unsigned int)((want < (1u << 22)) ? (1u << 22) : (want > (1u << 26) ? (1u << 26) : want));
     int rc;
-    if ((rc = ensure(pb->split, (size_t)slots * 2 * split_bytes(cap) + 256))) return rc;
+    if (slots > kMaxChunkStreams) {
+        set_error("too many chunk streams");
+        return MCDC_E_INVALID;
+    }
+    for (int q = 0; q < slots; ++q)
+        if ((rc = ensure(pb->split[q], 2 * split_bytes(cap) + 256))) return rc;
     // (two bank counters, then the children kernel's work counter)
     if ((rc = ensure(pb->counters_split, (size_t)slots * 3 * sizeof(unsigned long long)))) return rc;
     unsigned long long *cnt = (unsigned long long *)pb->counters_split.p;
     for (int q = 0; q < slots; ++q) {
-        char *base = (char *)pb->split.p + (size_t)q * 2 * split_bytes(cap);
+        char *base = (char *)pb->split[q].p;
         SB[q][0] = carve_split(base, cap, cnt + 3 * q);
         SB[q][1] = carve_split(base + split_bytes(cap), cap, cnt + 3 * q + 1);
     }
@@ -931,6 +963,13 @@ int split_generations(mcdc_problem *pb, const RunArgs &R, dev::SplitBank SB[2], 
     if (fm == 1) return run_generations<1>(pb, R, SB, cfirst, st, prof);
     if (fm == 7) return run_generations<7>(pb, R, SB, cfirst, st, prof);
     return run_generations<0>(pb, R, SB, cfirst, st, prof);
+}
+
+int history_reserve(mcdc_problem *p, uint64_t count, uint64_t chunk_opt) {
+    if (count == 0 || !has_progeny(p->d)) return MCDC_OK;
+    const uint64_t chunk = weighted_chunk(p->d, count, chunk_opt);
+    SplitBank SB[kMaxChunkStreams][2]{};
+    return weighted_reserve(p, chunk, weighted_streams(count, chunk), SB);
 }
 
 int launch_history(mcdc_problem *p, const RunArgs &R, uint64_t first, uint64_t count, uint64_t chunk,

@@ -16,6 +16,7 @@ namespace mcdc {
 constexpr int kMaxGroups = 32;      // outgoing-group search is unrolled over this
 constexpr int kCounters = 10;       // census, surface, collision; 5 terminations; splits; fission progeny
 constexpr int kLdsTallyMax = 4096;  // doubles of the event form's per-step LDS tally slice
+constexpr int kMaxChunkStreams = 4;   // weighted bank chunks in flight at once, at most
 constexpr uint64_t kWindowChunk = 1ULL << 23;  // histories per chunk of a weight-window run
 constexpr uint64_t kFissionChunk = 1ULL << 20; // histories per chunk of a run with fission
 constexpr double kMaxNu = 64.0;                // largest mean number of neutrons per fission
@@ -228,15 +229,16 @@ struct mcdc_problem {
         void *p = nullptr;
         size_t bytes = 0;
     };
-    Buf S, L, qoi_hist, qoi_sums, counters, overflow, bank, queues, split, prof, counters_split, tally_part, work, comb;
+    Buf S, L, qoi_hist, qoi_sums, counters, overflow, bank, queues, prof, counters_split, tally_part, work, comb;
+    Buf split[mcdc::kMaxChunkStreams];   // each chunk stream's pair of split banks (one allocation each)
     Buf mean, var, raw, leak_mean, leak_var, tc_mean, tc_var;
     void *graph_cache = nullptr;   // captured census steps of the event form
     // weighted history-form runs: a second stream (default priority) and
     // events for overlapping bank chunks, pinned host words for their
     // generation counts
-    void *aux_stream = nullptr;
-    void *aux_events[4] = {nullptr, nullptr, nullptr, nullptr};
-    unsigned long long *host_counts = nullptr;
+    void *aux_streams[mcdc::kMaxChunkStreams - 1] = {};   // weighted chunks: streams beside the caller's
+    void *aux_events[2 * mcdc::kMaxChunkStreams] = {};   // per stream: batch done, join
+    unsigned long long *host_counts = nullptr;      // [kMaxChunkStreams]
     // MCDC_ALG_AUTO: the faster form for one history count, once timed
     uint64_t auto_n = 0;
     int auto_alg = -1;
@@ -249,6 +251,10 @@ int hip_fail(hipError_t e, const char *what);
 int ensure(mcdc_problem::Buf &b, size_t bytes);
 
 // launchers (return a hipError_t as int)
+// Allocates beforehand the device memory a history-form run of `count`
+// histories will take (the weighted runs' split banks), so that a run's
+// timed region holds no allocation.
+int history_reserve(mcdc_problem *p, uint64_t count, uint64_t chunk_opt);
 int launch_history(mcdc_problem *p, const RunArgs &R, uint64_t first, uint64_t count,
                    uint64_t chunk, hipStream_t st, Profiler &prof);
 int launch_event(mcdc_problem *p, const RunArgs &R, uint64_t first, uint64_t count,

@@ -595,18 +595,20 @@ extern "C" int mcdc_problem_create(const mcdc_problem_desc *desc, mcdc_problem *
 extern "C" int mcdc_problem_destroy(mcdc_problem *p) {
     if (!p) return MCDC_OK;
     destroy_graph_cache(p);
-    if (p->aux_stream) (void)hipStreamDestroy((hipStream_t)p->aux_stream);
+    for (void *a : p->aux_streams)
+        if (a) (void)hipStreamDestroy((hipStream_t)a);
     for (void *e : p->aux_events)
         if (e) (void)hipEventDestroy((hipEvent_t)e);
     if (p->host_counts) (void)hipHostFree(p->host_counts);
     if (p->blob) (void)hipFree(p->blob);
     if (p->ww_dev) (void)hipFree(p->ww_dev);
     mcdc_problem::Buf *bufs[] = {&p->S, &p->L, &p->qoi_hist, &p->qoi_sums, &p->counters,
-                                 &p->overflow, &p->bank, &p->queues, &p->split, &p->prof,
+                                 &p->overflow, &p->bank, &p->queues, &p->prof,
                                  &p->counters_split, &p->tally_part, &p->mean,
                                  &p->var, &p->raw, &p->leak_mean, &p->leak_var, &p->tc_mean, &p->tc_var, &p->work,
                                  &p->comb};
     for (auto *b : bufs) free_buf(*b);
+    for (auto &b : p->split) free_buf(b);
     delete p;
     return MCDC_OK;
 }

@@ -310,6 +310,10 @@ extern "C" int mcdc_run(mcdc_problem *p, uint64_t n_histories, uint64_t seed, co
     Events ev;
     HIP_CHECK(hipEventCreate(&ev.a), "hipEventCreate");
     HIP_CHECK(hipEventCreate(&ev.b), "hipEventCreate");
+    // (the history form's split banks are allocated before the run's timed
+    // region, so kernel_ms holds device time only)
+    if (opt.algorithm == MCDC_ALG_HISTORY && (rc = history_reserve(p, n_histories, (uint64_t)opt.bank_capacity)))
+        return rc;
     HIP_CHECK(hipEventRecord(ev.a, st), "hipEventRecord");
 
     RunArgs R;
