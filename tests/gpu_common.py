@@ -11,6 +11,12 @@ Tolerances (written here, used by every parity test):
   variance is a difference of batch means that agree to ~1e-15 relative;
   with batch means spread by ~1e-4 of the mean the difference keeps about
   1e-11 relative accuracy, and 1e-9 leaves margin for bins with few scores.
+  Plus 16 eps (max |mean|)^2 absolute: the variance is formed as
+  (sum of squared batch means - squared sum / B) / (B (B - 1)), whose
+  cancellation leaves an error of order eps m^2 in either order of
+  summation, the whole result when every batch mean is the same (a
+  deterministic bin: the true variance is 0 and each side returns its
+  rounding).
 """
 from __future__ import annotations
 
@@ -22,12 +28,21 @@ RTOL = 1e-12
 VAR_RTOL = 1e-9
 
 
-def close(gpu, ref, rtol=RTOL, what=""):
+EPS = np.finfo(np.float64).eps
+
+
+def var_floor(mean):
+    """Absolute tolerance of a batch variance of the given means."""
+    m = np.abs(np.asarray(mean, dtype=np.float64))
+    return 16.0 * EPS * (m.max() ** 2 if m.size else 0.0)
+
+
+def close(gpu, ref, rtol=RTOL, what="", atol=0.0):
     gpu = np.asarray(gpu, dtype=np.float64).ravel()
     ref = np.asarray(ref, dtype=np.float64).ravel()
     assert gpu.shape == ref.shape, (what, gpu.shape, ref.shape)
     scale = np.abs(ref).max() if ref.size else 0.0
-    tol = rtol * np.abs(ref) + 1e-12 * scale
+    tol = rtol * np.abs(ref) + 1e-12 * scale + atol
     bad = np.abs(gpu - ref) > tol
     assert not bad.any(), (what, int(bad.sum()), np.nonzero(bad)[0][:5], gpu[bad][:5], ref[bad][:5])
 
@@ -67,12 +82,12 @@ def compare_full(prob, N, seed, algorithm, ww=None, **kw):
     assert g["fission"] == int(tot[9])
     close(g["raw"], e["raw"], what="raw")
     close(g["mean"], e["mean"], what="mean")
-    close(g["var"], e["var"], rtol=VAR_RTOL, what="var")
+    close(g["var"], e["var"], rtol=VAR_RTOL, what="var", atol=var_floor(e["mean"]))
     close(g["leak_mean"], e["leak_mean"], what="leak mean")
-    close(g["leak_var"], e["leak_var"], rtol=VAR_RTOL, what="leak var")
+    close(g["leak_var"], e["leak_var"], rtol=VAR_RTOL, what="leak var", atol=var_floor(e["leak_mean"]))
     if prob["tally"].get("time_crossing", False):
         close(g["tc_mean"], e["tc_mean"], what="time-crossing mean")
-        close(g["tc_var"], e["tc_var"], rtol=VAR_RTOL, what="time-crossing var")
+        close(g["tc_var"], e["tc_var"], rtol=VAR_RTOL, what="time-crossing var", atol=var_floor(e["tc_mean"]))
     else:
         assert "tc_mean" not in g
     if prob.get("qoi") is not None:

@@ -2,7 +2,9 @@
 per geometry cell, its negative side filled with a material of its own) in
 both forms against the oracle: beams through a sphere, a double cone along
 and across its axis and a tilted plane crossed both ways (with scattering
-inside, so every root rule is reached from both sides), sphere lattices
+inside, so every root rule is reached from both sides), degenerate cases
+(a constant quadric, a beam tangent to a sphere, a plane quadric on a
+mesh plane, a sphere touching its cell's faces), sphere lattices
 (pulse, implicit capture, time-crossing tally, weight windows), a lattice
 of mixed quadrics (rotated ellipsoids with cross terms, cones, hyperboloids,
 planes, cells without one) under a tally mesh finer than the cells, several
@@ -44,6 +46,10 @@ CASES = {
     "spheres": (lambda: w.sphere_lattice(n=3, n_layers=2, n_groups=3), 4001, 96),
     "spheres_ic": (lambda: _ic(w.sphere_lattice(n=3, n_layers=2, n_groups=2, gen_seed=24)), 3001, 97),
     "spheres_tc": (lambda: _tc(w.sphere_lattice(n=2, n_layers=2, n_groups=2, gen_seed=25)), 3001, 98),
+    "const_inside": (_beam(np.array([0, 0, 0, 0, 0, 0, 0, 0, 0, -1.0]), 0, 1, (0.0, 1.2, 0.9)), 3001, 106),
+    "tangent": (_beam(w.sphere_quadric((1.0, 1.0, 1.0), 0.6), 0, 1, (0.0, 1.6, 1.0)), 2001, 107),
+    "coincident_plane": (_beam(w.plane_quadric((1.0, 0.0, 0.0), 1.0), 0, 1, (0.0, 1.3, 0.7)), 3001, 108),
+    "touching_sphere": (_beam(w.sphere_quadric((1.0, 1.0, 1.0), 1.0), 0, 1, (0.0, 1.0, 1.0)), 3001, 109),
     "mixed": (lambda: w.mixed_quadric_lattice(), 5003, 99),
     "mixed_vacuum": (lambda: w.mixed_quadric_lattice(n=4, n_layers=3, gen_seed=31, bc=w.VACUUM), 5003, 100),
 }

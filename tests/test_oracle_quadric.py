@@ -196,3 +196,47 @@ def test_quadric_validation():
                      "material": np.zeros_like(s["material"])}
     with pytest.raises(Exception):
         oracle.run(s, 10, 1)
+
+
+def test_constant_quadrics_reduce_to_plain_cells():
+    """A quadric with only its constant term: K < 0 is inside everywhere,
+    so the run is bit for bit that of the cell filled with the inside
+    material; K > 0 is inside nowhere, so it is the run without it."""
+    const_in = np.array([0, 0, 0, 0, 0, 0, 0, 0, 0, -1.0])
+    p = w.beam_through_quadric(const_in, scatter=0.6)
+    q = w.beam_through_quadric(const_in, scatter=0.6)
+    q["quadrics"] = None
+    q["material"] = np.ones_like(q["material"])
+    a, b = oracle.run(p, 3000, 5, records=True), oracle.run(q, 3000, 5, records=True)
+    assert np.array_equal(a["rec"], b["rec"]) and np.array_equal(a["S"], b["S"])
+    p = w.beam_through_quadric(-const_in, scatter=0.6)
+    q = dict(p)
+    q["quadrics"] = None
+    a, b = oracle.run(p, 3000, 5, records=True), oracle.run(q, 3000, 5, records=True)
+    assert np.array_equal(a["rec"], b["rec"]) and np.array_equal(a["S"], b["S"])
+
+
+def test_tangent_beam_never_enters():
+    """A beam tangent to the sphere (zero discriminant from outside) makes
+    no quadric crossing: every particle leaks, with one surface event per
+    mesh plane and none more."""
+    p = w.beam_through_quadric(w.sphere_quadric((1.0, 1.0, 1.0), 0.6), point=(0.0, 1.6, 1.0))
+    r = oracle.run(p, 2000, 7)
+    t = r["tot"].astype(np.int64)
+    assert int(t[3 + oracle.T_LEAK]) == 2000 and int(t[3 + oracle.T_ABSORB]) == 0
+    assert int(t[1]) == 2000 * 20
+
+
+@pytest.mark.parametrize("coef, point, chord", [
+    # a plane quadric on the mesh plane x = 1 (the plane and the quadric tie;
+    # planes go first, then the quadric at distance 0)
+    (w.plane_quadric((1.0, 0.0, 0.0), 1.0), (0.0, 1.3, 0.7), 1.0),
+    # a sphere touching the cell's faces, the beam along its axis: born on
+    # the surface moving in
+    (w.sphere_quadric((1.0, 1.0, 1.0), 1.0), (0.0, 1.0, 1.0), 2.0),
+])
+def test_degenerate_crossings_keep_the_transmission(coef, point, chord):
+    p = w.beam_through_quadric(coef, point=point)
+    r = oracle.run(p, 40000, 9)
+    e = oracle.estimates(p, r)
+    _check([e["leak_mean"][0, 0, 1]], [e["leak_var"][0, 0, 1]], [math.exp(-1.5 * chord)])
