@@ -93,10 +93,12 @@ __device__ __forceinline__ int hcollide(const DevProblem &P, const RunArgs &R, P
 // returns the termination code, -1 while the particle lives, or
 // kCollisionPending when the flight ends in a collision (its material in
 // m_coll), which hcollide then applies.  Split progeny go to the split bank.
+// (slice: the workgroup's LDS copy of batch b0's track-length tally, or
+// nullptr: a score of that batch goes there, any other to HBM)
 template <int FM, bool WW>
 __device__ __forceinline__ int hflight(const DevProblem &P, const RunArgs &R, Particle &p, int &cell, int b,
                                        uint64_t hid, Acc &acc, const SplitBank &SB, int &since, int &m_coll,
-                                       Held &held) {
+                                       Held &held, double *slice = nullptr, int b0 = -1) {
     if (since >= kMaxEventsPerStep) return kLost;
     ++since;
     const Flight f = next_event<FM>(P, p, cell);
@@ -104,7 +106,11 @@ __device__ __forceinline__ int hflight(const DevProblem &P, const RunArgs &R, Pa
     const double sc = p.w * f.d;
     const int tb = P.cell_tal[cell];
     if (tb >= 0) {
-        held.add(tally_copy(P, R, b) + ((int64_t)p.k * P.G + p.g) * P.nts + tb, sc);
+        const int64_t j = ((int64_t)p.k * P.G + p.g) * P.nts + tb;
+        if (slice && b == b0)
+            atomicAdd(slice + j, sc);
+        else
+            held.add(tally_copy(P, R, b) + j, sc);
         acc.track += sc;
     }
     if (P.qoi_on && P.cell_qoi[cell] && P.qoi_groups[p.g]) acc.qoi += sc;
@@ -243,8 +249,10 @@ __device__ __forceinline__ void end_history(const DevProblem &P, const RunArgs &
 // scattered times and which waits on memory most of the time, refills as
 // soon as a few lanes are idle.
 constexpr int kRefillMin = 32, kRefillMinProgeny = 4;
-// LDS budget for the persistent kernel's staged tables.
+// LDS budget for the persistent kernel's staged tables, and for its LDS
+// slice of one batch's tally (analog runs).
 constexpr int64_t kHistoryTablesMax = 40 * 1024;
+constexpr int64_t kHistorySliceMax = 48 * 1024;
 
 // Persistent history form: every wave takes chunks of consecutive histories
 // [first, first + count) from a device counter; a lane whose particle has
@@ -253,16 +261,37 @@ constexpr int64_t kHistoryTablesMax = 40 * 1024;
 // counter has passed the end and its lanes are idle.
 // (LT: the flight tables are copied into LDS first; the workgroups live
 // for the whole run, so the copy is paid once per workgroup.)
-template <int FM, bool WW, bool LT>
+// (SL, analog runs whose tally of one batch fits in LDS: workgroup w takes
+// the histories [w H, (w + 1) H) of the chunk, H = ceil(count / grid), its
+// waves drawing chunks of them from a workgroup counter, so that they
+// belong to one batch or two; the scores of the range's first batch b0 go
+// to an LDS copy of that batch's tally (gn doubles behind the staged
+// tables), added to HBM once at the end.)
+template <int FM, bool WW, bool LT, bool SL = false>
 __global__ void __launch_bounds__(256) k_history(DevProblem P0, RunArgs R, uint64_t first, uint64_t count,
                                                  uint64_t chunk_first, SplitBank SB, unsigned long long *next,
-                                                 unsigned int wave_chunk, LdsTables tabs) {
+                                                 unsigned int wave_chunk, LdsTables tabs, int gn = 0) {
     __shared__ unsigned long long red[kCounters + 1];
     __shared__ double qsum[2];
+    __shared__ unsigned long long wg_next;
     extern __shared__ double lds_tables[];
     if (threadIdx.x < kCounters + 1) red[threadIdx.x] = 0ull;
     if (threadIdx.x < 2) qsum[threadIdx.x] = 0.0;
+    if (threadIdx.x == 0) wg_next = 0ull;
     const DevProblem P = stage_tables<LT, 256>(P0, tabs, reinterpret_cast<char *>(lds_tables));
+    // the workgroup's range and its slice
+    uint64_t w_lo = 0, w_hi = count;
+    int b0 = -1;
+    double *slice = nullptr;
+    if constexpr (SL) {
+        const uint64_t H = (count + gridDim.x - 1) / gridDim.x;
+        w_lo = (uint64_t)blockIdx.x * H;
+        w_hi = (w_lo + H < count) ? w_lo + H : count;
+        if (w_lo > count) w_lo = count;
+        b0 = (int)(((first + w_lo + 1) * (uint64_t)R.B - 1) / R.N);
+        slice = lds_tables + (LT ? (tabs.bytes + 15) / 16 * 2 : 0);
+        for (int j = threadIdx.x; j < gn; j += 256) slice[j] = 0.0;
+    }
     __syncthreads();
 
     uint64_t c_pos = 0, c_end = 0;   // the wave's current chunk (wave-uniform)
@@ -284,14 +313,16 @@ __global__ void __launch_bounds__(256) k_history(DevProblem P0, RunArgs R, uint6
         while (need && !drained) {
             if (c_pos == c_end) {
                 unsigned long long base = 0;
-                if (__lane_id() == 0) base = atomicAdd(next, (unsigned long long)wave_chunk);
+                if (__lane_id() == 0)
+                    base = SL ? w_lo + atomicAdd(&wg_next, (unsigned long long)wave_chunk)
+                              : atomicAdd(next, (unsigned long long)wave_chunk);
                 base = __shfl(base, 0);
-                if (base >= count) {
+                if (base >= w_hi) {
                     drained = true;
                     break;
                 }
                 c_pos = base;
-                c_end = (base + wave_chunk < count) ? base + wave_chunk : count;
+                c_end = (base + wave_chunk < w_hi) ? base + wave_chunk : w_hi;
                 s_pos = history_stream(P, R.seed, first + c_pos);
             }
             const uint64_t avail = c_end - c_pos;
@@ -330,7 +361,7 @@ __global__ void __launch_bounds__(256) k_history(DevProblem P0, RunArgs R, uint6
             pm = -1;
         }
         if (busy && pm < 0 && code < 0) {
-            code = hflight<FM, WW>(P, R, p, cell, b, i, acc, SB, since, pm, held);
+            code = hflight<FM, WW>(P, R, p, cell, b, i, acc, SB, since, pm, held, slice, b0);
             if (code == kCollisionPending) code = -1;
             else pm = -1;
         }
@@ -341,6 +372,15 @@ __global__ void __launch_bounds__(256) k_history(DevProblem P0, RunArgs R, uint6
         }
     }
     held.release();
+    if constexpr (SL) {
+        // the slice into batch b0's tally copy of this workgroup
+        __syncthreads();
+        if (b0 >= 0 && w_lo < w_hi) {
+            double *dst = tally_copy(P, R, b0);
+            for (int j = threadIdx.x; j < gn; j += 256)
+                if (slice[j] != 0.0) atomic_add_f64(dst + j, slice[j]);
+        }
+    }
     // totals: wave reductions, then one atomic per counter and workgroup
 #pragma unroll
     for (int j = 0; j < kCounters; ++j) {
@@ -542,11 +582,21 @@ int launch_main(mcdc_problem *pb, const DevProblem &P, const RunArgs &R, uint64_
     }
     LdsTables tabs{};
     const bool lt = table_layout(P, tabs, kHistoryTablesMax);
-    const size_t shmem = lt ? (size_t)tabs.bytes : 0;
+    // analog slab runs (x the only finite axis) without the time-crossing
+    // tally whose tally of one batch fits beside the tables score that batch
+    // in LDS (SL; in 3-D problems the slice's registers would cost a wave
+    // per SIMD)
+    constexpr bool kSlice = FM == 1 && !WW;
+    const int64_t gn64 = (int64_t)P.K * P.G * P.nts;
+    const bool sl = kSlice && lt && !P.tc_on && gn64 > 0 && gn64 * 8 <= kHistorySliceMax;
+    const int gn = sl ? (int)gn64 : 0;
+    const size_t shmem = lt ? (size_t)(tabs.bytes + 15) / 16 * 16 + (size_t)gn * 8 : 0;
+    const void *kern = lt ? reinterpret_cast<const void *>(&k_history<FM, WW, true>)
+                          : reinterpret_cast<const void *>(&k_history<FM, WW, false>);
+    if constexpr (kSlice)
+        if (sl) kern = reinterpret_cast<const void *>(&k_history<FM, WW, true, true>);
     int per_cu = 0, n_cu = 0;
-    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &per_cu, lt ? reinterpret_cast<const void *>(&k_history<FM, WW, true>)
-                    : reinterpret_cast<const void *>(&k_history<FM, WW, false>), bs, shmem);
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, bs, shmem);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, pb->device);
     if (e != hipSuccess) return hip_fail(e, "occupancy query");
     uint64_t grid = (uint64_t)(per_cu > 0 ? per_cu : 1) * (uint64_t)(n_cu > 0 ? n_cu : 1);
@@ -556,18 +606,23 @@ int launch_main(mcdc_problem *pb, const DevProblem &P, const RunArgs &R, uint64_
     const uint64_t grid_needed = ((count + wc - 1) / wc + bs / 64 - 1) / (bs / 64);
     if (grid > grid_needed) grid = grid_needed;
     hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(1), 0, st, next);
+    if constexpr (kSlice) {
+        if (sl) {
+            launch_timed(prof, MCDC_PROF_HISTORY, k_history<FM, WW, true, true>, dim3((unsigned)grid), dim3(bs),
+                         (uint32_t)shmem, st, P, R, first, count, chunk_first, SB, next, (unsigned int)wc, tabs, gn);
+            return MCDC_OK;
+        }
+    }
     if (lt)
         launch_timed(prof, MCDC_PROF_HISTORY, k_history<FM, WW, true>, dim3((unsigned)grid), dim3(bs),
-                     (uint32_t)shmem, st, P, R, first, count, chunk_first, SB, next, (unsigned int)wc, tabs);
+                     (uint32_t)shmem, st, P, R, first, count, chunk_first, SB, next, (unsigned int)wc, tabs, 0);
     else
         launch_timed(prof, MCDC_PROF_HISTORY, k_history<FM, WW, false>, dim3((unsigned)grid), dim3(bs), 0u, st, P, R,
-                     first, count, chunk_first, SB, next, (unsigned int)wc, tabs);
+                     first, count, chunk_first, SB, next, (unsigned int)wc, tabs, 0);
     return MCDC_OK;
 }
 
 // Split progeny of one chunk, generation by generation, until none are left.
-// Generations are queued kGensPerCheck at a time, each launch reading its
-// input count on the device; the host reads the count once per batch.
 // Generations are queued kGensPerCheck at a time, each launch reading its
 // input count on the device; the host reads the count once per batch.
 constexpr int kGensPerCheck = 4;
