@@ -264,9 +264,10 @@ constexpr int64_t kHistorySliceMax = 48 * 1024;
 // (SL, analog runs whose tally of one batch fits in LDS: workgroup w takes
 // the histories [w H, (w + 1) H) of the chunk, H = ceil(count / grid), its
 // waves drawing chunks of them from a workgroup counter, so that they
-// belong to one batch or two; the scores of the range's first batch b0 go
-// to an LDS copy of that batch's tally (gn doubles behind the staged
-// tables), added to HBM once at the end.)
+// belong to one batch or two whenever a batch holds at least H histories;
+// the scores of the range's first batch b0 go to an LDS copy of that
+// batch's tally (gn doubles behind the staged tables), added to HBM once at
+// the end, and those of any later batch straight to HBM.)
 template <int FM, bool WW, bool LT, bool SL = false>
 __global__ void __launch_bounds__(256) k_history(DevProblem P0, RunArgs R, uint64_t first, uint64_t count,
                                                  uint64_t chunk_first, SplitBank SB, unsigned long long *next,

@@ -273,3 +273,28 @@ def test_auto_form_choice_single_problem():
     import oracle
     r = oracle.run(p, 20011, 3)
     assert np.array_equal(first["events"], r["tot"][0:3])
+
+
+def _slice_slab(n_bins, n_time_bins, n_batches=16):
+    """Pulsed slab whose one-batch tally has n_bins x n_time_bins doubles."""
+    return w.slab(thickness=40.0, sigma_t=1.0, sigma_s=0.9, speed=1.0, n_bins=n_bins, source="plane",
+                  x_src=20.0, time_edges=np.linspace(0.0, 20.0, n_time_bins + 1), n_batches=n_batches)
+
+
+# the history form scores an analog slab's batch in LDS when that batch's
+# tally takes at most 48 KB: 64 x 96 doubles is exactly that, 65 x 96 one
+# time-bin row more (scores go to HBM); one history per batch puts every
+# workgroup's range across many batches
+SLICE = {
+    "fits": (lambda: _slice_slab(64, 96), 4001, 61),
+    "over": (lambda: _slice_slab(65, 96), 4001, 62),
+    "batch_per_history": (lambda: _slice_slab(50, 40, n_batches=700), 700, 63),
+}
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("case", list(SLICE))
+def test_history_slice_boundaries(case):
+    make, N, seed = SLICE[case]
+    print(f"[parity] history slice {case} N={N}", flush=True)
+    compare_full(make(), N, seed, "history")
