@@ -265,9 +265,9 @@ constexpr int64_t kHistorySliceMax = 48 * 1024;
 // the histories [w H, (w + 1) H) of the chunk, H = ceil(count / grid), its
 // waves drawing chunks of them from a workgroup counter, so that they
 // belong to one batch or two whenever a batch holds at least H histories;
-// the scores of the range's first batch b0 go to an LDS copy of that
-// batch's tally (gn doubles behind the staged tables), added to HBM once at
-// the end, and those of any later batch straight to HBM.)
+// the track-length scores of the range's first batch b0 go to an LDS copy
+// of that batch's tally (gn doubles behind the staged tables), added to HBM
+// once at the end, and those of any later batch straight to HBM.)
 template <int FM, bool WW, bool LT, bool SL = false>
 __global__ void __launch_bounds__(256) k_history(DevProblem P0, RunArgs R, uint64_t first, uint64_t count,
                                                  uint64_t chunk_first, SplitBank SB, unsigned long long *next,
@@ -583,13 +583,13 @@ int launch_main(mcdc_problem *pb, const DevProblem &P, const RunArgs &R, uint64_
     }
     LdsTables tabs{};
     const bool lt = table_layout(P, tabs, kHistoryTablesMax);
-    // analog slab runs (x the only finite axis) without the time-crossing
-    // tally whose tally of one batch fits beside the tables score that batch
-    // in LDS (SL; in 3-D problems the slice's registers would cost a wave
-    // per SIMD)
+    // analog slab runs (x the only finite axis) whose track-length tally of
+    // one batch fits beside the tables score that batch in LDS (SL; the
+    // time-crossing tally, if any, still goes to HBM; in 3-D problems the
+    // slice's registers would cost a wave per SIMD)
     constexpr bool kSlice = FM == 1 && !WW;
-    const int64_t gn64 = (int64_t)P.K * P.G * P.nts;
-    const bool sl = kSlice && lt && !P.tc_on && gn64 > 0 && gn64 * 8 <= kHistorySliceMax;
+    const int64_t gn64 = P.ntally;
+    const bool sl = kSlice && lt && gn64 > 0 && gn64 * 8 <= kHistorySliceMax;
     const int gn = sl ? (int)gn64 : 0;
     const size_t shmem = lt ? (size_t)(tabs.bytes + 15) / 16 * 16 + (size_t)gn * 8 : 0;
     const void *kern = lt ? reinterpret_cast<const void *>(&k_history<FM, WW, true>)
