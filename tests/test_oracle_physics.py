@@ -117,14 +117,8 @@ def test_multigroup_slab_matches_sn():
     """Leakage, group transfer (up-scatter included) and the angular law
     together: the oracle's 3-group slab bin fluxes, group by group, agree
     with the multigroup S_N solution."""
-    edges = np.linspace(0.0, 6.0, 25)
-    prob = w.make_problem(
-        sigma_t=[MG_ST], sigma_s=[MG_SS], speed=[1.0, 1.0, 1.0],
-        planes=[np.array([0.0, 6.0]), np.array([]), np.array([])], material=np.zeros((1, 1, 1)),
-        bc=[w.VACUUM] * 6,
-        source={"kind": "surface", "axis": 0, "sign": 1, "mu_law": "cosine", "lo": [0.0, 0.0, 0.0],
-                "hi": [0.0, 0.0, 0.0], "group_pmf": MG_PMF},
-        tally={"mesh": [edges, np.array([]), np.array([])], "time_edges": [0.0, math.inf], "n_batches": 32})
+    prob = w.multigroup_slab(MG_ST, MG_SS, MG_PMF)
+    edges = prob["tally"]["mesh"][0]
     res = oracle.run(prob, 200000, 15)
     e = oracle.estimates(prob, res)
     exact = sn_slab_mg(6.0, MG_ST, MG_SS, MG_PMF, n_cells=2400, n_mu=64)(edges)

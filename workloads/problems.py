@@ -173,6 +173,23 @@ def slab(thickness=10.0, sigma_t=1.0, sigma_s=0.5, speed=1.0, n_bins=20,
                "n_batches": n_batches})
 
 
+def multigroup_slab(sigma_t=(1.0, 1.5, 2.0), sigma_s=((0.3, 0.4, 0.1), (0.0, 0.6, 0.5), (0.0, 0.2, 1.2)),
+                    group_pmf=(0.6, 0.3, 0.1), thickness=6.0, n_bins=24, n_batches=32):
+    """Multigroup slab [0, thickness], vacuum faces, one material with the
+    transfer matrix sigma_s[g][g'] (from g to g'; down- and up-scatter), lit
+    at x = 0 by a cosine-law current whose group follows group_pmf; steady
+    flux tallies in n_bins x-bins."""
+    G = len(sigma_t)
+    return make_problem(
+        sigma_t=[list(sigma_t)], sigma_s=[[list(r) for r in sigma_s]], speed=[1.0] * G,
+        planes=[np.array([0.0, thickness]), _empty(), _empty()], material=np.zeros((1, 1, 1)),
+        bc=[VACUUM] * 6,
+        source={"kind": "surface", "axis": 0, "sign": 1, "mu_law": "cosine", "lo": [0.0, 0.0, 0.0],
+                "hi": [0.0, 0.0, 0.0], "group_pmf": list(group_pmf)},
+        tally={"mesh": [np.linspace(0.0, thickness, n_bins + 1), _empty(), _empty()],
+               "time_edges": np.array([0.0, math.inf]), "n_batches": n_batches})
+
+
 def cfg1_slab_steady(c=0.5, mu_law="cosine", n_batches=32):
     """Slab of 10 mfp, Sigma_t = 1, scattering ratio c, surface source at x=0,
     20 tally bins, steady state (one time bin [0, inf))."""
