@@ -299,6 +299,41 @@ def sn_slab_mg(L, sigma_t, sigma_s, pmf, n_cells=2400, n_mu=64, tol=1e-12, law="
     return bins
 
 
+def sn_slab_mg_volume(L, sigma_t, sigma_s, pmf, n_cells=2400, n_mu=64, tol=1e-12):
+    """G-group slab [0, L], vacuum on both faces, with a unit isotropic
+    source spread uniformly over the slab (group g with probability pmf[g])
+    and isotropic scattering with the transfer matrix sigma_s[g, g'] (from
+    g to g'): mu dpsi/dx + St_g' psi = (1/2)(pmf[g'] / L + sum_g
+    Ss[g, g'] phi_g), swept as in sn_slab_mg.  Returns a function mapping
+    coarse bin edges to [G, bins] averages of the scalar flux (track length
+    per unit length per source particle)."""
+    sigma_t = np.asarray(sigma_t, dtype=np.float64)
+    sigma_s = np.asarray(sigma_s, dtype=np.float64)
+    G = sigma_t.size
+    h = L / n_cells
+    mu, wt = np.polynomial.legendre.leggauss(n_mu)
+    phi = np.zeros((G, n_cells))
+    for _ in range(5000):
+        diff = 0.0
+        for g2 in range(G):
+            q = 0.5 * (pmf[g2] / L + sum(sigma_s[g, g2] * phi[g] for g in range(G)))
+            new = _sn_sweep(q, sigma_t[g2], h, mu, wt)
+            diff = max(diff, float(np.max(np.abs(new - phi[g2]))))
+            phi[g2] = new
+        if diff < tol:
+            break
+
+    def bins(edges):
+        edges = np.asarray(edges, dtype=np.float64)
+        out = np.zeros((G, edges.size - 1))
+        for j, (a_, b_) in enumerate(zip(edges[:-1], edges[1:])):
+            i0, i1 = int(round(a_ / h)), int(round(b_ / h))
+            out[:, j] = phi[:, i0:i1].mean(axis=1)
+        return out
+
+    return bins
+
+
 def sn_slab_k(L, sigma_t, sigma_s, nu_sigma_f, n_cells=2000, n_mu=64, tol=1e-11):
     """One-group bare slab [0, L] (vacuum faces), isotropic scattering and
     fission: k-eigenvalue by power iteration on the fission source, each

@@ -15,7 +15,8 @@ import oracle
 import workloads as w
 from refs import (infinite_medium_pulse_bins, infinite_medium_steady,
                   plane_pulse_uncollided_bin, pulse_population, slab_absorber_bins,
-                  slab_absorber_transmission, sn_slab, sn_slab_mg)
+                  slab_absorber_transmission, sn_slab, sn_slab_mg,
+                  sn_slab_mg_volume)
 
 Z_MAX = 4.5
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
@@ -122,6 +123,39 @@ def test_multigroup_slab_matches_sn():
     res = oracle.run(prob, 200000, 15)
     e = oracle.estimates(prob, res)
     exact = sn_slab_mg(6.0, MG_ST, MG_SS, MG_PMF, n_cells=2400, n_mu=64)(edges)
+    m, v = e["mean"].reshape(3, -1), e["var"].reshape(3, -1)
+    _check(m, v, exact, floor=2e-5 * exact.max())
+
+
+def test_volume_source_sn_infinite_limit():
+    """The volume-source solver's flux far from thick faces is the
+    infinite-medium M^-1 S (M = diag(St) - Ss^T), here mid-slab in a
+    60-mfp slab."""
+    st, ss = np.array(MG_ST), np.array(MG_SS)
+    L = 60.0
+    f = sn_slab_mg_volume(L, st, ss, MG_PMF, n_cells=3000, n_mu=32)(np.array([29.0, 31.0]))[:, 0]
+    inf = np.linalg.solve(np.diag(st) - ss.T, np.array(MG_PMF) / L)
+    np.testing.assert_allclose(f, inf, rtol=1e-6)
+
+
+def test_reflected_box_column_matches_the_z_slab():
+    """A 3-D box of one material, reflective on its x and y faces and
+    vacuum on z, with a uniform volume source: the flux depends on z
+    alone, and integrated over the box's cross-section (the tally's x and
+    y axes carry no mesh planes, so they count with width 1) it is the
+    multigroup z-slab's, so the 3-D tracking with reflections, leakage and
+    group transfer is pinned against multigroup S_N."""
+    H, side, nz = 8.0, 1.26, 16
+    prob = w.make_problem(
+        sigma_t=[MG_ST], sigma_s=[MG_SS], speed=[1.0, 1.0, 1.0],
+        planes=[np.array([0.0, side]), np.array([0.0, side]), np.array([0.0, H])], material=np.zeros((1, 1, 1)),
+        bc=[w.REFLECTIVE, w.REFLECTIVE, w.REFLECTIVE, w.REFLECTIVE, w.VACUUM, w.VACUUM],
+        source={"kind": "isotropic", "lo": [0.0, 0.0, 0.0], "hi": [side, side, H], "group_pmf": MG_PMF},
+        tally={"mesh": [np.array([]), np.array([]), np.linspace(0.0, H, nz + 1)], "time_edges": [0.0, math.inf],
+               "n_batches": 32})
+    res = oracle.run(prob, 100000, 16)
+    e = oracle.estimates(prob, res)
+    exact = sn_slab_mg_volume(H, MG_ST, MG_SS, MG_PMF, n_cells=1600, n_mu=64)(np.linspace(0.0, H, nz + 1))
     m, v = e["mean"].reshape(3, -1), e["var"].reshape(3, -1)
     _check(m, v, exact, floor=2e-5 * exact.max())
 
