@@ -26,6 +26,7 @@ SMALL = {
                                                time_edges=[0.0, 0.25, 0.5, 1.0, 2.0, 4.0]), 4099, 17),
     "void_box": (lambda: w.void_box(), 3001, 5),
     "slab_mg3": (lambda: w.multigroup_slab(), 6007, 18),
+    "reflected_column": (lambda: w.reflected_column(), 4003, 19),
     "dogleg": (lambda: w.cfg5_dogleg(), 4001, 50),
     "census_heavy": (lambda: w.reflective_box([0.3, 0.5], [[0.1, 0.15], [0.0, 0.4]], [0.7, 1.3],
                                               time_edges=np.linspace(0.0, 9.1, 71)), 2003, 8),

@@ -145,14 +145,8 @@ def test_reflected_box_column_matches_the_z_slab():
     y axes carry no mesh planes, so they count with width 1) it is the
     multigroup z-slab's, so the 3-D tracking with reflections, leakage and
     group transfer is pinned against multigroup S_N."""
-    H, side, nz = 8.0, 1.26, 16
-    prob = w.make_problem(
-        sigma_t=[MG_ST], sigma_s=[MG_SS], speed=[1.0, 1.0, 1.0],
-        planes=[np.array([0.0, side]), np.array([0.0, side]), np.array([0.0, H])], material=np.zeros((1, 1, 1)),
-        bc=[w.REFLECTIVE, w.REFLECTIVE, w.REFLECTIVE, w.REFLECTIVE, w.VACUUM, w.VACUUM],
-        source={"kind": "isotropic", "lo": [0.0, 0.0, 0.0], "hi": [side, side, H], "group_pmf": MG_PMF},
-        tally={"mesh": [np.array([]), np.array([]), np.linspace(0.0, H, nz + 1)], "time_edges": [0.0, math.inf],
-               "n_batches": 32})
+    H, nz = 8.0, 16
+    prob = w.reflected_column(MG_ST, MG_SS, MG_PMF, height=H, n_z_bins=nz)
     res = oracle.run(prob, 100000, 16)
     e = oracle.estimates(prob, res)
     exact = sn_slab_mg_volume(H, MG_ST, MG_SS, MG_PMF, n_cells=1600, n_mu=64)(np.linspace(0.0, H, nz + 1))

@@ -190,6 +190,24 @@ def multigroup_slab(sigma_t=(1.0, 1.5, 2.0), sigma_s=((0.3, 0.4, 0.1), (0.0, 0.6
                "time_edges": np.array([0.0, math.inf]), "n_batches": n_batches})
 
 
+def reflected_column(sigma_t=(1.0, 1.5, 2.0), sigma_s=((0.3, 0.4, 0.1), (0.0, 0.6, 0.5), (0.0, 0.2, 1.2)),
+                     group_pmf=(0.6, 0.3, 0.1), side=1.26, height=8.0, n_z_bins=16, n_batches=32):
+    """Box side x side x height of one material, reflective on its x and y
+    faces and vacuum on z, with a uniform isotropic volume source (group
+    from group_pmf): its flux depends on z alone.  Steady flux tallies in
+    n_z_bins z-bins (x and y without mesh planes)."""
+    G = len(sigma_t)
+    return make_problem(
+        sigma_t=[list(sigma_t)], sigma_s=[[list(r) for r in sigma_s]], speed=[1.0] * G,
+        planes=[np.array([0.0, side]), np.array([0.0, side]), np.array([0.0, height])],
+        material=np.zeros((1, 1, 1)),
+        bc=[REFLECTIVE, REFLECTIVE, REFLECTIVE, REFLECTIVE, VACUUM, VACUUM],
+        source={"kind": "isotropic", "lo": [0.0, 0.0, 0.0], "hi": [side, side, height],
+                "group_pmf": list(group_pmf)},
+        tally={"mesh": [_empty(), _empty(), np.linspace(0.0, height, n_z_bins + 1)],
+               "time_edges": np.array([0.0, math.inf]), "n_batches": n_batches})
+
+
 def cfg1_slab_steady(c=0.5, mu_law="cosine", n_batches=32):
     """Slab of 10 mfp, Sigma_t = 1, scattering ratio c, surface source at x=0,
     20 tally bins, steady state (one time bin [0, inf))."""
